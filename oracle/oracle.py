@@ -1,0 +1,180 @@
+"""Python access to the plain FP64 CPU oracle (``fstat_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the CPU-baseline leg of the benchmark.  The product library never imports it.
+
+Every function here is a thin ctypes wrapper around the C file, except
+``inner``/``fstat_from_templates``, which restate the paper's definitions in
+numpy for the pins (Sec. II.A, Eqs. "inner_product" and "coherent_F_stat").
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fstat_oracle.c")
+_LIB = os.path.join(_HERE, "libfstat_oracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain IEEE double, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
+               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.or_set_pn_order.argtypes = [ctypes.c_int]
+        L.or_phase.argtypes = [_dp, ctypes.c_double, _dp, ctypes.c_int64, _dp, _dp]
+        L.or_tf.argtypes = [_dp, _dp, ctypes.c_int64, _dp]
+        L.or_orbit.argtypes = [_dp, ctypes.c_int64, _dp]
+        L.or_response.argtypes = [_dp, _dp, _dp, ctypes.c_int64, _dp]
+        L.or_link.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_double, _dp]
+        L.or_basis.argtypes = [_dp, _dp, ctypes.c_int64, _dp]
+        L.or_support.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+        L.or_signal.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                ctypes.c_double, _dp]
+        L.or_fstat.argtypes = [_dp, _dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                               ctypes.c_double, _dp, ctypes.c_int64, _i32p, ctypes.c_int32,
+                               _dp, _dp, ctypes.c_int64, _dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def set_pn_order(order: int) -> None:
+    lib().or_set_pn_order(int(order))
+
+
+def phase_cycles(theta6, f, phic=0.0):
+    """Psi(f)/(2 pi) as (hi, lo) doubles (App. A)."""
+    t, tp = _d(theta6)
+    f, fp = _d(np.atleast_1d(f))
+    hi = np.empty_like(f); lo = np.empty_like(f)
+    if lib().or_phase(tp, float(phic), fp, f.size, hi.ctypes.data_as(_dp), lo.ctypes.data_as(_dp)):
+        raise ValueError("bad parameters")
+    return hi, lo
+
+
+def tf(theta6, f):
+    """SPA time t_f = (1/2pi) dPsi/df (Sec. IV)."""
+    t, tp = _d(theta6)
+    f, fp = _d(np.atleast_1d(f))
+    out = np.empty_like(f)
+    if lib().or_tf(tp, fp, f.size, out.ctypes.data_as(_dp)):
+        raise ValueError("bad parameters")
+    return out
+
+
+def orbit(t):
+    t, tp = _d(np.atleast_1d(t))
+    out = np.empty((t.size, 3, 3))
+    lib().or_orbit(tp, t.size, out.ctypes.data_as(_dp))
+    return out
+
+
+def response(theta6, f, t):
+    """TDI-X transfer (T+, Tx) at frequency f with the orbit frozen at time t."""
+    th, tp = _d(theta6)
+    f, fp = _d(np.atleast_1d(f))
+    t, tt = _d(np.broadcast_to(np.atleast_1d(t), f.shape))
+    out = np.empty((f.size, 4))
+    if lib().or_response(tp, fp, tt, f.size, out.ctypes.data_as(_dp)):
+        raise ValueError("bad parameters")
+    return out[:, 0] + 1j * out[:, 1], out[:, 2] + 1j * out[:, 3]
+
+
+def link(pos, r, s, theta, phi, f):
+    p, pp = _d(pos)
+    out = np.empty(4)
+    lib().or_link(pp, int(r), int(s), float(theta), float(phi), float(f), out.ctypes.data_as(_dp))
+    return out[0] + 1j * out[1], out[2] + 1j * out[3]
+
+
+def basis(theta6, f):
+    """The four basis templates A^i(f): complex array [n, 4]."""
+    th, tp = _d(theta6)
+    f, fp = _d(np.atleast_1d(f))
+    out = np.empty((f.size, 4, 2))
+    if lib().or_basis(tp, fp, f.size, out.ctypes.data_as(_dp)):
+        raise ValueError("bad parameters")
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def support(theta6, T_obs, f_first, f_last):
+    th, tp = _d(theta6)
+    out = np.empty(2)
+    ok = lib().or_support(tp, float(T_obs), float(f_first), float(f_last), out.ctypes.data_as(_dp))
+    if ok < 0:
+        raise ValueError("bad parameters")
+    return (float(out[0]), float(out[1])) if ok else None
+
+
+def signal(theta6, amp4, df, k_lo, nbins, T_obs):
+    """sum_i a_i A^i on the grid, zero outside the support: complex [nbins]."""
+    th, tp = _d(theta6)
+    a, ap = _d(amp4)
+    out = np.empty((int(nbins), 2))
+    if lib().or_signal(tp, ap, float(df), int(k_lo), int(nbins), float(T_obs), out.ctypes.data_as(_dp)):
+        raise ValueError("bad parameters")
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def fstat(data, psd, k_lo, df, T_obs, params, np_parts, part_stride=None, want_cond=False):
+    """Semi-coherent F (Eq. "semi-cohF").  Returns (F_hat, F_part[, cond])."""
+    data = np.ascontiguousarray(data, dtype=np.complex128)
+    dv = data.view(np.float64)
+    psd, pp = _d(psd)
+    params = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64)
+    n = params.shape[0]
+    npa = np.ascontiguousarray(np.broadcast_to(np.asarray(np_parts, dtype=np.int32), (n,)))
+    stride = int(part_stride or (npa.max() if n else 1))
+    Fh = np.empty(n)
+    Fp = np.zeros((n, stride))
+    cond = np.zeros((n, stride)) if want_cond else None
+    rc = lib().or_fstat(dv.ctypes.data_as(_dp), pp, data.size, int(k_lo), float(df), float(T_obs),
+                        params.ctypes.data_as(_dp), n, npa.ctypes.data_as(_i32p), 0,
+                        Fh.ctypes.data_as(_dp), Fp.ctypes.data_as(_dp), stride,
+                        cond.ctypes.data_as(_dp) if want_cond else None)
+    if rc:
+        raise ValueError(f"oracle fstat failed ({rc})")
+    return (Fh, Fp, cond) if want_cond else (Fh, Fp)
+
+
+# ---- numpy restatements used by the pins ---------------------------------
+
+def inner(a, b, psd, df):
+    """<a,b> = 4 df Re sum a conj(b) / S (Sec. II.A, Eq. "inner_product")."""
+    return 4.0 * df * np.real(np.sum(a * np.conj(b) / psd))
+
+
+def fstat_from_templates(s, A, psd, df):
+    """F = 1/2 N^T M^{-1} N from explicit templates A[n, 4] (least squares, so
+    a singular M is handled by the minimum-norm solution)."""
+    N = np.array([inner(s, A[:, i], psd, df) for i in range(4)])
+    M = np.array([[inner(A[:, i], A[:, j], psd, df) for j in range(4)] for i in range(4)])
+    a = np.linalg.lstsq(M, N, rcond=1e-12)[0]
+    return 0.5 * N @ a, N, M
