@@ -1,0 +1,166 @@
+"""Benchmark: batched semi-coherent F-statistic on the paper-scale workload.
+
+Workload (one step = one batched evaluation, all of the hot path):
+  2.5 yr (T = 7.89e7 s) of one TDI-X channel, df = 1/T, 10-100 mHz ->
+  7,101,001 bins; Gaussian noise from the TDI-X PSD plus one eccentric
+  inspiral (Mc ~ U(10, 50), e0 ~ U(0, 0.1), SNR ~ U(11, 14)); 4096 particles
+  uniform in t_c in [3.3, 3.8] yr, Mc in [10, 50] Msun, delta_mu in [0, 0.9],
+  full sky, e0 in [0, 0.1]; Np = 64 equal-width frequency partitions.
+Inputs are resident in device memory before the timed region starts.
+
+Prints one JSON line (see the repository documentation for every field).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector peak (256 CUs x 2.4 GHz x 128 FLOP/clk)
+PEAK_FP32_TFLOPS = 157.3
+# FP64 floating-point operations per bin-template of the bin-loop kernel
+# (FMA = 2), from rocprofv3 FP64 VALU instruction counters divided by the
+# bin-template evaluations of the same launch.
+FLOP_PER_BIN = {"fp64": None, "mixed": None}
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(n_particles: int, seed_pts: int = 2003):
+    import torch
+    from paper_2407_10797_amd import fstat, synth as S
+    g = S.grid_paper()
+    psd = S.psd_tdix(g.freqs())
+    noise = S.noise(psd, g.df, S.PAPER_SEEDS["noise"])
+    inj, snr = S.paper_injection_params()
+    amps = S.random_amplitudes(S.PAPER_SEEDS["inj"])
+    sig = fstat.waveform(g.T_obs, g.df, g.k_lo, g.nbins, inj, amps).cpu().numpy()
+    data = noise + S.snr_scale(sig, psd, g.df, snr) * sig
+    pts = S.uniform_box(S.PAPER_BOX, n_particles, seed_pts)
+    return g, data, psd, pts, inj
+
+
+def time_path(plan, prm, npart, steps, warmup, mixed):
+    import torch
+    for _ in range(warmup):
+        plan.eval(prm, npart, mixed=mixed)
+    torch.cuda.synchronize()
+    plan.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        F = plan.eval(prm, npart, mixed=mixed)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, launches, bins = plan.profile_read(reset=True)
+    return dict(seconds=t1 - t0, kernel_ms=kms / max(launches, 1),
+                bins_per_launch=bins / max(launches, 1), F=F)
+
+
+def cpu_baseline(g, data, psd, pts, npart, sample):
+    from oracle import oracle as O
+    sub = pts[:sample]
+    t0 = time.perf_counter()
+    O.fstat(data, psd, g.k_lo, g.df, g.T_obs, sub, [npart])
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": sample / dt, "unit": "templates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{sample} of the {len(pts)} particles, Np={npart}, full 7,101,001-bin data, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--np", type=int, default=64)
+    ap.add_argument("--particles", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--only", choices=["fp64", "mixed"], default=None)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device-to-device copy of BYTES (for scaling "
+                         "FETCH_SIZE/WRITE_SIZE counters) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU (got --gpus {args.gpus}); "
+              "multi-GPU sharding is described in DESIGN.md but not implemented", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2407_10797_amd import fstat
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.copy_calibration:
+        n = args.copy_calibration // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 8 * n}))
+        return
+    _log("building workload")
+    g, data, psd, pts, inj = make_workload(args.particles)
+    plan = fstat.Plan(data, psd, g.T_obs, g.df, g.k_lo, profile=True)
+    prm = torch.from_numpy(pts).cuda()
+    torch.cuda.synchronize()
+    variants = {}
+    for name, mixed in (("fp64", False), ("mixed", True)):
+        if (mixed and args.no_mixed) or (args.only and args.only != name):
+            continue
+        try:
+            r = time_path(plan, prm, args.np, args.steps, args.warmup, mixed)
+        except fstat.FstatError as e:
+            _log(f"{name}: {e}")
+            continue
+        tps = args.particles * args.steps / r["seconds"]
+        fpb = FLOP_PER_BIN[name]
+        peak = PEAK_FP64_TFLOPS
+        achieved = (fpb * r["bins_per_launch"] / (r["kernel_ms"] * 1e-3) / 1e12) if fpb else None
+        variants[name] = dict(templates_per_s=tps, ms_per_step=1e3 * r["seconds"] / args.steps,
+                              kernel_ms=r["kernel_ms"], bins_per_launch=r["bins_per_launch"],
+                              bin_templates_per_s=r["bins_per_launch"] / (r["kernel_ms"] * 1e-3),
+                              roofline=dict(bound="alu", achieved=achieved, peak=peak,
+                                            unit="TFLOP/s",
+                                            frac=(achieved / peak) if achieved else None,
+                                            traffic=None))
+        _log(f"{name}: {tps:.1f} templates/s, kernel {r['kernel_ms']:.2f} ms/launch, "
+             f"{r['bins_per_launch']:.3e} bin-templates/launch")
+    head = variants.get("fp64") or next(iter(variants.values()))
+    out = {
+        "metric": "F-stat templates/s at 7.1M bins, Np=64; %roofline; plain vs mixed+surrogate",
+        "value": head["templates_per_s"],
+        "unit": "templates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "paper-scale: 2.5 yr TDI-X, 7,101,001 bins (10-100 mHz), "
+                               f"{args.particles} particles per batch, Np={args.np}, FP64 path",
+                   "global_batch": args.particles, "np": args.np, "nbins": int(g.nbins)},
+        "roofline": head["roofline"],
+        "variants": variants,
+    }
+    if not args.no_cpu:
+        _log("timing the CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(g, data, psd, pts, args.np, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

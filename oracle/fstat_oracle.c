@@ -28,13 +28,15 @@
  * repository's design notes; each is marked where it is used below.
  *
  * Precision: the template phase reaches 10^7 cycles, so it is evaluated in
- * x87 extended precision (long double, 64-bit significand) and reduced modulo
- * one cycle before the trigonometric functions are taken in double.  All
- * other arithmetic is plain double with compensated (Neumaier) summation.
+ * IEEE binary128 (__float128) and reduced modulo one cycle before the
+ * trigonometric functions are taken in double; t_f uses x87 extended
+ * precision.  All other arithmetic is plain double with compensated
+ * (Neumaier) summation.
  *
  * Parity status of each function is stated in its header comment.
  */
 #include <math.h>
+#include <quadmath.h>
 #include <complex.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -84,48 +86,66 @@ static long double eta_of(const or_intr *p) {
   return (1.0L - d * d) / 4.0L;
 }
 
-/* PN part of the phase in radians: (3/128)(pi Mc f)^{-5/3} sum_k alpha_k v^k
- * + Psi_e, with v = (pi M f)^{1/3} and M = Mc eta^{-3/5}.  The alpha_k are the
- * non-spinning TaylorF2 coefficients of the literature the paper cites
- * (parity unpinned beyond the Newtonian term: the paper does not print them).
- * Psi_e is the leading-order eccentric correction
- * -(2355/1462) e0^2 (f0/f)^{19/9} times the Newtonian term, with e0 defined
- * at the GW frequency f0 = 10 mHz (Sec. II.A, Table I).                      */
-static long double pn_psi_rad(const or_intr *p, long double f) {
-  const long double pi = OR_PI_L;
-  long double eta = eta_of(p);
-  long double mc = (long double)p->mc * (long double)OR_MSUN_S;
-  long double m = mc * powl(eta, -0.6L);
-  long double v = cbrtl(pi * m * f);
-  long double newt = 3.0L / (128.0L * powl(pi * mc * f, 5.0L / 3.0L));
-  long double s = 1.0L;
-  if (g_pn_order >= 2) {
-    long double v2 = v * v, v3 = v2 * v, v4 = v3 * v, v5 = v4 * v, v6 = v5 * v;
-    long double a2 = 3715.0L / 756.0L + 55.0L * eta / 9.0L;
-    long double a3 = -16.0L * pi;
-    long double a4 = 15293365.0L / 508032.0L + 27145.0L * eta / 504.0L +
-                     3085.0L * eta * eta / 72.0L;
-    long double a5 = pi * (38645.0L / 756.0L - 65.0L * eta / 9.0L) *
-                     (1.0L + 3.0L * logl(v * sqrtl(6.0L)));
-    long double a6 = 11583231236531.0L / 4694215680.0L - 640.0L * pi * pi / 3.0L -
-                     6848.0L * OR_EULER_L / 21.0L - 6848.0L / 21.0L * logl(4.0L * v) +
-                     (-15737765635.0L / 3048192.0L + 2255.0L * pi * pi / 12.0L) * eta +
-                     76055.0L * eta * eta / 1728.0L - 127825.0L * eta * eta * eta / 1296.0L;
-    s += a2 * v2 + a3 * v3 + a4 * v4 + a5 * v5 + a6 * v6;
-  }
-  long double e0 = (long double)p->e0;
-  long double ecc = -(2355.0L / 1462.0L) * e0 * e0 *
-                    powl((long double)OR_F0_ECC / f, 19.0L / 9.0L);
-  return newt * (s + ecc);
+/* The phase reaches 10^7 cycles and the statistic is sensitive to phase
+ * errors of order 1e-12 rad (amplified by the conditioning of M), so the
+ * phase is evaluated in IEEE binary128 (__float128, 113-bit significand):
+ * per-particle quantities once, then three quad transcendentals per bin.  */
+typedef __float128 qd;
+static const qd OR_PI_Q = 3.14159265358979323846264338327950288Q;
+static const qd OR_EULER_Q = 0.57721566490153286060651209008240243Q;
+
+typedef struct {
+  qd tc, mc, eta, m;              /* t_c [s], Mc [s], eta, M = Mc eta^{-3/5} [s] */
+  qd a2, a3, a4, c5, a6c, b6, e0sq;
+} or_pq;
+
+static or_pq phase_consts(const or_intr *p) {
+  or_pq c;
+  const qd pi = OR_PI_Q;
+  qd d = (qd)p->dmu;
+  c.tc = (qd)p->tc;
+  c.mc = (qd)p->mc * (qd)OR_MSUN_S;
+  c.eta = (1 - d * d) / 4;
+  c.m = c.mc * powq(c.eta, -0.6Q);
+  qd eta = c.eta;
+  c.a2 = 3715.0Q / 756 + 55 * eta / 9;
+  c.a3 = -16 * pi;
+  c.a4 = 15293365.0Q / 508032 + 27145 * eta / 504 + 3085 * eta * eta / 72;
+  c.c5 = pi * (38645.0Q / 756 - 65 * eta / 9);
+  c.a6c = 11583231236531.0Q / 4694215680 - 640 * pi * pi / 3 - 6848 * OR_EULER_Q / 21 +
+          (-15737765635.0Q / 3048192 + 2255 * pi * pi / 12) * eta + 76055 * eta * eta / 1728 -
+          127825 * eta * eta * eta / 1296;
+  c.b6 = -6848.0Q / 21;
+  c.e0sq = (qd)p->e0 * (qd)p->e0;
+  return c;
 }
 
-/* Full phase Psi(f)/(2 pi) in cycles, long double (App. A with phi_p and phi_D
- * carried by the response instead of the phase, see or_response).          */
-static long double phase_cycles(const or_intr *p, double f, double phic) {
-  const long double pi = OR_PI_L;
-  long double fl = (long double)f;
-  return fl * (long double)p->tc - (long double)phic / (2.0L * pi) - 0.125L +
-         pn_psi_rad(p, fl) / (2.0L * pi);
+/* Psi(f)/(2 pi) in cycles (App. A with phi_p and phi_D carried by the
+ * response instead of the phase, see response()):
+ *   f t_c - phi_c/(2 pi) - 1/8 + (3/128)(pi Mc f)^{-5/3} [sum_k alpha_k v^k + Psi_e/Psi_N] / (2 pi)
+ * v = (pi M f)^{1/3}; (3/128)(pi Mc f)^{-5/3} = 3 / (128 eta v^5).
+ * alpha_k: non-spinning TaylorF2 coefficients of the literature the paper
+ * cites (parity unpinned beyond the Newtonian term: the paper does not print
+ * them).  Psi_e: leading-order eccentric correction -(2355/1462) e0^2
+ * (f0/f)^{19/9} times the Newtonian term, e0 defined at the GW frequency
+ * f0 = 10 mHz (Sec. II.A, Table I).                                        */
+static qd phase_cycles_q(const or_pq *c, double f, double phic) {
+  const qd pi = OR_PI_Q;
+  qd F = (qd)f;
+  qd v = cbrtq(pi * c->m * F);
+  qd v2 = v * v, v5 = v2 * v2 * v;
+  qd newt = 3 / (128 * c->eta * v5);
+  qd s = 1;
+  if (g_pn_order >= 2) {
+    qd lv = logq(v);
+    qd v3 = v2 * v, v4 = v2 * v2, v6 = v3 * v3;
+    qd a5 = c->c5 * (1 + 3 * (lv + logq(sqrtq(6.0Q))));
+    qd a6 = c->a6c + c->b6 * (lv + logq(4.0Q));
+    s += c->a2 * v2 + c->a3 * v3 + c->a4 * v4 + a5 * v5 + a6 * v6;
+  }
+  qd ecc = 0;
+  if (c->e0sq != 0) ecc = -(2355.0Q / 1462) * c->e0sq * powq((qd)OR_F0_ECC / F, 19.0Q / 9);
+  return F * c->tc - (qd)phic / (2 * pi) - 0.125Q + newt * (s + ecc) / (2 * pi);
 }
 
 /* dPsi/df (radians per Hz): each term of the series differentiated by hand.
@@ -252,10 +272,10 @@ static void response(const or_intr *p, double f, double t, double complex T[2]) 
  * g = f^{-7/6} exp(-i Psi(f)) with phi_c = 0.  With the App. B amplitudes
  * a_1..a_4 this reproduces h_X = T+ h+ + Tx hx for h+ = (1+cos^2 i)/2 ...,
  * hx = -i cos(i) ... rotated by psi (reading of the App. B conventions).    */
-static void basis_at(const or_intr *p, double f, double complex A[4]) {
-  long double cyc = phase_cycles(p, f, 0.0);
-  long double fr = cyc - floorl(cyc);
-  double ph = 2.0 * OR_PI * (double)fr;
+static void basis_at(const or_intr *p, const or_pq *pq, double f, double complex A[4]) {
+  qd cyc = phase_cycles_q(pq, f, 0.0);
+  double fr = (double)(cyc - floorq(cyc));
+  double ph = 2.0 * OR_PI * fr;
   double complex g = pow(f, -7.0 / 6.0) * cexp(-I * ph);
   double complex T[2];
   response(p, f, tf_of(p, f), T);
@@ -400,9 +420,10 @@ int or_phase(const double *theta6, double phic, const double *f, int64_t n, doub
   or_intr p = unpack(theta6);
   if (!params_ok(&p)) return -1;
   for (int64_t i = 0; i < n; ++i) {
-    long double c = phase_cycles(&p, f[i], phic);
+    or_pq pq = phase_consts(&p);
+    qd c = phase_cycles_q(&pq, f[i], phic);
     hi[i] = (double)c;
-    lo[i] = (double)(c - (long double)hi[i]);
+    lo[i] = (double)(c - (qd)hi[i]);
   }
   return 0;
 }
@@ -453,9 +474,10 @@ void or_link(const double *pos9, int r, int s, double theta, double phi, double 
 int or_basis(const double *theta6, const double *f, int64_t n, double *out) {
   or_intr p = unpack(theta6);
   if (!params_ok(&p)) return -1;
+  or_pq pq = phase_consts(&p);
   for (int64_t i = 0; i < n; ++i) {
     double complex A[4];
-    basis_at(&p, f[i], A);
+    basis_at(&p, &pq, f[i], A);
     for (int b = 0; b < 4; ++b) {
       out[8 * i + 2 * b] = creal(A[b]);
       out[8 * i + 2 * b + 1] = cimag(A[b]);
@@ -484,12 +506,13 @@ int or_signal(const double *theta6, const double *amp4, double df, int64_t k_lo,
   double f_first = (double)k_lo * df, f_last = (double)(k_lo + nbins - 1) * df;
   double flo, fhi;
   if (!support(&p, T_obs, f_first, f_last, &flo, &fhi)) return 0;
+  or_pq pq = phase_consts(&p);
 #pragma omp parallel for schedule(static)
   for (int64_t j = 0; j < nbins; ++j) {
     double f = (double)(k_lo + j) * df;
     if (f < flo || f > fhi) continue;
     double complex A[4];
-    basis_at(&p, f, A);
+    basis_at(&p, &pq, f, A);
     double complex h = amp4[0] * A[0] + amp4[1] * A[1] + amp4[2] * A[2] + amp4[3] * A[3];
     out[2 * j] = creal(h);
     out[2 * j + 1] = cimag(h);
@@ -541,13 +564,14 @@ int or_fstat(const double *data, const double *psd, int64_t nbins, int64_t k_lo,
     if (!accN || !accM || !edge) { err = 1; free(accN); free(accM); free(edge); continue; }
     double span = fhi - flo;
     for (int l = 0; l <= Np; ++l) edge[l] = flo + (span * (double)l) / (double)Np;
+    or_pq pq = phase_consts(&p);
     int l = 0;
     for (int64_t j = 0; j < nbins; ++j) {
       double f = (double)(k_lo + j) * df;
       if (f < flo || f > fhi) continue;
       while (l < Np - 1 && f >= edge[l + 1]) ++l;
       double complex A[4];
-      basis_at(&p, f, A);
+      basis_at(&p, &pq, f, A);
       double complex s = data[2 * j] + I * data[2 * j + 1];
       for (int a = 0; a < 4; ++a) {
         acc_add(&accN[4 * l + a], creal(s * conj(A[a])) / psd[j]);

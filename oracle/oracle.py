@@ -27,7 +27,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain IEEE double, no contraction)."""
     if force or not os.path.exists(_LIB):
         cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
-               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", _LIB + ".tmp", "-lm"]
+               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", _LIB + ".tmp", "-lquadmath", "-lm"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB

@@ -1,0 +1,347 @@
+// fstat_api.hip -- C ABI of libfstat (see include/fstat.h): plans, batched
+// evaluation and template generation.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fstat.h"
+#include "fstat_api_internal.h"
+
+using namespace fstat;
+
+namespace fstat {
+
+static thread_local std::string g_err;
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return FSTAT_OK;
+  return set_error(e == hipErrorOutOfMemory ? FSTAT_ENOMEM : FSTAT_EDEVICE, "%s: %s", what,
+                   hipGetErrorString(e));
+}
+
+template <typename T>
+static int dev_alloc(T** p, size_t count, const char* what) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hip_check(hipMalloc((void**)p, count * sizeof(T)), what);
+}
+
+template <typename T>
+static void dev_free(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+// grow-only device buffer
+template <typename T>
+static int ensure(T** p, size_t* cap, size_t need, const char* what) {
+  if (need <= *cap && *p) return FSTAT_OK;
+  dev_free(*p);
+  *cap = 0;
+  int rc = dev_alloc(p, need, what);
+  if (rc == FSTAT_OK) *cap = need;
+  return rc;
+}
+
+int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride) {
+  int rc;
+  size_t m = (size_t)n * (size_t)stride;
+  size_t cap_items = (size_t)n * ((size_t)((P->grid.nbins + P->chunk - 1) / P->chunk) + stride);
+  if (cap_items > (size_t)INT32_MAX)
+    return set_error(FSTAT_EINVAL, "work list too large (%zu items)", cap_items);
+  if ((rc = ensure(&P->ws.pc, &P->cap.pc, (size_t)n, "alloc pc"))) return rc;
+  if ((rc = ensure(&P->ws.bounds, &P->cap.bounds, (size_t)n * (stride + 1), "alloc bounds"))) return rc;
+  if ((rc = ensure(&P->ws.cnt, &P->cap.cnt, m, "alloc cnt"))) return rc;
+  if ((rc = ensure(&P->ws.off, &P->cap.off, m, "alloc off"))) return rc;
+  if ((rc = ensure(&P->ws.Fl, &P->cap.Fl, m, "alloc Fl"))) return rc;
+  if ((rc = ensure(&P->ws.total, &P->cap.total, 1, "alloc total"))) return rc;
+  if ((rc = ensure(&P->ws.items, &P->cap.items, cap_items, "alloc items"))) return rc;
+  if ((rc = ensure(&P->ws.partials, &P->cap.partials, cap_items * 8, "alloc partials"))) return rc;
+  return FSTAT_OK;
+}
+
+int eval_blocks(fstat_plan_s* P, bool mixed) {
+  int& cached = mixed ? P->blocks_mixed : P->blocks_fp64;
+  if (cached > 0) return cached;
+  int per_cu = 0;
+  hipError_t e = mixed ? occupancy_mixed(&per_cu) : occupancy_fp64(&per_cu);
+  if (e != hipSuccess || per_cu < 1) per_cu = 2;
+  cached = P->num_cu * per_cu;
+  return cached;
+}
+
+// Enqueue one evaluation with device pointers.
+int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t* np,
+                int32_t np_uniform, int32_t stride, double* F_hat, double* F_part,
+                int64_t part_stride, bool mixed, hipStream_t s, const uint8_t* skip,
+                bool allow_profile) {
+  int rc = ensure_workspace(P, n, stride);
+  if (rc) return rc;
+  launch_setup(P->grid, params, n, np, np_uniform, stride, P->chunk, skip, P->ws, s);
+  launch_worklist(n * (int64_t)stride, P->ws, s);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool prof = P->profile && allow_profile;
+  if (prof) {
+    if ((rc = hip_check(hipEventCreate(&e0), "event")) || (rc = hip_check(hipEventCreate(&e1), "event")))
+      return rc;
+    (void)hipEventRecord(e0, s);
+  }
+  launch_eval(mixed, P->grid, stride, P->chunk, P->ws, P->b64, P->b32, eval_blocks(P, mixed), s);
+  if (prof) {
+    (void)hipEventRecord(e1, s);
+    P->events.emplace_back(e0, e1);
+  }
+  launch_solve_mean(n, stride, P->ws, F_hat, F_part, part_stride, prof ? P->bin_counter : nullptr, s);
+  return hip_check(hipGetLastError(), "kernel launch");
+}
+
+}  // namespace fstat
+
+extern "C" {
+
+const char* fstat_last_error(void) { return g_err.c_str(); }
+
+int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_opts* opts,
+                      void* hip_stream) {
+  g_err.clear();
+  if (!out || !d) return set_error(FSTAT_EINVAL, "null plan or data descriptor");
+  *out = nullptr;
+  if (d->nbins < 1 || d->nbins > INT32_MAX - 1) return set_error(FSTAT_EINVAL, "nbins out of range");
+  if (!(d->df > 0.0) || !std::isfinite(d->df)) return set_error(FSTAT_EINVAL, "df must be > 0");
+  if (d->k_lo < 1) return set_error(FSTAT_EINVAL, "k_lo must be >= 1");
+  if (!(d->T_obs > 0.0) || !std::isfinite(d->T_obs)) return set_error(FSTAT_EINVAL, "T_obs must be > 0");
+  if (!d->data || !d->psd) return set_error(FSTAT_EINVAL, "null data or psd");
+  uint32_t flags = opts ? opts->flags : 0u;
+  int prec = opts ? opts->precision : 0;
+  if (prec == 0) prec = FSTAT_FP64 | FSTAT_MIXED;
+  if (prec & ~(FSTAT_FP64 | FSTAT_MIXED)) return set_error(FSTAT_EINVAL, "bad precision mask");
+  int chunk = (opts && opts->chunk > 0) ? opts->chunk : 2048;
+  if (chunk < 64 || chunk > (1 << 24)) return set_error(FSTAT_EINVAL, "chunk out of range");
+  const bool dev = (flags & FSTAT_DEVICE_PTRS) != 0;
+  const int64_t nb = d->nbins;
+  if (!dev) {
+    for (int64_t j = 0; j < nb; ++j) {
+      if (!(d->psd[j] > 0.0) || !std::isfinite(d->psd[j]))
+        return set_error(FSTAT_EINVAL, "psd[%lld] must be finite and > 0", (long long)j);
+      if (!std::isfinite(d->data[2 * j]) || !std::isfinite(d->data[2 * j + 1]))
+        return set_error(FSTAT_EINVAL, "data[%lld] is not finite", (long long)j);
+    }
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  fstat_plan_s* P = new fstat_plan_s();
+  P->grid = Grid{d->df, d->T_obs, d->k_lo, nb};
+  P->prec = prec;
+  P->chunk = chunk;
+  int rc = hip_check(hipGetDevice(&P->device), "hipGetDevice");
+  if (!rc) rc = hip_check(hipDeviceGetAttribute(&P->num_cu, hipDeviceAttributeMultiprocessorCount,
+                                                P->device), "device attribute");
+  double *dd = nullptr, *dp = nullptr, *umax = nullptr;
+  if (!rc) rc = dev_alloc(&P->b64.wr, nb, "alloc wr");
+  if (!rc) rc = dev_alloc(&P->b64.wi, nb, "alloc wi");
+  if (!rc) rc = dev_alloc(&P->b64.u, nb, "alloc u");
+  if (!rc) rc = dev_alloc(&P->b64.s0, nb, "alloc s0");
+  if (!rc) rc = dev_alloc(&P->b64.c0, nb, "alloc c0");
+  if (!rc && (prec & FSTAT_MIXED)) {
+    rc = dev_alloc(&P->b32.wr, nb, "alloc wr32");
+    if (!rc) rc = dev_alloc(&P->b32.wi, nb, "alloc wi32");
+    if (!rc) rc = dev_alloc(&P->b32.u, nb, "alloc u32");
+    if (!rc) rc = dev_alloc(&P->b32.s0, nb, "alloc s032");
+    if (!rc) rc = dev_alloc(&P->b32.c0, nb, "alloc c032");
+  }
+  if (!rc) rc = dev_alloc(&umax, 1, "alloc umax");
+  if (!rc && (flags & FSTAT_PROFILE)) {
+    P->profile = true;
+    rc = dev_alloc(&P->bin_counter, 1, "alloc counter");
+    if (!rc) rc = hip_check(hipMemsetAsync(P->bin_counter, 0, sizeof(unsigned long long), s), "memset");
+  }
+  const double* ddata = d->data;
+  const double* dpsd = d->psd;
+  if (!rc && !dev) {
+    rc = dev_alloc(&dd, 2 * nb, "alloc data staging");
+    if (!rc) rc = dev_alloc(&dp, nb, "alloc psd staging");
+    if (!rc) rc = hip_check(hipMemcpyAsync(dd, d->data, sizeof(double) * 2 * nb,
+                                           hipMemcpyHostToDevice, s), "copy data");
+    if (!rc) rc = hip_check(hipMemcpyAsync(dp, d->psd, sizeof(double) * nb,
+                                           hipMemcpyHostToDevice, s), "copy psd");
+    ddata = dd;
+    dpsd = dp;
+  }
+  if (!rc) {
+    launch_prep(P->grid, ddata, dpsd, P->b64, s);
+    launch_max(P->b64.u, nb, umax, s);
+    launch_scale(P->grid, umax, P->b64, P->b32, s);
+    rc = hip_check(hipGetLastError(), "prep launch");
+  }
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "plan prep");
+  dev_free(dd);
+  dev_free(dp);
+  dev_free(umax);
+  if (rc) {
+    fstat_plan_destroy(P);
+    return rc;
+  }
+  if (!(prec & FSTAT_FP64)) {
+    // the FP64 arrays are only needed to build the FP32 copies
+    dev_free(P->b64.wr); dev_free(P->b64.wi); dev_free(P->b64.u);
+    dev_free(P->b64.s0); dev_free(P->b64.c0);
+  }
+  *out = P;
+  return FSTAT_OK;
+}
+
+void fstat_plan_destroy(fstat_plan_t P) {
+  if (!P) return;
+  dev_free(P->b64.wr); dev_free(P->b64.wi); dev_free(P->b64.u);
+  dev_free(P->b64.s0); dev_free(P->b64.c0);
+  dev_free(P->b32.wr); dev_free(P->b32.wi); dev_free(P->b32.u);
+  dev_free(P->b32.s0); dev_free(P->b32.c0);
+  dev_free(P->ws.pc); dev_free(P->ws.bounds); dev_free(P->ws.cnt); dev_free(P->ws.off);
+  dev_free(P->ws.total); dev_free(P->ws.items); dev_free(P->ws.partials); dev_free(P->ws.Fl);
+  dev_free(P->io.params); dev_free(P->io.np); dev_free(P->io.F_hat); dev_free(P->io.F_part);
+  pso_release(P);
+  for (auto& e : P->events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  dev_free(P->bin_counter);
+  delete P;
+}
+
+int fstat_profile_read(fstat_plan_t P, int reset, double* kernel_ms, int64_t* launches,
+                       int64_t* bin_templates) {
+  g_err.clear();
+  if (!P || !P->profile) return set_error(FSTAT_EINVAL, "plan was not created with FSTAT_PROFILE");
+  double tot = 0.0;
+  for (auto& e : P->events) {
+    int rc = hip_check(hipEventSynchronize(e.second), "event sync");
+    if (rc) return rc;
+    float ms = 0.f;
+    if ((rc = hip_check(hipEventElapsedTime(&ms, e.first, e.second), "elapsed"))) return rc;
+    tot += ms;
+  }
+  unsigned long long bins = 0;
+  int rc = hip_check(hipMemcpy(&bins, P->bin_counter, sizeof(bins), hipMemcpyDeviceToHost), "read counter");
+  if (rc) return rc;
+  if (kernel_ms) *kernel_ms = tot;
+  if (launches) *launches = (int64_t)P->events.size();
+  if (bin_templates) *bin_templates = (int64_t)bins;
+  if (reset) {
+    for (auto& e : P->events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    P->events.clear();
+    rc = hip_check(hipMemset(P->bin_counter, 0, sizeof(unsigned long long)), "reset counter");
+  }
+  return rc;
+}
+
+int fstat_eval(fstat_plan_t P, const double* params, int64_t n, const int32_t* np,
+               int32_t np_uniform, double* F_hat, double* F_part, int64_t part_stride,
+               uint32_t flags, void* hip_stream) {
+  g_err.clear();
+  if (!P) return set_error(FSTAT_EINVAL, "null plan");
+  if (n < 0) return set_error(FSTAT_EINVAL, "n < 0");
+  if (n == 0) return FSTAT_OK;
+  if (!params || !F_hat) return set_error(FSTAT_EINVAL, "null params or F_hat");
+  const bool mixed = (flags & FSTAT_EVAL_MIXED) != 0;
+  const bool dev = (flags & FSTAT_DEVICE_PTRS) != 0;
+  if (mixed && !(P->prec & FSTAT_MIXED)) return set_error(FSTAT_EINVAL, "plan has no mixed data");
+  if (!mixed && !(P->prec & FSTAT_FP64)) return set_error(FSTAT_EINVAL, "plan has no FP64 data");
+  int32_t stride;
+  if (np) {
+    if (part_stride < 1 || part_stride > 65536)
+      return set_error(FSTAT_EINVAL, "part_stride must give the largest np (1..65536)");
+    stride = (int32_t)part_stride;
+  } else {
+    if (np_uniform < 1 || np_uniform > 65536) return set_error(FSTAT_EINVAL, "np_uniform out of range");
+    if (F_part && part_stride < np_uniform) return set_error(FSTAT_EINVAL, "part_stride < np");
+    stride = np_uniform;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (dev) return eval_device(P, params, n, np, np_uniform, stride, F_hat, F_part, part_stride, mixed, s);
+  // host pointers: validate, stage, run, copy back
+  for (int64_t i = 0; i < n; ++i) {
+    const double* t = params + 6 * i;
+    bool ok = true;
+    for (int k = 0; k < 6; ++k) ok = ok && std::isfinite(t[k]);
+    if (!ok || !(t[1] > 0.0) || !(std::fabs(t[2]) < 1.0) || !(t[5] >= 0.0))
+      return set_error(FSTAT_EINVAL, "particle %lld has invalid parameters", (long long)i);
+    if (np && (np[i] < 1 || np[i] > stride))
+      return set_error(FSTAT_EINVAL, "np[%lld] = %d outside 1..part_stride", (long long)i, np[i]);
+  }
+  int rc;
+  if ((rc = ensure(&P->io.params, &P->cap.params, (size_t)n * 6, "alloc params"))) return rc;
+  if ((rc = ensure(&P->io.np, &P->cap.np, (size_t)n, "alloc np"))) return rc;
+  if ((rc = ensure(&P->io.F_hat, &P->cap.F_hat, (size_t)n, "alloc F_hat"))) return rc;
+  int64_t ps = F_part ? part_stride : 0;
+  if (F_part && (rc = ensure(&P->io.F_part, &P->cap.F_part, (size_t)n * ps, "alloc F_part"))) return rc;
+  if ((rc = hip_check(hipMemcpyAsync(P->io.params, params, sizeof(double) * 6 * n,
+                                     hipMemcpyHostToDevice, s), "copy params"))) return rc;
+  if (np && (rc = hip_check(hipMemcpyAsync(P->io.np, np, sizeof(int32_t) * n,
+                                           hipMemcpyHostToDevice, s), "copy np"))) return rc;
+  if (F_part && (rc = hip_check(hipMemcpyAsync(P->io.F_part, F_part, sizeof(double) * n * ps,
+                                               hipMemcpyHostToDevice, s), "copy F_part"))) return rc;
+  rc = eval_device(P, P->io.params, n, np ? P->io.np : nullptr, np_uniform, stride, P->io.F_hat,
+                   F_part ? P->io.F_part : nullptr, ps, mixed, s);
+  if (rc) return rc;
+  if ((rc = hip_check(hipMemcpyAsync(F_hat, P->io.F_hat, sizeof(double) * n,
+                                     hipMemcpyDeviceToHost, s), "copy F_hat"))) return rc;
+  if (F_part && (rc = hip_check(hipMemcpyAsync(F_part, P->io.F_part, sizeof(double) * n * ps,
+                                               hipMemcpyDeviceToHost, s), "copy F_part"))) return rc;
+  return hip_check(hipStreamSynchronize(s), "eval");
+}
+
+int fstat_waveform(double T_obs, double df, int64_t k_lo, int64_t nbins, const double* params6,
+                   const double* amps4, double* out, uint32_t flags, void* hip_stream) {
+  g_err.clear();
+  if (nbins < 1 || nbins > INT32_MAX - 1 || !(df > 0.0) || k_lo < 1 || !(T_obs > 0.0))
+    return set_error(FSTAT_EINVAL, "bad grid");
+  if (!params6 || !amps4 || !out) return set_error(FSTAT_EINVAL, "null argument");
+  const bool dev = (flags & FSTAT_DEVICE_PTRS) != 0;
+  if (!dev) {
+    bool ok = true;
+    for (int k = 0; k < 6; ++k) ok = ok && std::isfinite(params6[k]);
+    for (int k = 0; k < 4; ++k) ok = ok && std::isfinite(amps4[k]);
+    if (!ok || !(params6[1] > 0.0) || !(std::fabs(params6[2]) < 1.0) || !(params6[5] >= 0.0))
+      return set_error(FSTAT_EINVAL, "invalid parameters");
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  Grid g{df, T_obs, k_lo, nbins};
+  WorkSpace ws{};
+  double *dpar = nullptr, *damp = nullptr, *dout = nullptr;
+  int rc = dev_alloc(&ws.pc, 1, "alloc pc");
+  if (!rc) rc = dev_alloc(&ws.bounds, 2, "alloc bounds");
+  if (!rc) rc = dev_alloc(&ws.cnt, 1, "alloc cnt");
+  const double* pp = params6;
+  const double* ap = amps4;
+  double* op = out;
+  if (!rc && !dev) {
+    rc = dev_alloc(&dpar, 6, "alloc params");
+    if (!rc) rc = dev_alloc(&damp, 4, "alloc amps");
+    if (!rc) rc = dev_alloc(&dout, 2 * nbins, "alloc out");
+    if (!rc) rc = hip_check(hipMemcpyAsync(dpar, params6, 6 * sizeof(double), hipMemcpyHostToDevice, s), "copy");
+    if (!rc) rc = hip_check(hipMemcpyAsync(damp, amps4, 4 * sizeof(double), hipMemcpyHostToDevice, s), "copy");
+    pp = dpar; ap = damp; op = dout;
+  }
+  if (!rc) {
+      launch_setup(g, pp, 1, nullptr, 1, 1, 1 << 24, nullptr, ws, s);
+    launch_waveform(g, ws.pc, ap, op, s);
+    rc = hip_check(hipGetLastError(), "waveform launch");
+  }
+  if (!rc && !dev)
+    rc = hip_check(hipMemcpyAsync(out, dout, sizeof(double) * 2 * nbins, hipMemcpyDeviceToHost, s), "copy out");
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "waveform");
+  dev_free(ws.pc); dev_free(ws.bounds); dev_free(ws.cnt);
+  dev_free(dpar); dev_free(damp); dev_free(dout);
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// fstat_api_internal.h -- plan object and helpers shared by the host-side
+// translation units of libfstat.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+#include <vector>
+
+#include "fstat_kernels.h"
+
+struct PsoState;  // defined in pso.hip
+
+struct fstat_plan_s {
+  int device = 0;
+  int num_cu = 0;
+  int prec = 0;
+  int chunk = 2048;
+  int blocks_fp64 = 0, blocks_mixed = 0;
+  fstat::Grid grid{};
+  fstat::BinData<double> b64{};
+  fstat::BinData<float> b32{};
+  fstat::WorkSpace ws{};
+  struct {
+    size_t pc = 0, bounds = 0, cnt = 0, off = 0, total = 0, items = 0, partials = 0, Fl = 0;
+    size_t params = 0, np = 0, F_hat = 0, F_part = 0;
+  } cap;
+  struct {
+    double* params = nullptr;
+    int32_t* np = nullptr;
+    double* F_hat = nullptr;
+    double* F_part = nullptr;
+  } io;
+  PsoState* pso = nullptr;
+  // profiling (FSTAT_PROFILE)
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  unsigned long long* bin_counter = nullptr;
+};
+
+namespace fstat {
+int set_error(int code, const char* fmt, ...);
+int hip_check(hipError_t e, const char* what);
+int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride);
+int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t* np,
+                int32_t np_uniform, int32_t stride, double* F_hat, double* F_part,
+                int64_t part_stride, bool mixed, hipStream_t s, const uint8_t* skip = nullptr,
+                bool allow_profile = true);
+int eval_blocks(fstat_plan_s* P, bool mixed);
+hipError_t occupancy_fp64(int* blocks_per_cu);
+hipError_t occupancy_mixed(int* blocks_per_cu);
+}  // namespace fstat
+
+void pso_release(fstat_plan_s* P);

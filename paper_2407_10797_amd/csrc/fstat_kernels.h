@@ -1,0 +1,58 @@
+// fstat_kernels.h -- host-side launchers of the libfstat kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fstat_internal.h"
+
+namespace fstat {
+
+// frequency grid f_j = (k_lo + j) df, j < nbins; support window [0, T_obs]
+struct Grid {
+  double df;
+  double T_obs;
+  int64_t k_lo;
+  int64_t nbins;
+};
+
+// per-bin prepared data of one precision (structure of arrays)
+template <typename T>
+struct BinData {
+  T* wr;   // Re w_j
+  T* wi;   // Im w_j
+  T* u;    // u_j
+  T* s0;   // sin(pi f_j L)
+  T* c0;   // cos(pi f_j L)
+};
+
+struct WorkSpace {
+  PartConst* pc;      // [n]
+  int32_t* bounds;    // [n][stride + 1]
+  int32_t* cnt;       // [n][stride]
+  int32_t* off;       // [n][stride]
+  int32_t* total;     // [1]
+  int2* items;        // [capacity]
+  double* partials;   // [capacity][8]
+  double* Fl;         // [n][stride]
+};
+
+void launch_prep(const Grid& g, const double* data, const double* psd, BinData<double> b,
+                 hipStream_t s);
+void launch_max(const double* u, int64_t n, double* out, hipStream_t s);
+void launch_scale(const Grid& g, const double* umax, BinData<double> b, BinData<float> b32,
+                  hipStream_t s);
+void launch_setup(const Grid& g, const double* params, int64_t n,
+                  const int32_t* np, int32_t np_uniform, int32_t stride, int32_t chunk,
+                  const uint8_t* skip, const WorkSpace& ws, hipStream_t s);
+void launch_worklist(int64_t m, const WorkSpace& ws, hipStream_t s);
+void launch_eval(bool mixed, const Grid& g, int32_t stride, int32_t chunk,
+                 const WorkSpace& ws, BinData<double> b, BinData<float> b32, int blocks,
+                 hipStream_t s);
+void launch_solve_mean(int64_t n, int32_t stride, const WorkSpace& ws, double* F_hat,
+                       double* F_part, int64_t part_stride, unsigned long long* bin_counter,
+                       hipStream_t s);
+void launch_waveform(const Grid& g, const PartConst* pc, const double* amps,
+                     double* out, hipStream_t s);
+
+}  // namespace fstat

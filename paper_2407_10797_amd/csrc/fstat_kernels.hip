@@ -1,0 +1,665 @@
+// fstat_kernels.hip -- gfx950 kernels of the batched semi-coherent F-statistic.
+//
+// One evaluation (Sec. II.B, Eq. semi-cohF of arXiv:2407.10797) is a chain of
+// small kernels around one heavy one:
+//   k_setup   one thread per particle: intrinsic parameters -> PN constants,
+//             sky frame, support [f_lo, f_hi] (bisection on t_f), Np partition
+//             boundaries (bin indices) and work-item counts per partition
+//   k_scan    exclusive scan of the work-item counts (one block)
+//   k_fill    work list: item -> (particle*stride + partition, chunk)
+//   k_eval_*  persistent grid, one wavefront per work item: for every bin of the
+//             chunk evaluate phase, t_f, TDI-X response and accumulate the eight
+//             partition sums {Z+, Zx, P, Q, R}; wavefront reduction; one partial
+//             per work item (deterministic, no atomics)
+//   k_solve   one thread per (particle, partition): ordered sum of partials and
+//             the 2x2 Hermitian closed form of F_l
+//   k_mean    one thread per particle: F_hat = mean_l F_l, or -inf / NaN
+#include "fstat_internal.h"
+#include "fstat_kernels.h"
+
+namespace fstat {
+
+// ---------------------------------------------------------------------------
+// plan-time per-bin preparation
+// ---------------------------------------------------------------------------
+// C(f) = (1 - z^2)(-i pi f L) exp(-i pi f L), z = exp(-2 i pi f L): the part of
+// the TDI-X transfer shared by every template.  With g = f^{-7/6} e^{-i Psi}
+// (App. A) and <a,b> = 4 df Re sum a conj(b) / S (Sec. II.A):
+//   w_j = 4 df s_j conj(C_j) f_j^{-7/6} / S_j,   u_j = 4 df |C_j|^2 f_j^{-7/3} / S_j.
+__global__ void k_prep(Grid g, const double* __restrict__ data, const double* __restrict__ psd,
+                       double* __restrict__ wr, double* __restrict__ wi, double* __restrict__ u,
+                       double* __restrict__ s0, double* __restrict__ c0) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= g.nbins) return;
+  double f = (double)(g.k_lo + j) * g.df;
+  double s, c;
+  sincospi(kLs * f, &s, &c);
+  double x0 = kPi * kLs * f;
+  double zr = c * c - s * s, zi = -2.0 * s * c;
+  double omr = 1.0 - (zr * zr - zi * zi), omi = -2.0 * zr * zi;  // 1 - z^2
+  double er = -x0 * s, ei = -x0 * c;                               // -i x0 e^{-i x0}
+  double Cr = omr * er - omi * ei, Ci = omr * ei + omi * er;
+  double amp = pow(f, -7.0 / 6.0);
+  double wgt = 4.0 * g.df / psd[j];
+  double dr = data[2 * j], di = data[2 * j + 1];
+  // s conj(C)
+  double pr = dr * Cr + di * Ci, pi = di * Cr - dr * Ci;
+  wr[j] = wgt * amp * pr;
+  wi[j] = wgt * amp * pi;
+  u[j] = wgt * amp * amp * (Cr * Cr + Ci * Ci);
+  s0[j] = s;
+  c0[j] = c;
+}
+
+// max of u over the band (one block, grid-stride) -> *out
+__global__ void k_max(const double* __restrict__ u, int64_t n, double* __restrict__ out) {
+  __shared__ double red[1024];
+  double m = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) m = fmax(m, u[j]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// Normalise so that max u = 1: F is invariant under (w, u) -> (g w, g^2 u)
+// (a rescaling of the template), and FP32 copies stay in range.
+__global__ void k_scale(Grid g, const double* __restrict__ umax, double* __restrict__ wr,
+                        double* __restrict__ wi, double* __restrict__ u,
+                        const double* __restrict__ s0, const double* __restrict__ c0,
+                        float* __restrict__ wr32, float* __restrict__ wi32,
+                        float* __restrict__ u32, float* __restrict__ s032,
+                        float* __restrict__ c032) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= g.nbins) return;
+  double m = umax[0];
+  double gam2 = (m > 0.0) ? 1.0 / m : 1.0;
+  double gam = sqrt(gam2);
+  double a = wr[j] * gam, b = wi[j] * gam, c = u[j] * gam2;
+  wr[j] = a; wi[j] = b; u[j] = c;
+  if (wr32) {
+    wr32[j] = (float)a; wi32[j] = (float)b; u32[j] = (float)c;
+    s032[j] = (float)s0[j]; c032[j] = (float)c0[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// particle setup: constants, support, partition boundaries, work counts
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double bin_freq(const Grid& g, int64_t j) {
+  return (double)(g.k_lo + j) * g.df;
+}
+
+// smallest j in [lo, hi+1] with f_j >= e
+__device__ int first_bin_at_or_above(const Grid& g, double e, int lo, int hi) {
+  double jd = ceil(e / g.df) - (double)g.k_lo;
+  int j = (jd < (double)lo) ? lo : (jd > (double)(hi + 1) ? hi + 1 : (int)jd);
+  while (j > lo && bin_freq(g, j - 1) >= e) --j;
+  while (j <= hi && bin_freq(g, j) < e) ++j;
+  return j;
+}
+
+__device__ double tf_only(const PartConst& P, double f) {
+  double fr, tf;
+  phase_and_tf(P, f, fr, tf);
+  return tf;
+}
+
+// frequency where t_f reaches t, by bisection on [fa, fb]
+__device__ double invert_tf(const PartConst& P, double t, double fa, double fb) {
+  for (int it = 0; it < 200; ++it) {
+    double fm = 0.5 * (fa + fb);
+    if (fm <= fa || fm >= fb) break;
+    if (tf_only(P, fm) < t) fa = fm; else fb = fm;
+  }
+  return fb;
+}
+
+// Per-particle phase coefficients (see PartConst), double-double where the
+// term they multiply reaches 10^2..10^7 cycles.
+__host__ __device__ void fill_constants(PartConst& P, const double* th) {
+  FSTAT_NO_CONTRACT
+  double tc = th[0], mc = th[1], dmu = th[2], theta = th[3], phi = th[4], e0 = th[5];
+  P.tc = tc;
+  dd m = two_prod(mc, kMsunS);                       // Mc [s], exact
+  P.mc_hi = m.hi; P.mc_lo = m.lo;
+  dd d2 = two_prod(dmu, dmu);
+  dd one_m = dd_add(dd{1.0, 0.0}, dd{-d2.hi, -d2.lo});
+  dd eta = dd{one_m.hi * 0.25, one_m.lo * 0.25};      // (1 - dmu^2)/4
+  const dd pi = {3.141592653589793116e+00, 1.2246467991473532e-16};
+  dd pi13 = dd_root(pi, 3, cbrt(pi.hi));
+  dd ie5 = dd_root(dd_div(dd{1.0, 0.0}, eta), 5, pow(eta.hi, -0.2));   // eta^{-1/5}
+  dd vfac = dd_mul(pi13, ie5);                        // v = vfac (Mc f)^{1/3}
+  dd vf2 = dd_mul(vfac, vfac), vf3 = dd_mul(vf2, vfac);
+  dd pi2 = dd_mul(pi, pi);
+  dd cN = dd_div(dd{3.0, 0.0}, dd_mul_d(dd_mul(pi2, dd_mul(pi13, pi13)), 256.0));
+  dd a2 = dd_add(dd_ratio(3715.0, 756.0), dd_mul(dd_ratio(55.0, 9.0), eta));
+  dd c1 = dd_mul(dd_mul(cN, a2), vf2);
+  dd c15 = dd_mul(dd_mul(cN, dd_mul_d(pi, -16.0)), vf3);
+  dd z = dd_mul_d(m, kF0Ecc);                         // f0 Mc
+  dd z19 = dd_mul(dd_mul(z, z), dd_root(z, 9, pow(z.hi, 1.0 / 9.0)));   // (f0 Mc)^{19/9}
+  dd ce = dd_mul(dd_mul(cN, dd_ratio(-2355.0, 1462.0)), dd_mul(two_prod(e0, e0), z19));
+  P.cN_hi = cN.hi; P.cN_lo = cN.lo;
+  P.c1_hi = c1.hi; P.c1_lo = c1.lo;
+  P.c15_hi = c15.hi; P.c15_lo = c15.lo;
+  P.ce_hi = ce.hi; P.ce_lo = ce.lo;
+  double et = eta.hi, vf = vfac.hi, K = cN.hi;
+  const double pisq = kPi * kPi;
+  double a4 = 15293365.0 / 508032.0 + 27145.0 * et / 504.0 + 3085.0 * et * et / 72.0;
+  double c5p = kPi * (38645.0 / 756.0 - 65.0 * et / 9.0);
+  const double euler = 0.57721566490153286061;
+  double a6c = 11583231236531.0 / 4694215680.0 - 640.0 * pisq / 3.0 - 6848.0 * euler / 21.0 +
+               (-15737765635.0 / 3048192.0 + 2255.0 * pisq / 12.0) * et +
+               76055.0 * et * et / 1728.0 - 127825.0 * et * et * et / 1296.0;
+  double vf4 = vf * vf * vf * vf, vf5 = vf4 * vf, vf6 = vf5 * vf;
+  P.c2 = K * a4 * vf4;
+  P.c5v5 = K * c5p * vf5;
+  P.c5 = 3.0 * P.c5v5;
+  P.c6 = K * vf6;
+  P.b6 = -6848.0 / 21.0;
+  P.a6k = a6c + P.b6 * log(4.0);
+  P.ln_vfac = log(vf);
+  double st, ct, sp, cp;
+  sincos(theta, &st, &ct);
+  sincos(phi, &sp, &cp);
+  P.k[0] = -st * cp; P.k[1] = -st * sp; P.k[2] = -ct;
+  P.u[0] = ct * cp;  P.u[1] = ct * sp;  P.u[2] = -st;
+  P.v[0] = sp;       P.v[1] = -cp;      P.v[2] = 0.0;
+}
+
+__global__ void k_setup(Grid g, const double* __restrict__ params, int64_t n,
+                        const int32_t* __restrict__ np, int32_t np_uniform, int32_t stride,
+                        int32_t chunk, const uint8_t* __restrict__ skip,
+                        PartConst* __restrict__ pc, int32_t* __restrict__ bounds,
+                        int32_t* __restrict__ cnt) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const double* th = params + 6 * p;
+  int npi = np ? np[p] : np_uniform;
+  PartConst P;
+  bool ok = true;
+  for (int i = 0; i < 6; ++i) ok = ok && isfinite(th[i]);
+  ok = ok && th[1] > 0.0 && fabs(th[2]) < 1.0 && th[5] >= 0.0 && npi >= 1 && npi <= stride;
+  int32_t* bp = bounds + p * (int64_t)(stride + 1);
+  int32_t* cp = cnt + p * (int64_t)stride;
+  for (int l = 0; l < stride; ++l) cp[l] = 0;
+  P.np = npi;
+  P.j_lo = 0; P.j_hi = -1;
+  if (!ok) {
+    P.status = kStatusInvalid;
+    pc[p] = P;
+    return;
+  }
+  if (skip && skip[p]) {  // outside the search box: not evaluated (let-them-fly)
+    P.status = kStatusEmpty;
+    pc[p] = P;
+    return;
+  }
+  fill_constants(P, th);
+  int last = (int)g.nbins - 1;
+  double f_first = bin_freq(g, 0), f_last = bin_freq(g, last);
+  double t_first = tf_only(P, f_first), t_last = tf_only(P, f_last);
+  bool empty = (t_last < 0.0) || (t_first > g.T_obs);
+  double flo = 0.0, fhi = 0.0;
+  if (!empty) {
+    flo = (t_first >= 0.0) ? f_first : invert_tf(P, 0.0, f_first, f_last);
+    fhi = (t_last <= g.T_obs) ? f_last : invert_tf(P, g.T_obs, f_first, f_last);
+    empty = !(flo <= fhi);
+  }
+  int jlo = 0, jhi = -1;
+  if (!empty) {
+    jlo = first_bin_at_or_above(g, flo, 0, last);
+    // largest j with f_j <= fhi
+    int j = first_bin_at_or_above(g, fhi, 0, last);
+    if (j > last || bin_freq(g, j) > fhi) --j;
+    jhi = j;
+    empty = jlo > jhi;
+  }
+  P.flo = flo; P.fhi = fhi;
+  if (empty) {
+    P.status = kStatusEmpty;
+    pc[p] = P;
+    return;
+  }
+  P.status = kStatusOk;
+  P.j_lo = jlo; P.j_hi = jhi;
+  pc[p] = P;
+  double span = fhi - flo;
+  bp[0] = jlo;
+  int prev = jlo;
+  for (int l = 1; l < npi; ++l) {
+    double e = flo + (span * (double)l) / (double)npi;
+    int b = first_bin_at_or_above(g, e, prev, jhi);
+    bp[l] = b;
+    prev = b;
+  }
+  bp[npi] = jhi + 1;
+  for (int l = 0; l < npi; ++l) {
+    int nb = bp[l + 1] - bp[l];
+    cp[l] = (nb + chunk - 1) / chunk;
+  }
+}
+
+// exclusive scan of cnt[m] into off[m]; total -> *total (single block)
+__global__ void k_scan(const int32_t* __restrict__ cnt, int64_t m, int32_t* __restrict__ off,
+                       int32_t* __restrict__ total) {
+  __shared__ int64_t part[1024];
+  int t = threadIdx.x, T = blockDim.x;
+  int64_t per = (m + T - 1) / T;
+  int64_t a = t * per, b = a + per < m ? a + per : m;
+  int64_t s = 0;
+  for (int64_t i = a; i < b; ++i) s += cnt[i];
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    int64_t run = 0;
+    for (int i = 0; i < T; ++i) { int64_t v = part[i]; part[i] = run; run += v; }
+    total[0] = (int32_t)run;
+  }
+  __syncthreads();
+  int64_t run = part[t];
+  for (int64_t i = a; i < b; ++i) { off[i] = (int32_t)run; run += cnt[i]; }
+}
+
+__global__ void k_fill(const int32_t* __restrict__ cnt, const int32_t* __restrict__ off, int64_t m,
+                       int2* __restrict__ items) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  int c = cnt[q], o = off[q];
+  for (int i = 0; i < c; ++i) items[o + i] = make_int2((int)q, i);
+}
+
+// ---------------------------------------------------------------------------
+// the hot loop, FP64
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void kahan_add(double& s, double& c, double x) {
+  double y = x - c;
+  double t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
+                                                   const PartConst* __restrict__ pc,
+                                                   const int32_t* __restrict__ bounds, int32_t stride,
+                                                   const int2* __restrict__ items,
+                                                   const int32_t* __restrict__ total, int32_t chunk,
+                                                   const double* __restrict__ wr,
+                                                   const double* __restrict__ wi,
+                                                   const double* __restrict__ u,
+                                                   const double* __restrict__ s0a,
+                                                   const double* __restrict__ c0a,
+                                                   double* __restrict__ partials) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const int W = total[0];
+  for (int w = wave; w < W; w += nwaves) {
+    int2 it = items[w];
+    int q = __builtin_amdgcn_readfirstlane(it.x);
+    int c = __builtin_amdgcn_readfirstlane(it.y);
+    int p = q / stride, l = q - p * stride;
+    const PartConst& P = pc[p];
+    const int32_t* bp = bounds + (int64_t)p * (stride + 1);
+    int b0 = bp[l] + c * chunk;
+    int b1 = min(bp[l + 1], b0 + chunk);
+    // Kahan-compensated per-lane sums (true sum ~ acc - cmp): the partition
+    // matrix can have cond ~ 1e5..1e8, which amplifies summation error.
+    double acc[8], cmp[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = cmp[i] = 0.0;
+    for (int j = b0 + lane; j < b1; j += 64) {
+      double f = bin_freq(g, j);
+      double fr, tf;
+      phase_and_tf(P, f, fr, tf);
+      double sps, cps;
+      sincospi(2.0 * fr, &sps, &cps);   // e^{i Psi}
+      double tpr, tpi, txr, txi;
+      response_fp64(P, f, tf, s0a[j], c0a[j], tpr, tpi, txr, txi);
+      double a = wr[j], b = wi[j], uu = u[j];
+      double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Psi}
+      double t[8];
+      t[0] = Wr * tpr + Wi * tpi;     // Z+ = sum W conj(T'+)
+      t[1] = Wi * tpr - Wr * tpi;
+      t[2] = Wr * txr + Wi * txi;     // Zx
+      t[3] = Wi * txr - Wr * txi;
+      t[4] = uu * (tpr * tpr + tpi * tpi);
+      t[5] = uu * (txr * txr + txi * txi);
+      t[6] = uu * (tpr * txr + tpi * txi);   // R = sum u T'+ conj(T'x)
+      t[7] = uu * (tpi * txr - tpr * txi);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) kahan_add(acc[i], cmp[i], t[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = wave_sum(acc[i] - cmp[i]);
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = acc[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the hot loop, mixed precision
+// ---------------------------------------------------------------------------
+// FP64: phase (cycles, double-double), SPA time, orbit angle and the large
+// Doppler term 2 k.(guiding centre) (1000 s, needs ~1e-12 relative).
+// FP32: constellation offsets, arm directions, antenna patterns, link sincs,
+// the reduced Doppler and template phases (hardware sin/cos on revolutions
+// reduced to [-1/2, 1/2]), products and Kahan-compensated partition sums.
+__device__ __forceinline__ void sincos_rev(double rev, float& s, float& c) {
+  double r = rev - rint(rev);            // [-1/2, 1/2] revolutions
+  float rf = (float)r;
+  s = __builtin_amdgcn_sinf(rf);         // sin(2 pi rf)
+  c = __builtin_amdgcn_cosf(rf);
+}
+__device__ __forceinline__ void sincos_revf(float r, float& s, float& c) {
+  r = r - rintf(r);
+  s = __builtin_amdgcn_sinf(r);
+  c = __builtin_amdgcn_cosf(r);
+}
+__device__ __forceinline__ float sincf_from(float num, float den) {
+  return (fabsf(den) < 1e-3f) ? 1.0f - den * den * (1.0f / 6.0f) : num / den;
+}
+__device__ __forceinline__ void kahan_addf(float& s, float& c, float x) {
+  float y = x - c;
+  float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+__device__ __forceinline__ void response_mixed(const PartConst& P, double f, double tf, float s0,
+                                               float c0, float& tpr, float& tpi, float& txr,
+                                               float& txi) {
+  double sad, cad;
+  sincospi(2.0 * tf * (1.0 / kYear), &sad, &cad);
+  double kP2 = 2.0 * kRs * (P.k[0] * cad + P.k[1] * sad);   // seconds, FP64
+  float sa = (float)sad, ca = (float)cad;
+  float c2a = ca * ca - sa * sa, s2a = 2.0f * sa * ca;
+  const float q = (float)(kLs / (4.0 * kSqrt3));
+  const float hz = (float)(0.5 * kLs);
+  const float cb1 = -0.5f, sb1 = (float)(0.5 * kSqrt3), cb2 = -0.5f, sb2 = -(float)(0.5 * kSqrt3);
+  float d0x = q * (c2a - 3.0f), d0y = q * s2a, d0z = -hz * ca;
+  float d1x = q * (c2a * cb1 + s2a * sb1 - 3.0f * cb1);
+  float d1y = q * (s2a * cb1 - c2a * sb1 - 3.0f * sb1);
+  float d1z = -hz * (ca * cb1 + sa * sb1);
+  float d2x = q * (c2a * cb2 + s2a * sb2 - 3.0f * cb2);
+  float d2y = q * (s2a * cb2 - c2a * sb2 - 3.0f * sb2);
+  float d2z = -hz * (ca * cb2 + sa * sb2);
+  const float kx = (float)P.k[0], ky = (float)P.k[1], kz = (float)P.k[2];
+  const float ux = (float)P.u[0], uy = (float)P.u[1], uz = (float)P.u[2];
+  const float vx = (float)P.v[0], vy = (float)P.v[1], vz = (float)P.v[2];
+  float kd0 = kx * d0x + ky * d0y + kz * d0z;
+  float kd1 = kx * d1x + ky * d1y + kz * d1z;
+  float kd2 = kx * d2x + ky * d2y + kz * d2z;
+  const float fl = (float)f;
+  const float x0 = (float)(kPi * kLs) * fl;
+  float zr = c0 * c0 - s0 * s0, zi = -2.0f * s0 * c0;
+  float out[2][4];
+#pragma unroll
+  for (int arm = 0; arm < 2; ++arm) {
+    float ax = (arm == 0 ? d1x : d2x) - d0x;
+    float ay = (arm == 0 ? d1y : d2y) - d0y;
+    float az = (arm == 0 ? d1z : d2z) - d0z;
+    float inv = __builtin_amdgcn_rsqf(ax * ax + ay * ay + az * az);
+    ax *= inv; ay *= inv; az *= inv;
+    float kn = kx * ax + ky * ay + kz * az;
+    float un = ux * ax + uy * ay + uz * az;
+    float vn = vx * ax + vy * ay + vz * az;
+    // exp(-i pi f k.(p0 + p_arm)): -f kp / 2 revolutions, reduced in FP64
+    double kp = kP2 + (double)(kd0 + (arm == 0 ? kd1 : kd2));
+    float se, ce;
+    sincos_rev(-0.5 * f * kp, se, ce);
+    float sq, cq;
+    sincos_revf(0.5f * (float)kLs * fl * kn, sq, cq);
+    float sp = sincf_from(s0 * cq + c0 * sq, x0 * (1.0f + kn));
+    float sm = sincf_from(s0 * cq - c0 * sq, x0 * (1.0f - kn));
+    float Sr = sp + zr * sm, Si = zi * sm;
+    out[arm][0] = ce * Sr - se * Si;
+    out[arm][1] = ce * Si + se * Sr;
+    out[arm][2] = un * un - vn * vn;
+    out[arm][3] = 2.0f * un * vn;
+  }
+  tpr = out[1][2] * out[1][0] - out[0][2] * out[0][0];
+  tpi = out[1][2] * out[1][1] - out[0][2] * out[0][1];
+  txr = out[1][3] * out[1][0] - out[0][3] * out[0][0];
+  txi = out[1][3] * out[1][1] - out[0][3] * out[0][1];
+}
+
+__global__ __launch_bounds__(256) void k_eval_mixed(Grid g,
+                                                    const PartConst* __restrict__ pc,
+                                                    const int32_t* __restrict__ bounds, int32_t stride,
+                                                    const int2* __restrict__ items,
+                                                    const int32_t* __restrict__ total, int32_t chunk,
+                                                    const float* __restrict__ wr,
+                                                    const float* __restrict__ wi,
+                                                    const float* __restrict__ u,
+                                                    const float* __restrict__ s0a,
+                                                    const float* __restrict__ c0a,
+                                                    double* __restrict__ partials) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const int W = total[0];
+  for (int w = wave; w < W; w += nwaves) {
+    int2 it = items[w];
+    int q = __builtin_amdgcn_readfirstlane(it.x);
+    int c = __builtin_amdgcn_readfirstlane(it.y);
+    int p = q / stride, l = q - p * stride;
+    const PartConst& P = pc[p];
+    const int32_t* bp = bounds + (int64_t)p * (stride + 1);
+    int b0 = bp[l] + c * chunk;
+    int b1 = min(bp[l + 1], b0 + chunk);
+    float acc[8], cmp[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = cmp[i] = 0.0f;
+    for (int j = b0 + lane; j < b1; j += 64) {
+      double f = bin_freq(g, j);
+      double fr, tf;
+      phase_and_tf(P, f, fr, tf);
+      float sps, cps;
+      sincos_rev(fr, sps, cps);
+      float tpr, tpi, txr, txi;
+      response_mixed(P, f, tf, s0a[j], c0a[j], tpr, tpi, txr, txi);
+      float a = wr[j], b = wi[j], uu = u[j];
+      float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
+      float t[8];
+      t[0] = Wr * tpr + Wi * tpi;
+      t[1] = Wi * tpr - Wr * tpi;
+      t[2] = Wr * txr + Wi * txi;
+      t[3] = Wi * txr - Wr * txi;
+      t[4] = uu * (tpr * tpr + tpi * tpi);
+      t[5] = uu * (txr * txr + txi * txi);
+      t[6] = uu * (tpr * txr + tpi * txi);
+      t[7] = uu * (tpi * txr - tpr * txi);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) kahan_addf(acc[i], cmp[i], t[i]);
+    }
+    double red[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) red[i] = wave_sum((double)acc[i] - (double)cmp[i]);
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = red[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// solve and mean
+// ---------------------------------------------------------------------------
+__global__ void k_solve(const PartConst* __restrict__ pc, int64_t n, int32_t stride,
+                        const int32_t* __restrict__ cnt, const int32_t* __restrict__ off,
+                        const double* __restrict__ partials, double* __restrict__ Fl,
+                        double* __restrict__ F_part, int64_t part_stride) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n * stride) return;
+  int64_t p = q / stride;
+  int l = (int)(q - p * stride);
+  const PartConst& P = pc[p];
+  if (l >= P.np || P.status == kStatusInvalid) return;
+  double F = 0.0;
+  if (P.status == kStatusOk) {
+    double a[8], e[8];
+    for (int k = 0; k < 8; ++k) a[k] = e[k] = 0.0;
+    int o = off[q], c = cnt[q];
+    for (int i = 0; i < c; ++i)
+      for (int k = 0; k < 8; ++k) {  // Neumaier sum over the chunks, in order
+        double x = partials[(int64_t)(o + i) * 8 + k];
+        double t = a[k] + x;
+        e[k] += (fabs(a[k]) >= fabs(x)) ? (a[k] - t) + x : (x - t) + a[k];
+        a[k] = t;
+      }
+    for (int k = 0; k < 8; ++k) a[k] += e[k];
+    F = solve_partition(a);
+  }
+  Fl[q] = F;
+  if (F_part) F_part[p * part_stride + l] = F;
+}
+
+__global__ void k_mean(const PartConst* __restrict__ pc, int64_t n, int32_t stride,
+                       const double* __restrict__ Fl, double* __restrict__ F_hat,
+                       double* __restrict__ F_part, int64_t part_stride,
+                       unsigned long long* __restrict__ bin_counter) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const PartConst& P = pc[p];
+  if (P.status == kStatusInvalid) {
+    F_hat[p] = __builtin_nan("");
+    if (F_part)
+      for (int l = 0; l < P.np && l < part_stride; ++l) F_part[p * part_stride + l] = __builtin_nan("");
+    return;
+  }
+  if (P.status == kStatusEmpty) {
+    F_hat[p] = -__builtin_inf();
+    return;
+  }
+  double s = 0.0;
+  for (int l = 0; l < P.np; ++l) s += Fl[p * stride + l];
+  F_hat[p] = s / (double)P.np;
+  if (bin_counter) atomicAdd(bin_counter, (unsigned long long)(P.j_hi - P.j_lo + 1));
+}
+
+// ---------------------------------------------------------------------------
+// template signal (for injections): sum_i a_i A^i with the full transfer
+// ---------------------------------------------------------------------------
+__global__ void k_waveform(Grid g, const PartConst* __restrict__ pc,
+                           const double* __restrict__ amps, double* __restrict__ out) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= g.nbins) return;
+  const PartConst& P = pc[0];
+  if (P.status != kStatusOk || j < P.j_lo || j > P.j_hi) {
+    out[2 * j] = 0.0;
+    out[2 * j + 1] = 0.0;
+    return;
+  }
+  double f = bin_freq(g, j);
+  double fr, tf;
+  phase_and_tf(P, f, fr, tf);
+  double sps, cps;
+  sincospi(2.0 * (fr - 0.125), &sps, &cps);   // Psi includes -pi/4 (App. A)
+  double s0, c0;
+  sincospi(kLs * f, &s0, &c0);
+  double tpr, tpi, txr, txi;
+  response_fp64(P, f, tf, s0, c0, tpr, tpi, txr, txi);
+  // full transfer T = C T'
+  double x0 = kPi * kLs * f;
+  double zr = c0 * c0 - s0 * s0, zi = -2.0 * s0 * c0;
+  double omr = 1.0 - (zr * zr - zi * zi), omi = -2.0 * zr * zi;
+  double er = -x0 * s0, ei = -x0 * c0;
+  double Cr = omr * er - omi * ei, Ci = omr * ei + omi * er;
+  double Tpr = Cr * tpr - Ci * tpi, Tpi = Cr * tpi + Ci * tpr;
+  double Txr = Cr * txr - Ci * txi, Txi = Cr * txi + Ci * txr;
+  // h = g [(a1 - i a3) T+ + (-a2 + i a4) Tx],  g = f^{-7/6} e^{-i Psi}
+  double a1 = amps[0], a2 = amps[1], a3 = amps[2], a4 = amps[3];
+  double hr = (a1 * Tpr + a3 * Tpi) + (-a2 * Txr - a4 * Txi);
+  double hi = (a1 * Tpi - a3 * Tpr) + (-a2 * Txi + a4 * Txr);
+  double amp = pow(f, -7.0 / 6.0);
+  // multiply by e^{-i Psi} = cps - i sps
+  out[2 * j] = amp * (hr * cps + hi * sps);
+  out[2 * j + 1] = amp * (hi * cps - hr * sps);
+}
+
+}  // namespace fstat
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+namespace fstat {
+
+static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_prep(const Grid& g, const double* data, const double* psd, BinData<double> b,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_prep, dim3(nblk(g.nbins, 256)), dim3(256), 0, s, g, data, psd, b.wr, b.wi,
+                     b.u, b.s0, b.c0);
+}
+
+void launch_max(const double* u, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_max, dim3(1), dim3(1024), 0, s, u, n, out);
+}
+
+void launch_scale(const Grid& g, const double* umax, BinData<double> b, BinData<float> b32,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(nblk(g.nbins, 256)), dim3(256), 0, s, g, umax, b.wr, b.wi, b.u,
+                     b.s0, b.c0, b32.wr, b32.wi, b32.u, b32.s0, b32.c0);
+}
+
+void launch_setup(const Grid& g, const double* params, int64_t n,
+                  const int32_t* np, int32_t np_uniform, int32_t stride, int32_t chunk,
+                  const uint8_t* skip, const WorkSpace& ws, hipStream_t s) {
+  hipLaunchKernelGGL(k_setup, dim3(nblk(n, 64)), dim3(64), 0, s, g, params, n, np, np_uniform,
+                     stride, chunk, skip, ws.pc, ws.bounds, ws.cnt);
+}
+
+void launch_worklist(int64_t m, const WorkSpace& ws, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ws.cnt, m, ws.off, ws.total);
+  hipLaunchKernelGGL(k_fill, dim3(nblk(m, 256)), dim3(256), 0, s, ws.cnt, ws.off, m, ws.items);
+}
+
+void launch_eval(bool mixed, const Grid& g, int32_t stride, int32_t chunk,
+                 const WorkSpace& ws, BinData<double> b, BinData<float> b32, int blocks,
+                 hipStream_t s) {
+  if (mixed)
+    hipLaunchKernelGGL(k_eval_mixed, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
+                       ws.items, ws.total, chunk, b32.wr, b32.wi, b32.u, b32.s0, b32.c0,
+                       ws.partials);
+  else
+    hipLaunchKernelGGL(k_eval_fp64, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
+                       ws.items, ws.total, chunk, b.wr, b.wi, b.u, b.s0, b.c0, ws.partials);
+}
+
+void launch_solve_mean(int64_t n, int32_t stride, const WorkSpace& ws, double* F_hat,
+                       double* F_part, int64_t part_stride, unsigned long long* bin_counter,
+                       hipStream_t s) {
+  int64_t m = n * stride;
+  hipLaunchKernelGGL(k_solve, dim3(nblk(m, 256)), dim3(256), 0, s, ws.pc, n, stride, ws.cnt,
+                     ws.off, ws.partials, ws.Fl, F_part, part_stride);
+  hipLaunchKernelGGL(k_mean, dim3(nblk(n, 256)), dim3(256), 0, s, ws.pc, n, stride, ws.Fl, F_hat,
+                     F_part, part_stride, bin_counter);
+}
+
+void launch_waveform(const Grid& g, const PartConst* pc, const double* amps,
+                     double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_waveform, dim3(nblk(g.nbins, 256)), dim3(256), 0, s, g, pc, amps, out);
+}
+
+}  // namespace fstat
+
+namespace fstat {
+hipError_t occupancy_fp64(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_eval_fp64, 256, 0);
+}
+hipError_t occupancy_mixed(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_eval_mixed, 256, 0);
+}
+}  // namespace fstat

@@ -1,0 +1,245 @@
+"""Python binding of libfstat (include/fstat.h): argument marshalling only.
+
+Every step of the F-statistic runs in the HIP kernels of ``libfstat.so``;
+PyTorch supplies device memory and the current HIP stream.  If the library
+has not been built this module raises on first use: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfstat.so")
+
+FSTAT_OK = 0
+FSTAT_EINVAL = -1
+FSTAT_ENOMEM = -2
+FSTAT_EDEVICE = -3
+FSTAT_EUNSUPPORTED = -4
+FSTAT_FP64 = 1
+FSTAT_MIXED = 2
+FSTAT_DEVICE_PTRS = 1
+FSTAT_EVAL_MIXED = 2
+FSTAT_PROFILE = 4
+
+EXPORTS = ("fstat_plan_create", "fstat_eval", "fstat_waveform", "pso_stage",
+           "fstat_profile_read", "fstat_plan_destroy", "fstat_last_error")
+
+
+class fstat_data_desc(ctypes.Structure):
+    _fields_ = [("T_obs", ctypes.c_double), ("df", ctypes.c_double),
+                ("k_lo", ctypes.c_int64), ("nbins", ctypes.c_int64),
+                ("data", ctypes.c_void_p), ("psd", ctypes.c_void_p)]
+
+
+class fstat_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class pso_stage_desc(ctypes.Structure):
+    _fields_ = [("n_runs", ctypes.c_int32), ("n_part", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("ring_k", ctypes.c_int32),
+                ("w_start", ctypes.c_double), ("w_end", ctypes.c_double),
+                ("c1", ctypes.c_double), ("c2", ctypes.c_double), ("vmax", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("box", ctypes.c_void_p), ("np", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32), ("use_graph", ctypes.c_int32)]
+
+
+class pso_result(ctypes.Structure):
+    _fields_ = [("best_x", ctypes.c_void_p), ("best_F", ctypes.c_void_p),
+                ("trace", ctypes.c_void_p), ("final_x", ctypes.c_void_p)]
+
+
+class FstatError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libfstat error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libfstat.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
+        L.fstat_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(fstat_data_desc),
+                                        ctypes.POINTER(fstat_opts), vp]
+        L.fstat_plan_create.restype = ctypes.c_int
+        L.fstat_eval.argtypes = [vp, vp, i64, vp, i32, vp, vp, i64, u32, vp]
+        L.fstat_eval.restype = ctypes.c_int
+        L.fstat_waveform.argtypes = [ctypes.c_double, ctypes.c_double, i64, i64, vp, vp, vp, u32, vp]
+        L.fstat_waveform.restype = ctypes.c_int
+        L.pso_stage.argtypes = [vp, ctypes.POINTER(pso_stage_desc), ctypes.POINTER(pso_result), vp]
+        L.pso_stage.restype = ctypes.c_int
+        L.fstat_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.fstat_profile_read.restype = ctypes.c_int
+        L.fstat_plan_destroy.argtypes = [vp]
+        L.fstat_plan_destroy.restype = None
+        L.fstat_last_error.argtypes = []
+        L.fstat_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def fstat_last_error() -> str:
+    return lib().fstat_last_error().decode()
+
+
+def _check(rc: int) -> None:
+    if rc != FSTAT_OK:
+        raise FstatError(rc, fstat_last_error())
+
+
+# ---- same-name wrappers of the C entry points --------------------------------
+
+def fstat_plan_create(desc: fstat_data_desc, opts: fstat_opts | None = None, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().fstat_plan_create(ctypes.byref(h), ctypes.byref(desc),
+                                   ctypes.byref(opts) if opts is not None else None, stream))
+    return h
+
+
+def fstat_eval(plan, params, n, np_ptr, np_uniform, F_hat, F_part, part_stride, flags, stream=None):
+    _check(lib().fstat_eval(plan, params, int(n), np_ptr, int(np_uniform), F_hat, F_part,
+                            int(part_stride), int(flags), stream))
+
+
+def fstat_waveform(T_obs, df, k_lo, nbins, params6, amps4, out, flags, stream=None):
+    _check(lib().fstat_waveform(float(T_obs), float(df), int(k_lo), int(nbins), params6, amps4,
+                                out, int(flags), stream))
+
+
+def pso_stage(plan, desc: pso_stage_desc, result: pso_result, stream=None):
+    _check(lib().pso_stage(plan, ctypes.byref(desc), ctypes.byref(result), stream))
+
+
+def fstat_profile_read(plan, reset: bool = True):
+    ms, n, bins = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().fstat_profile_read(plan, int(reset), ctypes.byref(ms), ctypes.byref(n),
+                                    ctypes.byref(bins)))
+    return ms.value, n.value, bins.value
+
+
+def fstat_plan_destroy(plan) -> None:
+    if plan:
+        lib().fstat_plan_destroy(plan)
+
+
+# ---- torch conveniences (device memory + current stream) ---------------------
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device available")
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A plan over one data set, with inputs kept resident in device memory."""
+
+    def __init__(self, data, psd, T_obs: float, df: float, k_lo: int,
+                 precision: int = 0, chunk: int = 0, profile: bool = False):
+        torch = _torch()
+        dev = torch.device("cuda")
+        d = torch.as_tensor(np.ascontiguousarray(data, dtype=np.complex128)
+                            if isinstance(data, np.ndarray) else data)
+        d = d.to(dev, torch.complex128).contiguous()
+        p = torch.as_tensor(psd).to(dev, torch.float64).contiguous()
+        self.nbins = int(p.numel())
+        self.T_obs, self.df, self.k_lo = float(T_obs), float(df), int(k_lo)
+        desc = fstat_data_desc(self.T_obs, self.df, self.k_lo, self.nbins,
+                               d.data_ptr(), p.data_ptr())
+        opts = fstat_opts(int(precision), FSTAT_DEVICE_PTRS | (FSTAT_PROFILE if profile else 0),
+                          int(chunk), 0)
+        self.handle = fstat_plan_create(desc, opts, _stream())
+        torch.cuda.current_stream().synchronize()
+
+    def eval(self, params, np_parts=1, part_stride: int | None = None, mixed: bool = False,
+             want_parts: bool = False):
+        """F_hat [n] (and F_part [n, stride]) for params [n, 6] on the device."""
+        torch = _torch()
+        prm = torch.as_tensor(params).to("cuda", torch.float64).contiguous()
+        n = prm.shape[0]
+        F = torch.empty(n, device="cuda", dtype=torch.float64)
+        if isinstance(np_parts, int):
+            npp, npu = None, np_parts
+            stride = part_stride or np_parts
+            np_t = None
+        else:
+            np_t = torch.as_tensor(np_parts).to("cuda", torch.int32).contiguous()
+            npp, npu = np_t.data_ptr(), 0
+            stride = part_stride or int(np_t.max().item())
+        Fp = torch.zeros((n, stride), device="cuda", dtype=torch.float64) if want_parts else None
+        flags = FSTAT_DEVICE_PTRS | (FSTAT_EVAL_MIXED if mixed else 0)
+        fstat_eval(self.handle, prm.data_ptr(), n, npp, npu, F.data_ptr(),
+                   Fp.data_ptr() if Fp is not None else None, stride, flags, _stream())
+        return (F, Fp) if want_parts else F
+
+    def pso(self, box, np_runs, n_part: int, iters: int, ring_k: int = 1, w=(0.7, 0.7),
+            c1: float = 1.5, c2: float = 1.5, vmax: float = 0.5, seed: int = 1,
+            mixed: bool = False, use_graph: bool = True, want_trace: bool = True,
+            want_final: bool = False):
+        """Run pso_stage: box [R, 6, 2] (physical), np_runs [R].  Returns dict
+        with best_x [R, 6], best_F [R], trace [iters, R], final_x [R, n_part, 6]."""
+        _torch()
+        box = np.ascontiguousarray(box, dtype=np.float64).reshape(-1, 6, 2)
+        R = box.shape[0]
+        npr = np.ascontiguousarray(np.broadcast_to(np.asarray(np_runs, dtype=np.int32), (R,)))
+        best_x = np.zeros((R, 6)); best_F = np.zeros(R)
+        trace = np.zeros((max(iters, 1), R)) if want_trace else None
+        final_x = np.zeros((R, n_part, 6)) if want_final else None
+        desc = pso_stage_desc(R, int(n_part), int(iters), int(ring_k), float(w[0]), float(w[1]),
+                              float(c1), float(c2), float(vmax), int(seed), box.ctypes.data,
+                              npr.ctypes.data, FSTAT_EVAL_MIXED if mixed else 0, int(use_graph))
+        res = pso_result(best_x.ctypes.data, best_F.ctypes.data,
+                         trace.ctypes.data if trace is not None else None,
+                         final_x.ctypes.data if final_x is not None else None)
+        pso_stage(self.handle, desc, res, _stream())
+        out = dict(best_x=best_x, best_F=best_F)
+        if trace is not None:
+            out["trace"] = trace[:iters]
+        if final_x is not None:
+            out["final_x"] = final_x
+        return out
+
+    def profile_read(self, reset: bool = True):
+        """(bin-loop kernel ms total, launches, bin-template evaluations)."""
+        return fstat_profile_read(self.handle, reset)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fstat_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def waveform(T_obs, df, k_lo, nbins, params6, amps4):
+    """sum_i a_i A^i on the grid, computed on the device; returns a torch
+    complex128 tensor on the device."""
+    torch = _torch()
+    p = torch.as_tensor(np.asarray(params6, dtype=np.float64)).cuda()
+    a = torch.as_tensor(np.asarray(amps4, dtype=np.float64)).cuda()
+    out = torch.empty(int(nbins), device="cuda", dtype=torch.complex128)
+    fstat_waveform(T_obs, df, k_lo, nbins, p.data_ptr(), a.data_ptr(), out.data_ptr(),
+                   FSTAT_DEVICE_PTRS, _stream())
+    return out
