@@ -246,15 +246,32 @@ static void link_transfer(const double pos[3][3], int r, int s, const double k[3
   *yx = g * (2.0 * un * vn);
 }
 
+/* Rigid constellation (reading of Sec. IV's orbit, on which the paper says its
+ * result does not depend): spacecraft 1 follows the analytic orbit and
+ * spacecraft 2, 3 sit at p1 + L n, with the arm directions n of the analytic
+ * orbit, so every arm has the nominal length L used for the delays. */
+static void rigid_positions(double t, double pos[3][3]) {
+  const double L = OR_ARM_M / OR_C;
+  double orb[3][3];
+  orbit(t, orb);
+  for (int c = 0; c < 3; ++c) pos[0][c] = orb[0][c];
+  for (int i = 1; i < 3; ++i) {
+    double d[3];
+    for (int c = 0; c < 3; ++c) d[c] = orb[i][c] - orb[0][c];
+    double nrm = sqrt(dot3(d, d));
+    for (int c = 0; c < 3; ++c) pos[i][c] = orb[0][c] + L * d[c] / nrm;
+  }
+}
+
 /* First-generation Michelson X at spacecraft 1 (index 0) with equal static
  * delays L (reading of the TDI-X combination the paper cites):
  *   X = (1 - z^2) [ (y_{1<-3} + z y_{3<-1}) - (y_{1<-2} + z y_{2<-1}) ],
  *   z = exp(-2 pi i f L).
- * Output: TDI-X transfer for the + and x polarisation, orbit at time t.   */
+ * Output: TDI-X transfer for the + and x polarisation, constellation at t. */
 static void response(const or_intr *p, double f, double t, double complex T[2]) {
   const double L = OR_ARM_M / OR_C;
   double pos[3][3], k[3], u[3], v[3];
-  orbit(t, pos);
+  rigid_positions(t, pos);
   sky_frame(p->theta, p->phi, k, u, v);
   double complex y13p, y13x, y31p, y31x, y12p, y12x, y21p, y21x;
   link_transfer(pos, 0, 2, k, u, v, f, &y13p, &y13x);
@@ -436,11 +453,12 @@ int or_tf(const double *theta6, const double *f, int64_t n, double *out) {
   return 0;
 }
 
-/* Spacecraft positions [n][3][3] (light-seconds) at times t. */
-void or_orbit(const double *t, int64_t n, double *out) {
+/* Spacecraft positions [n][3][3] (light-seconds) at times t: the analytic
+ * orbit (rigid = 0) or the rigid constellation used by the response (1). */
+void or_orbit(const double *t, int64_t n, int rigid, double *out) {
   for (int64_t i = 0; i < n; ++i) {
     double pos[3][3];
-    orbit(t[i], pos);
+    if (rigid) rigid_positions(t[i], pos); else orbit(t[i], pos);
     memcpy(out + 9 * i, pos, sizeof(pos));
   }
 }

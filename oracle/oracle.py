@@ -45,7 +45,7 @@ def lib():
         L.or_set_pn_order.argtypes = [ctypes.c_int]
         L.or_phase.argtypes = [_dp, ctypes.c_double, _dp, ctypes.c_int64, _dp, _dp]
         L.or_tf.argtypes = [_dp, _dp, ctypes.c_int64, _dp]
-        L.or_orbit.argtypes = [_dp, ctypes.c_int64, _dp]
+        L.or_orbit.argtypes = [_dp, ctypes.c_int64, ctypes.c_int, _dp]
         L.or_response.argtypes = [_dp, _dp, _dp, ctypes.c_int64, _dp]
         L.or_link.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, _dp]
@@ -89,10 +89,12 @@ def tf(theta6, f):
     return out
 
 
-def orbit(t):
+def orbit(t, rigid=False):
+    """Spacecraft positions [n, 3, 3]: analytic orbit, or the rigid
+    constellation (arms of length L along the orbit's arm directions)."""
     t, tp = _d(np.atleast_1d(t))
     out = np.empty((t.size, 3, 3))
-    lib().or_orbit(tp, t.size, out.ctypes.data_as(_dp))
+    lib().or_orbit(tp, t.size, int(bool(rigid)), out.ctypes.data_as(_dp))
     return out
 
 

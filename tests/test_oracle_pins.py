@@ -140,6 +140,19 @@ def test_single_link_matches_time_domain_definition():
         np.testing.assert_allclose(yx, n @ ex @ n * two_pass, rtol=1e-10, atol=1e-14)
 
 
+def test_rigid_constellation():
+    """The response's constellation: spacecraft 1 on the analytic orbit, the
+    other two at distance L along the orbit's arm directions."""
+    t = np.array([0.0, 1.3e7, 2.9e7])
+    orb, rig = O.orbit(t), O.orbit(t, rigid=True)
+    np.testing.assert_array_equal(rig[:, 0], orb[:, 0])
+    for i in (1, 2):
+        d = rig[:, i] - rig[:, 0]
+        np.testing.assert_allclose(np.linalg.norm(d, axis=1), L_S, rtol=1e-14)
+        e = orb[:, i] - orb[:, 0]
+        np.testing.assert_allclose(d / L_S, e / np.linalg.norm(e, axis=1)[:, None], atol=1e-14)
+
+
 def test_tdix_low_frequency_limit():
     """For f L << 1 first-generation X reduces to the long-wavelength
     Michelson response 8 pi^2 f^2 L^2 (n_b.H.n_b - n_a.H.n_a)."""
@@ -148,7 +161,7 @@ def test_tdix_low_frequency_limit():
     f = 1e-8   # Doppler phase 2 pi f k.p ~ 3e-5 rad, f L ~ 1e-7
     p = P0.copy(); p[3], p[4] = th, ph
     Tp, Tx = O.response(p, np.array([f]), np.array([t]))
-    pos = O.orbit(np.array([t]))[0]
+    pos = O.orbit(np.array([t]), rigid=True)[0]
     na = (pos[1] - pos[0]) / np.linalg.norm(pos[1] - pos[0])
     nb = (pos[2] - pos[0]) / np.linalg.norm(pos[2] - pos[0])
     u = np.array([math.cos(th) * math.cos(ph), math.cos(th) * math.sin(ph), -math.sin(th)])
@@ -166,7 +179,7 @@ def test_tdix_combination_from_delayed_links():
     y12(t-2L) + y21(t-3L) - y12(t) - y21(t-L) - y13(t-2L) - y31(t-3L)."""
     p = P0.copy()
     f, t = 0.0432, 1.7e7
-    pos = O.orbit(np.array([t]))[0]
+    pos = O.orbit(np.array([t]), rigid=True)[0]
     Tp, Tx = O.response(p, np.array([f]), np.array([t]))
     y = {(r, s): O.link(pos, r, s, p[3], p[4], f) for r, s in ((0, 2), (2, 0), (0, 1), (1, 0))}
     D = lambda m: np.exp(-2j * np.pi * f * m * L_S)
