@@ -49,15 +49,15 @@ def make_workload(n_particles: int, seed_pts: int = 2003):
     return g, data, psd, pts, inj
 
 
-def time_path(plan, prm, npart, steps, warmup, mixed):
+def time_path(plan, prm, npart, steps, warmup, mixed, surrogate=False):
     import torch
     for _ in range(warmup):
-        plan.eval(prm, npart, mixed=mixed)
+        plan.eval(prm, npart, mixed=mixed, surrogate=surrogate)
     torch.cuda.synchronize()
     plan.profile_read(reset=True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        F = plan.eval(prm, npart, mixed=mixed)
+        F = plan.eval(prm, npart, mixed=mixed, surrogate=surrogate)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kms, launches, bins = plan.profile_read(reset=True)
@@ -87,7 +87,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "mixed"], default=None)
+    ap.add_argument("--only", choices=["fp64", "mixed", "mixed+surrogate"], default=None)
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-steps", type=int, default=3000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (for scaling "
                          "FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -114,16 +116,24 @@ def main():
     prm = torch.from_numpy(pts).cuda()
     torch.cuda.synchronize()
     variants = {}
-    for name, mixed in (("fp64", False), ("mixed", True)):
-        if (mixed and args.no_mixed) or (args.only and args.only != name):
+    for name, mixed, sur in (("fp64", False, False), ("mixed", True, False),
+                             ("mixed+surrogate", True, True)):
+        if (mixed and args.no_mixed) or (args.only and args.only != name) or (sur and args.no_surrogate):
             continue
+        extra = {}
         try:
-            r = time_path(plan, prm, args.np, args.steps, args.warmup, mixed)
+            if sur:
+                t0 = time.perf_counter()
+                rep = plan.train_surrogate(steps=args.surrogate_steps)
+                extra = dict(train_s=time.perf_counter() - t0, val_rmse=rep["val_rmse"])
+            r = time_path(plan, prm, args.np, args.steps, args.warmup, mixed, sur)
+            if sur:
+                extra["used"], extra["fallback"] = plan.surrogate_stats()
         except fstat.FstatError as e:
             _log(f"{name}: {e}")
             continue
         tps = args.particles * args.steps / r["seconds"]
-        fpb = FLOP_PER_BIN[name]
+        fpb = FLOP_PER_BIN.get(name)
         peak = PEAK_FP64_TFLOPS
         achieved = (fpb * r["bins_per_launch"] / (r["kernel_ms"] * 1e-3) / 1e12) if fpb else None
         variants[name] = dict(templates_per_s=tps, ms_per_step=1e3 * r["seconds"] / args.steps,
@@ -132,7 +142,7 @@ def main():
                               roofline=dict(bound="alu", achieved=achieved, peak=peak,
                                             unit="TFLOP/s",
                                             frac=(achieved / peak) if achieved else None,
-                                            traffic=None))
+                                            traffic=None), **extra)
         _log(f"{name}: {tps:.1f} templates/s, kernel {r['kernel_ms']:.2f} ms/launch, "
              f"{r['bins_per_launch']:.3e} bin-templates/launch")
     head = variants.get("fp64") or next(iter(variants.values()))

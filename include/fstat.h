@@ -59,6 +59,8 @@ extern "C" {
 #define FSTAT_DEVICE_PTRS 1u  /* all array arguments are device pointers    */
 #define FSTAT_EVAL_MIXED 2u   /* fstat_eval: use the mixed-precision path   */
 #define FSTAT_PROFILE 4u      /* fstat_opts.flags: time the bin-loop kernel  */
+#define FSTAT_EVAL_SURROGATE 8u /* fstat_eval / pso_stage: learned eccentric
+                                   phase for particles with Np >= 16        */
 
 typedef struct fstat_plan_s *fstat_plan_t;
 
@@ -157,6 +159,46 @@ int pso_stage(fstat_plan_t plan, const pso_stage_desc *desc, pso_result *result,
  * the last reset.  Waits for the recorded events.  EINVAL without profiling. */
 int fstat_profile_read(fstat_plan_t plan, int reset, double *kernel_ms, int64_t *launches,
                        int64_t *bin_templates);
+
+/* ---- learned surrogate for the eccentric phase (App. A) ------------------- */
+/* One forward and backward pass of the surrogate network on the device, for
+ * checking its training kernels: 3 -> 256 -> 256 -> 256 -> 256 -> 1 with SiLU,
+ * BF16 MFMA operands and FP32 accumulation, mean squared error.
+ *   params [198657] FP32 (layout W1[256][3] b1 | W2[256][256] b2 | W3 b3 |
+ *          W4 b4 | w5[256] b5), x [B][3], t [B] (host pointers), B a
+ *          positive multiple of 64; out: loss, grad [198657], y [B] or NULL.
+ * EINVAL on bad sizes.  Allocates and frees its own device buffers.        */
+int fstat_mlp_grad(const float *params, const float *x, const float *t, int32_t B, double *loss,
+                   float *grad, float *y);
+
+/* Train the plan's surrogate for the eccentric phase correction Psi_e
+ * (App. A) on the device: n_samples (f, Mc, e0) points uniform over
+ * f in [10, 100] mHz, Mc in [10, 50] Msun, e0 in [0, 0.15], targets from the
+ * plain template code (Psi_e in units of e0^2 times the Newtonian phase), the
+ * last 1/16 held out; `steps` Adam steps of `batch` samples with a cosine
+ * step-size decay from `lr`.  Afterwards fstat_eval / pso_stage accept
+ * FSTAT_EVAL_SURROGATE: for particles with Np >= 16 the network is evaluated
+ * at four knots per partition and interpolated to every bin; a particle keeps
+ * it only if, in every partition, the residual against the analytic term at
+ * the knots and mid-points (mean removed) implies a mismatch <= 1e-3, else it
+ * falls back to the analytic template.  Np = 1 never uses it.
+ * EINVAL: batch not a positive multiple of 64, n_samples < 17 batches,
+ * steps < 1 or lr <= 0.  Waits for completion.                           */
+typedef struct {
+  int64_t n_samples;   /* training + held-out samples                           */
+  int32_t batch;       /* samples per step, a multiple of 64                    */
+  int32_t steps;       /* optimiser steps                                       */
+  double lr;           /* initial Adam step size                                */
+  uint64_t seed;       /* sample and initialisation seed                        */
+  double *loss_trace;  /* [steps] training loss per step (host), or NULL        */
+  double val_rmse;     /* out: held-out root-mean-square error (network units)  */
+  double val_max;      /* out: held-out max |error| (network units)             */
+} fstat_surrogate_desc;
+int fstat_surrogate_train(fstat_plan_t plan, fstat_surrogate_desc *desc, void *hip_stream);
+
+/* Particles of the last FSTAT_EVAL_SURROGATE evaluation that used the
+ * surrogate and that fell back to the analytic template.                  */
+int fstat_surrogate_stats(fstat_plan_t plan, int64_t *used, int64_t *fallback);
 
 /* Release the plan and its device memory (NULL is ignored). */
 void fstat_plan_destroy(fstat_plan_t plan);

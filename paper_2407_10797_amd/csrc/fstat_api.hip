@@ -87,10 +87,12 @@ int eval_blocks(fstat_plan_s* P, bool mixed) {
 int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t* np,
                 int32_t np_uniform, int32_t stride, double* F_hat, double* F_part,
                 int64_t part_stride, bool mixed, hipStream_t s, const uint8_t* skip,
-                bool allow_profile) {
+                bool allow_profile, bool surrogate) {
   int rc = ensure_workspace(P, n, stride);
   if (rc) return rc;
+  if (surrogate && (rc = sur_ensure(P, n, stride))) return rc;
   launch_setup(P->grid, params, n, np, np_uniform, stride, P->chunk, skip, P->ws, s);
+  if (surrogate && (rc = sur_prepare(P, n, stride, s))) return rc;
   launch_worklist(n * (int64_t)stride, P->ws, s);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool prof = P->profile && allow_profile;
@@ -99,7 +101,8 @@ int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t*
       return rc;
     (void)hipEventRecord(e0, s);
   }
-  launch_eval(mixed, P->grid, stride, P->chunk, P->ws, P->b64, P->b32, eval_blocks(P, mixed), s);
+  launch_eval(mixed, P->grid, stride, P->chunk, P->ws, P->b64, P->b32,
+              surrogate ? P->sur_ek : nullptr, eval_blocks(P, mixed), s);
   if (prof) {
     (void)hipEventRecord(e1, s);
     P->events.emplace_back(e0, e1);
@@ -212,6 +215,7 @@ void fstat_plan_destroy(fstat_plan_t P) {
   dev_free(P->ws.total); dev_free(P->ws.items); dev_free(P->ws.partials); dev_free(P->ws.Fl);
   dev_free(P->io.params); dev_free(P->io.np); dev_free(P->io.F_hat); dev_free(P->io.F_part);
   pso_release(P);
+  sur_release(P);
   for (auto& e : P->events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   dev_free(P->bin_counter);
   delete P;
@@ -253,6 +257,8 @@ int fstat_eval(fstat_plan_t P, const double* params, int64_t n, const int32_t* n
   if (!params || !F_hat) return set_error(FSTAT_EINVAL, "null params or F_hat");
   const bool mixed = (flags & FSTAT_EVAL_MIXED) != 0;
   const bool dev = (flags & FSTAT_DEVICE_PTRS) != 0;
+  const bool sur = (flags & FSTAT_EVAL_SURROGATE) != 0;
+  if (sur && !P->sur_trained) return set_error(FSTAT_EINVAL, "surrogate requested but not trained");
   if (mixed && !(P->prec & FSTAT_MIXED)) return set_error(FSTAT_EINVAL, "plan has no mixed data");
   if (!mixed && !(P->prec & FSTAT_FP64)) return set_error(FSTAT_EINVAL, "plan has no FP64 data");
   int32_t stride;
@@ -266,7 +272,9 @@ int fstat_eval(fstat_plan_t P, const double* params, int64_t n, const int32_t* n
     stride = np_uniform;
   }
   hipStream_t s = (hipStream_t)hip_stream;
-  if (dev) return eval_device(P, params, n, np, np_uniform, stride, F_hat, F_part, part_stride, mixed, s);
+  if (dev)
+    return eval_device(P, params, n, np, np_uniform, stride, F_hat, F_part, part_stride, mixed, s,
+                       nullptr, true, sur);
   // host pointers: validate, stage, run, copy back
   for (int64_t i = 0; i < n; ++i) {
     const double* t = params + 6 * i;
@@ -290,7 +298,7 @@ int fstat_eval(fstat_plan_t P, const double* params, int64_t n, const int32_t* n
   if (F_part && (rc = hip_check(hipMemcpyAsync(P->io.F_part, F_part, sizeof(double) * n * ps,
                                                hipMemcpyHostToDevice, s), "copy F_part"))) return rc;
   rc = eval_device(P, P->io.params, n, np ? P->io.np : nullptr, np_uniform, stride, P->io.F_hat,
-                   F_part ? P->io.F_part : nullptr, ps, mixed, s);
+                   F_part ? P->io.F_part : nullptr, ps, mixed, s, nullptr, true, sur);
   if (rc) return rc;
   if ((rc = hip_check(hipMemcpyAsync(F_hat, P->io.F_hat, sizeof(double) * n,
                                      hipMemcpyDeviceToHost, s), "copy F_hat"))) return rc;

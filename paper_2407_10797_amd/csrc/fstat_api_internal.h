@@ -11,6 +11,9 @@
 #include "fstat_kernels.h"
 
 struct PsoState;  // defined in pso.hip
+namespace fstat {
+struct Mlp;       // defined in mlp.h
+}
 
 struct fstat_plan_s {
   int device = 0;
@@ -37,6 +40,14 @@ struct fstat_plan_s {
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   unsigned long long* bin_counter = nullptr;
+  // learned surrogate (surrogate.hip)
+  fstat::Mlp* sur = nullptr;
+  bool sur_trained = false;
+  float* sur_X = nullptr;
+  double* sur_ek = nullptr;
+  double* sur_mm = nullptr;
+  unsigned long long* sur_counters = nullptr;
+  size_t cap_sur_X = 0, cap_sur_ek = 0, cap_sur_mm = 0, cap_sur_counters = 0;
 };
 
 namespace fstat {
@@ -46,7 +57,10 @@ int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride);
 int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t* np,
                 int32_t np_uniform, int32_t stride, double* F_hat, double* F_part,
                 int64_t part_stride, bool mixed, hipStream_t s, const uint8_t* skip = nullptr,
-                bool allow_profile = true);
+                bool allow_profile = true, bool surrogate = false);
+int sur_ensure(fstat_plan_s* P, int64_t n, int32_t stride);
+int sur_prepare(fstat_plan_s* P, int64_t n, int32_t stride, hipStream_t s);
+void sur_release(fstat_plan_s* P);
 int eval_blocks(fstat_plan_s* P, bool mixed);
 hipError_t occupancy_fp64(int* blocks_per_cu);
 hipError_t occupancy_mixed(int* blocks_per_cu);

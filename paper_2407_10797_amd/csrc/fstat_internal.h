@@ -30,6 +30,7 @@ constexpr double kLs = kArm / kC;                // arm light time [s]
 constexpr double kRs = kAU / kC;                 // orbit radius [s]
 constexpr double kSqrt3 = 1.7320508075688772935;
 constexpr double kRankCut = 1e-12;               // singular-M eigenvalue ratio
+constexpr int kSurMinNp = 16;                    // surrogate only in stages with Np >= 16
 
 // ---- double-double helpers ---------------------------------------------------
 // Error-free transformations must not be contracted: with fp-contract=fast the
@@ -118,11 +119,15 @@ struct PartConst {
   double cN_hi, cN_lo, c1_hi, c1_lo, c15_hi, c15_lo, ce_hi, ce_lo;
   double c2, c5, c6, a6k, b6, ln_vfac;
   double c5v5;             // cN c5' vfac^5 (enters t_f)
+  double ecc_k;            // -(2355/1462) e0^2: Psi_e = ecc_k (f0/f)^{19/9} Psi_N
+  double nn_mc, nn_e0;     // surrogate inputs for Mc and e0, mapped to [-1, 1]
   double k[3], u[3], v[3];
   double flo, fhi;
   int32_t j_lo, j_hi;      // support bins (inclusive); j_lo > j_hi when empty
   int32_t np;
   int32_t status;          // 0 ok, 1 empty support, 2 invalid parameters
+  int32_t sur;             // 1: eccentric term from the surrogate knots
+  int32_t pad_;
 };
 
 enum { kStatusOk = 0, kStatusEmpty = 1, kStatusInvalid = 2 };
@@ -130,8 +135,19 @@ enum { kStatusOk = 0, kStatusEmpty = 1, kStatusInvalid = 2 };
 // ---- phase and SPA time -------------------------------------------------------
 // Fractional cycle of Psi(f)/(2 pi) (constant phase offsets dropped: the
 // F-statistic absorbs them) and the SPA time t_f = (1/2 pi) dPsi/df.
+// Cubic Lagrange interpolation through four knots x_a (ek[0..3]) with
+// coefficients c_a = value_a / prod_{b != a}(x_a - x_b) (ek[4..7]):
+// I(f) = sum_a c_a prod_{b != a} (f - x_b).
+__host__ __device__ __forceinline__ double knot_interp(const double* ek, double f) {
+  double d0 = f - ek[0], d1 = f - ek[1], d2 = f - ek[2], d3 = f - ek[3];
+  double d01 = d0 * d1, d23 = d2 * d3;
+  return ek[4] * (d1 * d23) + ek[5] * (d0 * d23) + ek[6] * (d01 * d3) + ek[7] * (d01 * d2);
+}
+
+// ek == nullptr: analytic eccentric term; otherwise the eccentric term (cycles)
+// is interpolated from the surrogate's knot values of the current partition.
 __host__ __device__ __forceinline__ void phase_and_tf(const PartConst& P, double f, double& frac,
-                                             double& tf) {
+                                             double& tf, const double* ek = nullptr) {
   FSTAT_NO_CONTRACT
   dd ft = two_prod(f, P.tc);
   double c_ft = (ft.hi - floor(ft.hi)) + ft.lo;
@@ -145,85 +161,200 @@ __host__ __device__ __forceinline__ void phase_and_tf(const PartConst& P, double
   dd y2 = dd_mul(y, y);
   dd y3 = dd_mul(y2, y);
   dd y5 = dd_mul(y3, y2);
-  dd y11 = dd_mul(dd_mul(y5, y5), y);
-  dd w = dd_root(y, 3, exp(lx * (-1.0 / 9.0)));     // y^{1/3}
+  double xy2 = x.hi * y2.hi;                         // x^{1/3} = 1 / y
   dd tN = dd_mul(dd{P.cN_hi, P.cN_lo}, y5);
   dd t1 = dd_mul(dd{P.c1_hi, P.c1_lo}, y3);
   dd t15 = dd_mul(dd{P.c15_hi, P.c15_lo}, y2);
-  dd te = dd_mul(dd_mul(dd{P.ce_hi, P.ce_lo}, y11), w);
+  dd te;
+  if (ek) {
+    te = dd{knot_interp(ek, f), 0.0};
+  } else {
+    // w = y^{1/3}: estimate, then one Newton step on w^3 = y
+    double w0 = exp(lx * (-1.0 / 9.0));
+    dd w3 = dd_mul_d(two_prod(w0, w0), w0);
+    double rw = ((y.hi - w3.hi) + (y.lo - w3.lo)) * xy2;
+    dd w = quick_two_sum(w0, w0 * rw * (1.0 / 3.0));
+    te = dd_mul(dd_mul(dd{P.ce_hi, P.ce_lo}, dd_mul(dd_mul(y5, y5), y)), w);
+  }
   double lnv = P.ln_vfac + lx * (1.0 / 3.0);
   double t2 = P.c2 * y.hi;
-  double t6 = P.c6 / y.hi;
+  double t6 = P.c6 * xy2;
   double small = t2 + P.c5 * lnv + t6 * (P.a6k + P.b6 * lnv);
   double ph = c_ft + dd_frac(tN) + dd_frac(t1) + dd_frac(t15) + dd_frac(te) + small;
   frac = ph - floor(ph);
-  // t_f: a term c y^m = c x^{-m/3} contributes -(m/3) c y^m / f to dPsi/df/(2 pi)
+  // t_f: a term c y^m = c x^{-m/3} contributes -(m/3) c y^m / f to dPsi/df/(2 pi);
+  // 1/f = Mc / x = Mc y^3
   double D = (-5.0 / 3.0) * tN.hi - t1.hi - (2.0 / 3.0) * t15.hi - (1.0 / 3.0) * t2 + P.c5v5 +
              t6 * (P.a6k + P.b6 + P.b6 * lnv) * (1.0 / 3.0) - (34.0 / 9.0) * te.hi;
-  tf = P.tc + D / f;
+  tf = P.tc + D * (P.mc_hi * y3.hi);
 }
 
-// ---- TDI-X response (particle-dependent part) --------------------------------
-// Returns T'_+ and T'_x such that the full transfer is C(f) T', with the
-// template-independent C(f) = (1 - z^2)(-i pi f L) exp(-i pi f L) folded into
-// the per-bin data.  s0, c0 = sin, cos(pi f L).
+// Per-particle phase coefficients (see PartConst), double-double where the
+// term they multiply reaches 10^2..10^7 cycles.
+__host__ __device__ inline void fill_constants(PartConst& P, const double* th) {
+  FSTAT_NO_CONTRACT
+  double tc = th[0], mc = th[1], dmu = th[2], theta = th[3], phi = th[4], e0 = th[5];
+  P.tc = tc;
+  dd m = two_prod(mc, kMsunS);                       // Mc [s], exact
+  P.mc_hi = m.hi; P.mc_lo = m.lo;
+  dd d2 = two_prod(dmu, dmu);
+  dd one_m = dd_add(dd{1.0, 0.0}, dd{-d2.hi, -d2.lo});
+  dd eta = dd{one_m.hi * 0.25, one_m.lo * 0.25};      // (1 - dmu^2)/4
+  const dd pi = {3.141592653589793116e+00, 1.2246467991473532e-16};
+  dd pi13 = dd_root(pi, 3, cbrt(pi.hi));
+  dd ie5 = dd_root(dd_div(dd{1.0, 0.0}, eta), 5, pow(eta.hi, -0.2));   // eta^{-1/5}
+  dd vfac = dd_mul(pi13, ie5);                        // v = vfac (Mc f)^{1/3}
+  dd vf2 = dd_mul(vfac, vfac), vf3 = dd_mul(vf2, vfac);
+  dd pi2 = dd_mul(pi, pi);
+  dd cN = dd_div(dd{3.0, 0.0}, dd_mul_d(dd_mul(pi2, dd_mul(pi13, pi13)), 256.0));
+  dd a2 = dd_add(dd_ratio(3715.0, 756.0), dd_mul(dd_ratio(55.0, 9.0), eta));
+  dd c1 = dd_mul(dd_mul(cN, a2), vf2);
+  dd c15 = dd_mul(dd_mul(cN, dd_mul_d(pi, -16.0)), vf3);
+  dd z = dd_mul_d(m, kF0Ecc);                         // f0 Mc
+  dd z19 = dd_mul(dd_mul(z, z), dd_root(z, 9, pow(z.hi, 1.0 / 9.0)));   // (f0 Mc)^{19/9}
+  dd ce = dd_mul(dd_mul(cN, dd_ratio(-2355.0, 1462.0)), dd_mul(two_prod(e0, e0), z19));
+  P.cN_hi = cN.hi; P.cN_lo = cN.lo;
+  P.c1_hi = c1.hi; P.c1_lo = c1.lo;
+  P.c15_hi = c15.hi; P.c15_lo = c15.lo;
+  P.ce_hi = ce.hi; P.ce_lo = ce.lo;
+  double et = eta.hi, vf = vfac.hi, K = cN.hi;
+  const double pisq = kPi * kPi;
+  double a4 = 15293365.0 / 508032.0 + 27145.0 * et / 504.0 + 3085.0 * et * et / 72.0;
+  double c5p = kPi * (38645.0 / 756.0 - 65.0 * et / 9.0);
+  const double euler = 0.57721566490153286061;
+  double a6c = 11583231236531.0 / 4694215680.0 - 640.0 * pisq / 3.0 - 6848.0 * euler / 21.0 +
+               (-15737765635.0 / 3048192.0 + 2255.0 * pisq / 12.0) * et +
+               76055.0 * et * et / 1728.0 - 127825.0 * et * et * et / 1296.0;
+  double vf4 = vf * vf * vf * vf, vf5 = vf4 * vf, vf6 = vf5 * vf;
+  P.c2 = K * a4 * vf4;
+  P.c5v5 = K * c5p * vf5;
+  P.c5 = 3.0 * P.c5v5;
+  P.c6 = K * vf6;
+  P.b6 = -6848.0 / 21.0;
+  P.a6k = a6c + P.b6 * log(4.0);
+  P.ln_vfac = log(vf);
+  P.ecc_k = -(2355.0 / 1462.0) * e0 * e0;
+  P.nn_mc = (mc - 30.0) / 20.0;
+  P.nn_e0 = e0 / 0.075 - 1.0;
+  P.sur = 0;
+  P.pad_ = 0;
+  double st, ct, sp, cp;
+  sincos(theta, &st, &ct);
+  sincos(phi, &sp, &cp);
+  P.k[0] = -st * cp; P.k[1] = -st * sp; P.k[2] = -ct;
+  P.u[0] = ct * cp;  P.u[1] = ct * sp;  P.u[2] = -st;
+  P.v[0] = sp;       P.v[1] = -cp;      P.v[2] = 0.0;
+}
+
+// Newtonian and eccentric phase terms (cycles) of the plain template at f:
+// tN = cN y^5 and te = ce y^{34/3} (App. A), in double precision; used to
+// build the surrogate's training targets and to judge its knot values.
+__host__ __device__ __forceinline__ void newton_and_ecc(const PartConst& P, double f, double& tN,
+                                                       double& te) {
+  FSTAT_NO_CONTRACT
+  dd x = dd_mul_d(dd{P.mc_hi, P.mc_lo}, f);
+  double lx = log(x.hi);
+  double y = exp(lx * (-1.0 / 3.0));
+  double y5 = y * y * y * y * y;
+  tN = (P.cN_hi + P.cN_lo) * y5;
+  te = (P.ce_hi + P.ce_lo) * y5 * y5 * y * exp(lx * (-1.0 / 9.0));
+}
+
+// ---- per-bin template (particle-dependent part) -------------------------------
+// Full basis template (Sec. II.A, Eq. response; Sec. IV, Eq. freDres, N = 0):
+//   A^1 = C(f) f^{-7/6} e^{-i Phi} T''_+,  Phi = Psi + 2 pi f k.p_1,
+// with C(f) = (1 - z^2)(-i pi f L) e^{-i pi f L} folded into the per-bin data,
+// and for a rigid constellation (arms of length L along the orbit's arm
+// directions n_a = 1->2, n_b = 1->3) the link propagation phase
+// e^{-i pi f k.(p_s + p_r)} = e^{-2 pi i f k.p_1} e^{-i pi f L k.n}: the common
+// factor joins the template phase, the arm factor reuses the sincos of the
+// link sinc argument.  Per arm
+//   S = e^{-i x0 kn} [sinc(x0 (1 + kn)) + z sinc(x0 (1 - kn))],  x0 = pi f L,
+//   T''_P = F^P_b S_b - F^P_a S_a,  F^+ = (u.n)^2 - (v.n)^2,  F^x = 2 (u.n)(v.n).
 __host__ __device__ __forceinline__ double sinc_from(double num, double den) {
   // num = sin(den) computed by angle addition; series near den = 0
   return (fabs(den) < 1e-6) ? 1.0 - den * den * (1.0 / 6.0) : num / den;
 }
 
-__host__ __device__ __forceinline__ void response_fp64(const PartConst& P, double f, double tf, double s0,
-                                              double c0, double& tpr, double& tpi, double& txr,
-                                              double& txi) {
-  // orbit at t_f: alpha = 2 pi t / yr; spacecraft i at beta_i = 2 pi i / 3
+// hardware reciprocal / reciprocal square root seeds refined by two Newton
+// steps (accurate to about one ulp)
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  r = r * __builtin_fma(-h * r, r, 1.5);
+  return r * __builtin_fma(-h * r, r, 1.5);
+}
+
+// spacecraft offsets from the guiding centre R (cos a, sin a, 0) for the
+// first-order analytic orbit: beta_i = 2 pi i / 3, e R / 2 = L / (4 sqrt 3),
+// sqrt(3) e R = L / 2
+template <typename T>
+__device__ __forceinline__ void orbit_offsets(T ca, T sa, T d[3][3]) {
+  const T q = (T)(kLs / (4.0 * kSqrt3));
+  const T hz = (T)(0.5 * kLs);
+  const T cb[3] = {(T)1.0, (T)-0.5, (T)-0.5};
+  const T sb[3] = {(T)0.0, (T)(0.5 * kSqrt3), (T)(-0.5 * kSqrt3)};
+  T c2a = ca * ca - sa * sa, s2a = (T)2.0 * sa * ca;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    d[i][0] = q * (c2a * cb[i] + s2a * sb[i] - (T)3.0 * cb[i]);
+    d[i][1] = q * (s2a * cb[i] - c2a * sb[i] - (T)3.0 * sb[i]);
+    d[i][2] = -hz * (ca * cb[i] + sa * sb[i]);
+  }
+}
+
+__device__ __forceinline__ void template_fp64(const PartConst& P, double f, double s0, double c0,
+                                              double& cph, double& sph, double& tpr,
+                                              double& tpi, double& txr, double& txi,
+                                              const double* ek = nullptr) {
+  double fr, tf;
+  phase_and_tf(P, f, fr, tf, ek);
   double sa, ca;
   sincospi(2.0 * tf * (1.0 / kYear), &sa, &ca);
-  double c2a = ca * ca - sa * sa, s2a = 2.0 * sa * ca;
-  const double q = kLs / (4.0 * kSqrt3);   // e R / 2
-  const double hz = 0.5 * kLs;             // sqrt(3) e R
-  const double cb1 = -0.5, sb1 = 0.5 * kSqrt3, cb2 = -0.5, sb2 = -0.5 * kSqrt3;
-  // offsets d_i of spacecraft i from the guiding centre R (cos a, sin a, 0)
-  double d0x = q * (c2a - 3.0), d0y = q * s2a, d0z = -hz * ca;
-  double d1x = q * (c2a * cb1 + s2a * sb1 - 3.0 * cb1);
-  double d1y = q * (s2a * cb1 - c2a * sb1 - 3.0 * sb1);
-  double d1z = -hz * (ca * cb1 + sa * sb1);
-  double d2x = q * (c2a * cb2 + s2a * sb2 - 3.0 * cb2);
-  double d2y = q * (s2a * cb2 - c2a * sb2 - 3.0 * sb2);
-  double d2z = -hz * (ca * cb2 + sa * sb2);
+  double d[3][3];
+  orbit_offsets<double>(ca, sa, d);
   const double kx = P.k[0], ky = P.k[1], kz = P.k[2];
-  double kP2 = 2.0 * kRs * (kx * ca + ky * sa);   // 2 k . (guiding centre)
-  double kd0 = kx * d0x + ky * d0y + kz * d0z;
-  double kd1 = kx * d1x + ky * d1y + kz * d1z;
-  double kd2 = kx * d2x + ky * d2y + kz * d2z;
-  double x0 = kPi * kLs * f;
-  double zr = c0 * c0 - s0 * s0, zi = -2.0 * s0 * c0;   // z = exp(-2 i pi f L)
-  double out[2][4];  // per arm: (re, im) of E S, and F+, Fx
+  double kp1 = kRs * (kx * ca + ky * sa) + (kx * d[0][0] + ky * d[0][1] + kz * d[0][2]);
+  double ph = fr + f * kp1;               // Phi / (2 pi) in cycles
+  ph -= rint(ph);
+  sincospi(2.0 * ph, &sph, &cph);
+  const double x0 = kPi * kLs * f;
+  const double zr = c0 * c0 - s0 * s0, zi = -2.0 * s0 * c0;   // z = e^{-2 i x0}
+  double out[2][4];
 #pragma unroll
   for (int arm = 0; arm < 2; ++arm) {
-    double ax = (arm == 0 ? d1x : d2x) - d0x;
-    double ay = (arm == 0 ? d1y : d2y) - d0y;
-    double az = (arm == 0 ? d1z : d2z) - d0z;
-    double inv = 1.0 / sqrt(ax * ax + ay * ay + az * az);
+    double ax = d[arm + 1][0] - d[0][0], ay = d[arm + 1][1] - d[0][1], az = d[arm + 1][2] - d[0][2];
+    double inv = rsq_nr(ax * ax + ay * ay + az * az);
     ax *= inv; ay *= inv; az *= inv;
     double kn = kx * ax + ky * ay + kz * az;
     double un = P.u[0] * ax + P.u[1] * ay + P.u[2] * az;
     double vn = P.v[0] * ax + P.v[1] * ay + P.v[2] * az;
-    // propagation phase exp(-i pi f k.(p_0 + p_arm))
-    double kp = kP2 + kd0 + (arm == 0 ? kd1 : kd2);
-    double se, ce;
-    sincospi(-f * kp, &se, &ce);
-    // sinc(x0 (1 + kn)) + z sinc(x0 (1 - kn))
     double sq, cq;
-    sincospi(kLs * f * kn, &sq, &cq);
-    double sp = sinc_from(s0 * cq + c0 * sq, x0 * (1.0 + kn));
-    double sm = sinc_from(s0 * cq - c0 * sq, x0 * (1.0 - kn));
+    sincospi(kLs * f * kn, &sq, &cq);    // x0 kn
+    double np_ = s0 * cq + c0 * sq, nm = s0 * cq - c0 * sq;   // sin(x0 (1 +- kn))
+    double dp = x0 * (1.0 + kn), dm = x0 * (1.0 - kn);
+    double sp, sm;
+    if (fabs(dp) > 1e-6 && fabs(dm) > 1e-6) {
+      double r = rcp_nr(dp * dm);
+      sp = np_ * dm * r;
+      sm = nm * dp * r;
+    } else {
+      sp = sinc_from(np_, dp);
+      sm = sinc_from(nm, dm);
+    }
     double Sr = sp + zr * sm, Si = zi * sm;
-    out[arm][0] = ce * Sr - se * Si;
-    out[arm][1] = ce * Si + se * Sr;
+    out[arm][0] = cq * Sr + sq * Si;      // e^{-i x0 kn} S
+    out[arm][1] = cq * Si - sq * Sr;
     out[arm][2] = un * un - vn * vn;
     out[arm][3] = 2.0 * un * vn;
   }
-  // T' = F_b (E_b S_b) - F_a (E_a S_a)   (arm 0 = a: 1-2, arm 1 = b: 1-3)
   tpr = out[1][2] * out[1][0] - out[0][2] * out[0][0];
   tpi = out[1][2] * out[1][1] - out[0][2] * out[0][1];
   txr = out[1][3] * out[1][0] - out[0][3] * out[0][0];

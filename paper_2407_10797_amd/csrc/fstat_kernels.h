@@ -47,8 +47,14 @@ void launch_setup(const Grid& g, const double* params, int64_t n,
                   const uint8_t* skip, const WorkSpace& ws, hipStream_t s);
 void launch_worklist(int64_t m, const WorkSpace& ws, hipStream_t s);
 void launch_eval(bool mixed, const Grid& g, int32_t stride, int32_t chunk,
-                 const WorkSpace& ws, BinData<double> b, BinData<float> b32, int blocks,
-                 hipStream_t s);
+                 const WorkSpace& ws, BinData<double> b, BinData<float> b32, const double* ek,
+                 int blocks, hipStream_t s);
+void launch_sur_data(uint64_t seed, int64_t n, float* X, float* T, hipStream_t s);
+void launch_sur_knots(const Grid& g, int32_t stride, int64_t n, int64_t rows, const WorkSpace& ws,
+                      float* X, hipStream_t s);
+void launch_sur_check(const Grid& g, int32_t stride, int64_t n, const WorkSpace& ws,
+                      const float* ynn, double* ek, double* mm, double thr,
+                      unsigned long long* counters, hipStream_t s);
 void launch_solve_mean(int64_t n, int32_t stride, const WorkSpace& ws, double* F_hat,
                        double* F_part, int64_t part_stride, unsigned long long* bin_counter,
                        hipStream_t s);

@@ -16,6 +16,7 @@
 //   k_mean    one thread per particle: F_hat = mean_l F_l, or -inf / NaN
 #include "fstat_internal.h"
 #include "fstat_kernels.h"
+#include "philox.h"
 
 namespace fstat {
 
@@ -116,58 +117,6 @@ __device__ double invert_tf(const PartConst& P, double t, double fa, double fb) 
     if (tf_only(P, fm) < t) fa = fm; else fb = fm;
   }
   return fb;
-}
-
-// Per-particle phase coefficients (see PartConst), double-double where the
-// term they multiply reaches 10^2..10^7 cycles.
-__host__ __device__ void fill_constants(PartConst& P, const double* th) {
-  FSTAT_NO_CONTRACT
-  double tc = th[0], mc = th[1], dmu = th[2], theta = th[3], phi = th[4], e0 = th[5];
-  P.tc = tc;
-  dd m = two_prod(mc, kMsunS);                       // Mc [s], exact
-  P.mc_hi = m.hi; P.mc_lo = m.lo;
-  dd d2 = two_prod(dmu, dmu);
-  dd one_m = dd_add(dd{1.0, 0.0}, dd{-d2.hi, -d2.lo});
-  dd eta = dd{one_m.hi * 0.25, one_m.lo * 0.25};      // (1 - dmu^2)/4
-  const dd pi = {3.141592653589793116e+00, 1.2246467991473532e-16};
-  dd pi13 = dd_root(pi, 3, cbrt(pi.hi));
-  dd ie5 = dd_root(dd_div(dd{1.0, 0.0}, eta), 5, pow(eta.hi, -0.2));   // eta^{-1/5}
-  dd vfac = dd_mul(pi13, ie5);                        // v = vfac (Mc f)^{1/3}
-  dd vf2 = dd_mul(vfac, vfac), vf3 = dd_mul(vf2, vfac);
-  dd pi2 = dd_mul(pi, pi);
-  dd cN = dd_div(dd{3.0, 0.0}, dd_mul_d(dd_mul(pi2, dd_mul(pi13, pi13)), 256.0));
-  dd a2 = dd_add(dd_ratio(3715.0, 756.0), dd_mul(dd_ratio(55.0, 9.0), eta));
-  dd c1 = dd_mul(dd_mul(cN, a2), vf2);
-  dd c15 = dd_mul(dd_mul(cN, dd_mul_d(pi, -16.0)), vf3);
-  dd z = dd_mul_d(m, kF0Ecc);                         // f0 Mc
-  dd z19 = dd_mul(dd_mul(z, z), dd_root(z, 9, pow(z.hi, 1.0 / 9.0)));   // (f0 Mc)^{19/9}
-  dd ce = dd_mul(dd_mul(cN, dd_ratio(-2355.0, 1462.0)), dd_mul(two_prod(e0, e0), z19));
-  P.cN_hi = cN.hi; P.cN_lo = cN.lo;
-  P.c1_hi = c1.hi; P.c1_lo = c1.lo;
-  P.c15_hi = c15.hi; P.c15_lo = c15.lo;
-  P.ce_hi = ce.hi; P.ce_lo = ce.lo;
-  double et = eta.hi, vf = vfac.hi, K = cN.hi;
-  const double pisq = kPi * kPi;
-  double a4 = 15293365.0 / 508032.0 + 27145.0 * et / 504.0 + 3085.0 * et * et / 72.0;
-  double c5p = kPi * (38645.0 / 756.0 - 65.0 * et / 9.0);
-  const double euler = 0.57721566490153286061;
-  double a6c = 11583231236531.0 / 4694215680.0 - 640.0 * pisq / 3.0 - 6848.0 * euler / 21.0 +
-               (-15737765635.0 / 3048192.0 + 2255.0 * pisq / 12.0) * et +
-               76055.0 * et * et / 1728.0 - 127825.0 * et * et * et / 1296.0;
-  double vf4 = vf * vf * vf * vf, vf5 = vf4 * vf, vf6 = vf5 * vf;
-  P.c2 = K * a4 * vf4;
-  P.c5v5 = K * c5p * vf5;
-  P.c5 = 3.0 * P.c5v5;
-  P.c6 = K * vf6;
-  P.b6 = -6848.0 / 21.0;
-  P.a6k = a6c + P.b6 * log(4.0);
-  P.ln_vfac = log(vf);
-  double st, ct, sp, cp;
-  sincos(theta, &st, &ct);
-  sincos(phi, &sp, &cp);
-  P.k[0] = -st * cp; P.k[1] = -st * sp; P.k[2] = -ct;
-  P.u[0] = ct * cp;  P.u[1] = ct * sp;  P.u[2] = -st;
-  P.v[0] = sp;       P.v[1] = -cp;      P.v[2] = 0.0;
 }
 
 __global__ void k_setup(Grid g, const double* __restrict__ params, int64_t n,
@@ -298,6 +247,7 @@ __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
                                                    const double* __restrict__ u,
                                                    const double* __restrict__ s0a,
                                                    const double* __restrict__ c0a,
+                                                   const double* __restrict__ ek,
                                                    double* __restrict__ partials) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -312,6 +262,7 @@ __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
     const int32_t* bp = bounds + (int64_t)p * (stride + 1);
     int b0 = bp[l] + c * chunk;
     int b1 = min(bp[l + 1], b0 + chunk);
+    const double* ekq = (ek && P.sur) ? ek + 8 * (int64_t)q : nullptr;
     // Kahan-compensated per-lane sums (true sum ~ acc - cmp): the partition
     // matrix can have cond ~ 1e5..1e8, which amplifies summation error.
     double acc[8], cmp[8];
@@ -319,14 +270,10 @@ __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
     for (int i = 0; i < 8; ++i) acc[i] = cmp[i] = 0.0;
     for (int j = b0 + lane; j < b1; j += 64) {
       double f = bin_freq(g, j);
-      double fr, tf;
-      phase_and_tf(P, f, fr, tf);
-      double sps, cps;
-      sincospi(2.0 * fr, &sps, &cps);   // e^{i Psi}
-      double tpr, tpi, txr, txi;
-      response_fp64(P, f, tf, s0a[j], c0a[j], tpr, tpi, txr, txi);
+      double cps, sps, tpr, tpi, txr, txi;
+      template_fp64(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq);
       double a = wr[j], b = wi[j], uu = u[j];
-      double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Psi}
+      double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
       double t[8];
       t[0] = Wr * tpr + Wi * tpi;     // Z+ = sum W conj(T'+)
       t[1] = Wi * tpr - Wr * tpi;
@@ -377,55 +324,49 @@ __device__ __forceinline__ void kahan_addf(float& s, float& c, float x) {
   s = t;
 }
 
-__device__ __forceinline__ void response_mixed(const PartConst& P, double f, double tf, float s0,
-                                               float c0, float& tpr, float& tpi, float& txr,
-                                               float& txi) {
+__device__ __forceinline__ void template_mixed(const PartConst& P, double f, float s0, float c0,
+                                               float& cph, float& sph, float& tpr, float& tpi,
+                                               float& txr, float& txi, const double* ek) {
+  double fr, tf;
+  phase_and_tf(P, f, fr, tf, ek);
   double sad, cad;
   sincospi(2.0 * tf * (1.0 / kYear), &sad, &cad);
-  double kP2 = 2.0 * kRs * (P.k[0] * cad + P.k[1] * sad);   // seconds, FP64
-  float sa = (float)sad, ca = (float)cad;
-  float c2a = ca * ca - sa * sa, s2a = 2.0f * sa * ca;
-  const float q = (float)(kLs / (4.0 * kSqrt3));
-  const float hz = (float)(0.5 * kLs);
-  const float cb1 = -0.5f, sb1 = (float)(0.5 * kSqrt3), cb2 = -0.5f, sb2 = -(float)(0.5 * kSqrt3);
-  float d0x = q * (c2a - 3.0f), d0y = q * s2a, d0z = -hz * ca;
-  float d1x = q * (c2a * cb1 + s2a * sb1 - 3.0f * cb1);
-  float d1y = q * (s2a * cb1 - c2a * sb1 - 3.0f * sb1);
-  float d1z = -hz * (ca * cb1 + sa * sb1);
-  float d2x = q * (c2a * cb2 + s2a * sb2 - 3.0f * cb2);
-  float d2y = q * (s2a * cb2 - c2a * sb2 - 3.0f * sb2);
-  float d2z = -hz * (ca * cb2 + sa * sb2);
+  double kP = kRs * (P.k[0] * cad + P.k[1] * sad);      // k . guiding centre [s], FP64
+  float d[3][3];
+  orbit_offsets<float>((float)cad, (float)sad, d);
   const float kx = (float)P.k[0], ky = (float)P.k[1], kz = (float)P.k[2];
   const float ux = (float)P.u[0], uy = (float)P.u[1], uz = (float)P.u[2];
   const float vx = (float)P.v[0], vy = (float)P.v[1], vz = (float)P.v[2];
-  float kd0 = kx * d0x + ky * d0y + kz * d0z;
-  float kd1 = kx * d1x + ky * d1y + kz * d1z;
-  float kd2 = kx * d2x + ky * d2y + kz * d2z;
+  float kd0 = kx * d[0][0] + ky * d[0][1] + kz * d[0][2];
+  sincos_rev(fr + f * (kP + (double)kd0), sph, cph);      // e^{i Phi}
   const float fl = (float)f;
   const float x0 = (float)(kPi * kLs) * fl;
-  float zr = c0 * c0 - s0 * s0, zi = -2.0f * s0 * c0;
+  const float zr = c0 * c0 - s0 * s0, zi = -2.0f * s0 * c0;
   float out[2][4];
 #pragma unroll
   for (int arm = 0; arm < 2; ++arm) {
-    float ax = (arm == 0 ? d1x : d2x) - d0x;
-    float ay = (arm == 0 ? d1y : d2y) - d0y;
-    float az = (arm == 0 ? d1z : d2z) - d0z;
+    float ax = d[arm + 1][0] - d[0][0], ay = d[arm + 1][1] - d[0][1], az = d[arm + 1][2] - d[0][2];
     float inv = __builtin_amdgcn_rsqf(ax * ax + ay * ay + az * az);
     ax *= inv; ay *= inv; az *= inv;
     float kn = kx * ax + ky * ay + kz * az;
     float un = ux * ax + uy * ay + uz * az;
     float vn = vx * ax + vy * ay + vz * az;
-    // exp(-i pi f k.(p0 + p_arm)): -f kp / 2 revolutions, reduced in FP64
-    double kp = kP2 + (double)(kd0 + (arm == 0 ? kd1 : kd2));
-    float se, ce;
-    sincos_rev(-0.5 * f * kp, se, ce);
     float sq, cq;
-    sincos_revf(0.5f * (float)kLs * fl * kn, sq, cq);
-    float sp = sincf_from(s0 * cq + c0 * sq, x0 * (1.0f + kn));
-    float sm = sincf_from(s0 * cq - c0 * sq, x0 * (1.0f - kn));
+    sincos_revf(0.5f * (float)kLs * fl * kn, sq, cq);      // x0 kn
+    float np_ = s0 * cq + c0 * sq, nm = s0 * cq - c0 * sq;
+    float dp = x0 * (1.0f + kn), dm = x0 * (1.0f - kn);
+    float sp, sm;
+    if (fabsf(dp) > 1e-3f && fabsf(dm) > 1e-3f) {
+      float r = __builtin_amdgcn_rcpf(dp * dm);
+      sp = np_ * dm * r;
+      sm = nm * dp * r;
+    } else {
+      sp = sincf_from(np_, dp);
+      sm = sincf_from(nm, dm);
+    }
     float Sr = sp + zr * sm, Si = zi * sm;
-    out[arm][0] = ce * Sr - se * Si;
-    out[arm][1] = ce * Si + se * Sr;
+    out[arm][0] = cq * Sr + sq * Si;
+    out[arm][1] = cq * Si - sq * Sr;
     out[arm][2] = un * un - vn * vn;
     out[arm][3] = 2.0f * un * vn;
   }
@@ -445,6 +386,7 @@ __global__ __launch_bounds__(256) void k_eval_mixed(Grid g,
                                                     const float* __restrict__ u,
                                                     const float* __restrict__ s0a,
                                                     const float* __restrict__ c0a,
+                                                    const double* __restrict__ ek,
                                                     double* __restrict__ partials) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -459,39 +401,168 @@ __global__ __launch_bounds__(256) void k_eval_mixed(Grid g,
     const int32_t* bp = bounds + (int64_t)p * (stride + 1);
     int b0 = bp[l] + c * chunk;
     int b1 = min(bp[l + 1], b0 + chunk);
-    float acc[8], cmp[8];
+    const double* ekq = (ek && P.sur) ? ek + 8 * (int64_t)q : nullptr;
+    // N-terms (Z+, Zx) in FP32 with Kahan; M-terms (P, Q, R) in FP64 from the
+    // FP32 response: the partition matrix can be ill-conditioned, and FP32
+    // sums would leave its weak eigen-direction unresolved.
+    float acc[4], cmp[4];
+    double m4[4];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] = cmp[i] = 0.0f;
+    for (int i = 0; i < 4; ++i) { acc[i] = cmp[i] = 0.0f; m4[i] = 0.0; }
     for (int j = b0 + lane; j < b1; j += 64) {
       double f = bin_freq(g, j);
-      double fr, tf;
-      phase_and_tf(P, f, fr, tf);
-      float sps, cps;
-      sincos_rev(fr, sps, cps);
-      float tpr, tpi, txr, txi;
-      response_mixed(P, f, tf, s0a[j], c0a[j], tpr, tpi, txr, txi);
-      float a = wr[j], b = wi[j], uu = u[j];
+      float cps, sps, tpr, tpi, txr, txi;
+      template_mixed(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq);
+      float a = wr[j], b = wi[j];
       float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
-      float t[8];
-      t[0] = Wr * tpr + Wi * tpi;
-      t[1] = Wi * tpr - Wr * tpi;
-      t[2] = Wr * txr + Wi * txi;
-      t[3] = Wi * txr - Wr * txi;
-      t[4] = uu * (tpr * tpr + tpi * tpi);
-      t[5] = uu * (txr * txr + txi * txi);
-      t[6] = uu * (tpr * txr + tpi * txi);
-      t[7] = uu * (tpi * txr - tpr * txi);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) kahan_addf(acc[i], cmp[i], t[i]);
+      kahan_addf(acc[0], cmp[0], Wr * tpr + Wi * tpi);
+      kahan_addf(acc[1], cmp[1], Wi * tpr - Wr * tpi);
+      kahan_addf(acc[2], cmp[2], Wr * txr + Wi * txi);
+      kahan_addf(acc[3], cmp[3], Wi * txr - Wr * txi);
+      double uu = (double)u[j];
+      double pr = tpr, pi = tpi, xr = txr, xi = txi;
+      m4[0] += uu * (pr * pr + pi * pi);
+      m4[1] += uu * (xr * xr + xi * xi);
+      m4[2] += uu * (pr * xr + pi * xi);
+      m4[3] += uu * (pi * xr - pr * xi);
     }
     double red[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) red[i] = wave_sum((double)acc[i] - (double)cmp[i]);
+    for (int i = 0; i < 4; ++i) red[i] = wave_sum((double)acc[i] - (double)cmp[i]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[4 + i] = wave_sum(m4[i]);
     if (lane == 0) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = red[i];
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// surrogate for the eccentric phase term (App. A): training data, knots,
+// spot check against the analytic term, per-particle decision
+// ---------------------------------------------------------------------------
+// network inputs (f, Mc, e0) mapped to [-1, 1] over f in [10, 100] mHz,
+// Mc in [10, 50] Msun, e0 in [0, 0.15]
+__device__ __forceinline__ float nn_f(double f) { return (float)(2.0 * (f - 0.01) / 0.09 - 1.0); }
+
+// Training samples from the plain template code: target y = te / (ecc_k tN),
+// the eccentric term in units of e0^2 and the Newtonian phase.
+__global__ void k_sur_data(uint64_t seed, int64_t n, float* __restrict__ X, float* __restrict__ T) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t ctr[4] = {(uint64_t)i, 0ull, 0ull, 0ull}, o[4];
+  philox4x64_10(ctr, seed, 0x5u, o);
+  double u0 = (double)(o[0] >> 11) * 0x1.0p-53, u1 = (double)(o[1] >> 11) * 0x1.0p-53,
+         u2 = (double)(o[2] >> 11) * 0x1.0p-53;
+  double f = 0.01 + 0.09 * u0, mc = 10.0 + 40.0 * u1, e0 = 1e-4 + (0.15 - 1e-4) * u2;
+  double th[6] = {0.0, mc, 0.0, 0.0, 0.0, e0};
+  PartConst P;
+  fill_constants(P, th);
+  double tN, te;
+  newton_and_ecc(P, f, tN, te);
+  T[i] = (float)(te / (P.ecc_k * tN));
+  X[3 * i + 0] = nn_f(f);
+  X[3 * i + 1] = (float)P.nn_mc;
+  X[3 * i + 2] = (float)P.nn_e0;
+}
+
+// four knots per partition (bins spread evenly over the partition), for
+// particles with Np >= kSurMinNp; one thread per (partition, knot)
+__device__ __forceinline__ bool sur_candidate(const PartConst& P, int l, const int32_t* bp) {
+  return P.status == kStatusOk && P.np >= kSurMinNp && l < P.np && (bp[l + 1] - bp[l]) >= 4;
+}
+__device__ __forceinline__ int knot_bin(const int32_t* bp, int l, int a) {
+  int nb = bp[l + 1] - bp[l];
+  return bp[l] + (a * (nb - 1)) / 3;
+}
+
+__global__ void k_sur_knots(Grid g, const PartConst* __restrict__ pc,
+                            const int32_t* __restrict__ bounds, int32_t stride, int64_t n,
+                            int64_t rows, float* __restrict__ X) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows) return;
+  if (t >= n * stride * 4) {   // padding rows of the network batch
+    X[3 * t + 0] = 0.f; X[3 * t + 1] = 0.f; X[3 * t + 2] = 0.f;
+    return;
+  }
+  int64_t q = t >> 2;
+  int a = (int)(t & 3);
+  int64_t p = q / stride;
+  int l = (int)(q - p * stride);
+  const PartConst& P = pc[p];
+  const int32_t* bp = bounds + p * (stride + 1);
+  float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+  if (sur_candidate(P, l, bp)) {
+    x0 = nn_f(bin_freq(g, knot_bin(bp, l, a)));
+    x1 = (float)P.nn_mc;
+    x2 = (float)P.nn_e0;
+  }
+  X[3 * t + 0] = x0; X[3 * t + 1] = x1; X[3 * t + 2] = x2;
+}
+
+// knot values -> Lagrange coefficients; mismatch estimate from the residual of
+// the interpolated surrogate against the analytic term at the four knots and
+// the three mid-points, after removing its mean (a constant phase per
+// partition is absorbed by the statistic): mm = (2 pi)^2 var(residual)
+__global__ void k_sur_check(Grid g, const PartConst* __restrict__ pc,
+                            const int32_t* __restrict__ bounds, int32_t stride, int64_t n,
+                            const float* __restrict__ ynn, double* __restrict__ ek,
+                            double* __restrict__ mm) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n * stride) return;
+  int64_t p = q / stride;
+  int l = (int)(q - p * stride);
+  const PartConst& P = pc[p];
+  const int32_t* bp = bounds + p * (stride + 1);
+  if (!sur_candidate(P, l, bp)) {
+    mm[q] = (P.status == kStatusOk && P.np >= kSurMinNp && l < P.np) ? 1e300 : 0.0;
+    return;
+  }
+  double xa[4], va[4];
+  for (int a = 0; a < 4; ++a) {
+    xa[a] = bin_freq(g, knot_bin(bp, l, a));
+    double tN, te;
+    newton_and_ecc(P, xa[a], tN, te);
+    va[a] = P.ecc_k * tN * (double)ynn[4 * q + a];
+  }
+  double* e = ek + 8 * q;
+  for (int a = 0; a < 4; ++a) {
+    double den = 1.0;
+    for (int b = 0; b < 4; ++b)
+      if (b != a) den *= xa[a] - xa[b];
+    e[a] = xa[a];
+    e[4 + a] = va[a] / den;
+  }
+  double r[7], mean = 0.0;
+  for (int i = 0; i < 7; ++i) {
+    int j = (i < 4) ? knot_bin(bp, l, i)
+                    : (knot_bin(bp, l, i - 4) + knot_bin(bp, l, i - 3)) / 2;
+    double f = bin_freq(g, j);
+    double tN, te;
+    newton_and_ecc(P, f, tN, te);
+    r[i] = knot_interp(e, f) - te;
+    mean += r[i];
+  }
+  mean /= 7.0;
+  double var = 0.0;
+  for (int i = 0; i < 7; ++i) var += (r[i] - mean) * (r[i] - mean);
+  mm[q] = 4.0 * kPi * kPi * var / 7.0;
+}
+
+// particle uses the surrogate when every partition's estimate is <= thr
+__global__ void k_sur_decide(PartConst* __restrict__ pc, int64_t n, int32_t stride,
+                             const double* __restrict__ mm, double thr,
+                             unsigned long long* __restrict__ counters) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  PartConst& P = pc[p];
+  if (P.status != kStatusOk || P.np < kSurMinNp) return;
+  double worst = 0.0;
+  for (int l = 0; l < P.np; ++l) worst = fmax(worst, mm[p * stride + l]);
+  int use = worst <= thr ? 1 : 0;
+  P.sur = use;
+  atomicAdd(counters + (use ? 0 : 1), 1ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -563,15 +634,18 @@ __global__ void k_waveform(Grid g, const PartConst* __restrict__ pc,
     return;
   }
   double f = bin_freq(g, j);
-  double fr, tf;
-  phase_and_tf(P, f, fr, tf);
-  double sps, cps;
-  sincospi(2.0 * (fr - 0.125), &sps, &cps);   // Psi includes -pi/4 (App. A)
   double s0, c0;
   sincospi(kLs * f, &s0, &c0);
-  double tpr, tpi, txr, txi;
-  response_fp64(P, f, tf, s0, c0, tpr, tpi, txr, txi);
-  // full transfer T = C T'
+  double cph, sph, tpr, tpi, txr, txi;
+  template_fp64(P, f, s0, c0, cph, sph, tpr, tpi, txr, txi);
+  // restore the constant phases the statistic drops: -pi/4 (App. A) and the
+  // f-independent part of the alpha_5 term, c5' cN vfac^5 (1 + 3 ln sqrt 6)
+  double ph0 = -0.125 + P.c5v5 * (1.0 + 1.5 * log(6.0));
+  ph0 -= rint(ph0);
+  double sc, cc;
+  sincospi(2.0 * ph0, &sc, &cc);
+  double cps = cph * cc - sph * sc, sps = sph * cc + cph * sc;   // e^{i Phi_full}
+  // full transfer: C(f) times the particle part T''
   double x0 = kPi * kLs * f;
   double zr = c0 * c0 - s0 * s0, zi = -2.0 * s0 * c0;
   double omr = 1.0 - (zr * zr - zi * zi), omi = -2.0 * zr * zi;
@@ -579,12 +653,12 @@ __global__ void k_waveform(Grid g, const PartConst* __restrict__ pc,
   double Cr = omr * er - omi * ei, Ci = omr * ei + omi * er;
   double Tpr = Cr * tpr - Ci * tpi, Tpi = Cr * tpi + Ci * tpr;
   double Txr = Cr * txr - Ci * txi, Txi = Cr * txi + Ci * txr;
-  // h = g [(a1 - i a3) T+ + (-a2 + i a4) Tx],  g = f^{-7/6} e^{-i Psi}
+  // h = f^{-7/6} e^{-i Phi} [(a1 - i a3) T+ + (-a2 + i a4) Tx]  (App. B basis)
   double a1 = amps[0], a2 = amps[1], a3 = amps[2], a4 = amps[3];
   double hr = (a1 * Tpr + a3 * Tpi) + (-a2 * Txr - a4 * Txi);
   double hi = (a1 * Tpi - a3 * Tpr) + (-a2 * Txi + a4 * Txr);
   double amp = pow(f, -7.0 / 6.0);
-  // multiply by e^{-i Psi} = cps - i sps
+  // multiply by e^{-i Phi} = cps - i sps
   out[2 * j] = amp * (hr * cps + hi * sps);
   out[2 * j + 1] = amp * (hi * cps - hr * sps);
 }
@@ -627,15 +701,15 @@ void launch_worklist(int64_t m, const WorkSpace& ws, hipStream_t s) {
 }
 
 void launch_eval(bool mixed, const Grid& g, int32_t stride, int32_t chunk,
-                 const WorkSpace& ws, BinData<double> b, BinData<float> b32, int blocks,
-                 hipStream_t s) {
+                 const WorkSpace& ws, BinData<double> b, BinData<float> b32, const double* ek,
+                 int blocks, hipStream_t s) {
   if (mixed)
     hipLaunchKernelGGL(k_eval_mixed, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
-                       ws.items, ws.total, chunk, b32.wr, b32.wi, b32.u, b32.s0, b32.c0,
+                       ws.items, ws.total, chunk, b32.wr, b32.wi, b32.u, b32.s0, b32.c0, ek,
                        ws.partials);
   else
     hipLaunchKernelGGL(k_eval_fp64, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
-                       ws.items, ws.total, chunk, b.wr, b.wi, b.u, b.s0, b.c0, ws.partials);
+                       ws.items, ws.total, chunk, b.wr, b.wi, b.u, b.s0, b.c0, ek, ws.partials);
 }
 
 void launch_solve_mean(int64_t n, int32_t stride, const WorkSpace& ws, double* F_hat,
@@ -646,6 +720,25 @@ void launch_solve_mean(int64_t n, int32_t stride, const WorkSpace& ws, double* F
                      ws.off, ws.partials, ws.Fl, F_part, part_stride);
   hipLaunchKernelGGL(k_mean, dim3(nblk(n, 256)), dim3(256), 0, s, ws.pc, n, stride, ws.Fl, F_hat,
                      F_part, part_stride, bin_counter);
+}
+
+void launch_sur_data(uint64_t seed, int64_t n, float* X, float* T, hipStream_t s) {
+  hipLaunchKernelGGL(k_sur_data, dim3(nblk(n, 128)), dim3(128), 0, s, seed, n, X, T);
+}
+
+void launch_sur_knots(const Grid& g, int32_t stride, int64_t n, int64_t rows, const WorkSpace& ws,
+                      float* X, hipStream_t s) {
+  hipLaunchKernelGGL(k_sur_knots, dim3(nblk(rows, 256)), dim3(256), 0, s, g, ws.pc, ws.bounds,
+                     stride, n, rows, X);
+}
+
+void launch_sur_check(const Grid& g, int32_t stride, int64_t n, const WorkSpace& ws,
+                      const float* ynn, double* ek, double* mm, double thr,
+                      unsigned long long* counters, hipStream_t s) {
+  hipLaunchKernelGGL(k_sur_check, dim3(nblk(n * stride, 128)), dim3(128), 0, s, g, ws.pc,
+                     ws.bounds, stride, n, ynn, ek, mm);
+  hipLaunchKernelGGL(k_sur_decide, dim3(nblk(n, 128)), dim3(128), 0, s, ws.pc, n, stride, mm, thr,
+                     counters);
 }
 
 void launch_waveform(const Grid& g, const PartConst* pc, const double* amps,

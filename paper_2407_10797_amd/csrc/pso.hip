@@ -17,42 +17,9 @@
 
 #include "../../include/fstat.h"
 #include "fstat_api_internal.h"
+#include "philox.h"
 
 namespace fstat {
-
-constexpr uint64_t kPhM0 = 0xD2E7470EE14C6C93ull;
-constexpr uint64_t kPhM1 = 0xCA5A826395121157ull;
-constexpr uint64_t kPhW0 = 0x9E3779B97F4A7C15ull;
-constexpr uint64_t kPhW1 = 0xBB67AE8584CAA73Bull;
-
-__device__ __forceinline__ void philox4x64_10(const uint64_t ctr_in[4], uint64_t k0, uint64_t k1,
-                                              uint64_t out[4]) {
-  uint64_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r > 0) {
-      k0 += kPhW0;
-      k1 += kPhW1;
-    }
-    uint64_t lo0 = kPhM0 * c0, hi0 = __umul64hi(kPhM0, c0);
-    uint64_t lo1 = kPhM1 * c2, hi1 = __umul64hi(kPhM1, c2);
-    uint64_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
-    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
-  }
-  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
-}
-
-// 12 uniforms in [0, 1) for (run, t, particle)
-__device__ __forceinline__ void draw12(uint64_t seed, uint64_t run, uint64_t t, uint64_t i,
-                                       double u[12]) {
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    uint64_t ctr[4] = {t, i, (uint64_t)b, 0ull}, o[4];
-    philox4x64_10(ctr, seed, run, o);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) u[4 * b + m] = (double)(o[m] >> 11) * 0x1.0p-53;
-  }
-}
 
 struct PsoArgs {
   int32_t n_runs, n_part, iters, ring_k;
@@ -207,6 +174,8 @@ extern "C" int pso_stage(fstat_plan_t P, const pso_stage_desc* d, pso_result* re
       !std::isfinite(d->c1) || !std::isfinite(d->c2))
     return set_error(FSTAT_EINVAL, "bad PSO coefficients");
   const bool mixed = (d->flags & FSTAT_EVAL_MIXED) != 0;
+  const bool sur = (d->flags & FSTAT_EVAL_SURROGATE) != 0;
+  if (sur && !P->sur_trained) return set_error(FSTAT_EINVAL, "surrogate requested but not trained");
   if (mixed && !(P->prec & FSTAT_MIXED)) return set_error(FSTAT_EINVAL, "plan has no mixed data");
   if (!mixed && !(P->prec & FSTAT_FP64)) return set_error(FSTAT_EINVAL, "plan has no FP64 data");
   int32_t stride = 1;
@@ -244,6 +213,7 @@ extern "C" int pso_stage(fstat_plan_t P, const pso_stage_desc* d, pso_result* re
       (rc = hip_check(hipMemcpyAsync(np_run, d->np, sizeof(int32_t) * R, hipMemcpyHostToDevice, s), "copy np")))
     return rc;
   if ((rc = ensure_workspace(P, n, stride))) return rc;
+  if (sur && (rc = sur_ensure(P, n, stride))) return rc;   // no allocation inside the capture
   (void)eval_blocks(P, mixed);   // occupancy query outside any capture
   PsoArgs a{R, Pn, I, d->ring_k, d->w_start, d->w_end, d->c1, d->c2, d->vmax, d->seed};
   const unsigned nb = (unsigned)((n + 255) / 256);
@@ -252,7 +222,7 @@ extern "C" int pso_stage(fstat_plan_t P, const pso_stage_desc* d, pso_result* re
   const size_t shmem = sizeof(double) * Pn + sizeof(int) * 2;
   auto iteration = [&]() -> int {
     hipLaunchKernelGGL(k_pso_decode, dim3(nb), dim3(256), 0, s, a, x, box, np_run, params, np, skip);
-    int r2 = eval_device(P, params, n, np, 0, stride, F, nullptr, 0, mixed, s, skip, false);
+    int r2 = eval_device(P, params, n, np, 0, stride, F, nullptr, 0, mixed, s, skip, false, sur);
     if (r2) return r2;
     hipLaunchKernelGGL(k_pso_update, dim3(R), dim3(tpb), shmem, s, a, F, x, v, pbx, pbf, gbx, gbf,
                        trace, iter);

@@ -24,9 +24,11 @@ FSTAT_MIXED = 2
 FSTAT_DEVICE_PTRS = 1
 FSTAT_EVAL_MIXED = 2
 FSTAT_PROFILE = 4
+FSTAT_EVAL_SURROGATE = 8
 
 EXPORTS = ("fstat_plan_create", "fstat_eval", "fstat_waveform", "pso_stage",
-           "fstat_profile_read", "fstat_plan_destroy", "fstat_last_error")
+           "fstat_profile_read", "fstat_mlp_grad", "fstat_surrogate_train",
+           "fstat_surrogate_stats", "fstat_plan_destroy", "fstat_last_error")
 
 
 class fstat_data_desc(ctypes.Structure):
@@ -52,6 +54,12 @@ class pso_stage_desc(ctypes.Structure):
 class pso_result(ctypes.Structure):
     _fields_ = [("best_x", ctypes.c_void_p), ("best_F", ctypes.c_void_p),
                 ("trace", ctypes.c_void_p), ("final_x", ctypes.c_void_p)]
+
+
+class fstat_surrogate_desc(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int64), ("batch", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("lr", ctypes.c_double), ("seed", ctypes.c_uint64), ("loss_trace", ctypes.c_void_p),
+                ("val_rmse", ctypes.c_double), ("val_max", ctypes.c_double)]
 
 
 class FstatError(RuntimeError):
@@ -83,6 +91,12 @@ def lib() -> ctypes.CDLL:
         L.fstat_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.fstat_profile_read.restype = ctypes.c_int
+        L.fstat_mlp_grad.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double), vp, vp]
+        L.fstat_mlp_grad.restype = ctypes.c_int
+        L.fstat_surrogate_train.argtypes = [vp, ctypes.POINTER(fstat_surrogate_desc), vp]
+        L.fstat_surrogate_train.restype = ctypes.c_int
+        L.fstat_surrogate_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.fstat_surrogate_stats.restype = ctypes.c_int
         L.fstat_plan_destroy.argtypes = [vp]
         L.fstat_plan_destroy.restype = None
         L.fstat_last_error.argtypes = []
@@ -130,6 +144,30 @@ def fstat_profile_read(plan, reset: bool = True):
     return ms.value, n.value, bins.value
 
 
+def fstat_mlp_grad(params, x, t):
+    """(loss, grad, y) of one device forward/backward pass of the surrogate."""
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    B = x.shape[0]
+    grad = np.zeros_like(params)
+    y = np.zeros(B, dtype=np.float32)
+    loss = ctypes.c_double()
+    _check(lib().fstat_mlp_grad(params.ctypes.data, x.ctypes.data, t.ctypes.data, int(B),
+                                ctypes.byref(loss), grad.ctypes.data, y.ctypes.data))
+    return loss.value, grad, y
+
+
+def fstat_surrogate_train(plan, desc: fstat_surrogate_desc, stream=None):
+    _check(lib().fstat_surrogate_train(plan, ctypes.byref(desc), stream))
+
+
+def fstat_surrogate_stats(plan):
+    used, fb = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().fstat_surrogate_stats(plan, ctypes.byref(used), ctypes.byref(fb)))
+    return used.value, fb.value
+
+
 def fstat_plan_destroy(plan) -> None:
     if plan:
         lib().fstat_plan_destroy(plan)
@@ -170,7 +208,7 @@ class Plan:
         torch.cuda.current_stream().synchronize()
 
     def eval(self, params, np_parts=1, part_stride: int | None = None, mixed: bool = False,
-             want_parts: bool = False):
+             want_parts: bool = False, surrogate: bool = False):
         """F_hat [n] (and F_part [n, stride]) for params [n, 6] on the device."""
         torch = _torch()
         prm = torch.as_tensor(params).to("cuda", torch.float64).contiguous()
@@ -185,7 +223,8 @@ class Plan:
             npp, npu = np_t.data_ptr(), 0
             stride = part_stride or int(np_t.max().item())
         Fp = torch.zeros((n, stride), device="cuda", dtype=torch.float64) if want_parts else None
-        flags = FSTAT_DEVICE_PTRS | (FSTAT_EVAL_MIXED if mixed else 0)
+        flags = (FSTAT_DEVICE_PTRS | (FSTAT_EVAL_MIXED if mixed else 0)
+                 | (FSTAT_EVAL_SURROGATE if surrogate else 0))
         fstat_eval(self.handle, prm.data_ptr(), n, npp, npu, F.data_ptr(),
                    Fp.data_ptr() if Fp is not None else None, stride, flags, _stream())
         return (F, Fp) if want_parts else F
@@ -193,7 +232,7 @@ class Plan:
     def pso(self, box, np_runs, n_part: int, iters: int, ring_k: int = 1, w=(0.7, 0.7),
             c1: float = 1.5, c2: float = 1.5, vmax: float = 0.5, seed: int = 1,
             mixed: bool = False, use_graph: bool = True, want_trace: bool = True,
-            want_final: bool = False):
+            want_final: bool = False, surrogate: bool = False):
         """Run pso_stage: box [R, 6, 2] (physical), np_runs [R].  Returns dict
         with best_x [R, 6], best_F [R], trace [iters, R], final_x [R, n_part, 6]."""
         _torch()
@@ -205,7 +244,9 @@ class Plan:
         final_x = np.zeros((R, n_part, 6)) if want_final else None
         desc = pso_stage_desc(R, int(n_part), int(iters), int(ring_k), float(w[0]), float(w[1]),
                               float(c1), float(c2), float(vmax), int(seed), box.ctypes.data,
-                              npr.ctypes.data, FSTAT_EVAL_MIXED if mixed else 0, int(use_graph))
+                              npr.ctypes.data,
+                              (FSTAT_EVAL_MIXED if mixed else 0) | (FSTAT_EVAL_SURROGATE if surrogate else 0),
+                              int(use_graph))
         res = pso_result(best_x.ctypes.data, best_F.ctypes.data,
                          trace.ctypes.data if trace is not None else None,
                          final_x.ctypes.data if final_x is not None else None)
@@ -216,6 +257,24 @@ class Plan:
         if final_x is not None:
             out["final_x"] = final_x
         return out
+
+    def train_surrogate(self, n_samples: int = 2_000_000, batch: int = 4096, steps: int = 4000,
+                        lr: float = 1e-3, seed: int = 5001, want_trace: bool = False):
+        """Train the eccentric-phase surrogate on the device; returns a dict with
+        held-out rmse/max error (network units) and optionally the loss trace."""
+        trace = np.zeros(steps) if want_trace else None
+        desc = fstat_surrogate_desc(int(n_samples), int(batch), int(steps), float(lr), int(seed),
+                                    trace.ctypes.data if trace is not None else None, 0.0, 0.0)
+        fstat_surrogate_train(self.handle, desc, _stream())
+        out = dict(val_rmse=desc.val_rmse, val_max=desc.val_max)
+        if trace is not None:
+            out["loss_trace"] = trace
+        return out
+
+    def surrogate_stats(self):
+        """(particles that used the surrogate, particles that fell back) in the last
+        surrogate evaluation."""
+        return fstat_surrogate_stats(self.handle)
 
     def profile_read(self, reset: bool = True):
         """(bin-loop kernel ms total, launches, bin-template evaluations)."""

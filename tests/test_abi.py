@@ -15,8 +15,9 @@ def _declared():
 
 def test_header_declares_the_boundary():
     assert _declared() == sorted(["fstat_plan_create", "fstat_eval", "fstat_waveform",
-                                  "pso_stage", "fstat_profile_read", "fstat_plan_destroy",
-                                  "fstat_last_error"])
+                                  "pso_stage", "fstat_profile_read", "fstat_mlp_grad",
+                                  "fstat_surrogate_train", "fstat_surrogate_stats",
+                                  "fstat_plan_destroy", "fstat_last_error"])
 
 
 def test_library_loads_and_exports_every_declared_symbol():
@@ -43,6 +44,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(fstat.fstat_opts) == 16
     assert ctypes.sizeof(fstat.pso_stage_desc) == 88
     assert ctypes.sizeof(fstat.pso_result) == 32
+    assert ctypes.sizeof(fstat.fstat_surrogate_desc) == 56
 
 
 def test_last_error_is_empty_string_initially():

@@ -367,3 +367,23 @@ def test_pso_oracle_dynamics_on_a_quadratic():
                  c1=2.0, c2=2.0, vmax=0.5, seed=11)
     assert np.all(np.diff(out["trace"], axis=0) >= 0)
     np.testing.assert_allclose(out["best_x"], centre[None, :], atol=1e-4)
+
+
+def test_mlp_oracle_gradient_matches_finite_differences():
+    """Backward pass of the surrogate reference equals central differences
+    of its own loss (checked on a random subset of parameters)."""
+    from oracle import mlp_oracle as MO
+    rng = np.random.default_rng(2)
+    p = MO.init(3)
+    x = rng.uniform(-1, 1, (16, 3))
+    t = rng.normal(size=16)
+    loss, g = MO.loss_and_grad(p, x, t)
+    assert p.size == g.size == MO.N_PARAMS == 198657
+    idx = rng.choice(p.size, 40, replace=False)
+    idx = np.concatenate([idx, [0, 767, 1023, 198400, 198656]])
+    for i in idx:
+        h = 1e-6
+        pp = p.copy(); pp[i] += h
+        pm = p.copy(); pm[i] -= h
+        fd = (MO.loss_and_grad(pp, x, t)[0] - MO.loss_and_grad(pm, x, t)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
