@@ -65,6 +65,50 @@ def time_path(plan, prm, npart, steps, warmup, mixed, surrogate=False):
                 bins_per_launch=bins / max(launches, 1), F=F)
 
 
+def pso_boxes(inj, R, seed=4001):
+    """Uneven per-run boxes around the injection: Mc widths log-spaced from 1 %
+    to 0.01 %, t_c windows of 1..30 days, full sky, e0 in [0, 0.1]."""
+    rng = np.random.default_rng(seed)
+    widths = np.logspace(-2, -4, R)
+    boxes = np.zeros((R, 6, 2))
+    for r in range(R):
+        wt = rng.uniform(1, 30) * 86400.0
+        ct = inj[0] + rng.uniform(-0.3, 0.3) * wt
+        cm = inj[1] * (1 + rng.uniform(-0.3, 0.3) * widths[r])
+        boxes[r] = [[ct - wt / 2, ct + wt / 2], [cm * (1 - widths[r] / 2), cm * (1 + widths[r] / 2)],
+                    [inj[2], inj[2]], [0.0, np.pi], [0.0, 2 * np.pi], [0.0, 0.1]]
+    return boxes
+
+
+def pso_bench(iters):
+    """Batched PSO stage on the 20,972-bin workload: 8 runs x 40 particles,
+    per-run Np 256/64/16/1 in every launch, (w, c1, c2) = (0.7, 1.5, 1.5)."""
+    import torch
+    from paper_2407_10797_amd import fstat, synth as S
+    g = S.grid_small()
+    inj = S.small_injection_params()
+    sig = fstat.waveform(g.T_obs, g.df, g.k_lo, g.nbins, inj,
+                         S.random_amplitudes(S.SMALL_SEEDS["inj"])).cpu().numpy()
+    data, psd = S.make_data(g, S.SMALL_SEEDS["noise"], sig, S.SMALL_SNR)
+    plan = fstat.Plan(data, psd, g.T_obs, g.df, g.k_lo)
+    boxes = pso_boxes(inj, 8)
+    nps = np.array([256, 64, 16, 1] * 2, dtype=np.int32)
+    out = {}
+    for mode, graph in (("graph", True), ("eager", False)):
+        plan.pso(boxes, nps, n_part=40, iters=20, use_graph=graph, seed=4001)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = plan.pso(boxes, nps, n_part=40, iters=iters, use_graph=graph, seed=4001)
+        dt = time.perf_counter() - t0
+        out[mode] = dict(iterations_per_s=iters / dt, templates_per_s=320 * iters / dt,
+                         us_per_iteration=1e6 * dt / iters)
+    out["best_F"] = [float(x) for x in res["best_F"]]
+    out["config"] = "8 runs x 40 particles, per-run Np 256/64/16/1, 20,972-bin data, " \
+                    f"{iters} iterations, w=0.7 c1=c2=1.5 vmax=0.5 ring radius 1"
+    plan.close()
+    return out
+
+
 def cpu_baseline(g, data, psd, pts, npart, sample):
     from oracle import oracle as O
     sub = pts[:sample]
@@ -90,13 +134,14 @@ def main():
     ap.add_argument("--only", choices=["fp64", "mixed", "mixed+surrogate"], default=None)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-steps", type=int, default=3000)
+    ap.add_argument("--pso-iters", type=int, default=2000, help="0 skips the PSO measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (for scaling "
                          "FETCH_SIZE/WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (got --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not implemented", file=sys.stderr)
+        print(f"bench.py: measures exactly one GPU (got --gpus {args.gpus}); "
+              "sharding across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2407_10797_amd import fstat
@@ -165,11 +210,16 @@ def main():
         "roofline": head["roofline"],
         "variants": variants,
     }
+    plan.close()
+    if args.pso_iters > 0:
+        _log("batched PSO stage")
+        out["pso"] = pso_bench(args.pso_iters)
+        _log(f"pso: {out['pso']['graph']['iterations_per_s']:.1f} iterations/s with hipGraph, "
+             f"{out['pso']['eager']['iterations_per_s']:.1f} eager")
     if not args.no_cpu:
         _log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(g, data, psd, pts, args.np, args.cpu_sample)
     print(json.dumps(out), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":

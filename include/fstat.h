@@ -61,6 +61,7 @@ extern "C" {
 #define FSTAT_PROFILE 4u      /* fstat_opts.flags: time the bin-loop kernel  */
 #define FSTAT_EVAL_SURROGATE 8u /* fstat_eval / pso_stage: learned eccentric
                                    phase for particles with Np >= 16        */
+#define FSTAT_AUTOTUNE_FORCE 16u /* fstat_autotune: ignore the cache         */
 
 typedef struct fstat_plan_s *fstat_plan_t;
 
@@ -115,6 +116,18 @@ int fstat_eval(fstat_plan_t plan, const double *params, int64_t n, const int32_t
  * FSTAT_DEVICE_PTRS (params, amps and out all on the device).           */
 int fstat_waveform(double T_obs, double df, int64_t k_lo, int64_t nbins, const double *params6,
                    const double *amps4, double *out, uint32_t flags, void *hip_stream);
+
+/* Autotuner for the bin loop: times fstat_eval of `params` (device pointers,
+ * n particles, uniform np) for work items of 256..8192 bins and persistent
+ * grids of 1, 2, 4 times the resident occupancy, keeps the fastest for the
+ * precision selected by flags (FSTAT_EVAL_MIXED) in the plan, and returns it.
+ * Results are cached in the text file named by $FSTAT_TUNE_CACHE (if set),
+ * keyed by GPU architecture, band size, Np class and precision;
+ * FSTAT_AUTOTUNE_FORCE re-measures.  Requires FSTAT_DEVICE_PTRS; waits for
+ * completion.  best_ms is -1 when the value came from the cache.          */
+int fstat_autotune(fstat_plan_t plan, const double *params, int64_t n, int32_t np_uniform,
+                   uint32_t flags, int32_t *best_chunk, int32_t *best_mult, double *best_ms,
+                   void *hip_stream);
 
 /* ---- particle swarm stage (Sec. III.A; batched runs of Sec. III.B) -------- */
 typedef struct {

@@ -4,6 +4,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -56,10 +58,11 @@ static int ensure(T** p, size_t* cap, size_t need, const char* what) {
   return rc;
 }
 
-int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride) {
+int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride, int chunk) {
   int rc;
+  if (chunk <= 0) chunk = P->chunk;
   size_t m = (size_t)n * (size_t)stride;
-  size_t cap_items = (size_t)n * ((size_t)((P->grid.nbins + P->chunk - 1) / P->chunk) + stride);
+  size_t cap_items = (size_t)n * ((size_t)((P->grid.nbins + chunk - 1) / chunk) + stride);
   if (cap_items > (size_t)INT32_MAX)
     return set_error(FSTAT_EINVAL, "work list too large (%zu items)", cap_items);
   if ((rc = ensure(&P->ws.pc, &P->cap.pc, (size_t)n, "alloc pc"))) return rc;
@@ -75,23 +78,26 @@ int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride) {
 
 int eval_blocks(fstat_plan_s* P, bool mixed) {
   int& cached = mixed ? P->blocks_mixed : P->blocks_fp64;
-  if (cached > 0) return cached;
-  int per_cu = 0;
-  hipError_t e = mixed ? occupancy_mixed(&per_cu) : occupancy_fp64(&per_cu);
-  if (e != hipSuccess || per_cu < 1) per_cu = 2;
-  cached = P->num_cu * per_cu;
-  return cached;
+  if (cached <= 0) {
+    int per_cu = 0;
+    hipError_t e = mixed ? occupancy_mixed(&per_cu) : occupancy_fp64(&per_cu);
+    if (e != hipSuccess || per_cu < 1) per_cu = 2;
+    cached = P->num_cu * per_cu;
+  }
+  return cached * (mixed ? P->grid_mult_mixed : P->grid_mult_fp64);
 }
+
 
 // Enqueue one evaluation with device pointers.
 int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t* np,
                 int32_t np_uniform, int32_t stride, double* F_hat, double* F_part,
                 int64_t part_stride, bool mixed, hipStream_t s, const uint8_t* skip,
                 bool allow_profile, bool surrogate) {
-  int rc = ensure_workspace(P, n, stride);
+  const int chunk = chunk_for(P, mixed);
+  int rc = ensure_workspace(P, n, stride, chunk);
   if (rc) return rc;
   if (surrogate && (rc = sur_ensure(P, n, stride))) return rc;
-  launch_setup(P->grid, params, n, np, np_uniform, stride, P->chunk, skip, P->ws, s);
+  launch_setup(P->grid, params, n, np, np_uniform, stride, chunk, skip, P->ws, s);
   if (surrogate && (rc = sur_prepare(P, n, stride, s))) return rc;
   launch_worklist(n * (int64_t)stride, P->ws, s);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -101,7 +107,7 @@ int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t*
       return rc;
     (void)hipEventRecord(e0, s);
   }
-  launch_eval(mixed, P->grid, stride, P->chunk, P->ws, P->b64, P->b32,
+  launch_eval(mixed, P->grid, stride, chunk, P->ws, P->b64, P->b32,
               surrogate ? P->sur_ek : nullptr, eval_blocks(P, mixed), s);
   if (prof) {
     (void)hipEventRecord(e1, s);
@@ -111,9 +117,128 @@ int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t*
   return hip_check(hipGetLastError(), "kernel launch");
 }
 
+// ---- autotuner --------------------------------------------------------------
+static std::string tune_key(const fstat_plan_s* P, int32_t np, bool mixed) {
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) arch = prop.gcnArchName;
+  int npc = 1;
+  while (npc < np) npc <<= 1;
+  int nbc = 0;
+  while ((1ll << nbc) < P->grid.nbins) ++nbc;
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s nbins2^%d np%d %s", arch.c_str(), nbc, npc, mixed ? "mixed" : "fp64");
+  for (char* c = buf; *c; ++c)
+    if (*c == ':') *c = '_';
+  return buf;
+}
+
+// Choices made in this process, keyed like the cache file.
+static std::mutex g_tune_mu;
+static std::map<std::string, std::pair<int, int>> g_tune_mem;
+
+static bool tune_cache_get(const std::string& key, int* chunk, int* mult) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_mem.find(key);
+    if (it != g_tune_mem.end()) {
+      *chunk = it->second.first; *mult = it->second.second;
+      return true;
+    }
+  }
+  const char* path = getenv("FSTAT_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* fp = fopen(path, "r");
+  if (!fp) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof(line), fp)) {
+    char k[400];
+    int c, m;
+    if (sscanf(line, "%399[^|]|%d %d", k, &c, &m) == 3 && key == k) {
+      *chunk = c; *mult = m; found = true;   // last entry wins
+    }
+  }
+  fclose(fp);
+  return found;
+}
+
+static void tune_cache_put(const std::string& key, int chunk, int mult) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_mem[key] = {chunk, mult};
+  }
+  const char* path = getenv("FSTAT_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* fp = fopen(path, "a");
+  if (!fp) return;
+  fprintf(fp, "%s|%d %d\n", key.c_str(), chunk, mult);
+  fclose(fp);
+}
+
 }  // namespace fstat
 
 extern "C" {
+
+int fstat_autotune(fstat_plan_t P, const double* params, int64_t n, int32_t np_uniform,
+                   uint32_t flags, int32_t* best_chunk, int32_t* best_mult, double* best_ms,
+                   void* hip_stream) {
+  g_err.clear();
+  if (!P || !params || n < 1 || np_uniform < 1 || np_uniform > 65536)
+    return set_error(FSTAT_EINVAL, "fstat_autotune: bad arguments");
+  if (!(flags & FSTAT_DEVICE_PTRS)) return set_error(FSTAT_EINVAL, "fstat_autotune needs device pointers");
+  const bool mixed = (flags & FSTAT_EVAL_MIXED) != 0;
+  if (mixed ? !(P->prec & FSTAT_MIXED) : !(P->prec & FSTAT_FP64))
+    return set_error(FSTAT_EINVAL, "precision not built into the plan");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const std::string key = tune_key(P, np_uniform, mixed);
+  int c = 0, m = 0;
+  double ms_best = -1.0;
+  if (!(flags & FSTAT_AUTOTUNE_FORCE) && tune_cache_get(key, &c, &m) && c >= 64 && m >= 1) {
+    // cached
+  } else {
+    static const int chunks[] = {256, 512, 1024, 2048, 4096, 8192};
+    static const int mults[] = {1, 2, 4};
+    double* F = nullptr;
+    int rc = hip_check(hipMalloc(&F, sizeof(double) * n), "alloc tune out");
+    hipEvent_t e0, e1;
+    if (!rc) rc = hip_check(hipEventCreate(&e0), "event");
+    if (!rc) rc = hip_check(hipEventCreate(&e1), "event");
+    const int save_c = P->chunk, save_cm = P->chunk_mixed;
+    const int save_m = mixed ? P->grid_mult_mixed : P->grid_mult_fp64;
+    for (int ci = 0; ci < 6 && !rc; ++ci)
+      for (int mi = 0; mi < 3 && !rc; ++mi) {
+        if (mixed) { P->chunk_mixed = chunks[ci]; P->grid_mult_mixed = mults[mi]; }
+        else { P->chunk = chunks[ci]; P->grid_mult_fp64 = mults[mi]; }
+        double t_min = 1e300;
+        for (int rep = 0; rep < 3 && !rc; ++rep) {
+          rc = hip_check(hipEventRecord(e0, s), "record");
+          if (!rc) rc = eval_device(P, params, n, nullptr, np_uniform, np_uniform, F, nullptr, 0,
+                                    mixed, s, nullptr, false, false);
+          if (!rc) rc = hip_check(hipEventRecord(e1, s), "record");
+          if (!rc) rc = hip_check(hipEventSynchronize(e1), "sync");
+          float ms = 0.f;
+          if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+          if (rep > 0 && ms < t_min) t_min = ms;   // first repetition is a warm-up
+        }
+        if (!rc && (ms_best < 0 || t_min < ms_best)) { ms_best = t_min; c = chunks[ci]; m = mults[mi]; }
+      }
+    P->chunk = save_c; P->chunk_mixed = save_cm;
+    if (mixed) P->grid_mult_mixed = save_m; else P->grid_mult_fp64 = save_m;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (F) (void)hipFree(F);
+    if (rc) return rc;
+    tune_cache_put(key, c, m);
+  }
+  if (mixed) { P->chunk_mixed = c; P->grid_mult_mixed = m; }
+  else { P->chunk = c; P->grid_mult_fp64 = m; }
+  if (best_chunk) *best_chunk = c;
+  if (best_mult) *best_mult = m;
+  if (best_ms) *best_ms = ms_best;
+  return FSTAT_OK;
+}
+
 
 const char* fstat_last_error(void) { return g_err.c_str(); }
 

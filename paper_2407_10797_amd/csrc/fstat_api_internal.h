@@ -19,7 +19,9 @@ struct fstat_plan_s {
   int device = 0;
   int num_cu = 0;
   int prec = 0;
-  int chunk = 2048;
+  int chunk = 2048;                 // bins per work item (both precisions unless tuned)
+  int chunk_mixed = 0;              // tuned value for the mixed path (0: use chunk)
+  int grid_mult_fp64 = 1, grid_mult_mixed = 1;   // persistent-grid multiplier
   int blocks_fp64 = 0, blocks_mixed = 0;
   fstat::Grid grid{};
   fstat::BinData<double> b64{};
@@ -51,9 +53,12 @@ struct fstat_plan_s {
 };
 
 namespace fstat {
+inline int chunk_for(const fstat_plan_s* P, bool mixed) {
+  return (mixed && P->chunk_mixed > 0) ? P->chunk_mixed : P->chunk;
+}
 int set_error(int code, const char* fmt, ...);
 int hip_check(hipError_t e, const char* what);
-int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride);
+int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride, int chunk = 0);
 int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t* np,
                 int32_t np_uniform, int32_t stride, double* F_hat, double* F_part,
                 int64_t part_stride, bool mixed, hipStream_t s, const uint8_t* skip = nullptr,

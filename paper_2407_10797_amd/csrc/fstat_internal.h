@@ -248,7 +248,7 @@ __host__ __device__ inline void fill_constants(PartConst& P, const double* th) {
 
 // Newtonian and eccentric phase terms (cycles) of the plain template at f:
 // tN = cN y^5 and te = ce y^{34/3} (App. A), in double precision; used to
-// build the surrogate's training targets and to judge its knot values.
+// build the surrogate's training targets and to check its knot values.
 __host__ __device__ __forceinline__ void newton_and_ecc(const PartConst& P, double f, double& tN,
                                                        double& te) {
   FSTAT_NO_CONTRACT

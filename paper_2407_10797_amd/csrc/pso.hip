@@ -212,7 +212,7 @@ extern "C" int pso_stage(fstat_plan_t P, const pso_stage_desc* d, pso_result* re
   if ((rc = hip_check(hipMemcpyAsync(box, d->box, sizeof(double) * R * 12, hipMemcpyHostToDevice, s), "copy box")) ||
       (rc = hip_check(hipMemcpyAsync(np_run, d->np, sizeof(int32_t) * R, hipMemcpyHostToDevice, s), "copy np")))
     return rc;
-  if ((rc = ensure_workspace(P, n, stride))) return rc;
+  if ((rc = ensure_workspace(P, n, stride, chunk_for(P, mixed)))) return rc;
   if (sur && (rc = sur_ensure(P, n, stride))) return rc;   // no allocation inside the capture
   (void)eval_blocks(P, mixed);   // occupancy query outside any capture
   PsoArgs a{R, Pn, I, d->ring_k, d->w_start, d->w_end, d->c1, d->c2, d->vmax, d->seed};

@@ -25,9 +25,10 @@ FSTAT_DEVICE_PTRS = 1
 FSTAT_EVAL_MIXED = 2
 FSTAT_PROFILE = 4
 FSTAT_EVAL_SURROGATE = 8
+FSTAT_AUTOTUNE_FORCE = 16
 
 EXPORTS = ("fstat_plan_create", "fstat_eval", "fstat_waveform", "pso_stage",
-           "fstat_profile_read", "fstat_mlp_grad", "fstat_surrogate_train",
+           "fstat_profile_read", "fstat_autotune", "fstat_mlp_grad", "fstat_surrogate_train",
            "fstat_surrogate_stats", "fstat_plan_destroy", "fstat_last_error")
 
 
@@ -97,6 +98,9 @@ def lib() -> ctypes.CDLL:
         L.fstat_surrogate_train.restype = ctypes.c_int
         L.fstat_surrogate_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.fstat_surrogate_stats.restype = ctypes.c_int
+        L.fstat_autotune.argtypes = [vp, vp, i64, i32, u32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                     ctypes.POINTER(ctypes.c_double), vp]
+        L.fstat_autotune.restype = ctypes.c_int
         L.fstat_plan_destroy.argtypes = [vp]
         L.fstat_plan_destroy.restype = None
         L.fstat_last_error.argtypes = []
@@ -166,6 +170,13 @@ def fstat_surrogate_stats(plan):
     used, fb = ctypes.c_int64(), ctypes.c_int64()
     _check(lib().fstat_surrogate_stats(plan, ctypes.byref(used), ctypes.byref(fb)))
     return used.value, fb.value
+
+
+def fstat_autotune(plan, params, n, np_uniform, flags, stream=None):
+    c, m, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(lib().fstat_autotune(plan, params, int(n), int(np_uniform), int(flags), ctypes.byref(c),
+                                ctypes.byref(m), ctypes.byref(ms), stream))
+    return c.value, m.value, ms.value
 
 
 def fstat_plan_destroy(plan) -> None:
@@ -270,6 +281,15 @@ class Plan:
         if trace is not None:
             out["loss_trace"] = trace
         return out
+
+    def autotune(self, params, np_parts: int, mixed: bool = False, force: bool = False):
+        """Pick the work-item size and grid multiplier for this precision; returns
+        (chunk, grid multiplier, best ms or -1 if cached)."""
+        torch = _torch()
+        prm = torch.as_tensor(params).to("cuda", torch.float64).contiguous()
+        flags = (FSTAT_DEVICE_PTRS | (FSTAT_EVAL_MIXED if mixed else 0)
+                 | (FSTAT_AUTOTUNE_FORCE if force else 0))
+        return fstat_autotune(self.handle, prm.data_ptr(), prm.shape[0], int(np_parts), flags, _stream())
 
     def surrogate_stats(self):
         """(particles that used the surrogate, particles that fell back) in the last

@@ -148,8 +148,8 @@ def small_box(inj: np.ndarray) -> np.ndarray:
                      [0.0, math.pi], [0.0, 2.0 * math.pi], [0.0, 0.1]])
 
 
-# Paper-scale workload (t_c range and sky from Table I; Mc and e0 ranges of
-# the spec configuration).
+# Paper-scale workload: t_c range and sky from Table I, Mc in [10, 50] Msun,
+# e0 in [0, 0.1], 2.5 yr of data at 1/T resolution over 10-100 mHz.
 PAPER_BOX = np.array([[3.3 * YEAR_S, 3.8 * YEAR_S], [10.0, 50.0], [0.0, 0.9],
                       [0.0, math.pi], [0.0, 2.0 * math.pi], [0.0, 0.1]])
 PAPER_SEEDS = dict(noise=2001, inj=2002, pts=2003)
