@@ -23,12 +23,30 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector peak (256 CUs x 2.4 GHz x 128 FLOP/clk)
-PEAK_FP32_TFLOPS = 157.3
-# FP64 floating-point operations per bin-template of the bin-loop kernel
-# (FMA = 2), from rocprofv3 FP64 VALU instruction counters divided by the
-# bin-template evaluations of the same launch.
-FLOP_PER_BIN = {"fp64": None, "mixed": None}
+# MI355X vector ALU: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-instructions/s;
+# with FMA = 2 FLOP that is 78.6 TFLOP/s for FP64 and for unpacked FP32 (the
+# library is built without packed FP32, so 157.3 is out of its reach).
+PEAK_VALU_TFLOPS = 78.6
+PEAK_LANE_INSTR = 256 * 64 * 2.4e9
+# Per bin-template figures of the bin-loop kernels (profiles/k_eval_paper_4096x64_counters.md):
+# floating-point operations (FP64 + FP32, FMA = 2), VALU instructions, HBM bytes read
+# per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes written per launch.
+FLOP_PER_BIN = {"fp64": 765.7, "mixed": 625.4}
+VALU_PER_BIN = {"fp64": 805.3, "mixed": 615.7}
+TRAFFIC = {"fp64": (38.65, 1.2045e8), "mixed": (18.66, 1.2092e8)}
+# sha256 of the kernel sources those counters were taken on; traffic is reported
+# as null once the sources differ.
+COUNTERS_SRC_SHA = "f08c95a4790a6e58f837f21b53d84902132ea977f218be72f582b9c4300e300b"
+KERNEL_SOURCES = ("fstat_kernels.hip", "fstat_internal.h", "fstat_kernels.h")
+
+
+def _kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2407_10797_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def _log(msg):
@@ -134,6 +152,7 @@ def main():
     ap.add_argument("--only", choices=["fp64", "mixed", "mixed+surrogate"], default=None)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-steps", type=int, default=3000)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default work-item shape")
     ap.add_argument("--pso-iters", type=int, default=2000, help="0 skips the PSO measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (for scaling "
@@ -161,6 +180,7 @@ def main():
     prm = torch.from_numpy(pts).cuda()
     torch.cuda.synchronize()
     variants = {}
+    same_src = _kernel_sha() == COUNTERS_SRC_SHA
     for name, mixed, sur in (("fp64", False, False), ("mixed", True, False),
                              ("mixed+surrogate", True, True)):
         if (mixed and args.no_mixed) or (args.only and args.only != name) or (sur and args.no_surrogate):
@@ -171,23 +191,33 @@ def main():
                 t0 = time.perf_counter()
                 rep = plan.train_surrogate(steps=args.surrogate_steps)
                 extra = dict(train_s=time.perf_counter() - t0, val_rmse=rep["val_rmse"])
+            if not args.no_autotune and not sur:
+                c, m, ms = plan.autotune(prm, args.np, mixed=mixed)
+                extra.update(tuned_chunk=c, tuned_grid_mult=m)
+                _log(f"{name}: autotuned work item {c} bins, grid x{m}")
             r = time_path(plan, prm, args.np, args.steps, args.warmup, mixed, sur)
+            items, exact_items = plan.interp_stats()
+            extra.update(work_items=items, exact_items=exact_items)
             if sur:
                 extra["used"], extra["fallback"] = plan.surrogate_stats()
         except fstat.FstatError as e:
             _log(f"{name}: {e}")
             continue
         tps = args.particles * args.steps / r["seconds"]
-        fpb = FLOP_PER_BIN.get(name)
-        peak = PEAK_FP64_TFLOPS
-        achieved = (fpb * r["bins_per_launch"] / (r["kernel_ms"] * 1e-3) / 1e12) if fpb else None
+        kind = "mixed" if mixed else "fp64"
+        secs = r["kernel_ms"] * 1e-3
+        achieved = FLOP_PER_BIN[kind] * r["bins_per_launch"] / secs / 1e12
+        rd, wr = TRAFFIC[kind]
+        traffic = rd * r["bins_per_launch"] + wr if same_src else None
         variants[name] = dict(templates_per_s=tps, ms_per_step=1e3 * r["seconds"] / args.steps,
                               kernel_ms=r["kernel_ms"], bins_per_launch=r["bins_per_launch"],
-                              bin_templates_per_s=r["bins_per_launch"] / (r["kernel_ms"] * 1e-3),
-                              roofline=dict(bound="alu", achieved=achieved, peak=peak,
-                                            unit="TFLOP/s",
-                                            frac=(achieved / peak) if achieved else None,
-                                            traffic=None), **extra)
+                              bin_templates_per_s=r["bins_per_launch"] / secs,
+                              valu_issue_frac=VALU_PER_BIN[kind] * r["bins_per_launch"] / secs
+                              / PEAK_LANE_INSTR if same_src else None,
+                              hbm_GBps=traffic / secs / 1e9 if traffic else None,
+                              roofline=dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TFLOPS,
+                                            unit="TFLOP/s", frac=achieved / PEAK_VALU_TFLOPS,
+                                            traffic=traffic), **extra)
         _log(f"{name}: {tps:.1f} templates/s, kernel {r['kernel_ms']:.2f} ms/launch, "
              f"{r['bins_per_launch']:.3e} bin-templates/launch")
     head = variants.get("fp64") or next(iter(variants.values()))

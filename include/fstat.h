@@ -62,6 +62,10 @@ extern "C" {
 #define FSTAT_EVAL_SURROGATE 8u /* fstat_eval / pso_stage: learned eccentric
                                    phase for particles with Np >= 16        */
 #define FSTAT_AUTOTUNE_FORCE 16u /* fstat_autotune: ignore the cache         */
+#define FSTAT_EVAL_EXACT 32u  /* fstat_eval / pso_stage / fstat_autotune: the
+                                 exact template at every bin instead of the
+                                 per-work-item interpolation of its smooth
+                                 factors (same result to ~1e-12)             */
 
 typedef struct fstat_plan_s *fstat_plan_t;
 
@@ -173,6 +177,16 @@ int pso_stage(fstat_plan_t plan, const pso_stage_desc *desc, pso_result *result,
 int fstat_profile_read(fstat_plan_t plan, int reset, double *kernel_ms, int64_t *launches,
                        int64_t *bin_templates);
 
+/* Work items of the plan's last evaluation, and how many of them were
+ * evaluated by the exact per-bin loop: items the interpolating loop handed
+ * over (fewer than 32 bins, or interpolants that missed an end point) plus,
+ * on the FP64 path, the interpolated items of partitions whose matrix has
+ * cond > 1e3 (evaluated again exactly); exact_items == items after an
+ * FSTAT_EVAL_EXACT evaluation.  Waits for hip_stream.  EINVAL before the
+ * first evaluation.                                                        */
+int fstat_interp_stats(fstat_plan_t plan, int64_t *items, int64_t *exact_items,
+                       void *hip_stream);
+
 /* ---- learned surrogate for the eccentric phase (App. A) ------------------- */
 /* One forward and backward pass of the surrogate network on the device, for
  * checking its training kernels: 3 -> 256 -> 256 -> 256 -> 256 -> 1 with SiLU,
@@ -183,6 +197,12 @@ int fstat_profile_read(fstat_plan_t plan, int reset, double *kernel_ms, int64_t 
  * EINVAL on bad sizes.  Allocates and frees its own device buffers.        */
 int fstat_mlp_grad(const float *params, const float *x, const float *t, int32_t B, double *loss,
                    float *grad, float *y);
+
+/* Inference-only forward of the same network (the fused kernel that evaluates
+ * the surrogate's knots): y[r] for R rows of x [R][3] (host pointers), any
+ * R in 1..2^31.  Same operand rounding as the training forward.  EINVAL on
+ * bad arguments.  Allocates and frees its own device buffers.             */
+int fstat_mlp_forward(const float *params, const float *x, int64_t R, float *y);
 
 /* Train the plan's surrogate for the eccentric phase correction Psi_e
  * (App. A) on the device: n_samples (f, Mc, e0) points uniform over

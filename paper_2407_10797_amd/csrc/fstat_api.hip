@@ -73,6 +73,19 @@ int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride, int chunk) {
   if ((rc = ensure(&P->ws.total, &P->cap.total, 1, "alloc total"))) return rc;
   if ((rc = ensure(&P->ws.items, &P->cap.items, cap_items, "alloc items"))) return rc;
   if ((rc = ensure(&P->ws.partials, &P->cap.partials, cap_items * 8, "alloc partials"))) return rc;
+  if ((rc = ensure(&P->ws.direct, &P->cap.direct, cap_items, "alloc direct"))) return rc;
+  if ((rc = ensure(&P->ws.ndirect, &P->cap.ndirect, 1, "alloc ndirect"))) return rc;
+  const size_t ntiles = (size_t)((P->grid.nbins + chunk - 1) / chunk);
+  if ((rc = ensure(&P->ws.tcnt, &P->cap.tcnt, ntiles, "alloc tcnt"))) return rc;
+  if ((rc = ensure(&P->ws.tcur, &P->cap.tcur, ntiles, "alloc tcur"))) return rc;
+  if ((rc = ensure(&P->ws.toff, &P->cap.toff, ntiles + 1, "alloc toff"))) return rc;
+  if ((rc = ensure(&P->ws.tile_items, &P->cap.tile_items, cap_items, "alloc tile items"))) return rc;
+  if ((rc = ensure(&P->ws.tile_ctr, &P->cap.tile_ctr, 1, "alloc tile counter"))) return rc;
+  if ((rc = ensure(&P->ws.xflag, &P->cap.xflag, cap_items, "alloc item flags"))) return rc;
+  if ((rc = ensure(&P->ws.rec, &P->cap.rec, cap_items * kInterpRec, "alloc interpolation records")))
+    return rc;
+  if ((rc = ensure(&P->ws.refine, &P->cap.refine, cap_items, "alloc refine list"))) return rc;
+  if ((rc = ensure(&P->ws.nrefine, &P->cap.nrefine, 1, "alloc refine count"))) return rc;
   return FSTAT_OK;
 }
 
@@ -92,8 +105,11 @@ int eval_blocks(fstat_plan_s* P, bool mixed) {
 int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t* np,
                 int32_t np_uniform, int32_t stride, double* F_hat, double* F_part,
                 int64_t part_stride, bool mixed, hipStream_t s, const uint8_t* skip,
-                bool allow_profile, bool surrogate) {
+                bool allow_profile, bool surrogate, bool exact) {
   const int chunk = chunk_for(P, mixed);
+  if (!exact && chunk > interp_max_tile(mixed))
+    return set_error(FSTAT_EINVAL, "work-item size %d exceeds the LDS tile limit %d (use a smaller "
+                     "chunk or FSTAT_EVAL_EXACT)", chunk, interp_max_tile(mixed));
   int rc = ensure_workspace(P, n, stride, chunk);
   if (rc) return rc;
   if (surrogate && (rc = sur_ensure(P, n, stride))) return rc;
@@ -107,7 +123,7 @@ int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t*
       return rc;
     (void)hipEventRecord(e0, s);
   }
-  launch_eval(mixed, P->grid, stride, chunk, P->ws, P->b64, P->b32,
+  launch_eval(mixed, !exact, P->grid, n, stride, chunk, P->ws, P->b64, P->b32,
               surrogate ? P->sur_ek : nullptr, eval_blocks(P, mixed), s);
   if (prof) {
     (void)hipEventRecord(e1, s);
@@ -188,10 +204,11 @@ int fstat_autotune(fstat_plan_t P, const double* params, int64_t n, int32_t np_u
     return set_error(FSTAT_EINVAL, "fstat_autotune: bad arguments");
   if (!(flags & FSTAT_DEVICE_PTRS)) return set_error(FSTAT_EINVAL, "fstat_autotune needs device pointers");
   const bool mixed = (flags & FSTAT_EVAL_MIXED) != 0;
+  const bool exact = (flags & FSTAT_EVAL_EXACT) != 0;
   if (mixed ? !(P->prec & FSTAT_MIXED) : !(P->prec & FSTAT_FP64))
     return set_error(FSTAT_EINVAL, "precision not built into the plan");
   hipStream_t s = (hipStream_t)hip_stream;
-  const std::string key = tune_key(P, np_uniform, mixed);
+  const std::string key = tune_key(P, np_uniform, mixed) + (exact ? " exact" : "");
   int c = 0, m = 0;
   double ms_best = -1.0;
   if (!(flags & FSTAT_AUTOTUNE_FORCE) && tune_cache_get(key, &c, &m) && c >= 64 && m >= 1) {
@@ -208,13 +225,14 @@ int fstat_autotune(fstat_plan_t P, const double* params, int64_t n, int32_t np_u
     const int save_m = mixed ? P->grid_mult_mixed : P->grid_mult_fp64;
     for (int ci = 0; ci < 6 && !rc; ++ci)
       for (int mi = 0; mi < 3 && !rc; ++mi) {
+        if (!exact && chunks[ci] > interp_max_tile(mixed)) continue;
         if (mixed) { P->chunk_mixed = chunks[ci]; P->grid_mult_mixed = mults[mi]; }
         else { P->chunk = chunks[ci]; P->grid_mult_fp64 = mults[mi]; }
         double t_min = 1e300;
         for (int rep = 0; rep < 3 && !rc; ++rep) {
           rc = hip_check(hipEventRecord(e0, s), "record");
           if (!rc) rc = eval_device(P, params, n, nullptr, np_uniform, np_uniform, F, nullptr, 0,
-                                    mixed, s, nullptr, false, false);
+                                    mixed, s, nullptr, false, false, exact);
           if (!rc) rc = hip_check(hipEventRecord(e1, s), "record");
           if (!rc) rc = hip_check(hipEventSynchronize(e1), "sync");
           float ms = 0.f;
@@ -276,6 +294,8 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
   int rc = hip_check(hipGetDevice(&P->device), "hipGetDevice");
   if (!rc) rc = hip_check(hipDeviceGetAttribute(&P->num_cu, hipDeviceAttributeMultiprocessorCount,
                                                 P->device), "device attribute");
+  if (!rc && interp_tables_init() != 0)
+    rc = set_error(FSTAT_EDEVICE, "could not upload the interpolation tables");
   double *dd = nullptr, *dp = nullptr, *umax = nullptr;
   if (!rc) rc = dev_alloc(&P->b64.wr, nb, "alloc wr");
   if (!rc) rc = dev_alloc(&P->b64.wi, nb, "alloc wi");
@@ -338,12 +358,34 @@ void fstat_plan_destroy(fstat_plan_t P) {
   dev_free(P->b32.s0); dev_free(P->b32.c0);
   dev_free(P->ws.pc); dev_free(P->ws.bounds); dev_free(P->ws.cnt); dev_free(P->ws.off);
   dev_free(P->ws.total); dev_free(P->ws.items); dev_free(P->ws.partials); dev_free(P->ws.Fl);
+  dev_free(P->ws.direct); dev_free(P->ws.ndirect);
+  dev_free(P->ws.tcnt); dev_free(P->ws.tcur); dev_free(P->ws.toff); dev_free(P->ws.tile_items);
+  dev_free(P->ws.tile_ctr); dev_free(P->ws.xflag); dev_free(P->ws.rec); dev_free(P->ws.refine); dev_free(P->ws.nrefine);
   dev_free(P->io.params); dev_free(P->io.np); dev_free(P->io.F_hat); dev_free(P->io.F_part);
   pso_release(P);
   sur_release(P);
   for (auto& e : P->events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   dev_free(P->bin_counter);
   delete P;
+}
+
+int fstat_interp_stats(fstat_plan_t P, int64_t* items, int64_t* exact_items, void* hip_stream) {
+  g_err.clear();
+  if (!P || !P->ws.total || !P->ws.ndirect || !P->ws.nrefine)
+    return set_error(FSTAT_EINVAL, "no evaluation yet");
+  hipStream_t s = (hipStream_t)hip_stream;
+  int32_t v[3] = {0, 0, 0};
+  int rc = hip_check(hipMemcpyAsync(&v[0], P->ws.total, sizeof(int32_t), hipMemcpyDeviceToHost, s),
+                     "read total");
+  if (!rc) rc = hip_check(hipMemcpyAsync(&v[1], P->ws.ndirect, sizeof(int32_t),
+                                         hipMemcpyDeviceToHost, s), "read ndirect");
+  if (!rc) rc = hip_check(hipMemcpyAsync(&v[2], P->ws.nrefine, sizeof(int32_t),
+                                         hipMemcpyDeviceToHost, s), "read nrefine");
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "interp stats");
+  if (rc) return rc;
+  if (items) *items = v[0];
+  if (exact_items) *exact_items = (int64_t)v[1] + v[2];
+  return FSTAT_OK;
 }
 
 int fstat_profile_read(fstat_plan_t P, int reset, double* kernel_ms, int64_t* launches,
@@ -383,6 +425,7 @@ int fstat_eval(fstat_plan_t P, const double* params, int64_t n, const int32_t* n
   const bool mixed = (flags & FSTAT_EVAL_MIXED) != 0;
   const bool dev = (flags & FSTAT_DEVICE_PTRS) != 0;
   const bool sur = (flags & FSTAT_EVAL_SURROGATE) != 0;
+  const bool exact = (flags & FSTAT_EVAL_EXACT) != 0;
   if (sur && !P->sur_trained) return set_error(FSTAT_EINVAL, "surrogate requested but not trained");
   if (mixed && !(P->prec & FSTAT_MIXED)) return set_error(FSTAT_EINVAL, "plan has no mixed data");
   if (!mixed && !(P->prec & FSTAT_FP64)) return set_error(FSTAT_EINVAL, "plan has no FP64 data");
@@ -399,7 +442,7 @@ int fstat_eval(fstat_plan_t P, const double* params, int64_t n, const int32_t* n
   hipStream_t s = (hipStream_t)hip_stream;
   if (dev)
     return eval_device(P, params, n, np, np_uniform, stride, F_hat, F_part, part_stride, mixed, s,
-                       nullptr, true, sur);
+                       nullptr, true, sur, exact);
   // host pointers: validate, stage, run, copy back
   for (int64_t i = 0; i < n; ++i) {
     const double* t = params + 6 * i;
@@ -423,7 +466,7 @@ int fstat_eval(fstat_plan_t P, const double* params, int64_t n, const int32_t* n
   if (F_part && (rc = hip_check(hipMemcpyAsync(P->io.F_part, F_part, sizeof(double) * n * ps,
                                                hipMemcpyHostToDevice, s), "copy F_part"))) return rc;
   rc = eval_device(P, P->io.params, n, np ? P->io.np : nullptr, np_uniform, stride, P->io.F_hat,
-                   F_part ? P->io.F_part : nullptr, ps, mixed, s, nullptr, true, sur);
+                   F_part ? P->io.F_part : nullptr, ps, mixed, s, nullptr, true, sur, exact);
   if (rc) return rc;
   if ((rc = hip_check(hipMemcpyAsync(F_hat, P->io.F_hat, sizeof(double) * n,
                                      hipMemcpyDeviceToHost, s), "copy F_hat"))) return rc;

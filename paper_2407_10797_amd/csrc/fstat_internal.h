@@ -189,6 +189,46 @@ __host__ __device__ __forceinline__ void phase_and_tf(const PartConst& P, double
   tf = P.tc + D * (P.mc_hi * y3.hi);
 }
 
+// The same phase unreduced (whole cycles kept, double-double) and t_f: the
+// interpolating bin loop takes phase differences across a work item from it.
+__host__ __device__ __forceinline__ dd phase_full(const PartConst& P, double f, double& tf,
+                                                  const double* ek = nullptr) {
+  FSTAT_NO_CONTRACT
+  dd ft = two_prod(f, P.tc);
+  dd x = dd_mul_d(dd{P.mc_hi, P.mc_lo}, f);
+  double lx = log(x.hi);
+  double y0 = exp(lx * (-1.0 / 3.0));
+  dd b = dd_mul(dd_mul_d(two_prod(y0, y0), y0), x);
+  double r = (1.0 - b.hi) - b.lo;
+  dd y = quick_two_sum(y0, y0 * r * (1.0 / 3.0));
+  dd y2 = dd_mul(y, y);
+  dd y3 = dd_mul(y2, y);
+  dd y5 = dd_mul(y3, y2);
+  double xy2 = x.hi * y2.hi;
+  dd tN = dd_mul(dd{P.cN_hi, P.cN_lo}, y5);
+  dd t1 = dd_mul(dd{P.c1_hi, P.c1_lo}, y3);
+  dd t15 = dd_mul(dd{P.c15_hi, P.c15_lo}, y2);
+  dd te;
+  if (ek) {
+    te = dd{knot_interp(ek, f), 0.0};
+  } else {
+    double w0 = exp(lx * (-1.0 / 9.0));
+    dd w3 = dd_mul_d(two_prod(w0, w0), w0);
+    double rw = ((y.hi - w3.hi) + (y.lo - w3.lo)) * xy2;
+    dd w = quick_two_sum(w0, w0 * rw * (1.0 / 3.0));
+    te = dd_mul(dd_mul(dd{P.ce_hi, P.ce_lo}, dd_mul(dd_mul(y5, y5), y)), w);
+  }
+  double lnv = P.ln_vfac + lx * (1.0 / 3.0);
+  double t2 = P.c2 * y.hi;
+  double t6 = P.c6 * xy2;
+  double small = t2 + P.c5 * lnv + t6 * (P.a6k + P.b6 * lnv);
+  dd ph = dd_add(dd_add(dd_add(ft, tN), dd_add(t1, t15)), dd_add(te, dd{small, 0.0}));
+  double D = (-5.0 / 3.0) * tN.hi - t1.hi - (2.0 / 3.0) * t15.hi - (1.0 / 3.0) * t2 + P.c5v5 +
+             t6 * (P.a6k + P.b6 + P.b6 * lnv) * (1.0 / 3.0) - (34.0 / 9.0) * te.hi;
+  tf = P.tc + D * (P.mc_hi * y3.hi);
+  return ph;
+}
+
 // Per-particle phase coefficients (see PartConst), double-double where the
 // term they multiply reaches 10^2..10^7 cycles.
 __host__ __device__ inline void fill_constants(PartConst& P, const double* th) {
@@ -276,6 +316,39 @@ __host__ __device__ __forceinline__ double sinc_from(double num, double den) {
   return (fabs(den) < 1e-6) ? 1.0 - den * den * (1.0 / 6.0) : num / den;
 }
 
+// sin(2 pi r) and cos(2 pi r) for |r| <= 1/2 turn: quarter-turn reduction
+// x = r - n/4 (exact), |2 pi x| <= pi/4, then the Taylor series of sin to
+// theta^15 and of cos to theta^16 (remainders below 1e-16), and the quarter
+// turns n applied by swapping and negating.
+__device__ __forceinline__ void sincos_turns(double r, double& s, double& c) {
+  const double n = rint(4.0 * r);
+  const double x = fma(-0.25, n, r);
+  const double th = x * 6.283185307179586477;
+  const double z = th * th;
+  double ps = -1.0 / 1307674368000.0;                // -1/15!
+  ps = fma(ps, z, 1.0 / 6227020800.0);               //  1/13!
+  ps = fma(ps, z, -1.0 / 39916800.0);                // -1/11!
+  ps = fma(ps, z, 1.0 / 362880.0);                   //  1/9!
+  ps = fma(ps, z, -1.0 / 5040.0);                    // -1/7!
+  ps = fma(ps, z, 1.0 / 120.0);                      //  1/5!
+  ps = fma(ps, z, -1.0 / 6.0);                       // -1/3!
+  const double sn = fma(th * z, ps, th);
+  double pc = 1.0 / 20922789888000.0;                //  1/16!
+  pc = fma(pc, z, -1.0 / 87178291200.0);             // -1/14!
+  pc = fma(pc, z, 1.0 / 479001600.0);                //  1/12!
+  pc = fma(pc, z, -1.0 / 3628800.0);                 // -1/10!
+  pc = fma(pc, z, 1.0 / 40320.0);                    //  1/8!
+  pc = fma(pc, z, -1.0 / 720.0);                     // -1/6!
+  pc = fma(pc, z, 1.0 / 24.0);                       //  1/4!
+  pc = fma(pc, z, -0.5);                             // -1/2!
+  const double cs = fma(z, pc, 1.0);
+  const int q = ((int)n) & 3;
+  const double a = (q & 1) ? cs : sn;
+  const double b = (q & 1) ? sn : cs;
+  s = (q & 2) ? -a : a;                               // q = 1: ( c, -s); 2: (-s, -c); 3: (-c, s)
+  c = ((q + 1) & 2) ? -b : b;
+}
+
 // hardware reciprocal / reciprocal square root seeds refined by two Newton
 // steps (accurate to about one ulp)
 __device__ __forceinline__ double rcp_nr(double x) {
@@ -310,21 +383,12 @@ __device__ __forceinline__ void orbit_offsets(T ca, T sa, T d[3][3]) {
   }
 }
 
-__device__ __forceinline__ void template_fp64(const PartConst& P, double f, double s0, double c0,
-                                              double& cph, double& sph, double& tpr,
-                                              double& tpi, double& txr, double& txi,
-                                              const double* ek = nullptr) {
-  double fr, tf;
-  phase_and_tf(P, f, fr, tf, ek);
-  double sa, ca;
-  sincospi(2.0 * tf * (1.0 / kYear), &sa, &ca);
-  double d[3][3];
-  orbit_offsets<double>(ca, sa, d);
+// TDI-X transfer (T''_+, T''_x) at f for the orbit angle (ca, sa) = (cos,
+// sin)(2 pi t_f / yr) and spacecraft offsets d; s0, c0 = sin, cos(pi f L).
+__device__ __forceinline__ void response_fp64(const PartConst& P, double f, double s0, double c0,
+                                              const double d[3][3], double& tpr, double& tpi,
+                                              double& txr, double& txi) {
   const double kx = P.k[0], ky = P.k[1], kz = P.k[2];
-  double kp1 = kRs * (kx * ca + ky * sa) + (kx * d[0][0] + ky * d[0][1] + kz * d[0][2]);
-  double ph = fr + f * kp1;               // Phi / (2 pi) in cycles
-  ph -= rint(ph);
-  sincospi(2.0 * ph, &sph, &cph);
   const double x0 = kPi * kLs * f;
   const double zr = c0 * c0 - s0 * s0, zi = -2.0 * s0 * c0;   // z = e^{-2 i x0}
   double out[2][4];
@@ -359,6 +423,46 @@ __device__ __forceinline__ void template_fp64(const PartConst& P, double f, doub
   tpi = out[1][2] * out[1][1] - out[0][2] * out[0][1];
   txr = out[1][3] * out[1][0] - out[0][3] * out[0][0];
   txi = out[1][3] * out[1][1] - out[0][3] * out[0][1];
+}
+
+// k . p_1 [s] of spacecraft 1 at orbit angle (ca, sa); fills the offsets d
+__device__ __forceinline__ double k_dot_p1(const PartConst& P, double ca, double sa, double d[3][3]) {
+  orbit_offsets<double>(ca, sa, d);
+  const double kx = P.k[0], ky = P.k[1], kz = P.k[2];
+  return kRs * (kx * ca + ky * sa) + (kx * d[0][0] + ky * d[0][1] + kz * d[0][2]);
+}
+
+__device__ __forceinline__ void template_fp64(const PartConst& P, double f, double s0, double c0,
+                                              double& cph, double& sph, double& tpr,
+                                              double& tpi, double& txr, double& txi,
+                                              const double* ek = nullptr) {
+  double fr, tf;
+  phase_and_tf(P, f, fr, tf, ek);
+  double sa, ca;
+  sincospi(2.0 * tf * (1.0 / kYear), &sa, &ca);
+  double d[3][3];
+  double kp1 = k_dot_p1(P, ca, sa, d);
+  double ph = fr + f * kp1;               // Phi / (2 pi) in cycles
+  ph -= rint(ph);
+  sincospi(2.0 * ph, &sph, &cph);
+  response_fp64(P, f, s0, c0, d, tpr, tpi, txr, txi);
+}
+
+// The template at an arbitrary frequency (an interpolation node): the whole
+// phase Phi / (2 pi) = Psi / (2 pi) + f k.p_1 in cycles (double-double, not
+// reduced) and the transfer without the Doppler factor.
+__device__ __forceinline__ dd template_node(const PartConst& P, double f, const double* ek,
+                                            double& tpr, double& tpi, double& txr, double& txi) {
+  double tf;
+  dd ph = phase_full(P, f, tf, ek);
+  double sa, ca;
+  sincospi(2.0 * tf * (1.0 / kYear), &sa, &ca);
+  double d[3][3];
+  double kp1 = k_dot_p1(P, ca, sa, d);
+  double s0, c0;
+  sincospi(kLs * f, &s0, &c0);
+  response_fp64(P, f, s0, c0, d, tpr, tpi, txr, txi);
+  return dd_add(ph, two_prod(f, kp1));
 }
 
 // ---- per-partition solve (2x2 Hermitian closed form) --------------------------

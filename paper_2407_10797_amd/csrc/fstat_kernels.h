@@ -35,6 +35,17 @@ struct WorkSpace {
   int2* items;        // [capacity]
   double* partials;   // [capacity][8]
   double* Fl;         // [n][stride]
+  int32_t* direct;    // [capacity] items the interpolating kernel hands to the exact kernel
+  int32_t* ndirect;   // [1]
+  int32_t* tcnt;      // [tiles] items per bin tile
+  int32_t* tcur;      // [tiles] scatter cursors
+  int32_t* toff;      // [tiles + 1] first item of each tile in tile_items
+  int32_t* tile_items;  // [capacity] item indices grouped by bin tile
+  int32_t* tile_ctr;  // [1] next tile to take (dynamic schedule)
+  uint8_t* xflag;     // [capacity] 1: item evaluated by the exact kernel
+  double* rec;        // [capacity][52] per-item interpolation records
+  int32_t* refine;    // [capacity] interpolated items of ill-conditioned partitions
+  int32_t* nrefine;   // [1]
 };
 
 void launch_prep(const Grid& g, const double* data, const double* psd, BinData<double> b,
@@ -46,7 +57,11 @@ void launch_setup(const Grid& g, const double* params, int64_t n,
                   const int32_t* np, int32_t np_uniform, int32_t stride, int32_t chunk,
                   const uint8_t* skip, const WorkSpace& ws, hipStream_t s);
 void launch_worklist(int64_t m, const WorkSpace& ws, hipStream_t s);
-void launch_eval(bool mixed, const Grid& g, int32_t stride, int32_t chunk,
+int interp_tables_init();
+int interp_max_tile(bool mixed);   // largest tile (bins) the LDS-staged loop accepts
+constexpr int kInterpRec = 52;     // doubles per interpolation record
+void launch_eval(bool mixed, bool interp, const Grid& g, int64_t n_particles, int32_t stride,
+                 int32_t chunk,
                  const WorkSpace& ws, BinData<double> b, BinData<float> b32, const double* ek,
                  int blocks, hipStream_t s);
 void launch_sur_data(uint64_t seed, int64_t n, float* X, float* T, hipStream_t s);

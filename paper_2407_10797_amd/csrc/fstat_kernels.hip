@@ -15,6 +15,8 @@
 //             the 2x2 Hermitian closed form of F_l
 //   k_mean    one thread per particle: F_hat = mean_l F_l, or -inf / NaN
 #include "fstat_internal.h"
+#include <type_traits>
+
 #include "fstat_kernels.h"
 #include "philox.h"
 
@@ -92,6 +94,15 @@ __global__ void k_scale(Grid g, const double* __restrict__ umax, double* __restr
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double bin_freq(const Grid& g, int64_t j) {
   return (double)(g.k_lo + j) * g.df;
+}
+
+// Work item c of a partition with bins [a, b): its part inside bin tile
+// a / T + c of the global tiling of the band into tiles of T bins.
+__device__ __forceinline__ int item_tile(int a, int c, int T) { return a / T + c; }
+__device__ __forceinline__ void item_bins(int a, int b, int c, int T, int& b0, int& b1) {
+  const int t = a / T + c;
+  b0 = max(a, t * T);
+  b1 = min(b, (t + 1) * T);
 }
 
 // smallest j in [lo, hi+1] with f_j >= e
@@ -186,15 +197,16 @@ __global__ void k_setup(Grid g, const double* __restrict__ params, int64_t n,
     prev = b;
   }
   bp[npi] = jhi + 1;
-  for (int l = 0; l < npi; ++l) {
-    int nb = bp[l + 1] - bp[l];
-    cp[l] = (nb + chunk - 1) / chunk;
+  for (int l = 0; l < npi; ++l) {   // bin tiles of the global tiling the partition meets
+    int a = bp[l], b = bp[l + 1];
+    cp[l] = b > a ? (b - 1) / chunk - a / chunk + 1 : 0;
   }
 }
 
 // exclusive scan of cnt[m] into off[m]; total -> *total (single block)
 __global__ void k_scan(const int32_t* __restrict__ cnt, int64_t m, int32_t* __restrict__ off,
-                       int32_t* __restrict__ total) {
+                       int32_t* __restrict__ total, int32_t* __restrict__ ndirect,
+                       int32_t* __restrict__ nrefine) {
   __shared__ int64_t part[1024];
   int t = threadIdx.x, T = blockDim.x;
   int64_t per = (m + T - 1) / T;
@@ -207,6 +219,8 @@ __global__ void k_scan(const int32_t* __restrict__ cnt, int64_t m, int32_t* __re
     int64_t run = 0;
     for (int i = 0; i < T; ++i) { int64_t v = part[i]; part[i] = run; run += v; }
     total[0] = (int32_t)run;
+    ndirect[0] = 0;
+    nrefine[0] = 0;
   }
   __syncthreads();
   int64_t run = part[t];
@@ -248,20 +262,24 @@ __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
                                                    const double* __restrict__ s0a,
                                                    const double* __restrict__ c0a,
                                                    const double* __restrict__ ek,
-                                                   double* __restrict__ partials) {
+                                                   double* __restrict__ partials,
+                                                   const int32_t* __restrict__ sel,
+                                                   const int32_t* __restrict__ nsel) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
-  const int W = total[0];
-  for (int w = wave; w < W; w += nwaves) {
+  // all items, or only those listed in sel (the interpolating kernel's rejects)
+  const int W = sel ? nsel[0] : total[0];
+  for (int iw = wave; iw < W; iw += nwaves) {
+    const int w = sel ? sel[iw] : iw;
     int2 it = items[w];
     int q = __builtin_amdgcn_readfirstlane(it.x);
     int c = __builtin_amdgcn_readfirstlane(it.y);
     int p = q / stride, l = q - p * stride;
     const PartConst& P = pc[p];
     const int32_t* bp = bounds + (int64_t)p * (stride + 1);
-    int b0 = bp[l] + c * chunk;
-    int b1 = min(bp[l + 1], b0 + chunk);
+    int b0, b1;
+    item_bins(bp[l], bp[l + 1], c, chunk, b0, b1);
     const double* ekq = (ek && P.sur) ? ek + 8 * (int64_t)q : nullptr;
     // Kahan-compensated per-lane sums (true sum ~ acc - cmp): the partition
     // matrix can have cond ~ 1e5..1e8, which amplifies summation error.
@@ -387,20 +405,24 @@ __global__ __launch_bounds__(256) void k_eval_mixed(Grid g,
                                                     const float* __restrict__ s0a,
                                                     const float* __restrict__ c0a,
                                                     const double* __restrict__ ek,
-                                                    double* __restrict__ partials) {
+                                                    double* __restrict__ partials,
+                                                   const int32_t* __restrict__ sel,
+                                                   const int32_t* __restrict__ nsel) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
-  const int W = total[0];
-  for (int w = wave; w < W; w += nwaves) {
+  // all items, or only those listed in sel (the interpolating kernel's rejects)
+  const int W = sel ? nsel[0] : total[0];
+  for (int iw = wave; iw < W; iw += nwaves) {
+    const int w = sel ? sel[iw] : iw;
     int2 it = items[w];
     int q = __builtin_amdgcn_readfirstlane(it.x);
     int c = __builtin_amdgcn_readfirstlane(it.y);
     int p = q / stride, l = q - p * stride;
     const PartConst& P = pc[p];
     const int32_t* bp = bounds + (int64_t)p * (stride + 1);
-    int b0 = bp[l] + c * chunk;
-    int b1 = min(bp[l + 1], b0 + chunk);
+    int b0, b1;
+    item_bins(bp[l], bp[l + 1], c, chunk, b0, b1);
     const double* ekq = (ek && P.sur) ? ek + 8 * (int64_t)q : nullptr;
     // N-terms (Z+, Zx) in FP32 with Kahan; M-terms (P, Q, R) in FP64 from the
     // FP32 response: the partition matrix can be ill-conditioned, and FP32
@@ -436,6 +458,433 @@ __global__ __launch_bounds__(256) void k_eval_mixed(Grid g,
       for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = red[i];
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// the hot loop, interpolating form (default)
+// ---------------------------------------------------------------------------
+// Within one work item (at most `chunk` consecutive bins of one partition)
+// every factor of the template except the fast phase is smooth in f, and the
+// phase is smooth once a linear term is taken out.  Per item, with m = j - b0
+// and s = 2 m / (nb - 1) - 1 in [-1, 1]:
+//   Phi(m) / (2 pi) = Phi_0 + B m + R(s),   R(-1) = R(+1) = 0 up to rounding,
+// where Phi_0 is the whole phase (cycles, double-double) at the first bin and
+// B the secant slope to the last bin; R and the four real components of the
+// transfer (T''_+, T''_x) are replaced by their degree-9 interpolants through
+// the 10 Chebyshev points of the first kind, written as monomials in s.  The
+// node values and the two end-point values are evaluated exactly
+// (template_node); an item whose interpolants miss either end point by more
+// than 1e-12 cycles (phase; the exact phase itself carries ~1e-13) or 2e-13 of
+// the largest transfer component, or that has fewer than kMinInterp bins,
+// goes to the exact per-bin kernels (sel list).
+// An error e in the template moves F by up to cond(M) e, so partitions whose
+// matrix has cond > kRefineCond are evaluated again exactly (k_mark).
+// Node evaluation packs 5 items x 12 points onto one wavefront's lanes.
+constexpr int kCheb = 10;
+constexpr int kLanesItem = kCheb + 2;
+constexpr int kItemsWave = 5;
+constexpr int kMinInterp = 32;
+constexpr double kInterpTolPhase = 1e-12;
+constexpr double kInterpTolT = 2e-13;
+constexpr double kRefineCond = 1e3;
+
+__constant__ double c_cheb_s[kCheb];          // nodes cos(pi (k + 1/2) / 10)
+__constant__ double c_cheb_G[kCheb][kCheb];   // node value k -> coefficient of s^n
+__constant__ double c_cheb_E[2][kCheb];       // node value k -> interpolant at s = -1, +1
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  int2 v = *reinterpret_cast<int2*>(&x);
+  v.x = __builtin_amdgcn_readlane(v.x, l);
+  v.y = __builtin_amdgcn_readlane(v.y, l);
+  return *reinterpret_cast<double*>(&v);
+}
+
+template <typename T>
+__device__ __forceinline__ T horner(const T* c, T s) {
+  T r = c[kCheb - 1];
+#pragma unroll
+  for (int n = kCheb - 2; n >= 0; --n) r = r * s + c[n];
+  return r;
+}
+
+// Per-item interpolation record: monomial coefficients of R, Re T''_+,
+// Im T''_+, Re T''_x, Im T''_x (kCheb each), then A = frac(Phi_0), B' = B - rint(B).
+constexpr int kRec = 5 * kCheb + 2;
+static_assert(kRec == kInterpRec && kRec <= 64, "record layout");
+
+// Node values, coefficients and end-point check of every work item (all
+// lanes active: lanes 60..63 repeat the last point of the last item).
+__global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
+                                                      const PartConst* __restrict__ pc,
+                                                      const int32_t* __restrict__ bounds,
+                                                      int32_t stride,
+                                                      const int2* __restrict__ items,
+                                                      const int32_t* __restrict__ total,
+                                                      int32_t T,
+                                                      const double* __restrict__ ek,
+                                                      double* __restrict__ rec,
+                                                      uint8_t* __restrict__ xflag,
+                                                      int32_t* __restrict__ direct,
+                                                      int32_t* __restrict__ ndirect) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const int W = total[0];
+  const int G = (W + kItemsWave - 1) / kItemsWave;
+  const int q = min(lane / kLanesItem, kItemsWave - 1);
+  const int k = min(lane - q * kLanesItem, kLanesItem - 1);
+  const int base = q * kLanesItem;
+  for (int grp = wave; grp < G; grp += nwaves) {
+    const int w = min(grp * kItemsWave + q, W - 1);
+    const int2 it = items[w];
+    const int p = it.x / stride, l = it.x - p * stride;
+    const PartConst& P = pc[p];
+    const int32_t* bp = bounds + (int64_t)p * (stride + 1);
+    int b0, b1;
+    item_bins(bp[l], bp[l + 1], it.y, T, b0, b1);
+    const int nb = b1 - b0;
+    const double* ekq = (ek && P.sur) ? ek + 8 * (int64_t)it.x : nullptr;
+    const double sk = k < kCheb ? c_cheb_s[k] : (k == kCheb ? -1.0 : 1.0);
+    const double mk = (sk + 1.0) * 0.5 * (double)(nb > 1 ? nb - 1 : 0);
+    const double f = ((double)(g.k_lo + b0) + mk) * g.df;
+    double v[5];
+    const dd ph = template_node(P, f, ekq, v[1], v[2], v[3], v[4]);
+    const double p0h = __shfl(ph.hi, base + kCheb, 64);
+    const double p0l = __shfl(ph.lo, base + kCheb, 64);
+    const double peh = __shfl(ph.hi, base + kCheb + 1, 64);
+    const double pel = __shfl(ph.lo, base + kCheb + 1, 64);
+    const dd span = dd_add(dd{peh, pel}, dd{-p0h, -p0l});
+    const double B = nb > 1 ? (span.hi + span.lo) / (double)(nb - 1) : 0.0;
+    {
+      const dd bm = two_prod(B, mk);
+      const dd r = dd_add(dd_add(ph, dd{-p0h, -p0l}), dd{-bm.hi, -bm.lo});
+      v[0] = r.hi + r.lo;
+    }
+    double coef[5], emin[5], eplu[5], tmax = 0.0;
+#pragma unroll
+    for (int fn = 0; fn < 5; ++fn) { coef[fn] = 0.0; emin[fn] = 0.0; eplu[fn] = 0.0; }
+#pragma unroll
+    for (int kn = 0; kn < kCheb; ++kn) {
+      const double gk = c_cheb_G[kn][k < kCheb ? k : 0];
+      const double em = c_cheb_E[0][kn], ep = c_cheb_E[1][kn];
+#pragma unroll
+      for (int fn = 0; fn < 5; ++fn) {
+        const double vn = __shfl(v[fn], base + kn, 64);
+        coef[fn] = fma(vn, gk, coef[fn]);
+        emin[fn] = fma(vn, em, emin[fn]);
+        eplu[fn] = fma(vn, ep, eplu[fn]);
+        if (fn > 0) tmax = fmax(tmax, fabs(vn));
+      }
+    }
+    bool bad = false;
+    if (k >= kCheb) {
+      const double* e = (k == kCheb) ? emin : eplu;
+      bad = !(fabs(e[0] - v[0]) <= kInterpTolPhase);
+#pragma unroll
+      for (int fn = 1; fn < 5; ++fn) bad = bad || !(fabs(e[fn] - v[fn]) <= kInterpTolT * tmax);
+    }
+    const uint64_t badmask = __ballot(bad);
+    const bool mine = lane - base < kLanesItem && grp * kItemsWave + q < W;   // not a repeat lane
+    if (!mine) continue;
+    const bool rej = nb < kMinInterp || ((badmask >> base) & ((1ull << kLanesItem) - 1ull)) != 0ull;
+    double* r = rec + (int64_t)w * kRec;
+    if (k < kCheb) {
+#pragma unroll
+      for (int fn = 0; fn < 5; ++fn) r[fn * kCheb + k] = coef[fn];
+    } else if (k == kCheb) {
+      FSTAT_NO_CONTRACT
+      r[5 * kCheb] = (p0h - floor(p0h)) + p0l;   // fractional cycle at the first bin
+      r[5 * kCheb + 1] = B - rint(B);            // whole cycles per bin drop out (m is an integer)
+      xflag[w] = rej ? 1 : 0;
+      if (rej) direct[atomicAdd(ndirect, 1)] = w;
+    }
+  }
+}
+
+// The bins of the interpolated items, tile by tile: the tile's w and u are
+// staged once in LDS; each wave takes one item at a time, broadcasts its
+// record into registers and runs the per-bin loop from LDS.
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_eval_interp(Grid g,
+                                                     const int32_t* __restrict__ bounds,
+                                                     int32_t stride,
+                                                     const int2* __restrict__ items,
+                                                     int32_t T,
+                                                     const int32_t* __restrict__ tile_items,
+                                                     const int32_t* __restrict__ tile_off,
+                                                     int32_t ntiles,
+                                                     int32_t* __restrict__ tile_ctr,
+                                                     const double* __restrict__ wr64,
+                                                     const double* __restrict__ wi64,
+                                                     const double* __restrict__ u64,
+                                                     const float* __restrict__ wr32,
+                                                     const float* __restrict__ wi32,
+                                                     const float* __restrict__ u32,
+                                                     const double* __restrict__ rec,
+                                                     const uint8_t* __restrict__ xflag,
+                                                     double* __restrict__ partials) {
+  typedef typename std::conditional<MIXED, float, double>::type DT;
+  extern __shared__ unsigned char smem[];
+  DT* s_wr = reinterpret_cast<DT*>(smem);      // the tile's w and u, [3][T]
+  DT* s_wi = s_wr + T;
+  DT* s_u = s_wi + T;
+  __shared__ int s_tile;
+  const DT* gwr;
+  const DT* gwi;
+  const DT* gu;
+  if constexpr (MIXED) { gwr = wr32; gwi = wi32; gu = u32; }
+  else { gwr = wr64; gwi = wi64; gu = u64; }
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int nwv = blockDim.x >> 6;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1);
+    __syncthreads();
+    const int t = s_tile;
+    if (t >= ntiles) break;
+    const int j0 = t * T;
+    const int nt = min((int64_t)T, g.nbins - j0);
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+      s_wr[i] = gwr[j0 + i];
+      s_wi[i] = gwi[j0 + i];
+      s_u[i] = gu[j0 + i];
+    }
+    __syncthreads();
+    const int i0 = tile_off[t];
+    const int cnt = tile_off[t + 1] - i0;
+    for (int idx = wv; idx < cnt; idx += nwv) {
+      const int w = tile_items[i0 + idx];
+      if (xflag[w]) continue;                      // evaluated by the exact kernel
+      const int2 it = items[w];
+      const int p = it.x / stride, l = it.x - p * stride;
+      const int32_t* bp = bounds + (int64_t)p * (stride + 1);
+      int b0, b1;
+      item_bins(bp[l], bp[l + 1], it.y, T, b0, b1);
+      const int nb = b1 - b0;
+      const double mine = rec[(int64_t)w * kRec + min(lane, kRec - 1)];
+      double cR[kCheb];
+#pragma unroll
+      for (int n = 0; n < kCheb; ++n) cR[n] = __shfl(mine, n, 64);
+      const double A = __shfl(mine, 5 * kCheb, 64);
+      const double Bp = __shfl(mine, 5 * kCheb + 1, 64);
+      const double alpha = 2.0 / (double)(nb - 1);
+      const int e0 = b0 - j0;            // LDS offset of the item's first bin
+      if constexpr (!MIXED) {
+        double cT[4][kCheb];
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+          for (int n = 0; n < kCheb; ++n) cT[fn][n] = __shfl(mine, (fn + 1) * kCheb + n, 64);
+        double acc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = 0.0;
+        for (int mi = lane; mi < nb; mi += 64) {
+          const double m = (double)mi;
+          const double s = fma(alpha, m, -1.0);
+          double ph = fma(Bp, m, horner(cR, s)) + A;
+          ph -= rint(ph);
+          double sps, cps;
+          sincos_turns(ph, sps, cps);
+          const double tpr = horner(cT[0], s), tpi = horner(cT[1], s);
+          const double txr = horner(cT[2], s), txi = horner(cT[3], s);
+          const double a = s_wr[e0 + mi], b = s_wi[e0 + mi], uu = s_u[e0 + mi];
+          const double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
+          acc[0] += Wr * tpr + Wi * tpi;
+          acc[1] += Wi * tpr - Wr * tpi;
+          acc[2] += Wr * txr + Wi * txi;
+          acc[3] += Wi * txr - Wr * txi;
+          acc[4] += uu * (tpr * tpr + tpi * tpi);
+          acc[5] += uu * (txr * txr + txi * txi);
+          acc[6] += uu * (tpr * txr + tpi * txi);
+          acc[7] += uu * (tpi * txr - tpr * txi);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = wave_sum(acc[i]);
+        if (lane == 0) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = acc[i];
+        }
+      } else {
+        float cT[4][kCheb];
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+          for (int n = 0; n < kCheb; ++n) cT[fn][n] = (float)__shfl(mine, (fn + 1) * kCheb + n, 64);
+        float acc[4], cmp[4];
+        double m4[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { acc[i] = cmp[i] = 0.0f; m4[i] = 0.0; }
+        for (int mi = lane; mi < nb; mi += 64) {
+          const double m = (double)mi;
+          const double s = fma(alpha, m, -1.0);
+          const double ph = fma(Bp, m, horner(cR, s)) + A;
+          const float rf = (float)(ph - rint(ph));
+          const float sps = __builtin_amdgcn_sinf(rf), cps = __builtin_amdgcn_cosf(rf);
+          const float sf = (float)s;
+          const float tpr = horner(cT[0], sf), tpi = horner(cT[1], sf);
+          const float txr = horner(cT[2], sf), txi = horner(cT[3], sf);
+          const float a = s_wr[e0 + mi], b = s_wi[e0 + mi];
+          const float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
+          kahan_addf(acc[0], cmp[0], Wr * tpr + Wi * tpi);
+          kahan_addf(acc[1], cmp[1], Wi * tpr - Wr * tpi);
+          kahan_addf(acc[2], cmp[2], Wr * txr + Wi * txi);
+          kahan_addf(acc[3], cmp[3], Wi * txr - Wr * txi);
+          const double uu = (double)s_u[e0 + mi];
+          const double pr = tpr, pi = tpi, xr = txr, xi = txi;
+          m4[0] += uu * (pr * pr + pi * pi);
+          m4[1] += uu * (xr * xr + xi * xi);
+          m4[2] += uu * (pr * xr + pi * xi);
+          m4[3] += uu * (pi * xr - pr * xi);
+        }
+        double red[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[i] = wave_sum((double)acc[i] - (double)cmp[i]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[4 + i] = wave_sum(m4[i]);
+        if (lane == 0) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = red[i];
+        }
+      }
+    }
+    __syncthreads();   // every wave is done with this tile's LDS and s_tile
+  }
+}
+
+// Partitions of interpolated items whose matrix has cond(M) > thr: their
+// interpolated items are listed for exact evaluation (the sums are formed as
+// in k_solve; the eigenvalues of the 2x2 Hermitian form give the condition).
+__global__ void k_mark(const PartConst* __restrict__ pc, int64_t n, int32_t stride,
+                       const int32_t* __restrict__ cnt, const int32_t* __restrict__ off,
+                       const double* __restrict__ partials, const uint8_t* __restrict__ xflag,
+                       double thr, int32_t* __restrict__ refine, int32_t* __restrict__ nrefine) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n * stride) return;
+  int64_t p = q / stride;
+  int l = (int)(q - p * stride);
+  const PartConst& P = pc[p];
+  if (l >= P.np || P.status != kStatusOk) return;
+  const int o = off[q], c = cnt[q];
+  int ninterp = 0;
+  for (int i = 0; i < c; ++i) ninterp += xflag[o + i] == 0;
+  if (ninterp == 0) return;
+  double a[8], e[8];
+  for (int k = 0; k < 8; ++k) a[k] = e[k] = 0.0;
+  for (int i = 0; i < c; ++i)
+    for (int k = 0; k < 8; ++k) {
+      double x = partials[(int64_t)(o + i) * 8 + k];
+      double t = a[k] + x;
+      e[k] += (fabs(a[k]) >= fabs(x)) ? (a[k] - t) + x : (x - t) + a[k];
+      a[k] = t;
+    }
+  for (int k = 0; k < 8; ++k) a[k] += e[k];
+  const double Pm = a[4], Qm = a[5], rr = a[6], ri = a[7];
+  const double hs = 0.5 * (Pm + Qm), hd = 0.5 * (Pm - Qm);
+  const double lp = hs + sqrt(hd * hd + rr * rr + ri * ri);
+  const double lm = (Pm * Qm - (rr * rr + ri * ri)) / lp;
+  if (!(lp > 0.0) || !(lm > lp / thr)) {
+    int at = atomicAdd(nrefine, ninterp);
+    for (int i = 0; i < c; ++i)
+      if (xflag[o + i] == 0) refine[at++] = o + i;
+  }
+}
+
+// ---- grouping of the work items by bin tile ---------------------------------
+__global__ void k_tile_zero(int32_t* __restrict__ tcnt, int32_t* __restrict__ tcur, int32_t ntiles,
+                            int32_t* __restrict__ tile_ctr) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ntiles) { tcnt[i] = 0; tcur[i] = 0; }
+  if (i == 0) tile_ctr[0] = 0;
+}
+
+__global__ void k_tile_count(const int2* __restrict__ items, const int32_t* __restrict__ total,
+                             const int32_t* __restrict__ bounds, int32_t stride, int32_t T,
+                             int32_t* __restrict__ tcnt) {
+  const int W = total[0];
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
+    const int2 it = items[w];
+    const int p = it.x / stride, l = it.x - p * stride;
+    atomicAdd(&tcnt[item_tile(bounds[(int64_t)p * (stride + 1) + l], it.y, T)], 1);
+  }
+}
+
+// exclusive scan of tcnt[n] into off[0..n] (off[n] = total), one block
+__global__ void k_tile_scan(const int32_t* __restrict__ tcnt, int32_t n, int32_t* __restrict__ off) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x, TB = blockDim.x;
+  const int per = (n + TB - 1) / TB;
+  const int a = t * per, b = min(n, a + per);
+  int32_t sum = 0;
+  for (int i = a; i < b; ++i) sum += tcnt[i];
+  part[t] = sum;
+  __syncthreads();
+  if (t == 0) {
+    int32_t run = 0;
+    for (int i = 0; i < TB; ++i) { int32_t x = part[i]; part[i] = run; run += x; }
+    off[n] = run;
+  }
+  __syncthreads();
+  int32_t run = part[t];
+  for (int i = a; i < b; ++i) { off[i] = run; run += tcnt[i]; }
+}
+
+__global__ void k_tile_scatter(const int2* __restrict__ items, const int32_t* __restrict__ total,
+                               const int32_t* __restrict__ bounds, int32_t stride, int32_t T,
+                               const int32_t* __restrict__ off, int32_t* __restrict__ tcur,
+                               int32_t* __restrict__ tile_items) {
+  const int W = total[0];
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
+    const int2 it = items[w];
+    const int p = it.x / stride, l = it.x - p * stride;
+    const int t = item_tile(bounds[(int64_t)p * (stride + 1) + l], it.y, T);
+    tile_items[off[t] + atomicAdd(&tcur[t], 1)] = w;
+  }
+}
+
+// every item is evaluated exactly: the reject count equals the item count
+__global__ void k_copy_count(const int32_t* __restrict__ total, int32_t* __restrict__ ndirect) {
+  if (threadIdx.x == 0) ndirect[0] = total[0];
+}
+
+// Chebyshev tables (long double on the host): node s_k = cos(pi (k + 1/2) / K);
+// interpolant coefficients c_j = (2 / K) sum_k v_k cos(pi j (k + 1/2) / K)
+// (c_0 halved) of p = sum_j c_j T_j(s); T_j expanded in monomials by
+// T_{j+1} = 2 s T_j - T_{j-1}.
+int interp_tables_init() {
+  static bool done[64] = {false};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  if (dev >= 0 && dev < 64 && done[dev]) return 0;
+  const int K = kCheb;
+  const long double pi = 3.141592653589793238462643383279502884L;
+  long double M[kCheb][kCheb] = {};
+  M[0][0] = 1.0L;
+  M[1][1] = 1.0L;
+  for (int j = 1; j + 1 < K; ++j)
+    for (int n = 0; n < K; ++n)
+      M[j + 1][n] = (n > 0 ? 2.0L * M[j][n - 1] : 0.0L) - M[j - 1][n];
+  double S[kCheb], G[kCheb][kCheb], E[2][kCheb];
+  for (int kk = 0; kk < K; ++kk) {
+    S[kk] = (double)cosl(pi * (kk + 0.5L) / K);
+    long double lm = 0.0L, lp = 0.0L;
+    for (int n = 0; n < K; ++n) {
+      long double gsum = 0.0L;
+      for (int j = 0; j < K; ++j) {
+        long double cj = (2.0L / K) * cosl(pi * j * (kk + 0.5L) / K) * (j == 0 ? 0.5L : 1.0L);
+        gsum += cj * M[j][n];
+      }
+      G[kk][n] = (double)gsum;
+      lp += gsum;
+      lm += (n & 1) ? -gsum : gsum;
+    }
+    E[0][kk] = (double)lm;
+    E[1][kk] = (double)lp;
+  }
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_s), S, sizeof(S)) != hipSuccess) return -1;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_G), G, sizeof(G)) != hipSuccess) return -1;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_E), E, sizeof(E)) != hipSuccess) return -1;
+  if (dev >= 0 && dev < 64) done[dev] = true;
+  return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -696,20 +1145,59 @@ void launch_setup(const Grid& g, const double* params, int64_t n,
 }
 
 void launch_worklist(int64_t m, const WorkSpace& ws, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ws.cnt, m, ws.off, ws.total);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ws.cnt, m, ws.off, ws.total, ws.ndirect, ws.nrefine);
   hipLaunchKernelGGL(k_fill, dim3(nblk(m, 256)), dim3(256), 0, s, ws.cnt, ws.off, m, ws.items);
 }
 
-void launch_eval(bool mixed, const Grid& g, int32_t stride, int32_t chunk,
-                 const WorkSpace& ws, BinData<double> b, BinData<float> b32, const double* ek,
-                 int blocks, hipStream_t s) {
-  if (mixed)
-    hipLaunchKernelGGL(k_eval_mixed, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
-                       ws.items, ws.total, chunk, b32.wr, b32.wi, b32.u, b32.s0, b32.c0, ek,
-                       ws.partials);
-  else
-    hipLaunchKernelGGL(k_eval_fp64, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
-                       ws.items, ws.total, chunk, b.wr, b.wi, b.u, b.s0, b.c0, ek, ws.partials);
+int interp_max_tile(bool mixed) { return mixed ? 4096 : 2048; }
+
+void launch_eval(bool mixed, bool interp, const Grid& g, int64_t n_particles, int32_t stride,
+                 int32_t chunk, const WorkSpace& ws, BinData<double> b, BinData<float> b32,
+                 const double* ek, int blocks, hipStream_t s) {
+  const int32_t* sel = nullptr;
+  const int32_t* nsel = nullptr;
+  if (!interp) hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(64), 0, s, ws.total, ws.ndirect);
+  if (interp) {
+    const int32_t ntiles = (int32_t)((g.nbins + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_tile_zero, dim3(nblk(ntiles, 256)), dim3(256), 0, s, ws.tcnt, ws.tcur,
+                       ntiles, ws.tile_ctr);
+    hipLaunchKernelGGL(k_tile_count, dim3(1024), dim3(256), 0, s, ws.items, ws.total, ws.bounds,
+                       stride, chunk, ws.tcnt);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, ws.tcnt, ntiles, ws.toff);
+    hipLaunchKernelGGL(k_tile_scatter, dim3(1024), dim3(256), 0, s, ws.items, ws.total, ws.bounds,
+                       stride, chunk, ws.toff, ws.tcur, ws.tile_items);
+    hipLaunchKernelGGL(k_interp_nodes, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
+                       ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.direct, ws.ndirect);
+    const size_t lds = 3 * (size_t)chunk * (mixed ? sizeof(float) : sizeof(double));
+    if (mixed)
+      hipLaunchKernelGGL(k_eval_interp<true>, dim3(blocks), dim3(256), lds, s, g, ws.bounds, stride,
+                         ws.items, chunk, ws.tile_items, ws.toff, ntiles, ws.tile_ctr, b.wr, b.wi,
+                         b.u, b32.wr, b32.wi, b32.u, ws.rec, ws.xflag, ws.partials);
+    else
+      hipLaunchKernelGGL(k_eval_interp<false>, dim3(blocks), dim3(256), lds, s, g, ws.bounds,
+                         stride, ws.items, chunk, ws.tile_items, ws.toff, ntiles, ws.tile_ctr,
+                         b.wr, b.wi, b.u, b32.wr, b32.wi, b32.u, ws.rec, ws.xflag, ws.partials);
+    sel = ws.direct;
+    nsel = ws.ndirect;
+  }
+  auto exact_pass = [&](const int32_t* list, const int32_t* count) {
+    if (mixed)
+      hipLaunchKernelGGL(k_eval_mixed, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
+                         ws.items, ws.total, chunk, b32.wr, b32.wi, b32.u, b32.s0, b32.c0, ek,
+                         ws.partials, list, count);
+    else
+      hipLaunchKernelGGL(k_eval_fp64, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
+                         ws.items, ws.total, chunk, b.wr, b.wi, b.u, b.s0, b.c0, ek, ws.partials,
+                         list, count);
+  };
+  exact_pass(sel, nsel);
+  if (interp && !mixed) {
+    // the mixed path's bar (1e-4 + 1e-6 cond) already covers the interpolation error
+    const int64_t m = (int64_t)n_particles * stride;
+    hipLaunchKernelGGL(k_mark, dim3(nblk(m, 256)), dim3(256), 0, s, ws.pc, n_particles, stride,
+                       ws.cnt, ws.off, ws.partials, ws.xflag, kRefineCond, ws.refine, ws.nrefine);
+    exact_pass(ws.refine, ws.nrefine);
+  }
 }
 
 void launch_solve_mean(int64_t n, int32_t stride, const WorkSpace& ws, double* F_hat,

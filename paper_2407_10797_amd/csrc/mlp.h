@@ -24,6 +24,10 @@ struct Mlp {
   float* m1 = nullptr;
   float* m2 = nullptr;
   uint16_t* wbf = nullptr;   // BF16 copies of W2..W4
+  float* red = nullptr;      // partial column sums of the backward pass
+  float* splitk = nullptr;   // split-K partial weight gradients [16][256][256]
+  float* yinf = nullptr;     // outputs of infer()
+  int64_t cap_inf = 0;
   float* z[4] = {nullptr, nullptr, nullptr, nullptr};        // pre-activations [B][256]
   uint16_t* h[4] = {nullptr, nullptr, nullptr, nullptr};     // BF16 activations
   float* dz = nullptr;
@@ -41,6 +45,8 @@ struct Mlp {
   void forward(const float* x, const float* tgt, int B, hipStream_t s);
   void backward(const float* x, int B, hipStream_t s);
   void adam(int t, float lr, hipStream_t s);
+  int infer_alloc(int64_t rows);
+  void infer(const float* x, int64_t rows, hipStream_t s);   // -> yinf[rows]
 };
 
 }  // namespace fstat

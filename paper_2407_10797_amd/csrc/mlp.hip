@@ -40,6 +40,7 @@ __device__ __forceinline__ float dsilu(float z) {
 // (BF16), FP32 accumulate.  Block = 4 wavefronts = 64x64 outputs, each wave a
 // 32x32 quadrant of 2x2 MFMA 16x16x16 tiles; K advances 16 at a time through
 // LDS.  M, N multiples of 64, K a multiple of 16 (checked by the host).
+// Split K: block z covers k in [z * kper, (z + 1) * kper) and writes C + z * cz.
 // Epilogue FWD: z = acc + bias[n] -> Z[m][n] (FP32), H[m][n] = bf16(SiLU(z)).
 // Epilogue STORE: C[m][n] = acc.
 // ---------------------------------------------------------------------------
@@ -51,18 +52,21 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t* __restrict__ 
                                                    int64_t sbk, int64_t sbn, int M, int N, int K,
                                                    float* __restrict__ C, int64_t ldc,
                                                    const float* __restrict__ bias,
-                                                   uint16_t* __restrict__ H, int64_t ldh) {
+                                                   uint16_t* __restrict__ H, int64_t ldh,
+                                                   int kper, int64_t cz) {
   __shared__ uint16_t As[64][16 + 4];
   __shared__ uint16_t Bs[16][64 + 4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int wr = w >> 1, wc = w & 1;
+  const int kbeg = blockIdx.z * kper, kend = min(K, kbeg + kper);
+  C += (int64_t)blockIdx.z * cz;
   v4f acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {       // 64x16 A tile and 16x64 B tile, 4 elements per thread
       int idx = t * 4 + e;
@@ -159,27 +163,57 @@ __global__ void k_out_back(const float* __restrict__ z4, int B, const float* __r
   dzb[g] = f2bf(d);
 }
 
-// column sums over the batch: out[n] = sum_m a[m][n] (or sum_m a[m][n] * b[m][k] form
-// via the callers' GEMMs); one thread per column, fixed order
-__global__ void k_colsum(const float* __restrict__ a, int B, int ncol, float* __restrict__ out) {
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= ncol) return;
-  float s = 0.f;
-  for (int m = 0; m < B; ++m) s += a[(int64_t)m * ncol + n];
-  out[n] = s;
+// Column reductions over the batch, in two fixed-order passes (no atomics):
+// part[s][q][n] = sum over the rows m of slice s of v(m, n) * wq(m), where
+// v = a[m][n] (or SiLU(a[m][n])) and wq(m) = wv[m * wstride + q] for q < NW,
+// 1 otherwise; then out_q[n * ostr_q] = sum_s part[s][q][n].  Block = 64 columns x 4
+// row groups; grid = (256 / 64, slices).
+constexpr int kRedSlices = 64;
+
+template <int Q, int NW, bool SILU>
+__global__ __launch_bounds__(256) void k_colred(const float* __restrict__ a, int B,
+                                                const float* __restrict__ wv, int wstride,
+                                                float* __restrict__ part) {
+  __shared__ float red[4][Q][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
+  const int rows = (B + gridDim.y - 1) / gridDim.y;
+  const int m0 = blockIdx.y * rows, m1 = min(B, m0 + rows);
+  float acc[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) acc[q] = 0.f;
+  for (int m = m0 + g; m < m1; m += 4) {
+    float v = a[(int64_t)m * kHid + n];
+    if (SILU) v = silu(v);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] += q < NW ? v * wv[(int64_t)m * wstride + q] : v;
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) red[g][q][c] = acc[q];
+  __syncthreads();
+  if (g == 0) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      part[((int64_t)blockIdx.y * Q + q) * kHid + n] =
+          red[0][q][c] + red[1][q][c] + red[2][q][c] + red[3][q][c];
+  }
 }
 
-// dW5[k] = sum_m dy[m] SiLU(z4[m][k]); db5 = sum_m dy[m]
-__global__ void k_grad_out(const float* __restrict__ z4, const float* __restrict__ dy, int B,
-                           float* __restrict__ dw5, float* __restrict__ db5) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k > kHid) return;
-  float s = 0.f;
-  if (k < kHid)
-    for (int m = 0; m < B; ++m) s += dy[m] * silu(z4[(int64_t)m * kHid + k]);
-  else
-    for (int m = 0; m < B; ++m) s += dy[m];
-  if (k < kHid) dw5[k] = s; else db5[0] = s;
+struct RedOut {
+  float* p[4];
+  int stride[4];
+};
+
+template <int Q>
+__global__ void k_colfin(const float* __restrict__ part, int slices, RedOut o) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= kHid) return;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    float s = 0.f;
+    for (int k = 0; k < slices; ++k) s += part[((int64_t)k * Q + q) * kHid + n];
+    o.p[q][(int64_t)n * o.stride[q]] = s;
+  }
 }
 
 // dz_prev = dh * SiLU'(z_prev)  (dh FP32 from the GEMM)
@@ -192,17 +226,114 @@ __global__ void k_act_back(const float* __restrict__ dh, const float* __restrict
   if (dzb) dzb[g] = f2bf(d);
 }
 
-// dW1[n][k] = sum_m dz1[m][n] x[m][k]; db1[n] = sum_m dz1[m][n]
-__global__ void k_grad_in(const float* __restrict__ dz1, const float* __restrict__ x, int B,
-                          float* __restrict__ dW1, float* __restrict__ db1) {
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= kHid) return;
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, sb = 0.f;
-  for (int m = 0; m < B; ++m) {
-    float d = dz1[(int64_t)m * kHid + n];
-    s0 += d * x[m * 3 + 0]; s1 += d * x[m * 3 + 1]; s2 += d * x[m * 3 + 2]; sb += d;
+// out[i] = sum_s part[s][i], i < 256 * 256 (split-K partial products, fixed order)
+constexpr int kSplitK = 16;
+__global__ void k_splitsum(const float* __restrict__ part, int ks, float* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)kHid * kHid) return;
+  float s = 0.f;
+  for (int k = 0; k < ks; ++k) s += part[(int64_t)k * kHid * kHid + i];
+  out[i] = s;
+}
+
+// sum of dy over the batch -> db5 (one block, fixed order)
+__global__ void k_sum_dy(const float* __restrict__ dy, int B, float* __restrict__ out) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < B; i += blockDim.x) s += dy[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
   }
-  dW1[n * 3 + 0] = s0; dW1[n * 3 + 1] = s1; dW1[n * 3 + 2] = s2; db1[n] = sb;
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// Inference-only forward of the whole network on R rows, keeping no
+// activations (knot evaluation).  One wavefront per 16 rows, four per block.
+// Layer 1 runs on the VALU straight into the MFMA A-operand layout (lane l:
+// row l % 16, k = 16 kb + 4 (l / 16) + j); layers 2-4 are 16x16x16 BF16 MFMA
+// tiles over all 256 outputs with the weights' BF16 copies read from L2 in
+// the B-operand layout (col l % 16, same k); between layers the 16x256 tile
+// goes through the wave's own LDS rows to turn the D layout (row 4 (l / 16)
+// + r, col l % 16) back into the A layout.  The output unit is a lane
+// reduction.  Same operand rounding as the training forward: BF16 hidden
+// activations, FP32 last pre-activation, FP32 output layer.
+__global__ __launch_bounds__(256, 2) void k_mlp_infer(const float* __restrict__ x, int64_t R,
+                                                   const float* __restrict__ P,
+                                                   const uint16_t* __restrict__ wbf,
+                                                   float* __restrict__ y) {
+  __shared__ uint16_t T[4][16][kHid + 8];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c16 = lane & 15, g4 = lane >> 4;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 16;
+  const int64_t row = r0 + c16 < R ? r0 + c16 : R - 1;
+  const float x0 = x[row * 3 + 0], x1 = x[row * 3 + 1], x2 = x[row * 3 + 2];
+  v4s a[16];
+  {
+    const float* W1 = P + mlp_off_w(0);
+    const float* b1 = P + mlp_off_b(0);
+#pragma unroll
+    for (int kb = 0; kb < 16; ++kb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 16 * kb + 4 * g4 + j;
+        float z = b1[k] + W1[3 * k] * x0 + W1[3 * k + 1] * x1 + W1[3 * k + 2] * x2;
+        a[kb][j] = (short)f2bf(silu(z));
+      }
+  }
+  v4f acc[16];
+  for (int L = 0; L < 3; ++L) {
+    const uint16_t* W = wbf + (size_t)L * kHid * kHid;
+    const float* bias = P + mlp_off_b(L + 1);
+#pragma unroll
+    for (int nt = 0; nt < 16; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int kb = 0; kb < 16; ++kb) {
+#pragma unroll
+      for (int nt = 0; nt < 16; ++nt) {
+        const v4s b = *reinterpret_cast<const v4s*>(W + (size_t)(16 * nt + c16) * kHid + 16 * kb + 4 * g4);
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[kb], b, acc[nt], 0, 0, 0);
+      }
+    }
+    if (L < 2) {
+#pragma unroll
+      for (int nt = 0; nt < 16; ++nt) {
+        const float bn = bias[16 * nt + c16];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) T[w][4 * g4 + r][16 * nt + c16] = f2bf(silu(acc[nt][r] + bn));
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kb = 0; kb < 16; ++kb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[kb][j] = (short)T[w][c16][16 * kb + 4 * g4 + j];
+      __syncthreads();
+    }
+  }
+  const float* w5 = P + mlp_off_w(4);
+  const float* b4 = P + mlp_off_b(3);
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int nt = 0; nt < 16; ++nt) {
+    const int n = 16 * nt + c16;
+    const float wn = w5[n], bn = b4[n];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s[r] += wn * silu(acc[nt][r] + bn);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) s[r] += __shfl_xor(s[r], o, 64);
+  if (c16 == 0) {
+    const float b5 = P[mlp_off_b(4)];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = r0 + 4 * g4 + r;
+      if (m < R) y[m] = s[r] + b5;
+    }
+  }
 }
 
 // Adam on the flat parameter vector; refreshes the BF16 copies of W2..W4
@@ -247,6 +378,8 @@ int Mlp::alloc(int batch) {
     if ((rc = A((void**)&m1, sizeof(float) * kNParams))) return rc;
     if ((rc = A((void**)&m2, sizeof(float) * kNParams))) return rc;
     if ((rc = A((void**)&wbf, sizeof(uint16_t) * 3 * kHid * kHid))) return rc;
+    if ((rc = A((void**)&red, sizeof(float) * kRedSlices * 4 * kHid))) return rc;
+    if ((rc = A((void**)&splitk, sizeof(float) * kSplitK * kHid * kHid))) return rc;
   }
   size_t BH = (size_t)batch * kHid;
   for (int l = 0; l < 4; ++l) {
@@ -277,10 +410,27 @@ void Mlp::release_acts() {
 
 void Mlp::release() {
   release_acts();
-  for (void* p : {(void*)params, (void*)grad, (void*)m1, (void*)m2, (void*)wbf})
+  for (void* p : {(void*)params, (void*)grad, (void*)m1, (void*)m2, (void*)wbf, (void*)red,
+                  (void*)splitk, (void*)yinf})
     if (p) (void)hipFree(p);
-  params = grad = m1 = m2 = nullptr;
+  params = grad = m1 = m2 = red = splitk = yinf = nullptr;
+  cap_inf = 0;
   wbf = nullptr;
+}
+
+int Mlp::infer_alloc(int64_t rows) {
+  if (yinf && rows <= cap_inf) return FSTAT_OK;
+  if (yinf) (void)hipFree(yinf);
+  yinf = nullptr;
+  cap_inf = 0;
+  int rc = hip_check(hipMalloc((void**)&yinf, sizeof(float) * (rows > 0 ? rows : 1)), "mlp alloc");
+  if (!rc) cap_inf = rows;
+  return rc;
+}
+
+void Mlp::infer(const float* x, int64_t rows, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_mlp_infer, dim3(nb(rows, 64)), dim3(256), 0, s, x, rows, params, wbf, yinf);
 }
 
 void Mlp::refresh_bf16(hipStream_t s) {
@@ -297,7 +447,7 @@ void Mlp::forward(const float* x, const float* tgt, int B, hipStream_t s) {
     hipLaunchKernelGGL((k_gemm_bf16<kEpiFwd>), dim3(kHid / 64, B / 64), dim3(256), 0, s, h[l - 1],
                        (int64_t)kHid, (int64_t)1, wbf + (size_t)(l - 1) * kHid * kHid, (int64_t)1,
                        (int64_t)kHid, B, kHid, kHid, z[l], (int64_t)kHid, P + mlp_off_b(l), h[l],
-                       (int64_t)kHid);
+                       (int64_t)kHid, kHid, (int64_t)0);
   }
   hipLaunchKernelGGL(k_layer_out, dim3(nb((int64_t)B * 64, 256)), dim3(256), 0, s, z[3], B,
                      P + mlp_off_w(4), P + mlp_off_b(4), tgt, y, dy, sq);
@@ -306,26 +456,42 @@ void Mlp::forward(const float* x, const float* tgt, int B, hipStream_t s) {
 // backward after forward(x, tgt): fills grad (flat layout)
 void Mlp::backward(const float* x, int B, hipStream_t s) {
   float* G = grad;
-  hipLaunchKernelGGL(k_grad_out, dim3(nb(kHid + 1, 64)), dim3(64), 0, s, z[3], dy, B,
-                     G + mlp_off_w(4), G + mlp_off_b(4));
+  const int sl = B / 64 < kRedSlices ? B / 64 : kRedSlices;
+  int ks = kSplitK;
+  while (ks > 1 && (B % (16 * ks))) ks >>= 1;
+  // dW5[k] = sum_m dy[m] SiLU(z4[m][k]); db5 = sum_m dy[m]
+  hipLaunchKernelGGL((k_colred<1, 1, true>), dim3(kHid / 64, sl), dim3(256), 0, s, z[3], B, dy, 1, red);
+  hipLaunchKernelGGL(k_colfin<1>, dim3(1), dim3(kHid), 0, s, red, sl,
+                     RedOut{{G + mlp_off_w(4), nullptr, nullptr, nullptr}, {1, 0, 0, 0}});
+  hipLaunchKernelGGL(k_sum_dy, dim3(1), dim3(256), 0, s, dy, B, G + mlp_off_b(4));
   hipLaunchKernelGGL(k_out_back, dim3(nb((int64_t)B * kHid, 256)), dim3(256), 0, s, z[3], B,
                      params + mlp_off_w(4), dy, dz, dzb);
   for (int l = 3; l >= 1; --l) {
-    // dW_l = dZ_l^T H_{l-1}: A(m,k) = dZ[k][m], B(k,n) = H_{l-1}[k][n]
-    hipLaunchKernelGGL((k_gemm_bf16<kEpiStore>), dim3(kHid / 64, kHid / 64), dim3(256), 0, s, dzb,
-                       (int64_t)1, (int64_t)kHid, h[l - 1], (int64_t)kHid, (int64_t)1, kHid, kHid,
-                       B, G + mlp_off_w(l), (int64_t)kHid, nullptr, nullptr, (int64_t)0);
-    hipLaunchKernelGGL(k_colsum, dim3(nb(kHid, 64)), dim3(64), 0, s, dz, B, kHid, G + mlp_off_b(l));
+    // dW_l = dZ_l^T H_{l-1}: A(m,k) = dZ[k][m], B(k,n) = H_{l-1}[k][n]; K = B split
+    // into kSplitK slices (16 blocks would not fill the chip), then summed in order
+    hipLaunchKernelGGL((k_gemm_bf16<kEpiStore>), dim3(kHid / 64, kHid / 64, ks), dim3(256), 0, s,
+                       dzb, (int64_t)1, (int64_t)kHid, h[l - 1], (int64_t)kHid, (int64_t)1, kHid,
+                       kHid, B, splitk, (int64_t)kHid, nullptr, nullptr, (int64_t)0, B / ks,
+                       (int64_t)kHid * kHid);
+    hipLaunchKernelGGL(k_splitsum, dim3(nb((int64_t)kHid * kHid, 256)), dim3(256), 0, s, splitk,
+                       ks, G + mlp_off_w(l));
+    hipLaunchKernelGGL((k_colred<1, 0, false>), dim3(kHid / 64, sl), dim3(256), 0, s, dz, B,
+                       (const float*)nullptr, 0, red);
+    hipLaunchKernelGGL(k_colfin<1>, dim3(1), dim3(kHid), 0, s, red, sl,
+                       RedOut{{G + mlp_off_b(l), nullptr, nullptr, nullptr}, {1, 0, 0, 0}});
     // dH_{l-1} = dZ_l W_l: A = dZ (ld kHid), B(k,n) = W_l[k][n]
     hipLaunchKernelGGL((k_gemm_bf16<kEpiStore>), dim3(kHid / 64, B / 64), dim3(256), 0, s, dzb,
                        (int64_t)kHid, (int64_t)1, wbf + (size_t)(l - 1) * kHid * kHid,
                        (int64_t)kHid, (int64_t)1, B, kHid, kHid, dh, (int64_t)kHid, nullptr,
-                       nullptr, (int64_t)0);
+                       nullptr, (int64_t)0, kHid, (int64_t)0);
     hipLaunchKernelGGL(k_act_back, dim3(nb((int64_t)B * kHid, 256)), dim3(256), 0, s, dh,
                        z[l - 1], (int64_t)B * kHid, dz, dzb);
   }
-  hipLaunchKernelGGL(k_grad_in, dim3(nb(kHid, 64)), dim3(64), 0, s, dz, x, B, G + mlp_off_w(0),
-                     G + mlp_off_b(0));
+  // dW1[n][k] = sum_m dz1[m][n] x[m][k]; db1[n] = sum_m dz1[m][n]
+  hipLaunchKernelGGL((k_colred<4, 3, false>), dim3(kHid / 64, sl), dim3(256), 0, s, dz, B, x, 3, red);
+  hipLaunchKernelGGL(k_colfin<4>, dim3(1), dim3(kHid), 0, s, red, sl,
+                     RedOut{{G + mlp_off_w(0), G + mlp_off_w(0) + 1, G + mlp_off_w(0) + 2,
+                             G + mlp_off_b(0)}, {3, 3, 3, 1}});
 }
 
 void Mlp::adam(int t, float lr, hipStream_t s) {
@@ -369,6 +535,29 @@ extern "C" int fstat_mlp_grad(const float* params, const float* x, const float* 
   }
   if (dx) (void)hipFree(dx);
   if (dt) (void)hipFree(dt);
+  net.release();
+  return rc;
+}
+
+extern "C" int fstat_mlp_forward(const float* params, const float* x, int64_t R, float* y) {
+  if (!params || !x || !y || R < 1 || R > ((int64_t)1 << 31))
+    return set_error(FSTAT_EINVAL, "fstat_mlp_forward: bad arguments");
+  Mlp net;
+  int rc = hip_check(hipMalloc((void**)&net.params, sizeof(float) * kNParams), "alloc params");
+  if (!rc) rc = hip_check(hipMalloc((void**)&net.wbf, sizeof(uint16_t) * 3 * kHid * kHid), "alloc wbf");
+  if (!rc) rc = net.infer_alloc(R);
+  float* dx = nullptr;
+  if (!rc) rc = hip_check(hipMalloc(&dx, sizeof(float) * 3 * R), "alloc x");
+  hipStream_t s = nullptr;
+  if (!rc) rc = hip_check(hipMemcpy(net.params, params, sizeof(float) * kNParams, hipMemcpyHostToDevice), "copy");
+  if (!rc) rc = hip_check(hipMemcpy(dx, x, sizeof(float) * 3 * R, hipMemcpyHostToDevice), "copy");
+  if (!rc) {
+    net.refresh_bf16(s);
+    net.infer(dx, R, s);
+    rc = hip_check(hipGetLastError(), "mlp launch");
+  }
+  if (!rc) rc = hip_check(hipMemcpy(y, net.yinf, sizeof(float) * R, hipMemcpyDeviceToHost), "copy y");
+  if (dx) (void)hipFree(dx);
   net.release();
   return rc;
 }

@@ -175,6 +175,7 @@ extern "C" int pso_stage(fstat_plan_t P, const pso_stage_desc* d, pso_result* re
     return set_error(FSTAT_EINVAL, "bad PSO coefficients");
   const bool mixed = (d->flags & FSTAT_EVAL_MIXED) != 0;
   const bool sur = (d->flags & FSTAT_EVAL_SURROGATE) != 0;
+  const bool exact = (d->flags & FSTAT_EVAL_EXACT) != 0;
   if (sur && !P->sur_trained) return set_error(FSTAT_EINVAL, "surrogate requested but not trained");
   if (mixed && !(P->prec & FSTAT_MIXED)) return set_error(FSTAT_EINVAL, "plan has no mixed data");
   if (!mixed && !(P->prec & FSTAT_FP64)) return set_error(FSTAT_EINVAL, "plan has no FP64 data");
@@ -222,7 +223,8 @@ extern "C" int pso_stage(fstat_plan_t P, const pso_stage_desc* d, pso_result* re
   const size_t shmem = sizeof(double) * Pn + sizeof(int) * 2;
   auto iteration = [&]() -> int {
     hipLaunchKernelGGL(k_pso_decode, dim3(nb), dim3(256), 0, s, a, x, box, np_run, params, np, skip);
-    int r2 = eval_device(P, params, n, np, 0, stride, F, nullptr, 0, mixed, s, skip, false, sur);
+    int r2 = eval_device(P, params, n, np, 0, stride, F, nullptr, 0, mixed, s, skip, false, sur,
+                         exact);
     if (r2) return r2;
     hipLaunchKernelGGL(k_pso_update, dim3(R), dim3(tpb), shmem, s, a, F, x, v, pbx, pbf, gbx, gbf,
                        trace, iter);

@@ -108,7 +108,7 @@ int sur_ensure(fstat_plan_s* P, int64_t n, int32_t stride) {
     return set_error(FSTAT_EINVAL, "surrogate requested but not trained (fstat_surrogate_train)");
   int64_t rows = knot_rows(n, stride);
   if (rows > (int64_t)INT32_MAX) return set_error(FSTAT_EINVAL, "too many surrogate knots");
-  int rc = P->sur->alloc((int)rows);
+  int rc = P->sur->infer_alloc(rows);
   if (!rc) rc = grow(&P->sur_X, &P->cap_sur_X, (size_t)rows * 3, "alloc knots");
   if (!rc) rc = grow(&P->sur_ek, &P->cap_sur_ek, (size_t)n * stride * 8, "alloc knot coeffs");
   if (!rc) rc = grow(&P->sur_mm, &P->cap_sur_mm, (size_t)n * stride, "alloc mismatch");
@@ -121,8 +121,8 @@ int sur_prepare(fstat_plan_s* P, int64_t n, int32_t stride, hipStream_t s) {
   int64_t rows = knot_rows(n, stride);
   hipLaunchKernelGGL(k_zero_ull, dim3(1), dim3(64), 0, s, P->sur_counters, 2);
   launch_sur_knots(P->grid, stride, n, rows, P->ws, P->sur_X, s);
-  P->sur->forward(P->sur_X, nullptr, (int)rows, s);
-  launch_sur_check(P->grid, stride, n, P->ws, P->sur->y, P->sur_ek, P->sur_mm, kSurMismatch,
+  P->sur->infer(P->sur_X, rows, s);
+  launch_sur_check(P->grid, stride, n, P->ws, P->sur->yinf, P->sur_ek, P->sur_mm, kSurMismatch,
                    P->sur_counters, s);
   return hip_check(hipGetLastError(), "surrogate launch");
 }

@@ -26,10 +26,12 @@ FSTAT_EVAL_MIXED = 2
 FSTAT_PROFILE = 4
 FSTAT_EVAL_SURROGATE = 8
 FSTAT_AUTOTUNE_FORCE = 16
+FSTAT_EVAL_EXACT = 32
 
 EXPORTS = ("fstat_plan_create", "fstat_eval", "fstat_waveform", "pso_stage",
-           "fstat_profile_read", "fstat_autotune", "fstat_mlp_grad", "fstat_surrogate_train",
-           "fstat_surrogate_stats", "fstat_plan_destroy", "fstat_last_error")
+           "fstat_profile_read", "fstat_interp_stats", "fstat_autotune", "fstat_mlp_grad", "fstat_mlp_forward",
+           "fstat_surrogate_train", "fstat_surrogate_stats", "fstat_plan_destroy",
+           "fstat_last_error")
 
 
 class fstat_data_desc(ctypes.Structure):
@@ -94,6 +96,10 @@ def lib() -> ctypes.CDLL:
         L.fstat_profile_read.restype = ctypes.c_int
         L.fstat_mlp_grad.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double), vp, vp]
         L.fstat_mlp_grad.restype = ctypes.c_int
+        L.fstat_interp_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
+        L.fstat_interp_stats.restype = ctypes.c_int
+        L.fstat_mlp_forward.argtypes = [vp, vp, i64, vp]
+        L.fstat_mlp_forward.restype = ctypes.c_int
         L.fstat_surrogate_train.argtypes = [vp, ctypes.POINTER(fstat_surrogate_desc), vp]
         L.fstat_surrogate_train.restype = ctypes.c_int
         L.fstat_surrogate_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -162,6 +168,22 @@ def fstat_mlp_grad(params, x, t):
     return loss.value, grad, y
 
 
+def fstat_interp_stats(plan, stream=None):
+    items, exact = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().fstat_interp_stats(plan, ctypes.byref(items), ctypes.byref(exact), stream))
+    return items.value, exact.value
+
+
+def fstat_mlp_forward(params, x):
+    """y of the fused inference kernel of the surrogate network."""
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.zeros(x.shape[0], dtype=np.float32)
+    _check(lib().fstat_mlp_forward(params.ctypes.data, x.ctypes.data, ctypes.c_int64(x.shape[0]),
+                                   y.ctypes.data))
+    return y
+
+
 def fstat_surrogate_train(plan, desc: fstat_surrogate_desc, stream=None):
     _check(lib().fstat_surrogate_train(plan, ctypes.byref(desc), stream))
 
@@ -219,7 +241,7 @@ class Plan:
         torch.cuda.current_stream().synchronize()
 
     def eval(self, params, np_parts=1, part_stride: int | None = None, mixed: bool = False,
-             want_parts: bool = False, surrogate: bool = False):
+             want_parts: bool = False, surrogate: bool = False, exact: bool = False):
         """F_hat [n] (and F_part [n, stride]) for params [n, 6] on the device."""
         torch = _torch()
         prm = torch.as_tensor(params).to("cuda", torch.float64).contiguous()
@@ -235,7 +257,7 @@ class Plan:
             stride = part_stride or int(np_t.max().item())
         Fp = torch.zeros((n, stride), device="cuda", dtype=torch.float64) if want_parts else None
         flags = (FSTAT_DEVICE_PTRS | (FSTAT_EVAL_MIXED if mixed else 0)
-                 | (FSTAT_EVAL_SURROGATE if surrogate else 0))
+                 | (FSTAT_EVAL_SURROGATE if surrogate else 0) | (FSTAT_EVAL_EXACT if exact else 0))
         fstat_eval(self.handle, prm.data_ptr(), n, npp, npu, F.data_ptr(),
                    Fp.data_ptr() if Fp is not None else None, stride, flags, _stream())
         return (F, Fp) if want_parts else F
@@ -243,7 +265,7 @@ class Plan:
     def pso(self, box, np_runs, n_part: int, iters: int, ring_k: int = 1, w=(0.7, 0.7),
             c1: float = 1.5, c2: float = 1.5, vmax: float = 0.5, seed: int = 1,
             mixed: bool = False, use_graph: bool = True, want_trace: bool = True,
-            want_final: bool = False, surrogate: bool = False):
+            want_final: bool = False, surrogate: bool = False, exact: bool = False):
         """Run pso_stage: box [R, 6, 2] (physical), np_runs [R].  Returns dict
         with best_x [R, 6], best_F [R], trace [iters, R], final_x [R, n_part, 6]."""
         _torch()
@@ -256,7 +278,8 @@ class Plan:
         desc = pso_stage_desc(R, int(n_part), int(iters), int(ring_k), float(w[0]), float(w[1]),
                               float(c1), float(c2), float(vmax), int(seed), box.ctypes.data,
                               npr.ctypes.data,
-                              (FSTAT_EVAL_MIXED if mixed else 0) | (FSTAT_EVAL_SURROGATE if surrogate else 0),
+                              (FSTAT_EVAL_MIXED if mixed else 0) | (FSTAT_EVAL_SURROGATE if surrogate else 0)
+                              | (FSTAT_EVAL_EXACT if exact else 0),
                               int(use_graph))
         res = pso_result(best_x.ctypes.data, best_F.ctypes.data,
                          trace.ctypes.data if trace is not None else None,
@@ -282,14 +305,19 @@ class Plan:
             out["loss_trace"] = trace
         return out
 
-    def autotune(self, params, np_parts: int, mixed: bool = False, force: bool = False):
+    def autotune(self, params, np_parts: int, mixed: bool = False, force: bool = False,
+                 exact: bool = False):
         """Pick the work-item size and grid multiplier for this precision; returns
         (chunk, grid multiplier, best ms or -1 if cached)."""
         torch = _torch()
         prm = torch.as_tensor(params).to("cuda", torch.float64).contiguous()
         flags = (FSTAT_DEVICE_PTRS | (FSTAT_EVAL_MIXED if mixed else 0)
-                 | (FSTAT_AUTOTUNE_FORCE if force else 0))
+                 | (FSTAT_AUTOTUNE_FORCE if force else 0) | (FSTAT_EVAL_EXACT if exact else 0))
         return fstat_autotune(self.handle, prm.data_ptr(), prm.shape[0], int(np_parts), flags, _stream())
+
+    def interp_stats(self):
+        """(work items, items evaluated exactly per bin) of the last evaluation."""
+        return fstat_interp_stats(self.handle, _stream())
 
     def surrogate_stats(self):
         """(particles that used the surrogate, particles that fell back) in the last

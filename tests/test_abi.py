@@ -15,8 +15,9 @@ def _declared():
 
 def test_header_declares_the_boundary():
     assert _declared() == sorted(["fstat_plan_create", "fstat_eval", "fstat_waveform",
-                                  "pso_stage", "fstat_profile_read", "fstat_autotune",
-                                  "fstat_mlp_grad",
+                                  "pso_stage", "fstat_profile_read", "fstat_interp_stats",
+                                  "fstat_autotune",
+                                  "fstat_mlp_grad", "fstat_mlp_forward",
                                   "fstat_surrogate_train", "fstat_surrogate_stats",
                                   "fstat_plan_destroy", "fstat_last_error"])
 

@@ -75,6 +75,26 @@ def test_small_workload_matches_oracle(small, torch_cuda, npart):
         assert np.max(_rel(F, Fo)) < REL
 
 
+@pytest.mark.parametrize("npart", [1, 16, 256])
+def test_interpolating_and_exact_bin_loops_agree(small, torch_cuda, npart):
+    """Default (per-item interpolation of the smooth factors, with exact
+    fallback) vs FSTAT_EVAL_EXACT (exact template at every bin): 1e-10 relative
+    per partition, plus 1e-14 cond(M_l); both against the oracle elsewhere."""
+    s = small
+    _, _, cond = O.fstat(s["data"], s["psd"], s["g"].k_lo, s["g"].df, s["g"].T_obs, s["pts"],
+                         [npart], want_cond=True)
+    F, P = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, want_parts=True)
+    items, exact_items = s["plan"].interp_stats()
+    Fe, Pe = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, want_parts=True, exact=True)
+    items_e, exact_e = s["plan"].interp_stats()
+    print(f"[interp] Np={npart}: {items} items, {exact_items} evaluated exactly", flush=True)
+    assert items == items_e and exact_e == items_e
+    P, Pe = P.cpu().numpy(), Pe.cpu().numpy()
+    c = np.where(np.isfinite(cond[:, :npart]), cond[:, :npart], 0.0)
+    r = _rel(P[:, :npart], Pe[:, :npart])
+    assert np.all(r <= 1e-10 + 1e-14 * c), float(r.max())
+
+
 def test_uneven_np_in_one_launch(small, torch_cuda):
     """Mixed partition counts in one batch equal separate uniform launches."""
     s = small

@@ -44,6 +44,29 @@ def test_mlp_forward_backward_match_fp64_reference(torch_cuda, B):
         o += n
 
 
+@pytest.mark.parametrize("R", [1, 100, 4096 + 17])
+def test_fused_inference_matches_training_forward_and_fp64(torch_cuda, R):
+    """The knot-evaluation kernel (whole network in one launch, ragged row
+    count) against the training forward (same operand rounding: 1e-5) and the
+    FP64 reference: BF16 operands (unit roundoff 2^-9) through three 256-term
+    layers of an untrained network leave ~1 % (3e-2, the gradient bar)."""
+    from paper_2407_10797_amd import fstat
+    rng = np.random.default_rng(R)
+    p = MO.init(11).astype(np.float32)
+    x = rng.uniform(-1, 1, (R, 3)).astype(np.float32)
+    y = fstat.fstat_mlp_forward(p, x)
+    y_ref, _, _ = MO.forward(p.astype(np.float64), x.astype(np.float64))
+    Bp = ((R + 63) // 64) * 64
+    xp = np.zeros((Bp, 3), np.float32)
+    xp[:R] = x
+    _, _, y_tr = fstat.fstat_mlp_grad(p, xp, np.zeros(Bp, np.float32))
+    print(f"[mlp-infer] R={R} vs training forward {_rel(y, y_tr[:R]):.2e}, vs FP64 {_rel(y, y_ref):.2e}",
+          flush=True)
+    assert np.all(np.isfinite(y))
+    assert _rel(y, y_tr[:R]) < 1e-5
+    assert _rel(y, y_ref) < 3e-2
+
+
 def test_mlp_rejects_bad_batch(torch_cuda):
     from paper_2407_10797_amd import fstat
     p = MO.init(1).astype(np.float32)
