@@ -28,15 +28,18 @@ sys.path.insert(0, ROOT)
 # library is built without packed FP32, so 157.3 is out of its reach).
 PEAK_VALU_TFLOPS = 78.6
 PEAK_LANE_INSTR = 256 * 64 * 2.4e9
-# Per bin-template figures of the bin-loop kernels (profiles/k_eval_paper_4096x64_counters.md):
-# floating-point operations (FP64 + FP32, FMA = 2), VALU instructions, HBM bytes read
-# per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes written per launch.
-FLOP_PER_BIN = {"fp64": 765.7, "mixed": 625.4}
-VALU_PER_BIN = {"fp64": 805.3, "mixed": 615.7}
-TRAFFIC = {"fp64": (38.65, 1.2045e8), "mixed": (18.66, 1.2092e8)}
-# sha256 of the kernel sources those counters were taken on; traffic is reported
-# as null once the sources differ.
-COUNTERS_SRC_SHA = "f08c95a4790a6e58f837f21b53d84902132ea977f218be72f582b9c4300e300b"
+# Per bin-template figures of the main bin-loop kernel of each path (the
+# interpolating loop k_eval_interp; profiles/k_eval_interp_paper_4096x64_counters.md):
+# floating-point operations (FP64 + FP32, FMA = 2, x64 lanes), VALU instructions, HBM
+# bytes read per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes
+# written per launch (WRITE_SIZE).
+MAIN_KERNEL = {"fp64": "k_eval_interp<false>", "mixed": "k_eval_interp<true>"}
+FLOP_PER_BIN = {"fp64": 183.6, "mixed": 155.0}
+VALU_PER_BIN = {"fp64": 146.1, "mixed": 117.5}
+TRAFFIC = {"fp64": (0.3499, 1.3105e8), "mixed": (0.3429, 1.3098e8)}
+# sha256 of the kernel sources those counters were taken on; the figures are
+# reported as null once the sources differ.
+COUNTERS_SRC_SHA = "ddf8cf99bbe254e14a2f5c663f8c35b545f08b5ebd16185c4383a46812d44e5e"
 KERNEL_SOURCES = ("fstat_kernels.hip", "fstat_internal.h", "fstat_kernels.h")
 
 
@@ -78,8 +81,8 @@ def time_path(plan, prm, npart, steps, warmup, mixed, surrogate=False):
         F = plan.eval(prm, npart, mixed=mixed, surrogate=surrogate)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kms, launches, bins = plan.profile_read(reset=True)
-    return dict(seconds=t1 - t0, kernel_ms=kms / max(launches, 1),
+    kms, mms, launches, bins = plan.profile_read(reset=True)
+    return dict(seconds=t1 - t0, kernel_ms=kms / max(launches, 1), main_ms=mms / max(launches, 1),
                 bins_per_launch=bins / max(launches, 1), F=F)
 
 
@@ -196,8 +199,8 @@ def main():
                 extra.update(tuned_chunk=c, tuned_grid_mult=m)
                 _log(f"{name}: autotuned work item {c} bins, grid x{m}")
             r = time_path(plan, prm, args.np, args.steps, args.warmup, mixed, sur)
-            items, exact_items = plan.interp_stats()
-            extra.update(work_items=items, exact_items=exact_items)
+            items, rejected, refined = plan.interp_stats()
+            extra.update(work_items=items, exact_items=rejected, refined_items=refined)
             if sur:
                 extra["used"], extra["fallback"] = plan.surrogate_stats()
         except fstat.FstatError as e:
@@ -205,21 +208,25 @@ def main():
             continue
         tps = args.particles * args.steps / r["seconds"]
         kind = "mixed" if mixed else "fp64"
-        secs = r["kernel_ms"] * 1e-3
-        achieved = FLOP_PER_BIN[kind] * r["bins_per_launch"] / secs / 1e12
+        secs = r["main_ms"] * 1e-3          # the main kernel alone (HIP events)
+        bins = r["bins_per_launch"]
+        # the per-bin figures belong to the kernel sources they were counted on
+        achieved = FLOP_PER_BIN[kind] * bins / secs / 1e12 if same_src else None
         rd, wr = TRAFFIC[kind]
-        traffic = rd * r["bins_per_launch"] + wr if same_src else None
+        traffic = rd * bins + wr if same_src else None
         variants[name] = dict(templates_per_s=tps, ms_per_step=1e3 * r["seconds"] / args.steps,
-                              kernel_ms=r["kernel_ms"], bins_per_launch=r["bins_per_launch"],
-                              bin_templates_per_s=r["bins_per_launch"] / secs,
-                              valu_issue_frac=VALU_PER_BIN[kind] * r["bins_per_launch"] / secs
-                              / PEAK_LANE_INSTR if same_src else None,
+                              stage_ms=r["kernel_ms"], main_kernel=MAIN_KERNEL[kind],
+                              main_kernel_ms=r["main_ms"], bins_per_launch=bins,
+                              bin_templates_per_s=bins / (r["kernel_ms"] * 1e-3),
+                              valu_issue_frac=VALU_PER_BIN[kind] * bins / secs / PEAK_LANE_INSTR
+                              if same_src else None,
                               hbm_GBps=traffic / secs / 1e9 if traffic else None,
                               roofline=dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TFLOPS,
-                                            unit="TFLOP/s", frac=achieved / PEAK_VALU_TFLOPS,
+                                            unit="TFLOP/s",
+                                            frac=achieved / PEAK_VALU_TFLOPS if achieved else None,
                                             traffic=traffic), **extra)
-        _log(f"{name}: {tps:.1f} templates/s, kernel {r['kernel_ms']:.2f} ms/launch, "
-             f"{r['bins_per_launch']:.3e} bin-templates/launch")
+        _log(f"{name}: {tps:.1f} templates/s, bin-loop stage {r['kernel_ms']:.2f} ms, main kernel "
+             f"{r['main_ms']:.2f} ms, {r['bins_per_launch']:.3e} bin-templates/launch")
     head = variants.get("fp64") or next(iter(variants.values()))
     out = {
         "metric": "F-stat templates/s at 7.1M bins, Np=64; %roofline; plain vs mixed+surrogate",

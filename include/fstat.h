@@ -81,8 +81,12 @@ typedef struct {
 typedef struct {
   int32_t precision;   /* mask of FSTAT_FP64 | FSTAT_MIXED; 0 = both           */
   uint32_t flags;      /* FSTAT_DEVICE_PTRS: data/psd are device pointers      */
-  int32_t chunk;       /* bins per work item; 0 = tuned default                */
+  int32_t chunk;       /* bins per work item (bin tile); 0 = 2048              */
   int32_t reserved;
+  double refine_budget; /* FP64 interpolating loop: partitions where the
+                           interpolation error could move F by more than this
+                           (relative; bound 2 cond(M) e) are evaluated again
+                           exactly.  0 = 1e-9; < 0 = never                   */
 } fstat_opts;
 
 /* Create a plan: validates the grid (EINVAL on nbins < 1, df <= 0, k_lo < 1,
@@ -169,22 +173,25 @@ typedef struct {
  * are written when the call returns.  EINVAL on bad sizes or boxes.       */
 int pso_stage(fstat_plan_t plan, const pso_stage_desc *desc, pso_result *result, void *hip_stream);
 
-/* Diagnostics for plans created with FSTAT_PROFILE: total duration of the
- * bin-loop kernel (HIP events recorded on the caller's stream around each
- * launch), number of launches, and the number of bin-template evaluations
- * performed (sum over particles of their support size), accumulated since
- * the last reset.  Waits for the recorded events.  EINVAL without profiling. */
-int fstat_profile_read(fstat_plan_t plan, int reset, double *kernel_ms, int64_t *launches,
-                       int64_t *bin_templates);
+/* Diagnostics for plans created with FSTAT_PROFILE, accumulated since the
+ * last reset, from HIP events recorded on the caller's stream: kernel_ms =
+ * the whole bin-loop stage (interpolation nodes, tile grouping, the
+ * interpolating loop, the exact passes), main_ms = its main kernel alone (the
+ * interpolating loop, or the exact loop under FSTAT_EVAL_EXACT); the number
+ * of evaluations; the bin-template evaluations performed (sum over particles
+ * of their support size).  Waits for the recorded events.  EINVAL without
+ * profiling.                                                               */
+int fstat_profile_read(fstat_plan_t plan, int reset, double *kernel_ms, double *main_ms,
+                       int64_t *launches, int64_t *bin_templates);
 
-/* Work items of the plan's last evaluation, and how many of them were
- * evaluated by the exact per-bin loop: items the interpolating loop handed
- * over (fewer than 32 bins, or interpolants that missed an end point) plus,
- * on the FP64 path, the interpolated items of partitions whose matrix has
- * cond > 1e3 (evaluated again exactly); exact_items == items after an
- * FSTAT_EVAL_EXACT evaluation.  Waits for hip_stream.  EINVAL before the
- * first evaluation.                                                        */
-int fstat_interp_stats(fstat_plan_t plan, int64_t *items, int64_t *exact_items,
+/* Work items of the plan's last evaluation and how many took the exact
+ * per-bin loop: `rejected` = items the interpolating loop handed over (fewer
+ * than 32 bins, or interpolants that missed an end point; all items after an
+ * FSTAT_EVAL_EXACT evaluation), `refined` = interpolated items evaluated again
+ * exactly because their partition's matrix is ill-conditioned enough for the
+ * interpolation error to matter (FP64 path only).  Waits for hip_stream.
+ * EINVAL before the first evaluation.                                      */
+int fstat_interp_stats(fstat_plan_t plan, int64_t *items, int64_t *rejected, int64_t *refined,
                        void *hip_stream);
 
 /* ---- learned surrogate for the eccentric phase (App. A) ------------------- */

@@ -1,5 +1,6 @@
 // fstat_api.hip -- C ABI of libfstat (see include/fstat.h): plans, batched
 // evaluation and template generation.
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -84,6 +85,7 @@ int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride, int chunk) {
   if ((rc = ensure(&P->ws.xflag, &P->cap.xflag, cap_items, "alloc item flags"))) return rc;
   if ((rc = ensure(&P->ws.rec, &P->cap.rec, cap_items * kInterpRec, "alloc interpolation records")))
     return rc;
+  if ((rc = ensure(&P->ws.xerr, &P->cap.xerr, cap_items, "alloc item errors"))) return rc;
   if ((rc = ensure(&P->ws.refine, &P->cap.refine, cap_items, "alloc refine list"))) return rc;
   if ((rc = ensure(&P->ws.nrefine, &P->cap.nrefine, 1, "alloc refine count"))) return rc;
   return FSTAT_OK;
@@ -116,18 +118,20 @@ int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t*
   launch_setup(P->grid, params, n, np, np_uniform, stride, chunk, skip, P->ws, s);
   if (surrogate && (rc = sur_prepare(P, n, stride, s))) return rc;
   launch_worklist(n * (int64_t)stride, P->ws, s);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  // profiling: the whole bin-loop stage (e[0], e[3]) and its main kernel (e[1], e[2])
+  std::array<hipEvent_t, 4> ev = {nullptr, nullptr, nullptr, nullptr};
   const bool prof = P->profile && allow_profile;
   if (prof) {
-    if ((rc = hip_check(hipEventCreate(&e0), "event")) || (rc = hip_check(hipEventCreate(&e1), "event")))
-      return rc;
-    (void)hipEventRecord(e0, s);
+    for (auto& e : ev)
+      if ((rc = hip_check(hipEventCreate(&e), "event"))) return rc;
+    (void)hipEventRecord(ev[0], s);
   }
-  launch_eval(mixed, !exact, P->grid, n, stride, chunk, P->ws, P->b64, P->b32,
-              surrogate ? P->sur_ek : nullptr, eval_blocks(P, mixed), s);
+  launch_eval(mixed, !exact, P->refine_budget, P->grid, n, stride, chunk, P->ws, P->b64, P->b32,
+              surrogate ? P->sur_ek : nullptr, eval_blocks(P, mixed), s,
+              prof ? &ev[1] : nullptr);
   if (prof) {
-    (void)hipEventRecord(e1, s);
-    P->events.emplace_back(e0, e1);
+    (void)hipEventRecord(ev[3], s);
+    P->events.push_back(ev);
   }
   launch_solve_mean(n, stride, P->ws, F_hat, F_part, part_stride, prof ? P->bin_counter : nullptr, s);
   return hip_check(hipGetLastError(), "kernel launch");
@@ -275,6 +279,8 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
   if (prec == 0) prec = FSTAT_FP64 | FSTAT_MIXED;
   if (prec & ~(FSTAT_FP64 | FSTAT_MIXED)) return set_error(FSTAT_EINVAL, "bad precision mask");
   int chunk = (opts && opts->chunk > 0) ? opts->chunk : 2048;
+  const double budget = (opts && opts->refine_budget != 0.0) ? opts->refine_budget : 1e-9;
+  if (!std::isfinite(budget)) return set_error(FSTAT_EINVAL, "refine_budget must be finite");
   if (chunk < 64 || chunk > (1 << 24)) return set_error(FSTAT_EINVAL, "chunk out of range");
   const bool dev = (flags & FSTAT_DEVICE_PTRS) != 0;
   const int64_t nb = d->nbins;
@@ -291,6 +297,7 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
   P->grid = Grid{d->df, d->T_obs, d->k_lo, nb};
   P->prec = prec;
   P->chunk = chunk;
+  P->refine_budget = budget;
   int rc = hip_check(hipGetDevice(&P->device), "hipGetDevice");
   if (!rc) rc = hip_check(hipDeviceGetAttribute(&P->num_cu, hipDeviceAttributeMultiprocessorCount,
                                                 P->device), "device attribute");
@@ -360,16 +367,18 @@ void fstat_plan_destroy(fstat_plan_t P) {
   dev_free(P->ws.total); dev_free(P->ws.items); dev_free(P->ws.partials); dev_free(P->ws.Fl);
   dev_free(P->ws.direct); dev_free(P->ws.ndirect);
   dev_free(P->ws.tcnt); dev_free(P->ws.tcur); dev_free(P->ws.toff); dev_free(P->ws.tile_items);
-  dev_free(P->ws.tile_ctr); dev_free(P->ws.xflag); dev_free(P->ws.rec); dev_free(P->ws.refine); dev_free(P->ws.nrefine);
+  dev_free(P->ws.tile_ctr); dev_free(P->ws.xflag); dev_free(P->ws.rec); dev_free(P->ws.xerr); dev_free(P->ws.refine); dev_free(P->ws.nrefine);
   dev_free(P->io.params); dev_free(P->io.np); dev_free(P->io.F_hat); dev_free(P->io.F_part);
   pso_release(P);
   sur_release(P);
-  for (auto& e : P->events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  for (auto& e : P->events)
+    for (auto x : e) (void)hipEventDestroy(x);
   dev_free(P->bin_counter);
   delete P;
 }
 
-int fstat_interp_stats(fstat_plan_t P, int64_t* items, int64_t* exact_items, void* hip_stream) {
+int fstat_interp_stats(fstat_plan_t P, int64_t* items, int64_t* rejected, int64_t* refined,
+                       void* hip_stream) {
   g_err.clear();
   if (!P || !P->ws.total || !P->ws.ndirect || !P->ws.nrefine)
     return set_error(FSTAT_EINVAL, "no evaluation yet");
@@ -384,30 +393,35 @@ int fstat_interp_stats(fstat_plan_t P, int64_t* items, int64_t* exact_items, voi
   if (!rc) rc = hip_check(hipStreamSynchronize(s), "interp stats");
   if (rc) return rc;
   if (items) *items = v[0];
-  if (exact_items) *exact_items = (int64_t)v[1] + v[2];
+  if (rejected) *rejected = v[1];
+  if (refined) *refined = v[2];
   return FSTAT_OK;
 }
 
-int fstat_profile_read(fstat_plan_t P, int reset, double* kernel_ms, int64_t* launches,
-                       int64_t* bin_templates) {
+int fstat_profile_read(fstat_plan_t P, int reset, double* kernel_ms, double* main_ms,
+                       int64_t* launches, int64_t* bin_templates) {
   g_err.clear();
   if (!P || !P->profile) return set_error(FSTAT_EINVAL, "plan was not created with FSTAT_PROFILE");
-  double tot = 0.0;
+  double tot = 0.0, tmain = 0.0;
   for (auto& e : P->events) {
-    int rc = hip_check(hipEventSynchronize(e.second), "event sync");
+    int rc = hip_check(hipEventSynchronize(e[3]), "event sync");
     if (rc) return rc;
-    float ms = 0.f;
-    if ((rc = hip_check(hipEventElapsedTime(&ms, e.first, e.second), "elapsed"))) return rc;
+    float ms = 0.f, mm = 0.f;
+    if ((rc = hip_check(hipEventElapsedTime(&ms, e[0], e[3]), "elapsed"))) return rc;
+    if ((rc = hip_check(hipEventElapsedTime(&mm, e[1], e[2]), "elapsed"))) return rc;
     tot += ms;
+    tmain += mm;
   }
   unsigned long long bins = 0;
   int rc = hip_check(hipMemcpy(&bins, P->bin_counter, sizeof(bins), hipMemcpyDeviceToHost), "read counter");
   if (rc) return rc;
   if (kernel_ms) *kernel_ms = tot;
+  if (main_ms) *main_ms = tmain;
   if (launches) *launches = (int64_t)P->events.size();
   if (bin_templates) *bin_templates = (int64_t)bins;
   if (reset) {
-    for (auto& e : P->events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto& e : P->events)
+      for (auto x : e) (void)hipEventDestroy(x);
     P->events.clear();
     rc = hip_check(hipMemset(P->bin_counter, 0, sizeof(unsigned long long)), "reset counter");
   }

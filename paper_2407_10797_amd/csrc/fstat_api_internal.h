@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <utility>
+#include <array>
 #include <vector>
 
 #include "fstat_kernels.h"
@@ -21,6 +22,7 @@ struct fstat_plan_s {
   int prec = 0;
   int chunk = 2048;                 // bins per work item (both precisions unless tuned)
   int chunk_mixed = 0;              // tuned value for the mixed path (0: use chunk)
+  double refine_budget = 1e-9;     // see fstat_opts.refine_budget
   int grid_mult_fp64 = 1, grid_mult_mixed = 1;   // persistent-grid multiplier
   int blocks_fp64 = 0, blocks_mixed = 0;
   fstat::Grid grid{};
@@ -30,7 +32,7 @@ struct fstat_plan_s {
   struct {
     size_t pc = 0, bounds = 0, cnt = 0, off = 0, total = 0, items = 0, partials = 0, Fl = 0;
     size_t direct = 0, ndirect = 0, tcnt = 0, tcur = 0, toff = 0, tile_items = 0, tile_ctr = 0;
-    size_t xflag = 0, refine = 0, nrefine = 0, rec = 0;
+    size_t xflag = 0, refine = 0, nrefine = 0, rec = 0, xerr = 0;
     size_t params = 0, np = 0, F_hat = 0, F_part = 0;
   } cap;
   struct {
@@ -42,7 +44,7 @@ struct fstat_plan_s {
   PsoState* pso = nullptr;
   // profiling (FSTAT_PROFILE)
   bool profile = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  std::vector<std::array<hipEvent_t, 4>> events;   // stage start, main start, main end, stage end
   unsigned long long* bin_counter = nullptr;
   // learned surrogate (surrogate.hip)
   fstat::Mlp* sur = nullptr;

@@ -189,13 +189,16 @@ __host__ __device__ __forceinline__ void phase_and_tf(const PartConst& P, double
   tf = P.tc + D * (P.mc_hi * y3.hi);
 }
 
-// The same phase unreduced (whole cycles kept, double-double) and t_f: the
-// interpolating bin loop takes phase differences across a work item from it.
-__host__ __device__ __forceinline__ dd phase_full(const PartConst& P, double f, double& tf,
+// The same phase unreduced (whole cycles kept, double-double) and t_f, at a
+// frequency given as double-double: the interpolating bin loop takes phase
+// differences across a work item from it, at node positions between bins,
+// where rounding f to a double would move the phase by t_f * 1e-16 f
+// (~1e-9 cycles at t_f ~ 1e8 s).
+__host__ __device__ __forceinline__ dd phase_full(const PartConst& P, dd f, dd& tf,
                                                   const double* ek = nullptr) {
   FSTAT_NO_CONTRACT
-  dd ft = two_prod(f, P.tc);
-  dd x = dd_mul_d(dd{P.mc_hi, P.mc_lo}, f);
+  dd ft = dd_mul_d(f, P.tc);
+  dd x = dd_mul(dd{P.mc_hi, P.mc_lo}, f);
   double lx = log(x.hi);
   double y0 = exp(lx * (-1.0 / 3.0));
   dd b = dd_mul(dd_mul_d(two_prod(y0, y0), y0), x);
@@ -210,7 +213,7 @@ __host__ __device__ __forceinline__ dd phase_full(const PartConst& P, double f, 
   dd t15 = dd_mul(dd{P.c15_hi, P.c15_lo}, y2);
   dd te;
   if (ek) {
-    te = dd{knot_interp(ek, f), 0.0};
+    te = dd{knot_interp(ek, f.hi), 0.0};
   } else {
     double w0 = exp(lx * (-1.0 / 9.0));
     dd w3 = dd_mul_d(two_prod(w0, w0), w0);
@@ -223,9 +226,12 @@ __host__ __device__ __forceinline__ dd phase_full(const PartConst& P, double f, 
   double t6 = P.c6 * xy2;
   double small = t2 + P.c5 * lnv + t6 * (P.a6k + P.b6 * lnv);
   dd ph = dd_add(dd_add(dd_add(ft, tN), dd_add(t1, t15)), dd_add(te, dd{small, 0.0}));
-  double D = (-5.0 / 3.0) * tN.hi - t1.hi - (2.0 / 3.0) * t15.hi - (1.0 / 3.0) * t2 + P.c5v5 +
-             t6 * (P.a6k + P.b6 + P.b6 * lnv) * (1.0 / 3.0) - (34.0 / 9.0) * te.hi;
-  tf = P.tc + D * (P.mc_hi * y3.hi);
+  // t_f in double-double as well: its rounding (1e-8 s at 1e8 s) would turn
+  // the orbit angle and the 1000-s Doppler term into ~1e-13-cycle noise
+  dd D = dd_add(dd_add(dd_mul_d(tN, -5.0 / 3.0), dd{-t1.hi, -t1.lo}),
+                dd_add(dd_mul_d(t15, -2.0 / 3.0), dd_mul_d(te, -34.0 / 9.0)));
+  D = dd_add(D, dd{-(1.0 / 3.0) * t2 + P.c5v5 + t6 * (P.a6k + P.b6 + P.b6 * lnv) * (1.0 / 3.0), 0.0});
+  tf = dd_add(dd{P.tc, 0.0}, dd_mul(D, dd_mul(dd{P.mc_hi, P.mc_lo}, y3)));
   return ph;
 }
 
@@ -448,21 +454,26 @@ __device__ __forceinline__ void template_fp64(const PartConst& P, double f, doub
   response_fp64(P, f, s0, c0, d, tpr, tpi, txr, txi);
 }
 
-// The template at an arbitrary frequency (an interpolation node): the whole
-// phase Phi / (2 pi) = Psi / (2 pi) + f k.p_1 in cycles (double-double, not
-// reduced) and the transfer without the Doppler factor.
-__device__ __forceinline__ dd template_node(const PartConst& P, double f, const double* ek,
+// The template at an arbitrary frequency fd (double-double; an interpolation
+// node): the whole phase Phi / (2 pi) = Psi / (2 pi) + f k.p_1 in cycles
+// (double-double, not reduced) and the transfer without the Doppler factor.
+__device__ __forceinline__ dd template_node(const PartConst& P, dd fd, const double* ek,
                                             double& tpr, double& tpi, double& txr, double& txi) {
-  double tf;
-  dd ph = phase_full(P, f, tf, ek);
+  dd tf;
+  dd ph = phase_full(P, fd, tf, ek);
+  const double f = fd.hi;
   double sa, ca;
-  sincospi(2.0 * tf * (1.0 / kYear), &sa, &ca);
+  {
+    FSTAT_NO_CONTRACT
+    const dd turns = dd_mul_d(tf, 1.0 / kYear);     // orbit angle in turns, reduced exactly
+    sincospi(2.0 * ((turns.hi - floor(turns.hi)) + turns.lo), &sa, &ca);
+  }
   double d[3][3];
   double kp1 = k_dot_p1(P, ca, sa, d);
   double s0, c0;
   sincospi(kLs * f, &s0, &c0);
   response_fp64(P, f, s0, c0, d, tpr, tpi, txr, txi);
-  return dd_add(ph, two_prod(f, kp1));
+  return dd_add(ph, dd_mul_d(fd, kp1));
 }
 
 // ---- per-partition solve (2x2 Hermitian closed form) --------------------------

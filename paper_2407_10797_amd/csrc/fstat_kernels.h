@@ -43,7 +43,8 @@ struct WorkSpace {
   int32_t* tile_items;  // [capacity] item indices grouped by bin tile
   int32_t* tile_ctr;  // [1] next tile to take (dynamic schedule)
   uint8_t* xflag;     // [capacity] 1: item evaluated by the exact kernel
-  double* rec;        // [capacity][52] per-item interpolation records
+  double* rec;        // [capacity][53] per-item interpolation records
+  float* xerr;        // [capacity] end-point error of each interpolated item
   int32_t* refine;    // [capacity] interpolated items of ill-conditioned partitions
   int32_t* nrefine;   // [1]
 };
@@ -59,11 +60,11 @@ void launch_setup(const Grid& g, const double* params, int64_t n,
 void launch_worklist(int64_t m, const WorkSpace& ws, hipStream_t s);
 int interp_tables_init();
 int interp_max_tile(bool mixed);   // largest tile (bins) the LDS-staged loop accepts
-constexpr int kInterpRec = 52;     // doubles per interpolation record
-void launch_eval(bool mixed, bool interp, const Grid& g, int64_t n_particles, int32_t stride,
-                 int32_t chunk,
+constexpr int kInterpRec = 53;     // doubles per interpolation record
+void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
+                 int64_t n_particles, int32_t stride, int32_t chunk,
                  const WorkSpace& ws, BinData<double> b, BinData<float> b32, const double* ek,
-                 int blocks, hipStream_t s);
+                 int blocks, hipStream_t s, hipEvent_t* ev_main = nullptr);
 void launch_sur_data(uint64_t seed, int64_t n, float* X, float* T, hipStream_t s);
 void launch_sur_knots(const Grid& g, int32_t stride, int64_t n, int64_t rows, const WorkSpace& ws,
                       float* X, hipStream_t s);

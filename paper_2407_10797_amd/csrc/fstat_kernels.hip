@@ -477,8 +477,9 @@ __global__ __launch_bounds__(256) void k_eval_mixed(Grid g,
 // than 1e-12 cycles (phase; the exact phase itself carries ~1e-13) or 2e-13 of
 // the largest transfer component, or that has fewer than kMinInterp bins,
 // goes to the exact per-bin kernels (sel list).
-// An error e in the template moves F by up to cond(M) e, so partitions whose
-// matrix has cond > kRefineCond are evaluated again exactly (k_mark).
+// An error e in the template moves F by up to 2 cond(M) e, so partitions
+// where that could exceed the plan's refinement budget (default 1e-9,
+// relative) are evaluated again exactly (k_mark).
 // Node evaluation packs 5 items x 12 points onto one wavefront's lanes.
 constexpr int kCheb = 10;
 constexpr int kLanesItem = kCheb + 2;
@@ -486,7 +487,6 @@ constexpr int kItemsWave = 5;
 constexpr int kMinInterp = 32;
 constexpr double kInterpTolPhase = 1e-12;
 constexpr double kInterpTolT = 2e-13;
-constexpr double kRefineCond = 1e3;
 
 __constant__ double c_cheb_s[kCheb];          // nodes cos(pi (k + 1/2) / 10)
 __constant__ double c_cheb_G[kCheb][kCheb];   // node value k -> coefficient of s^n
@@ -508,8 +508,9 @@ __device__ __forceinline__ T horner(const T* c, T s) {
 }
 
 // Per-item interpolation record: monomial coefficients of R, Re T''_+,
-// Im T''_+, Re T''_x, Im T''_x (kCheb each), then A = frac(Phi_0), B' = B - rint(B).
-constexpr int kRec = 5 * kCheb + 2;
+// Im T''_+, Re T''_x, Im T''_x (kCheb each), then A = frac(Phi_0),
+// B' = B - rint(B) and B.
+constexpr int kRec = 5 * kCheb + 3;
 static_assert(kRec == kInterpRec && kRec <= 64, "record layout");
 
 // Node values, coefficients and end-point check of every work item (all
@@ -524,6 +525,7 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
                                                       const double* __restrict__ ek,
                                                       double* __restrict__ rec,
                                                       uint8_t* __restrict__ xflag,
+                                                      float* __restrict__ xerr,
                                                       int32_t* __restrict__ direct,
                                                       int32_t* __restrict__ ndirect) {
   const int lane = threadIdx.x & 63;
@@ -546,7 +548,8 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
     const double* ekq = (ek && P.sur) ? ek + 8 * (int64_t)it.x : nullptr;
     const double sk = k < kCheb ? c_cheb_s[k] : (k == kCheb ? -1.0 : 1.0);
     const double mk = (sk + 1.0) * 0.5 * (double)(nb > 1 ? nb - 1 : 0);
-    const double f = ((double)(g.k_lo + b0) + mk) * g.df;
+    // exact frequency (k_lo + b0 + mk) df of the node, as double-double
+    const dd f = dd_add(two_prod((double)(g.k_lo + b0), g.df), two_prod(mk, g.df));
     double v[5];
     const dd ph = template_node(P, f, ekq, v[1], v[2], v[3], v[4]);
     const double p0h = __shfl(ph.hi, base + kCheb, 64);
@@ -577,13 +580,21 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
       }
     }
     bool bad = false;
+    double err = 0.0;           // relative template error at this end point
     if (k >= kCheb) {
       const double* e = (k == kCheb) ? emin : eplu;
-      bad = !(fabs(e[0] - v[0]) <= kInterpTolPhase);
+      const double dph = fabs(e[0] - v[0]);
+      bad = !(dph <= kInterpTolPhase);
+      err = 2.0 * kPi * dph;
 #pragma unroll
-      for (int fn = 1; fn < 5; ++fn) bad = bad || !(fabs(e[fn] - v[fn]) <= kInterpTolT * tmax);
+      for (int fn = 1; fn < 5; ++fn) {
+        const double d = fabs(e[fn] - v[fn]);
+        bad = bad || !(d <= kInterpTolT * tmax);
+        err = fmax(err, d / tmax);
+      }
     }
     const uint64_t badmask = __ballot(bad);
+    err = fmax(err, __shfl(err, base + kCheb + 1, 64));
     const bool mine = lane - base < kLanesItem && grp * kItemsWave + q < W;   // not a repeat lane
     if (!mine) continue;
     const bool rej = nb < kMinInterp || ((badmask >> base) & ((1ull << kLanesItem) - 1ull)) != 0ull;
@@ -595,7 +606,9 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
       FSTAT_NO_CONTRACT
       r[5 * kCheb] = (p0h - floor(p0h)) + p0l;   // fractional cycle at the first bin
       r[5 * kCheb + 1] = B - rint(B);            // whole cycles per bin drop out (m is an integer)
+      r[5 * kCheb + 2] = B;
       xflag[w] = rej ? 1 : 0;
+      xerr[w] = (float)err;
       if (rej) direct[atomicAdd(ndirect, 1)] = w;
     }
   }
@@ -667,6 +680,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
       for (int n = 0; n < kCheb; ++n) cR[n] = __shfl(mine, n, 64);
       const double A = __shfl(mine, 5 * kCheb, 64);
       const double Bp = __shfl(mine, 5 * kCheb + 1, 64);
+      const double Bf = __shfl(mine, 5 * kCheb + 2, 64);
       const double alpha = 2.0 / (double)(nb - 1);
       const int e0 = b0 - j0;            // LDS offset of the item's first bin
       if constexpr (!MIXED) {
@@ -678,10 +692,19 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         double acc[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) acc[i] = 0.0;
+        // The grid is f_j = (k_lo + j) df rounded to a double; the interpolants
+        // are exact in f, so the phase moves by (dPhi/df)(f_j - exact) =
+        // -(B / df) e_j, with e_j the rounding error of the product (from an
+        // FMA): up to ~1e-9 cycles at t_f ~ 1e8 s.
+        const double kB = -Bf / g.df;
+        const double j00 = (double)(g.k_lo + b0);
         for (int mi = lane; mi < nb; mi += 64) {
           const double m = (double)mi;
           const double s = fma(alpha, m, -1.0);
-          double ph = fma(Bp, m, horner(cR, s)) + A;
+          const double jd = j00 + m;
+          const double fj = jd * g.df;
+          const double ej = fma(jd, g.df, -fj);
+          double ph = fma(Bp, m, horner(cR, s)) + fma(kB, ej, A);
           ph -= rint(ph);
           double sps, cps;
           sincos_turns(ph, sps, cps);
@@ -751,13 +774,16 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
   }
 }
 
-// Partitions of interpolated items whose matrix has cond(M) > thr: their
-// interpolated items are listed for exact evaluation (the sums are formed as
-// in k_solve; the eigenvalues of the 2x2 Hermitian form give the condition).
+// Partitions whose interpolation error could move F by more than `budget`
+// (relative): 2 cond(M) e_max > budget, with e_max the largest end-point
+// error of their interpolated items; those items are listed for exact
+// evaluation (the sums are formed as in k_solve; the eigenvalues of the 2x2
+// Hermitian form give the condition).
 __global__ void k_mark(const PartConst* __restrict__ pc, int64_t n, int32_t stride,
                        const int32_t* __restrict__ cnt, const int32_t* __restrict__ off,
                        const double* __restrict__ partials, const uint8_t* __restrict__ xflag,
-                       double thr, int32_t* __restrict__ refine, int32_t* __restrict__ nrefine) {
+                       const float* __restrict__ xerr, double budget,
+                       int32_t* __restrict__ refine, int32_t* __restrict__ nrefine) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n * stride) return;
   int64_t p = q / stride;
@@ -766,7 +792,12 @@ __global__ void k_mark(const PartConst* __restrict__ pc, int64_t n, int32_t stri
   if (l >= P.np || P.status != kStatusOk) return;
   const int o = off[q], c = cnt[q];
   int ninterp = 0;
-  for (int i = 0; i < c; ++i) ninterp += xflag[o + i] == 0;
+  double emax = 1e-16;
+  for (int i = 0; i < c; ++i)
+    if (xflag[o + i] == 0) {
+      ++ninterp;
+      emax = fmax(emax, (double)xerr[o + i]);
+    }
   if (ninterp == 0) return;
   double a[8], e[8];
   for (int k = 0; k < 8; ++k) a[k] = e[k] = 0.0;
@@ -782,7 +813,8 @@ __global__ void k_mark(const PartConst* __restrict__ pc, int64_t n, int32_t stri
   const double hs = 0.5 * (Pm + Qm), hd = 0.5 * (Pm - Qm);
   const double lp = hs + sqrt(hd * hd + rr * rr + ri * ri);
   const double lm = (Pm * Qm - (rr * rr + ri * ri)) / lp;
-  if (!(lp > 0.0) || !(lm > lp / thr)) {
+  // F moves by up to 2 cond(M) e for a relative template error e
+  if (!(lp > 0.0) || !(2.0 * emax * lp <= budget * lm)) {
     int at = atomicAdd(nrefine, ninterp);
     for (int i = 0; i < c; ++i)
       if (xflag[o + i] == 0) refine[at++] = o + i;
@@ -1151,9 +1183,10 @@ void launch_worklist(int64_t m, const WorkSpace& ws, hipStream_t s) {
 
 int interp_max_tile(bool mixed) { return mixed ? 4096 : 2048; }
 
-void launch_eval(bool mixed, bool interp, const Grid& g, int64_t n_particles, int32_t stride,
-                 int32_t chunk, const WorkSpace& ws, BinData<double> b, BinData<float> b32,
-                 const double* ek, int blocks, hipStream_t s) {
+void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
+                 int64_t n_particles, int32_t stride, int32_t chunk, const WorkSpace& ws,
+                 BinData<double> b, BinData<float> b32, const double* ek, int blocks,
+                 hipStream_t s, hipEvent_t* ev_main) {
   const int32_t* sel = nullptr;
   const int32_t* nsel = nullptr;
   if (!interp) hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(64), 0, s, ws.total, ws.ndirect);
@@ -1167,8 +1200,10 @@ void launch_eval(bool mixed, bool interp, const Grid& g, int64_t n_particles, in
     hipLaunchKernelGGL(k_tile_scatter, dim3(1024), dim3(256), 0, s, ws.items, ws.total, ws.bounds,
                        stride, chunk, ws.toff, ws.tcur, ws.tile_items);
     hipLaunchKernelGGL(k_interp_nodes, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
-                       ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.direct, ws.ndirect);
+                       ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.xerr, ws.direct,
+                       ws.ndirect);
     const size_t lds = 3 * (size_t)chunk * (mixed ? sizeof(float) : sizeof(double));
+    if (ev_main) (void)hipEventRecord(ev_main[0], s);
     if (mixed)
       hipLaunchKernelGGL(k_eval_interp<true>, dim3(blocks), dim3(256), lds, s, g, ws.bounds, stride,
                          ws.items, chunk, ws.tile_items, ws.toff, ntiles, ws.tile_ctr, b.wr, b.wi,
@@ -1177,6 +1212,7 @@ void launch_eval(bool mixed, bool interp, const Grid& g, int64_t n_particles, in
       hipLaunchKernelGGL(k_eval_interp<false>, dim3(blocks), dim3(256), lds, s, g, ws.bounds,
                          stride, ws.items, chunk, ws.tile_items, ws.toff, ntiles, ws.tile_ctr,
                          b.wr, b.wi, b.u, b32.wr, b32.wi, b32.u, ws.rec, ws.xflag, ws.partials);
+    if (ev_main) (void)hipEventRecord(ev_main[1], s);
     sel = ws.direct;
     nsel = ws.ndirect;
   }
@@ -1190,12 +1226,15 @@ void launch_eval(bool mixed, bool interp, const Grid& g, int64_t n_particles, in
                          ws.items, ws.total, chunk, b.wr, b.wi, b.u, b.s0, b.c0, ek, ws.partials,
                          list, count);
   };
+  if (!interp && ev_main) (void)hipEventRecord(ev_main[0], s);
   exact_pass(sel, nsel);
-  if (interp && !mixed) {
+  if (!interp && ev_main) (void)hipEventRecord(ev_main[1], s);
+  if (interp && !mixed && refine_budget > 0.0) {
     // the mixed path's bar (1e-4 + 1e-6 cond) already covers the interpolation error
     const int64_t m = (int64_t)n_particles * stride;
     hipLaunchKernelGGL(k_mark, dim3(nblk(m, 256)), dim3(256), 0, s, ws.pc, n_particles, stride,
-                       ws.cnt, ws.off, ws.partials, ws.xflag, kRefineCond, ws.refine, ws.nrefine);
+                       ws.cnt, ws.off, ws.partials, ws.xflag, ws.xerr, refine_budget, ws.refine,
+                       ws.nrefine);
     exact_pass(ws.refine, ws.nrefine);
   }
 }

@@ -42,7 +42,8 @@ class fstat_data_desc(ctypes.Structure):
 
 class fstat_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("refine_budget", ctypes.c_double)]
 
 
 class pso_stage_desc(ctypes.Structure):
@@ -92,11 +93,13 @@ def lib() -> ctypes.CDLL:
         L.pso_stage.argtypes = [vp, ctypes.POINTER(pso_stage_desc), ctypes.POINTER(pso_result), vp]
         L.pso_stage.restype = ctypes.c_int
         L.fstat_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
-                                         ctypes.POINTER(i64), ctypes.POINTER(i64)]
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
+                                         ctypes.POINTER(i64)]
         L.fstat_profile_read.restype = ctypes.c_int
         L.fstat_mlp_grad.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double), vp, vp]
         L.fstat_mlp_grad.restype = ctypes.c_int
-        L.fstat_interp_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
+        L.fstat_interp_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                         ctypes.POINTER(i64), vp]
         L.fstat_interp_stats.restype = ctypes.c_int
         L.fstat_mlp_forward.argtypes = [vp, vp, i64, vp]
         L.fstat_mlp_forward.restype = ctypes.c_int
@@ -148,10 +151,10 @@ def pso_stage(plan, desc: pso_stage_desc, result: pso_result, stream=None):
 
 
 def fstat_profile_read(plan, reset: bool = True):
-    ms, n, bins = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
-    _check(lib().fstat_profile_read(plan, int(reset), ctypes.byref(ms), ctypes.byref(n),
-                                    ctypes.byref(bins)))
-    return ms.value, n.value, bins.value
+    ms, mm, n, bins = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().fstat_profile_read(plan, int(reset), ctypes.byref(ms), ctypes.byref(mm),
+                                    ctypes.byref(n), ctypes.byref(bins)))
+    return ms.value, mm.value, n.value, bins.value
 
 
 def fstat_mlp_grad(params, x, t):
@@ -169,9 +172,10 @@ def fstat_mlp_grad(params, x, t):
 
 
 def fstat_interp_stats(plan, stream=None):
-    items, exact = ctypes.c_int64(), ctypes.c_int64()
-    _check(lib().fstat_interp_stats(plan, ctypes.byref(items), ctypes.byref(exact), stream))
-    return items.value, exact.value
+    items, rej, ref = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().fstat_interp_stats(plan, ctypes.byref(items), ctypes.byref(rej), ctypes.byref(ref),
+                                    stream))
+    return items.value, rej.value, ref.value
 
 
 def fstat_mlp_forward(params, x):
@@ -224,7 +228,8 @@ class Plan:
     """A plan over one data set, with inputs kept resident in device memory."""
 
     def __init__(self, data, psd, T_obs: float, df: float, k_lo: int,
-                 precision: int = 0, chunk: int = 0, profile: bool = False):
+                 precision: int = 0, chunk: int = 0, profile: bool = False,
+                 refine_budget: float = 0.0):
         torch = _torch()
         dev = torch.device("cuda")
         d = torch.as_tensor(np.ascontiguousarray(data, dtype=np.complex128)
@@ -236,7 +241,7 @@ class Plan:
         desc = fstat_data_desc(self.T_obs, self.df, self.k_lo, self.nbins,
                                d.data_ptr(), p.data_ptr())
         opts = fstat_opts(int(precision), FSTAT_DEVICE_PTRS | (FSTAT_PROFILE if profile else 0),
-                          int(chunk), 0)
+                          int(chunk), 0, float(refine_budget))
         self.handle = fstat_plan_create(desc, opts, _stream())
         torch.cuda.current_stream().synchronize()
 
@@ -316,7 +321,8 @@ class Plan:
         return fstat_autotune(self.handle, prm.data_ptr(), prm.shape[0], int(np_parts), flags, _stream())
 
     def interp_stats(self):
-        """(work items, items evaluated exactly per bin) of the last evaluation."""
+        """(work items, items handed to the exact loop, items refined exactly) of
+        the last evaluation."""
         return fstat_interp_stats(self.handle, _stream())
 
     def surrogate_stats(self):
@@ -325,7 +331,8 @@ class Plan:
         return fstat_surrogate_stats(self.handle)
 
     def profile_read(self, reset: bool = True):
-        """(bin-loop kernel ms total, launches, bin-template evaluations)."""
+        """(bin-loop stage ms, its main kernel ms, evaluations, bin-template
+        evaluations), totals since the last reset."""
         return fstat_profile_read(self.handle, reset)
 
     def close(self):

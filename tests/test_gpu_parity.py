@@ -84,11 +84,12 @@ def test_interpolating_and_exact_bin_loops_agree(small, torch_cuda, npart):
     _, _, cond = O.fstat(s["data"], s["psd"], s["g"].k_lo, s["g"].df, s["g"].T_obs, s["pts"],
                          [npart], want_cond=True)
     F, P = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, want_parts=True)
-    items, exact_items = s["plan"].interp_stats()
+    items, rej, ref = s["plan"].interp_stats()
     Fe, Pe = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, want_parts=True, exact=True)
-    items_e, exact_e = s["plan"].interp_stats()
-    print(f"[interp] Np={npart}: {items} items, {exact_items} evaluated exactly", flush=True)
-    assert items == items_e and exact_e == items_e
+    items_e, rej_e, ref_e = s["plan"].interp_stats()
+    print(f"[interp] Np={npart}: {items} items, {rej} handed to the exact loop, {ref} refined",
+          flush=True)
+    assert items == items_e and rej_e == items_e and ref_e == 0
     P, Pe = P.cpu().numpy(), Pe.cpu().numpy()
     c = np.where(np.isfinite(cond[:, :npart]), cond[:, :npart], 0.0)
     r = _rel(P[:, :npart], Pe[:, :npart])
