@@ -72,6 +72,8 @@ int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride, int chunk) {
   if ((rc = ensure(&P->ws.off, &P->cap.off, m, "alloc off"))) return rc;
   if ((rc = ensure(&P->ws.Fl, &P->cap.Fl, m, "alloc Fl"))) return rc;
   if ((rc = ensure(&P->ws.total, &P->cap.total, 1, "alloc total"))) return rc;
+  if (m > (size_t)4096 * 4096) return set_error(FSTAT_EINVAL, "n * stride above 16.7M partitions");
+  if ((rc = ensure(&P->ws.bsum, &P->cap.bsum, (m + 4095) / 4096, "alloc scan sums"))) return rc;
   if ((rc = ensure(&P->ws.items, &P->cap.items, cap_items, "alloc items"))) return rc;
   if ((rc = ensure(&P->ws.partials, &P->cap.partials, cap_items * 8, "alloc partials"))) return rc;
   if ((rc = ensure(&P->ws.direct, &P->cap.direct, cap_items, "alloc direct"))) return rc;
@@ -365,7 +367,7 @@ void fstat_plan_destroy(fstat_plan_t P) {
   dev_free(P->b32.s0); dev_free(P->b32.c0);
   dev_free(P->ws.pc); dev_free(P->ws.bounds); dev_free(P->ws.cnt); dev_free(P->ws.off);
   dev_free(P->ws.total); dev_free(P->ws.items); dev_free(P->ws.partials); dev_free(P->ws.Fl);
-  dev_free(P->ws.direct); dev_free(P->ws.ndirect);
+  dev_free(P->ws.direct); dev_free(P->ws.ndirect); dev_free(P->ws.bsum);
   dev_free(P->ws.tcnt); dev_free(P->ws.tcur); dev_free(P->ws.toff); dev_free(P->ws.tile_items);
   dev_free(P->ws.tile_ctr); dev_free(P->ws.xflag); dev_free(P->ws.rec); dev_free(P->ws.xerr); dev_free(P->ws.refine); dev_free(P->ws.nrefine);
   dev_free(P->io.params); dev_free(P->io.np); dev_free(P->io.F_hat); dev_free(P->io.F_part);

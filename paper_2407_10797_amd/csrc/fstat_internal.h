@@ -222,10 +222,14 @@ __host__ __device__ __forceinline__ dd phase_full(const PartConst& P, dd f, dd& 
     te = dd_mul(dd_mul(dd{P.ce_hi, P.ce_lo}, dd_mul(dd_mul(y5, y5), y)), w);
   }
   double lnv = P.ln_vfac + lx * (1.0 / 3.0);
-  double t2 = P.c2 * y.hi;
+  // the alpha_4 term reaches ~1e2 cycles: double-double too, so that its
+  // rounding does not add ~1e-14-cycle noise between interpolation nodes
+  dd t2d = dd_mul_d(y, P.c2);
+  double t2 = t2d.hi;
   double t6 = P.c6 * xy2;
-  double small = t2 + P.c5 * lnv + t6 * (P.a6k + P.b6 * lnv);
-  dd ph = dd_add(dd_add(dd_add(ft, tN), dd_add(t1, t15)), dd_add(te, dd{small, 0.0}));
+  double small = P.c5 * lnv + t6 * (P.a6k + P.b6 * lnv);
+  dd ph = dd_add(dd_add(dd_add(ft, tN), dd_add(t1, t15)),
+                 dd_add(te, dd_add(t2d, dd{small, 0.0})));
   // t_f in double-double as well: its rounding (1e-8 s at 1e8 s) would turn
   // the orbit angle and the 1000-s Doppler term into ~1e-13-cycle noise
   dd D = dd_add(dd_add(dd_mul_d(tN, -5.0 / 3.0), dd{-t1.hi, -t1.lo}),
@@ -324,29 +328,28 @@ __host__ __device__ __forceinline__ double sinc_from(double num, double den) {
 
 // sin(2 pi r) and cos(2 pi r) for |r| <= 1/2 turn: quarter-turn reduction
 // x = r - n/4 (exact), |2 pi x| <= pi/4, then the Taylor series of sin to
-// theta^15 and of cos to theta^16 (remainders below 1e-16), and the quarter
-// turns n applied by swapping and negating.
+// theta^15 and of cos to theta^16 (remainders below 1e-16; the polynomials
+// in theta^2 evaluated in Estrin form), and the quarter turns n applied by
+// swapping and negating.
 __device__ __forceinline__ void sincos_turns(double r, double& s, double& c) {
   const double n = rint(4.0 * r);
   const double x = fma(-0.25, n, r);
   const double th = x * 6.283185307179586477;
   const double z = th * th;
-  double ps = -1.0 / 1307674368000.0;                // -1/15!
-  ps = fma(ps, z, 1.0 / 6227020800.0);               //  1/13!
-  ps = fma(ps, z, -1.0 / 39916800.0);                // -1/11!
-  ps = fma(ps, z, 1.0 / 362880.0);                   //  1/9!
-  ps = fma(ps, z, -1.0 / 5040.0);                    // -1/7!
-  ps = fma(ps, z, 1.0 / 120.0);                      //  1/5!
-  ps = fma(ps, z, -1.0 / 6.0);                       // -1/3!
+  const double z2 = z * z, z4 = z2 * z2;
+  // sin: th + th z (S1 + S2 z + ... + S7 z^6), S_k = (-1)^k / (2k+1)!  (Estrin form)
+  const double s01 = fma(1.0 / 120.0, z, -1.0 / 6.0);
+  const double s23 = fma(1.0 / 362880.0, z, -1.0 / 5040.0);
+  const double s45 = fma(1.0 / 6227020800.0, z, -1.0 / 39916800.0);
+  const double s6 = -1.0 / 1307674368000.0;
+  const double ps = fma(fma(s6, z2, s45), z4, fma(s23, z2, s01));
   const double sn = fma(th * z, ps, th);
-  double pc = 1.0 / 20922789888000.0;                //  1/16!
-  pc = fma(pc, z, -1.0 / 87178291200.0);             // -1/14!
-  pc = fma(pc, z, 1.0 / 479001600.0);                //  1/12!
-  pc = fma(pc, z, -1.0 / 3628800.0);                 // -1/10!
-  pc = fma(pc, z, 1.0 / 40320.0);                    //  1/8!
-  pc = fma(pc, z, -1.0 / 720.0);                     // -1/6!
-  pc = fma(pc, z, 1.0 / 24.0);                       //  1/4!
-  pc = fma(pc, z, -0.5);                             // -1/2!
+  // cos: 1 + z (C1 + C2 z + ... + C8 z^7), C_k = (-1)^k / (2k)!
+  const double c01 = fma(1.0 / 24.0, z, -0.5);
+  const double c23 = fma(1.0 / 40320.0, z, -1.0 / 720.0);
+  const double c45 = fma(1.0 / 479001600.0, z, -1.0 / 3628800.0);
+  const double c67 = fma(1.0 / 20922789888000.0, z, -1.0 / 87178291200.0);
+  const double pc = fma(fma(c67, z2, c45), z4, fma(c23, z2, c01));
   const double cs = fma(z, pc, 1.0);
   const int q = ((int)n) & 3;
   const double a = (q & 1) ? cs : sn;

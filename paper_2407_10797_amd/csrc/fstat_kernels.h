@@ -32,6 +32,7 @@ struct WorkSpace {
   int32_t* cnt;       // [n][stride]
   int32_t* off;       // [n][stride]
   int32_t* total;     // [1]
+  int32_t* bsum;      // [ceil(n stride / 4096)] block sums of the count scan
   int2* items;        // [capacity]
   double* partials;   // [capacity][8]
   double* Fl;         // [n][stride]

@@ -5,7 +5,7 @@
 //   k_setup   one thread per particle: intrinsic parameters -> PN constants,
 //             sky frame, support [f_lo, f_hi] (bisection on t_f), Np partition
 //             boundaries (bin indices) and work-item counts per partition
-//   k_scan    exclusive scan of the work-item counts (one block)
+//   k_scan_*  exclusive scan of the work-item counts (three passes)
 //   k_fill    work list: item -> (particle*stride + partition, chunk)
 //   k_eval_*  persistent grid, one wavefront per work item: for every bin of the
 //             chunk evaluate phase, t_f, TDI-X response and accumulate the eight
@@ -203,28 +203,80 @@ __global__ void k_setup(Grid g, const double* __restrict__ params, int64_t n,
   }
 }
 
-// exclusive scan of cnt[m] into off[m]; total -> *total (single block)
-__global__ void k_scan(const int32_t* __restrict__ cnt, int64_t m, int32_t* __restrict__ off,
-                       int32_t* __restrict__ total, int32_t* __restrict__ ndirect,
-                       int32_t* __restrict__ nrefine) {
-  __shared__ int64_t part[1024];
-  int t = threadIdx.x, T = blockDim.x;
-  int64_t per = (m + T - 1) / T;
-  int64_t a = t * per, b = a + per < m ? a + per : m;
-  int64_t s = 0;
-  for (int64_t i = a; i < b; ++i) s += cnt[i];
-  part[t] = s;
+// Exclusive scan of cnt[m] into off[m] in three passes over blocks of
+// kScanBlock counts: block sums, a one-block scan of the sums (which also
+// writes *total and clears the exact-path counters), then each block's local
+// scan plus its offset.
+constexpr int kScanBlock = 4096;   // counts per block (1024 threads x 4)
+
+__device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t* sh, int32_t& total) {
+  // inclusive scan across the 1024 threads of the block (Hillis-Steele in LDS)
+  const int t = threadIdx.x;
+  sh[t] = x;
   __syncthreads();
-  if (t == 0) {
-    int64_t run = 0;
-    for (int i = 0; i < T; ++i) { int64_t v = part[i]; part[i] = run; run += v; }
-    total[0] = (int32_t)run;
+  for (int o = 1; o < 1024; o <<= 1) {
+    int32_t y = t >= o ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += y;
+    __syncthreads();
+  }
+  total = sh[1023];
+  int32_t r = sh[t] - x;
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(const int32_t* __restrict__ cnt, int64_t m,
+                                                    int32_t* __restrict__ bsum) {
+  __shared__ int32_t red[1024];
+  const int64_t i0 = (int64_t)blockIdx.x * kScanBlock + 4 * threadIdx.x;
+  int32_t v = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v += (i0 + e < m) ? cnt[i0 + e] : 0;
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+// nb <= 1024 * 4 block sums (m <= 16.7M counts), one block
+__global__ __launch_bounds__(1024) void k_scan_top(int32_t* __restrict__ bsum, int32_t nb,
+                                                   int32_t* __restrict__ total,
+                                                   int32_t* __restrict__ ndirect,
+                                                   int32_t* __restrict__ nrefine) {
+  __shared__ int32_t sh[1024];
+  const int i0 = 4 * threadIdx.x;
+  int32_t v[4], x = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) { v[e] = (i0 + e < nb) ? bsum[i0 + e] : 0; x += v[e]; }
+  int32_t tot;
+  int32_t run = block_excl_scan(x, sh, tot);
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (i0 + e < nb) { bsum[i0 + e] = run; run += v[e]; }
+  if (threadIdx.x == 0) {
+    total[0] = tot;
     ndirect[0] = 0;
     nrefine[0] = 0;
   }
-  __syncthreads();
-  int64_t run = part[t];
-  for (int64_t i = a; i < b; ++i) { off[i] = (int32_t)run; run += cnt[i]; }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__ cnt, int64_t m,
+                                                     const int32_t* __restrict__ bsum,
+                                                     int32_t* __restrict__ off) {
+  __shared__ int32_t sh[1024];
+  const int64_t i0 = (int64_t)blockIdx.x * kScanBlock + 4 * threadIdx.x;
+  int32_t v[4], x = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) { v[e] = (i0 + e < m) ? cnt[i0 + e] : 0; x += v[e]; }
+  int32_t tot;
+  int32_t run = block_excl_scan(x, sh, tot) + bsum[blockIdx.x];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (i0 + e < m) { off[i0 + e] = run; run += v[e]; }
 }
 
 __global__ void k_fill(const int32_t* __restrict__ cnt, const int32_t* __restrict__ off, int64_t m,
@@ -249,6 +301,31 @@ __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
+}
+
+// Sums of eight per-lane values over the wavefront in 10 exchanges instead of
+// 8 x 6: each step hands half of the remaining values to the partner lane
+// (xor 32, 16, 8), then the last value is summed over lanes xor 4, 2, 1.
+// Returns the total of value number idx = 4 b5 + 2 b4 + b3 (b = lane bits);
+// lanes with (lane & 7) == 0 hold the eight distinct totals.  Fixed order.
+__device__ __forceinline__ double wave_sum8(const double* a, int lane, int& idx) {
+  const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
+  double b[4], c[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double keep = h5 ? a[4 + i] : a[i], give = h5 ? a[i] : a[4 + i];
+    b[i] = keep + __shfl_xor(give, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double keep = h4 ? b[2 + i] : b[i], give = h4 ? b[i] : b[2 + i];
+    c[i] = keep + __shfl_xor(give, 16, 64);
+  }
+  double d = (h3 ? c[1] : c[0]) + __shfl_xor(h3 ? c[0] : c[1], 8, 64);
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+  idx = (h5 ? 4 : 0) + (h4 ? 2 : 0) + (h3 ? 1 : 0);
+  return d;
 }
 
 __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
@@ -491,6 +568,12 @@ constexpr double kInterpTolT = 2e-13;
 __constant__ double c_cheb_s[kCheb];          // nodes cos(pi (k + 1/2) / 10)
 __constant__ double c_cheb_G[kCheb][kCheb];   // node value k -> coefficient of s^n
 __constant__ double c_cheb_E[2][kCheb];       // node value k -> interpolant at s = -1, +1
+// The mixed path's transfer interpolants: the Chebyshev series truncated
+// after degree kDegT (its error, a few 1e-10 at 2048 bins, is far below FP32
+// rounding), as monomials, and their values at s = -1, +1.
+constexpr int kDegT = 6;
+__constant__ double c_cheb_G6[kCheb][kDegT + 1];
+__constant__ double c_cheb_E6[2][kCheb];
 
 __device__ __forceinline__ double readlane_d(double x, int l) {
   int2 v = *reinterpret_cast<int2*>(&x);
@@ -507,14 +590,43 @@ __device__ __forceinline__ T horner(const T* c, T s) {
   return r;
 }
 
-// Per-item interpolation record: monomial coefficients of R, Re T''_+,
-// Im T''_+, Re T''_x, Im T''_x (kCheb each), then A = frac(Phi_0),
-// B' = B - rint(B) and B.
+template <int D, typename T>
+__device__ __forceinline__ T horner_n(const T* c, T s) {
+  T r = c[D];
+#pragma unroll
+  for (int n = D - 1; n >= 0; --n) r = r * s + c[n];
+  return r;
+}
+
+// The same degree-9 polynomial by Estrin's scheme, with the powers s^2, s^4,
+// s^8 shared by the five polynomials of a bin: 9 FMAs as in Horner's rule,
+// but a dependency depth of 4 instead of 9.
+static_assert(kCheb == 10, "estrin9 is written for degree 9");
+__device__ __forceinline__ double estrin9(const double* c, double s, double s2, double s4,
+                                          double s8) {
+  const double q01 = fma(c[1], s, c[0]), q23 = fma(c[3], s, c[2]);
+  const double q45 = fma(c[5], s, c[4]), q67 = fma(c[7], s, c[6]);
+  const double q89 = fma(c[9], s, c[8]);
+  const double a = fma(q23, s2, q01), b = fma(q67, s2, q45);
+  return fma(q89, s8, fma(b, s4, a));
+}
+
+// Per-item interpolation record: monomial coefficients of R (kCheb), then of
+// Re T''_+, Im T''_+, Re T''_x, Im T''_x (nT each: kCheb, or kDegT + 1 on the
+// mixed path), then A = frac(Phi_0), B' = B - rint(B) and B.
 constexpr int kRec = 5 * kCheb + 3;
 static_assert(kRec == kInterpRec && kRec <= 64, "record layout");
+template <bool MIXED> struct RecLayout {
+  static constexpr int nT = MIXED ? kDegT + 1 : kCheb;
+  static constexpr int tail = kCheb + 4 * nT;   // A, B', B
+};
+// tolerances of the end-point check on the mixed path (FP32 products)
+constexpr double kInterpTolPhaseMixed = 1e-9;
+constexpr double kInterpTolTMixed = 3e-8;
 
 // Node values, coefficients and end-point check of every work item (all
 // lanes active: lanes 60..63 repeat the last point of the last item).
+template <bool MIXED>
 __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
                                                       const PartConst* __restrict__ pc,
                                                       const int32_t* __restrict__ bounds,
@@ -563,33 +675,38 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
       const dd r = dd_add(dd_add(ph, dd{-p0h, -p0l}), dd{-bm.hi, -bm.lo});
       v[0] = r.hi + r.lo;
     }
+    typedef RecLayout<MIXED> L;
     double coef[5], emin[5], eplu[5], tmax = 0.0;
 #pragma unroll
     for (int fn = 0; fn < 5; ++fn) { coef[fn] = 0.0; emin[fn] = 0.0; eplu[fn] = 0.0; }
 #pragma unroll
     for (int kn = 0; kn < kCheb; ++kn) {
       const double gk = c_cheb_G[kn][k < kCheb ? k : 0];
+      const double gt = MIXED ? c_cheb_G6[kn][k < L::nT ? k : 0] : gk;
       const double em = c_cheb_E[0][kn], ep = c_cheb_E[1][kn];
+      const double emt = MIXED ? c_cheb_E6[0][kn] : em, ept = MIXED ? c_cheb_E6[1][kn] : ep;
 #pragma unroll
       for (int fn = 0; fn < 5; ++fn) {
         const double vn = __shfl(v[fn], base + kn, 64);
-        coef[fn] = fma(vn, gk, coef[fn]);
-        emin[fn] = fma(vn, em, emin[fn]);
-        eplu[fn] = fma(vn, ep, eplu[fn]);
+        coef[fn] = fma(vn, fn ? gt : gk, coef[fn]);
+        emin[fn] = fma(vn, fn ? emt : em, emin[fn]);
+        eplu[fn] = fma(vn, fn ? ept : ep, eplu[fn]);
         if (fn > 0) tmax = fmax(tmax, fabs(vn));
       }
     }
+    const double tolP = MIXED ? kInterpTolPhaseMixed : kInterpTolPhase;
+    const double tolT = MIXED ? kInterpTolTMixed : kInterpTolT;
     bool bad = false;
     double err = 0.0;           // relative template error at this end point
     if (k >= kCheb) {
       const double* e = (k == kCheb) ? emin : eplu;
       const double dph = fabs(e[0] - v[0]);
-      bad = !(dph <= kInterpTolPhase);
+      bad = !(dph <= tolP);
       err = 2.0 * kPi * dph;
 #pragma unroll
       for (int fn = 1; fn < 5; ++fn) {
         const double d = fabs(e[fn] - v[fn]);
-        bad = bad || !(d <= kInterpTolT * tmax);
+        bad = bad || !(d <= tolT * tmax);
         err = fmax(err, d / tmax);
       }
     }
@@ -600,13 +717,16 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
     const bool rej = nb < kMinInterp || ((badmask >> base) & ((1ull << kLanesItem) - 1ull)) != 0ull;
     double* r = rec + (int64_t)w * kRec;
     if (k < kCheb) {
+      r[k] = coef[0];
+      if (k < L::nT) {
 #pragma unroll
-      for (int fn = 0; fn < 5; ++fn) r[fn * kCheb + k] = coef[fn];
+        for (int fn = 1; fn < 5; ++fn) r[kCheb + (fn - 1) * L::nT + k] = coef[fn];
+      }
     } else if (k == kCheb) {
       FSTAT_NO_CONTRACT
-      r[5 * kCheb] = (p0h - floor(p0h)) + p0l;   // fractional cycle at the first bin
-      r[5 * kCheb + 1] = B - rint(B);            // whole cycles per bin drop out (m is an integer)
-      r[5 * kCheb + 2] = B;
+      r[L::tail] = (p0h - floor(p0h)) + p0l;     // fractional cycle at the first bin
+      r[L::tail + 1] = B - rint(B);              // whole cycles per bin drop out (m is an integer)
+      r[L::tail + 2] = B;
       xflag[w] = rej ? 1 : 0;
       xerr[w] = (float)err;
       if (rej) direct[atomicAdd(ndirect, 1)] = w;
@@ -642,6 +762,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
   DT* s_wi = s_wr + T;
   DT* s_u = s_wi + T;
   __shared__ int s_tile;
+  __shared__ double s_rec[4][64];                // each wave's current item record
   const DT* gwr;
   const DT* gwi;
   const DT* gu;
@@ -674,13 +795,18 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
       int b0, b1;
       item_bins(bp[l], bp[l + 1], it.y, T, b0, b1);
       const int nb = b1 - b0;
-      const double mine = rec[(int64_t)w * kRec + min(lane, kRec - 1)];
+      typedef RecLayout<MIXED> L;
+      // the record through the wave's LDS slot: one write, then broadcast reads
+      // (LDS operations of one wave complete in order)
+      double* R = s_rec[wv];
+      if (lane < kRec) R[lane] = rec[(int64_t)w * kRec + lane];
+      __builtin_amdgcn_wave_barrier();
       double cR[kCheb];
 #pragma unroll
-      for (int n = 0; n < kCheb; ++n) cR[n] = __shfl(mine, n, 64);
-      const double A = __shfl(mine, 5 * kCheb, 64);
-      const double Bp = __shfl(mine, 5 * kCheb + 1, 64);
-      const double Bf = __shfl(mine, 5 * kCheb + 2, 64);
+      for (int n = 0; n < kCheb; ++n) cR[n] = R[n];
+      const double A = R[L::tail];
+      const double Bp = R[L::tail + 1];
+      const double Bf = R[L::tail + 2];
       const double alpha = 2.0 / (double)(nb - 1);
       const int e0 = b0 - j0;            // LDS offset of the item's first bin
       if constexpr (!MIXED) {
@@ -688,7 +814,8 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
 #pragma unroll
         for (int fn = 0; fn < 4; ++fn)
 #pragma unroll
-          for (int n = 0; n < kCheb; ++n) cT[fn][n] = __shfl(mine, (fn + 1) * kCheb + n, 64);
+          for (int n = 0; n < kCheb; ++n) cT[fn][n] = R[kCheb + fn * L::nT + n];
+        __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
         double acc[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) acc[i] = 0.0;
@@ -698,19 +825,30 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         // FMA): up to ~1e-9 cycles at t_f ~ 1e8 s.
         const double kB = -Bf / g.df;
         const double j00 = (double)(g.k_lo + b0);
+        // the next bin's w, u are read one iteration ahead (LDS latency)
+        const int last = nb - 1;
+        double a_n = s_wr[e0 + min(lane, last)], b_n = s_wi[e0 + min(lane, last)];
+        double u_n = s_u[e0 + min(lane, last)];
         for (int mi = lane; mi < nb; mi += 64) {
+          const double a = a_n, b = b_n, uu = u_n;
+          {
+            const int nx = e0 + min(mi + 64, last);
+            a_n = s_wr[nx];
+            b_n = s_wi[nx];
+            u_n = s_u[nx];
+          }
           const double m = (double)mi;
           const double s = fma(alpha, m, -1.0);
+          const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
           const double jd = j00 + m;
           const double fj = jd * g.df;
           const double ej = fma(jd, g.df, -fj);
-          double ph = fma(Bp, m, horner(cR, s)) + fma(kB, ej, A);
+          double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
           ph -= rint(ph);
           double sps, cps;
           sincos_turns(ph, sps, cps);
-          const double tpr = horner(cT[0], s), tpi = horner(cT[1], s);
-          const double txr = horner(cT[2], s), txi = horner(cT[3], s);
-          const double a = s_wr[e0 + mi], b = s_wi[e0 + mi], uu = s_u[e0 + mi];
+          const double tpr = estrin9(cT[0], s, s2, s4, s8), tpi = estrin9(cT[1], s, s2, s4, s8);
+          const double txr = estrin9(cT[2], s, s2, s4, s8), txi = estrin9(cT[3], s, s2, s4, s8);
           const double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
           acc[0] += Wr * tpr + Wi * tpi;
           acc[1] += Wi * tpr - Wr * tpi;
@@ -721,22 +859,23 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
           acc[6] += uu * (tpr * txr + tpi * txi);
           acc[7] += uu * (tpi * txr - tpr * txi);
         }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] = wave_sum(acc[i]);
-        if (lane == 0) {
-#pragma unroll
-          for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = acc[i];
-        }
+        int idx;
+        const double tot = wave_sum8(acc, lane, idx);
+        if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
       } else {
-        float cT[4][kCheb];
+        float cT[4][kDegT + 1];
 #pragma unroll
         for (int fn = 0; fn < 4; ++fn)
 #pragma unroll
-          for (int n = 0; n < kCheb; ++n) cT[fn][n] = (float)__shfl(mine, (fn + 1) * kCheb + n, 64);
-        float acc[4], cmp[4];
+          for (int n = 0; n <= kDegT; ++n) cT[fn][n] = (float)R[kCheb + fn * L::nT + n];
+        __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
+        // per lane at most T / 64 terms: plain FP32 sums of the N-terms (their
+        // rounding, ~1e-7 relative, is far inside the mixed path's bar); M-terms
+        // in FP64 from the FP32 response
+        float acc[4];
         double m4[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) { acc[i] = cmp[i] = 0.0f; m4[i] = 0.0; }
+        for (int i = 0; i < 4; ++i) { acc[i] = 0.0f; m4[i] = 0.0; }
         for (int mi = lane; mi < nb; mi += 64) {
           const double m = (double)mi;
           const double s = fma(alpha, m, -1.0);
@@ -744,14 +883,14 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
           const float rf = (float)(ph - rint(ph));
           const float sps = __builtin_amdgcn_sinf(rf), cps = __builtin_amdgcn_cosf(rf);
           const float sf = (float)s;
-          const float tpr = horner(cT[0], sf), tpi = horner(cT[1], sf);
-          const float txr = horner(cT[2], sf), txi = horner(cT[3], sf);
+          const float tpr = horner_n<kDegT>(cT[0], sf), tpi = horner_n<kDegT>(cT[1], sf);
+          const float txr = horner_n<kDegT>(cT[2], sf), txi = horner_n<kDegT>(cT[3], sf);
           const float a = s_wr[e0 + mi], b = s_wi[e0 + mi];
           const float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
-          kahan_addf(acc[0], cmp[0], Wr * tpr + Wi * tpi);
-          kahan_addf(acc[1], cmp[1], Wi * tpr - Wr * tpi);
-          kahan_addf(acc[2], cmp[2], Wr * txr + Wi * txi);
-          kahan_addf(acc[3], cmp[3], Wi * txr - Wr * txi);
+          acc[0] += Wr * tpr + Wi * tpi;
+          acc[1] += Wi * tpr - Wr * tpi;
+          acc[2] += Wr * txr + Wi * txi;
+          acc[3] += Wi * txr - Wr * txi;
           const double uu = (double)s_u[e0 + mi];
           const double pr = tpr, pi = tpi, xr = txr, xi = txi;
           m4[0] += uu * (pr * pr + pi * pi);
@@ -761,13 +900,10 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         }
         double red[8];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) red[i] = wave_sum((double)acc[i] - (double)cmp[i]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) red[4 + i] = wave_sum(m4[i]);
-        if (lane == 0) {
-#pragma unroll
-          for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = red[i];
-        }
+        for (int i = 0; i < 4; ++i) { red[i] = (double)acc[i]; red[4 + i] = m4[i]; }
+        int idx;
+        const double tot = wave_sum8(red, lane, idx);
+        if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
       }
     }
     __syncthreads();   // every wave is done with this tile's LDS and s_tile
@@ -895,26 +1031,36 @@ int interp_tables_init() {
   for (int j = 1; j + 1 < K; ++j)
     for (int n = 0; n < K; ++n)
       M[j + 1][n] = (n > 0 ? 2.0L * M[j][n - 1] : 0.0L) - M[j - 1][n];
-  double S[kCheb], G[kCheb][kCheb], E[2][kCheb];
+  double S[kCheb], G[kCheb][kCheb], E[2][kCheb], G6[kCheb][kDegT + 1], E6[2][kCheb];
   for (int kk = 0; kk < K; ++kk) {
     S[kk] = (double)cosl(pi * (kk + 0.5L) / K);
-    long double lm = 0.0L, lp = 0.0L;
+    long double lm = 0.0L, lp = 0.0L, lm6 = 0.0L, lp6 = 0.0L;
     for (int n = 0; n < K; ++n) {
-      long double gsum = 0.0L;
+      long double gsum = 0.0L, g6 = 0.0L;
       for (int j = 0; j < K; ++j) {
         long double cj = (2.0L / K) * cosl(pi * j * (kk + 0.5L) / K) * (j == 0 ? 0.5L : 1.0L);
         gsum += cj * M[j][n];
+        if (j <= kDegT) g6 += cj * M[j][n];
       }
       G[kk][n] = (double)gsum;
       lp += gsum;
       lm += (n & 1) ? -gsum : gsum;
+      if (n <= kDegT) {
+        G6[kk][n] = (double)g6;
+        lp6 += g6;
+        lm6 += (n & 1) ? -g6 : g6;
+      }
     }
     E[0][kk] = (double)lm;
     E[1][kk] = (double)lp;
+    E6[0][kk] = (double)lm6;
+    E6[1][kk] = (double)lp6;
   }
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_s), S, sizeof(S)) != hipSuccess) return -1;
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_G), G, sizeof(G)) != hipSuccess) return -1;
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_E), E, sizeof(E)) != hipSuccess) return -1;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_G6), G6, sizeof(G6)) != hipSuccess) return -1;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_E6), E6, sizeof(E6)) != hipSuccess) return -1;
   if (dev >= 0 && dev < 64) done[dev] = true;
   return 0;
 }
@@ -1177,7 +1323,11 @@ void launch_setup(const Grid& g, const double* params, int64_t n,
 }
 
 void launch_worklist(int64_t m, const WorkSpace& ws, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ws.cnt, m, ws.off, ws.total, ws.ndirect, ws.nrefine);
+  const int32_t nb = (int32_t)((m + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(1024), 0, s, ws.cnt, m, ws.bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, ws.bsum, nb, ws.total, ws.ndirect,
+                     ws.nrefine);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, s, ws.cnt, m, ws.bsum, ws.off);
   hipLaunchKernelGGL(k_fill, dim3(nblk(m, 256)), dim3(256), 0, s, ws.cnt, ws.off, m, ws.items);
 }
 
@@ -1199,9 +1349,14 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, ws.tcnt, ntiles, ws.toff);
     hipLaunchKernelGGL(k_tile_scatter, dim3(1024), dim3(256), 0, s, ws.items, ws.total, ws.bounds,
                        stride, chunk, ws.toff, ws.tcur, ws.tile_items);
-    hipLaunchKernelGGL(k_interp_nodes, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
-                       ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.xerr, ws.direct,
-                       ws.ndirect);
+    if (mixed)
+      hipLaunchKernelGGL(k_interp_nodes<true>, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds,
+                         stride, ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.xerr,
+                         ws.direct, ws.ndirect);
+    else
+      hipLaunchKernelGGL(k_interp_nodes<false>, dim3(blocks), dim3(256), 0, s, g, ws.pc,
+                         ws.bounds, stride, ws.items, ws.total, chunk, ek, ws.rec, ws.xflag,
+                         ws.xerr, ws.direct, ws.ndirect);
     const size_t lds = 3 * (size_t)chunk * (mixed ? sizeof(float) : sizeof(double));
     if (ev_main) (void)hipEventRecord(ev_main[0], s);
     if (mixed)
