@@ -297,12 +297,6 @@ __device__ __forceinline__ void kahan_add(double& s, double& c, double x) {
   s = t;
 }
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
-
 // Sums of eight per-lane values over the wavefront in 10 exchanges instead of
 // 8 x 6: each step hands half of the remaining values to the partner lane
 // (xor 32, 16, 8), then the last value is summed over lanes xor 4, 2, 1.
@@ -382,11 +376,10 @@ __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
       for (int i = 0; i < 8; ++i) kahan_add(acc[i], cmp[i], t[i]);
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] = wave_sum(acc[i] - cmp[i]);
-    if (lane == 0) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = acc[i];
-    }
+    for (int i = 0; i < 8; ++i) acc[i] -= cmp[i];
+    int idx;
+    const double tot = wave_sum8(acc, lane, idx);
+    if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
   }
 }
 
@@ -527,13 +520,10 @@ __global__ __launch_bounds__(256) void k_eval_mixed(Grid g,
     }
     double red[8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) red[i] = wave_sum((double)acc[i] - (double)cmp[i]);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) red[4 + i] = wave_sum(m4[i]);
-    if (lane == 0) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = red[i];
-    }
+    for (int i = 0; i < 4; ++i) { red[i] = (double)acc[i] - (double)cmp[i]; red[4 + i] = m4[i]; }
+    int idx;
+    const double tot = wave_sum8(red, lane, idx);
+    if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
   }
 }
 
