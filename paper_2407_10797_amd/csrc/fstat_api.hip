@@ -82,6 +82,7 @@ int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride, int chunk) {
   if ((rc = ensure(&P->ws.tcnt, &P->cap.tcnt, ntiles, "alloc tcnt"))) return rc;
   if ((rc = ensure(&P->ws.tcur, &P->cap.tcur, ntiles, "alloc tcur"))) return rc;
   if ((rc = ensure(&P->ws.toff, &P->cap.toff, ntiles + 1, "alloc toff"))) return rc;
+  if ((rc = ensure(&P->ws.uoff, &P->cap.uoff, ntiles + 1, "alloc uoff"))) return rc;
   if ((rc = ensure(&P->ws.tile_items, &P->cap.tile_items, cap_items, "alloc tile items"))) return rc;
   if ((rc = ensure(&P->ws.tile_ctr, &P->cap.tile_ctr, 1, "alloc tile counter"))) return rc;
   if ((rc = ensure(&P->ws.xflag, &P->cap.xflag, cap_items, "alloc item flags"))) return rc;
@@ -368,7 +369,8 @@ void fstat_plan_destroy(fstat_plan_t P) {
   dev_free(P->ws.pc); dev_free(P->ws.bounds); dev_free(P->ws.cnt); dev_free(P->ws.off);
   dev_free(P->ws.total); dev_free(P->ws.items); dev_free(P->ws.partials); dev_free(P->ws.Fl);
   dev_free(P->ws.direct); dev_free(P->ws.ndirect); dev_free(P->ws.bsum);
-  dev_free(P->ws.tcnt); dev_free(P->ws.tcur); dev_free(P->ws.toff); dev_free(P->ws.tile_items);
+  dev_free(P->ws.tcnt); dev_free(P->ws.tcur); dev_free(P->ws.toff); dev_free(P->ws.uoff);
+  dev_free(P->ws.tile_items);
   dev_free(P->ws.tile_ctr); dev_free(P->ws.xflag); dev_free(P->ws.rec); dev_free(P->ws.xerr); dev_free(P->ws.refine); dev_free(P->ws.nrefine);
   dev_free(P->io.params); dev_free(P->io.np); dev_free(P->io.F_hat); dev_free(P->io.F_part);
   pso_release(P);

@@ -31,7 +31,8 @@ struct fstat_plan_s {
   fstat::WorkSpace ws{};
   struct {
     size_t pc = 0, bounds = 0, cnt = 0, off = 0, total = 0, items = 0, partials = 0, Fl = 0;
-    size_t direct = 0, ndirect = 0, tcnt = 0, tcur = 0, toff = 0, tile_items = 0, tile_ctr = 0;
+    size_t direct = 0, ndirect = 0, tcnt = 0, tcur = 0, toff = 0, uoff = 0, tile_items = 0,
+           tile_ctr = 0;
     size_t xflag = 0, refine = 0, nrefine = 0, rec = 0, xerr = 0, bsum = 0;
     size_t params = 0, np = 0, F_hat = 0, F_part = 0;
   } cap;

@@ -41,8 +41,9 @@ struct WorkSpace {
   int32_t* tcnt;      // [tiles] items per bin tile
   int32_t* tcur;      // [tiles] scatter cursors
   int32_t* toff;      // [tiles + 1] first item of each tile in tile_items
+  int32_t* uoff;      // [tiles + 1] first scheduling unit of each tile
   int32_t* tile_items;  // [capacity] item indices grouped by bin tile
-  int32_t* tile_ctr;  // [1] next tile to take (dynamic schedule)
+  int32_t* tile_ctr;  // [1] next unit to take (dynamic schedule)
   uint8_t* xflag;     // [capacity] 1: item evaluated by the exact kernel
   double* rec;        // [capacity][53] per-item interpolation records
   float* xerr;        // [capacity] end-point error of each interpolated item

@@ -2,18 +2,26 @@
 //
 // One evaluation (Sec. II.B, Eq. semi-cohF of arXiv:2407.10797) is a chain of
 // small kernels around one heavy one:
-//   k_setup   one thread per particle: intrinsic parameters -> PN constants,
-//             sky frame, support [f_lo, f_hi] (bisection on t_f), Np partition
-//             boundaries (bin indices) and work-item counts per partition
-//   k_scan_*  exclusive scan of the work-item counts (three passes)
-//   k_fill    work list: item -> (particle*stride + partition, chunk)
-//   k_eval_*  persistent grid, one wavefront per work item: for every bin of the
-//             chunk evaluate phase, t_f, TDI-X response and accumulate the eight
-//             partition sums {Z+, Zx, P, Q, R}; wavefront reduction; one partial
-//             per work item (deterministic, no atomics)
-//   k_solve   one thread per (particle, partition): ordered sum of partials and
-//             the 2x2 Hermitian closed form of F_l
-//   k_mean    one thread per particle: F_hat = mean_l F_l, or -inf / NaN
+//   k_setup         one wavefront per particle: intrinsic parameters -> PN
+//                   constants, sky frame, support [f_lo, f_hi] (t_f inverted by
+//                   a 64-point search), Np partition edges (bin indices) and the
+//                   work-item counts: a work item is the part of a partition
+//                   inside one tile of the global tiling of the band
+//   k_scan_*        exclusive scan of the work-item counts (three passes)
+//   k_fill          work list: item -> (particle*stride + partition, tile index)
+//   k_interp_nodes  exact template at 10 Chebyshev nodes and both ends of every
+//                   item -> interpolation record, or hand-over to the exact loop
+//   k_tile_*        items grouped by tile; scheduling units of <= 32 items
+//   k_eval_interp   persistent blocks take units dynamically, stage the tile's
+//                   data in LDS, and evaluate the interpolated template at every
+//                   bin of each item: the eight partition sums {Z+, Zx, P, Q, R}
+//                   per item (deterministic, no float atomics)
+//   k_eval_fp64 /   the exact template at every bin, for handed-over items, for
+//   k_eval_mixed    refinement and under FSTAT_EVAL_EXACT
+//   k_mark          partitions whose interpolation error could matter -> exact
+//   k_solve         one thread per (particle, partition): ordered sum of the
+//                   item partials and the 2x2 Hermitian closed form of F_l
+//   k_mean          one thread per particle: F_hat = mean_l F_l, or -inf / NaN
 #include "fstat_internal.h"
 #include <type_traits>
 
@@ -120,23 +128,42 @@ __device__ double tf_only(const PartConst& P, double f) {
   return tf;
 }
 
-// frequency where t_f reaches t, by bisection on [fa, fb]
-__device__ double invert_tf(const PartConst& P, double t, double fa, double fb) {
+// Frequency where t_f (increasing in f) reaches t on [fa, fb], by one
+// wavefront: rounds of a 64-point search (each lane evaluates one interior
+// point, the ballot of points below t brackets the root; 65x narrower per
+// round) down to a few ulps, then bisection to the double resolution.
+__device__ double invert_tf(const PartConst& P, double t, double fa, double fb, int lane) {
+  for (int it = 0; it < 12; ++it) {
+    const double h = (fb - fa) * (1.0 / 65.0);
+    if (!(h > 64.0 * 2.3e-16 * fb)) break;
+    const double f = fa + h * (double)(lane + 1);
+    const uint64_t below = __ballot(tf_only(P, f) < t);
+    const int k = __popcll(below);                 // points below t (a prefix: t_f increases)
+    const double nfa = k > 0 ? fa + h * (double)k : fa;
+    const double nfb = k < 64 ? fa + h * (double)(k + 1) : fb;
+    fa = nfa;
+    fb = fmin(nfb, fb);
+  }
   for (int it = 0; it < 200; ++it) {
-    double fm = 0.5 * (fa + fb);
+    const double fm = 0.5 * (fa + fb);
     if (fm <= fa || fm >= fb) break;
     if (tf_only(P, fm) < t) fa = fm; else fb = fm;
   }
   return fb;
 }
 
-__global__ void k_setup(Grid g, const double* __restrict__ params, int64_t n,
-                        const int32_t* __restrict__ np, int32_t np_uniform, int32_t stride,
-                        int32_t chunk, const uint8_t* __restrict__ skip,
-                        PartConst* __restrict__ pc, int32_t* __restrict__ bounds,
-                        int32_t* __restrict__ cnt) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+// One wavefront per particle: constants, support, partition edges (one per
+// lane), work-item counts.
+__global__ __launch_bounds__(256) void k_setup(Grid g, const double* __restrict__ params,
+                                               int64_t n, const int32_t* __restrict__ np,
+                                               int32_t np_uniform, int32_t stride, int32_t chunk,
+                                               const uint8_t* __restrict__ skip,
+                                               PartConst* __restrict__ pc,
+                                               int32_t* __restrict__ bounds,
+                                               int32_t* __restrict__ cnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (p >= n) return;                      // whole wavefronts
   const double* th = params + 6 * p;
   int npi = np ? np[p] : np_uniform;
   PartConst P;
@@ -145,17 +172,17 @@ __global__ void k_setup(Grid g, const double* __restrict__ params, int64_t n,
   ok = ok && th[1] > 0.0 && fabs(th[2]) < 1.0 && th[5] >= 0.0 && npi >= 1 && npi <= stride;
   int32_t* bp = bounds + p * (int64_t)(stride + 1);
   int32_t* cp = cnt + p * (int64_t)stride;
-  for (int l = 0; l < stride; ++l) cp[l] = 0;
+  for (int l = lane; l < stride; l += 64) cp[l] = 0;
   P.np = npi;
   P.j_lo = 0; P.j_hi = -1;
   if (!ok) {
     P.status = kStatusInvalid;
-    pc[p] = P;
+    if (lane == 0) pc[p] = P;
     return;
   }
   if (skip && skip[p]) {  // outside the search box: not evaluated (let-them-fly)
     P.status = kStatusEmpty;
-    pc[p] = P;
+    if (lane == 0) pc[p] = P;
     return;
   }
   fill_constants(P, th);
@@ -165,8 +192,8 @@ __global__ void k_setup(Grid g, const double* __restrict__ params, int64_t n,
   bool empty = (t_last < 0.0) || (t_first > g.T_obs);
   double flo = 0.0, fhi = 0.0;
   if (!empty) {
-    flo = (t_first >= 0.0) ? f_first : invert_tf(P, 0.0, f_first, f_last);
-    fhi = (t_last <= g.T_obs) ? f_last : invert_tf(P, g.T_obs, f_first, f_last);
+    flo = (t_first >= 0.0) ? f_first : invert_tf(P, 0.0, f_first, f_last, lane);
+    fhi = (t_last <= g.T_obs) ? f_last : invert_tf(P, g.T_obs, f_first, f_last, lane);
     empty = !(flo <= fhi);
   }
   int jlo = 0, jhi = -1;
@@ -181,25 +208,25 @@ __global__ void k_setup(Grid g, const double* __restrict__ params, int64_t n,
   P.flo = flo; P.fhi = fhi;
   if (empty) {
     P.status = kStatusEmpty;
-    pc[p] = P;
+    if (lane == 0) pc[p] = P;
     return;
   }
   P.status = kStatusOk;
   P.j_lo = jlo; P.j_hi = jhi;
-  pc[p] = P;
-  double span = fhi - flo;
-  bp[0] = jlo;
-  int prev = jlo;
-  for (int l = 1; l < npi; ++l) {
-    double e = flo + (span * (double)l) / (double)npi;
-    int b = first_bin_at_or_above(g, e, prev, jhi);
-    bp[l] = b;
-    prev = b;
-  }
-  bp[npi] = jhi + 1;
-  for (int l = 0; l < npi; ++l) {   // bin tiles of the global tiling the partition meets
-    int a = bp[l], b = bp[l + 1];
-    cp[l] = b > a ? (b - 1) / chunk - a / chunk + 1 : 0;
+  if (lane == 0) pc[p] = P;
+  // edges e_l = flo + span l / Np: bin bp[l] is the first at or above e_l; each
+  // lane computes both edges of its partitions (no exchange between lanes)
+  const double span = fhi - flo;
+  auto edge = [&](int l) -> int {
+    if (l == 0) return jlo;
+    if (l == npi) return jhi + 1;
+    return first_bin_at_or_above(g, flo + (span * (double)l) / (double)npi, jlo, jhi);
+  };
+  for (int l = lane; l < npi; l += 64) {
+    const int a = edge(l), b = edge(l + 1);
+    bp[l] = a;
+    if (l == npi - 1) bp[npi] = b;
+    cp[l] = b > a ? (b - 1) / chunk - a / chunk + 1 : 0;   // bin tiles the partition meets
   }
 }
 
@@ -554,6 +581,7 @@ constexpr int kItemsWave = 5;
 constexpr int kMinInterp = 32;
 constexpr double kInterpTolPhase = 1e-12;
 constexpr double kInterpTolT = 2e-13;
+constexpr int kUnitItems = 32;      // items per scheduling unit of the bin loop
 
 __constant__ double c_cheb_s[kCheb];          // nodes cos(pi (k + 1/2) / 10)
 __constant__ double c_cheb_G[kCheb][kCheb];   // node value k -> coefficient of s^n
@@ -735,6 +763,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                                                      int32_t T,
                                                      const int32_t* __restrict__ tile_items,
                                                      const int32_t* __restrict__ tile_off,
+                                                     const int32_t* __restrict__ unit_off,
                                                      int32_t ntiles,
                                                      int32_t* __restrict__ tile_ctr,
                                                      const double* __restrict__ wr64,
@@ -751,7 +780,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
   DT* s_wr = reinterpret_cast<DT*>(smem);      // the tile's w and u, [3][T]
   DT* s_wi = s_wr + T;
   DT* s_u = s_wi + T;
-  __shared__ int s_tile;
+  __shared__ int s_unit[3];                       // tile, first item, item count
   __shared__ double s_rec[4][64];                // each wave's current item record
   const DT* gwr;
   const DT* gwi;
@@ -761,11 +790,27 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int nwv = blockDim.x >> 6;
+  const int nunits = unit_off[ntiles];
   for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1);
+    // next unit (dynamic): up to kUnitItems items of one tile
+    if (threadIdx.x == 0) {
+      const int u = atomicAdd(tile_ctr, 1);
+      int t = -1, first = 0, count = 0;
+      if (u < nunits) {
+        int lo = 0, hi = ntiles;                     // last tile with unit_off[t] <= u
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (unit_off[mid] <= u) lo = mid; else hi = mid;
+        }
+        t = lo;
+        first = tile_off[t] + (u - unit_off[t]) * kUnitItems;
+        count = min(kUnitItems, tile_off[t + 1] - first);
+      }
+      s_unit[0] = t; s_unit[1] = first; s_unit[2] = count;
+    }
     __syncthreads();
-    const int t = s_tile;
-    if (t >= ntiles) break;
+    const int t = s_unit[0];
+    if (t < 0) break;
     const int j0 = t * T;
     const int nt = min((int64_t)T, g.nbins - j0);
     for (int i = threadIdx.x; i < nt; i += blockDim.x) {
@@ -774,8 +819,8 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
       s_u[i] = gu[j0 + i];
     }
     __syncthreads();
-    const int i0 = tile_off[t];
-    const int cnt = tile_off[t + 1] - i0;
+    const int i0 = s_unit[1];
+    const int cnt = s_unit[2];
     for (int idx = wv; idx < cnt; idx += nwv) {
       const int w = tile_items[i0 + idx];
       if (xflag[w]) continue;                      // evaluated by the exact kernel
@@ -896,7 +941,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
       }
     }
-    __syncthreads();   // every wave is done with this tile's LDS and s_tile
+    __syncthreads();   // every wave is done with this unit's LDS and s_unit
   }
 }
 
@@ -955,47 +1000,112 @@ __global__ void k_tile_zero(int32_t* __restrict__ tcnt, int32_t* __restrict__ tc
   if (i == 0) tile_ctr[0] = 0;
 }
 
-__global__ void k_tile_count(const int2* __restrict__ items, const int32_t* __restrict__ total,
-                             const int32_t* __restrict__ bounds, int32_t stride, int32_t T,
-                             int32_t* __restrict__ tcnt) {
-  const int W = total[0];
-  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
-    const int2 it = items[w];
-    const int p = it.x / stride, l = it.x - p * stride;
-    atomicAdd(&tcnt[item_tile(bounds[(int64_t)p * (stride + 1) + l], it.y, T)], 1);
-  }
-}
+// Items per tile.  When the tiles fit in LDS the block first counts its own
+// items there and then adds its non-zero counts to the global ones: with few
+// tiles (a narrow band) every item would otherwise hit the same few counters.
+constexpr int kTileHist = 8192;
 
-// exclusive scan of tcnt[n] into off[0..n] (off[n] = total), one block
-__global__ void k_tile_scan(const int32_t* __restrict__ tcnt, int32_t n, int32_t* __restrict__ off) {
-  __shared__ int32_t part[1024];
-  const int t = threadIdx.x, TB = blockDim.x;
-  const int per = (n + TB - 1) / TB;
-  const int a = t * per, b = min(n, a + per);
-  int32_t sum = 0;
-  for (int i = a; i < b; ++i) sum += tcnt[i];
-  part[t] = sum;
-  __syncthreads();
-  if (t == 0) {
-    int32_t run = 0;
-    for (int i = 0; i < TB; ++i) { int32_t x = part[i]; part[i] = run; run += x; }
-    off[n] = run;
-  }
-  __syncthreads();
-  int32_t run = part[t];
-  for (int i = a; i < b; ++i) { off[i] = run; run += tcnt[i]; }
-}
-
-__global__ void k_tile_scatter(const int2* __restrict__ items, const int32_t* __restrict__ total,
-                               const int32_t* __restrict__ bounds, int32_t stride, int32_t T,
-                               const int32_t* __restrict__ off, int32_t* __restrict__ tcur,
-                               int32_t* __restrict__ tile_items) {
+__global__ __launch_bounds__(256) void k_tile_count(const int2* __restrict__ items,
+                                                    const int32_t* __restrict__ total,
+                                                    const int32_t* __restrict__ bounds,
+                                                    int32_t stride, int32_t T, int32_t ntiles,
+                                                    int32_t* __restrict__ tcnt) {
+  __shared__ int32_t h[kTileHist];
+  const bool local = ntiles <= kTileHist;
   const int W = total[0];
+  if (local) {
+    for (int i = threadIdx.x; i < ntiles; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+  }
   for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
     const int2 it = items[w];
     const int p = it.x / stride, l = it.x - p * stride;
     const int t = item_tile(bounds[(int64_t)p * (stride + 1) + l], it.y, T);
-    tile_items[off[t] + atomicAdd(&tcur[t], 1)] = w;
+    if (local) atomicAdd(&h[t], 1);
+    else atomicAdd(&tcnt[t], 1);
+  }
+  if (local) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < ntiles; i += blockDim.x)
+      if (h[i]) atomicAdd(&tcnt[i], h[i]);
+  }
+}
+
+// Exclusive scans of the per-tile item counts into off[0..n] and of the
+// per-tile unit counts ceil(cnt / kUnitItems) into uoff[0..n] (a unit is the
+// bin loop's scheduling step: one tile, up to kUnitItems of its items).  One
+// block.
+
+__global__ void k_tile_scan(const int32_t* __restrict__ tcnt, int32_t n, int32_t* __restrict__ off,
+                            int32_t* __restrict__ uoff) {
+  __shared__ int32_t part[1024], upart[1024];
+  const int t = threadIdx.x, TB = blockDim.x;
+  const int per = (n + TB - 1) / TB;
+  const int a = t * per, b = min(n, a + per);
+  int32_t sum = 0, usum = 0;
+  for (int i = a; i < b; ++i) {
+    sum += tcnt[i];
+    usum += (tcnt[i] + kUnitItems - 1) / kUnitItems;
+  }
+  part[t] = sum;
+  upart[t] = usum;
+  __syncthreads();
+  if (t == 0) {
+    int32_t run = 0, urun = 0;
+    for (int i = 0; i < TB; ++i) {
+      int32_t x = part[i], y = upart[i];
+      part[i] = run; upart[i] = urun;
+      run += x; urun += y;
+    }
+    off[n] = run;
+    uoff[n] = urun;
+  }
+  __syncthreads();
+  int32_t run = part[t], urun = upart[t];
+  for (int i = a; i < b; ++i) {
+    off[i] = run; uoff[i] = urun;
+    run += tcnt[i];
+    urun += (tcnt[i] + kUnitItems - 1) / kUnitItems;
+  }
+}
+
+// Items into tile order.  With the tiles in LDS, the block ranks its items per
+// tile locally and reserves one range per tile with a single global atomic.
+__global__ __launch_bounds__(256) void k_tile_scatter(const int2* __restrict__ items,
+                                                      const int32_t* __restrict__ total,
+                                                      const int32_t* __restrict__ bounds,
+                                                      int32_t stride, int32_t T, int32_t ntiles,
+                                                      const int32_t* __restrict__ off,
+                                                      int32_t* __restrict__ tcur,
+                                                      int32_t* __restrict__ tile_items) {
+  __shared__ int32_t h[kTileHist];
+  const bool local = ntiles <= kTileHist;
+  const int W = total[0];
+  if (!local) {
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
+      const int2 it = items[w];
+      const int p = it.x / stride, l = it.x - p * stride;
+      const int t = item_tile(bounds[(int64_t)p * (stride + 1) + l], it.y, T);
+      tile_items[off[t] + atomicAdd(&tcur[t], 1)] = w;
+    }
+    return;
+  }
+  for (int i = threadIdx.x; i < ntiles; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
+    const int2 it = items[w];
+    const int p = it.x / stride, l = it.x - p * stride;
+    atomicAdd(&h[item_tile(bounds[(int64_t)p * (stride + 1) + l], it.y, T)], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ntiles; i += blockDim.x)    // counts -> reserved bases
+    if (h[i]) h[i] = off[i] + atomicAdd(&tcur[i], h[i]);
+  __syncthreads();
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
+    const int2 it = items[w];
+    const int p = it.x / stride, l = it.x - p * stride;
+    const int t = item_tile(bounds[(int64_t)p * (stride + 1) + l], it.y, T);
+    tile_items[atomicAdd(&h[t], 1)] = w;
   }
 }
 
@@ -1308,7 +1418,7 @@ void launch_scale(const Grid& g, const double* umax, BinData<double> b, BinData<
 void launch_setup(const Grid& g, const double* params, int64_t n,
                   const int32_t* np, int32_t np_uniform, int32_t stride, int32_t chunk,
                   const uint8_t* skip, const WorkSpace& ws, hipStream_t s) {
-  hipLaunchKernelGGL(k_setup, dim3(nblk(n, 64)), dim3(64), 0, s, g, params, n, np, np_uniform,
+  hipLaunchKernelGGL(k_setup, dim3(nblk(n * 64, 256)), dim3(256), 0, s, g, params, n, np, np_uniform,
                      stride, chunk, skip, ws.pc, ws.bounds, ws.cnt);
 }
 
@@ -1335,10 +1445,10 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
     hipLaunchKernelGGL(k_tile_zero, dim3(nblk(ntiles, 256)), dim3(256), 0, s, ws.tcnt, ws.tcur,
                        ntiles, ws.tile_ctr);
     hipLaunchKernelGGL(k_tile_count, dim3(1024), dim3(256), 0, s, ws.items, ws.total, ws.bounds,
-                       stride, chunk, ws.tcnt);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, ws.tcnt, ntiles, ws.toff);
+                       stride, chunk, ntiles, ws.tcnt);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, ws.tcnt, ntiles, ws.toff, ws.uoff);
     hipLaunchKernelGGL(k_tile_scatter, dim3(1024), dim3(256), 0, s, ws.items, ws.total, ws.bounds,
-                       stride, chunk, ws.toff, ws.tcur, ws.tile_items);
+                       stride, chunk, ntiles, ws.toff, ws.tcur, ws.tile_items);
     if (mixed)
       hipLaunchKernelGGL(k_interp_nodes<true>, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds,
                          stride, ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.xerr,
@@ -1351,11 +1461,13 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
     if (ev_main) (void)hipEventRecord(ev_main[0], s);
     if (mixed)
       hipLaunchKernelGGL(k_eval_interp<true>, dim3(blocks), dim3(256), lds, s, g, ws.bounds, stride,
-                         ws.items, chunk, ws.tile_items, ws.toff, ntiles, ws.tile_ctr, b.wr, b.wi,
+                         ws.items, chunk, ws.tile_items, ws.toff, ws.uoff, ntiles, ws.tile_ctr,
+                         b.wr, b.wi,
                          b.u, b32.wr, b32.wi, b32.u, ws.rec, ws.xflag, ws.partials);
     else
       hipLaunchKernelGGL(k_eval_interp<false>, dim3(blocks), dim3(256), lds, s, g, ws.bounds,
-                         stride, ws.items, chunk, ws.tile_items, ws.toff, ntiles, ws.tile_ctr,
+                         stride, ws.items, chunk, ws.tile_items, ws.toff, ws.uoff, ntiles,
+                         ws.tile_ctr,
                          b.wr, b.wi, b.u, b32.wr, b32.wi, b32.u, ws.rec, ws.xflag, ws.partials);
     if (ev_main) (void)hipEventRecord(ev_main[1], s);
     sel = ws.direct;
