@@ -251,12 +251,13 @@ __global__ void k_sum_dy(const float* __restrict__ dy, int B, float* __restrict_
 }
 
 // Inference-only forward of the whole network on R rows, keeping no
-// activations (knot evaluation).  One wavefront per 16 rows, four per block.
+// activations (knot evaluation).  One wavefront per 16 rows, four per block;
+// the weights pass through LDS in 8 KB k-slabs shared by the four waves.
 // Layer 1 runs on the VALU straight into the MFMA A-operand layout (lane l:
 // row l % 16, k = 16 kb + 4 (l / 16) + j); layers 2-4 are 16x16x16 BF16 MFMA
-// tiles over all 256 outputs with the weights' BF16 copies read from L2 in
-// the B-operand layout (col l % 16, same k); between layers the 16x256 tile
-// goes through the wave's own LDS rows to turn the D layout (row 4 (l / 16)
+// tiles over all 256 outputs with the weights' BF16 copies read from the LDS
+// slabs in the B-operand layout (col l % 16, same k); between layers the
+// 16x256 tile goes through the wave's own LDS rows to turn the D layout (row 4 (l / 16)
 // + r, col l % 16) back into the A layout.  The output unit is a lane
 // reduction.  Same operand rounding as the training forward: BF16 hidden
 // activations, FP32 last pre-activation, FP32 output layer.
@@ -265,6 +266,7 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(const float* __restrict__ 
                                                    const uint16_t* __restrict__ wbf,
                                                    float* __restrict__ y) {
   __shared__ uint16_t T[4][16][kHid + 8];
+  __shared__ __align__(16) uint16_t Ws[2][kHid][16 + 4];   // two k-slabs of W (rows n, 16 k)
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c16 = lane & 15, g4 = lane >> 4;
   const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 16;
@@ -284,18 +286,38 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(const float* __restrict__ 
       }
   }
   v4f acc[16];
+  // W_l[n][k] in k-slabs of 16 (8 KB), staged in LDS once for the block's four
+  // waves and double-buffered: slab kb + 1 is fetched while slab kb is used
+  const int tid = threadIdx.x;                      // row n of W that this thread stages
   for (int L = 0; L < 3; ++L) {
     const uint16_t* W = wbf + (size_t)L * kHid * kHid;
     const float* bias = P + mlp_off_b(L + 1);
 #pragma unroll
     for (int nt = 0; nt < 16; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
+    {
+      const uint2* src = reinterpret_cast<const uint2*>(W + (size_t)tid * kHid);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2*>(&Ws[0][tid][4 * q]) = src[q];
+    }
+    __syncthreads();
+#pragma unroll
     for (int kb = 0; kb < 16; ++kb) {
+      uint2 nxt[4];
+      if (kb + 1 < 16) {
+        const uint2* src = reinterpret_cast<const uint2*>(W + (size_t)tid * kHid + 16 * (kb + 1));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nxt[q] = src[q];
+      }
 #pragma unroll
       for (int nt = 0; nt < 16; ++nt) {
-        const v4s b = *reinterpret_cast<const v4s*>(W + (size_t)(16 * nt + c16) * kHid + 16 * kb + 4 * g4);
+        const v4s b = *reinterpret_cast<const v4s*>(&Ws[kb & 1][16 * nt + c16][4 * g4]);
         acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[kb], b, acc[nt], 0, 0, 0);
       }
+      if (kb + 1 < 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2*>(&Ws[(kb + 1) & 1][tid][4 * q]) = nxt[q];
+      }
+      __syncthreads();
     }
     if (L < 2) {
 #pragma unroll

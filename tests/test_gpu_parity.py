@@ -110,6 +110,23 @@ def test_uneven_np_in_one_launch(small, torch_cuda):
         np.testing.assert_array_equal(P[idx, :k], Pu.cpu().numpy()[:, :k])
 
 
+def test_many_partitions_ragged_mix(small, torch_cuda):
+    """Np up to 1000 (more partitions than support bins, so many are empty)
+    mixed with odd counts in one launch, element by element against the
+    oracle."""
+    s = small
+    pts = s["pts"][:32]
+    nps = np.array([1000, 3, 777, 1] * 8, dtype=np.int32)
+    F, P = s["plan"].eval(torch_cuda.from_numpy(pts), torch_cuda.from_numpy(nps), 1000,
+                          want_parts=True)
+    Fo, Po, cond = O.fstat(s["data"], s["psd"], s["g"].k_lo, s["g"].df, s["g"].T_obs, pts, nps,
+                           part_stride=1000, want_cond=True)
+    F, P = F.cpu().numpy(), P.cpu().numpy()
+    _check_parts(P, Po, cond, nps)
+    tolF = REL + 1e-14 * np.nanmax(np.where(np.isfinite(cond), cond, 0.0), axis=1)
+    assert np.all(_rel(F, Fo) <= tolF), np.max(_rel(F, Fo))
+
+
 def test_batch_composition_does_not_change_results(small, torch_cuda):
     """Results for a particle do not depend on which other particles share the launch."""
     s = small
