@@ -396,7 +396,7 @@ static void lu_solve4(const double Min[4][4], const double N[4], double a[4]) {
 
 /* Eq. "coherent_F_stat": F = 1/2 N^T M^{-1} N, with a = M^{-1} N.
  * Returns F; writes lambda_max/lambda_min to *cond (inf when singular).   */
-static double fstat_solve(const double M[4][4], const double N[4], double *cond) {
+static double fstat_solve(const double M[4][4], const double N[4], double *cond, double a_out[4]) {
   double lam[4], V[4][4];
   jacobi4(M, lam, V);
   double lmax = lam[0], lmin = lam[0];
@@ -404,18 +404,20 @@ static double fstat_solve(const double M[4][4], const double N[4], double *cond)
     if (lam[i] > lmax) lmax = lam[i];
     if (lam[i] < lmin) lmin = lam[i];
   }
+  for (int r = 0; r < 4; ++r) a_out[r] = 0.0;
   if (!(lmax > 0.0)) { *cond = INFINITY; return 0.0; }
   *cond = (lmin > 0.0) ? lmax / lmin : INFINITY;
   if (lmin > OR_RANK_CUT * lmax) {
-    double a[4];
-    lu_solve4(M, N, a);
-    return 0.5 * (N[0] * a[0] + N[1] * a[1] + N[2] * a[2] + N[3] * a[3]);
+    lu_solve4(M, N, a_out);           /* the maximiser a = M^{-1} N (Eq. aandMN3) */
+    return 0.5 * (N[0] * a_out[0] + N[1] * a_out[1] + N[2] * a_out[2] + N[3] * a_out[3]);
   }
+  /* pseudo-inverse: the minimum-norm maximiser */
   double F = 0.0;
   for (int i = 0; i < 4; ++i) {
     if (lam[i] <= OR_RANK_CUT * lmax) continue;
     double proj = V[0][i] * N[0] + V[1][i] * N[1] + V[2][i] * N[2] + V[3][i] * N[3];
     F += 0.5 * proj * proj / lam[i];
+    for (int r = 0; r < 4; ++r) a_out[r] += V[r][i] * proj / lam[i];
   }
   return F;
 }
@@ -549,7 +551,8 @@ int or_signal(const double *theta6, const double *amp4, double df, int64_t k_lo,
  * arguments.                                                               */
 int or_fstat(const double *data, const double *psd, int64_t nbins, int64_t k_lo, double df,
              double T_obs, const double *params, int64_t n, const int32_t *np, int32_t np_uniform,
-             double *F_hat, double *F_part, int64_t part_stride, double *cond_out) {
+             double *F_hat, double *F_part, int64_t part_stride, double *cond_out,
+             double *amps_out) {
   if (nbins <= 0 || n < 0 || !(df > 0.0)) return -1;
   for (int64_t i = 0; i < n; ++i) {
     or_intr p = unpack(params + 6 * i);
@@ -568,11 +571,13 @@ int or_fstat(const double *data, const double *psd, int64_t nbins, int64_t k_lo,
     double flo, fhi;
     double *fp = F_part ? F_part + i * part_stride : NULL;
     double *cp = cond_out ? cond_out + i * part_stride : NULL;
+    double *ap = amps_out ? amps_out + 4 * i * part_stride : NULL;
     if (!support(&p, T_obs, f_first, f_last, &flo, &fhi)) {
       F_hat[i] = -INFINITY;
       for (int l = 0; l < Np; ++l) {
         if (fp) fp[l] = 0.0;
         if (cp) cp[l] = INFINITY;
+        if (ap) for (int r = 0; r < 4; ++r) ap[4 * l + r] = 0.0;
       }
       continue;
     }
@@ -604,9 +609,11 @@ int or_fstat(const double *data, const double *psd, int64_t nbins, int64_t k_lo,
         N[a] = 4.0 * df * acc_val(&accN[4 * q + a]);
         for (int b = 0; b < 4; ++b) M[a][b] = 4.0 * df * acc_val(&accM[16 * q + 4 * a + b]);
       }
-      double Fl = fstat_solve(M, N, &cnd);
+      double a[4];
+      double Fl = fstat_solve(M, N, &cnd, a);
       if (fp) fp[q] = Fl;
       if (cp) cp[q] = cnd;
+      if (ap) for (int r = 0; r < 4; ++r) ap[4 * q + r] = a[r];
       sum += Fl;
     }
     F_hat[i] = sum / (double)Np;

@@ -55,7 +55,7 @@ def lib():
                                 ctypes.c_double, _dp]
         L.or_fstat.argtypes = [_dp, _dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
                                ctypes.c_double, _dp, ctypes.c_int64, _i32p, ctypes.c_int32,
-                               _dp, _dp, ctypes.c_int64, _dp]
+                               _dp, _dp, ctypes.c_int64, _dp, _dp]
         _lib = L
     return _lib
 
@@ -145,8 +145,11 @@ def signal(theta6, amp4, df, k_lo, nbins, T_obs):
     return out[:, 0] + 1j * out[:, 1]
 
 
-def fstat(data, psd, k_lo, df, T_obs, params, np_parts, part_stride=None, want_cond=False):
-    """Semi-coherent F (Eq. "semi-cohF").  Returns (F_hat, F_part[, cond])."""
+def fstat(data, psd, k_lo, df, T_obs, params, np_parts, part_stride=None, want_cond=False,
+          want_amps=False):
+    """Semi-coherent F (Eq. "semi-cohF").  Returns (F_hat, F_part[, cond][, amps]):
+    amps [n, stride, 4] are the maximising amplitudes a = M^{-1} N of each
+    partition (Eq. "aandMN3"), minimum-norm when M is singular."""
     data = np.ascontiguousarray(data, dtype=np.complex128)
     dv = data.view(np.float64)
     psd, pp = _d(psd)
@@ -157,13 +160,20 @@ def fstat(data, psd, k_lo, df, T_obs, params, np_parts, part_stride=None, want_c
     Fh = np.empty(n)
     Fp = np.zeros((n, stride))
     cond = np.zeros((n, stride)) if want_cond else None
+    amps = np.zeros((n, stride, 4)) if want_amps else None
     rc = lib().or_fstat(dv.ctypes.data_as(_dp), pp, data.size, int(k_lo), float(df), float(T_obs),
                         params.ctypes.data_as(_dp), n, npa.ctypes.data_as(_i32p), 0,
                         Fh.ctypes.data_as(_dp), Fp.ctypes.data_as(_dp), stride,
-                        cond.ctypes.data_as(_dp) if want_cond else None)
+                        cond.ctypes.data_as(_dp) if want_cond else None,
+                        amps.ctypes.data_as(_dp) if want_amps else None)
     if rc:
         raise ValueError(f"oracle fstat failed ({rc})")
-    return (Fh, Fp, cond) if want_cond else (Fh, Fp)
+    out = (Fh, Fp)
+    if want_cond:
+        out += (cond,)
+    if want_amps:
+        out += (amps,)
+    return out
 
 
 # ---- numpy restatements used by the pins ---------------------------------

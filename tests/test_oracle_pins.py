@@ -387,3 +387,78 @@ def test_mlp_oracle_gradient_matches_finite_differences():
         pm = p.copy(); pm[i] -= h
         fd = (MO.loss_and_grad(pp, x, t)[0] - MO.loss_and_grad(pm, x, t)[0]) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_amplitudes_recover_noise_free_injection(seed):
+    """With s = sum_i a_i A^i and no noise, N = M a, so the maximiser
+    M^{-1} N (Eq. aandMN3) returns the injected a exactly, in every
+    partition as well as coherently."""
+    g, inj = _small_case()
+    a = np.random.default_rng(seed).normal(size=4)
+    sig = O.signal(inj, a, g.df, g.k_lo, g.nbins, g.T_obs)
+    psd = S.psd_tdix(g.freqs())
+    for Np in (1, 4):
+        _, _, cond, amps = O.fstat(sig, psd, g.k_lo, g.df, g.T_obs, inj, [Np], want_cond=True,
+                                   want_amps=True)
+        for l in range(Np):
+            if cond[0, l] < 1e8:
+                np.testing.assert_allclose(amps[0, l], a, rtol=0, atol=1e-12 * cond[0, l] * np.abs(a).max() + 1e-12)
+
+
+def test_amplitudes_maximise_the_likelihood():
+    """On noisy data the returned a is the maximiser of Lambda(a) = <s,h> - 1/2 <h,h>
+    (Eq. 2, h = sum a_i A^i): the gradient N - M a, formed from the explicit
+    templates, vanishes; no point a numerical optimiser finds is higher; and
+    2 F = a . N."""
+    sub, psd, d, inj = _tiny_problem()
+    p = inj.copy()
+    p[0] += 300.0
+    A = O.basis(p, sub.freqs())
+    Fh, _, amps = O.fstat(d, psd, sub.k_lo, sub.df, 1e30, p, [1], want_amps=True)
+    a = amps[0, 0]
+    N = np.array([O.inner(d, A[:, i], psd, sub.df) for i in range(4)])
+    M = np.array([[O.inner(A[:, i], A[:, j], psd, sub.df) for j in range(4)] for i in range(4)])
+    np.testing.assert_allclose(M @ a, N, rtol=0, atol=1e-9 * np.abs(N).max())
+    np.testing.assert_allclose(2 * Fh[0], a @ N, rtol=1e-10)
+    scale = np.sqrt(M[0, 0])
+    An = A / scale                         # a for An is scale * a for A; keeps it O(1)
+    def negL(x):
+        h = An @ x
+        return -(O.inner(d, h, psd, sub.df) - 0.5 * O.inner(h, h, psd, sub.df))
+    res = optimize.minimize(negL, np.zeros(4), method="BFGS", options=dict(gtol=1e-12))
+    assert -negL(a * scale) >= -res.fun - 1e-9 * abs(res.fun)
+
+
+def test_extrinsic_face_on_closed_form():
+    """iota = 0: a = (cos u, -sin u, -sin u, -cos u) / D with u = 2 psi + phi_c,
+    so A+ = -Ax = 2 / D and only 2 psi + phi_c is defined (App. B)."""
+    from oracle import extrinsic as X
+    D, u = 2.5, 0.7
+    a = np.array([np.cos(u), -np.sin(u), -np.sin(u), -np.cos(u)]) / D
+    np.testing.assert_allclose(X.forward(D, 0.0, 0.2, u - 0.4), a, atol=1e-15)
+    out = X.inverse(a)
+    np.testing.assert_allclose(out[0], D, rtol=1e-14)
+    assert abs(out[1]) < 1e-7
+    np.testing.assert_allclose(X.forward(*out), a, atol=1e-12)
+
+
+def test_extrinsic_round_trip():
+    """App. B inverse of the forward map: D_L and iota come back; (psi, phi_c)
+    come back modulo the (pi/2, pi) symmetry, so the forward map of the
+    recovered values reproduces a."""
+    from oracle import extrinsic as X
+    rng = np.random.default_rng(12)
+    n = 5000
+    D = rng.uniform(0.5, 5.0, n)
+    iota = np.arccos(rng.uniform(-0.95, 0.95, n))
+    psi = rng.uniform(0.0, np.pi, n)
+    phic = rng.uniform(0.0, 2 * np.pi, n)
+    a = X.forward(D, iota, psi, phic)
+    out = X.inverse(a)
+    np.testing.assert_allclose(out[:, 0], D, rtol=1e-10)
+    np.testing.assert_allclose(out[:, 1], iota, atol=1e-9)
+    np.testing.assert_allclose(X.forward(*out.T), a, atol=1e-10 * np.abs(a).max())
+    dpsi = np.mod(out[:, 2] - psi, np.pi / 2)
+    assert np.all(np.minimum(dpsi, np.pi / 2 - dpsi) < 1e-8)
+    np.testing.assert_allclose(X.forward(D, iota, psi + np.pi / 2, phic + np.pi), a, atol=1e-14)
