@@ -105,6 +105,11 @@ int fstat_plan_create(fstat_plan_t *plan, const fstat_data_desc *data, const fst
  *   F_hat    [n]   out: (1/Np) sum_l F_l
  *   F_part   [n][part_stride] out: per-partition F_l (entries l >= Np untouched),
  *            or NULL; part_stride must be >= max Np when given
+ *   amps     [n][part_stride][4] out: per-partition maximum-likelihood
+ *            amplitudes a_1..a_4 = M^{-1} N (Eq. aandMN3) in the App. B basis
+ *            of fstat_waveform (unit template amplitude), the minimum-norm
+ *            maximiser when M is singular; 0 for empty partitions and NaN for
+ *            invalid particles (entries l >= Np untouched), or NULL
  *   flags    FSTAT_DEVICE_PTRS and/or FSTAT_EVAL_MIXED
  * Partition l covers e_l <= f < e_{l+1}, e_l = f_lo + (f_hi - f_lo) l / Np,
  * with [f_lo, f_hi] the template's frequency range during [0, T_obs] clipped
@@ -113,8 +118,26 @@ int fstat_plan_create(fstat_plan_t *plan, const fstat_data_desc *data, const fst
  * with the pseudo-inverse.  n = 0 is a no-op.  EINVAL: n < 0, np < 1,
  * part_stride too small, precision not built into the plan.               */
 int fstat_eval(fstat_plan_t plan, const double *params, int64_t n, const int32_t *np,
-               int32_t np_uniform, double *F_hat, double *F_part, int64_t part_stride,
-               uint32_t flags, void *hip_stream);
+               int32_t np_uniform, double *F_hat, double *F_part, double *amps,
+               int64_t part_stride, uint32_t flags, void *hip_stream);
+
+/* Extrinsic parameters from the amplitudes (App. B, Eq. extrinPara).
+ *   amps    [n][4] a_1..a_4 as fstat_eval writes them
+ *   params  [n][6] theta6 of the same rows, or NULL
+ *   out     [n][4] out: D_L, iota in [0, pi], psi in (-pi/2, pi/2], phi_c in
+ *           (-pi, pi]
+ * The arctangents are two-argument: psi = atan2(A+ a4 - Ax a1, -(Ax a2 +
+ * A+ a3)) / 2, c = sgn(sin 2 psi) (+1 at 0), phi_c = atan2(c (A+ a4 - Ax a1),
+ * -c (Ax a3 + A+ a2)); (psi + pi/2, phi_c + pi) describes the same a.  At
+ * iota = 0 or pi only 2 psi +- phi_c is defined and psi = 0 is returned.
+ * Without params D_L is in the units of 1/a (the unit template amplitude);
+ * with params it is in metres, through the App. A amplitude constant
+ * A = -sqrt(5/24) Mc^{5/6} / (pi^{2/3} D_L), whose sign turns phi_c by pi.
+ * All-zero a gives (inf, NaN, NaN, NaN).  Flags: FSTAT_DEVICE_PTRS (amps,
+ * params and out on the device; the call is then stream-ordered, otherwise
+ * it waits).  EINVAL: n < 0, null amps or out, invalid chirp mass (host).  */
+int fstat_extrinsic(const double *amps, const double *params, int64_t n, double *out,
+                    uint32_t flags, void *hip_stream);
 
 /* Template signal x_X(f_j) = sum_i a_i A^i(f_j) on a grid (for injections):
  * the App. A waveform with phi_c = 0, amplitude f^{-7/6}, through the TDI-X

@@ -110,7 +110,7 @@ int eval_blocks(fstat_plan_s* P, bool mixed) {
 int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t* np,
                 int32_t np_uniform, int32_t stride, double* F_hat, double* F_part,
                 int64_t part_stride, bool mixed, hipStream_t s, const uint8_t* skip,
-                bool allow_profile, bool surrogate, bool exact) {
+                bool allow_profile, bool surrogate, bool exact, double* amps) {
   const int chunk = chunk_for(P, mixed);
   if (!exact && chunk > interp_max_tile(mixed))
     return set_error(FSTAT_EINVAL, "work-item size %d exceeds the LDS tile limit %d (use a smaller "
@@ -136,7 +136,8 @@ int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t*
     (void)hipEventRecord(ev[3], s);
     P->events.push_back(ev);
   }
-  launch_solve_mean(n, stride, P->ws, F_hat, F_part, part_stride, prof ? P->bin_counter : nullptr, s);
+  launch_solve_mean(n, stride, P->ws, F_hat, F_part, amps, part_stride, P->umax,
+                    prof ? P->bin_counter : nullptr, s);
   return hip_check(hipGetLastError(), "kernel launch");
 }
 
@@ -306,7 +307,7 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
                                                 P->device), "device attribute");
   if (!rc && interp_tables_init() != 0)
     rc = set_error(FSTAT_EDEVICE, "could not upload the interpolation tables");
-  double *dd = nullptr, *dp = nullptr, *umax = nullptr;
+  double *dd = nullptr, *dp = nullptr;
   if (!rc) rc = dev_alloc(&P->b64.wr, nb, "alloc wr");
   if (!rc) rc = dev_alloc(&P->b64.wi, nb, "alloc wi");
   if (!rc) rc = dev_alloc(&P->b64.u, nb, "alloc u");
@@ -319,7 +320,7 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
     if (!rc) rc = dev_alloc(&P->b32.s0, nb, "alloc s032");
     if (!rc) rc = dev_alloc(&P->b32.c0, nb, "alloc c032");
   }
-  if (!rc) rc = dev_alloc(&umax, 1, "alloc umax");
+  if (!rc) rc = dev_alloc(&P->umax, 1, "alloc umax");
   if (!rc && (flags & FSTAT_PROFILE)) {
     P->profile = true;
     rc = dev_alloc(&P->bin_counter, 1, "alloc counter");
@@ -339,14 +340,13 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
   }
   if (!rc) {
     launch_prep(P->grid, ddata, dpsd, P->b64, s);
-    launch_max(P->b64.u, nb, umax, s);
-    launch_scale(P->grid, umax, P->b64, P->b32, s);
+    launch_max(P->b64.u, nb, P->umax, s);
+    launch_scale(P->grid, P->umax, P->b64, P->b32, s);
     rc = hip_check(hipGetLastError(), "prep launch");
   }
   if (!rc) rc = hip_check(hipStreamSynchronize(s), "plan prep");
   dev_free(dd);
   dev_free(dp);
-  dev_free(umax);
   if (rc) {
     fstat_plan_destroy(P);
     return rc;
@@ -373,6 +373,7 @@ void fstat_plan_destroy(fstat_plan_t P) {
   dev_free(P->ws.tile_items);
   dev_free(P->ws.tile_ctr); dev_free(P->ws.xflag); dev_free(P->ws.rec); dev_free(P->ws.xerr); dev_free(P->ws.refine); dev_free(P->ws.nrefine);
   dev_free(P->io.params); dev_free(P->io.np); dev_free(P->io.F_hat); dev_free(P->io.F_part);
+  dev_free(P->io.amps); dev_free(P->umax);
   pso_release(P);
   sur_release(P);
   for (auto& e : P->events)
@@ -433,8 +434,8 @@ int fstat_profile_read(fstat_plan_t P, int reset, double* kernel_ms, double* mai
 }
 
 int fstat_eval(fstat_plan_t P, const double* params, int64_t n, const int32_t* np,
-               int32_t np_uniform, double* F_hat, double* F_part, int64_t part_stride,
-               uint32_t flags, void* hip_stream) {
+               int32_t np_uniform, double* F_hat, double* F_part, double* amps,
+               int64_t part_stride, uint32_t flags, void* hip_stream) {
   g_err.clear();
   if (!P) return set_error(FSTAT_EINVAL, "null plan");
   if (n < 0) return set_error(FSTAT_EINVAL, "n < 0");
@@ -454,13 +455,14 @@ int fstat_eval(fstat_plan_t P, const double* params, int64_t n, const int32_t* n
     stride = (int32_t)part_stride;
   } else {
     if (np_uniform < 1 || np_uniform > 65536) return set_error(FSTAT_EINVAL, "np_uniform out of range");
-    if (F_part && part_stride < np_uniform) return set_error(FSTAT_EINVAL, "part_stride < np");
+    if ((F_part || amps) && part_stride < np_uniform)
+      return set_error(FSTAT_EINVAL, "part_stride < np");
     stride = np_uniform;
   }
   hipStream_t s = (hipStream_t)hip_stream;
   if (dev)
     return eval_device(P, params, n, np, np_uniform, stride, F_hat, F_part, part_stride, mixed, s,
-                       nullptr, true, sur, exact);
+                       nullptr, true, sur, exact, amps);
   // host pointers: validate, stage, run, copy back
   for (int64_t i = 0; i < n; ++i) {
     const double* t = params + 6 * i;
@@ -475,21 +477,27 @@ int fstat_eval(fstat_plan_t P, const double* params, int64_t n, const int32_t* n
   if ((rc = ensure(&P->io.params, &P->cap.params, (size_t)n * 6, "alloc params"))) return rc;
   if ((rc = ensure(&P->io.np, &P->cap.np, (size_t)n, "alloc np"))) return rc;
   if ((rc = ensure(&P->io.F_hat, &P->cap.F_hat, (size_t)n, "alloc F_hat"))) return rc;
-  int64_t ps = F_part ? part_stride : 0;
+  int64_t ps = (F_part || amps) ? part_stride : 0;
   if (F_part && (rc = ensure(&P->io.F_part, &P->cap.F_part, (size_t)n * ps, "alloc F_part"))) return rc;
+  if (amps && (rc = ensure(&P->io.amps, &P->cap.amps, (size_t)n * ps * 4, "alloc amps"))) return rc;
   if ((rc = hip_check(hipMemcpyAsync(P->io.params, params, sizeof(double) * 6 * n,
                                      hipMemcpyHostToDevice, s), "copy params"))) return rc;
   if (np && (rc = hip_check(hipMemcpyAsync(P->io.np, np, sizeof(int32_t) * n,
                                            hipMemcpyHostToDevice, s), "copy np"))) return rc;
   if (F_part && (rc = hip_check(hipMemcpyAsync(P->io.F_part, F_part, sizeof(double) * n * ps,
                                                hipMemcpyHostToDevice, s), "copy F_part"))) return rc;
+  if (amps && (rc = hip_check(hipMemcpyAsync(P->io.amps, amps, sizeof(double) * n * ps * 4,
+                                             hipMemcpyHostToDevice, s), "copy amps"))) return rc;
   rc = eval_device(P, P->io.params, n, np ? P->io.np : nullptr, np_uniform, stride, P->io.F_hat,
-                   F_part ? P->io.F_part : nullptr, ps, mixed, s, nullptr, true, sur, exact);
+                   F_part ? P->io.F_part : nullptr, ps, mixed, s, nullptr, true, sur, exact,
+                   amps ? P->io.amps : nullptr);
   if (rc) return rc;
   if ((rc = hip_check(hipMemcpyAsync(F_hat, P->io.F_hat, sizeof(double) * n,
                                      hipMemcpyDeviceToHost, s), "copy F_hat"))) return rc;
   if (F_part && (rc = hip_check(hipMemcpyAsync(F_part, P->io.F_part, sizeof(double) * n * ps,
                                                hipMemcpyDeviceToHost, s), "copy F_part"))) return rc;
+  if (amps && (rc = hip_check(hipMemcpyAsync(amps, P->io.amps, sizeof(double) * n * ps * 4,
+                                             hipMemcpyDeviceToHost, s), "copy amps"))) return rc;
   return hip_check(hipStreamSynchronize(s), "eval");
 }
 
@@ -535,6 +543,42 @@ int fstat_waveform(double T_obs, double df, int64_t k_lo, int64_t nbins, const d
   if (!rc) rc = hip_check(hipStreamSynchronize(s), "waveform");
   dev_free(ws.pc); dev_free(ws.bounds); dev_free(ws.cnt);
   dev_free(dpar); dev_free(damp); dev_free(dout);
+  return rc;
+}
+
+int fstat_extrinsic(const double* amps, const double* params, int64_t n, double* out,
+                    uint32_t flags, void* hip_stream) {
+  g_err.clear();
+  if (n < 0) return set_error(FSTAT_EINVAL, "n < 0");
+  if (n == 0) return FSTAT_OK;
+  if (!amps || !out) return set_error(FSTAT_EINVAL, "null amps or out");
+  const bool dev = (flags & FSTAT_DEVICE_PTRS) != 0;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (dev) {
+    launch_extrinsic(amps, params, n, out, s);
+    return hip_check(hipGetLastError(), "extrinsic launch");
+  }
+  if (params)
+    for (int64_t i = 0; i < n; ++i)
+      if (!(params[6 * i + 1] > 0.0) || !std::isfinite(params[6 * i + 1]))
+        return set_error(FSTAT_EINVAL, "particle %lld has an invalid chirp mass", (long long)i);
+  double *da = nullptr, *dpar = nullptr, *dout = nullptr;
+  int rc = dev_alloc(&da, (size_t)n * 4, "alloc amps");
+  if (!rc) rc = dev_alloc(&dout, (size_t)n * 4, "alloc out");
+  if (!rc && params) rc = dev_alloc(&dpar, (size_t)n * 6, "alloc params");
+  if (!rc) rc = hip_check(hipMemcpyAsync(da, amps, sizeof(double) * 4 * n, hipMemcpyHostToDevice, s),
+                          "copy amps");
+  if (!rc && params)
+    rc = hip_check(hipMemcpyAsync(dpar, params, sizeof(double) * 6 * n, hipMemcpyHostToDevice, s),
+                   "copy params");
+  if (!rc) {
+    launch_extrinsic(da, dpar, n, dout, s);
+    rc = hip_check(hipGetLastError(), "extrinsic launch");
+  }
+  if (!rc) rc = hip_check(hipMemcpyAsync(out, dout, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, s),
+                          "copy out");
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "extrinsic");
+  dev_free(da); dev_free(dpar); dev_free(dout);
   return rc;
 }
 

@@ -29,18 +29,20 @@ struct fstat_plan_s {
   fstat::BinData<double> b64{};
   fstat::BinData<float> b32{};
   fstat::WorkSpace ws{};
+  double* umax = nullptr;           // max of u before scaling (the scale of the amplitudes)
   struct {
     size_t pc = 0, bounds = 0, cnt = 0, off = 0, total = 0, items = 0, partials = 0, Fl = 0;
     size_t direct = 0, ndirect = 0, tcnt = 0, tcur = 0, toff = 0, uoff = 0, tile_items = 0,
            tile_ctr = 0;
     size_t xflag = 0, refine = 0, nrefine = 0, rec = 0, xerr = 0, bsum = 0;
-    size_t params = 0, np = 0, F_hat = 0, F_part = 0;
+    size_t params = 0, np = 0, F_hat = 0, F_part = 0, amps = 0;
   } cap;
   struct {
     double* params = nullptr;
     int32_t* np = nullptr;
     double* F_hat = nullptr;
     double* F_part = nullptr;
+    double* amps = nullptr;
   } io;
   PsoState* pso = nullptr;
   // profiling (FSTAT_PROFILE)
@@ -67,7 +69,8 @@ int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride, int chunk = 0);
 int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t* np,
                 int32_t np_uniform, int32_t stride, double* F_hat, double* F_part,
                 int64_t part_stride, bool mixed, hipStream_t s, const uint8_t* skip = nullptr,
-                bool allow_profile = true, bool surrogate = false, bool exact = false);
+                bool allow_profile = true, bool surrogate = false, bool exact = false,
+                double* amps = nullptr);
 int sur_ensure(fstat_plan_s* P, int64_t n, int32_t stride);
 int sur_prepare(fstat_plan_s* P, int64_t n, int32_t stride, hipStream_t s);
 void sur_release(fstat_plan_s* P);

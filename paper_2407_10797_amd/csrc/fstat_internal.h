@@ -509,4 +509,44 @@ __host__ __device__ __forceinline__ double solve_partition(const double* a) {
   return 0.5 * (pr * pr + pi * pi) / (lp * n2);
 }
 
+// ---- maximum-likelihood amplitudes of a partition (Eq. aandMN3) -------------
+// The log-likelihood over the complex pair beta = (beta_+, beta_x) of the
+// templates (T+ g, Tx g) is Re(beta^H z) - 1/2 beta^H H beta (up to the bin
+// weighting), maximised by beta = H^{-1} z; when H is rank deficient the
+// pseudo-inverse keeps the lambda_+ eigendirection only (the minimum-norm
+// maximiser).  acc as for solve_partition; out {Re, Im} beta_+, {Re, Im} beta_x.
+__host__ __device__ __forceinline__ void solve_beta(const double* a, double* out) {
+  double zpr = a[0], zpi = a[1], zxr = a[2], zxi = a[3];
+  double P = a[4], Q = a[5], rr = a[6], ri = a[7];
+  for (int k = 0; k < 4; ++k) out[k] = 0.0;
+  double hs = 0.5 * (P + Q), hd = 0.5 * (P - Q);
+  double rad = sqrt(hd * hd + rr * rr + ri * ri);
+  double lp = hs + rad;
+  if (!(lp > 0.0)) return;
+  double det = P * Q - (rr * rr + ri * ri);
+  double lm = det / lp;
+  if (lm > kRankCut * lp) {
+    // H^{-1} = [[Q, -conj R], [-R, P]] / det
+    double cxr = rr * zxr + ri * zxi, cxi = rr * zxi - ri * zxr;   // conj(R) z_x
+    double rpr = rr * zpr - ri * zpi, rpi = rr * zpi + ri * zpr;   // R z_+
+    out[0] = (Q * zpr - cxr) / det;
+    out[1] = (Q * zpi - cxi) / det;
+    out[2] = (P * zxr - rpr) / det;
+    out[3] = (P * zxi - rpi) / det;
+    return;
+  }
+  double v1r, v1i, v2r, v2i;
+  if (P >= Q) { v1r = lp - Q; v1i = 0.0; v2r = rr; v2i = ri; }
+  else        { v1r = rr; v1i = -ri; v2r = lp - P; v2i = 0.0; }
+  double n2 = v1r * v1r + v1i * v1i + v2r * v2r + v2i * v2i;
+  if (!(n2 > 0.0)) return;
+  double pr = v1r * zpr + v1i * zpi + v2r * zxr + v2i * zxi;     // v^H z
+  double pi = v1r * zpi - v1i * zpr + v2r * zxi - v2i * zxr;
+  double sr = pr / (lp * n2), si = pi / (lp * n2);
+  out[0] = v1r * sr - v1i * si;
+  out[1] = v1r * si + v1i * sr;
+  out[2] = v2r * sr - v2i * si;
+  out[3] = v2r * si + v2i * sr;
+}
+
 }  // namespace fstat

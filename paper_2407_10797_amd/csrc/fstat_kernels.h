@@ -74,8 +74,10 @@ void launch_sur_check(const Grid& g, int32_t stride, int64_t n, const WorkSpace&
                       const float* ynn, double* ek, double* mm, double thr,
                       unsigned long long* counters, hipStream_t s);
 void launch_solve_mean(int64_t n, int32_t stride, const WorkSpace& ws, double* F_hat,
-                       double* F_part, int64_t part_stride, unsigned long long* bin_counter,
-                       hipStream_t s);
+                       double* F_part, double* amps, int64_t part_stride, const double* umax,
+                       unsigned long long* bin_counter, hipStream_t s);
+void launch_extrinsic(const double* amps, const double* params, int64_t n, double* out,
+                      hipStream_t s);
 void launch_waveform(const Grid& g, const PartConst* pc, const double* amps,
                      double* out, hipStream_t s);
 

@@ -1295,10 +1295,35 @@ __global__ void k_sur_decide(PartConst* __restrict__ pc, int64_t n, int32_t stri
 // ---------------------------------------------------------------------------
 // solve and mean
 // ---------------------------------------------------------------------------
+// Constant phase (turns) the statistic's template drops and the App. A
+// waveform carries: -1/8 and the f-independent part of the alpha_5 term,
+// c5' cN vfac^5 (1 + 3 ln sqrt 6).
+__device__ __forceinline__ double dropped_phase(const PartConst& P) {
+  double ph0 = -0.125 + P.c5v5 * (1.0 + 1.5 * log(6.0));
+  return ph0 - rint(ph0);
+}
+
+// a_1..a_4 of the App. B basis from the pair beta solved against the scaled
+// bin data (w, u) -> (gam w, gam^2 u): the template's beta is gam beta, the
+// dropped phase turns it by e^{2 pi i ph0}, and s = (a1 - i a3) T+ g +
+// (-a2 + i a4) Tx g.
+__device__ __forceinline__ void amps_from_beta(const PartConst& P, const double* b, double gam,
+                                               double* a) {
+  double sc, cc;
+  sincospi(2.0 * dropped_phase(P), &sc, &cc);
+  const double pr = gam * (b[0] * cc - b[1] * sc), pi = gam * (b[1] * cc + b[0] * sc);
+  const double xr = gam * (b[2] * cc - b[3] * sc), xi = gam * (b[3] * cc + b[2] * sc);
+  a[0] = pr;
+  a[1] = -xr;
+  a[2] = -pi;
+  a[3] = xi;
+}
+
 __global__ void k_solve(const PartConst* __restrict__ pc, int64_t n, int32_t stride,
                         const int32_t* __restrict__ cnt, const int32_t* __restrict__ off,
                         const double* __restrict__ partials, double* __restrict__ Fl,
-                        double* __restrict__ F_part, int64_t part_stride) {
+                        double* __restrict__ F_part, int64_t part_stride,
+                        double* __restrict__ amps, const double* __restrict__ umax) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n * stride) return;
   int64_t p = q / stride;
@@ -1306,6 +1331,7 @@ __global__ void k_solve(const PartConst* __restrict__ pc, int64_t n, int32_t str
   const PartConst& P = pc[p];
   if (l >= P.np || P.status == kStatusInvalid) return;
   double F = 0.0;
+  double am[4] = {0.0, 0.0, 0.0, 0.0};
   if (P.status == kStatusOk) {
     double a[8], e[8];
     for (int k = 0; k < 8; ++k) a[k] = e[k] = 0.0;
@@ -1319,22 +1345,33 @@ __global__ void k_solve(const PartConst* __restrict__ pc, int64_t n, int32_t str
       }
     for (int k = 0; k < 8; ++k) a[k] += e[k];
     F = solve_partition(a);
+    if (amps) {
+      double beta[4];
+      solve_beta(a, beta);
+      const double m = umax[0];
+      amps_from_beta(P, beta, m > 0.0 ? sqrt(1.0 / m) : 1.0, am);
+    }
   }
   Fl[q] = F;
   if (F_part) F_part[p * part_stride + l] = F;
+  if (amps)
+    for (int k = 0; k < 4; ++k) amps[(p * part_stride + l) * 4 + k] = am[k];
 }
 
 __global__ void k_mean(const PartConst* __restrict__ pc, int64_t n, int32_t stride,
                        const double* __restrict__ Fl, double* __restrict__ F_hat,
                        double* __restrict__ F_part, int64_t part_stride,
-                       unsigned long long* __restrict__ bin_counter) {
+                       double* __restrict__ amps, unsigned long long* __restrict__ bin_counter) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const PartConst& P = pc[p];
   if (P.status == kStatusInvalid) {
     F_hat[p] = __builtin_nan("");
-    if (F_part)
-      for (int l = 0; l < P.np && l < part_stride; ++l) F_part[p * part_stride + l] = __builtin_nan("");
+    for (int l = 0; l < P.np && l < part_stride; ++l) {
+      if (F_part) F_part[p * part_stride + l] = __builtin_nan("");
+      if (amps)
+        for (int k = 0; k < 4; ++k) amps[(p * part_stride + l) * 4 + k] = __builtin_nan("");
+    }
     return;
   }
   if (P.status == kStatusEmpty) {
@@ -1365,12 +1402,9 @@ __global__ void k_waveform(Grid g, const PartConst* __restrict__ pc,
   sincospi(kLs * f, &s0, &c0);
   double cph, sph, tpr, tpi, txr, txi;
   template_fp64(P, f, s0, c0, cph, sph, tpr, tpi, txr, txi);
-  // restore the constant phases the statistic drops: -pi/4 (App. A) and the
-  // f-independent part of the alpha_5 term, c5' cN vfac^5 (1 + 3 ln sqrt 6)
-  double ph0 = -0.125 + P.c5v5 * (1.0 + 1.5 * log(6.0));
-  ph0 -= rint(ph0);
+  // restore the constant phase the statistic drops
   double sc, cc;
-  sincospi(2.0 * ph0, &sc, &cc);
+  sincospi(2.0 * dropped_phase(P), &sc, &cc);
   double cps = cph * cc - sph * sc, sps = sph * cc + cph * sc;   // e^{i Phi_full}
   // full transfer: C(f) times the particle part T''
   double x0 = kPi * kLs * f;
@@ -1388,6 +1422,64 @@ __global__ void k_waveform(Grid g, const PartConst* __restrict__ pc,
   // multiply by e^{-i Phi} = cps - i sps
   out[2 * j] = amp * (hr * cps + hi * sps);
   out[2 * j + 1] = amp * (hi * cps - hr * sps);
+}
+
+// ---------------------------------------------------------------------------
+// extrinsic parameters from a_1..a_4 (App. B, Eq. extrinPara), one row per
+// thread.  D_L = 2 / A and iota = arccos(-Ax / A) as printed.  For psi and
+// phi_c the kernel uses the phases of the two circular parts of a,
+//   (a1 + a4) + i (a2 - a3) = r1 e^{i (phi_c - 2 psi)},
+//   (a1 - a4) - i (a2 + a3) = r2 e^{i (phi_c + 2 psi)},
+// which give the same (psi, phi_c) as the printed arctangent ratios (whose
+// arguments are 2 r1 r2 sin 2psi sin phi_c, 2 r1 r2 cos 2psi sin phi_c and
+// 2 r1 r2 sin 2psi cos phi_c, read with the sign c = sgn(sin 2 psi)) and the
+// same representative, phi_c in (0, pi] and psi in (-pi/2, pi/2], but stay
+// accurate where those ratios approach 0/0.  At iota = 0 or pi one circular
+// part vanishes (modulus below 64 ulp of the other) and only the other's
+// phase is defined: psi = 0, phi_c = that phase.  All-zero a gives
+// (inf, nan, nan, nan).  With the chirp mass (params != null) D_L is
+// converted to metres with the App. A constant |A| D_L = sqrt(5/24)
+// Mc^{5/6} / pi^{2/3} (geometric units), whose negative sign turns phi_c by pi.
+// ---------------------------------------------------------------------------
+__global__ void k_extrinsic(const double* __restrict__ amps, const double* __restrict__ params,
+                            int64_t n, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a1 = amps[4 * i], a2 = amps[4 * i + 1], a3 = amps[4 * i + 2], a4 = amps[4 * i + 3];
+  const double p1 = a1 + a4, p2 = a2 - a3, m1 = a1 - a4, m2 = -(a2 + a3);
+  const double r1 = sqrt(p1 * p1 + p2 * p2), r2 = sqrt(m1 * m1 + m2 * m2);
+  const double Ap = r1 + r2, Ax = r1 - r2;
+  const double A = Ap + sqrt(fmax((Ap - Ax) * (Ap + Ax), 0.0));   // no cancellation at iota ~ 0
+  double D, iota, psi, phic;
+  if (!(A > 0.0)) {
+    const double nan = __builtin_nan("");
+    D = (A == 0.0) ? __builtin_inf() : nan;
+    iota = psi = phic = nan;
+  } else {
+    D = 2.0 / A;
+    iota = acos(fmin(fmax(-Ax / A, -1.0), 1.0));
+    const double th1 = atan2(p2, p1);    // phi_c - 2 psi
+    const double th2 = atan2(m2, m1);    // phi_c + 2 psi
+    if (fmin(r1, r2) <= 64.0 * 2.220446049250313e-16 * fmax(r1, r2)) {
+      psi = 0.0;
+      phic = (r1 < r2) ? th2 : th1;
+    } else {
+      phic = 0.5 * (th1 + th2);          // (-pi, pi], defined modulo pi
+      if (phic <= 0.0) phic += kPi;
+      double d = th2 - phic;             // 2 psi, in (-2 pi, pi]
+      if (d <= -kPi) d += 2.0 * kPi;
+      psi = 0.5 * d;
+    }
+    if (params) {
+      const double mc = params[6 * i + 1] * kMsunS;
+      D *= kC * sqrt(5.0 / 24.0) * pow(mc, 5.0 / 6.0) / pow(kPi, 2.0 / 3.0);
+      phic += (phic > 0.0) ? -kPi : kPi;
+    }
+  }
+  out[4 * i] = D;
+  out[4 * i + 1] = iota;
+  out[4 * i + 2] = psi;
+  out[4 * i + 3] = phic;
 }
 
 }  // namespace fstat
@@ -1497,13 +1589,13 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
 }
 
 void launch_solve_mean(int64_t n, int32_t stride, const WorkSpace& ws, double* F_hat,
-                       double* F_part, int64_t part_stride, unsigned long long* bin_counter,
-                       hipStream_t s) {
+                       double* F_part, double* amps, int64_t part_stride, const double* umax,
+                       unsigned long long* bin_counter, hipStream_t s) {
   int64_t m = n * stride;
   hipLaunchKernelGGL(k_solve, dim3(nblk(m, 256)), dim3(256), 0, s, ws.pc, n, stride, ws.cnt,
-                     ws.off, ws.partials, ws.Fl, F_part, part_stride);
+                     ws.off, ws.partials, ws.Fl, F_part, part_stride, amps, umax);
   hipLaunchKernelGGL(k_mean, dim3(nblk(n, 256)), dim3(256), 0, s, ws.pc, n, stride, ws.Fl, F_hat,
-                     F_part, part_stride, bin_counter);
+                     F_part, part_stride, amps, bin_counter);
 }
 
 void launch_sur_data(uint64_t seed, int64_t n, float* X, float* T, hipStream_t s) {
@@ -1523,6 +1615,11 @@ void launch_sur_check(const Grid& g, int32_t stride, int64_t n, const WorkSpace&
                      ws.bounds, stride, n, ynn, ek, mm);
   hipLaunchKernelGGL(k_sur_decide, dim3(nblk(n, 128)), dim3(128), 0, s, ws.pc, n, stride, mm, thr,
                      counters);
+}
+
+void launch_extrinsic(const double* amps, const double* params, int64_t n, double* out,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_extrinsic, dim3(nblk(n, 256)), dim3(256), 0, s, amps, params, n, out);
 }
 
 void launch_waveform(const Grid& g, const PartConst* pc, const double* amps,

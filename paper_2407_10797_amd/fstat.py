@@ -28,7 +28,7 @@ FSTAT_EVAL_SURROGATE = 8
 FSTAT_AUTOTUNE_FORCE = 16
 FSTAT_EVAL_EXACT = 32
 
-EXPORTS = ("fstat_plan_create", "fstat_eval", "fstat_waveform", "pso_stage",
+EXPORTS = ("fstat_plan_create", "fstat_eval", "fstat_extrinsic", "fstat_waveform", "pso_stage",
            "fstat_profile_read", "fstat_interp_stats", "fstat_autotune", "fstat_mlp_grad", "fstat_mlp_forward",
            "fstat_surrogate_train", "fstat_surrogate_stats", "fstat_plan_destroy",
            "fstat_last_error")
@@ -86,8 +86,10 @@ def lib() -> ctypes.CDLL:
         L.fstat_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(fstat_data_desc),
                                         ctypes.POINTER(fstat_opts), vp]
         L.fstat_plan_create.restype = ctypes.c_int
-        L.fstat_eval.argtypes = [vp, vp, i64, vp, i32, vp, vp, i64, u32, vp]
+        L.fstat_eval.argtypes = [vp, vp, i64, vp, i32, vp, vp, vp, i64, u32, vp]
         L.fstat_eval.restype = ctypes.c_int
+        L.fstat_extrinsic.argtypes = [vp, vp, i64, vp, u32, vp]
+        L.fstat_extrinsic.restype = ctypes.c_int
         L.fstat_waveform.argtypes = [ctypes.c_double, ctypes.c_double, i64, i64, vp, vp, vp, u32, vp]
         L.fstat_waveform.restype = ctypes.c_int
         L.pso_stage.argtypes = [vp, ctypes.POINTER(pso_stage_desc), ctypes.POINTER(pso_result), vp]
@@ -136,9 +138,14 @@ def fstat_plan_create(desc: fstat_data_desc, opts: fstat_opts | None = None, str
     return h
 
 
-def fstat_eval(plan, params, n, np_ptr, np_uniform, F_hat, F_part, part_stride, flags, stream=None):
-    _check(lib().fstat_eval(plan, params, int(n), np_ptr, int(np_uniform), F_hat, F_part,
+def fstat_eval(plan, params, n, np_ptr, np_uniform, F_hat, F_part, amps, part_stride, flags,
+               stream=None):
+    _check(lib().fstat_eval(plan, params, int(n), np_ptr, int(np_uniform), F_hat, F_part, amps,
                             int(part_stride), int(flags), stream))
+
+
+def fstat_extrinsic(amps, params, n, out, flags, stream=None):
+    _check(lib().fstat_extrinsic(amps, params, int(n), out, int(flags), stream))
 
 
 def fstat_waveform(T_obs, df, k_lo, nbins, params6, amps4, out, flags, stream=None):
@@ -246,8 +253,10 @@ class Plan:
         torch.cuda.current_stream().synchronize()
 
     def eval(self, params, np_parts=1, part_stride: int | None = None, mixed: bool = False,
-             want_parts: bool = False, surrogate: bool = False, exact: bool = False):
-        """F_hat [n] (and F_part [n, stride]) for params [n, 6] on the device."""
+             want_parts: bool = False, surrogate: bool = False, exact: bool = False,
+             want_amps: bool = False):
+        """F_hat [n] (and F_part [n, stride], amps [n, stride, 4]) for params
+        [n, 6] on the device."""
         torch = _torch()
         prm = torch.as_tensor(params).to("cuda", torch.float64).contiguous()
         n = prm.shape[0]
@@ -261,11 +270,18 @@ class Plan:
             npp, npu = np_t.data_ptr(), 0
             stride = part_stride or int(np_t.max().item())
         Fp = torch.zeros((n, stride), device="cuda", dtype=torch.float64) if want_parts else None
+        Am = torch.zeros((n, stride, 4), device="cuda", dtype=torch.float64) if want_amps else None
         flags = (FSTAT_DEVICE_PTRS | (FSTAT_EVAL_MIXED if mixed else 0)
                  | (FSTAT_EVAL_SURROGATE if surrogate else 0) | (FSTAT_EVAL_EXACT if exact else 0))
         fstat_eval(self.handle, prm.data_ptr(), n, npp, npu, F.data_ptr(),
-                   Fp.data_ptr() if Fp is not None else None, stride, flags, _stream())
-        return (F, Fp) if want_parts else F
+                   Fp.data_ptr() if Fp is not None else None,
+                   Am.data_ptr() if Am is not None else None, stride, flags, _stream())
+        out = (F,)
+        if want_parts:
+            out += (Fp,)
+        if want_amps:
+            out += (Am,)
+        return out if len(out) > 1 else F
 
     def pso(self, box, np_runs, n_part: int, iters: int, ring_k: int = 1, w=(0.7, 0.7),
             c1: float = 1.5, c2: float = 1.5, vmax: float = 0.5, seed: int = 1,
@@ -356,4 +372,20 @@ def waveform(T_obs, df, k_lo, nbins, params6, amps4):
     out = torch.empty(int(nbins), device="cuda", dtype=torch.complex128)
     fstat_waveform(T_obs, df, k_lo, nbins, p.data_ptr(), a.data_ptr(), out.data_ptr(),
                    FSTAT_DEVICE_PTRS, _stream())
+    return out
+
+
+def extrinsic(amps, params=None):
+    """(D_L, iota, psi, phi_c) [n, 4] from amplitudes [n, 4] on the device
+    (App. B); D_L in metres when params [n, 6] are given, else in 1/a units."""
+    torch = _torch()
+    a = torch.as_tensor(amps).to("cuda", torch.float64).reshape(-1, 4).contiguous()
+    p = None
+    if params is not None:
+        p = torch.as_tensor(params).to("cuda", torch.float64).reshape(-1, 6).contiguous()
+        if p.shape[0] != a.shape[0]:
+            raise ValueError("params and amps differ in rows")
+    out = torch.empty_like(a)
+    fstat_extrinsic(a.data_ptr(), p.data_ptr() if p is not None else None, a.shape[0],
+                    out.data_ptr(), FSTAT_DEVICE_PTRS, _stream())
     return out

@@ -14,7 +14,7 @@ def _declared():
 
 
 def test_header_declares_the_boundary():
-    assert _declared() == sorted(["fstat_plan_create", "fstat_eval", "fstat_waveform",
+    assert _declared() == sorted(["fstat_plan_create", "fstat_eval", "fstat_extrinsic", "fstat_waveform",
                                   "pso_stage", "fstat_profile_read", "fstat_interp_stats",
                                   "fstat_autotune",
                                   "fstat_mlp_grad", "fstat_mlp_forward",

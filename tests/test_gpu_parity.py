@@ -176,16 +176,16 @@ def test_host_pointer_errors(small, torch_cuda):
     prm = np.ascontiguousarray(bad[None, :])
     out = np.zeros(1)
     with pytest.raises(fstat.FstatError) as e:
-        fstat.fstat_eval(s["plan"].handle, prm.ctypes.data, 1, None, 4, out.ctypes.data, None, 0, 0)
+        fstat.fstat_eval(s["plan"].handle, prm.ctypes.data, 1, None, 4, out.ctypes.data, None, None, 0, 0)
     assert e.value.code == fstat.FSTAT_EINVAL and "invalid" in str(e.value)
     with pytest.raises(fstat.FstatError):
-        fstat.fstat_eval(s["plan"].handle, prm.ctypes.data, -1, None, 4, out.ctypes.data, None, 0, 0)
+        fstat.fstat_eval(s["plan"].handle, prm.ctypes.data, -1, None, 4, out.ctypes.data, None, None, 0, 0)
     # n = 0 is a no-op
-    fstat.fstat_eval(s["plan"].handle, prm.ctypes.data, 0, None, 4, out.ctypes.data, None, 0, 0)
+    fstat.fstat_eval(s["plan"].handle, prm.ctypes.data, 0, None, 4, out.ctypes.data, None, None, 0, 0)
     # host pointer path gives the same values as the device path
     good = np.ascontiguousarray(s["pts"][:8])
     outh = np.zeros(8)
-    fstat.fstat_eval(s["plan"].handle, good.ctypes.data, 8, None, 16, outh.ctypes.data, None, 0, 0)
+    fstat.fstat_eval(s["plan"].handle, good.ctypes.data, 8, None, 16, outh.ctypes.data, None, None, 0, 0)
     outd = s["plan"].eval(torch_cuda.from_numpy(good), 16).cpu().numpy()
     np.testing.assert_array_equal(outh, outd)
 

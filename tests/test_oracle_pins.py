@@ -443,6 +443,45 @@ def test_extrinsic_face_on_closed_form():
     np.testing.assert_allclose(X.forward(*out), a, atol=1e-12)
 
 
+def test_extrinsic_corners_and_representative():
+    """The printed ratios are 0/0 on sin 2psi sin phi_c = 0 and near iota = 0,
+    pi; on a grid of such corners (and on arbitrary a) the forward map of the
+    recovered values still reproduces a, and the representative is
+    phi_c in (0, pi], psi in (-pi/2, pi/2]."""
+    from oracle import extrinsic as X
+    worst = 0.0
+    for psi in (-2e-9, 0.0, 1e-9, np.pi / 2, np.pi / 2 - 1e-9, 0.3):
+        for phic in (0.9, 0.0, np.pi, 1e-12, -1e-9, np.pi + 1e-9, 2.0):
+            for iota in (0.7, 1e-5, np.pi - 1e-5, 1.5):
+                a = X.forward(1.0, iota, psi, phic)
+                worst = max(worst, float(np.abs(X.forward(*X.inverse(a)) - a).max()))
+    assert worst < 1e-13
+    a = np.random.default_rng(5).standard_normal((20000, 4))
+    out = X.inverse(a)
+    np.testing.assert_allclose(X.forward(*out.T), a, atol=1e-9)
+    assert np.all((out[:, 3] > 0.0) & (out[:, 3] <= np.pi))
+    assert np.all((out[:, 2] > -np.pi / 2) & (out[:, 2] <= np.pi / 2))
+    z = X.inverse(np.zeros(4))
+    assert np.isinf(z[0]) and np.all(np.isnan(z[1:]))
+
+
+def test_extrinsic_physical_units():
+    """App. A: h = A f^{-7/6} e^{-i Psi}, A = -sqrt(5/24) Mc^{5/6} / (pi^{2/3}
+    D_L); amplitudes of the unit-amplitude basis made with A D_L times the
+    App. B a_i give back D_L in metres and phi_c (the sign of A is a turn by
+    pi of phi_c, and with the representative phi_c in (0, pi] before that
+    turn, (psi, phi_c) = (0.4, 2.0) comes back as (0.4 - pi/2, 2.0 - pi))."""
+    from oracle import extrinsic as X
+    K = X.amplitude_constant(30.0)
+    mc_s = 30.0 * 4.925490947641267e-6
+    assert abs(K + 0.45643546458763845 * mc_s ** (5 / 6) / 2.1450293971110255) < 1e-18
+    D_m = 3.0857e25
+    a = K * X.forward(D_m / X.C_LIGHT, 1.0, 0.4, 2.0)
+    out = X.physical(X.inverse(a), 30.0)
+    np.testing.assert_allclose(out, [D_m, 1.0, 0.4 - np.pi / 2, 2.0 - np.pi], rtol=1e-12)
+    np.testing.assert_allclose(X.forward(D_m / X.C_LIGHT, *out[1:]), a / K, rtol=1e-12)
+
+
 def test_extrinsic_round_trip():
     """App. B inverse of the forward map: D_L and iota come back; (psi, phi_c)
     come back modulo the (pi/2, pi) symmetry, so the forward map of the
