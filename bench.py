@@ -34,12 +34,12 @@ PEAK_LANE_INSTR = 256 * 64 * 2.4e9
 # bytes read per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes
 # written per launch (WRITE_SIZE).
 MAIN_KERNEL = {"fp64": "k_eval_interp<false>", "mixed": "k_eval_interp<true>"}
-FLOP_PER_BIN = {"fp64": 187.2, "mixed": 117.4}
-VALU_PER_BIN = {"fp64": 144.8, "mixed": 88.1}
-TRAFFIC = {"fp64": (0.3475, 1.3102e8), "mixed": (0.3557, 1.3129e8)}
+FLOP_PER_BIN = {"fp64": 187.2, "mixed": 117.0}
+VALU_PER_BIN = {"fp64": 145.4, "mixed": 85.7}
+TRAFFIC = {"fp64": (0.5039, 1.3105e8), "mixed": (0.2731, 7.440e7)}
 # sha256 of the kernel sources those counters were taken on; the figures are
 # reported as null once the sources differ.
-COUNTERS_SRC_SHA = "bf572f06454fa7edb6b81f8f9fdf2e604f71bb088fb987a0b9c38f1dd9b20843"
+COUNTERS_SRC_SHA = "706577946fe4ac664300f6ce8545c364574e1fdcbf2f00060d15c511635d10c3"
 KERNEL_SOURCES = ("fstat_kernels.hip", "fstat_internal.h", "fstat_kernels.h")
 
 
