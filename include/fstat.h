@@ -196,6 +196,78 @@ typedef struct {
  * are written when the call returns.  EINVAL on bad sizes or boxes.       */
 int pso_stage(fstat_plan_t plan, const pso_stage_desc *desc, pso_result *result, void *hip_stream);
 
+/* ---- hierarchical search (Sec. III.B, Fig. 2) ------------------------------ */
+typedef struct {
+  double box[6][2];    /* full search range {lo, hi}: t_c [s], Mc [Msun], delta_mu,
+                          theta [rad], phi [rad], e0                              */
+  int32_t n_slices;    /* stage 1: the t_c range cut into this many equal,
+                          contiguous intervals (paper: 24)                        */
+  int32_t runs[3];     /* PSO runs per search space in stages 1..3 (24, 8, 48)  */
+  int32_t iters[3];    /* PSO iterations per run (8000, 8000, 15000)            */
+  int32_t np[3];       /* N_seg of the statistic (16, 16, 1)                    */
+  int32_t n_part;      /* particles per run, 1..1024 (128)                      */
+  int32_t ring_k;      /* ring radius of the local best; <= 0: global best      */
+  double w_start, w_end, c1, c2, vmax;   /* PSO constants as in pso_stage_desc */
+  double width2[2];    /* stage-2 box widths in t_c [s] and Mc [Msun]
+                          (0.01 yr, 0.6)                                          */
+  double width3[5];    /* stage-3 box widths in t_c [s], Mc [Msun], theta, phi,
+                          e0 (0.004 yr, 0.3, 0.4, 0.4, 0.006)                     */
+  uint64_t seed;       /* stage s uses PSO seed  seed + s * 0x9E3779B97F4A7C15  */
+  uint32_t flags[3];   /* per stage: FSTAT_EVAL_MIXED / _SURROGATE / _EXACT     */
+  int32_t use_graph;   /* as in pso_stage_desc                                  */
+  int32_t max_stage;   /* stop after this stage (1..3); 0 = 3                   */
+  const char *checkpoint; /* text file that keeps the results of finished stages
+                          (written after each stage, read to resume), or NULL  */
+} fstat_search_desc;
+
+typedef struct {
+  int32_t stages_done;      /* out: stages finished (resumed ones included)   */
+  int32_t stages_resumed;   /* out: stages taken from the checkpoint           */
+  double *stage1_x;         /* [n_slices][6] best of each t_c interval, or NULL */
+  double *stage1_F;         /* [n_slices], or NULL                              */
+  double *stage2_x;         /* [n_slices][6] best of each stage-2 space, or NULL */
+  double *stage2_F;         /* [n_slices], or NULL                              */
+  double stage3_x[2][6];    /* best of the stage-3 spaces around theta, pi - theta */
+  double stage3_F[2];
+  double best_x[6];         /* final intrinsic estimate (stage 3, else the last
+                               finished stage's best)                          */
+  double best_F;            /* its F_hat at that stage's N_seg                  */
+  double amps[4];           /* a_1..a_4 at best_x, fully coherent (N_seg = 1)  */
+  double extrinsic[4];      /* D_L [m], iota, psi, phi_c from amps (App. B)    */
+  double stage_ms[3];       /* wall time of each stage run here (0: resumed)   */
+  int64_t evals[3];         /* template evaluations per stage (runs x n_part x
+                               iters over all spaces)                          */
+} fstat_search_result;
+
+/* The three-stage search: stage 1 runs runs[0] PSO runs in each of n_slices
+ * equal t_c intervals of the full box and keeps the best of each interval;
+ * stage 2 centres a box of widths width2 in (t_c, Mc) on each of those, keeps
+ * the other parameters' full ranges, runs runs[1] runs in each and keeps the
+ * single best over all of them; stage 3 centres boxes of widths width3 in
+ * (t_c, Mc, theta, phi, e0) on that point and on its mirror theta -> pi - theta
+ * (delta_mu keeps its full range), runs runs[2] runs in each, and the best of
+ * the two is the estimate.  Boxes are clipped to the full box, except phi when
+ * the full box spans the whole circle (the statistic is periodic in phi).
+ * Every MAX takes the first of equal values.  Then the amplitudes a at the
+ * estimate (fstat_eval, N_seg = 1, FP64) and the extrinsic parameters
+ * (fstat_extrinsic with the chirp mass) are filled in.  All runs of a stage
+ * go to one pso_stage call (run index = space * runs + k).  With a checkpoint
+ * path, finished stages are read back if the file was written for the same
+ * descriptor and grid (else EINVAL) and each newly finished stage is
+ * written; max_stage stops early so that a long search can be split over
+ * several processes.  Waits for completion.  EINVAL on bad sizes or
+ * widths; errors of pso_stage pass through.                               */
+int fstat_search(fstat_plan_t plan, const fstat_search_desc *desc, fstat_search_result *result,
+                 void *hip_stream);
+
+/* The boxes one stage of fstat_search would search (host arithmetic only, no
+ * device call): stage 1 ignores `centres` and gives n_slices boxes; stage 2
+ * gives one box per centre (n_centres of them); stage 3 gives the two boxes
+ * around centres[0] (theta and pi - theta).  boxes_out: [n][6][2].  Returns
+ * the number of boxes, or a negative error code.                          */
+int fstat_search_boxes(const fstat_search_desc *desc, int32_t stage, const double *centres,
+                       int32_t n_centres, double *boxes_out);
+
 /* Diagnostics for plans created with FSTAT_PROFILE, accumulated since the
  * last reset, from HIP events recorded on the caller's stream: kernel_ms =
  * the whole bin-loop stage (interpolation nodes, tile grouping, the

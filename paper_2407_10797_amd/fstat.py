@@ -29,6 +29,7 @@ FSTAT_AUTOTUNE_FORCE = 16
 FSTAT_EVAL_EXACT = 32
 
 EXPORTS = ("fstat_plan_create", "fstat_eval", "fstat_extrinsic", "fstat_waveform", "pso_stage",
+           "fstat_search", "fstat_search_boxes",
            "fstat_profile_read", "fstat_interp_stats", "fstat_autotune", "fstat_mlp_grad", "fstat_mlp_forward",
            "fstat_surrogate_train", "fstat_surrogate_stats", "fstat_plan_destroy",
            "fstat_last_error")
@@ -58,6 +59,27 @@ class pso_stage_desc(ctypes.Structure):
 class pso_result(ctypes.Structure):
     _fields_ = [("best_x", ctypes.c_void_p), ("best_F", ctypes.c_void_p),
                 ("trace", ctypes.c_void_p), ("final_x", ctypes.c_void_p)]
+
+
+class fstat_search_desc(ctypes.Structure):
+    _fields_ = [("box", (ctypes.c_double * 2) * 6), ("n_slices", ctypes.c_int32),
+                ("runs", ctypes.c_int32 * 3), ("iters", ctypes.c_int32 * 3), ("np", ctypes.c_int32 * 3),
+                ("n_part", ctypes.c_int32), ("ring_k", ctypes.c_int32),
+                ("w_start", ctypes.c_double), ("w_end", ctypes.c_double), ("c1", ctypes.c_double),
+                ("c2", ctypes.c_double), ("vmax", ctypes.c_double),
+                ("width2", ctypes.c_double * 2), ("width3", ctypes.c_double * 5),
+                ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32 * 3), ("use_graph", ctypes.c_int32),
+                ("max_stage", ctypes.c_int32), ("checkpoint", ctypes.c_char_p)]
+
+
+class fstat_search_result(ctypes.Structure):
+    _fields_ = [("stages_done", ctypes.c_int32), ("stages_resumed", ctypes.c_int32),
+                ("stage1_x", ctypes.c_void_p), ("stage1_F", ctypes.c_void_p),
+                ("stage2_x", ctypes.c_void_p), ("stage2_F", ctypes.c_void_p),
+                ("stage3_x", (ctypes.c_double * 6) * 2), ("stage3_F", ctypes.c_double * 2),
+                ("best_x", ctypes.c_double * 6), ("best_F", ctypes.c_double),
+                ("amps", ctypes.c_double * 4), ("extrinsic", ctypes.c_double * 4),
+                ("stage_ms", ctypes.c_double * 3), ("evals", ctypes.c_int64 * 3)]
 
 
 class fstat_surrogate_desc(ctypes.Structure):
@@ -94,6 +116,11 @@ def lib() -> ctypes.CDLL:
         L.fstat_waveform.restype = ctypes.c_int
         L.pso_stage.argtypes = [vp, ctypes.POINTER(pso_stage_desc), ctypes.POINTER(pso_result), vp]
         L.pso_stage.restype = ctypes.c_int
+        L.fstat_search.argtypes = [vp, ctypes.POINTER(fstat_search_desc),
+                                   ctypes.POINTER(fstat_search_result), vp]
+        L.fstat_search.restype = ctypes.c_int
+        L.fstat_search_boxes.argtypes = [ctypes.POINTER(fstat_search_desc), i32, vp, i32, vp]
+        L.fstat_search_boxes.restype = ctypes.c_int
         L.fstat_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                          ctypes.POINTER(i64)]
@@ -155,6 +182,65 @@ def fstat_waveform(T_obs, df, k_lo, nbins, params6, amps4, out, flags, stream=No
 
 def pso_stage(plan, desc: pso_stage_desc, result: pso_result, stream=None):
     _check(lib().pso_stage(plan, ctypes.byref(desc), ctypes.byref(result), stream))
+
+
+def fstat_search(plan, desc: fstat_search_desc, result: fstat_search_result, stream=None):
+    _check(lib().fstat_search(plan, ctypes.byref(desc), ctypes.byref(result), stream))
+
+
+def fstat_search_boxes(desc: fstat_search_desc, stage, centres, n_centres, boxes_out):
+    n = lib().fstat_search_boxes(ctypes.byref(desc), int(stage), centres, int(n_centres), boxes_out)
+    if n < 0:
+        raise FstatError(n, fstat_last_error())
+    return n
+
+
+YEAR_S = 365.25 * 86400.0
+
+# Sec. III.B: 24 t_c intervals x 24 runs (N_seg 16, 8000 iterations), 24 spaces
+# x 8 runs, 2 spaces (theta, pi - theta) x 48 runs (N_seg 1, 15000
+# iterations); 128 particles; c1 = c2 = 2, vmax = 0.5 (Sec. III.A).
+PAPER_SEARCH = dict(n_slices=24, runs=(24, 8, 48), iters=(8000, 8000, 15000), np=(16, 16, 1),
+                    n_part=128, ring_k=1, w=(0.9, 0.4), c1=2.0, c2=2.0, vmax=0.5,
+                    width2=(0.01 * YEAR_S, 0.6),
+                    width3=(0.004 * YEAR_S, 0.3, 0.4, 0.4, 0.006))
+
+
+def search_desc(box, seed: int = 1, flags=(0, 0, 0), use_graph: bool = True, max_stage: int = 0,
+                checkpoint: str | None = None, **kw) -> fstat_search_desc:
+    """Descriptor for fstat_search: PAPER_SEARCH settings overridden by kw."""
+    c = dict(PAPER_SEARCH, **kw)
+    box = np.asarray(box, dtype=np.float64).reshape(6, 2)
+    d = fstat_search_desc()
+    for j in range(6):
+        d.box[j][0], d.box[j][1] = box[j]
+    d.n_slices = int(c["n_slices"])
+    for s in range(3):
+        d.runs[s], d.iters[s], d.np[s] = int(c["runs"][s]), int(c["iters"][s]), int(c["np"][s])
+        d.flags[s] = int(flags[s])
+    d.n_part, d.ring_k = int(c["n_part"]), int(c["ring_k"])
+    d.w_start, d.w_end = float(c["w"][0]), float(c["w"][1])
+    d.c1, d.c2, d.vmax = float(c["c1"]), float(c["c2"]), float(c["vmax"])
+    for j in range(2):
+        d.width2[j] = float(c["width2"][j])
+    for j in range(5):
+        d.width3[j] = float(c["width3"][j])
+    d.seed = int(seed)
+    d.use_graph = int(use_graph)
+    d.max_stage = int(max_stage)
+    d.checkpoint = checkpoint.encode() if checkpoint else None
+    return d
+
+
+def search_boxes(desc: fstat_search_desc, stage: int, centres=None) -> np.ndarray:
+    """Boxes [n, 6, 2] that stage `stage` of fstat_search searches."""
+    cen = None if centres is None else np.ascontiguousarray(np.atleast_2d(centres), dtype=np.float64)
+    nc = 0 if cen is None else cen.shape[0]
+    cap = {1: desc.n_slices, 2: nc, 3: 2}.get(int(stage), 0)
+    out = np.zeros((max(cap, 1), 6, 2))
+    n = fstat_search_boxes(desc, stage, cen.ctypes.data if cen is not None else None, nc,
+                           out.ctypes.data)
+    return out[:n]
 
 
 def fstat_profile_read(plan, reset: bool = True):
@@ -312,6 +398,23 @@ class Plan:
         if final_x is not None:
             out["final_x"] = final_x
         return out
+
+    def search(self, desc: fstat_search_desc) -> dict:
+        """Run fstat_search; returns its results as numpy arrays and floats."""
+        _torch()
+        n = desc.n_slices
+        s1x, s1F = np.zeros((n, 6)), np.zeros(n)
+        s2x, s2F = np.zeros((n, 6)), np.zeros(n)
+        r = fstat_search_result()
+        r.stage1_x, r.stage1_F = s1x.ctypes.data, s1F.ctypes.data
+        r.stage2_x, r.stage2_F = s2x.ctypes.data, s2F.ctypes.data
+        fstat_search(self.handle, desc, r, _stream())
+        return dict(stages_done=r.stages_done, stages_resumed=r.stages_resumed,
+                    stage1_x=s1x, stage1_F=s1F, stage2_x=s2x, stage2_F=s2F,
+                    stage3_x=np.array(r.stage3_x), stage3_F=np.array(r.stage3_F),
+                    best_x=np.array(r.best_x), best_F=r.best_F, amps=np.array(r.amps),
+                    extrinsic=np.array(r.extrinsic), stage_ms=np.array(r.stage_ms),
+                    evals=np.array(r.evals))
 
     def train_surrogate(self, n_samples: int = 2_000_000, batch: int = 4096, steps: int = 4000,
                         lr: float = 1e-3, seed: int = 5001, want_trace: bool = False):
