@@ -130,6 +130,52 @@ def pso_bench(iters):
     return out
 
 
+def search_bench(iters, ckpt, last_stage=3, resume=False):
+    """The three-stage search (Sec. III.B) on the paper-scale workload with the
+    paper's run counts (24 t_c intervals x 24 runs, 24 x 8, 2 x 48; 128
+    particles; N_seg 16, 16, 1) and `iters` iterations per stage; stages 1-2
+    on the mixed path, stage 3 in FP64.  Runs stage by stage through the
+    checkpoint file `ckpt` (kept with resume=True), so that a search longer
+    than one process can be continued by the next, up to `last_stage`."""
+    import torch
+    from paper_2407_10797_amd import fstat, synth as S
+    g, data, psd, pts, inj = make_workload(4096)
+    plan = fstat.Plan(data, psd, g.T_obs, g.df, g.k_lo)
+    prm = torch.from_numpy(pts).cuda()
+    plan.autotune(prm, 16, mixed=True)
+    plan.autotune(prm, 1)
+    if not resume and os.path.exists(ckpt):
+        os.remove(ckpt)
+    desc = dict(seed=2004, flags=(fstat.FSTAT_EVAL_MIXED, fstat.FSTAT_EVAL_MIXED, 0),
+                checkpoint=ckpt, iters=tuple(iters))
+    res, stage_s, evals = None, [None] * 3, [None] * 3
+    for stage in range(1, last_stage + 1):
+        res = plan.search(fstat.search_desc(S.PAPER_BOX, max_stage=stage, **desc))
+        k = stage - 1
+        if res["stages_resumed"] >= stage:
+            _log(f"search stage {stage}: taken from {ckpt}")
+            continue
+        stage_s[k], evals[k] = res["stage_ms"][k] / 1e3, int(res["evals"][k])
+        _log(f"search stage {stage}: {evals[k]:.3e} evaluations in {stage_s[k]:.1f} s "
+             f"({evals[k] / stage_s[k]:.3e}/s); best F {res['best_F']:.2f}")
+    F_true = plan.eval(torch.from_numpy(inj[None]).cuda(), 1).cpu().numpy()[0]
+    plan.close()
+    names = ["t_c", "Mc", "delta_mu", "theta", "phi", "e0"]
+    out = dict(config=f"paper-scale workload, box {S.PAPER_BOX.tolist()}, runs (24x24, 24x8, 2x48) x 128 "
+                      f"particles, iterations {tuple(iters)}, N_seg (16, 16, 1), stages 1-2 mixed, "
+                      "stage 3 FP64",
+               stages_done=int(res["stages_done"]), stage_s=stage_s, evals=evals,
+               evals_per_s=[e / s if e and s else None for e, s in zip(evals, stage_s)],
+               best_F=float(res["best_F"]), F_injection_coherent=float(F_true),
+               stage1_F=[float(x) for x in res["stage1_F"]],
+               stage2_F=[float(x) for x in res["stage2_F"]],
+               estimate=dict(zip(names, map(float, res["best_x"]))),
+               injection=dict(zip(names, map(float, inj))))
+    if res["stages_done"] == 3:
+        out["extrinsic"] = dict(zip(["D_L_m", "iota", "psi", "phi_c"], map(float, res["extrinsic"])))
+    return out
+
+
 def cpu_baseline(g, data, psd, pts, npart, sample):
     from oracle import oracle as O
     sub = pts[:sample]
@@ -152,8 +198,15 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "mixed", "mixed+surrogate", "pso"], default=None,
-                    help="one paper-scale variant, or only the batched PSO measurement")
+    ap.add_argument("--only", choices=["fp64", "mixed", "mixed+surrogate", "pso", "search"], default=None,
+                    help="one paper-scale variant, or only the batched PSO measurement, or only "
+                         "the three-stage search")
+    ap.add_argument("--search-iters", default="400,400,800",
+                    help="PSO iterations of the three search stages (--only search)")
+    ap.add_argument("--search-checkpoint", default="gpurun_out/search.ckpt")
+    ap.add_argument("--search-last-stage", type=int, default=3)
+    ap.add_argument("--search-resume", action="store_true",
+                    help="continue from --search-checkpoint instead of starting afresh")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-steps", type=int, default=3000)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default work-item shape")
@@ -177,6 +230,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 8 * n}))
+        return
+    if args.only == "search":
+        out = {"search": search_bench([int(x) for x in args.search_iters.split(",")],
+                                      args.search_checkpoint, args.search_last_stage,
+                                      args.search_resume)}
+        print(json.dumps(out), flush=True)
         return
     if args.only == "pso":
         out = {"pso": pso_bench(args.pso_iters)}

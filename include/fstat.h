@@ -193,7 +193,9 @@ typedef struct {
  *   x <- x + v,
  * with r1, r2 ~ U[0,1) drawn per particle, dimension and iteration from
  * Philox4x64-10.  All state stays on the device; results (host pointers)
- * are written when the call returns.  EINVAL on bad sizes or boxes.       */
+ * are written when the call returns.  With the environment variable
+ * FSTAT_PROGRESS = N > 0 the call waits for the device every N iterations
+ * and prints one progress line to stderr.  EINVAL on bad sizes or boxes.  */
 int pso_stage(fstat_plan_t plan, const pso_stage_desc *desc, pso_result *result, void *hip_stream);
 
 /* ---- hierarchical search (Sec. III.B, Fig. 2) ------------------------------ */

@@ -12,6 +12,8 @@
 // for iteration k; three blocks give 12 uniforms u = (bits >> 11) 2^-53:
 // u[0..5] and u[6..11] are (x0, v0 draw) at t = 0 and (r1, r2) afterwards.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -161,6 +163,22 @@ struct DevBufs {
   }
 };
 
+// $FSTAT_PROGRESS = N > 0: every N iterations wait for the stream and print
+// one line to stderr (long stages report while they run).
+int report_progress(int done, int total, hipStream_t s) {
+  static const long every = [] {
+    const char* e = getenv("FSTAT_PROGRESS");
+    return e ? strtol(e, nullptr, 10) : 0L;
+  }();
+  if (every <= 0 || done % every != 0 || done == total) return FSTAT_OK;
+  int rc = hip_check(hipStreamSynchronize(s), "pso progress");
+  if (!rc) {
+    fprintf(stderr, "[pso] %d / %d iterations\n", done, total);
+    fflush(stderr);
+  }
+  return rc;
+}
+
 }  // namespace
 
 extern "C" int pso_stage(fstat_plan_t P, const pso_stage_desc* d, pso_result* res,
@@ -244,14 +262,17 @@ extern "C" int pso_stage(fstat_plan_t P, const pso_stage_desc* d, pso_result* re
     }
     if ((rc = hip_check(ec, "end capture"))) return rc;
     rc = hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
-    for (int k = 0; k < I && !rc; ++k) rc = hip_check(hipGraphLaunch(exec, s), "graph launch");
+    for (int k = 0; k < I && !rc; ++k) {
+      rc = hip_check(hipGraphLaunch(exec, s), "graph launch");
+      if (!rc) rc = report_progress(k + 1, I, s);
+    }
     if (!rc) rc = hip_check(hipStreamSynchronize(s), "pso graph");
     if (exec) (void)hipGraphExecDestroy(exec);
     (void)hipGraphDestroy(graph);
     if (rc) return rc;
   } else {
     for (int k = 0; k < I; ++k)
-      if ((rc = iteration())) return rc;
+      if ((rc = iteration()) || (rc = report_progress(k + 1, I, s))) return rc;
   }
   // results: run bests in physical units
   std::vector<double> hx((size_t)R * 6), hb((size_t)R * 12);
