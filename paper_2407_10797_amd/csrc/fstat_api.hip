@@ -129,9 +129,16 @@ int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t*
       if ((rc = hip_check(hipEventCreate(&e), "event"))) return rc;
     (void)hipEventRecord(ev[0], s);
   }
+  UModel um;
+  um.coef = P->ucoef;
+  um.bad_prefix = P->ubad;
+  um.resid = P->ures;
+  um.ntiles = P->n_utiles;
+  um.ssum = cheb_sums_table();
+  if (!um.ssum) um.coef = nullptr;
   launch_eval(mixed, !exact, P->refine_budget, P->grid, n, stride, chunk, P->ws, P->b64, P->b32,
               surrogate ? P->sur_ek : nullptr, eval_blocks(P, mixed), s,
-              prof ? &ev[1] : nullptr);
+              prof ? &ev[1] : nullptr, um);
   if (prof) {
     (void)hipEventRecord(ev[3], s);
     P->events.push_back(ev);
@@ -338,13 +345,37 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
     ddata = dd;
     dpsd = dp;
   }
+  std::vector<double> ures;
+  if (!rc) {
+    P->n_utiles = (int32_t)((nb + kUTile - 1) / kUTile);
+    ures.assign((size_t)P->n_utiles, 0.0);
+    rc = dev_alloc(&P->ucoef, (size_t)P->n_utiles * kUCoef, "alloc u model");
+    if (!rc) rc = dev_alloc(&P->ubad, (size_t)P->n_utiles + 1, "alloc u model flags");
+  }
+  if (!rc) rc = dev_alloc(&P->ures, (size_t)P->n_utiles, "alloc u model residuals");
+  double* dres = P->ures;
   if (!rc) {
     launch_prep(P->grid, ddata, dpsd, P->b64, s);
     launch_max(P->b64.u, nb, P->umax, s);
     launch_scale(P->grid, P->umax, P->b64, P->b32, s);
+    launch_ufit(P->b64.u, nb, P->n_utiles, P->ucoef, dres, s);
     rc = hip_check(hipGetLastError(), "prep launch");
   }
+  if (!rc) rc = hip_check(hipMemcpyAsync(ures.data(), dres, sizeof(double) * P->n_utiles,
+                                         hipMemcpyDeviceToHost, s), "read u model residuals");
   if (!rc) rc = hip_check(hipStreamSynchronize(s), "plan prep");
+  if (!rc) {
+    // prefix count of u-tiles the smooth model does not fit to within kUFitTol
+    std::vector<int32_t> bad((size_t)P->n_utiles + 1, 0);
+    for (int32_t i = 0; i < P->n_utiles; ++i) {
+      const bool ok = ures[(size_t)i] <= kUFitTol;
+      bad[(size_t)i + 1] = bad[(size_t)i] + (ok ? 0 : 1);
+      P->n_ufit += ok ? 1 : 0;
+    }
+    rc = hip_check(hipMemcpyAsync(P->ubad, bad.data(), sizeof(int32_t) * bad.size(),
+                                  hipMemcpyHostToDevice, s), "copy u model flags");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "plan prep");
+  }
   dev_free(dd);
   dev_free(dp);
   if (rc) {
@@ -373,7 +404,8 @@ void fstat_plan_destroy(fstat_plan_t P) {
   dev_free(P->ws.tile_items);
   dev_free(P->ws.tile_ctr); dev_free(P->ws.xflag); dev_free(P->ws.rec); dev_free(P->ws.xerr); dev_free(P->ws.refine); dev_free(P->ws.nrefine);
   dev_free(P->io.params); dev_free(P->io.np); dev_free(P->io.F_hat); dev_free(P->io.F_part);
-  dev_free(P->io.amps); dev_free(P->umax);
+  dev_free(P->io.amps); dev_free(P->umax); dev_free(P->ucoef); dev_free(P->ubad);
+  dev_free(P->ures);
   pso_release(P);
   sur_release(P);
   for (auto& e : P->events)

@@ -30,6 +30,11 @@ struct fstat_plan_s {
   fstat::BinData<float> b32{};
   fstat::WorkSpace ws{};
   double* umax = nullptr;           // max of u before scaling (the scale of the amplitudes)
+  double* ucoef = nullptr;          // smooth model of u per u-tile (M-term quadrature)
+  int32_t* ubad = nullptr;          // prefix count of u-tiles the model does not fit
+  double* ures = nullptr;           // relative residual of the model per u-tile
+  int32_t n_utiles = 0;
+  int32_t n_ufit = 0;               // u-tiles fitted to within tolerance
   struct {
     size_t pc = 0, bounds = 0, cnt = 0, off = 0, total = 0, items = 0, partials = 0, Fl = 0;
     size_t direct = 0, ndirect = 0, tcnt = 0, tcur = 0, toff = 0, uoff = 0, tile_items = 0,

@@ -62,11 +62,32 @@ void launch_setup(const Grid& g, const double* params, int64_t n,
 void launch_worklist(int64_t m, const WorkSpace& ws, hipStream_t s);
 int interp_tables_init();
 int interp_max_tile(bool mixed);   // largest tile (bins) the LDS-staged loop accepts
-constexpr int kInterpRec = 53;     // doubles per interpolation record
+constexpr int kInterpRec = 54;     // doubles per interpolation record
+
+// Smooth model of the template-independent weight u = 4 df f^{-7/3} |C|^2 / S
+// (scaled): a degree-9 Chebyshev least-squares fit per u-tile of kUTile bins,
+// with its largest relative residual on the tile's bins.  Items whose bins
+// lie in tiles fitted to within kUFitTol get their M-terms (P, Q, R) by
+// quadrature of the interpolated u |T|^2 products instead of a per-bin sum.
+constexpr int kUTile = 256;
+constexpr int kUCoef = 10;
+constexpr double kUFitTol = 1e-13;
+constexpr int kSsumMax = 8192;     // largest item length of the quadrature table
+struct UModel {
+  const double* coef = nullptr;        // [ntiles][kUCoef] Chebyshev coefficients
+  const int32_t* bad_prefix = nullptr; // [ntiles + 1] count of unfit tiles before each
+  const double* resid = nullptr;       // [ntiles] largest relative residual of each fit
+  int32_t ntiles = 0;
+  const double* ssum = nullptr;        // [5][kSsumMax + 1]: sum_m T_2i(s_m), s_m = 2m/(nb-1) - 1
+};
+const double* cheb_sums_table();       // the current device's quadrature table (after init)
+void launch_ufit(const double* u, int64_t nbins, int32_t ntiles, double* coef, double* resid,
+                 hipStream_t s);
 void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
                  int64_t n_particles, int32_t stride, int32_t chunk,
                  const WorkSpace& ws, BinData<double> b, BinData<float> b32, const double* ek,
-                 int blocks, hipStream_t s, hipEvent_t* ev_main = nullptr);
+                 int blocks, hipStream_t s, hipEvent_t* ev_main = nullptr,
+                 const UModel& um = UModel{});
 void launch_sur_data(uint64_t seed, int64_t n, float* X, float* T, hipStream_t s);
 void launch_sur_knots(const Grid& g, int32_t stride, int64_t n, int64_t rows, const WorkSpace& ws,
                       float* X, hipStream_t s);

@@ -349,6 +349,23 @@ __device__ __forceinline__ double wave_sum8(const double* a, int lane, int& idx)
   return d;
 }
 
+// The same for four values: idx = 2 b5 + b4; lanes with (lane & 15) == 0
+// hold the four totals.
+__device__ __forceinline__ double wave_sum4(const double* a, int lane, int& idx) {
+  const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0;
+  double b[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double keep = h5 ? a[2 + i] : a[i], give = h5 ? a[i] : a[2 + i];
+    b[i] = keep + __shfl_xor(give, 32, 64);
+  }
+  double d = (h4 ? b[1] : b[0]) + __shfl_xor(h4 ? b[0] : b[1], 16, 64);
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+  idx = (h5 ? 2 : 0) + (h4 ? 1 : 0);
+  return d;
+}
+
 __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
                                                    const PartConst* __restrict__ pc,
                                                    const int32_t* __restrict__ bounds, int32_t stride,
@@ -592,6 +609,14 @@ __constant__ double c_cheb_E[2][kCheb];       // node value k -> interpolant at 
 constexpr int kDegT = 6;
 __constant__ double c_cheb_G6[kCheb][kDegT + 1];
 __constant__ double c_cheb_E6[2][kCheb];
+// Quadrature of an item's interpolant: sum over its bins of the degree-9
+// interpolant through the nodes = sum_k W_k g(s_k), W_k = sum_j c_jk S_j(nb)
+// with c_jk the node-to-Chebyshev-coefficient map and S_j(nb) = sum_m T_j(s_m)
+// (zero for odd j: the bins are symmetric in s).  c_cheb_D[i][k] = c_{2i,k}.
+__constant__ double c_cheb_D[5][kCheb];
+// Least-squares fit of u on a u-tile: inverse Gram matrix of T_0..T_9 on the
+// kUTile equispaced points s_m = 2m/(kUTile-1) - 1.
+__constant__ double c_ufit_Ginv[kUCoef][kUCoef];
 
 __device__ __forceinline__ double readlane_d(double x, int l) {
   int2 v = *reinterpret_cast<int2*>(&x);
@@ -631,13 +656,110 @@ __device__ __forceinline__ double estrin9(const double* c, double s, double s2, 
 
 // Per-item interpolation record: monomial coefficients of R (kCheb), then of
 // Re T''_+, Im T''_+, Re T''_x, Im T''_x (nT each: kCheb, or kDegT + 1 on the
-// mixed path), then A = frac(Phi_0), B' = B - rint(B) and B.
-constexpr int kRec = 5 * kCheb + 3;
+// mixed path), then A = frac(Phi_0), B' = B - rint(B), B, and 1 when the
+// item's M-terms were summed by quadrature (0: sum them per bin).
+constexpr int kRec = 5 * kCheb + 4;
 static_assert(kRec == kInterpRec && kRec <= 64, "record layout");
 template <bool MIXED> struct RecLayout {
   static constexpr int nT = MIXED ? kDegT + 1 : kCheb;
-  static constexpr int tail = kCheb + 4 * nT;   // A, B', B
+  static constexpr int tail = kCheb + 4 * nT;   // A, B', B, M-by-quadrature flag
 };
+
+// Chebyshev series sum_k c_k T_k(x) (Clenshaw).
+__device__ __forceinline__ double cheb_eval10(const double* __restrict__ c, double x) {
+  double b1 = 0.0, b2 = 0.0;
+  const double x2 = 2.0 * x;
+#pragma unroll
+  for (int k = kUCoef - 1; k >= 1; --k) {
+    const double b0 = fma(x2, b1, c[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return fma(x, b1, c[0] - b2);
+}
+
+// S_j(nb) = sum_{m < nb} T_j(2m/(nb-1) - 1) for j = 0, 2, .., 8, one nb per
+// thread (Neumaier sums); S_j(1) = T_j(0) stands for the single bin at s = 0
+// and S_j(0) = 0.
+__global__ void k_cheb_sums(double* __restrict__ out) {
+  const int nb = blockIdx.x * blockDim.x + threadIdx.x;
+  if (nb > kSsumMax) return;
+  double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, e[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int m = 0; m < nb; ++m) {
+    const double s = nb > 1 ? 2.0 * (double)m / (double)(nb - 1) - 1.0 : 0.0;
+    double tv[9];
+    tv[0] = 1.0;
+    tv[1] = s;
+#pragma unroll
+    for (int j = 2; j <= 8; ++j) tv[j] = fma(2.0 * s, tv[j - 1], -tv[j - 2]);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const double x = tv[2 * i], tt = a[i] + x;
+      e[i] += (fabs(a[i]) >= fabs(x)) ? (a[i] - tt) + x : (x - tt) + a[i];
+      a[i] = tt;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) out[i * (kSsumMax + 1) + nb] = a[i] + e[i];
+}
+
+// Fit of u on each u-tile (one block of kUTile threads per tile): Chebyshev
+// coefficients by least squares and the largest residual relative to the
+// tile's largest |u|; a partial last tile is left unfit (residual inf).
+__global__ __launch_bounds__(kUTile) void k_ufit(const double* __restrict__ u, int64_t nbins,
+                                                 int32_t ntiles, double* __restrict__ coef,
+                                                 double* __restrict__ resid) {
+  __shared__ double red[kUCoef][kUTile / 64];
+  __shared__ double c_s[kUCoef];
+  __shared__ double mx[2][kUTile / 64];
+  const int tile = blockIdx.x;
+  const int m = threadIdx.x, lane = m & 63, wv = m >> 6;
+  if (tile >= ntiles) return;
+  const int64_t j = (int64_t)tile * kUTile + m;
+  const bool full = (int64_t)(tile + 1) * kUTile <= nbins;
+  const double um = (j < nbins) ? u[j] : 0.0;
+  const double s = 2.0 * (double)m / (double)(kUTile - 1) - 1.0;
+  double tk[kUCoef];
+  tk[0] = 1.0;
+  tk[1] = s;
+#pragma unroll
+  for (int k = 2; k < kUCoef; ++k) tk[k] = fma(2.0 * s, tk[k - 1], -tk[k - 2]);
+#pragma unroll
+  for (int k = 0; k < kUCoef; ++k) {
+    double v = um * tk[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) red[k][wv] = v;
+  }
+  __syncthreads();
+  if (m < kUCoef) {
+    double c = 0.0;
+#pragma unroll
+    for (int k = 0; k < kUCoef; ++k) {
+      double b = 0.0;
+#pragma unroll
+      for (int w = 0; w < kUTile / 64; ++w) b += red[k][w];
+      c = fma(c_ufit_Ginv[m][k], b, c);
+    }
+    c_s[m] = c;
+    if (full) coef[(int64_t)tile * kUCoef + m] = c;
+    else coef[(int64_t)tile * kUCoef + m] = 0.0;
+  }
+  __syncthreads();
+  double r = (j < nbins) ? fabs(um - cheb_eval10(c_s, s)) : 0.0, a = fabs(um);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    r = fmax(r, __shfl_xor(r, o, 64));
+    a = fmax(a, __shfl_xor(a, o, 64));
+  }
+  if (lane == 0) { mx[0][wv] = r; mx[1][wv] = a; }
+  __syncthreads();
+  if (m == 0) {
+    double rr = 0.0, aa = 0.0;
+    for (int w = 0; w < kUTile / 64; ++w) { rr = fmax(rr, mx[0][w]); aa = fmax(aa, mx[1][w]); }
+    resid[tile] = !full ? __builtin_inf() : (aa > 0.0 ? rr / aa : 0.0);
+  }
+}
 // tolerances of the end-point check on the mixed path (FP32 products)
 constexpr double kInterpTolPhaseMixed = 1e-9;
 constexpr double kInterpTolTMixed = 3e-8;
@@ -657,7 +779,9 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
                                                       uint8_t* __restrict__ xflag,
                                                       float* __restrict__ xerr,
                                                       int32_t* __restrict__ direct,
-                                                      int32_t* __restrict__ ndirect) {
+                                                      int32_t* __restrict__ ndirect,
+                                                      UModel um,
+                                                      double* __restrict__ partials) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
@@ -693,10 +817,37 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
       const dd r = dd_add(dd_add(ph, dd{-p0h, -p0l}), dd{-bm.hi, -bm.lo});
       v[0] = r.hi + r.lo;
     }
+    // M-term integrands u |T+|^2, u |Tx|^2, u Re(T+ conj Tx), u Im(T+ conj Tx)
+    // at this point, u from the smooth fit of its u-tile; usable when every
+    // u-tile the item touches is fitted to within kUFitTol
+    bool ufit = um.coef != nullptr && nb >= kMinInterp && nb <= kSsumMax;
+    double gq[4], wq = 0.0, ures = 0.0;
+    {
+      const int ut0 = b0 / kUTile, ut1 = (b1 - 1) / kUTile;
+      ufit = ufit && ut1 < um.ntiles && (um.bad_prefix[ut1 + 1] - um.bad_prefix[ut0]) == 0;
+      if (ufit)   // largest fit residual over the item's u-tiles (12 lanes share the scan)
+        for (int ut = ut0 + k; ut <= ut1; ut += kLanesItem) ures = fmax(ures, um.resid[ut]);
+      const double x = (double)b0 + mk;
+      const int ut = min(max((int)(x * (1.0 / kUTile)), 0), max(um.ntiles - 1, 0));
+      const double loc = 2.0 * (x - (double)ut * kUTile) / (double)(kUTile - 1) - 1.0;
+      const double uu = um.coef ? cheb_eval10(um.coef + (int64_t)ut * kUCoef, loc) : 0.0;
+      gq[0] = uu * fma(v[1], v[1], v[2] * v[2]);
+      gq[1] = uu * fma(v[3], v[3], v[4] * v[4]);
+      gq[2] = uu * fma(v[1], v[3], v[2] * v[4]);
+      gq[3] = uu * fma(v[2], v[3], -v[1] * v[4]);
+      if (k < kCheb && um.ssum) {
+        const int nq = min(nb, kSsumMax);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) wq = fma(c_cheb_D[i][k], um.ssum[i * (kSsumMax + 1) + nq], wq);
+      }
+    }
     typedef RecLayout<MIXED> L;
     double coef[5], emin[5], eplu[5], tmax = 0.0;
+    double gsum[4], gmin[4], gplu[4], gmax = 0.0;
 #pragma unroll
     for (int fn = 0; fn < 5; ++fn) { coef[fn] = 0.0; emin[fn] = 0.0; eplu[fn] = 0.0; }
+#pragma unroll
+    for (int fn = 0; fn < 4; ++fn) { gsum[fn] = 0.0; gmin[fn] = 0.0; gplu[fn] = 0.0; }
 #pragma unroll
     for (int kn = 0; kn < kCheb; ++kn) {
       const double gk = c_cheb_G[kn][k < kCheb ? k : 0];
@@ -710,6 +861,15 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
         emin[fn] = fma(vn, fn ? emt : em, emin[fn]);
         eplu[fn] = fma(vn, fn ? ept : ep, eplu[fn]);
         if (fn > 0) tmax = fmax(tmax, fabs(vn));
+      }
+      const double wk = __shfl(wq, base + kn, 64);
+#pragma unroll
+      for (int fn = 0; fn < 4; ++fn) {
+        const double gn = __shfl(gq[fn], base + kn, 64);
+        gsum[fn] = fma(gn, wk, gsum[fn]);
+        gmin[fn] = fma(gn, em, gmin[fn]);
+        gplu[fn] = fma(gn, ep, gplu[fn]);
+        if (fn < 2) gmax = fmax(gmax, fabs(gn));
       }
     }
     const double tolP = MIXED ? kInterpTolPhaseMixed : kInterpTolPhase;
@@ -728,11 +888,28 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
         err = fmax(err, d / tmax);
       }
     }
+    // end-point check of the M-term interpolants (relative to max u |T|^2)
+    double gerr = 0.0;
+    if (k >= kCheb) {
+      const double* e = (k == kCheb) ? gmin : gplu;
+#pragma unroll
+      for (int fn = 0; fn < 4; ++fn) gerr = fmax(gerr, fabs(e[fn] - gq[fn]));
+      gerr = gmax > 0.0 ? gerr / gmax : (gerr > 0.0 ? 1.0 : 0.0);
+    }
+    const double tolG = MIXED ? kInterpTolTMixed : 4.0 * kInterpTolT;
+    const uint64_t gbadmask = __ballot(k >= kCheb && !(gerr <= tolG));
+    gerr = fmax(gerr, __shfl(gerr, base + kCheb + 1, 64));
+#pragma unroll
+    for (int kk = 0; kk < kLanesItem; ++kk) gerr = fmax(gerr, __shfl(ures, base + kk, 64));
     const uint64_t badmask = __ballot(bad);
     err = fmax(err, __shfl(err, base + kCheb + 1, 64));
     const bool mine = lane - base < kLanesItem && grp * kItemsWave + q < W;   // not a repeat lane
     if (!mine) continue;
     const bool rej = nb < kMinInterp || ((badmask >> base) & ((1ull << kLanesItem) - 1ull)) != 0ull;
+    const bool mq = ufit && ((gbadmask >> base) & ((1ull << kLanesItem) - 1ull)) == 0ull;
+    if (mq) err = fmax(err, gerr);
+    if (mq && k < 4)
+      partials[(int64_t)w * 8 + 4 + k] = k == 0 ? gsum[0] : (k == 1 ? gsum[1] : (k == 2 ? gsum[2] : gsum[3]));
     double* r = rec + (int64_t)w * kRec;
     if (k < kCheb) {
       r[k] = coef[0];
@@ -745,6 +922,7 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
       r[L::tail] = (p0h - floor(p0h)) + p0l;     // fractional cycle at the first bin
       r[L::tail + 1] = B - rint(B);              // whole cycles per bin drop out (m is an integer)
       r[L::tail + 2] = B;
+      r[L::tail + 3] = mq ? 1.0 : 0.0;
       xflag[w] = rej ? 1 : 0;
       xerr[w] = (float)err;
       if (rej) direct[atomicAdd(ndirect, 1)] = w;
@@ -842,6 +1020,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
       const double A = R[L::tail];
       const double Bp = R[L::tail + 1];
       const double Bf = R[L::tail + 2];
+      const bool mq = R[L::tail + 3] != 0.0;   // M-terms already summed by quadrature
       const double alpha = 2.0 / (double)(nb - 1);
       const int e0 = b0 - j0;            // LDS offset of the item's first bin
       if constexpr (!MIXED) {
@@ -851,52 +1030,65 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
 #pragma unroll
           for (int n = 0; n < kCheb; ++n) cT[fn][n] = R[kCheb + fn * L::nT + n];
         __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
-        double acc[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] = 0.0;
         // The grid is f_j = (k_lo + j) df rounded to a double; the interpolants
         // are exact in f, so the phase moves by (dPhi/df)(f_j - exact) =
         // -(B / df) e_j, with e_j the rounding error of the product (from an
         // FMA): up to ~1e-9 cycles at t_f ~ 1e8 s.
         const double kB = -Bf / g.df;
         const double j00 = (double)(g.k_lo + b0);
-        // the next bin's w, u are read one iteration ahead (LDS latency)
         const int last = nb - 1;
-        double a_n = s_wr[e0 + min(lane, last)], b_n = s_wi[e0 + min(lane, last)];
-        double u_n = s_u[e0 + min(lane, last)];
-        for (int mi = lane; mi < nb; mi += 64) {
-          const double a = a_n, b = b_n, uu = u_n;
-          {
-            const int nx = e0 + min(mi + 64, last);
-            a_n = s_wr[nx];
-            b_n = s_wi[nx];
-            u_n = s_u[nx];
+        // WM: also sum the M-terms per bin (items without quadrature M-terms)
+        auto loop = [&](auto wm) {
+          constexpr bool WM = decltype(wm)::value;
+          double acc[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) acc[i] = 0.0;
+          // the next bin's w, u are read one iteration ahead (LDS latency)
+          double a_n = s_wr[e0 + min(lane, last)], b_n = s_wi[e0 + min(lane, last)];
+          double u_n = WM ? s_u[e0 + min(lane, last)] : 0.0;
+          for (int mi = lane; mi < nb; mi += 64) {
+            const double a = a_n, b = b_n, uu = u_n;
+            {
+              const int nx = e0 + min(mi + 64, last);
+              a_n = s_wr[nx];
+              b_n = s_wi[nx];
+              if constexpr (WM) u_n = s_u[nx];
+            }
+            const double m = (double)mi;
+            const double s = fma(alpha, m, -1.0);
+            const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
+            const double jd = j00 + m;
+            const double fj = jd * g.df;
+            const double ej = fma(jd, g.df, -fj);
+            double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
+            ph -= rint(ph);
+            double sps, cps;
+            sincos_turns(ph, sps, cps);
+            const double tpr = estrin9(cT[0], s, s2, s4, s8), tpi = estrin9(cT[1], s, s2, s4, s8);
+            const double txr = estrin9(cT[2], s, s2, s4, s8), txi = estrin9(cT[3], s, s2, s4, s8);
+            const double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
+            acc[0] += Wr * tpr + Wi * tpi;
+            acc[1] += Wi * tpr - Wr * tpi;
+            acc[2] += Wr * txr + Wi * txi;
+            acc[3] += Wi * txr - Wr * txi;
+            if constexpr (WM) {
+              acc[4] += uu * (tpr * tpr + tpi * tpi);
+              acc[5] += uu * (txr * txr + txi * txi);
+              acc[6] += uu * (tpr * txr + tpi * txi);
+              acc[7] += uu * (tpi * txr - tpr * txi);
+            }
           }
-          const double m = (double)mi;
-          const double s = fma(alpha, m, -1.0);
-          const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
-          const double jd = j00 + m;
-          const double fj = jd * g.df;
-          const double ej = fma(jd, g.df, -fj);
-          double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
-          ph -= rint(ph);
-          double sps, cps;
-          sincos_turns(ph, sps, cps);
-          const double tpr = estrin9(cT[0], s, s2, s4, s8), tpi = estrin9(cT[1], s, s2, s4, s8);
-          const double txr = estrin9(cT[2], s, s2, s4, s8), txi = estrin9(cT[3], s, s2, s4, s8);
-          const double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
-          acc[0] += Wr * tpr + Wi * tpi;
-          acc[1] += Wi * tpr - Wr * tpi;
-          acc[2] += Wr * txr + Wi * txi;
-          acc[3] += Wi * txr - Wr * txi;
-          acc[4] += uu * (tpr * tpr + tpi * tpi);
-          acc[5] += uu * (txr * txr + txi * txi);
-          acc[6] += uu * (tpr * txr + tpi * txi);
-          acc[7] += uu * (tpi * txr - tpr * txi);
-        }
-        int idx;
-        const double tot = wave_sum8(acc, lane, idx);
-        if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
+          int idx;
+          if constexpr (WM) {
+            const double tot = wave_sum8(acc, lane, idx);
+            if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
+          } else {
+            const double tot = wave_sum4(acc, lane, idx);
+            if ((lane & 15) == 0) partials[(int64_t)w * 8 + idx] = tot;
+          }
+        };
+        if (mq) loop(std::false_type{});
+        else loop(std::true_type{});
       } else {
         float cT[4][kDegT + 1];
 #pragma unroll
@@ -906,39 +1098,54 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
         // per lane at most T / 64 terms: plain FP32 sums of the N-terms (their
         // rounding, ~1e-7 relative, is far inside the mixed path's bar); M-terms
-        // in FP64 from the FP32 response
-        float acc[4];
-        double m4[4];
+        // (items without quadrature M-terms) in FP64 from the FP32 response
+        auto loop = [&](auto wm) {
+          constexpr bool WM = decltype(wm)::value;
+          float acc[4];
+          double m4[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) { acc[i] = 0.0f; m4[i] = 0.0; }
-        for (int mi = lane; mi < nb; mi += 64) {
-          const double m = (double)mi;
-          const double s = fma(alpha, m, -1.0);
-          const double ph = fma(Bp, m, horner(cR, s)) + A;
-          const float rf = (float)(ph - rint(ph));
-          const float sps = __builtin_amdgcn_sinf(rf), cps = __builtin_amdgcn_cosf(rf);
-          const float sf = (float)s;
-          const float tpr = horner_n<kDegT>(cT[0], sf), tpi = horner_n<kDegT>(cT[1], sf);
-          const float txr = horner_n<kDegT>(cT[2], sf), txi = horner_n<kDegT>(cT[3], sf);
-          const float a = s_wr[e0 + mi], b = s_wi[e0 + mi];
-          const float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
-          acc[0] += Wr * tpr + Wi * tpi;
-          acc[1] += Wi * tpr - Wr * tpi;
-          acc[2] += Wr * txr + Wi * txi;
-          acc[3] += Wi * txr - Wr * txi;
-          const double uu = (double)s_u[e0 + mi];
-          const double pr = tpr, pi = tpi, xr = txr, xi = txi;
-          m4[0] += uu * (pr * pr + pi * pi);
-          m4[1] += uu * (xr * xr + xi * xi);
-          m4[2] += uu * (pr * xr + pi * xi);
-          m4[3] += uu * (pi * xr - pr * xi);
-        }
-        double red[8];
+          for (int i = 0; i < 4; ++i) { acc[i] = 0.0f; m4[i] = 0.0; }
+          for (int mi = lane; mi < nb; mi += 64) {
+            const double m = (double)mi;
+            const double s = fma(alpha, m, -1.0);
+            const double ph = fma(Bp, m, horner(cR, s)) + A;
+            const float rf = (float)(ph - rint(ph));
+            const float sps = __builtin_amdgcn_sinf(rf), cps = __builtin_amdgcn_cosf(rf);
+            const float sf = (float)s;
+            const float tpr = horner_n<kDegT>(cT[0], sf), tpi = horner_n<kDegT>(cT[1], sf);
+            const float txr = horner_n<kDegT>(cT[2], sf), txi = horner_n<kDegT>(cT[3], sf);
+            const float a = s_wr[e0 + mi], b = s_wi[e0 + mi];
+            const float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
+            acc[0] += Wr * tpr + Wi * tpi;
+            acc[1] += Wi * tpr - Wr * tpi;
+            acc[2] += Wr * txr + Wi * txi;
+            acc[3] += Wi * txr - Wr * txi;
+            if constexpr (WM) {
+              const double uu = (double)s_u[e0 + mi];
+              const double pr = tpr, pi = tpi, xr = txr, xi = txi;
+              m4[0] += uu * (pr * pr + pi * pi);
+              m4[1] += uu * (xr * xr + xi * xi);
+              m4[2] += uu * (pr * xr + pi * xi);
+              m4[3] += uu * (pi * xr - pr * xi);
+            }
+          }
+          int idx;
+          if constexpr (WM) {
+            double red[8];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) { red[i] = (double)acc[i]; red[4 + i] = m4[i]; }
-        int idx;
-        const double tot = wave_sum8(red, lane, idx);
-        if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
+            for (int i = 0; i < 4; ++i) { red[i] = (double)acc[i]; red[4 + i] = m4[i]; }
+            const double tot = wave_sum8(red, lane, idx);
+            if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
+          } else {
+            double red[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[i] = (double)acc[i];
+            const double tot = wave_sum4(red, lane, idx);
+            if ((lane & 15) == 0) partials[(int64_t)w * 8 + idx] = tot;
+          }
+        };
+        if (mq) loop(std::false_type{});
+        else loop(std::true_type{});
       }
     }
     __syncthreads();   // every wave is done with this unit's LDS and s_unit
@@ -1118,6 +1325,8 @@ __global__ void k_copy_count(const int32_t* __restrict__ total, int32_t* __restr
 // interpolant coefficients c_j = (2 / K) sum_k v_k cos(pi j (k + 1/2) / K)
 // (c_0 halved) of p = sum_j c_j T_j(s); T_j expanded in monomials by
 // T_{j+1} = 2 s T_j - T_{j-1}.
+static double* g_ssum[64] = {};   // per device: S_j(nb) table (lives until the process ends)
+
 int interp_tables_init() {
   static bool done[64] = {false};
   int dev = 0;
@@ -1161,8 +1370,57 @@ int interp_tables_init() {
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_E), E, sizeof(E)) != hipSuccess) return -1;
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_G6), G6, sizeof(G6)) != hipSuccess) return -1;
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_E6), E6, sizeof(E6)) != hipSuccess) return -1;
-  if (dev >= 0 && dev < 64) done[dev] = true;
+  // quadrature weights' Chebyshev part (even degrees only)
+  double D[5][kCheb];
+  for (int i = 0; i < 5; ++i)
+    for (int kk = 0; kk < K; ++kk)
+      D[i][kk] = (double)((2.0L / K) * cosl(pi * (2 * i) * (kk + 0.5L) / K) * (i == 0 ? 0.5L : 1.0L));
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_D), D, sizeof(D)) != hipSuccess) return -1;
+  // inverse Gram matrix of the u-tile least-squares fit (Gauss-Jordan)
+  long double Gm[kUCoef][2 * kUCoef] = {};
+  for (int m = 0; m < kUTile; ++m) {
+    const long double s = 2.0L * m / (kUTile - 1) - 1.0L;
+    long double tv[kUCoef];
+    tv[0] = 1.0L;
+    tv[1] = s;
+    for (int k = 2; k < kUCoef; ++k) tv[k] = 2.0L * s * tv[k - 1] - tv[k - 2];
+    for (int a = 0; a < kUCoef; ++a)
+      for (int b = 0; b < kUCoef; ++b) Gm[a][b] += tv[a] * tv[b];
+  }
+  for (int a = 0; a < kUCoef; ++a) Gm[a][kUCoef + a] = 1.0L;
+  for (int c = 0; c < kUCoef; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < kUCoef; ++r)
+      if (fabsl(Gm[r][c]) > fabsl(Gm[piv][c])) piv = r;
+    for (int b = 0; b < 2 * kUCoef; ++b) { long double x = Gm[c][b]; Gm[c][b] = Gm[piv][b]; Gm[piv][b] = x; }
+    const long double d = Gm[c][c];
+    for (int b = 0; b < 2 * kUCoef; ++b) Gm[c][b] /= d;
+    for (int r = 0; r < kUCoef; ++r)
+      if (r != c) {
+        const long double f = Gm[r][c];
+        for (int b = 0; b < 2 * kUCoef; ++b) Gm[r][b] -= f * Gm[c][b];
+      }
+  }
+  double Gi[kUCoef][kUCoef];
+  for (int a = 0; a < kUCoef; ++a)
+    for (int b = 0; b < kUCoef; ++b) Gi[a][b] = (double)Gm[a][kUCoef + b];
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_ufit_Ginv), Gi, sizeof(Gi)) != hipSuccess) return -1;
+  // quadrature table S_j(nb), one per device
+  double* tab = nullptr;
+  if (hipMalloc((void**)&tab, sizeof(double) * 5 * (kSsumMax + 1)) != hipSuccess) return -1;
+  hipLaunchKernelGGL(k_cheb_sums, dim3((kSsumMax + 256) / 256), dim3(256), 0, 0, tab);
+  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) return -1;
+  if (dev >= 0 && dev < 64) {
+    g_ssum[dev] = tab;
+    done[dev] = true;
+  }
   return 0;
+}
+
+const double* cheb_sums_table() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  return g_ssum[dev];
 }
 
 // ---------------------------------------------------------------------------
@@ -1528,7 +1786,7 @@ int interp_max_tile(bool mixed) { return mixed ? 4096 : 2048; }
 void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
                  int64_t n_particles, int32_t stride, int32_t chunk, const WorkSpace& ws,
                  BinData<double> b, BinData<float> b32, const double* ek, int blocks,
-                 hipStream_t s, hipEvent_t* ev_main) {
+                 hipStream_t s, hipEvent_t* ev_main, const UModel& um) {
   const int32_t* sel = nullptr;
   const int32_t* nsel = nullptr;
   if (!interp) hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(64), 0, s, ws.total, ws.ndirect);
@@ -1544,11 +1802,11 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
     if (mixed)
       hipLaunchKernelGGL(k_interp_nodes<true>, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds,
                          stride, ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.xerr,
-                         ws.direct, ws.ndirect);
+                         ws.direct, ws.ndirect, um, ws.partials);
     else
       hipLaunchKernelGGL(k_interp_nodes<false>, dim3(blocks), dim3(256), 0, s, g, ws.pc,
                          ws.bounds, stride, ws.items, ws.total, chunk, ek, ws.rec, ws.xflag,
-                         ws.xerr, ws.direct, ws.ndirect);
+                         ws.xerr, ws.direct, ws.ndirect, um, ws.partials);
     const size_t lds = 3 * (size_t)chunk * (mixed ? sizeof(float) : sizeof(double));
     if (ev_main) (void)hipEventRecord(ev_main[0], s);
     if (mixed)
@@ -1615,6 +1873,12 @@ void launch_sur_check(const Grid& g, int32_t stride, int64_t n, const WorkSpace&
                      ws.bounds, stride, n, ynn, ek, mm);
   hipLaunchKernelGGL(k_sur_decide, dim3(nblk(n, 128)), dim3(128), 0, s, ws.pc, n, stride, mm, thr,
                      counters);
+}
+
+void launch_ufit(const double* u, int64_t nbins, int32_t ntiles, double* coef, double* resid,
+                 hipStream_t s) {
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_ufit, dim3(ntiles), dim3(kUTile), 0, s, u, nbins, ntiles, coef, resid);
 }
 
 void launch_extrinsic(const double* amps, const double* params, int64_t n, double* out,
