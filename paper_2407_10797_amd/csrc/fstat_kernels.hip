@@ -605,7 +605,9 @@ __constant__ double c_cheb_G[kCheb][kCheb];   // node value k -> coefficient of 
 __constant__ double c_cheb_E[2][kCheb];       // node value k -> interpolant at s = -1, +1
 // The mixed path's transfer interpolants: the Chebyshev series truncated
 // after degree kDegT (its error, a few 1e-10 at 2048 bins, is far below FP32
-// rounding), as monomials, and their values at s = -1, +1.
+// rounding), as monomials, and their values at s = -1, +1.  (Degree 4 would
+// save 8 FP32 operations per bin but fails the end check on enough 4096-bin
+// items that the exact fallback costs more.)
 constexpr int kDegT = 6;
 __constant__ double c_cheb_G6[kCheb][kDegT + 1];
 __constant__ double c_cheb_E6[2][kCheb];
