@@ -62,7 +62,7 @@ void launch_setup(const Grid& g, const double* params, int64_t n,
 void launch_worklist(int64_t m, const WorkSpace& ws, hipStream_t s);
 int interp_tables_init();
 int interp_max_tile(bool mixed);   // largest tile (bins) the LDS-staged loop accepts
-constexpr int kInterpRec = 54;     // doubles per interpolation record
+constexpr int kInterpRec = 55;     // doubles per interpolation record
 
 // Smooth model of the template-independent weight u = 4 df f^{-7/3} |C|^2 / S
 // (scaled): a degree-9 Chebyshev least-squares fit per u-tile of kUTile bins,

@@ -611,6 +611,12 @@ __constant__ double c_cheb_E[2][kCheb];       // node value k -> interpolant at 
 constexpr int kDegT = 6;
 __constant__ double c_cheb_G6[kCheb][kDegT + 1];
 __constant__ double c_cheb_E6[2][kCheb];
+// The FP64 loop's transfer interpolants may be truncated after degree 5 or 7
+// per item when that keeps them within the item's own error (most paper-scale
+// items need 5-7 of the 10 Chebyshev terms at the 2e-13 bar): maps node value
+// -> monomial coefficient and -> value at s = -1, +1 of the truncated series.
+__constant__ double c_cheb_Gt[2][kCheb][kCheb];   // [0]: degree 5, [1]: degree 7
+__constant__ double c_cheb_Et[2][2][kCheb];
 // Quadrature of an item's interpolant: sum over its bins of the degree-9
 // interpolant through the nodes = sum_k W_k g(s_k), W_k = sum_j c_jk S_j(nb)
 // with c_jk the node-to-Chebyshev-coefficient map and S_j(nb) = sum_m T_j(s_m)
@@ -656,11 +662,31 @@ __device__ __forceinline__ double estrin9(const double* c, double s, double s2, 
   return fma(q89, s8, fma(b, s4, a));
 }
 
+// Degree-D Estrin forms of the same monomial series (D = 5, 7) for the FP64
+// loop's transfer interpolants truncated by the node kernel.
+template <int D>
+__device__ __forceinline__ double estrin_d(const double* c, double s, double s2, double s4,
+                                           double s8) {
+  static_assert(D == 5 || D == 7 || D == 9, "degree 5, 7 or 9");
+  if constexpr (D == 9) {
+    return estrin9(c, s, s2, s4, s8);
+  } else if constexpr (D == 7) {
+    const double q01 = fma(c[1], s, c[0]), q23 = fma(c[3], s, c[2]);
+    const double q45 = fma(c[5], s, c[4]), q67 = fma(c[7], s, c[6]);
+    return fma(fma(q67, s2, q45), s4, fma(q23, s2, q01));
+  } else {
+    const double q01 = fma(c[1], s, c[0]), q23 = fma(c[3], s, c[2]);
+    const double q45 = fma(c[5], s, c[4]);
+    return fma(q45, s4, fma(q23, s2, q01));
+  }
+}
+
 // Per-item interpolation record: monomial coefficients of R (kCheb), then of
 // Re T''_+, Im T''_+, Re T''_x, Im T''_x (nT each: kCheb, or kDegT + 1 on the
-// mixed path), then A = frac(Phi_0), B' = B - rint(B), B, and 1 when the
-// item's M-terms were summed by quadrature (0: sum them per bin).
-constexpr int kRec = 5 * kCheb + 4;
+// mixed path), then A = frac(Phi_0), B' = B - rint(B), B, 1 when the item's
+// M-terms were summed by quadrature (0: sum them per bin), and the degree the
+// FP64 loop evaluates the transfer interpolants at (5, 7 or 9).
+constexpr int kRec = 5 * kCheb + 5;
 static_assert(kRec == kInterpRec && kRec <= 64, "record layout");
 template <bool MIXED> struct RecLayout {
   static constexpr int nT = MIXED ? kDegT + 1 : kCheb;
@@ -846,11 +872,19 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
     typedef RecLayout<MIXED> L;
     double coef[5], emin[5], eplu[5], tmax = 0.0;
     double gsum[4], gmin[4], gplu[4], gmax = 0.0;
+    // FP64: the transfer series truncated after degree 5 and 7 ([0], [1])
+    double ctr[2][4], etm[2][4], etp[2][4];
+#pragma unroll
+    for (int v2 = 0; v2 < 2; ++v2)
+#pragma unroll
+      for (int fn = 0; fn < 4; ++fn) { ctr[v2][fn] = 0.0; etm[v2][fn] = 0.0; etp[v2][fn] = 0.0; }
 #pragma unroll
     for (int fn = 0; fn < 5; ++fn) { coef[fn] = 0.0; emin[fn] = 0.0; eplu[fn] = 0.0; }
 #pragma unroll
     for (int fn = 0; fn < 4; ++fn) { gsum[fn] = 0.0; gmin[fn] = 0.0; gplu[fn] = 0.0; }
-#pragma unroll
+    // not unrolled: unrolling hoists every node's table loads and needs more
+    // registers than the kernel can hold at a useful occupancy
+#pragma unroll 1
     for (int kn = 0; kn < kCheb; ++kn) {
       const double gk = c_cheb_G[kn][k < kCheb ? k : 0];
       const double gt = MIXED ? c_cheb_G6[kn][k < L::nT ? k : 0] : gk;
@@ -863,6 +897,16 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
         emin[fn] = fma(vn, fn ? emt : em, emin[fn]);
         eplu[fn] = fma(vn, fn ? ept : ep, eplu[fn]);
         if (fn > 0) tmax = fmax(tmax, fabs(vn));
+        if constexpr (!MIXED) {
+          if (fn > 0) {
+#pragma unroll
+            for (int v2 = 0; v2 < 2; ++v2) {
+              ctr[v2][fn - 1] = fma(vn, c_cheb_Gt[v2][kn][k < kCheb ? k : 0], ctr[v2][fn - 1]);
+              etm[v2][fn - 1] = fma(vn, c_cheb_Et[v2][0][kn], etm[v2][fn - 1]);
+              etp[v2][fn - 1] = fma(vn, c_cheb_Et[v2][1][kn], etp[v2][fn - 1]);
+            }
+          }
+        }
       }
       const double wk = __shfl(wq, base + kn, 64);
 #pragma unroll
@@ -878,6 +922,7 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
     const double tolT = MIXED ? kInterpTolTMixed : kInterpTolT;
     bool bad = false;
     double err = 0.0;           // relative template error at this end point
+    double errt[2] = {0.0, 0.0};   // transfer error of the degree-5 and -7 truncations
     if (k >= kCheb) {
       const double* e = (k == kCheb) ? emin : eplu;
       const double dph = fabs(e[0] - v[0]);
@@ -888,6 +933,13 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
         const double d = fabs(e[fn] - v[fn]);
         bad = bad || !(d <= tolT * tmax);
         err = fmax(err, d / tmax);
+        if constexpr (!MIXED) {
+#pragma unroll
+          for (int v2 = 0; v2 < 2; ++v2) {
+            const double et = (k == kCheb) ? etm[v2][fn - 1] : etp[v2][fn - 1];
+            errt[v2] = fmax(errt[v2], fabs(et - v[fn]) / tmax);
+          }
+        }
       }
     }
     // end-point check of the M-term interpolants (relative to max u |T|^2)
@@ -904,7 +956,17 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
 #pragma unroll
     for (int kk = 0; kk < kLanesItem; ++kk) gerr = fmax(gerr, __shfl(ures, base + kk, 64));
     const uint64_t badmask = __ballot(bad);
-    err = fmax(err, __shfl(err, base + kCheb + 1, 64));
+    err = fmax(__shfl(err, base + kCheb, 64), __shfl(err, base + kCheb + 1, 64));
+    // FP64: lowest transfer degree whose truncation error stays within the
+    // item's own interpolation error (or 2.5e-14 of the largest component)
+    int degT = kCheb - 1;
+    if constexpr (!MIXED) {
+      const double allow = fmin(fmax(err, 2.5e-14), tolT);
+      const double e7 = fmax(__shfl(errt[1], base + kCheb, 64), __shfl(errt[1], base + kCheb + 1, 64));
+      const double e5 = fmax(__shfl(errt[0], base + kCheb, 64), __shfl(errt[0], base + kCheb + 1, 64));
+      if (e5 <= allow) { degT = 5; err = fmax(err, e5); }
+      else if (e7 <= allow) { degT = 7; err = fmax(err, e7); }
+    }
     const bool mine = lane - base < kLanesItem && grp * kItemsWave + q < W;   // not a repeat lane
     if (!mine) continue;
     const bool rej = nb < kMinInterp || ((badmask >> base) & ((1ull << kLanesItem) - 1ull)) != 0ull;
@@ -917,10 +979,13 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
       r[k] = coef[0];
       if (k < L::nT) {
 #pragma unroll
-        for (int fn = 1; fn < 5; ++fn) r[kCheb + (fn - 1) * L::nT + k] = coef[fn];
+        for (int fn = 1; fn < 5; ++fn)
+          r[kCheb + (fn - 1) * L::nT + k] =
+              degT == 5 ? ctr[0][fn - 1] : (degT == 7 ? ctr[1][fn - 1] : coef[fn]);
       }
     } else if (k == kCheb) {
       FSTAT_NO_CONTRACT
+      r[L::tail + 4] = (double)degT;
       r[L::tail] = (p0h - floor(p0h)) + p0l;     // fractional cycle at the first bin
       r[L::tail + 1] = B - rint(B);              // whole cycles per bin drop out (m is an integer)
       r[L::tail + 2] = B;
@@ -1023,6 +1088,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
       const double Bp = R[L::tail + 1];
       const double Bf = R[L::tail + 2];
       const bool mq = R[L::tail + 3] != 0.0;   // M-terms already summed by quadrature
+      const int degT = (int)R[L::tail + 4];      // transfer degree (FP64 loop)
       const double alpha = 2.0 / (double)(nb - 1);
       const int e0 = b0 - j0;            // LDS offset of the item's first bin
       if constexpr (!MIXED) {
@@ -1039,9 +1105,11 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         const double kB = -Bf / g.df;
         const double j00 = (double)(g.k_lo + b0);
         const int last = nb - 1;
-        // WM: also sum the M-terms per bin (items without quadrature M-terms)
-        auto loop = [&](auto wm) {
+        // WM: also sum the M-terms per bin (items without quadrature M-terms);
+        // DT: degree of the transfer interpolants (5, 7 or 9)
+        auto loop = [&](auto wm, auto dt) {
           constexpr bool WM = decltype(wm)::value;
+          constexpr int DT = decltype(dt)::value;
           double acc[8];
 #pragma unroll
           for (int i = 0; i < 8; ++i) acc[i] = 0.0;
@@ -1066,8 +1134,10 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
             ph -= rint(ph);
             double sps, cps;
             sincos_turns(ph, sps, cps);
-            const double tpr = estrin9(cT[0], s, s2, s4, s8), tpi = estrin9(cT[1], s, s2, s4, s8);
-            const double txr = estrin9(cT[2], s, s2, s4, s8), txi = estrin9(cT[3], s, s2, s4, s8);
+            const double tpr = estrin_d<DT>(cT[0], s, s2, s4, s8);
+            const double tpi = estrin_d<DT>(cT[1], s, s2, s4, s8);
+            const double txr = estrin_d<DT>(cT[2], s, s2, s4, s8);
+            const double txi = estrin_d<DT>(cT[3], s, s2, s4, s8);
             const double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
             acc[0] += Wr * tpr + Wi * tpi;
             acc[1] += Wi * tpr - Wr * tpi;
@@ -1089,8 +1159,18 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
             if ((lane & 15) == 0) partials[(int64_t)w * 8 + idx] = tot;
           }
         };
-        if (mq) loop(std::false_type{});
-        else loop(std::true_type{});
+        using D5 = std::integral_constant<int, 5>;
+        using D7 = std::integral_constant<int, 7>;
+        using D9 = std::integral_constant<int, 9>;
+        if (mq) {
+          if (degT == 5) loop(std::false_type{}, D5{});
+          else if (degT == 7) loop(std::false_type{}, D7{});
+          else loop(std::false_type{}, D9{});
+        } else {
+          if (degT == 5) loop(std::true_type{}, D5{});
+          else if (degT == 7) loop(std::true_type{}, D7{});
+          else loop(std::true_type{}, D9{});
+        }
       } else {
         float cT[4][kDegT + 1];
 #pragma unroll
@@ -1372,6 +1452,26 @@ int interp_tables_init() {
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_E), E, sizeof(E)) != hipSuccess) return -1;
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_G6), G6, sizeof(G6)) != hipSuccess) return -1;
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_E6), E6, sizeof(E6)) != hipSuccess) return -1;
+  // truncations after degree 5 and 7 (FP64 loop)
+  double Gt[2][kCheb][kCheb], Et[2][2][kCheb];
+  for (int v = 0; v < 2; ++v) {
+    const int dmax = v == 0 ? 5 : 7;
+    for (int kk = 0; kk < K; ++kk) {
+      long double lm = 0.0L, lp = 0.0L;
+      for (int n = 0; n < K; ++n) {
+        long double gsum = 0.0L;
+        for (int j = 0; j <= dmax; ++j)
+          gsum += (2.0L / K) * cosl(pi * j * (kk + 0.5L) / K) * (j == 0 ? 0.5L : 1.0L) * M[j][n];
+        Gt[v][kk][n] = (double)gsum;
+        lp += gsum;
+        lm += (n & 1) ? -gsum : gsum;
+      }
+      Et[v][0][kk] = (double)lm;
+      Et[v][1][kk] = (double)lp;
+    }
+  }
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_Gt), Gt, sizeof(Gt)) != hipSuccess) return -1;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_Et), Et, sizeof(Et)) != hipSuccess) return -1;
   // quadrature weights' Chebyshev part (even degrees only)
   double D[5][kCheb];
   for (int i = 0; i < 5; ++i)
