@@ -599,6 +599,7 @@ constexpr int kMinInterp = 32;
 constexpr double kInterpTolPhase = 1e-12;
 constexpr double kInterpTolT = 2e-13;
 constexpr int kUnitItems = 32;      // items per scheduling unit of the bin loop
+constexpr double kTruncFloor = 6e-14;  // FP64 transfer truncation allowance
 
 __constant__ double c_cheb_s[kCheb];          // nodes cos(pi (k + 1/2) / 10)
 __constant__ double c_cheb_G[kCheb][kCheb];   // node value k -> coefficient of s^n
@@ -832,7 +833,7 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
     const double mk = (sk + 1.0) * 0.5 * (double)(nb > 1 ? nb - 1 : 0);
     // exact frequency (k_lo + b0 + mk) df of the node, as double-double
     const dd f = dd_add(two_prod((double)(g.k_lo + b0), g.df), two_prod(mk, g.df));
-    double v[5];
+    double v[5], v0lo;
     const dd ph = template_node(P, f, ekq, v[1], v[2], v[3], v[4]);
     const double p0h = __shfl(ph.hi, base + kCheb, 64);
     const double p0l = __shfl(ph.lo, base + kCheb, 64);
@@ -843,7 +844,8 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
     {
       const dd bm = two_prod(B, mk);
       const dd r = dd_add(dd_add(ph, dd{-p0h, -p0l}), dd{-bm.hi, -bm.lo});
-      v[0] = r.hi + r.lo;
+      v[0] = r.hi;        // R at the node as a normalised double-double
+      v0lo = r.lo;
     }
     // M-term integrands u |T+|^2, u |Tx|^2, u Re(T+ conj Tx), u Im(T+ conj Tx)
     // at this point, u from the smooth fit of its u-tile; usable when every
@@ -882,6 +884,11 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
     for (int fn = 0; fn < 5; ++fn) { coef[fn] = 0.0; emin[fn] = 0.0; eplu[fn] = 0.0; }
 #pragma unroll
     for (int fn = 0; fn < 4; ++fn) { gsum[fn] = 0.0; gmin[fn] = 0.0; gplu[fn] = 0.0; }
+    // R's coefficient and end values in double-double: R reaches a few cycles,
+    // the node-to-monomial map has entries of a few hundred, and a plain double
+    // sum would leave ~1e-13 cycles of cancellation error in the coefficients
+    dd cRd{0.0, 0.0}, eRm{0.0, 0.0}, eRp{0.0, 0.0};
+    double cRx = 0.0, eRmx = 0.0, eRpx = 0.0;
     // not unrolled: unrolling hoists every node's table loads and needs more
     // registers than the kernel can hold at a useful occupancy
 #pragma unroll 1
@@ -890,21 +897,28 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
       const double gt = MIXED ? c_cheb_G6[kn][k < L::nT ? k : 0] : gk;
       const double em = c_cheb_E[0][kn], ep = c_cheb_E[1][kn];
       const double emt = MIXED ? c_cheb_E6[0][kn] : em, ept = MIXED ? c_cheb_E6[1][kn] : ep;
+      {
+        const double vn = __shfl(v[0], base + kn, 64), vl = __shfl(v0lo, base + kn, 64);
+        cRd = dd_add(cRd, two_prod(vn, gk));
+        eRm = dd_add(eRm, two_prod(vn, em));
+        eRp = dd_add(eRp, two_prod(vn, ep));
+        cRx = fma(vl, gk, cRx);
+        eRmx = fma(vl, em, eRmx);
+        eRpx = fma(vl, ep, eRpx);
+      }
 #pragma unroll
-      for (int fn = 0; fn < 5; ++fn) {
+      for (int fn = 1; fn < 5; ++fn) {
         const double vn = __shfl(v[fn], base + kn, 64);
-        coef[fn] = fma(vn, fn ? gt : gk, coef[fn]);
-        emin[fn] = fma(vn, fn ? emt : em, emin[fn]);
-        eplu[fn] = fma(vn, fn ? ept : ep, eplu[fn]);
-        if (fn > 0) tmax = fmax(tmax, fabs(vn));
+        coef[fn] = fma(vn, gt, coef[fn]);
+        emin[fn] = fma(vn, emt, emin[fn]);
+        eplu[fn] = fma(vn, ept, eplu[fn]);
+        tmax = fmax(tmax, fabs(vn));
         if constexpr (!MIXED) {
-          if (fn > 0) {
 #pragma unroll
-            for (int v2 = 0; v2 < 2; ++v2) {
-              ctr[v2][fn - 1] = fma(vn, c_cheb_Gt[v2][kn][k < kCheb ? k : 0], ctr[v2][fn - 1]);
-              etm[v2][fn - 1] = fma(vn, c_cheb_Et[v2][0][kn], etm[v2][fn - 1]);
-              etp[v2][fn - 1] = fma(vn, c_cheb_Et[v2][1][kn], etp[v2][fn - 1]);
-            }
+          for (int v2 = 0; v2 < 2; ++v2) {
+            ctr[v2][fn - 1] = fma(vn, c_cheb_Gt[v2][kn][k < kCheb ? k : 0], ctr[v2][fn - 1]);
+            etm[v2][fn - 1] = fma(vn, c_cheb_Et[v2][0][kn], etm[v2][fn - 1]);
+            etp[v2][fn - 1] = fma(vn, c_cheb_Et[v2][1][kn], etp[v2][fn - 1]);
           }
         }
       }
@@ -920,12 +934,16 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
     }
     const double tolP = MIXED ? kInterpTolPhaseMixed : kInterpTolPhase;
     const double tolT = MIXED ? kInterpTolTMixed : kInterpTolT;
+    coef[0] = cRd.hi + (cRd.lo + cRx);
     bool bad = false;
     double err = 0.0;           // relative template error at this end point
     double errt[2] = {0.0, 0.0};   // transfer error of the degree-5 and -7 truncations
     if (k >= kCheb) {
       const double* e = (k == kCheb) ? emin : eplu;
-      const double dph = fabs(e[0] - v[0]);
+      const dd eR = (k == kCheb) ? eRm : eRp;
+      const double eRx = (k == kCheb) ? eRmx : eRpx;
+      const dd dR = dd_add(eR, dd{-v[0], -v0lo});
+      const double dph = fabs(dR.hi + (dR.lo + eRx));
       bad = !(dph <= tolP);
       err = 2.0 * kPi * dph;
 #pragma unroll
@@ -958,10 +976,12 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
     const uint64_t badmask = __ballot(bad);
     err = fmax(__shfl(err, base + kCheb, 64), __shfl(err, base + kCheb + 1, 64));
     // FP64: lowest transfer degree whose truncation error stays within the
-    // item's own interpolation error (or 2.5e-14 of the largest component)
+    // item's own interpolation error, or kTruncFloor of the largest component
+    // (a larger allowance sends more items of ill-conditioned partitions to
+    // the exact re-evaluation than the lower degree saves)
     int degT = kCheb - 1;
     if constexpr (!MIXED) {
-      const double allow = fmin(fmax(err, 2.5e-14), tolT);
+      const double allow = fmin(fmax(err, kTruncFloor), tolT);
       const double e7 = fmax(__shfl(errt[1], base + kCheb, 64), __shfl(errt[1], base + kCheb + 1, 64));
       const double e5 = fmax(__shfl(errt[0], base + kCheb, 64), __shfl(errt[0], base + kCheb + 1, 64));
       if (e5 <= allow) { degT = 5; err = fmax(err, e5); }
@@ -1273,11 +1293,18 @@ __global__ void k_mark(const PartConst* __restrict__ pc, int64_t n, int32_t stri
   const double hs = 0.5 * (Pm + Qm), hd = 0.5 * (Pm - Qm);
   const double lp = hs + sqrt(hd * hd + rr * rr + ri * ri);
   const double lm = (Pm * Qm - (rr * rr + ri * ri)) / lp;
-  // F moves by up to 2 cond(M) e for a relative template error e
+  // F moves by up to 2 cond(M) e for a relative template error e, e the
+  // largest error among the partition's interpolated items: re-evaluating the
+  // items above budget / (2 cond) brings the bound under the budget
   if (!(lp > 0.0) || !(2.0 * emax * lp <= budget * lm)) {
-    int at = atomicAdd(nrefine, ninterp);
+    const bool all = !(lp > 0.0) || !(lm > 0.0);
+    const double thr = all ? 0.0 : budget * lm / (2.0 * lp);
+    int nsel = 0;
     for (int i = 0; i < c; ++i)
-      if (xflag[o + i] == 0) refine[at++] = o + i;
+      if (xflag[o + i] == 0 && (all || (double)xerr[o + i] > thr)) ++nsel;
+    int at = atomicAdd(nrefine, nsel);
+    for (int i = 0; i < c; ++i)
+      if (xflag[o + i] == 0 && (all || (double)xerr[o + i] > thr)) refine[at++] = o + i;
   }
 }
 
