@@ -263,25 +263,51 @@ static void rigid_positions(double t, double pos[3][3]) {
   }
 }
 
-/* First-generation Michelson X at spacecraft 1 (index 0) with equal static
- * delays L (reading of the TDI-X combination the paper cites):
- *   X = (1 - z^2) [ (y_{1<-3} + z y_{3<-1}) - (y_{1<-2} + z y_{2<-1}) ],
- *   z = exp(-2 pi i f L).
- * Output: TDI-X transfer for the + and x polarisation, constellation at t. */
-static void response(const or_intr *p, double f, double t, double complex T[2]) {
+/* First-generation Michelson combination at spacecraft a (index a) with equal
+ * static delays L (reading of the TDI-X combination the paper cites); with
+ * b = a + 1, c = a + 2 (mod 3):
+ *   M_a = (1 - z^2) [ (y_{a<-c} + z y_{c<-a}) - (y_{a<-b} + z y_{b<-a}) ],
+ *   z = exp(-2 pi i f L);  X = M_0, Y = M_1, Z = M_2 (cyclic relabelling).
+ * Output: transfer for the + and x polarisation, constellation at t.      */
+static void michelson(const or_intr *p, double f, double t, int a, double complex T[2]) {
   const double L = OR_ARM_M / OR_C;
   double pos[3][3], k[3], u[3], v[3];
   rigid_positions(t, pos);
   sky_frame(p->theta, p->phi, k, u, v);
-  double complex y13p, y13x, y31p, y31x, y12p, y12x, y21p, y21x;
-  link_transfer(pos, 0, 2, k, u, v, f, &y13p, &y13x);
-  link_transfer(pos, 2, 0, k, u, v, f, &y31p, &y31x);
-  link_transfer(pos, 0, 1, k, u, v, f, &y12p, &y12x);
-  link_transfer(pos, 1, 0, k, u, v, f, &y21p, &y21x);
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  double complex yacp, yacx, ycap, ycax, yabp, yabx, ybap, ybax;
+  link_transfer(pos, a, c, k, u, v, f, &yacp, &yacx);
+  link_transfer(pos, c, a, k, u, v, f, &ycap, &ycax);
+  link_transfer(pos, a, b, k, u, v, f, &yabp, &yabx);
+  link_transfer(pos, b, a, k, u, v, f, &ybap, &ybax);
   double complex z = cexp(-2.0 * I * OR_PI * f * L);
   double complex pre = 1.0 - z * z;
-  T[0] = pre * ((y13p + z * y31p) - (y12p + z * y21p));
-  T[1] = pre * ((y13x + z * y31x) - (y12x + z * y21x));
+  T[0] = pre * ((yacp + z * ycap) - (yabp + z * ybap));
+  T[1] = pre * ((yacx + z * ycax) - (yabx + z * ybax));
+}
+
+static void response(const or_intr *p, double f, double t, double complex T[2]) {
+  michelson(p, f, t, 0, T);
+}
+
+/* Channel codes: 0 X, 1 Y, 2 Z, and the noise-orthogonal combinations of the
+ * equal-arm Michelson channels (Sec. II.A names them; the paper itself uses X
+ * only): 3 A = (Z - X)/sqrt 2, 4 E = (X - 2Y + Z)/sqrt 6, 5 T = (X + Y + Z)/sqrt 3. */
+static int channel_ok(int ch) { return ch >= 0 && ch <= 5; }
+static void response_ch(const or_intr *p, double f, double t, int ch, double complex T[2]) {
+  if (ch <= 2) {
+    michelson(p, f, t, ch, T);
+    return;
+  }
+  double complex X[2], Y[2], Z[2];
+  michelson(p, f, t, 0, X);
+  michelson(p, f, t, 1, Y);
+  michelson(p, f, t, 2, Z);
+  for (int q = 0; q < 2; ++q) {
+    if (ch == 3) T[q] = (Z[q] - X[q]) / sqrt(2.0);
+    else if (ch == 4) T[q] = (X[q] - 2.0 * Y[q] + Z[q]) / sqrt(6.0);
+    else T[q] = (X[q] + Y[q] + Z[q]) / sqrt(3.0);
+  }
 }
 
 /* Four real-amplitude basis templates at one frequency (Eq. "response"):
@@ -289,13 +315,13 @@ static void response(const or_intr *p, double f, double t, double complex T[2]) 
  * g = f^{-7/6} exp(-i Psi(f)) with phi_c = 0.  With the App. B amplitudes
  * a_1..a_4 this reproduces h_X = T+ h+ + Tx hx for h+ = (1+cos^2 i)/2 ...,
  * hx = -i cos(i) ... rotated by psi (reading of the App. B conventions).    */
-static void basis_at(const or_intr *p, const or_pq *pq, double f, double complex A[4]) {
+static void basis_at(const or_intr *p, const or_pq *pq, double f, int ch, double complex A[4]) {
   qd cyc = phase_cycles_q(pq, f, 0.0);
   double fr = (double)(cyc - floorq(cyc));
   double ph = 2.0 * OR_PI * fr;
   double complex g = pow(f, -7.0 / 6.0) * cexp(-I * ph);
   double complex T[2];
-  response(p, f, tf_of(p, f), T);
+  response_ch(p, f, tf_of(p, f), ch, T);
   A[0] = T[0] * g;
   A[1] = -T[1] * g;
   A[2] = -I * T[0] * g;
@@ -479,6 +505,21 @@ int or_response(const double *theta6, const double *f, const double *t, int64_t 
   return 0;
 }
 
+/* Transfer of channel `ch` (codes above) at frequencies f and orbit times t:
+ * output [n][2][2].                                                         */
+int or_response_ch(const double *theta6, const double *f, const double *t, int64_t n, int ch,
+                   double *out) {
+  or_intr p = unpack(theta6);
+  if (!params_ok(&p) || !channel_ok(ch)) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    double complex T[2];
+    response_ch(&p, f[i], t[i], ch, T);
+    out[4 * i + 0] = creal(T[0]); out[4 * i + 1] = cimag(T[0]);
+    out[4 * i + 2] = creal(T[1]); out[4 * i + 3] = cimag(T[1]);
+  }
+  return 0;
+}
+
 /* Single-link transfer y_{r<-s} for unit + and x amplitude at frequency f and
  * explicit spacecraft positions pos[3][3] (for the time-domain pin).        */
 void or_link(const double *pos9, int r, int s, double theta, double phi, double f, double *out4) {
@@ -490,14 +531,14 @@ void or_link(const double *pos9, int r, int s, double theta, double phi, double 
   out4[0] = creal(yp); out4[1] = cimag(yp); out4[2] = creal(yx); out4[3] = cimag(yx);
 }
 
-/* Basis templates A^1..A^4 at frequencies f: output [n][4][2]. */
-int or_basis(const double *theta6, const double *f, int64_t n, double *out) {
+/* Basis templates A^1..A^4 of channel ch at frequencies f: output [n][4][2]. */
+int or_basis(const double *theta6, const double *f, int64_t n, int ch, double *out) {
   or_intr p = unpack(theta6);
-  if (!params_ok(&p)) return -1;
+  if (!params_ok(&p) || !channel_ok(ch)) return -1;
   or_pq pq = phase_consts(&p);
   for (int64_t i = 0; i < n; ++i) {
     double complex A[4];
-    basis_at(&p, &pq, f[i], A);
+    basis_at(&p, &pq, f[i], ch, A);
     for (int b = 0; b < 4; ++b) {
       out[8 * i + 2 * b] = creal(A[b]);
       out[8 * i + 2 * b + 1] = cimag(A[b]);
@@ -519,9 +560,9 @@ int or_support(const double *theta6, double T_obs, double f_first, double f_last
 /* Injected signal sum_i a_i A^i on the grid f_j = (k_lo + j) df, set to zero
  * outside the template support during [0, T_obs].  Output [nbins][2].     */
 int or_signal(const double *theta6, const double *amp4, double df, int64_t k_lo, int64_t nbins,
-              double T_obs, double *out) {
+              double T_obs, int ch, double *out) {
   or_intr p = unpack(theta6);
-  if (!params_ok(&p) || nbins <= 0) return -1;
+  if (!params_ok(&p) || nbins <= 0 || !channel_ok(ch)) return -1;
   memset(out, 0, sizeof(double) * 2 * (size_t)nbins);
   double f_first = (double)k_lo * df, f_last = (double)(k_lo + nbins - 1) * df;
   double flo, fhi;
@@ -532,7 +573,7 @@ int or_signal(const double *theta6, const double *amp4, double df, int64_t k_lo,
     double f = (double)(k_lo + j) * df;
     if (f < flo || f > fhi) continue;
     double complex A[4];
-    basis_at(&p, &pq, f, A);
+    basis_at(&p, &pq, f, ch, A);
     double complex h = amp4[0] * A[0] + amp4[1] * A[1] + amp4[2] * A[2] + amp4[3] * A[3];
     out[2 * j] = creal(h);
     out[2 * j + 1] = cimag(h);
@@ -541,8 +582,10 @@ int or_signal(const double *theta6, const double *amp4, double df, int64_t k_lo,
 }
 
 /* Semi-coherent F-statistic (Eq. "semi-cohF").
- *   data  [nbins][2]  s(f_j), f_j = (k_lo + j) df
- *   psd   [nbins]     one-sided S_n(f_j) > 0
+ *   data  [nch][nbins][2]  s_c(f_j), f_j = (k_lo + j) df, channel c = chans[c]
+ *         (chans NULL, nch 1: TDI-X)
+ *   psd   [nch][nbins]     one-sided S_c(f_j) > 0 (channel noises independent:
+ *         N and M are sums over the channels)
  *   params[n][6], np[n] (or np == NULL and np_uniform)
  *   F_hat [n]; F_part [n][part_stride] (or NULL); cond [n][part_stride] (or NULL)
  * Partition edges e_l = f_lo + (f_hi - f_lo) l / Np; bin j is in partition l
@@ -552,15 +595,17 @@ int or_signal(const double *theta6, const double *amp4, double df, int64_t k_lo,
 int or_fstat(const double *data, const double *psd, int64_t nbins, int64_t k_lo, double df,
              double T_obs, const double *params, int64_t n, const int32_t *np, int32_t np_uniform,
              double *F_hat, double *F_part, int64_t part_stride, double *cond_out,
-             double *amps_out) {
-  if (nbins <= 0 || n < 0 || !(df > 0.0)) return -1;
+             double *amps_out, const int32_t *chans, int32_t nch) {
+  if (nbins <= 0 || n < 0 || !(df > 0.0) || nch < 1) return -1;
+  for (int c = 0; c < nch; ++c)
+    if (!channel_ok(chans ? chans[c] : 0)) return -1;
   for (int64_t i = 0; i < n; ++i) {
     or_intr p = unpack(params + 6 * i);
     int npi = np ? np[i] : np_uniform;
     if (!params_ok(&p) || npi < 1) return -1;
     if (F_part && npi > part_stride) return -1;
   }
-  for (int64_t j = 0; j < nbins; ++j)
+  for (int64_t j = 0; j < nbins * nch; ++j)
     if (!(psd[j] > 0.0)) return -1;
   const double f_first = (double)k_lo * df, f_last = (double)(k_lo + nbins - 1) * df;
   int err = 0;
@@ -593,13 +638,16 @@ int or_fstat(const double *data, const double *psd, int64_t nbins, int64_t k_lo,
       double f = (double)(k_lo + j) * df;
       if (f < flo || f > fhi) continue;
       while (l < Np - 1 && f >= edge[l + 1]) ++l;
-      double complex A[4];
-      basis_at(&p, &pq, f, A);
-      double complex s = data[2 * j] + I * data[2 * j + 1];
-      for (int a = 0; a < 4; ++a) {
-        acc_add(&accN[4 * l + a], creal(s * conj(A[a])) / psd[j]);
-        for (int b = 0; b < 4; ++b)
-          acc_add(&accM[16 * l + 4 * a + b], creal(A[a] * conj(A[b])) / psd[j]);
+      for (int c = 0; c < nch; ++c) {   /* channels with independent noise: sums add */
+        double complex A[4];
+        basis_at(&p, &pq, f, chans ? chans[c] : 0, A);
+        const int64_t jc = (int64_t)c * nbins + j;
+        double complex s = data[2 * jc] + I * data[2 * jc + 1];
+        for (int a = 0; a < 4; ++a) {
+          acc_add(&accN[4 * l + a], creal(s * conj(A[a])) / psd[jc]);
+          for (int b = 0; b < 4; ++b)
+            acc_add(&accM[16 * l + 4 * a + b], creal(A[a] * conj(A[b])) / psd[jc]);
+        }
       }
     }
     double sum = 0.0;

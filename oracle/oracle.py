@@ -49,13 +49,14 @@ def lib():
         L.or_response.argtypes = [_dp, _dp, _dp, ctypes.c_int64, _dp]
         L.or_link.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, _dp]
-        L.or_basis.argtypes = [_dp, _dp, ctypes.c_int64, _dp]
+        L.or_response_ch.argtypes = [_dp, _dp, _dp, ctypes.c_int64, ctypes.c_int, _dp]
+        L.or_basis.argtypes = [_dp, _dp, ctypes.c_int64, ctypes.c_int, _dp]
         L.or_support.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
         L.or_signal.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
-                                ctypes.c_double, _dp]
+                                ctypes.c_double, ctypes.c_int, _dp]
         L.or_fstat.argtypes = [_dp, _dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
                                ctypes.c_double, _dp, ctypes.c_int64, _i32p, ctypes.c_int32,
-                               _dp, _dp, ctypes.c_int64, _dp, _dp]
+                               _dp, _dp, ctypes.c_int64, _dp, _dp, _i32p, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -109,6 +110,24 @@ def response(theta6, f, t):
     return out[:, 0] + 1j * out[:, 1], out[:, 2] + 1j * out[:, 3]
 
 
+CHANNELS = {"X": 0, "Y": 1, "Z": 2, "A": 3, "E": 4, "T": 5}
+
+
+def _ch(channel) -> int:
+    return CHANNELS[channel] if isinstance(channel, str) else int(channel)
+
+
+def response_ch(theta6, f, t, channel):
+    """Transfer (T+, Tx) of a TDI channel ('X', 'Y', 'Z', 'A', 'E', 'T')."""
+    th, tp = _d(theta6)
+    f, fp = _d(np.atleast_1d(f))
+    t, tt = _d(np.broadcast_to(np.atleast_1d(t), f.shape))
+    out = np.empty((f.size, 4))
+    if lib().or_response_ch(tp, fp, tt, f.size, _ch(channel), out.ctypes.data_as(_dp)):
+        raise ValueError("bad parameters")
+    return out[:, 0] + 1j * out[:, 1], out[:, 2] + 1j * out[:, 3]
+
+
 def link(pos, r, s, theta, phi, f):
     p, pp = _d(pos)
     out = np.empty(4)
@@ -116,12 +135,12 @@ def link(pos, r, s, theta, phi, f):
     return out[0] + 1j * out[1], out[2] + 1j * out[3]
 
 
-def basis(theta6, f):
-    """The four basis templates A^i(f): complex array [n, 4]."""
+def basis(theta6, f, channel="X"):
+    """The four basis templates A^i(f) of a channel: complex array [n, 4]."""
     th, tp = _d(theta6)
     f, fp = _d(np.atleast_1d(f))
     out = np.empty((f.size, 4, 2))
-    if lib().or_basis(tp, fp, f.size, out.ctypes.data_as(_dp)):
+    if lib().or_basis(tp, fp, f.size, _ch(channel), out.ctypes.data_as(_dp)):
         raise ValueError("bad parameters")
     return out[..., 0] + 1j * out[..., 1]
 
@@ -135,24 +154,32 @@ def support(theta6, T_obs, f_first, f_last):
     return (float(out[0]), float(out[1])) if ok else None
 
 
-def signal(theta6, amp4, df, k_lo, nbins, T_obs):
-    """sum_i a_i A^i on the grid, zero outside the support: complex [nbins]."""
+def signal(theta6, amp4, df, k_lo, nbins, T_obs, channel="X"):
+    """sum_i a_i A^i of a channel on the grid, zero outside the support:
+    complex [nbins]."""
     th, tp = _d(theta6)
     a, ap = _d(amp4)
     out = np.empty((int(nbins), 2))
-    if lib().or_signal(tp, ap, float(df), int(k_lo), int(nbins), float(T_obs), out.ctypes.data_as(_dp)):
+    if lib().or_signal(tp, ap, float(df), int(k_lo), int(nbins), float(T_obs), _ch(channel),
+                       out.ctypes.data_as(_dp)):
         raise ValueError("bad parameters")
     return out[:, 0] + 1j * out[:, 1]
 
 
 def fstat(data, psd, k_lo, df, T_obs, params, np_parts, part_stride=None, want_cond=False,
-          want_amps=False):
+          want_amps=False, channels=None):
     """Semi-coherent F (Eq. "semi-cohF").  Returns (F_hat, F_part[, cond][, amps]):
     amps [n, stride, 4] are the maximising amplitudes a = M^{-1} N of each
-    partition (Eq. "aandMN3"), minimum-norm when M is singular."""
-    data = np.ascontiguousarray(data, dtype=np.complex128)
+    partition (Eq. "aandMN3"), minimum-norm when M is singular.  With
+    `channels` (e.g. "AET"), data and psd are [channels, nbins] and N, M are
+    summed over the channels (independent noise); without, one TDI-X channel."""
+    chans = None
+    if channels is not None:
+        chans = np.ascontiguousarray([_ch(c) for c in channels], dtype=np.int32)
+    nch = 1 if chans is None else len(chans)
+    data = np.ascontiguousarray(data, dtype=np.complex128).reshape(nch, -1)
     dv = data.view(np.float64)
-    psd, pp = _d(psd)
+    psd, pp = _d(np.asarray(psd, dtype=np.float64).reshape(nch, -1))
     params = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64)
     n = params.shape[0]
     npa = np.ascontiguousarray(np.broadcast_to(np.asarray(np_parts, dtype=np.int32), (n,)))
@@ -161,11 +188,12 @@ def fstat(data, psd, k_lo, df, T_obs, params, np_parts, part_stride=None, want_c
     Fp = np.zeros((n, stride))
     cond = np.zeros((n, stride)) if want_cond else None
     amps = np.zeros((n, stride, 4)) if want_amps else None
-    rc = lib().or_fstat(dv.ctypes.data_as(_dp), pp, data.size, int(k_lo), float(df), float(T_obs),
-                        params.ctypes.data_as(_dp), n, npa.ctypes.data_as(_i32p), 0,
+    rc = lib().or_fstat(dv.ctypes.data_as(_dp), pp, data.shape[1], int(k_lo), float(df),
+                        float(T_obs), params.ctypes.data_as(_dp), n, npa.ctypes.data_as(_i32p), 0,
                         Fh.ctypes.data_as(_dp), Fp.ctypes.data_as(_dp), stride,
                         cond.ctypes.data_as(_dp) if want_cond else None,
-                        amps.ctypes.data_as(_dp) if want_amps else None)
+                        amps.ctypes.data_as(_dp) if want_amps else None,
+                        chans.ctypes.data_as(_i32p) if chans is not None else None, nch)
     if rc:
         raise ValueError(f"oracle fstat failed ({rc})")
     out = (Fh, Fp)

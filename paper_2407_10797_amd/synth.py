@@ -74,6 +74,25 @@ def psd_tdix(f: np.ndarray) -> np.ndarray:
     return 16.0 * np.sin(x) ** 2 * (s_oms + (3.0 + np.cos(2.0 * x)) * s_acc)
 
 
+def psd_channel(f: np.ndarray, channel: str) -> np.ndarray:
+    """One-sided PSD of a first-generation equal-arm TDI channel with the noise
+    levels above: X, Y, Z as psd_tdix; A = E = S_X - S_XY and T = S_X + 2 S_XY
+    with the Michelson cross spectrum S_XY = -8 sin^2(x) cos(x) (S_oms + 4 S_acc)
+    (the channels A, E, T have independent noise)."""
+    f = np.asarray(f, dtype=np.float64)
+    if channel in ("X", "Y", "Z"):
+        return psd_tdix(f)
+    x = 2.0 * np.pi * f * ARM_M / C_SI
+    s_acc = S_ACC_ASD ** 2 * (1.0 + (F_KNEE_ACC / f) ** 2) / (2.0 * np.pi * f * C_SI) ** 2
+    s_oms = S_OMS_ASD ** 2 * (2.0 * np.pi * f / C_SI) ** 2
+    s2, c1 = np.sin(x) ** 2, np.cos(x)
+    if channel in ("A", "E"):
+        return 8.0 * s2 * ((2.0 + c1) * s_oms + 2.0 * (3.0 + 2.0 * c1 + np.cos(2.0 * x)) * s_acc)
+    if channel == "T":
+        return 16.0 * s2 * ((1.0 - c1) * s_oms + 2.0 * (1.0 - c1) ** 2 * s_acc)
+    raise ValueError(f"unknown channel {channel!r}")
+
+
 def noise(psd: np.ndarray, df: float, seed: int) -> np.ndarray:
     """Stationary Gaussian noise on the grid: n_j = sqrt(S_j / (4 df)) (x + i y),
     x, y ~ N(0, 1), so that Var <n, h> = <h, h>."""

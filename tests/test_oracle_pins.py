@@ -501,3 +501,68 @@ def test_extrinsic_round_trip():
     dpsi = np.mod(out[:, 2] - psi, np.pi / 2)
     assert np.all(np.minimum(dpsi, np.pi / 2 - dpsi) < 1e-8)
     np.testing.assert_allclose(X.forward(D, iota, psi + np.pi / 2, phic + np.pi), a, atol=1e-14)
+
+
+# ---- several TDI channels (Sec. II.A names X, Y, Z and A, E, T) ----------------
+
+def test_michelson_channels_are_cyclic_relabellings():
+    """Y and Z are X with the spacecraft labels turned once and twice: the
+    X combination built from single links of the relabelled constellation
+    equals the oracle's Y (Z)."""
+    inj = S.small_injection_params()
+    t, f = 3.1e6, 0.027
+    pos = O.orbit(np.array([t]), rigid=True)[0]
+    L = S.ARM_M / S.C_SI
+    z = np.exp(-2j * np.pi * f * L)
+    def x_of(pp):
+        y = lambda r, s: O.link(pp, r, s, inj[3], inj[4], f)
+        (a02p, a02x), (a20p, a20x) = y(0, 2), y(2, 0)
+        (a01p, a01x), (a10p, a10x) = y(0, 1), y(1, 0)
+        pre = 1 - z * z
+        return pre * ((a02p + z * a20p) - (a01p + z * a10p)), pre * ((a02x + z * a20x) - (a01x + z * a10x))
+    for shift, ch in ((0, "X"), (1, "Y"), (2, "Z")):
+        ref = x_of(np.ascontiguousarray(np.roll(pos, -shift, axis=0)))
+        got = O.response_ch(inj, f, t, ch)
+        for q in range(2):
+            np.testing.assert_allclose(got[q][0], ref[q], rtol=1e-12)
+
+
+def test_symmetric_channel_is_blind_at_long_wavelengths():
+    """T = (X + Y + Z)/sqrt 3: the three arm differences of a symmetric triangle
+    cancel for a spin-2 wave at leading order, so |T|/|X| -> 0 as f -> 0 (here
+    faster than f^2), while A and E keep the Michelson order."""
+    inj = S.small_injection_params()
+    r = []
+    for f in (1e-4, 2e-4):
+        TX, TT, TA = (O.response_ch(inj, f, 2e6, c) for c in "XTA")
+        r.append(abs(TT[0][0]) / abs(TX[0][0]))
+        assert 0.1 < abs(TA[0][0]) / abs(TX[0][0]) < 10.0
+    assert r[0] < 1e-6 and r[1] / r[0] > 3.5
+
+
+def test_aet_spectra_follow_from_the_michelson_cross_spectrum():
+    """S_A = S_E = S_X - S_XY, S_T = S_X + 2 S_XY with S_XY = -8 sin^2 x cos x
+    (S_oms + 4 S_acc), i.e. S_X = (S_A + S_E + S_T)/3 - the sum of the three
+    orthogonal channels carries the Michelson power."""
+    f = np.linspace(1e-3, 0.2, 400)
+    SX, SA, SE, ST = (S.psd_channel(f, c) for c in "XAET")
+    np.testing.assert_allclose(SA, SE, rtol=0)
+    np.testing.assert_allclose((SA + SE + ST) / 3.0, SX, rtol=1e-12)
+    assert np.all(SA > 0) and np.all(ST > 0)
+
+
+@pytest.mark.parametrize("channels", ["X", "AET", "XYZ"])
+def test_two_F_equals_rho2_several_channels(channels):
+    """Noise-free s_c = sum a_i A_c^i in every channel: N = M a with N, M summed
+    over the channels, so 2F = rho^2 = sum_c <s_c, s_c>."""
+    g, inj = _small_case()
+    a = np.random.default_rng(4).normal(size=4)
+    s = np.array([O.signal(inj, a, g.df, g.k_lo, g.nbins, g.T_obs, channel=c) for c in channels])
+    psd = np.array([S.psd_channel(g.freqs(), c) for c in channels])
+    rho2 = sum(4 * g.df * np.sum(np.abs(s[i]) ** 2 / psd[i]) for i in range(len(channels)))
+    for Np in (1, 4):
+        Fh, Fp = O.fstat(s, psd, g.k_lo, g.df, g.T_obs, inj, [Np], channels=channels)
+        np.testing.assert_allclose(2 * Fp[0].sum(), rho2, rtol=1e-10)
+    if channels == "X":
+        F1, P1 = O.fstat(s[0], psd[0], g.k_lo, g.df, g.T_obs, inj, [4])
+        np.testing.assert_array_equal(Fp, P1)
