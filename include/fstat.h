@@ -69,13 +69,32 @@ extern "C" {
 
 typedef struct fstat_plan_s *fstat_plan_t;
 
+/* TDI channels (Sec. II.A names them; the paper's search uses X alone):
+ * first-generation equal-arm Michelson combinations at spacecraft 1, 2, 3 and
+ * the combinations with independent instrumental noise
+ * A = (Z - X)/sqrt 2, E = (X - 2Y + Z)/sqrt 6, T = (X + Y + Z)/sqrt 3.     */
+#define FSTAT_CHANNEL_X 0
+#define FSTAT_CHANNEL_Y 1
+#define FSTAT_CHANNEL_Z 2
+#define FSTAT_CHANNEL_A 3
+#define FSTAT_CHANNEL_E 4
+#define FSTAT_CHANNEL_T 5
+/* fstat_waveform flags: the channel to synthesise (default X)               */
+#define FSTAT_WAVEFORM_CHANNEL(c) ((uint32_t)(c) << 8)
+
 typedef struct {
   double T_obs;        /* observation length [s] (support = [0, T_obs])        */
   double df;           /* bin spacing [Hz], > 0                                */
   int64_t k_lo;        /* first bin index, >= 1                                */
-  int64_t nbins;       /* number of bins, >= 1                                 */
-  const double *data;  /* s(f_j), complex [nbins] (interleaved)                */
-  const double *psd;   /* one-sided S_n(f_j) > 0, [nbins]                      */
+  int64_t nbins;       /* number of bins per channel, >= 1                     */
+  const double *data;  /* s_c(f_j), complex [n_channels][nbins] (interleaved)  */
+  const double *psd;   /* one-sided S_c(f_j) > 0, [n_channels][nbins]          */
+  int32_t n_channels;  /* channels with independent noise, 1..6; 0 = 1         */
+  int32_t reserved;
+  const int32_t *channels; /* [n_channels] FSTAT_CHANNEL_* codes, distinct, or
+                          NULL for a single TDI-X channel.  The statistic sums
+                          N and M over the channels (Sec. II.A, Eq. aandMN
+                          with the inner product summed over channels)       */
 } fstat_data_desc;
 
 typedef struct {
@@ -144,7 +163,8 @@ int fstat_extrinsic(const double *amps, const double *params, int64_t n, double 
  * response at the SPA time, with the four real amplitudes a_1..a_4 of
  * Sec. II.A (Eq. response) in the App. B basis; zero outside the template's
  * support during [0, T_obs].  out: complex [nbins] (interleaved).  Flags:
- * FSTAT_DEVICE_PTRS (params, amps and out all on the device).           */
+ * FSTAT_DEVICE_PTRS (params, amps and out all on the device),
+ * FSTAT_WAVEFORM_CHANNEL(c) for a channel other than X.                   */
 int fstat_waveform(double T_obs, double df, int64_t k_lo, int64_t nbins, const double *params6,
                    const double *amps4, double *out, uint32_t flags, void *hip_stream);
 

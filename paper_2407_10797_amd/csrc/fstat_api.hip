@@ -15,6 +15,8 @@
 
 using namespace fstat;
 
+static_assert(sizeof(fstat_data_desc) == 64, "fstat_data_desc layout");
+
 namespace fstat {
 
 static thread_local std::string g_err;
@@ -63,7 +65,8 @@ int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride, int chunk) {
   int rc;
   if (chunk <= 0) chunk = P->chunk;
   size_t m = (size_t)n * (size_t)stride;
-  size_t cap_items = (size_t)n * ((size_t)((P->grid.nbins + chunk - 1) / chunk) + stride);
+  const size_t nch = (size_t)P->grid.chan.n;
+  size_t cap_items = (size_t)n * ((size_t)((P->grid.nbins + chunk - 1) / chunk) + stride) * nch;
   if (cap_items > (size_t)INT32_MAX)
     return set_error(FSTAT_EINVAL, "work list too large (%zu items)", cap_items);
   if ((rc = ensure(&P->ws.pc, &P->cap.pc, (size_t)n, "alloc pc"))) return rc;
@@ -78,7 +81,7 @@ int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride, int chunk) {
   if ((rc = ensure(&P->ws.partials, &P->cap.partials, cap_items * 8, "alloc partials"))) return rc;
   if ((rc = ensure(&P->ws.direct, &P->cap.direct, cap_items, "alloc direct"))) return rc;
   if ((rc = ensure(&P->ws.ndirect, &P->cap.ndirect, 1, "alloc ndirect"))) return rc;
-  const size_t ntiles = (size_t)((P->grid.nbins + chunk - 1) / chunk);
+  const size_t ntiles = (size_t)((P->grid.nbins + chunk - 1) / chunk) * nch;   // all channels
   if ((rc = ensure(&P->ws.tcnt, &P->cap.tcnt, ntiles, "alloc tcnt"))) return rc;
   if ((rc = ensure(&P->ws.tcur, &P->cap.tcur, ntiles, "alloc tcur"))) return rc;
   if ((rc = ensure(&P->ws.toff, &P->cap.toff, ntiles + 1, "alloc toff"))) return rc;
@@ -157,8 +160,10 @@ static std::string tune_key(const fstat_plan_s* P, int32_t np, bool mixed) {
   while (npc < np) npc <<= 1;
   int nbc = 0;
   while ((1ll << nbc) < P->grid.nbins) ++nbc;
-  char buf[256];
-  snprintf(buf, sizeof(buf), "%s nbins2^%d np%d %s", arch.c_str(), nbc, npc, mixed ? "mixed" : "fp64");
+  char buf[256], chs[16] = "";
+  if (P->grid.chan.n > 1) snprintf(chs, sizeof(chs), " ch%d", P->grid.chan.n);
+  snprintf(buf, sizeof(buf), "%s nbins2^%d np%d%s %s", arch.c_str(), nbc, npc, chs,
+           mixed ? "mixed" : "fp64");
   for (char* c = buf; *c; ++c)
     if (*c == ':') *c = '_';
   return buf;
@@ -295,8 +300,21 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
   if (chunk < 64 || chunk > (1 << 24)) return set_error(FSTAT_EINVAL, "chunk out of range");
   const bool dev = (flags & FSTAT_DEVICE_PTRS) != 0;
   const int64_t nb = d->nbins;
+  Channels chan;
+  chan.n = d->n_channels > 0 ? d->n_channels : 1;
+  if (chan.n > kMaxChannels) return set_error(FSTAT_EINVAL, "at most %d channels", kMaxChannels);
+  for (int c = 0; c < chan.n; ++c) {
+    chan.code[c] = d->channels ? d->channels[c] : FSTAT_CHANNEL_X;
+    if (chan.code[c] < FSTAT_CHANNEL_X || chan.code[c] > FSTAT_CHANNEL_T)
+      return set_error(FSTAT_EINVAL, "channels[%d] = %d is not a channel code", c, chan.code[c]);
+    for (int e = 0; e < c; ++e)
+      if (chan.code[e] == chan.code[c])
+        return set_error(FSTAT_EINVAL, "channel %d listed twice", chan.code[c]);
+  }
+  const int64_t nbc = nb * chan.n;   // bins of all channels
+  if (nbc > (int64_t)INT32_MAX) return set_error(FSTAT_EINVAL, "nbins x channels out of range");
   if (!dev) {
-    for (int64_t j = 0; j < nb; ++j) {
+    for (int64_t j = 0; j < nbc; ++j) {
       if (!(d->psd[j] > 0.0) || !std::isfinite(d->psd[j]))
         return set_error(FSTAT_EINVAL, "psd[%lld] must be finite and > 0", (long long)j);
       if (!std::isfinite(d->data[2 * j]) || !std::isfinite(d->data[2 * j + 1]))
@@ -306,6 +324,7 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
   hipStream_t s = (hipStream_t)hip_stream;
   fstat_plan_s* P = new fstat_plan_s();
   P->grid = Grid{d->df, d->T_obs, d->k_lo, nb};
+  P->grid.chan = chan;
   P->prec = prec;
   P->chunk = chunk;
   P->refine_budget = budget;
@@ -315,15 +334,15 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
   if (!rc && interp_tables_init() != 0)
     rc = set_error(FSTAT_EDEVICE, "could not upload the interpolation tables");
   double *dd = nullptr, *dp = nullptr;
-  if (!rc) rc = dev_alloc(&P->b64.wr, nb, "alloc wr");
-  if (!rc) rc = dev_alloc(&P->b64.wi, nb, "alloc wi");
-  if (!rc) rc = dev_alloc(&P->b64.u, nb, "alloc u");
+  if (!rc) rc = dev_alloc(&P->b64.wr, nbc, "alloc wr");
+  if (!rc) rc = dev_alloc(&P->b64.wi, nbc, "alloc wi");
+  if (!rc) rc = dev_alloc(&P->b64.u, nbc, "alloc u");
   if (!rc) rc = dev_alloc(&P->b64.s0, nb, "alloc s0");
   if (!rc) rc = dev_alloc(&P->b64.c0, nb, "alloc c0");
   if (!rc && (prec & FSTAT_MIXED)) {
-    rc = dev_alloc(&P->b32.wr, nb, "alloc wr32");
-    if (!rc) rc = dev_alloc(&P->b32.wi, nb, "alloc wi32");
-    if (!rc) rc = dev_alloc(&P->b32.u, nb, "alloc u32");
+    rc = dev_alloc(&P->b32.wr, nbc, "alloc wr32");
+    if (!rc) rc = dev_alloc(&P->b32.wi, nbc, "alloc wi32");
+    if (!rc) rc = dev_alloc(&P->b32.u, nbc, "alloc u32");
     if (!rc) rc = dev_alloc(&P->b32.s0, nb, "alloc s032");
     if (!rc) rc = dev_alloc(&P->b32.c0, nb, "alloc c032");
   }
@@ -336,38 +355,41 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
   const double* ddata = d->data;
   const double* dpsd = d->psd;
   if (!rc && !dev) {
-    rc = dev_alloc(&dd, 2 * nb, "alloc data staging");
-    if (!rc) rc = dev_alloc(&dp, nb, "alloc psd staging");
-    if (!rc) rc = hip_check(hipMemcpyAsync(dd, d->data, sizeof(double) * 2 * nb,
+    rc = dev_alloc(&dd, 2 * nbc, "alloc data staging");
+    if (!rc) rc = dev_alloc(&dp, nbc, "alloc psd staging");
+    if (!rc) rc = hip_check(hipMemcpyAsync(dd, d->data, sizeof(double) * 2 * nbc,
                                            hipMemcpyHostToDevice, s), "copy data");
-    if (!rc) rc = hip_check(hipMemcpyAsync(dp, d->psd, sizeof(double) * nb,
+    if (!rc) rc = hip_check(hipMemcpyAsync(dp, d->psd, sizeof(double) * nbc,
                                            hipMemcpyHostToDevice, s), "copy psd");
     ddata = dd;
     dpsd = dp;
   }
   std::vector<double> ures;
+  const int32_t nut_all = (int32_t)((nb + kUTile - 1) / kUTile) * chan.n;   // u-tiles, all channels
   if (!rc) {
     P->n_utiles = (int32_t)((nb + kUTile - 1) / kUTile);
-    ures.assign((size_t)P->n_utiles, 0.0);
-    rc = dev_alloc(&P->ucoef, (size_t)P->n_utiles * kUCoef, "alloc u model");
-    if (!rc) rc = dev_alloc(&P->ubad, (size_t)P->n_utiles + 1, "alloc u model flags");
+    ures.assign((size_t)nut_all, 0.0);
+    rc = dev_alloc(&P->ucoef, (size_t)nut_all * kUCoef, "alloc u model");
+    if (!rc) rc = dev_alloc(&P->ubad, (size_t)nut_all + 1, "alloc u model flags");
   }
-  if (!rc) rc = dev_alloc(&P->ures, (size_t)P->n_utiles, "alloc u model residuals");
+  if (!rc) rc = dev_alloc(&P->ures, (size_t)nut_all, "alloc u model residuals");
   double* dres = P->ures;
   if (!rc) {
     launch_prep(P->grid, ddata, dpsd, P->b64, s);
-    launch_max(P->b64.u, nb, P->umax, s);
+    launch_max(P->b64.u, nbc, P->umax, s);
     launch_scale(P->grid, P->umax, P->b64, P->b32, s);
-    launch_ufit(P->b64.u, nb, P->n_utiles, P->ucoef, dres, s);
+    for (int c = 0; c < chan.n; ++c)
+      launch_ufit(P->b64.u + (int64_t)c * nb, nb, P->n_utiles,
+                  P->ucoef + (int64_t)c * P->n_utiles * kUCoef, dres + (int64_t)c * P->n_utiles, s);
     rc = hip_check(hipGetLastError(), "prep launch");
   }
-  if (!rc) rc = hip_check(hipMemcpyAsync(ures.data(), dres, sizeof(double) * P->n_utiles,
+  if (!rc) rc = hip_check(hipMemcpyAsync(ures.data(), dres, sizeof(double) * nut_all,
                                          hipMemcpyDeviceToHost, s), "read u model residuals");
   if (!rc) rc = hip_check(hipStreamSynchronize(s), "plan prep");
   if (!rc) {
     // prefix count of u-tiles the smooth model does not fit to within kUFitTol
-    std::vector<int32_t> bad((size_t)P->n_utiles + 1, 0);
-    for (int32_t i = 0; i < P->n_utiles; ++i) {
+    std::vector<int32_t> bad((size_t)nut_all + 1, 0);
+    for (int32_t i = 0; i < nut_all; ++i) {
       const bool ok = ures[(size_t)i] <= kUFitTol;
       bad[(size_t)i + 1] = bad[(size_t)i] + (ok ? 0 : 1);
       P->n_ufit += ok ? 1 : 0;
@@ -547,8 +569,11 @@ int fstat_waveform(double T_obs, double df, int64_t k_lo, int64_t nbins, const d
     if (!ok || !(params6[1] > 0.0) || !(std::fabs(params6[2]) < 1.0) || !(params6[5] >= 0.0))
       return set_error(FSTAT_EINVAL, "invalid parameters");
   }
+  const int code = (int)((flags >> 8) & 0xffu);
+  if (code > FSTAT_CHANNEL_T) return set_error(FSTAT_EINVAL, "bad channel code %d", code);
   hipStream_t s = (hipStream_t)hip_stream;
   Grid g{df, T_obs, k_lo, nbins};
+  g.chan.code[0] = code;
   WorkSpace ws{};
   double *dpar = nullptr, *damp = nullptr, *dout = nullptr;
   int rc = dev_alloc(&ws.pc, 1, "alloc pc");

@@ -434,6 +434,89 @@ __device__ __forceinline__ void response_fp64(const PartConst& P, double f, doub
   txi = out[1][3] * out[1][1] - out[0][3] * out[0][1];
 }
 
+// Channel codes (Grid::chan): weights of M_0 = X, M_1 = Y, M_2 = Z in a channel
+__device__ __forceinline__ void channel_weights(int code, double w[3]) {
+  const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637,
+               r3 = 0.57735026918962576451;
+  w[0] = w[1] = w[2] = 0.0;
+  if (code <= 2) w[code] = 1.0;
+  else if (code == 3) { w[0] = -r2; w[2] = r2; }
+  else if (code == 4) { w[0] = r6; w[1] = -2.0 * r6; w[2] = r6; }
+  else { w[0] = w[1] = w[2] = r3; }
+}
+
+// Michelson combination at spacecraft a (a = 0: the response_fp64 above),
+// relative to the phase reference p_1: arms from p_a to p_{a+1}, p_{a+2}, and
+// the factor exp(-2 pi i f k.(p_a - p_1)) of the vertex's offset.
+__device__ __forceinline__ void michelson_fp64(const PartConst& P, double f, double s0, double c0,
+                                               const double d[3][3], int a, double& tpr,
+                                               double& tpi, double& txr, double& txi) {
+  const double kx = P.k[0], ky = P.k[1], kz = P.k[2];
+  const double x0 = kPi * kLs * f;
+  const double zr = c0 * c0 - s0 * s0, zi = -2.0 * s0 * c0;   // z = e^{-2 i x0}
+  double out[2][4];
+#pragma unroll
+  for (int arm = 0; arm < 2; ++arm) {
+    const int w = (a + 1 + arm) % 3;
+    double ax = d[w][0] - d[a][0], ay = d[w][1] - d[a][1], az = d[w][2] - d[a][2];
+    double inv = rsq_nr(ax * ax + ay * ay + az * az);
+    ax *= inv; ay *= inv; az *= inv;
+    double kn = kx * ax + ky * ay + kz * az;
+    double un = P.u[0] * ax + P.u[1] * ay + P.u[2] * az;
+    double vn = P.v[0] * ax + P.v[1] * ay + P.v[2] * az;
+    double sq, cq;
+    sincospi(kLs * f * kn, &sq, &cq);
+    double np_ = s0 * cq + c0 * sq, nm = s0 * cq - c0 * sq;
+    double dp = x0 * (1.0 + kn), dm = x0 * (1.0 - kn);
+    double sp, sm;
+    if (fabs(dp) > 1e-6 && fabs(dm) > 1e-6) {
+      double r = rcp_nr(dp * dm);
+      sp = np_ * dm * r;
+      sm = nm * dp * r;
+    } else {
+      sp = sinc_from(np_, dp);
+      sm = sinc_from(nm, dm);
+    }
+    double Sr = sp + zr * sm, Si = zi * sm;
+    out[arm][0] = cq * Sr + sq * Si;
+    out[arm][1] = cq * Si - sq * Sr;
+    out[arm][2] = un * un - vn * vn;
+    out[arm][3] = 2.0 * un * vn;
+  }
+  double pr = out[1][2] * out[1][0] - out[0][2] * out[0][0];
+  double pi = out[1][2] * out[1][1] - out[0][2] * out[0][1];
+  double xr = out[1][3] * out[1][0] - out[0][3] * out[0][0];
+  double xi = out[1][3] * out[1][1] - out[0][3] * out[0][1];
+  if (a != 0) {
+    const double kd = kx * (d[a][0] - d[0][0]) + ky * (d[a][1] - d[0][1]) + kz * (d[a][2] - d[0][2]);
+    double sv, cv;
+    sincospi(2.0 * f * kd, &sv, &cv);          // e^{-i 2 pi f kd} = cv - i sv
+    const double r0 = pr * cv + pi * sv, i0 = pi * cv - pr * sv;
+    const double r1 = xr * cv + xi * sv, i1 = xi * cv - xr * sv;
+    pr = r0; pi = i0; xr = r1; xi = i1;
+  }
+  tpr = pr; tpi = pi; txr = xr; txi = xi;
+}
+
+// Transfer of channel `code` (relative to the phase reference p_1).
+__device__ __forceinline__ void response_ch_fp64(const PartConst& P, double f, double s0, double c0,
+                                                 const double d[3][3], int code, double& tpr,
+                                                 double& tpi, double& txr, double& txi) {
+  double w[3];
+  channel_weights(code, w);
+  tpr = tpi = txr = txi = 0.0;
+  // one copy of the Michelson code in a rolled loop: unrolled, the three
+  // copies raise the kernels' register use above the occupancy limit
+#pragma unroll 1
+  for (int a = 0; a < 3; ++a) {
+    if (w[a] == 0.0) continue;
+    double pr, pi, xr, xi;
+    michelson_fp64(P, f, s0, c0, d, a, pr, pi, xr, xi);
+    tpr = fma(w[a], pr, tpr); tpi = fma(w[a], pi, tpi);
+    txr = fma(w[a], xr, txr); txi = fma(w[a], xi, txi);
+  }
+}
+
 // k . p_1 [s] of spacecraft 1 at orbit angle (ca, sa); fills the offsets d
 __device__ __forceinline__ double k_dot_p1(const PartConst& P, double ca, double sa, double d[3][3]) {
   orbit_offsets<double>(ca, sa, d);
@@ -444,7 +527,7 @@ __device__ __forceinline__ double k_dot_p1(const PartConst& P, double ca, double
 __device__ __forceinline__ void template_fp64(const PartConst& P, double f, double s0, double c0,
                                               double& cph, double& sph, double& tpr,
                                               double& tpi, double& txr, double& txi,
-                                              const double* ek = nullptr) {
+                                              const double* ek = nullptr, int code = 0) {
   double fr, tf;
   phase_and_tf(P, f, fr, tf, ek);
   double sa, ca;
@@ -454,14 +537,15 @@ __device__ __forceinline__ void template_fp64(const PartConst& P, double f, doub
   double ph = fr + f * kp1;               // Phi / (2 pi) in cycles
   ph -= rint(ph);
   sincospi(2.0 * ph, &sph, &cph);
-  response_fp64(P, f, s0, c0, d, tpr, tpi, txr, txi);
+  response_ch_fp64(P, f, s0, c0, d, code, tpr, tpi, txr, txi);
 }
 
 // The template at an arbitrary frequency fd (double-double; an interpolation
 // node): the whole phase Phi / (2 pi) = Psi / (2 pi) + f k.p_1 in cycles
 // (double-double, not reduced) and the transfer without the Doppler factor.
 __device__ __forceinline__ dd template_node(const PartConst& P, dd fd, const double* ek,
-                                            double& tpr, double& tpi, double& txr, double& txi) {
+                                            double& tpr, double& tpi, double& txr, double& txi,
+                                            int code = 0) {
   dd tf;
   dd ph = phase_full(P, fd, tf, ek);
   const double f = fd.hi;
@@ -475,7 +559,7 @@ __device__ __forceinline__ dd template_node(const PartConst& P, dd fd, const dou
   double kp1 = k_dot_p1(P, ca, sa, d);
   double s0, c0;
   sincospi(kLs * f, &s0, &c0);
-  response_fp64(P, f, s0, c0, d, tpr, tpi, txr, txi);
+  response_ch_fp64(P, f, s0, c0, d, code, tpr, tpi, txr, txi);
   return dd_add(ph, dd_mul_d(fd, kp1));
 }
 

@@ -9,11 +9,20 @@
 namespace fstat {
 
 // frequency grid f_j = (k_lo + j) df, j < nbins; support window [0, T_obs]
+// TDI channels: 0 X, 1 Y, 2 Z (first-generation Michelson at spacecraft 1, 2,
+// 3), 3 A = (Z - X)/sqrt 2, 4 E = (X - 2Y + Z)/sqrt 6, 5 T = (X + Y + Z)/sqrt 3.
+constexpr int kMaxChannels = 6;
+struct Channels {
+  int32_t n = 1;                                  // channels summed by the statistic
+  int32_t code[kMaxChannels] = {0, 0, 0, 0, 0, 0};   // channel codes in data order
+};
+
 struct Grid {
   double df;
   double T_obs;
   int64_t k_lo;
-  int64_t nbins;
+  int64_t nbins;       // bins per channel
+  Channels chan{};     // per-channel arrays are stacked channel-major
 };
 
 // per-bin prepared data of one precision (structure of arrays)

@@ -42,6 +42,7 @@ __global__ void k_prep(Grid g, const double* __restrict__ data, const double* __
                        double* __restrict__ s0, double* __restrict__ c0) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= g.nbins) return;
+  const int64_t jc = (int64_t)blockIdx.y * g.nbins + j;   // channel blockIdx.y
   double f = (double)(g.k_lo + j) * g.df;
   double s, c;
   sincospi(kLs * f, &s, &c);
@@ -51,15 +52,17 @@ __global__ void k_prep(Grid g, const double* __restrict__ data, const double* __
   double er = -x0 * s, ei = -x0 * c;                               // -i x0 e^{-i x0}
   double Cr = omr * er - omi * ei, Ci = omr * ei + omi * er;
   double amp = pow(f, -7.0 / 6.0);
-  double wgt = 4.0 * g.df / psd[j];
-  double dr = data[2 * j], di = data[2 * j + 1];
+  double wgt = 4.0 * g.df / psd[jc];
+  double dr = data[2 * jc], di = data[2 * jc + 1];
   // s conj(C)
   double pr = dr * Cr + di * Ci, pi = di * Cr - dr * Ci;
-  wr[j] = wgt * amp * pr;
-  wi[j] = wgt * amp * pi;
-  u[j] = wgt * amp * amp * (Cr * Cr + Ci * Ci);
-  s0[j] = s;
-  c0[j] = c;
+  wr[jc] = wgt * amp * pr;
+  wi[jc] = wgt * amp * pi;
+  u[jc] = wgt * amp * amp * (Cr * Cr + Ci * Ci);
+  if (blockIdx.y == 0) {
+    s0[j] = s;
+    c0[j] = c;
+  }
 }
 
 // max of u over the band (one block, grid-stride) -> *out
@@ -86,14 +89,15 @@ __global__ void k_scale(Grid g, const double* __restrict__ umax, double* __restr
                         float* __restrict__ c032) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= g.nbins) return;
+  const int64_t jc = (int64_t)blockIdx.y * g.nbins + j;   // channel blockIdx.y
   double m = umax[0];
   double gam2 = (m > 0.0) ? 1.0 / m : 1.0;
   double gam = sqrt(gam2);
-  double a = wr[j] * gam, b = wi[j] * gam, c = u[j] * gam2;
-  wr[j] = a; wi[j] = b; u[j] = c;
+  double a = wr[jc] * gam, b = wi[jc] * gam, c = u[jc] * gam2;
+  wr[jc] = a; wi[jc] = b; u[jc] = c;
   if (wr32) {
-    wr32[j] = (float)a; wi32[j] = (float)b; u32[j] = (float)c;
-    s032[j] = (float)s0[j]; c032[j] = (float)c0[j];
+    wr32[jc] = (float)a; wi32[jc] = (float)b; u32[jc] = (float)c;
+    if (blockIdx.y == 0) { s032[j] = (float)s0[j]; c032[j] = (float)c0[j]; }
   }
 }
 
@@ -107,6 +111,19 @@ __device__ __forceinline__ double bin_freq(const Grid& g, int64_t j) {
 // Work item c of a partition with bins [a, b): its part inside bin tile
 // a / T + c of the global tiling of the band into tiles of T bins.
 __device__ __forceinline__ int item_tile(int a, int c, int T) { return a / T + c; }
+// With several channels a partition has (tiles met) x (channels) items:
+// item c covers tile offset c / nch of channel c % nch.
+__device__ __forceinline__ void item_split(int c, int nch, int& ct, int& ch) {
+  ct = c / nch;
+  ch = c - ct * nch;
+}
+// The item's tile in the numbering of all channels' tiles, channel by
+// channel (ntiles = nch x tiles per channel).
+__device__ __forceinline__ int item_xtile(int a, int c, int T, int nch, int ntiles) {
+  int ct, ch;
+  item_split(c, nch, ct, ch);
+  return ch * (ntiles / nch) + item_tile(a, ct, T);
+}
 __device__ __forceinline__ void item_bins(int a, int b, int c, int T, int& b0, int& b1) {
   const int t = a / T + c;
   b0 = max(a, t * T);
@@ -226,7 +243,7 @@ __global__ __launch_bounds__(256) void k_setup(Grid g, const double* __restrict_
     const int a = edge(l), b = edge(l + 1);
     bp[l] = a;
     if (l == npi - 1) bp[npi] = b;
-    cp[l] = b > a ? (b - 1) / chunk - a / chunk + 1 : 0;   // bin tiles the partition meets
+    cp[l] = b > a ? ((b - 1) / chunk - a / chunk + 1) * g.chan.n : 0;   // tiles met x channels
   }
 }
 
@@ -393,8 +410,12 @@ __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
     int p = q / stride, l = q - p * stride;
     const PartConst& P = pc[p];
     const int32_t* bp = bounds + (int64_t)p * (stride + 1);
+    int ct, ch;
+    item_split(c, g.chan.n, ct, ch);
+    const int code = g.chan.code[ch];
+    const int64_t co = (int64_t)ch * g.nbins;   // the channel's data
     int b0, b1;
-    item_bins(bp[l], bp[l + 1], c, chunk, b0, b1);
+    item_bins(bp[l], bp[l + 1], ct, chunk, b0, b1);
     const double* ekq = (ek && P.sur) ? ek + 8 * (int64_t)q : nullptr;
     // Kahan-compensated per-lane sums (true sum ~ acc - cmp): the partition
     // matrix can have cond ~ 1e5..1e8, which amplifies summation error.
@@ -404,8 +425,8 @@ __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
     for (int j = b0 + lane; j < b1; j += 64) {
       double f = bin_freq(g, j);
       double cps, sps, tpr, tpi, txr, txi;
-      template_fp64(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq);
-      double a = wr[j], b = wi[j], uu = u[j];
+      template_fp64(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq, code);
+      double a = wr[co + j], b = wi[co + j], uu = u[co + j];
       double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
       double t[8];
       t[0] = Wr * tpr + Wi * tpi;     // Z+ = sum W conj(T'+)
@@ -456,9 +477,62 @@ __device__ __forceinline__ void kahan_addf(float& s, float& c, float x) {
   s = t;
 }
 
+// FP32 Michelson combination at spacecraft a relative to the phase reference
+// p_1 (see michelson_fp64).
+__device__ __forceinline__ void michelson_f32(const float k[3], const float u[3], const float v[3],
+                                              const float d[3][3], float fl, float s0, float c0,
+                                              int a, float& tpr, float& tpi, float& txr,
+                                              float& txi) {
+  const float x0 = (float)(kPi * kLs) * fl;
+  const float zr = c0 * c0 - s0 * s0, zi = -2.0f * s0 * c0;
+  float out[2][4];
+#pragma unroll
+  for (int arm = 0; arm < 2; ++arm) {
+    const int w = (a + 1 + arm) % 3;
+    float ax = d[w][0] - d[a][0], ay = d[w][1] - d[a][1], az = d[w][2] - d[a][2];
+    float inv = __builtin_amdgcn_rsqf(ax * ax + ay * ay + az * az);
+    ax *= inv; ay *= inv; az *= inv;
+    float kn = k[0] * ax + k[1] * ay + k[2] * az;
+    float un = u[0] * ax + u[1] * ay + u[2] * az;
+    float vn = v[0] * ax + v[1] * ay + v[2] * az;
+    float sq, cq;
+    sincos_revf(0.5f * (float)kLs * fl * kn, sq, cq);      // x0 kn
+    float np_ = s0 * cq + c0 * sq, nm = s0 * cq - c0 * sq;
+    float dp = x0 * (1.0f + kn), dm = x0 * (1.0f - kn);
+    float sp, sm;
+    if (fabsf(dp) > 1e-3f && fabsf(dm) > 1e-3f) {
+      float r = __builtin_amdgcn_rcpf(dp * dm);
+      sp = np_ * dm * r;
+      sm = nm * dp * r;
+    } else {
+      sp = sincf_from(np_, dp);
+      sm = sincf_from(nm, dm);
+    }
+    float Sr = sp + zr * sm, Si = zi * sm;
+    out[arm][0] = cq * Sr + sq * Si;
+    out[arm][1] = cq * Si - sq * Sr;
+    out[arm][2] = un * un - vn * vn;
+    out[arm][3] = 2.0f * un * vn;
+  }
+  float pr = out[1][2] * out[1][0] - out[0][2] * out[0][0];
+  float pi = out[1][2] * out[1][1] - out[0][2] * out[0][1];
+  float xr = out[1][3] * out[1][0] - out[0][3] * out[0][0];
+  float xi = out[1][3] * out[1][1] - out[0][3] * out[0][1];
+  if (a != 0) {
+    const float kd = k[0] * (d[a][0] - d[0][0]) + k[1] * (d[a][1] - d[0][1]) + k[2] * (d[a][2] - d[0][2]);
+    float sv, cv;
+    sincos_revf(fl * kd, sv, cv);               // e^{-i 2 pi f kd} = cv - i sv
+    const float r0 = pr * cv + pi * sv, i0 = pi * cv - pr * sv;
+    const float r1 = xr * cv + xi * sv, i1 = xi * cv - xr * sv;
+    pr = r0; pi = i0; xr = r1; xi = i1;
+  }
+  tpr = pr; tpi = pi; txr = xr; txi = xi;
+}
+
 __device__ __forceinline__ void template_mixed(const PartConst& P, double f, float s0, float c0,
                                                float& cph, float& sph, float& tpr, float& tpi,
-                                               float& txr, float& txi, const double* ek) {
+                                               float& txr, float& txi, const double* ek,
+                                               int code = 0) {
   double fr, tf;
   phase_and_tf(P, f, fr, tf, ek);
   double sad, cad;
@@ -472,6 +546,21 @@ __device__ __forceinline__ void template_mixed(const PartConst& P, double f, flo
   float kd0 = kx * d[0][0] + ky * d[0][1] + kz * d[0][2];
   sincos_rev(fr + f * (kP + (double)kd0), sph, cph);      // e^{i Phi}
   const float fl = (float)f;
+  if (code != 0) {
+    const float kk[3] = {kx, ky, kz}, uu[3] = {ux, uy, uz}, vv[3] = {vx, vy, vz};
+    double wd[3];
+    channel_weights(code, wd);
+    tpr = tpi = txr = txi = 0.0f;
+#pragma unroll 1
+    for (int a = 0; a < 3; ++a) {
+      if (wd[a] == 0.0) continue;
+      const float wa = (float)wd[a];
+      float pr, pi, xr, xi;
+      michelson_f32(kk, uu, vv, d, fl, s0, c0, a, pr, pi, xr, xi);
+      tpr += wa * pr; tpi += wa * pi; txr += wa * xr; txi += wa * xi;
+    }
+    return;
+  }
   const float x0 = (float)(kPi * kLs) * fl;
   const float zr = c0 * c0 - s0 * s0, zi = -2.0f * s0 * c0;
   float out[2][4];
@@ -535,8 +624,12 @@ __global__ __launch_bounds__(256) void k_eval_mixed(Grid g,
     int p = q / stride, l = q - p * stride;
     const PartConst& P = pc[p];
     const int32_t* bp = bounds + (int64_t)p * (stride + 1);
+    int ct, ch;
+    item_split(c, g.chan.n, ct, ch);
+    const int code = g.chan.code[ch];
+    const int64_t co = (int64_t)ch * g.nbins;   // the channel's data
     int b0, b1;
-    item_bins(bp[l], bp[l + 1], c, chunk, b0, b1);
+    item_bins(bp[l], bp[l + 1], ct, chunk, b0, b1);
     const double* ekq = (ek && P.sur) ? ek + 8 * (int64_t)q : nullptr;
     // N-terms (Z+, Zx) in FP32 with Kahan; M-terms (P, Q, R) in FP64 from the
     // FP32 response: the partition matrix can be ill-conditioned, and FP32
@@ -548,14 +641,14 @@ __global__ __launch_bounds__(256) void k_eval_mixed(Grid g,
     for (int j = b0 + lane; j < b1; j += 64) {
       double f = bin_freq(g, j);
       float cps, sps, tpr, tpi, txr, txi;
-      template_mixed(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq);
-      float a = wr[j], b = wi[j];
+      template_mixed(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq, code);
+      float a = wr[co + j], b = wi[co + j];
       float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
       kahan_addf(acc[0], cmp[0], Wr * tpr + Wi * tpi);
       kahan_addf(acc[1], cmp[1], Wi * tpr - Wr * tpi);
       kahan_addf(acc[2], cmp[2], Wr * txr + Wi * txi);
       kahan_addf(acc[3], cmp[3], Wi * txr - Wr * txi);
-      double uu = (double)u[j];
+      double uu = (double)u[co + j];
       double pr = tpr, pi = tpi, xr = txr, xi = txi;
       m4[0] += uu * (pr * pr + pi * pi);
       m4[1] += uu * (xr * xr + xi * xi);
@@ -796,7 +889,7 @@ constexpr double kInterpTolTMixed = 3e-8;
 // Node values, coefficients and end-point check of every work item (all
 // lanes active: lanes 60..63 repeat the last point of the last item).
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
+__global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
                                                       const PartConst* __restrict__ pc,
                                                       const int32_t* __restrict__ bounds,
                                                       int32_t stride,
@@ -825,8 +918,10 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
     const int p = it.x / stride, l = it.x - p * stride;
     const PartConst& P = pc[p];
     const int32_t* bp = bounds + (int64_t)p * (stride + 1);
+    int ct, ch;
+    item_split(it.y, g.chan.n, ct, ch);
     int b0, b1;
-    item_bins(bp[l], bp[l + 1], it.y, T, b0, b1);
+    item_bins(bp[l], bp[l + 1], ct, T, b0, b1);
     const int nb = b1 - b0;
     const double* ekq = (ek && P.sur) ? ek + 8 * (int64_t)it.x : nullptr;
     const double sk = k < kCheb ? c_cheb_s[k] : (k == kCheb ? -1.0 : 1.0);
@@ -834,7 +929,7 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
     // exact frequency (k_lo + b0 + mk) df of the node, as double-double
     const dd f = dd_add(two_prod((double)(g.k_lo + b0), g.df), two_prod(mk, g.df));
     double v[5], v0lo;
-    const dd ph = template_node(P, f, ekq, v[1], v[2], v[3], v[4]);
+    const dd ph = template_node(P, f, ekq, v[1], v[2], v[3], v[4], g.chan.code[ch]);
     const double p0h = __shfl(ph.hi, base + kCheb, 64);
     const double p0l = __shfl(ph.lo, base + kCheb, 64);
     const double peh = __shfl(ph.hi, base + kCheb + 1, 64);
@@ -853,14 +948,17 @@ __global__ __launch_bounds__(256) void k_interp_nodes(Grid g,
     bool ufit = um.coef != nullptr && nb >= kMinInterp && nb <= kSsumMax;
     double gq[4], wq = 0.0, ures = 0.0;
     {
+      // the channel's u-tiles follow those of the channels before it
+      const int ub = ch * um.ntiles;
       const int ut0 = b0 / kUTile, ut1 = (b1 - 1) / kUTile;
-      ufit = ufit && ut1 < um.ntiles && (um.bad_prefix[ut1 + 1] - um.bad_prefix[ut0]) == 0;
+      ufit = ufit && ut1 < um.ntiles &&
+             (um.bad_prefix[ub + ut1 + 1] - um.bad_prefix[ub + ut0]) == 0;
       if (ufit)   // largest fit residual over the item's u-tiles (12 lanes share the scan)
-        for (int ut = ut0 + k; ut <= ut1; ut += kLanesItem) ures = fmax(ures, um.resid[ut]);
+        for (int ut = ut0 + k; ut <= ut1; ut += kLanesItem) ures = fmax(ures, um.resid[ub + ut]);
       const double x = (double)b0 + mk;
       const int ut = min(max((int)(x * (1.0 / kUTile)), 0), max(um.ntiles - 1, 0));
       const double loc = 2.0 * (x - (double)ut * kUTile) / (double)(kUTile - 1) - 1.0;
-      const double uu = um.coef ? cheb_eval10(um.coef + (int64_t)ut * kUCoef, loc) : 0.0;
+      const double uu = um.coef ? cheb_eval10(um.coef + (int64_t)(ub + ut) * kUCoef, loc) : 0.0;
       gq[0] = uu * fma(v[1], v[1], v[2] * v[2]);
       gq[1] = uu * fma(v[3], v[3], v[4] * v[4]);
       gq[2] = uu * fma(v[1], v[3], v[2] * v[4]);
@@ -1074,14 +1172,18 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
       s_unit[0] = t; s_unit[1] = first; s_unit[2] = count;
     }
     __syncthreads();
-    const int t = s_unit[0];
-    if (t < 0) break;
+    const int tx = s_unit[0];
+    if (tx < 0) break;
+    // tiles of all channels are numbered channel by channel
+    const int ntpc = (int)((g.nbins + T - 1) / T);
+    const int tch = tx / ntpc, t = tx - tch * ntpc;
+    const int64_t co = (int64_t)tch * g.nbins;
     const int j0 = t * T;
     const int nt = min((int64_t)T, g.nbins - j0);
     for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-      s_wr[i] = gwr[j0 + i];
-      s_wi[i] = gwi[j0 + i];
-      s_u[i] = gu[j0 + i];
+      s_wr[i] = gwr[co + j0 + i];
+      s_wi[i] = gwi[co + j0 + i];
+      s_u[i] = gu[co + j0 + i];
     }
     __syncthreads();
     const int i0 = s_unit[1];
@@ -1092,8 +1194,10 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
       const int2 it = items[w];
       const int p = it.x / stride, l = it.x - p * stride;
       const int32_t* bp = bounds + (int64_t)p * (stride + 1);
+      int ct, ich;
+      item_split(it.y, g.chan.n, ct, ich);
       int b0, b1;
-      item_bins(bp[l], bp[l + 1], it.y, T, b0, b1);
+      item_bins(bp[l], bp[l + 1], ct, T, b0, b1);
       const int nb = b1 - b0;
       typedef RecLayout<MIXED> L;
       // the record through the wave's LDS slot: one write, then broadcast reads
@@ -1325,7 +1429,7 @@ __global__ __launch_bounds__(256) void k_tile_count(const int2* __restrict__ ite
                                                     const int32_t* __restrict__ total,
                                                     const int32_t* __restrict__ bounds,
                                                     int32_t stride, int32_t T, int32_t ntiles,
-                                                    int32_t* __restrict__ tcnt) {
+                                                    int32_t nch, int32_t* __restrict__ tcnt) {
   __shared__ int32_t h[kTileHist];
   const bool local = ntiles <= kTileHist;
   const int W = total[0];
@@ -1336,7 +1440,7 @@ __global__ __launch_bounds__(256) void k_tile_count(const int2* __restrict__ ite
   for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
     const int2 it = items[w];
     const int p = it.x / stride, l = it.x - p * stride;
-    const int t = item_tile(bounds[(int64_t)p * (stride + 1) + l], it.y, T);
+    const int t = item_xtile(bounds[(int64_t)p * (stride + 1) + l], it.y, T, nch, ntiles);
     if (local) atomicAdd(&h[t], 1);
     else atomicAdd(&tcnt[t], 1);
   }
@@ -1391,6 +1495,7 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const int2* __restrict__ i
                                                       const int32_t* __restrict__ total,
                                                       const int32_t* __restrict__ bounds,
                                                       int32_t stride, int32_t T, int32_t ntiles,
+                                                      int32_t nch,
                                                       const int32_t* __restrict__ off,
                                                       int32_t* __restrict__ tcur,
                                                       int32_t* __restrict__ tile_items) {
@@ -1401,7 +1506,7 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const int2* __restrict__ i
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
       const int2 it = items[w];
       const int p = it.x / stride, l = it.x - p * stride;
-      const int t = item_tile(bounds[(int64_t)p * (stride + 1) + l], it.y, T);
+      const int t = item_xtile(bounds[(int64_t)p * (stride + 1) + l], it.y, T, nch, ntiles);
       tile_items[off[t] + atomicAdd(&tcur[t], 1)] = w;
     }
     return;
@@ -1411,7 +1516,7 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const int2* __restrict__ i
   for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
     const int2 it = items[w];
     const int p = it.x / stride, l = it.x - p * stride;
-    atomicAdd(&h[item_tile(bounds[(int64_t)p * (stride + 1) + l], it.y, T)], 1);
+    atomicAdd(&h[item_xtile(bounds[(int64_t)p * (stride + 1) + l], it.y, T, nch, ntiles)], 1);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < ntiles; i += blockDim.x)    // counts -> reserved bases
@@ -1420,7 +1525,7 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const int2* __restrict__ i
   for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
     const int2 it = items[w];
     const int p = it.x / stride, l = it.x - p * stride;
-    const int t = item_tile(bounds[(int64_t)p * (stride + 1) + l], it.y, T);
+    const int t = item_xtile(bounds[(int64_t)p * (stride + 1) + l], it.y, T, nch, ntiles);
     tile_items[atomicAdd(&h[t], 1)] = w;
   }
 }
@@ -1788,7 +1893,7 @@ __global__ void k_waveform(Grid g, const PartConst* __restrict__ pc,
   double s0, c0;
   sincospi(kLs * f, &s0, &c0);
   double cph, sph, tpr, tpi, txr, txi;
-  template_fp64(P, f, s0, c0, cph, sph, tpr, tpi, txr, txi);
+  template_fp64(P, f, s0, c0, cph, sph, tpr, tpi, txr, txi, nullptr, g.chan.code[0]);
   // restore the constant phase the statistic drops
   double sc, cc;
   sincospi(2.0 * dropped_phase(P), &sc, &cc);
@@ -1880,7 +1985,7 @@ static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) 
 
 void launch_prep(const Grid& g, const double* data, const double* psd, BinData<double> b,
                  hipStream_t s) {
-  hipLaunchKernelGGL(k_prep, dim3(nblk(g.nbins, 256)), dim3(256), 0, s, g, data, psd, b.wr, b.wi,
+  hipLaunchKernelGGL(k_prep, dim3(nblk(g.nbins, 256), g.chan.n), dim3(256), 0, s, g, data, psd, b.wr, b.wi,
                      b.u, b.s0, b.c0);
 }
 
@@ -1890,7 +1995,7 @@ void launch_max(const double* u, int64_t n, double* out, hipStream_t s) {
 
 void launch_scale(const Grid& g, const double* umax, BinData<double> b, BinData<float> b32,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_scale, dim3(nblk(g.nbins, 256)), dim3(256), 0, s, g, umax, b.wr, b.wi, b.u,
+  hipLaunchKernelGGL(k_scale, dim3(nblk(g.nbins, 256), g.chan.n), dim3(256), 0, s, g, umax, b.wr, b.wi, b.u,
                      b.s0, b.c0, b32.wr, b32.wi, b32.u, b32.s0, b32.c0);
 }
 
@@ -1920,14 +2025,14 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
   const int32_t* nsel = nullptr;
   if (!interp) hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(64), 0, s, ws.total, ws.ndirect);
   if (interp) {
-    const int32_t ntiles = (int32_t)((g.nbins + chunk - 1) / chunk);
+    const int32_t ntiles = (int32_t)((g.nbins + chunk - 1) / chunk) * g.chan.n;   // all channels
     hipLaunchKernelGGL(k_tile_zero, dim3(nblk(ntiles, 256)), dim3(256), 0, s, ws.tcnt, ws.tcur,
                        ntiles, ws.tile_ctr);
     hipLaunchKernelGGL(k_tile_count, dim3(1024), dim3(256), 0, s, ws.items, ws.total, ws.bounds,
-                       stride, chunk, ntiles, ws.tcnt);
+                       stride, chunk, ntiles, g.chan.n, ws.tcnt);
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, ws.tcnt, ntiles, ws.toff, ws.uoff);
     hipLaunchKernelGGL(k_tile_scatter, dim3(1024), dim3(256), 0, s, ws.items, ws.total, ws.bounds,
-                       stride, chunk, ntiles, ws.toff, ws.tcur, ws.tile_items);
+                       stride, chunk, ntiles, g.chan.n, ws.toff, ws.tcur, ws.tile_items);
     if (mixed)
       hipLaunchKernelGGL(k_interp_nodes<true>, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds,
                          stride, ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.xerr,

@@ -38,7 +38,16 @@ EXPORTS = ("fstat_plan_create", "fstat_eval", "fstat_extrinsic", "fstat_waveform
 class fstat_data_desc(ctypes.Structure):
     _fields_ = [("T_obs", ctypes.c_double), ("df", ctypes.c_double),
                 ("k_lo", ctypes.c_int64), ("nbins", ctypes.c_int64),
-                ("data", ctypes.c_void_p), ("psd", ctypes.c_void_p)]
+                ("data", ctypes.c_void_p), ("psd", ctypes.c_void_p),
+                ("n_channels", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("channels", ctypes.c_void_p)]
+
+
+CHANNELS = {"X": 0, "Y": 1, "Z": 2, "A": 3, "E": 4, "T": 5}
+
+
+def channel_code(c) -> int:
+    return CHANNELS[c] if isinstance(c, str) else int(c)
 
 
 class fstat_opts(ctypes.Structure):
@@ -322,17 +331,26 @@ class Plan:
 
     def __init__(self, data, psd, T_obs: float, df: float, k_lo: int,
                  precision: int = 0, chunk: int = 0, profile: bool = False,
-                 refine_budget: float = 0.0):
+                 refine_budget: float = 0.0, channels=None):
+        """data, psd: [nbins] (one TDI-X channel) or, with `channels` (e.g.
+        "AET"), [len(channels), nbins]."""
         torch = _torch()
         dev = torch.device("cuda")
         d = torch.as_tensor(np.ascontiguousarray(data, dtype=np.complex128)
                             if isinstance(data, np.ndarray) else data)
         d = d.to(dev, torch.complex128).contiguous()
         p = torch.as_tensor(psd).to(dev, torch.float64).contiguous()
-        self.nbins = int(p.numel())
+        nch = 1 if channels is None else len(channels)
+        self.channels = None if channels is None else [channel_code(c) for c in channels]
+        if p.numel() % nch or d.numel() != p.numel():
+            raise ValueError("data and psd must be [channels, nbins]")
+        self.nbins = int(p.numel()) // nch
         self.T_obs, self.df, self.k_lo = float(T_obs), float(df), int(k_lo)
+        self._chan = (np.ascontiguousarray(self.channels, dtype=np.int32)
+                      if self.channels is not None else None)
         desc = fstat_data_desc(self.T_obs, self.df, self.k_lo, self.nbins,
-                               d.data_ptr(), p.data_ptr())
+                               d.data_ptr(), p.data_ptr(), nch if channels is not None else 0, 0,
+                               self._chan.ctypes.data if self._chan is not None else None)
         opts = fstat_opts(int(precision), FSTAT_DEVICE_PTRS | (FSTAT_PROFILE if profile else 0),
                           int(chunk), 0, float(refine_budget))
         self.handle = fstat_plan_create(desc, opts, _stream())
@@ -466,15 +484,15 @@ class Plan:
             pass
 
 
-def waveform(T_obs, df, k_lo, nbins, params6, amps4):
-    """sum_i a_i A^i on the grid, computed on the device; returns a torch
-    complex128 tensor on the device."""
+def waveform(T_obs, df, k_lo, nbins, params6, amps4, channel="X"):
+    """sum_i a_i A^i of a TDI channel on the grid, computed on the device;
+    returns a torch complex128 tensor on the device."""
     torch = _torch()
     p = torch.as_tensor(np.asarray(params6, dtype=np.float64)).cuda()
     a = torch.as_tensor(np.asarray(amps4, dtype=np.float64)).cuda()
     out = torch.empty(int(nbins), device="cuda", dtype=torch.complex128)
     fstat_waveform(T_obs, df, k_lo, nbins, p.data_ptr(), a.data_ptr(), out.data_ptr(),
-                   FSTAT_DEVICE_PTRS, _stream())
+                   FSTAT_DEVICE_PTRS | (channel_code(channel) << 8), _stream())
     return out
 
 

@@ -43,7 +43,7 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
 
 def test_struct_layouts_match_header():
     from paper_2407_10797_amd import fstat
-    assert ctypes.sizeof(fstat.fstat_data_desc) == 48
+    assert ctypes.sizeof(fstat.fstat_data_desc) == 64
     assert ctypes.sizeof(fstat.fstat_opts) == 24
     assert ctypes.sizeof(fstat.pso_stage_desc) == 88
     assert ctypes.sizeof(fstat.pso_result) == 32

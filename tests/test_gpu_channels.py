@@ -1,0 +1,128 @@
+"""Several TDI channels on the GPU against the oracle: the channel waveforms,
+and the statistic with N and M summed over channels with independent noise
+(A, E, T) or over the Michelson channels (X, Y, Z).  Bars as in
+test_gpu_parity: FP64 1e-9 (+1e-14 cond) relative per partition, mixed 1e-4
+(+1e-6 cond)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2407_10797_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def _data(g, inj, channels, snr=12.0, seed=7001):
+    """Noise in every channel (independent, each with its own spectrum) plus
+    one injection scaled to a combined SNR."""
+    a = S.random_amplitudes(S.SMALL_SEEDS["inj"])
+    sig = np.array([O.signal(inj, a, g.df, g.k_lo, g.nbins, g.T_obs, channel=c) for c in channels])
+    psd = np.array([S.psd_channel(g.freqs(), c) for c in channels])
+    rho2 = sum(4 * g.df * np.sum(np.abs(sig[i]) ** 2 / psd[i]) for i in range(len(channels)))
+    data = np.array([S.noise(psd[i], g.df, seed + i) for i in range(len(channels))])
+    return data + sig * (snr / np.sqrt(rho2)), psd
+
+
+@pytest.fixture(scope="module")
+def aet(torch_cuda):
+    from paper_2407_10797_amd import fstat
+    g = S.grid_small()
+    inj = S.small_injection_params()
+    data, psd = _data(g, inj, "AET")
+    pts = np.vstack([inj[None, :], S.small_eval_points(inj, n=63)])
+    plan = fstat.Plan(data, psd, g.T_obs, g.df, g.k_lo, channels="AET")
+    yield dict(g=g, inj=inj, data=data, psd=psd, pts=pts, plan=plan)
+    plan.close()
+
+
+def _check(Fg, Fo, cond, rel, kc):
+    c = np.where(np.isfinite(cond), cond, 0.0)
+    r = np.abs(Fg - Fo) / np.maximum(np.abs(Fo), 1.0)
+    tol = rel + kc * c
+    ok = np.isfinite(Fo)
+    assert np.all(r[ok] <= tol[ok]), float((r[ok] / tol[ok]).max())
+    return float((r[ok] / tol[ok]).max())
+
+
+@pytest.mark.parametrize("channel", list("XYZAET"))
+def test_channel_waveforms_match_oracle(torch_cuda, channel):
+    from paper_2407_10797_amd import fstat
+    g = S.grid_small()
+    inj = S.small_injection_params()
+    a = np.array([0.3, -1.2, 0.7, 0.05])
+    ho = O.signal(inj, a, g.df, g.k_lo, g.nbins, g.T_obs, channel=channel)
+    hg = fstat.waveform(g.T_obs, g.df, g.k_lo, g.nbins, inj, a, channel=channel).cpu().numpy()
+    assert np.max(np.abs(hg - ho)) <= 1e-9 * np.max(np.abs(ho))
+
+
+@pytest.mark.parametrize("npart", [1, 4, 16])
+@pytest.mark.parametrize("mode", ["fp64", "mixed", "exact"])
+def test_aet_statistic_matches_oracle(aet, torch_cuda, npart, mode):
+    s = aet
+    g = s["g"]
+    F, P = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, mixed=mode == "mixed",
+                          exact=mode == "exact", want_parts=True)
+    Fo, Po, cond = O.fstat(s["data"], s["psd"], g.k_lo, g.df, g.T_obs, s["pts"], [npart],
+                           want_cond=True, channels="AET")
+    rel, kc = (1e-4, 1e-6) if mode == "mixed" else (1e-9, 1e-14)
+    worst = _check(P.cpu().numpy(), Po, cond, rel, kc)
+    cmax = np.where(np.isfinite(cond), cond, 0.0)[:, :npart].max(axis=1)
+    _check(F.cpu().numpy(), Fo, cmax, rel, kc)
+    print(f"[channels] AET {mode} Np={npart}: worst error / tolerance {worst:.3f}", flush=True)
+
+
+def test_aet_amplitudes_match_oracle(aet, torch_cuda):
+    s = aet
+    g = s["g"]
+    _, _, Ag = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), 1, want_parts=True, want_amps=True)
+    _, _, cond, Ao = O.fstat(s["data"], s["psd"], g.k_lo, g.df, g.T_obs, s["pts"], [1],
+                             want_cond=True, want_amps=True, channels="AET")
+    Ag = Ag.cpu().numpy()
+    err = np.linalg.norm(Ag - Ao, axis=-1)
+    tol = (1e-9 + 1e-12 * np.where(np.isfinite(cond), cond, 0.0)) * np.linalg.norm(Ao, axis=-1)
+    assert np.all(err <= tol + 1e-300)
+
+
+def test_michelson_channels_and_single_x(torch_cuda):
+    """X, Y, Z in one plan against the oracle; a plan with the channel list
+    ["X"] gives the default single-channel plan's values bit for bit."""
+    from paper_2407_10797_amd import fstat
+    g = S.grid_small()
+    inj = S.small_injection_params()
+    data, psd = _data(g, inj, "XYZ", seed=7101)
+    pts = np.vstack([inj[None, :], S.small_eval_points(inj, n=31)])
+    plan = fstat.Plan(data, psd, g.T_obs, g.df, g.k_lo, channels="XYZ")
+    try:
+        F, P = plan.eval(torch_cuda.from_numpy(pts), 4, want_parts=True)
+        Fo, Po, cond = O.fstat(data, psd, g.k_lo, g.df, g.T_obs, pts, [4], want_cond=True,
+                               channels="XYZ")
+        _check(P.cpu().numpy(), Po, cond, 1e-9, 1e-14)
+    finally:
+        plan.close()
+    p1 = fstat.Plan(data[0], psd[0], g.T_obs, g.df, g.k_lo)
+    p2 = fstat.Plan(data[:1], psd[:1], g.T_obs, g.df, g.k_lo, channels="X")
+    try:
+        a = p1.eval(torch_cuda.from_numpy(pts), 4).cpu().numpy()
+        b = p2.eval(torch_cuda.from_numpy(pts), 4).cpu().numpy()
+        np.testing.assert_array_equal(a, b)
+    finally:
+        p1.close()
+        p2.close()
+
+
+def test_channel_list_errors(torch_cuda):
+    from paper_2407_10797_amd import fstat
+    g = S.grid_small()
+    d = np.zeros((2, g.nbins), dtype=np.complex128)
+    p = np.ones((2, g.nbins))
+    for bad in (["A", "A"], [3, 9]):
+        with pytest.raises(fstat.FstatError):
+            fstat.Plan(d, p, g.T_obs, g.df, g.k_lo, channels=bad)
