@@ -176,6 +176,39 @@ def search_bench(iters, ckpt, last_stage=3, resume=False):
     return out
 
 
+def aet_bench(pts, npart, steps, warmup, autotune=True):
+    """The same batch on three channels with independent noise (A, E, T),
+    N and M summed over them: FP64 path."""
+    import torch
+    from paper_2407_10797_amd import fstat, synth as S
+    g = S.grid_paper()
+    inj, snr = S.paper_injection_params()
+    amps = S.random_amplitudes(S.PAPER_SEEDS["inj"])
+    f = g.freqs()
+    psd = np.array([S.psd_channel(f, c) for c in "AET"])
+    sig = np.array([fstat.waveform(g.T_obs, g.df, g.k_lo, g.nbins, inj, amps, channel=c).cpu().numpy()
+                    for c in "AET"])
+    rho2 = sum(4 * g.df * np.sum(np.abs(sig[i]) ** 2 / psd[i]) for i in range(3))
+    data = np.array([S.noise(psd[i], g.df, S.PAPER_SEEDS["noise"] + 100 * (i + 1)) for i in range(3)])
+    data += sig * (snr / np.sqrt(rho2))
+    plan = fstat.Plan(data, psd, g.T_obs, g.df, g.k_lo, profile=True, channels="AET")
+    del data, sig
+    prm = torch.from_numpy(pts).cuda()
+    extra = {}
+    if autotune:
+        c, m, _ = plan.autotune(prm, npart)
+        extra.update(tuned_chunk=c, tuned_grid_mult=m)
+    r = time_path(plan, prm, npart, steps, warmup, False)
+    items, rejected, refined = plan.interp_stats()
+    plan.close()
+    tps = len(pts) * steps / r["seconds"]
+    return dict(templates_per_s=tps, ms_per_step=1e3 * r["seconds"] / steps,
+                stage_ms=r["kernel_ms"], main_kernel_ms=r["main_ms"],
+                channel_bin_templates_per_s=3 * r["bins_per_launch"] / (r["kernel_ms"] * 1e-3),
+                work_items=items, exact_items=rejected, refined_items=refined,
+                config="A, E, T with independent noise, same particles, Np and bins as fp64", **extra)
+
+
 def cpu_baseline(g, data, psd, pts, npart, sample):
     from oracle import oracle as O
     sub = pts[:sample]
@@ -198,7 +231,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "mixed", "mixed+surrogate", "pso", "search"], default=None,
+    ap.add_argument("--no-aet", action="store_true", help="skip the three-channel measurement")
+    ap.add_argument("--only", choices=["fp64", "mixed", "mixed+surrogate", "pso", "search", "aet"],
+                    default=None,
                     help="one paper-scale variant, or only the batched PSO measurement, or only "
                          "the three-stage search")
     ap.add_argument("--search-iters", default="400,400,800",
@@ -293,6 +328,16 @@ def main():
                                             traffic=traffic), **extra)
         _log(f"{name}: {tps:.1f} templates/s, bin-loop stage {r['kernel_ms']:.2f} ms, main kernel "
              f"{r['main_ms']:.2f} ms, {r['bins_per_launch']:.3e} bin-templates/launch")
+    plan.close()
+    if not args.no_aet and args.only in (None, "aet"):
+        try:
+            variants["aet-fp64"] = aet_bench(pts, args.np, args.steps, args.warmup,
+                                             not args.no_autotune)
+            v = variants["aet-fp64"]
+            _log(f"aet-fp64: {v['templates_per_s']:.1f} templates/s (3 channels), bin-loop stage "
+                 f"{v['stage_ms']:.2f} ms, main kernel {v['main_kernel_ms']:.2f} ms")
+        except fstat.FstatError as e:
+            _log(f"aet-fp64: {e}")
     head = variants.get("fp64") or next(iter(variants.values()))
     out = {
         "metric": "F-stat templates/s at 7.1M bins, Np=64; %roofline; plain vs mixed+surrogate",
@@ -313,7 +358,6 @@ def main():
         "roofline": head["roofline"],
         "variants": variants,
     }
-    plan.close()
     if args.pso_iters > 0:
         _log("batched PSO stage")
         out["pso"] = pso_bench(args.pso_iters)
