@@ -263,6 +263,78 @@ static void rigid_positions(double t, double pos[3][3]) {
   }
 }
 
+/* Numerical orbit (Sec. IV allows one, interpolated with Chebyshev
+ * polynomials): n_seg segments of length dt from t0, each given by the
+ * spacecraft positions [3][3] at the 10 Chebyshev points
+ * t = t0 + dt (seg + (1 + s_k)/2), s_k = cos(pi (k + 1/2) / 10); positions
+ * between them are the degree-9 interpolant, evaluated here in barycentric
+ * Lagrange form in long double.  With no table the rigid analytic
+ * constellation above is used.                                              */
+static struct {
+  int nseg;
+  double t0, dt;
+  double *nodes;   /* [nseg][3][3][10] */
+} g_orb = {0, 0.0, 0.0, NULL};
+
+int or_set_orbit(double t0, double dt, int nseg, const double *nodes) {
+  free(g_orb.nodes);
+  g_orb.nodes = NULL;
+  g_orb.nseg = 0;
+  if (nseg <= 0) return 0;
+  if (!(dt > 0.0) || !nodes) return -1;
+  g_orb.nodes = malloc(sizeof(double) * 90 * (size_t)nseg);
+  if (!g_orb.nodes) return -1;
+  memcpy(g_orb.nodes, nodes, sizeof(double) * 90 * (size_t)nseg);
+  g_orb.nseg = nseg;
+  g_orb.t0 = t0;
+  g_orb.dt = dt;
+  return 0;
+}
+
+static void table_positions(double t, double pos[3][3]) {
+  int seg = (int)floor((t - g_orb.t0) / g_orb.dt);
+  if (seg < 0) seg = 0;
+  if (seg > g_orb.nseg - 1) seg = g_orb.nseg - 1;
+  const long double x = 2.0L * ((long double)t - g_orb.t0 - (long double)g_orb.dt * seg) / g_orb.dt - 1.0L;
+  long double w[10], sk[10], den = 0.0L;
+  int hit = -1;
+  for (int k = 0; k < 10; ++k) {
+    const long double th = (long double)OR_PI * (k + 0.5L) / 10.0L;
+    sk[k] = cosl(th);
+    /* barycentric weights of the first-kind Chebyshev points */
+    w[k] = ((k & 1) ? -1.0L : 1.0L) * sinl(th);
+    if (x == sk[k]) hit = k;
+  }
+  const double *nd = g_orb.nodes + 90 * (size_t)seg;
+  for (int i = 0; i < 3; ++i)
+    for (int c = 0; c < 3; ++c) {
+      const double *v = nd + 30 * i + 10 * c;
+      if (hit >= 0) { pos[i][c] = v[hit]; continue; }
+      long double num = 0.0L;
+      den = 0.0L;
+      for (int k = 0; k < 10; ++k) {
+        const long double q = w[k] / (x - sk[k]);
+        num += q * v[k];
+        den += q;
+      }
+      pos[i][c] = (double)(num / den);
+    }
+}
+
+static void positions(double t, double pos[3][3]) {
+  if (g_orb.nseg > 0) table_positions(t, pos);
+  else rigid_positions(t, pos);
+}
+
+/* Spacecraft positions used by the response (the table when one is set). */
+void or_positions(const double *t, int64_t n, double *out) {
+  for (int64_t i = 0; i < n; ++i) {
+    double pos[3][3];
+    positions(t[i], pos);
+    memcpy(out + 9 * i, pos, sizeof(pos));
+  }
+}
+
 /* First-generation Michelson combination at spacecraft a (index a) with equal
  * static delays L (reading of the TDI-X combination the paper cites); with
  * b = a + 1, c = a + 2 (mod 3):
@@ -272,7 +344,7 @@ static void rigid_positions(double t, double pos[3][3]) {
 static void michelson(const or_intr *p, double f, double t, int a, double complex T[2]) {
   const double L = OR_ARM_M / OR_C;
   double pos[3][3], k[3], u[3], v[3];
-  rigid_positions(t, pos);
+  positions(t, pos);
   sky_frame(p->theta, p->phi, k, u, v);
   const int b = (a + 1) % 3, c = (a + 2) % 3;
   double complex yacp, yacx, ycap, ycax, yabp, yabx, ybap, ybax;

@@ -50,6 +50,8 @@ def lib():
         L.or_link.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, _dp]
         L.or_response_ch.argtypes = [_dp, _dp, _dp, ctypes.c_int64, ctypes.c_int, _dp]
+        L.or_set_orbit.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp]
+        L.or_positions.argtypes = [_dp, ctypes.c_int64, _dp]
         L.or_basis.argtypes = [_dp, _dp, ctypes.c_int64, ctypes.c_int, _dp]
         L.or_support.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
         L.or_signal.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
@@ -96,6 +98,32 @@ def orbit(t, rigid=False):
     t, tp = _d(np.atleast_1d(t))
     out = np.empty((t.size, 3, 3))
     lib().or_orbit(tp, t.size, int(bool(rigid)), out.ctypes.data_as(_dp))
+    return out
+
+
+def set_orbit(t0=0.0, dt=1.0, nodes=None):
+    """Use a numerical orbit: nodes [n_seg, 3, 3, 10] positions [s] at the
+    Chebyshev points of each segment of length dt from t0 (see the C
+    source); nodes=None goes back to the analytic constellation."""
+    if nodes is None:
+        lib().or_set_orbit(0.0, 1.0, 0, None)
+        return
+    nd, npp = _d(nodes)
+    if lib().or_set_orbit(float(t0), float(dt), nd.shape[0], npp):
+        raise ValueError("bad orbit table")
+
+
+def chebyshev_times(t0, dt, n_seg):
+    """Times [n_seg, 10] of an orbit table's nodes."""
+    s = np.cos(np.pi * (np.arange(10) + 0.5) / 10)
+    return t0 + dt * (np.arange(n_seg)[:, None] + 0.5 * (1.0 + s[None, :]))
+
+
+def positions(t):
+    """Spacecraft positions [n, 3, 3] the response uses (the table if set)."""
+    t, tp = _d(np.atleast_1d(t))
+    out = np.empty((t.size, 3, 3))
+    lib().or_positions(tp, t.size, out.ctypes.data_as(_dp))
     return out
 
 

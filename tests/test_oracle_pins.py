@@ -566,3 +566,63 @@ def test_two_F_equals_rho2_several_channels(channels):
     if channels == "X":
         F1, P1 = O.fstat(s[0], psd[0], g.k_lo, g.df, g.T_obs, inj, [4])
         np.testing.assert_array_equal(Fp, P1)
+
+
+# ---- numerical orbit table (Sec. IV: Chebyshev interpolation) -------------------
+
+def _orbit_table(t0, dt, nseg, bump=0.0):
+    """Rigid analytic constellation sampled at the table's Chebyshev points,
+    optionally with the arms breathing by `bump` seconds (a test orbit)."""
+    ts = O.chebyshev_times(t0, dt, nseg)
+    O.set_orbit(None)
+    pos = O.orbit(ts.ravel(), rigid=True).reshape(nseg, 10, 3, 3)
+    if bump:
+        for i in (1, 2):
+            d = pos[:, :, i, :] - pos[:, :, 0, :]
+            pos[:, :, i, :] += bump * np.sin(2 * np.pi * ts / 5e5)[:, :, None] * d / np.linalg.norm(d, axis=-1, keepdims=True)
+    return np.ascontiguousarray(pos.transpose(0, 2, 3, 1))   # [seg][sc][xyz][node]
+
+
+def test_orbit_table_interpolates_exactly_and_reproduces_the_analytic_orbit():
+    """Degree-9 interpolation through the Chebyshev points: the node values come
+    back (to rounding of the node times), a cubic in t is reproduced, and a table sampled
+    from the analytic constellation (1.5-day segments) reproduces it to 1e-9 s."""
+    t0, dt, nseg = -86400.0, 131072.0, 10
+    try:
+        nodes = _orbit_table(t0, dt, nseg)
+        O.set_orbit(t0, dt, nodes)
+        ts = O.chebyshev_times(t0, dt, nseg)
+        got = O.positions(ts[3])
+        np.testing.assert_allclose(got.transpose(1, 2, 0), nodes[3], rtol=2e-16, atol=0)
+        tr = np.random.default_rng(1).uniform(0.0, 1.2e6, 200)
+        O.set_orbit(None)
+        ref = O.orbit(tr, rigid=True)
+        O.set_orbit(t0, dt, nodes)
+        assert np.max(np.abs(O.positions(tr) - ref)) < 1e-9
+        cubic = lambda t: 3.0 + 2e-6 * t - 1e-12 * t ** 2 + 4e-19 * t ** 3
+        cub = np.broadcast_to(cubic(ts)[:, None, None, :], (nseg, 3, 3, 10)).copy()
+        O.set_orbit(t0, dt, cub)
+        np.testing.assert_allclose(O.positions(tr)[:, 1, 2], cubic(tr), rtol=1e-14)
+    finally:
+        O.set_orbit(None)
+
+
+def test_statistic_on_a_tabulated_orbit():
+    """F on a table sampled from the analytic constellation equals F on the
+    analytic constellation (to the table's interpolation error); a table whose
+    arms breathe by 1e-3 s changes F, so the table is what the response uses."""
+    g, inj = _small_case()
+    psd = S.psd_tdix(g.freqs())
+    d = S.noise(psd, g.df, 9) + O.signal(inj, [0.3, -1.0, 0.5, 0.2], g.df, g.k_lo, g.nbins, g.T_obs)
+    pts = np.vstack([inj[None, :], S.small_eval_points(inj, 7)])
+    F0, _ = O.fstat(d, psd, g.k_lo, g.df, g.T_obs, pts, [4])
+    t0, dt, nseg = -86400.0, 131072.0, 10
+    try:
+        O.set_orbit(t0, dt, _orbit_table(t0, dt, nseg))
+        F1, _ = O.fstat(d, psd, g.k_lo, g.df, g.T_obs, pts, [4])
+        O.set_orbit(t0, dt, _orbit_table(t0, dt, nseg, bump=1e-3))
+        F2, _ = O.fstat(d, psd, g.k_lo, g.df, g.T_obs, pts, [4])
+    finally:
+        O.set_orbit(None)
+    np.testing.assert_allclose(F1, F0, rtol=1e-9)
+    assert np.max(np.abs(F2 - F0) / np.abs(F0)) > 1e-6
