@@ -140,6 +140,21 @@ int fstat_eval(fstat_plan_t plan, const double *params, int64_t n, const int32_t
                int32_t np_uniform, double *F_hat, double *F_part, double *amps,
                int64_t part_stride, uint32_t flags, void *hip_stream);
 
+/* Numerical spacecraft orbit for the plan's templates (Sec. IV: a numerical
+ * orbit interpolated with Chebyshev polynomials instead of the analytic one).
+ *   nodes  [n_seg][3][3][10]: positions of spacecraft 1..3 (x, y, z in
+ *          seconds of light travel, the frame of the analytic orbit) at the
+ *          Chebyshev points t = t0 + dt (seg + (1 + s_k)/2),
+ *          s_k = cos(pi (k + 1/2) / 10), of each segment of length dt
+ * Positions between the points are the degree-9 interpolant of the segment
+ * that holds t.  The table must cover [0, T_obs].  The plan converts it to
+ * Chebyshev coefficients and keeps its own copy; later fstat_eval,
+ * pso_stage and fstat_search calls use it.  n_seg = 0 returns to the analytic
+ * orbit.  Flags: FSTAT_DEVICE_PTRS (nodes on the device).  Waits for
+ * completion.  EINVAL: coverage, dt <= 0, non-finite values.               */
+int fstat_plan_set_orbit(fstat_plan_t plan, double t0, double dt, int32_t n_seg,
+                         const double *nodes, uint32_t flags, void *hip_stream);
+
 /* Extrinsic parameters from the amplitudes (App. B, Eq. extrinPara).
  *   amps    [n][4] a_1..a_4 as fstat_eval writes them
  *   params  [n][6] theta6 of the same rows, or NULL

@@ -427,7 +427,7 @@ void fstat_plan_destroy(fstat_plan_t P) {
   dev_free(P->ws.tile_ctr); dev_free(P->ws.xflag); dev_free(P->ws.rec); dev_free(P->ws.xerr); dev_free(P->ws.refine); dev_free(P->ws.nrefine);
   dev_free(P->io.params); dev_free(P->io.np); dev_free(P->io.F_hat); dev_free(P->io.F_part);
   dev_free(P->io.amps); dev_free(P->umax); dev_free(P->ucoef); dev_free(P->ubad);
-  dev_free(P->ures);
+  dev_free(P->ures); dev_free(P->orb_coef);
   pso_release(P);
   sur_release(P);
   for (auto& e : P->events)
@@ -601,6 +601,58 @@ int fstat_waveform(double T_obs, double df, int64_t k_lo, int64_t nbins, const d
   dev_free(ws.pc); dev_free(ws.bounds); dev_free(ws.cnt);
   dev_free(dpar); dev_free(damp); dev_free(dout);
   return rc;
+}
+
+int fstat_plan_set_orbit(fstat_plan_t P, double t0, double dt, int32_t n_seg, const double* nodes,
+                         uint32_t flags, void* hip_stream) {
+  g_err.clear();
+  if (!P) return set_error(FSTAT_EINVAL, "null plan");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (n_seg == 0) {   // back to the analytic orbit
+    int rc = hip_check(hipStreamSynchronize(s), "orbit");
+    dev_free(P->orb_coef);
+    P->orb_coef = nullptr;
+    P->grid.orb = OrbitTable{};
+    return rc;
+  }
+  if (n_seg < 0 || !nodes) return set_error(FSTAT_EINVAL, "n_seg < 0 or null nodes");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t0))
+    return set_error(FSTAT_EINVAL, "t0 must be finite and dt > 0");
+  if (t0 > 0.0 || t0 + dt * n_seg < P->grid.T_obs)
+    return set_error(FSTAT_EINVAL, "the table must cover [0, T_obs]");
+  const size_t nv = (size_t)n_seg * 90;
+  std::vector<double> v(nv), c(nv);
+  int rc = 0;
+  if (flags & FSTAT_DEVICE_PTRS) {
+    if ((rc = hip_check(hipMemcpyAsync(v.data(), nodes, sizeof(double) * nv, hipMemcpyDeviceToHost, s),
+                        "copy orbit")) ||
+        (rc = hip_check(hipStreamSynchronize(s), "copy orbit")))
+      return rc;
+  } else {
+    memcpy(v.data(), nodes, sizeof(double) * nv);
+  }
+  for (size_t i = 0; i < nv; ++i)
+    if (!std::isfinite(v[i])) return set_error(FSTAT_EINVAL, "orbit node %zu is not finite", i);
+  // node values at s_k = cos(pi (k + 1/2) / 10) -> Chebyshev coefficients
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (size_t sq = 0; sq < (size_t)n_seg * 9; ++sq)
+    for (int j = 0; j < 10; ++j) {
+      long double a = 0.0L;
+      for (int k = 0; k < 10; ++k) a += (long double)v[sq * 10 + k] * cosl(pi * j * (k + 0.5L) / 10.0L);
+      c[sq * 10 + j] = (double)(a * (j == 0 ? 1.0L : 2.0L) / 10.0L);
+    }
+  double* dc = nullptr;
+  if ((rc = dev_alloc(&dc, nv, "alloc orbit"))) return rc;
+  rc = hip_check(hipMemcpyAsync(dc, c.data(), sizeof(double) * nv, hipMemcpyHostToDevice, s), "copy orbit");
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "copy orbit");
+  if (rc) { dev_free(dc); return rc; }
+  dev_free(P->orb_coef);
+  P->orb_coef = dc;
+  P->grid.orb.coef = dc;
+  P->grid.orb.nseg = n_seg;
+  P->grid.orb.t0 = t0;
+  P->grid.orb.dt = dt;
+  return FSTAT_OK;
 }
 
 int fstat_extrinsic(const double* amps, const double* params, int64_t n, double* out,

@@ -33,6 +33,7 @@ struct fstat_plan_s {
   double* ucoef = nullptr;          // smooth model of u per u-tile (M-term quadrature)
   int32_t* ubad = nullptr;          // prefix count of u-tiles the model does not fit
   double* ures = nullptr;           // relative residual of the model per u-tile
+  double* orb_coef = nullptr;       // numerical orbit (fstat_plan_set_orbit)
   int32_t n_utiles = 0;
   int32_t n_ufit = 0;               // u-tiles fitted to within tolerance
   struct {

@@ -113,6 +113,16 @@ __host__ __device__ __forceinline__ double dd_frac(dd a) {
 // c5 = 3 cN c5' vfac^5 with alpha_5 = c5'(1 + 3 ln(v sqrt 6)); c6 = cN vfac^6;
 // alpha_6 = a6k + b6 ln v.  The terms that reach 10^2..10^7 cycles are
 // carried as double-double, so the fractional cycle is exact to ~1e-14.
+// Numerical orbit: nseg segments of length dt from t0, each a degree-9
+// Chebyshev series per spacecraft and coordinate (positions in seconds of
+// light travel), coef [nseg][3][3][10]; coef == nullptr: analytic orbit.
+struct OrbitTable {
+  const double* coef = nullptr;
+  int32_t nseg = 0;
+  double t0 = 0.0;
+  double dt = 1.0;
+};
+
 struct PartConst {
   double tc;
   double mc_hi, mc_lo;     // Mc [s]
@@ -392,25 +402,45 @@ __device__ __forceinline__ void orbit_offsets(T ca, T sa, T d[3][3]) {
   }
 }
 
-// TDI-X transfer (T''_+, T''_x) at f for the orbit angle (ca, sa) = (cos,
-// sin)(2 pi t_f / yr) and spacecraft offsets d; s0, c0 = sin, cos(pi f L).
-__device__ __forceinline__ void response_fp64(const PartConst& P, double f, double s0, double c0,
-                                              const double d[3][3], double& tpr, double& tpi,
-                                              double& txr, double& txi) {
+// Channel codes (Grid::chan): weights of M_0 = X, M_1 = Y, M_2 = Z in a channel
+__device__ __forceinline__ void channel_weights(int code, double w[3]) {
+  const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637,
+               r3 = 0.57735026918962576451;
+  w[0] = w[1] = w[2] = 0.0;
+  if (code <= 2) w[code] = 1.0;
+  else if (code == 3) { w[0] = -r2; w[2] = r2; }
+  else if (code == 4) { w[0] = r6; w[1] = -2.0 * r6; w[2] = r6; }
+  else { w[0] = w[1] = w[2] = r3; }
+}
+
+// TDI transfer (T''_+, T''_x) at f of the Michelson combination at spacecraft
+// a (a = 0: X) relative to the phase reference p_1: arms from p_a to p_{a+1},
+// p_{a+2}, and the factor exp(-2 pi i f k.(p_a - p_1)) of the vertex's offset.
+// d are the spacecraft offsets, s0, c0 = sin, cos(pi f L).  Delays and sinc
+// arguments take the nominal arm length L.  The link phase pi f k.(p_s + p_r)
+// takes L n for the arm vector on the analytic (rigid) constellation, the arm
+// vector itself when `table` (a numerical orbit, whose arms need not have
+// length L).
+__device__ __forceinline__ void michelson_fp64(const PartConst& P, double f, double s0, double c0,
+                                               const double d[3][3], int a, double& tpr,
+                                               double& tpi, double& txr, double& txi,
+                                               bool table = false) {
   const double kx = P.k[0], ky = P.k[1], kz = P.k[2];
   const double x0 = kPi * kLs * f;
   const double zr = c0 * c0 - s0 * s0, zi = -2.0 * s0 * c0;   // z = e^{-2 i x0}
   double out[2][4];
 #pragma unroll
   for (int arm = 0; arm < 2; ++arm) {
-    double ax = d[arm + 1][0] - d[0][0], ay = d[arm + 1][1] - d[0][1], az = d[arm + 1][2] - d[0][2];
-    double inv = rsq_nr(ax * ax + ay * ay + az * az);
+    const int w = (a + 1 + arm) % 3;
+    double ax = d[w][0] - d[a][0], ay = d[w][1] - d[a][1], az = d[w][2] - d[a][2];
+    const double r2 = ax * ax + ay * ay + az * az;
+    double inv = rsq_nr(r2);
     ax *= inv; ay *= inv; az *= inv;
     double kn = kx * ax + ky * ay + kz * az;
     double un = P.u[0] * ax + P.u[1] * ay + P.u[2] * az;
     double vn = P.v[0] * ax + P.v[1] * ay + P.v[2] * az;
     double sq, cq;
-    sincospi(kLs * f * kn, &sq, &cq);    // x0 kn
+    sincospi(kLs * f * kn, &sq, &cq);
     double np_ = s0 * cq + c0 * sq, nm = s0 * cq - c0 * sq;   // sin(x0 (1 +- kn))
     double dp = x0 * (1.0 + kn), dm = x0 * (1.0 - kn);
     double sp, sm;
@@ -423,62 +453,14 @@ __device__ __forceinline__ void response_fp64(const PartConst& P, double f, doub
       sm = sinc_from(nm, dm);
     }
     double Sr = sp + zr * sm, Si = zi * sm;
-    out[arm][0] = cq * Sr + sq * Si;      // e^{-i x0 kn} S
-    out[arm][1] = cq * Si - sq * Sr;
-    out[arm][2] = un * un - vn * vn;
-    out[arm][3] = 2.0 * un * vn;
-  }
-  tpr = out[1][2] * out[1][0] - out[0][2] * out[0][0];
-  tpi = out[1][2] * out[1][1] - out[0][2] * out[0][1];
-  txr = out[1][3] * out[1][0] - out[0][3] * out[0][0];
-  txi = out[1][3] * out[1][1] - out[0][3] * out[0][1];
-}
-
-// Channel codes (Grid::chan): weights of M_0 = X, M_1 = Y, M_2 = Z in a channel
-__device__ __forceinline__ void channel_weights(int code, double w[3]) {
-  const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637,
-               r3 = 0.57735026918962576451;
-  w[0] = w[1] = w[2] = 0.0;
-  if (code <= 2) w[code] = 1.0;
-  else if (code == 3) { w[0] = -r2; w[2] = r2; }
-  else if (code == 4) { w[0] = r6; w[1] = -2.0 * r6; w[2] = r6; }
-  else { w[0] = w[1] = w[2] = r3; }
-}
-
-// Michelson combination at spacecraft a (a = 0: the response_fp64 above),
-// relative to the phase reference p_1: arms from p_a to p_{a+1}, p_{a+2}, and
-// the factor exp(-2 pi i f k.(p_a - p_1)) of the vertex's offset.
-__device__ __forceinline__ void michelson_fp64(const PartConst& P, double f, double s0, double c0,
-                                               const double d[3][3], int a, double& tpr,
-                                               double& tpi, double& txr, double& txi) {
-  const double kx = P.k[0], ky = P.k[1], kz = P.k[2];
-  const double x0 = kPi * kLs * f;
-  const double zr = c0 * c0 - s0 * s0, zi = -2.0 * s0 * c0;   // z = e^{-2 i x0}
-  double out[2][4];
-#pragma unroll
-  for (int arm = 0; arm < 2; ++arm) {
-    const int w = (a + 1 + arm) % 3;
-    double ax = d[w][0] - d[a][0], ay = d[w][1] - d[a][1], az = d[w][2] - d[a][2];
-    double inv = rsq_nr(ax * ax + ay * ay + az * az);
-    ax *= inv; ay *= inv; az *= inv;
-    double kn = kx * ax + ky * ay + kz * az;
-    double un = P.u[0] * ax + P.u[1] * ay + P.u[2] * az;
-    double vn = P.v[0] * ax + P.v[1] * ay + P.v[2] * az;
-    double sq, cq;
-    sincospi(kLs * f * kn, &sq, &cq);
-    double np_ = s0 * cq + c0 * sq, nm = s0 * cq - c0 * sq;
-    double dp = x0 * (1.0 + kn), dm = x0 * (1.0 - kn);
-    double sp, sm;
-    if (fabs(dp) > 1e-6 && fabs(dm) > 1e-6) {
-      double r = rcp_nr(dp * dm);
-      sp = np_ * dm * r;
-      sm = nm * dp * r;
-    } else {
-      sp = sinc_from(np_, dp);
-      sm = sinc_from(nm, dm);
+    if (table) {   // link phase from the arm vector: rotate by exp(-i pi f kn (|d| - L))
+      double se, ce;
+      sincospi(f * kn * (r2 * inv - kLs), &se, &ce);
+      const double tr = sq * ce + cq * se, tc = cq * ce - sq * se;
+      sq = tr;
+      cq = tc;
     }
-    double Sr = sp + zr * sm, Si = zi * sm;
-    out[arm][0] = cq * Sr + sq * Si;
+    out[arm][0] = cq * Sr + sq * Si;      // e^{-i x0 kn} S
     out[arm][1] = cq * Si - sq * Sr;
     out[arm][2] = un * un - vn * vn;
     out[arm][3] = 2.0 * un * vn;
@@ -501,7 +483,8 @@ __device__ __forceinline__ void michelson_fp64(const PartConst& P, double f, dou
 // Transfer of channel `code` (relative to the phase reference p_1).
 __device__ __forceinline__ void response_ch_fp64(const PartConst& P, double f, double s0, double c0,
                                                  const double d[3][3], int code, double& tpr,
-                                                 double& tpi, double& txr, double& txi) {
+                                                 double& tpi, double& txr, double& txi,
+                                                 bool table = false) {
   double w[3];
   channel_weights(code, w);
   tpr = tpi = txr = txi = 0.0;
@@ -511,10 +494,44 @@ __device__ __forceinline__ void response_ch_fp64(const PartConst& P, double f, d
   for (int a = 0; a < 3; ++a) {
     if (w[a] == 0.0) continue;
     double pr, pi, xr, xi;
-    michelson_fp64(P, f, s0, c0, d, a, pr, pi, xr, xi);
+    michelson_fp64(P, f, s0, c0, d, a, pr, pi, xr, xi, table);
     tpr = fma(w[a], pr, tpr); tpi = fma(w[a], pi, tpi);
     txr = fma(w[a], xr, txr); txi = fma(w[a], xi, txi);
   }
+}
+
+// Spacecraft positions [s] at time t from an orbit table (Clenshaw on the
+// segment that holds t; the first or last segment outside the table).
+__device__ __forceinline__ void table_positions(const OrbitTable& o, double t, double p[3][3]) {
+  int seg = (int)floor((t - o.t0) / o.dt);
+  seg = min(max(seg, 0), o.nseg - 1);
+  const double x = 2.0 * ((t - o.t0) - o.dt * (double)seg) / o.dt - 1.0;
+  const double* c = o.coef + (int64_t)seg * 90;
+#pragma unroll 1
+  for (int q = 0; q < 9; ++q) {
+    const double* cq = c + 10 * q;
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int k = 9; k >= 1; --k) {
+      const double b0 = fma(2.0 * x, b1, cq[k] - b2);
+      b2 = b1;
+      b1 = b0;
+    }
+    p[q / 3][q % 3] = fma(x, b1, cq[0] - b2);
+  }
+}
+
+// k . p_1 from the table, with d[i] = p_i - p_1 (the response uses only
+// differences of the d and k . (d_a - d_0)).
+__device__ __forceinline__ double k_dot_p1_table(const PartConst& P, const OrbitTable& o, double t,
+                                                 double d[3][3]) {
+  double p[3][3];
+  table_positions(o, t, p);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d[i][c] = p[i][c] - p[0][c];
+  return P.k[0] * p[0][0] + P.k[1] * p[0][1] + P.k[2] * p[0][2];
 }
 
 // k . p_1 [s] of spacecraft 1 at orbit angle (ca, sa); fills the offsets d
@@ -527,17 +544,23 @@ __device__ __forceinline__ double k_dot_p1(const PartConst& P, double ca, double
 __device__ __forceinline__ void template_fp64(const PartConst& P, double f, double s0, double c0,
                                               double& cph, double& sph, double& tpr,
                                               double& tpi, double& txr, double& txi,
-                                              const double* ek = nullptr, int code = 0) {
+                                              const double* ek = nullptr, int code = 0,
+                                              const OrbitTable* orb = nullptr) {
   double fr, tf;
   phase_and_tf(P, f, fr, tf, ek);
-  double sa, ca;
-  sincospi(2.0 * tf * (1.0 / kYear), &sa, &ca);
   double d[3][3];
-  double kp1 = k_dot_p1(P, ca, sa, d);
+  double kp1;
+  if (orb && orb->coef) {
+    kp1 = k_dot_p1_table(P, *orb, tf, d);
+  } else {
+    double sa, ca;
+    sincospi(2.0 * tf * (1.0 / kYear), &sa, &ca);
+    kp1 = k_dot_p1(P, ca, sa, d);
+  }
   double ph = fr + f * kp1;               // Phi / (2 pi) in cycles
   ph -= rint(ph);
   sincospi(2.0 * ph, &sph, &cph);
-  response_ch_fp64(P, f, s0, c0, d, code, tpr, tpi, txr, txi);
+  response_ch_fp64(P, f, s0, c0, d, code, tpr, tpi, txr, txi, orb && orb->coef);
 }
 
 // The template at an arbitrary frequency fd (double-double; an interpolation
@@ -545,21 +568,26 @@ __device__ __forceinline__ void template_fp64(const PartConst& P, double f, doub
 // (double-double, not reduced) and the transfer without the Doppler factor.
 __device__ __forceinline__ dd template_node(const PartConst& P, dd fd, const double* ek,
                                             double& tpr, double& tpi, double& txr, double& txi,
-                                            int code = 0) {
+                                            int code = 0, const OrbitTable* orb = nullptr) {
   dd tf;
   dd ph = phase_full(P, fd, tf, ek);
   const double f = fd.hi;
-  double sa, ca;
-  {
-    FSTAT_NO_CONTRACT
-    const dd turns = dd_mul_d(tf, 1.0 / kYear);     // orbit angle in turns, reduced exactly
-    sincospi(2.0 * ((turns.hi - floor(turns.hi)) + turns.lo), &sa, &ca);
-  }
   double d[3][3];
-  double kp1 = k_dot_p1(P, ca, sa, d);
+  double kp1;
+  if (orb && orb->coef) {
+    kp1 = k_dot_p1_table(P, *orb, tf.hi + tf.lo, d);
+  } else {
+    double sa, ca;
+    {
+      FSTAT_NO_CONTRACT
+      const dd turns = dd_mul_d(tf, 1.0 / kYear);     // orbit angle in turns, reduced exactly
+      sincospi(2.0 * ((turns.hi - floor(turns.hi)) + turns.lo), &sa, &ca);
+    }
+    kp1 = k_dot_p1(P, ca, sa, d);
+  }
   double s0, c0;
   sincospi(kLs * f, &s0, &c0);
-  response_ch_fp64(P, f, s0, c0, d, code, tpr, tpi, txr, txi);
+  response_ch_fp64(P, f, s0, c0, d, code, tpr, tpi, txr, txi, orb && orb->coef);
   return dd_add(ph, dd_mul_d(fd, kp1));
 }
 

@@ -23,6 +23,7 @@ struct Grid {
   int64_t k_lo;
   int64_t nbins;       // bins per channel
   Channels chan{};     // per-channel arrays are stacked channel-major
+  OrbitTable orb{};    // spacecraft orbit (analytic unless a table is set)
 };
 
 // per-bin prepared data of one precision (structure of arrays)

@@ -425,7 +425,7 @@ __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
     for (int j = b0 + lane; j < b1; j += 64) {
       double f = bin_freq(g, j);
       double cps, sps, tpr, tpi, txr, txi;
-      template_fp64(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq, code);
+      template_fp64(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq, code, &g.orb);
       double a = wr[co + j], b = wi[co + j], uu = u[co + j];
       double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
       double t[8];
@@ -482,7 +482,7 @@ __device__ __forceinline__ void kahan_addf(float& s, float& c, float x) {
 __device__ __forceinline__ void michelson_f32(const float k[3], const float u[3], const float v[3],
                                               const float d[3][3], float fl, float s0, float c0,
                                               int a, float& tpr, float& tpi, float& txr,
-                                              float& txi) {
+                                              float& txi, bool table = false) {
   const float x0 = (float)(kPi * kLs) * fl;
   const float zr = c0 * c0 - s0 * s0, zi = -2.0f * s0 * c0;
   float out[2][4];
@@ -490,7 +490,8 @@ __device__ __forceinline__ void michelson_f32(const float k[3], const float u[3]
   for (int arm = 0; arm < 2; ++arm) {
     const int w = (a + 1 + arm) % 3;
     float ax = d[w][0] - d[a][0], ay = d[w][1] - d[a][1], az = d[w][2] - d[a][2];
-    float inv = __builtin_amdgcn_rsqf(ax * ax + ay * ay + az * az);
+    const float r2 = ax * ax + ay * ay + az * az;
+    float inv = __builtin_amdgcn_rsqf(r2);
     ax *= inv; ay *= inv; az *= inv;
     float kn = k[0] * ax + k[1] * ay + k[2] * az;
     float un = u[0] * ax + u[1] * ay + u[2] * az;
@@ -509,6 +510,13 @@ __device__ __forceinline__ void michelson_f32(const float k[3], const float u[3]
       sm = sincf_from(nm, dm);
     }
     float Sr = sp + zr * sm, Si = zi * sm;
+    if (table) {   // link phase from the arm vector (see michelson_fp64)
+      float se, ce;
+      sincos_revf(0.5f * fl * kn * (r2 * inv - (float)kLs), se, ce);
+      const float tr = sq * ce + cq * se, tc = cq * ce - sq * se;
+      sq = tr;
+      cq = tc;
+    }
     out[arm][0] = cq * Sr + sq * Si;
     out[arm][1] = cq * Si - sq * Sr;
     out[arm][2] = un * un - vn * vn;
@@ -532,20 +540,31 @@ __device__ __forceinline__ void michelson_f32(const float k[3], const float u[3]
 __device__ __forceinline__ void template_mixed(const PartConst& P, double f, float s0, float c0,
                                                float& cph, float& sph, float& tpr, float& tpi,
                                                float& txr, float& txi, const double* ek,
-                                               int code = 0) {
+                                               int code = 0, const OrbitTable* orb = nullptr) {
   double fr, tf;
   phase_and_tf(P, f, fr, tf, ek);
-  double sad, cad;
-  sincospi(2.0 * tf * (1.0 / kYear), &sad, &cad);
-  double kP = kRs * (P.k[0] * cad + P.k[1] * sad);      // k . guiding centre [s], FP64
+  double kP;                                             // FP64 part of k . p_1 [s]
   float d[3][3];
-  orbit_offsets<float>((float)cad, (float)sad, d);
+  if (orb && orb->coef) {
+    double dd3[3][3];
+    kP = k_dot_p1_table(P, *orb, tf, dd3);             // d = p_i - p_1, so k . d_0 = 0
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) d[i][c] = (float)dd3[i][c];
+  } else {
+    double sad, cad;
+    sincospi(2.0 * tf * (1.0 / kYear), &sad, &cad);
+    kP = kRs * (P.k[0] * cad + P.k[1] * sad);           // k . guiding centre [s], FP64
+    orbit_offsets<float>((float)cad, (float)sad, d);
+  }
   const float kx = (float)P.k[0], ky = (float)P.k[1], kz = (float)P.k[2];
   const float ux = (float)P.u[0], uy = (float)P.u[1], uz = (float)P.u[2];
   const float vx = (float)P.v[0], vy = (float)P.v[1], vz = (float)P.v[2];
   float kd0 = kx * d[0][0] + ky * d[0][1] + kz * d[0][2];
   sincos_rev(fr + f * (kP + (double)kd0), sph, cph);      // e^{i Phi}
   const float fl = (float)f;
+  const bool table = orb && orb->coef;
   if (code != 0) {
     const float kk[3] = {kx, ky, kz}, uu[3] = {ux, uy, uz}, vv[3] = {vx, vy, vz};
     double wd[3];
@@ -556,7 +575,7 @@ __device__ __forceinline__ void template_mixed(const PartConst& P, double f, flo
       if (wd[a] == 0.0) continue;
       const float wa = (float)wd[a];
       float pr, pi, xr, xi;
-      michelson_f32(kk, uu, vv, d, fl, s0, c0, a, pr, pi, xr, xi);
+      michelson_f32(kk, uu, vv, d, fl, s0, c0, a, pr, pi, xr, xi, table);
       tpr += wa * pr; tpi += wa * pi; txr += wa * xr; txi += wa * xi;
     }
     return;
@@ -567,7 +586,8 @@ __device__ __forceinline__ void template_mixed(const PartConst& P, double f, flo
 #pragma unroll
   for (int arm = 0; arm < 2; ++arm) {
     float ax = d[arm + 1][0] - d[0][0], ay = d[arm + 1][1] - d[0][1], az = d[arm + 1][2] - d[0][2];
-    float inv = __builtin_amdgcn_rsqf(ax * ax + ay * ay + az * az);
+    const float r2 = ax * ax + ay * ay + az * az;
+    float inv = __builtin_amdgcn_rsqf(r2);
     ax *= inv; ay *= inv; az *= inv;
     float kn = kx * ax + ky * ay + kz * az;
     float un = ux * ax + uy * ay + uz * az;
@@ -586,6 +606,13 @@ __device__ __forceinline__ void template_mixed(const PartConst& P, double f, flo
       sm = sincf_from(nm, dm);
     }
     float Sr = sp + zr * sm, Si = zi * sm;
+    if (table) {   // link phase from the arm vector (see michelson_fp64)
+      float se, ce;
+      sincos_revf(0.5f * fl * kn * (r2 * inv - (float)kLs), se, ce);
+      const float tr = sq * ce + cq * se, tc = cq * ce - sq * se;
+      sq = tr;
+      cq = tc;
+    }
     out[arm][0] = cq * Sr + sq * Si;
     out[arm][1] = cq * Si - sq * Sr;
     out[arm][2] = un * un - vn * vn;
@@ -641,7 +668,7 @@ __global__ __launch_bounds__(256) void k_eval_mixed(Grid g,
     for (int j = b0 + lane; j < b1; j += 64) {
       double f = bin_freq(g, j);
       float cps, sps, tpr, tpi, txr, txi;
-      template_mixed(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq, code);
+      template_mixed(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq, code, &g.orb);
       float a = wr[co + j], b = wi[co + j];
       float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
       kahan_addf(acc[0], cmp[0], Wr * tpr + Wi * tpi);
@@ -887,8 +914,10 @@ constexpr double kInterpTolPhaseMixed = 1e-9;
 constexpr double kInterpTolTMixed = 3e-8;
 
 // Node values, coefficients and end-point check of every work item (all
-// lanes active: lanes 60..63 repeat the last point of the last item).
-template <bool MIXED>
+// lanes active: lanes 60..63 repeat the last point of the last item).  TAB:
+// the plan has a numerical orbit (a separate instance keeps the table code
+// out of the analytic kernel's registers).
+template <bool MIXED, bool TAB>
 __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
                                                       const PartConst* __restrict__ pc,
                                                       const int32_t* __restrict__ bounds,
@@ -929,7 +958,8 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     // exact frequency (k_lo + b0 + mk) df of the node, as double-double
     const dd f = dd_add(two_prod((double)(g.k_lo + b0), g.df), two_prod(mk, g.df));
     double v[5], v0lo;
-    const dd ph = template_node(P, f, ekq, v[1], v[2], v[3], v[4], g.chan.code[ch]);
+    const dd ph = template_node(P, f, ekq, v[1], v[2], v[3], v[4], g.chan.code[ch],
+                                TAB ? &g.orb : nullptr);
     const double p0h = __shfl(ph.hi, base + kCheb, 64);
     const double p0l = __shfl(ph.lo, base + kCheb, 64);
     const double peh = __shfl(ph.hi, base + kCheb + 1, 64);
@@ -1893,7 +1923,7 @@ __global__ void k_waveform(Grid g, const PartConst* __restrict__ pc,
   double s0, c0;
   sincospi(kLs * f, &s0, &c0);
   double cph, sph, tpr, tpi, txr, txi;
-  template_fp64(P, f, s0, c0, cph, sph, tpr, tpi, txr, txi, nullptr, g.chan.code[0]);
+  template_fp64(P, f, s0, c0, cph, sph, tpr, tpi, txr, txi, nullptr, g.chan.code[0], &g.orb);
   // restore the constant phase the statistic drops
   double sc, cc;
   sincospi(2.0 * dropped_phase(P), &sc, &cc);
@@ -2033,14 +2063,14 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, ws.tcnt, ntiles, ws.toff, ws.uoff);
     hipLaunchKernelGGL(k_tile_scatter, dim3(1024), dim3(256), 0, s, ws.items, ws.total, ws.bounds,
                        stride, chunk, ntiles, g.chan.n, ws.toff, ws.tcur, ws.tile_items);
-    if (mixed)
-      hipLaunchKernelGGL(k_interp_nodes<true>, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds,
-                         stride, ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.xerr,
-                         ws.direct, ws.ndirect, um, ws.partials);
-    else
-      hipLaunchKernelGGL(k_interp_nodes<false>, dim3(blocks), dim3(256), 0, s, g, ws.pc,
-                         ws.bounds, stride, ws.items, ws.total, chunk, ek, ws.rec, ws.xflag,
-                         ws.xerr, ws.direct, ws.ndirect, um, ws.partials);
+    {
+      const bool tab = g.orb.coef != nullptr;
+      auto nodes = mixed ? (tab ? k_interp_nodes<true, true> : k_interp_nodes<true, false>)
+                         : (tab ? k_interp_nodes<false, true> : k_interp_nodes<false, false>);
+      hipLaunchKernelGGL(nodes, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
+                         ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.xerr, ws.direct,
+                         ws.ndirect, um, ws.partials);
+    }
     const size_t lds = 3 * (size_t)chunk * (mixed ? sizeof(float) : sizeof(double));
     if (ev_main) (void)hipEventRecord(ev_main[0], s);
     if (mixed)

@@ -28,7 +28,8 @@ FSTAT_EVAL_SURROGATE = 8
 FSTAT_AUTOTUNE_FORCE = 16
 FSTAT_EVAL_EXACT = 32
 
-EXPORTS = ("fstat_plan_create", "fstat_eval", "fstat_extrinsic", "fstat_waveform", "pso_stage",
+EXPORTS = ("fstat_plan_create", "fstat_plan_set_orbit", "fstat_eval", "fstat_extrinsic",
+           "fstat_waveform", "pso_stage",
            "fstat_search", "fstat_search_boxes",
            "fstat_profile_read", "fstat_interp_stats", "fstat_autotune", "fstat_mlp_grad", "fstat_mlp_forward",
            "fstat_surrogate_train", "fstat_surrogate_stats", "fstat_plan_destroy",
@@ -120,6 +121,8 @@ def lib() -> ctypes.CDLL:
         L.fstat_eval.argtypes = [vp, vp, i64, vp, i32, vp, vp, vp, i64, u32, vp]
         L.fstat_eval.restype = ctypes.c_int
         L.fstat_extrinsic.argtypes = [vp, vp, i64, vp, u32, vp]
+        L.fstat_plan_set_orbit.argtypes = [vp, ctypes.c_double, ctypes.c_double, i32, vp, u32, vp]
+        L.fstat_plan_set_orbit.restype = ctypes.c_int
         L.fstat_extrinsic.restype = ctypes.c_int
         L.fstat_waveform.argtypes = [ctypes.c_double, ctypes.c_double, i64, i64, vp, vp, vp, u32, vp]
         L.fstat_waveform.restype = ctypes.c_int
@@ -178,6 +181,11 @@ def fstat_eval(plan, params, n, np_ptr, np_uniform, F_hat, F_part, amps, part_st
                stream=None):
     _check(lib().fstat_eval(plan, params, int(n), np_ptr, int(np_uniform), F_hat, F_part, amps,
                             int(part_stride), int(flags), stream))
+
+
+def fstat_plan_set_orbit(plan, t0, dt, n_seg, nodes, flags, stream=None):
+    _check(lib().fstat_plan_set_orbit(plan, float(t0), float(dt), int(n_seg), nodes, int(flags),
+                                      stream))
 
 
 def fstat_extrinsic(amps, params, n, out, flags, stream=None):
@@ -416,6 +424,18 @@ class Plan:
         if final_x is not None:
             out["final_x"] = final_x
         return out
+
+    def set_orbit(self, t0: float = 0.0, dt: float = 1.0, nodes=None):
+        """Numerical orbit: nodes [n_seg, 3, 3, 10] positions [s] at the
+        Chebyshev points of each segment (see fstat_plan_set_orbit); None
+        returns to the analytic orbit."""
+        if nodes is None:
+            fstat_plan_set_orbit(self.handle, 0.0, 1.0, 0, None, 0, _stream())
+            return
+        nd = np.ascontiguousarray(nodes, dtype=np.float64)
+        if nd.ndim != 4 or nd.shape[1:] != (3, 3, 10):
+            raise ValueError("nodes must be [n_seg, 3, 3, 10]")
+        fstat_plan_set_orbit(self.handle, t0, dt, nd.shape[0], nd.ctypes.data, 0, _stream())
 
     def search(self, desc: fstat_search_desc) -> dict:
         """Run fstat_search; returns its results as numpy arrays and floats."""

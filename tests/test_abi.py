@@ -14,7 +14,8 @@ def _declared():
 
 
 def test_header_declares_the_boundary():
-    assert _declared() == sorted(["fstat_plan_create", "fstat_eval", "fstat_extrinsic", "fstat_waveform",
+    assert _declared() == sorted(["fstat_plan_create", "fstat_plan_set_orbit", "fstat_eval",
+                                  "fstat_extrinsic", "fstat_waveform",
                                   "fstat_search", "fstat_search_boxes",
                                   "pso_stage", "fstat_profile_read", "fstat_interp_stats",
                                   "fstat_autotune",

@@ -1,0 +1,140 @@
+"""Numerical orbit (Sec. IV: Chebyshev interpolation of tabulated spacecraft
+positions) on the GPU against the oracle with the same table.  Bars as in
+test_gpu_parity: FP64 1e-9 (+1e-14 cond) relative per partition, mixed 1e-4
+(+1e-6 cond)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2407_10797_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+T0, DT, NSEG = -86400.0, 131072.0, 10
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def _table(bump=0.0):
+    """The rigid analytic constellation at the table's Chebyshev points; with
+    bump > 0 the arms breathe by up to bump seconds (a test orbit that is not
+    the analytic one)."""
+    ts = O.chebyshev_times(T0, DT, NSEG)
+    O.set_orbit(None)
+    pos = O.orbit(ts.ravel(), rigid=True).reshape(NSEG, 10, 3, 3)
+    for i in (1, 2):
+        d = pos[:, :, i, :] - pos[:, :, 0, :]
+        pos[:, :, i, :] += (bump * np.sin(2 * np.pi * ts / 5e5)[:, :, None]
+                            * d / np.linalg.norm(d, axis=-1, keepdims=True))
+    return np.ascontiguousarray(pos.transpose(0, 2, 3, 1))   # [seg][sc][xyz][node]
+
+
+@pytest.fixture(scope="module")
+def case(torch_cuda):
+    from paper_2407_10797_amd import fstat
+    g = S.grid_small()
+    inj = S.small_injection_params()
+    sig = O.signal(inj, S.random_amplitudes(S.SMALL_SEEDS["inj"]), g.df, g.k_lo, g.nbins, g.T_obs)
+    data, psd = S.make_data(g, S.SMALL_SEEDS["noise"], sig, S.SMALL_SNR)
+    pts = np.vstack([inj[None, :], S.small_eval_points(inj, n=63)])
+    plan = fstat.Plan(data, psd, g.T_obs, g.df, g.k_lo)
+    yield dict(g=g, data=data, psd=psd, pts=pts, plan=plan, fstat=fstat)
+    plan.close()
+
+
+def _check(Fg, Fo, cond, rel, kc):
+    c = np.where(np.isfinite(cond), cond, 0.0)
+    r = np.abs(Fg - Fo) / np.maximum(np.abs(Fo), 1.0)
+    tol = rel + kc * c
+    ok = np.isfinite(Fo)
+    assert np.all(r[ok] <= tol[ok]), float((r[ok] / tol[ok]).max())
+    return float((r[ok] / tol[ok]).max())
+
+
+@pytest.mark.parametrize("npart", [1, 4])
+@pytest.mark.parametrize("mode", ["fp64", "mixed", "exact"])
+def test_breathing_orbit_matches_oracle(case, torch_cuda, npart, mode):
+    s = case
+    g = s["g"]
+    nodes = _table(bump=1e-3)
+    s["plan"].set_orbit(T0, DT, nodes)
+    try:
+        F, P = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, mixed=mode == "mixed",
+                              exact=mode == "exact", want_parts=True)
+        O.set_orbit(T0, DT, nodes)
+        Fo, Po, cond = O.fstat(s["data"], s["psd"], g.k_lo, g.df, g.T_obs, s["pts"], [npart],
+                               want_cond=True)
+    finally:
+        O.set_orbit(None)
+        s["plan"].set_orbit()
+    rel, kc = (1e-4, 1e-6) if mode == "mixed" else (1e-9, 1e-14)
+    worst = _check(P.cpu().numpy(), Po, cond, rel, kc)
+    print(f"[orbit] breathing table {mode} Np={npart}: worst error / tolerance {worst:.3f}",
+          flush=True)
+    # the table changes the statistic: the analytic plan differs from it
+    F0 = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart).cpu().numpy()
+    assert np.max(np.abs(F0 - Fo) / np.maximum(np.abs(Fo), 1.0)) > 1e-6
+
+
+def test_sampled_analytic_table_reproduces_analytic_plan(case, torch_cuda):
+    """A table sampled from the analytic constellation gives the analytic
+    statistic to the interpolation error; clearing the table restores the
+    analytic path bit for bit."""
+    s = case
+    x = torch_cuda.from_numpy(s["pts"])
+    F0 = s["plan"].eval(x, 4).cpu().numpy()
+    s["plan"].set_orbit(T0, DT, _table())
+    try:
+        F1 = s["plan"].eval(x, 4).cpu().numpy()
+    finally:
+        s["plan"].set_orbit()
+    np.testing.assert_allclose(F1, F0, rtol=1e-9, atol=1e-9)
+    np.testing.assert_array_equal(s["plan"].eval(x, 4).cpu().numpy(), F0)
+
+
+def test_orbit_with_aet_channels(torch_cuda):
+    """The table enters every channel's response (A, E, T at once)."""
+    from paper_2407_10797_amd import fstat
+    g = S.grid_small()
+    inj = S.small_injection_params()
+    a = S.random_amplitudes(S.SMALL_SEEDS["inj"])
+    chans = "AET"
+    nodes = _table(bump=1e-3)
+    O.set_orbit(T0, DT, nodes)
+    try:
+        sig = np.array([O.signal(inj, a, g.df, g.k_lo, g.nbins, g.T_obs, channel=c) for c in chans])
+        psd = np.array([S.psd_channel(g.freqs(), c) for c in chans])
+        data = np.array([S.noise(psd[i], g.df, 7301 + i) for i in range(3)]) + 3.0 * sig / np.abs(sig).max()
+        pts = np.vstack([inj[None, :], S.small_eval_points(inj, n=15)])
+        Fo, Po, cond = O.fstat(data, psd, g.k_lo, g.df, g.T_obs, pts, [4], want_cond=True,
+                               channels=chans)
+    finally:
+        O.set_orbit(None)
+    plan = fstat.Plan(data, psd, g.T_obs, g.df, g.k_lo, channels=chans)
+    try:
+        plan.set_orbit(T0, DT, nodes)
+        F, P = plan.eval(torch_cuda.from_numpy(pts), 4, want_parts=True)
+    finally:
+        plan.close()
+    _check(P.cpu().numpy(), Po, cond, 1e-9, 1e-14)
+
+
+def test_orbit_table_errors(case):
+    s = case
+    fstat = s["fstat"]
+    nodes = _table()
+    T = s["g"].T_obs
+    for t0, dt, nd in ((1.0, DT, nodes),                        # starts after 0
+                       (T0, DT, nodes[:2]),                     # ends before T_obs
+                       (T0, 0.0, nodes),                        # dt <= 0
+                       (T0, DT, np.where(np.arange(10) == 3, np.nan, nodes))):   # NaN node
+        with pytest.raises(fstat.FstatError):
+            s["plan"].set_orbit(t0, dt, nd)
+    with pytest.raises(ValueError):
+        s["plan"].set_orbit(T0, DT, nodes[..., :9])
+    assert T0 + DT * NSEG >= T
