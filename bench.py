@@ -221,6 +221,29 @@ def aet_bench(pts, npart, steps, warmup, autotune=True):
                 config="A, E, T with independent noise, same particles, Np and bins as fp64", **extra)
 
 
+def orbit_bench(plan, g, pts, npart, steps, warmup, mixed):
+    """The main batch with a numerical orbit: exact Kepler orbits tabulated at
+    Chebyshev points over 2^20-s segments covering the observation."""
+    import torch
+    from paper_2407_10797_amd import synth as S
+    dt = 2.0 ** 20
+    nseg = int(np.ceil((g.T_obs + 0.5 * dt) / dt))
+    plan.set_orbit(-0.5 * dt, dt, S.kepler_orbit_nodes(-0.5 * dt, dt, nseg))
+    try:
+        prm = torch.from_numpy(pts).cuda()
+        r = time_path(plan, prm, npart, steps, warmup, mixed)
+        items, rejected, refined = plan.interp_stats()
+    finally:
+        plan.set_orbit()
+    tps = len(pts) * steps / r["seconds"]
+    return dict(templates_per_s=tps, ms_per_step=1e3 * r["seconds"] / steps,
+                stage_ms=r["kernel_ms"], main_kernel_ms=r["main_ms"],
+                bin_templates_per_s=r["bins_per_launch"] / (r["kernel_ms"] * 1e-3),
+                work_items=items, exact_items=rejected, refined_items=refined,
+                config=f"Kepler-orbit table, {nseg} segments of 2^20 s, same particles, Np and "
+                       "bins as the analytic-orbit line")
+
+
 def cpu_baseline(g, data, psd, pts, npart, sample):
     from oracle import oracle as O
     sub = pts[:sample]
@@ -244,7 +267,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-aet", action="store_true", help="skip the three-channel measurement")
-    ap.add_argument("--only", choices=["fp64", "mixed", "mixed+surrogate", "pso", "search", "aet"],
+    ap.add_argument("--no-orbit", action="store_true", help="skip the numerical-orbit measurement")
+    ap.add_argument("--only", choices=["fp64", "mixed", "mixed+surrogate", "pso", "search", "aet",
+                                       "orbit"],
                     default=None,
                     help="one paper-scale variant, or only the batched PSO measurement, or only "
                          "the three-stage search")
@@ -341,6 +366,17 @@ def main():
                                             traffic=traffic), **extra)
         _log(f"{name}: {tps:.1f} templates/s, bin-loop stage {r['kernel_ms']:.2f} ms, main kernel "
              f"{r['main_ms']:.2f} ms, {r['bins_per_launch']:.3e} bin-templates/launch")
+    if not args.no_orbit and args.only in (None, "orbit"):
+        for name, mixed in (("orbit-fp64", False), ("orbit-mixed", True)):
+            if mixed and args.no_mixed:
+                continue
+            try:
+                variants[name] = v = orbit_bench(plan, g, pts, args.np, args.steps, args.warmup,
+                                                 mixed)
+                _log(f"{name}: {v['templates_per_s']:.1f} templates/s, bin-loop stage "
+                     f"{v['stage_ms']:.2f} ms, main kernel {v['main_kernel_ms']:.2f} ms")
+            except fstat.FstatError as e:
+                _log(f"{name}: {e}")
     plan.close()
     if not args.no_aet and args.only in (None, "aet"):
         try:
@@ -368,7 +404,7 @@ def main():
         "config": {"workload": "paper-scale: 2.5 yr TDI-X, 7,101,001 bins (10-100 mHz), "
                                f"{args.particles} particles per batch, Np={args.np}, FP64 path",
                    "global_batch": args.particles, "np": args.np, "nbins": int(g.nbins)},
-        "roofline": head["roofline"],
+        "roofline": head.get("roofline"),
         "variants": variants,
     }
     if args.pso_iters > 0:

@@ -116,6 +116,9 @@ __host__ __device__ __forceinline__ double dd_frac(dd a) {
 // Numerical orbit: nseg segments of length dt from t0, each a degree-9
 // Chebyshev series per spacecraft and coordinate (positions in seconds of
 // light travel), coef [nseg][3][3][10]; coef == nullptr: analytic orbit.
+// Read-only device memory addressed through the constant address space, so
+// that wave-uniform reads become scalar loads.
+typedef __attribute__((address_space(4))) double kconst_double;
 struct OrbitTable {
   const double* coef = nullptr;
   int32_t nseg = 0;
@@ -500,16 +503,13 @@ __device__ __forceinline__ void response_ch_fp64(const PartConst& P, double f, d
   }
 }
 
-// Spacecraft positions [s] at time t from an orbit table (Clenshaw on the
-// segment that holds t; the first or last segment outside the table).
-__device__ __forceinline__ void table_positions(const OrbitTable& o, double t, double p[3][3]) {
-  int seg = (int)floor((t - o.t0) / o.dt);
-  seg = min(max(seg, 0), o.nseg - 1);
-  const double x = 2.0 * ((t - o.t0) - o.dt * (double)seg) / o.dt - 1.0;
-  const double* c = o.coef + (int64_t)seg * 90;
-#pragma unroll 1
+// The nine degree-9 Chebyshev series of one table segment at x in [-1, 1]
+// (Clenshaw's recurrence), coefficients c[9][10].
+template <typename C>
+__device__ __forceinline__ void clenshaw_positions(const C* c, double x, double p[3][3]) {
+#pragma unroll
   for (int q = 0; q < 9; ++q) {
-    const double* cq = c + 10 * q;
+    const C* cq = c + 10 * q;
     double b1 = 0.0, b2 = 0.0;
 #pragma unroll
     for (int k = 9; k >= 1; --k) {
@@ -521,12 +521,41 @@ __device__ __forceinline__ void table_positions(const OrbitTable& o, double t, d
   }
 }
 
+// Spacecraft positions [s] at time t = th + tl (tl = 0 for a plain double)
+// from an orbit table: Clenshaw on the segment that holds t (the first or last
+// segment outside the table).  The offset from the segment's start is formed
+// without rounding t itself (whose ulp at 1e8 s, 1.5e-8 s, would move the
+// positions by ~1e-12 s and the Doppler phase by ~1e-13 cycles).
+__device__ __forceinline__ void table_positions(const OrbitTable& o, double th, double tl,
+                                                double p[3][3]) {
+  int seg;
+  double x;
+  {
+    FSTAT_NO_CONTRACT
+    const dd a = two_sum(th, -o.t0);                      // t - t0
+    seg = (int)floor(a.hi / o.dt);
+    seg = min(max(seg, 0), o.nseg - 1);
+    const dd s0 = two_prod(o.dt, (double)seg);            // segment start - t0
+    // a.hi - s0.hi is exact inside the table (the two are within a factor 2)
+    const double loc = (a.hi - s0.hi) + ((a.lo - s0.lo) + tl);
+    x = 2.0 * loc / o.dt - 1.0;
+  }
+  // All active lanes in one segment (the usual case): its coefficients are
+  // read through the scalar cache (wave-uniform address, read only);
+  // otherwise each lane reads its own segment's.
+  const int s = __builtin_amdgcn_readfirstlane(seg);
+  if (__builtin_amdgcn_ballot_w64(seg != s) == 0)
+    clenshaw_positions((const kconst_double*)(o.coef + (int64_t)s * 90), x, p);
+  else
+    clenshaw_positions(o.coef + (int64_t)seg * 90, x, p);
+}
+
 // k . p_1 from the table, with d[i] = p_i - p_1 (the response uses only
 // differences of the d and k . (d_a - d_0)).
-__device__ __forceinline__ double k_dot_p1_table(const PartConst& P, const OrbitTable& o, double t,
-                                                 double d[3][3]) {
+__device__ __forceinline__ double k_dot_p1_table(const PartConst& P, const OrbitTable& o, double th,
+                                                 double tl, double d[3][3]) {
   double p[3][3];
-  table_positions(o, t, p);
+  table_positions(o, th, tl, p);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -551,7 +580,7 @@ __device__ __forceinline__ void template_fp64(const PartConst& P, double f, doub
   double d[3][3];
   double kp1;
   if (orb && orb->coef) {
-    kp1 = k_dot_p1_table(P, *orb, tf, d);
+    kp1 = k_dot_p1_table(P, *orb, tf, 0.0, d);
   } else {
     double sa, ca;
     sincospi(2.0 * tf * (1.0 / kYear), &sa, &ca);
@@ -575,7 +604,7 @@ __device__ __forceinline__ dd template_node(const PartConst& P, dd fd, const dou
   double d[3][3];
   double kp1;
   if (orb && orb->coef) {
-    kp1 = k_dot_p1_table(P, *orb, tf.hi + tf.lo, d);
+    kp1 = k_dot_p1_table(P, *orb, tf.hi, tf.lo, d);
   } else {
     double sa, ca;
     {

@@ -547,7 +547,7 @@ __device__ __forceinline__ void template_mixed(const PartConst& P, double f, flo
   float d[3][3];
   if (orb && orb->coef) {
     double dd3[3][3];
-    kP = k_dot_p1_table(P, *orb, tf, dd3);             // d = p_i - p_1, so k . d_0 = 0
+    kP = k_dot_p1_table(P, *orb, tf, 0.0, dd3);             // d = p_i - p_1, so k . d_0 = 0
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll

@@ -19,6 +19,7 @@ import numpy as np
 
 YEAR_S = 31557600.0          # Julian year [s]
 C_SI = 299792458.0
+AU_M = 1.495978707e11        # astronomical unit [m]
 ARM_M = 2.5e9                # nominal arm length [m]
 S_ACC_ASD = 3e-15            # acceleration noise [m s^-2 Hz^-1/2]
 S_OMS_ASD = 15e-12           # optical metrology noise [m Hz^-1/2]
@@ -192,3 +193,45 @@ def make_data(grid: Grid, seed_noise: int, signal: np.ndarray | None = None,
     if signal is not None:
         d = d + snr_scale(signal, psd, grid.df, snr) * signal
     return d.astype(dtype), psd
+
+
+def chebyshev_node_times(t0: float, dt: float, nseg: int) -> np.ndarray:
+    """Times [nseg, 10] of an orbit table's nodes: t0 + dt (seg + (1 + s_k)/2),
+    s_k = cos(pi (k + 1/2) / 10)."""
+    s = np.cos(np.pi * (np.arange(10) + 0.5) / 10)
+    return t0 + dt * (np.arange(nseg)[:, None] + 0.5 * (1.0 + s[None, :]))
+
+
+def kepler_positions(t: np.ndarray) -> np.ndarray:
+    """Positions [n, 3, 3] (spacecraft, xyz; seconds of light travel) of three
+    spacecraft on exact heliocentric Kepler orbits that keep a triangle of
+    side ~ARM_M tilted by ~60 degrees to the ecliptic (semi-major axis 1 AU,
+    eccentricity ~ L / (2 sqrt 3 AU), orbital planes inclined by ~L / (2 AU)).
+    Unlike a first-order analytic orbit the arms flex by about one per cent
+    over a year: a stand-in for a numerically integrated orbit."""
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    R, alpha = AU_M / C_SI, ARM_M / (2.0 * AU_M)
+    incl = math.atan(alpha / (1.0 + alpha / math.sqrt(3.0)))
+    ecc = math.sqrt(1.0 + 2.0 * alpha / math.sqrt(3.0) + 4.0 * alpha * alpha / 3.0) - 1.0
+    out = np.empty((t.size, 3, 3))
+    for k in range(3):
+        sig = 2.0 * np.pi * k / 3.0
+        M = 2.0 * np.pi * t / YEAR_S - sig
+        E = M.copy()
+        for _ in range(8):                       # Kepler's equation, Newton
+            E -= (E - ecc * np.sin(E) - M) / (1.0 - ecc * np.cos(E))
+        xp = R * (np.cos(E) - ecc)               # in the orbital plane, perihelion on +x
+        yp = R * math.sqrt(1.0 - ecc * ecc) * np.sin(E)
+        x, z = xp * math.cos(incl), xp * math.sin(incl)
+        out[:, k, 0] = x * math.cos(sig) - yp * math.sin(sig)
+        out[:, k, 1] = x * math.sin(sig) + yp * math.cos(sig)
+        out[:, k, 2] = z
+    return out
+
+
+def kepler_orbit_nodes(t0: float, dt: float, nseg: int) -> np.ndarray:
+    """Orbit table [nseg, 3, 3, 10] (segment, spacecraft, xyz, node) of
+    kepler_positions at the Chebyshev node times."""
+    ts = chebyshev_node_times(t0, dt, nseg)
+    pos = kepler_positions(ts.ravel()).reshape(nseg, 10, 3, 3)
+    return np.ascontiguousarray(pos.transpose(0, 2, 3, 1))

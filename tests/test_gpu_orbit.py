@@ -81,6 +81,27 @@ def test_breathing_orbit_matches_oracle(case, torch_cuda, npart, mode):
     assert np.max(np.abs(F0 - Fo) / np.maximum(np.abs(Fo), 1.0)) > 1e-6
 
 
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_kepler_orbit_matches_oracle(case, torch_cuda, mode):
+    """A realistic table: exact Kepler orbits whose arms flex by ~1 %."""
+    s = case
+    g = s["g"]
+    nodes = S.kepler_orbit_nodes(T0, DT, NSEG)
+    s["plan"].set_orbit(T0, DT, nodes)
+    try:
+        F, P = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), 4, mixed=mode == "mixed",
+                              want_parts=True)
+        O.set_orbit(T0, DT, nodes)
+        Fo, Po, cond = O.fstat(s["data"], s["psd"], g.k_lo, g.df, g.T_obs, s["pts"], [4],
+                               want_cond=True)
+    finally:
+        O.set_orbit(None)
+        s["plan"].set_orbit()
+    rel, kc = (1e-4, 1e-6) if mode == "mixed" else (1e-9, 1e-14)
+    worst = _check(P.cpu().numpy(), Po, cond, rel, kc)
+    print(f"[orbit] Kepler table {mode} Np=4: worst error / tolerance {worst:.3f}", flush=True)
+
+
 def test_sampled_analytic_table_reproduces_analytic_plan(case, torch_cuda):
     """A table sampled from the analytic constellation gives the analytic
     statistic to the interpolation error; clearing the table restores the

@@ -626,3 +626,28 @@ def test_statistic_on_a_tabulated_orbit():
         O.set_orbit(None)
     np.testing.assert_allclose(F1, F0, rtol=1e-9)
     assert np.max(np.abs(F2 - F0) / np.abs(F0)) > 1e-6
+
+
+def test_kepler_orbit_input_is_a_flexing_triangle():
+    """The Keplerian stand-in for a numerical orbit (an input, not oracle
+    arithmetic): guiding centre at 1 AU, arms within 1.5 % of L and flexing,
+    plane tilted by 60 degrees, one-year period; the oracle interpolates a
+    table of it (2^20-s segments) to 1e-9 s."""
+    t = np.linspace(0.0, S.YEAR_S, 1500)
+    p = S.kepler_positions(t)
+    L = S.ARM_M / S.C_SI
+    arms = np.array([np.linalg.norm(p[:, i] - p[:, (i + 1) % 3], axis=1) for i in range(3)])
+    assert np.all(np.abs(arms / L - 1) < 0.015) and np.ptp(arms) > 1e-3 * L
+    c = p.mean(axis=1)
+    np.testing.assert_allclose(np.linalg.norm(c, axis=1), S.AU_M / S.C_SI, rtol=1e-4)
+    n = np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0])
+    tilt = np.degrees(np.arccos(np.abs(n[:, 2]) / np.linalg.norm(n, axis=1)))
+    assert np.all(np.abs(tilt - 60.0) < 1.0)
+    np.testing.assert_allclose(S.kepler_positions(t[:5] + S.YEAR_S), p[:5], atol=1e-9)
+    t0, dt, nseg = -2.0 ** 19, 2.0 ** 20, 40
+    try:
+        O.set_orbit(t0, dt, S.kepler_orbit_nodes(t0, dt, nseg))
+        tr = np.random.default_rng(3).uniform(0.0, 3.9e7, 300)
+        assert np.max(np.abs(O.positions(tr) - S.kepler_positions(tr))) < 1e-9
+    finally:
+        O.set_orbit(None)
