@@ -339,36 +339,46 @@ __host__ __device__ __forceinline__ double sinc_from(double num, double den) {
   return (fabs(den) < 1e-6) ? 1.0 - den * den * (1.0 / 6.0) : num / den;
 }
 
-// sin(2 pi r) and cos(2 pi r) for |r| <= 1/2 turn: quarter-turn reduction
-// x = r - n/4 (exact), |2 pi x| <= pi/4, then the Taylor series of sin to
-// theta^15 and of cos to theta^16 (remainders below 1e-16; the polynomials
-// in theta^2 evaluated in Estrin form), and the quarter turns n applied by
-// swapping and negating.
+// a * b + c as one three-operand FMA into a fresh register
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
+// sin(2 pi r) and cos(2 pi r) for any double r (in turns): half-turn
+// reduction x = r - n/2, n = rint(2 r) (exact), so |2 pi x| <= pi/2; the
+// Taylor series of sin to theta^21 and of cos to theta^20 (remainders below
+// 2e-17 there; the polynomials in theta^2 in Estrin form), and the factor
+// (-1)^n from the parity of n in floating point (no lane-dependent selects).
 __device__ __forceinline__ void sincos_turns(double r, double& s, double& c) {
-  const double n = rint(4.0 * r);
-  const double x = fma(-0.25, n, r);
+  const double n = rint(2.0 * r);
+  const double x = fma(-0.5, n, r);
+  const double sg = fma(-4.0, __builtin_amdgcn_fract(0.5 * n), 1.0);   // (-1)^n
   const double th = x * 6.283185307179586477;
   const double z = th * th;
-  const double z2 = z * z, z4 = z2 * z2;
-  // sin: th + th z (S1 + S2 z + ... + S7 z^6), S_k = (-1)^k / (2k+1)!  (Estrin form)
-  const double s01 = fma(1.0 / 120.0, z, -1.0 / 6.0);
-  const double s23 = fma(1.0 / 362880.0, z, -1.0 / 5040.0);
-  const double s45 = fma(1.0 / 6227020800.0, z, -1.0 / 39916800.0);
-  const double s6 = -1.0 / 1307674368000.0;
-  const double ps = fma(fma(s6, z2, s45), z4, fma(s23, z2, s01));
-  const double sn = fma(th * z, ps, th);
-  // cos: 1 + z (C1 + C2 z + ... + C8 z^7), C_k = (-1)^k / (2k)!
-  const double c01 = fma(1.0 / 24.0, z, -0.5);
-  const double c23 = fma(1.0 / 40320.0, z, -1.0 / 720.0);
-  const double c45 = fma(1.0 / 479001600.0, z, -1.0 / 3628800.0);
-  const double c67 = fma(1.0 / 20922789888000.0, z, -1.0 / 87178291200.0);
-  const double pc = fma(fma(c67, z2, c45), z4, fma(c23, z2, c01));
-  const double cs = fma(z, pc, 1.0);
-  const int q = ((int)n) & 3;
-  const double a = (q & 1) ? cs : sn;
-  const double b = (q & 1) ? sn : cs;
-  s = (q & 2) ? -a : a;                               // q = 1: ( c, -s); 2: (-s, -c); 3: (-c, s)
-  c = ((q + 1) & 2) ? -b : b;
+  const double z2 = z * z, z4 = z2 * z2, z8 = z4 * z4;
+  // Estrin form.  The first level pairs two constants; written as a plain
+  // fma the compiler keeps both in vector registers and copies the addend
+  // before an accumulating FMA (one extra move per pair), so these take the
+  // three-operand FMA explicitly.
+  // sin: th + th z (S1 + S2 z + ... + S10 z^9), S_k = (-1)^k / (2k+1)!
+  const double s12 = fma3(1.0 / 120.0, z, -1.0 / 6.0);
+  const double s34 = fma3(1.0 / 362880.0, z, -1.0 / 5040.0);
+  const double s56 = fma3(1.0 / 6227020800.0, z, -1.0 / 39916800.0);
+  const double s78 = fma3(1.0 / 355687428096000.0, z, -1.0 / 1307674368000.0);
+  const double s9a = fma3(1.0 / 51090942171709440000.0, z, -1.0 / 121645100408832000.0);
+  const double ps = fma(fma(s78, z2, s56), z4, fma(s34, z2, s12)) + s9a * z8;
+  // cos: 1 + z (C1 + C2 z + ... + C10 z^9), C_k = (-1)^k / (2k)!
+  const double c12 = fma(1.0 / 24.0, z, -0.5);
+  const double c34 = fma3(1.0 / 40320.0, z, -1.0 / 720.0);
+  const double c56 = fma3(1.0 / 479001600.0, z, -1.0 / 3628800.0);
+  const double c78 = fma3(1.0 / 20922789888000.0, z, -1.0 / 87178291200.0);
+  const double c9a = fma3(1.0 / 2432902008176640000.0, z, -1.0 / 6402373705728000.0);
+  const double pc = fma(fma(c78, z2, c56), z4, fma(c34, z2, c12)) + c9a * z8;
+  const double ts = sg * th;
+  s = fma(ts * z, ps, ts);
+  c = fma(sg * z, pc, sg);
 }
 
 // hardware reciprocal / reciprocal square root seeds refined by two Newton

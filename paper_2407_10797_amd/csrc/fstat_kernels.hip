@@ -1284,8 +1284,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
             const double jd = j00 + m;
             const double fj = jd * g.df;
             const double ej = fma(jd, g.df, -fj);
-            double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
-            ph -= rint(ph);
+            const double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
             double sps, cps;
             sincos_turns(ph, sps, cps);
             const double tpr = estrin_d<DT>(cT[0], s, s2, s4, s8);
