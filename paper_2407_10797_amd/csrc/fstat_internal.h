@@ -339,10 +339,11 @@ __host__ __device__ __forceinline__ double sinc_from(double num, double den) {
   return (fabs(den) < 1e-6) ? 1.0 - den * den * (1.0 / 6.0) : num / den;
 }
 
-// a * b + c as one three-operand FMA into a fresh register
+// a * b + c as one three-operand FMA into a fresh register, a wave-uniform
+// (a scalar register: constants cost scalar moves, not vector ones)
 __device__ __forceinline__ double fma3(double a, double b, double c) {
   double d;
-  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "s"(a), "v"(b), "v"(c));
   return d;
 }
 

@@ -1173,6 +1173,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
   DT* s_wr = reinterpret_cast<DT*>(smem);      // the tile's w and u, [3][T]
   DT* s_wi = s_wr + T;
   DT* s_u = s_wi + T;
+  double* s_e = reinterpret_cast<double*>(s_u + T);   // FP64 loop: grid rounding e_j, [T]
   __shared__ int s_unit[3];                       // tile, first item, item count
   __shared__ double s_rec[4][64];                // each wave's current item record
   const DT* gwr;
@@ -1214,6 +1215,12 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
       s_wr[i] = gwr[co + j0 + i];
       s_wi[i] = gwi[co + j0 + i];
       s_u[i] = gu[co + j0 + i];
+      if constexpr (!MIXED) {
+        // f_j = (k_lo + j) df rounds to a double; e_j is the rounding error of
+        // that product (one FMA), formed once per bin of the tile
+        const double jd = (double)(g.k_lo + j0 + i);
+        s_e[i] = fma(jd, g.df, -(jd * g.df));
+      }
     }
     __syncthreads();
     const int i0 = s_unit[1];
@@ -1254,10 +1261,9 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
         // The grid is f_j = (k_lo + j) df rounded to a double; the interpolants
         // are exact in f, so the phase moves by (dPhi/df)(f_j - exact) =
-        // -(B / df) e_j, with e_j the rounding error of the product (from an
-        // FMA): up to ~1e-9 cycles at t_f ~ 1e8 s.
+        // -(B / df) e_j, with e_j the rounding error of the product (staged
+        // with the tile): up to ~1e-9 cycles at t_f ~ 1e8 s.
         const double kB = -Bf / g.df;
-        const double j00 = (double)(g.k_lo + b0);
         const int last = nb - 1;
         // WM: also sum the M-terms per bin (items without quadrature M-terms);
         // DT: degree of the transfer interpolants (5, 7 or 9)
@@ -1270,20 +1276,19 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
           // the next bin's w, u are read one iteration ahead (LDS latency)
           double a_n = s_wr[e0 + min(lane, last)], b_n = s_wi[e0 + min(lane, last)];
           double u_n = WM ? s_u[e0 + min(lane, last)] : 0.0;
+          double e_n = s_e[e0 + min(lane, last)];
           for (int mi = lane; mi < nb; mi += 64) {
-            const double a = a_n, b = b_n, uu = u_n;
+            const double a = a_n, b = b_n, uu = u_n, ej = e_n;
             {
               const int nx = e0 + min(mi + 64, last);
               a_n = s_wr[nx];
               b_n = s_wi[nx];
+              e_n = s_e[nx];
               if constexpr (WM) u_n = s_u[nx];
             }
             const double m = (double)mi;
             const double s = fma(alpha, m, -1.0);
             const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
-            const double jd = j00 + m;
-            const double fj = jd * g.df;
-            const double ej = fma(jd, g.df, -fj);
             const double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
             double sps, cps;
             sincos_turns(ph, sps, cps);
@@ -2070,7 +2075,8 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
                          ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.xerr, ws.direct,
                          ws.ndirect, um, ws.partials);
     }
-    const size_t lds = 3 * (size_t)chunk * (mixed ? sizeof(float) : sizeof(double));
+    // w, u (and e_j on the FP64 path) of one tile
+    const size_t lds = (size_t)chunk * (mixed ? 3 * sizeof(float) : 4 * sizeof(double));
     if (ev_main) (void)hipEventRecord(ev_main[0], s);
     if (mixed)
       hipLaunchKernelGGL(k_eval_interp<true>, dim3(blocks), dim3(256), lds, s, g, ws.bounds, stride,
