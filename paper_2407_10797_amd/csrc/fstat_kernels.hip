@@ -1253,12 +1253,6 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
       const double alpha = 2.0 / (double)(nb - 1);
       const int e0 = b0 - j0;            // LDS offset of the item's first bin
       if constexpr (!MIXED) {
-        double cT[4][kCheb];
-#pragma unroll
-        for (int fn = 0; fn < 4; ++fn)
-#pragma unroll
-          for (int n = 0; n < kCheb; ++n) cT[fn][n] = R[kCheb + fn * L::nT + n];
-        __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
         // The grid is f_j = (k_lo + j) df rounded to a double; the interpolants
         // are exact in f, so the phase moves by (dPhi/df)(f_j - exact) =
         // -(B / df) e_j, with e_j the rounding error of the product (staged
@@ -1270,49 +1264,96 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         auto loop = [&](auto wm, auto dt) {
           constexpr bool WM = decltype(wm)::value;
           constexpr int DT = decltype(dt)::value;
-          double acc[8];
-#pragma unroll
-          for (int i = 0; i < 8; ++i) acc[i] = 0.0;
-          // the next bin's w, u are read one iteration ahead (LDS latency)
+          // the next bin's w, u, e_j are read one iteration ahead (LDS latency)
           double a_n = s_wr[e0 + min(lane, last)], b_n = s_wi[e0 + min(lane, last)];
           double u_n = WM ? s_u[e0 + min(lane, last)] : 0.0;
           double e_n = s_e[e0 + min(lane, last)];
-          for (int mi = lane; mi < nb; mi += 64) {
-            const double a = a_n, b = b_n, uu = u_n, ej = e_n;
-            {
-              const int nx = e0 + min(mi + 64, last);
-              a_n = s_wr[nx];
-              b_n = s_wi[nx];
-              e_n = s_e[nx];
-              if constexpr (WM) u_n = s_u[nx];
-            }
-            const double m = (double)mi;
-            const double s = fma(alpha, m, -1.0);
-            const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
-            const double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
-            double sps, cps;
-            sincos_turns(ph, sps, cps);
-            const double tpr = estrin_d<DT>(cT[0], s, s2, s4, s8);
-            const double tpi = estrin_d<DT>(cT[1], s, s2, s4, s8);
-            const double txr = estrin_d<DT>(cT[2], s, s2, s4, s8);
-            const double txi = estrin_d<DT>(cT[3], s, s2, s4, s8);
-            const double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
-            acc[0] += Wr * tpr + Wi * tpi;
-            acc[1] += Wi * tpr - Wr * tpi;
-            acc[2] += Wr * txr + Wi * txi;
-            acc[3] += Wi * txr - Wr * txi;
-            if constexpr (WM) {
+          int idx;
+          if constexpr (WM) {
+            double cT[4][DT + 1];
+#pragma unroll
+            for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+              for (int n = 0; n <= DT; ++n) cT[fn][n] = R[kCheb + fn * L::nT + n];
+            __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
+            double acc[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] = 0.0;
+            for (int mi = lane; mi < nb; mi += 64) {
+              const double a = a_n, b = b_n, uu = u_n, ej = e_n;
+              {
+                const int nx = e0 + min(mi + 64, last);
+                a_n = s_wr[nx];
+                b_n = s_wi[nx];
+                e_n = s_e[nx];
+                u_n = s_u[nx];
+              }
+              const double m = (double)mi;
+              const double s = fma(alpha, m, -1.0);
+              const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
+              const double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
+              double sps, cps;
+              sincos_turns(ph, sps, cps);
+              const double tpr = estrin_d<DT>(cT[0], s, s2, s4, s8);
+              const double tpi = estrin_d<DT>(cT[1], s, s2, s4, s8);
+              const double txr = estrin_d<DT>(cT[2], s, s2, s4, s8);
+              const double txi = estrin_d<DT>(cT[3], s, s2, s4, s8);
+              const double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
+              acc[0] += Wr * tpr + Wi * tpi;
+              acc[1] += Wi * tpr - Wr * tpi;
+              acc[2] += Wr * txr + Wi * txi;
+              acc[3] += Wi * txr - Wr * txi;
               acc[4] += uu * (tpr * tpr + tpi * tpi);
               acc[5] += uu * (txr * txr + txi * txi);
               acc[6] += uu * (tpr * txr + tpi * txi);
               acc[7] += uu * (tpi * txr - tpr * txi);
             }
-          }
-          int idx;
-          if constexpr (WM) {
             const double tot = wave_sum8(acc, lane, idx);
             if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
           } else {
+            // N-terms only.  They are linear in the transfer interpolants
+            // T(s) = sum_k c_k s^k, so the loop sums the moments
+            // sum_j w_j e^{i Phi_j} s_j^k (k <= DT) and the coefficients are
+            // applied once per lane afterwards: no transfer polynomial per bin.
+            double mr[DT + 1], mm[DT + 1];
+#pragma unroll
+            for (int k = 0; k <= DT; ++k) mr[k] = mm[k] = 0.0;
+            for (int mi = lane; mi < nb; mi += 64) {
+              const double a = a_n, b = b_n, ej = e_n;
+              {
+                const int nx = e0 + min(mi + 64, last);
+                a_n = s_wr[nx];
+                b_n = s_wi[nx];
+                e_n = s_e[nx];
+              }
+              const double m = (double)mi;
+              const double s = fma(alpha, m, -1.0);
+              const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
+              const double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
+              double sps, cps;
+              sincos_turns(ph, sps, cps);
+              const double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
+              const double s3 = s2 * s;
+              const double pw[10] = {1.0, s, s2, s3, s4, s4 * s, s4 * s2, s4 * s3, s8, s8 * s};
+              mr[0] += Wr;
+              mm[0] += Wi;
+#pragma unroll
+              for (int k = 1; k <= DT; ++k) {
+                mr[k] = fma(Wr, pw[k], mr[k]);
+                mm[k] = fma(Wi, pw[k], mm[k]);
+              }
+            }
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k <= DT; ++k) {
+              const double t0 = R[kCheb + k], t1 = R[kCheb + L::nT + k];
+              const double t2 = R[kCheb + 2 * L::nT + k], t3 = R[kCheb + 3 * L::nT + k];
+              acc[0] += t0 * mr[k] + t1 * mm[k];      // sum Wr T+r + Wi T+i
+              acc[1] += t0 * mm[k] - t1 * mr[k];      // sum Wi T+r - Wr T+i
+              acc[2] += t2 * mr[k] + t3 * mm[k];
+              acc[3] += t2 * mm[k] - t3 * mr[k];
+            }
+            __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
             const double tot = wave_sum4(acc, lane, idx);
             if ((lane & 15) == 0) partials[(int64_t)w * 8 + idx] = tot;
           }
