@@ -1371,37 +1371,38 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
           else loop(std::true_type{}, D9{});
         }
       } else {
-        float cT[4][kDegT + 1];
-#pragma unroll
-        for (int fn = 0; fn < 4; ++fn)
-#pragma unroll
-          for (int n = 0; n <= kDegT; ++n) cT[fn][n] = (float)R[kCheb + fn * L::nT + n];
-        __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
         // per lane at most T / 64 terms: plain FP32 sums of the N-terms (their
         // rounding, ~1e-7 relative, is far inside the mixed path's bar); M-terms
         // (items without quadrature M-terms) in FP64 from the FP32 response
         auto loop = [&](auto wm) {
           constexpr bool WM = decltype(wm)::value;
-          float acc[4];
-          double m4[4];
+          int idx;
+          if constexpr (WM) {
+            float cT[4][kDegT + 1];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) { acc[i] = 0.0f; m4[i] = 0.0; }
-          for (int mi = lane; mi < nb; mi += 64) {
-            const double m = (double)mi;
-            const double s = fma(alpha, m, -1.0);
-            const double ph = fma(Bp, m, horner(cR, s)) + A;
-            const float rf = (float)(ph - rint(ph));
-            const float sps = __builtin_amdgcn_sinf(rf), cps = __builtin_amdgcn_cosf(rf);
-            const float sf = (float)s;
-            const float tpr = horner_n<kDegT>(cT[0], sf), tpi = horner_n<kDegT>(cT[1], sf);
-            const float txr = horner_n<kDegT>(cT[2], sf), txi = horner_n<kDegT>(cT[3], sf);
-            const float a = s_wr[e0 + mi], b = s_wi[e0 + mi];
-            const float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
-            acc[0] += Wr * tpr + Wi * tpi;
-            acc[1] += Wi * tpr - Wr * tpi;
-            acc[2] += Wr * txr + Wi * txi;
-            acc[3] += Wi * txr - Wr * txi;
-            if constexpr (WM) {
+            for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+              for (int n = 0; n <= kDegT; ++n) cT[fn][n] = (float)R[kCheb + fn * L::nT + n];
+            __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
+            float acc[4];
+            double m4[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { acc[i] = 0.0f; m4[i] = 0.0; }
+            for (int mi = lane; mi < nb; mi += 64) {
+              const double m = (double)mi;
+              const double s = fma(alpha, m, -1.0);
+              const double ph = fma(Bp, m, horner(cR, s)) + A;
+              const float rf = (float)(ph - rint(ph));
+              const float sps = __builtin_amdgcn_sinf(rf), cps = __builtin_amdgcn_cosf(rf);
+              const float sf = (float)s;
+              const float tpr = horner_n<kDegT>(cT[0], sf), tpi = horner_n<kDegT>(cT[1], sf);
+              const float txr = horner_n<kDegT>(cT[2], sf), txi = horner_n<kDegT>(cT[3], sf);
+              const float a = s_wr[e0 + mi], b = s_wi[e0 + mi];
+              const float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
+              acc[0] += Wr * tpr + Wi * tpi;
+              acc[1] += Wi * tpr - Wr * tpi;
+              acc[2] += Wr * txr + Wi * txi;
+              acc[3] += Wi * txr - Wr * txi;
               const double uu = (double)s_u[e0 + mi];
               const double pr = tpr, pi = tpi, xr = txr, xi = txi;
               m4[0] += uu * (pr * pr + pi * pi);
@@ -1409,18 +1410,48 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
               m4[2] += uu * (pr * xr + pi * xi);
               m4[3] += uu * (pi * xr - pr * xi);
             }
-          }
-          int idx;
-          if constexpr (WM) {
             double red[8];
 #pragma unroll
             for (int i = 0; i < 4; ++i) { red[i] = (double)acc[i]; red[4 + i] = m4[i]; }
             const double tot = wave_sum8(red, lane, idx);
             if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
           } else {
-            double red[4];
+            // N-terms only: FP32 moments sum_j w_j e^{i Phi_j} s_j^k (k <= 6), the
+            // transfer coefficients applied per lane after the loop in FP64
+            float mr[kDegT + 1], mm[kDegT + 1];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) red[i] = (double)acc[i];
+            for (int k = 0; k <= kDegT; ++k) mr[k] = mm[k] = 0.0f;
+            for (int mi = lane; mi < nb; mi += 64) {
+              const double m = (double)mi;
+              const double s = fma(alpha, m, -1.0);
+              const double ph = fma(Bp, m, horner(cR, s)) + A;
+              const float rf = (float)(ph - rint(ph));
+              const float sps = __builtin_amdgcn_sinf(rf), cps = __builtin_amdgcn_cosf(rf);
+              const float sf = (float)s;
+              const float a = s_wr[e0 + mi], b = s_wi[e0 + mi];
+              const float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
+              const float s2 = sf * sf, s3 = s2 * sf, s4 = s2 * s2;
+              const float pw[7] = {1.0f, sf, s2, s3, s4, s4 * sf, s4 * s2};
+              mr[0] += Wr;
+              mm[0] += Wi;
+#pragma unroll
+              for (int k = 1; k <= kDegT; ++k) {
+                mr[k] = fmaf(Wr, pw[k], mr[k]);
+                mm[k] = fmaf(Wi, pw[k], mm[k]);
+              }
+            }
+            double red[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k <= kDegT; ++k) {
+              const double t0 = R[kCheb + k], t1 = R[kCheb + L::nT + k];
+              const double t2 = R[kCheb + 2 * L::nT + k], t3 = R[kCheb + 3 * L::nT + k];
+              const double r = mr[k], q = mm[k];
+              red[0] += t0 * r + t1 * q;
+              red[1] += t0 * q - t1 * r;
+              red[2] += t2 * r + t3 * q;
+              red[3] += t2 * q - t3 * r;
+            }
+            __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
             const double tot = wave_sum4(red, lane, idx);
             if ((lane & 15) == 0) partials[(int64_t)w * 8 + idx] = tot;
           }
