@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 # MI355X vector ALU: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-instructions/s;
 # with FMA = 2 FLOP that is 78.6 TFLOP/s for FP64.  FP32 arithmetic issues at
 # twice that rate (157.3 TFLOP/s; measured here: the mixed loop's instruction
-# count exceeds the single-rate issue budget by 10 %), so a kernel that mixes
+# rate has exceeded the single-rate issue budget), so a kernel that mixes
 # the two is held to the time floor f64 / 78.6 + f32 / 157.3.
 PEAK_VALU_TFLOPS = 78.6
 PEAK_F32_TFLOPS = 157.3
@@ -44,14 +44,14 @@ def _peak_tflops(kind):
 # bytes read per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes
 # written per launch (WRITE_SIZE).
 MAIN_KERNEL = {"fp64": "k_eval_interp<false>", "mixed": "k_eval_interp<true>"}
-FLOP_PER_BIN = {"fp64": 145.55, "mixed": 96.86}      # FP64 + FP32
-FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 72.33}      # of which FP32
-VALU_PER_BIN = {"fp64": 122.49, "mixed": 67.54}
-VALU32_PER_BIN = {"fp64": 0.01, "mixed": 42.20}      # of which FP32 arithmetic
-TRAFFIC = {"fp64": (0.5130, 6.657e7), "mixed": (0.2774, 3.778e7)}
+FLOP_PER_BIN = {"fp64": 124.69, "mixed": 65.99}      # FP64 + FP32
+FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 39.18}      # of which FP32
+VALU_PER_BIN = {"fp64": 91.97, "mixed": 52.21}
+VALU32_PER_BIN = {"fp64": 0.01, "mixed": 25.12}      # of which FP32 arithmetic
+TRAFFIC = {"fp64": (0.5130, 6.651e7), "mixed": (0.2776, 3.779e7)}
 # sha256 of the kernel sources those counters were taken on; the figures are
 # reported as null once the sources differ.
-COUNTERS_SRC_SHA = "6f23cdd13c0c5edbe8e5c46605e96f33e6c65e9f8f6b3cb30cb146b6bbbeac7d"
+COUNTERS_SRC_SHA = "9a4d66bebc2cb5efcb9f6e96a75666e2588837b7dfd215a775351f2dbb165752"
 KERNEL_SOURCES = ("fstat_kernels.hip", "fstat_internal.h", "fstat_kernels.h")
 
 
