@@ -347,41 +347,6 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
   return d;
 }
 
-// sin(2 pi r) and cos(2 pi r) for any double r (in turns): half-turn
-// reduction x = r - n/2, n = rint(2 r) (exact), so |2 pi x| <= pi/2; the
-// Taylor series of sin to theta^21 and of cos to theta^20 (remainders below
-// 2e-17 there; the polynomials in theta^2 in Estrin form), and the factor
-// (-1)^n from the parity of n in floating point (no lane-dependent selects).
-__device__ __forceinline__ void sincos_turns(double r, double& s, double& c) {
-  const double n = rint(2.0 * r);
-  const double x = fma(-0.5, n, r);
-  const double sg = fma(-4.0, __builtin_amdgcn_fract(0.5 * n), 1.0);   // (-1)^n
-  const double th = x * 6.283185307179586477;
-  const double z = th * th;
-  const double z2 = z * z, z4 = z2 * z2, z8 = z4 * z4;
-  // Estrin form.  The first level pairs two constants; written as a plain
-  // fma the compiler keeps both in vector registers and copies the addend
-  // before an accumulating FMA (one extra move per pair), so these take the
-  // three-operand FMA explicitly.
-  // sin: th + th z (S1 + S2 z + ... + S10 z^9), S_k = (-1)^k / (2k+1)!
-  const double s12 = fma3(1.0 / 120.0, z, -1.0 / 6.0);
-  const double s34 = fma3(1.0 / 362880.0, z, -1.0 / 5040.0);
-  const double s56 = fma3(1.0 / 6227020800.0, z, -1.0 / 39916800.0);
-  const double s78 = fma3(1.0 / 355687428096000.0, z, -1.0 / 1307674368000.0);
-  const double s9a = fma3(1.0 / 51090942171709440000.0, z, -1.0 / 121645100408832000.0);
-  const double ps = fma(fma(s78, z2, s56), z4, fma(s34, z2, s12)) + s9a * z8;
-  // cos: 1 + z (C1 + C2 z + ... + C10 z^9), C_k = (-1)^k / (2k)!
-  const double c12 = fma(1.0 / 24.0, z, -0.5);
-  const double c34 = fma3(1.0 / 40320.0, z, -1.0 / 720.0);
-  const double c56 = fma3(1.0 / 479001600.0, z, -1.0 / 3628800.0);
-  const double c78 = fma3(1.0 / 20922789888000.0, z, -1.0 / 87178291200.0);
-  const double c9a = fma3(1.0 / 2432902008176640000.0, z, -1.0 / 6402373705728000.0);
-  const double pc = fma(fma(c78, z2, c56), z4, fma(c34, z2, c12)) + c9a * z8;
-  const double ts = sg * th;
-  s = fma(ts * z, ps, ts);
-  c = fma(sg * z, pc, sg);
-}
-
 // hardware reciprocal / reciprocal square root seeds refined by two Newton
 // steps (accurate to about one ulp)
 __device__ __forceinline__ double rcp_nr(double x) {

@@ -809,6 +809,28 @@ __device__ __forceinline__ double estrin_d(const double* c, double s, double s2,
 // FP64 loop evaluates the transfer interpolants at (5, 7 or 9).
 constexpr int kRec = 5 * kCheb + 5;
 static_assert(kRec == kInterpRec && kRec <= 64, "record layout");
+// sin(2 pi r), cos(2 pi r) for |r| < 2^22 turns: r = n / kSinTab + x with x
+// exact and |x| <= 1 / (2 kSinTab); the coarse factor from the LDS table, the
+// fine one from short Taylor series (sin to theta^5, cos to theta^6:
+// remainders below 1e-19 for |theta| <= pi / kSinTab), combined by the
+// angle-addition formulas.  In the bin loop |r| stays below ~1e4 turns (the
+// item's start phase is below one turn, the linear term below half a turn
+// per bin, the residual a few hundred turns at most).
+constexpr int kSinTab = 512;
+__device__ __forceinline__ void sincos_tab(double r, const double2* tab, double& s, double& c) {
+  const double n = rint(r * (double)kSinTab);
+  const double x = fma(-1.0 / (double)kSinTab, n, r);
+  const double2 e = tab[(int)n & (kSinTab - 1)];
+  const double th = x * 6.283185307179586477;
+  const double z = th * th;
+  const double ps = fma3(1.0 / 120.0, z, -1.0 / 6.0);
+  const double pc = fma(fma3(-1.0 / 720.0, z, 1.0 / 24.0), z, -0.5);
+  const double sl = fma(th * z, ps, th);
+  const double cl = fma(z, pc, 1.0);
+  s = fma(e.x, cl, e.y * sl);
+  c = fma(e.y, cl, -(e.x * sl));
+}
+
 template <bool MIXED> struct RecLayout {
   static constexpr int nT = MIXED ? kDegT + 1 : kCheb;
   static constexpr int tail = kCheb + 4 * nT;   // A, B', B, M-by-quadrature flag
@@ -1174,6 +1196,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
   DT* s_wi = s_wr + T;
   DT* s_u = s_wi + T;
   double* s_e = reinterpret_cast<double*>(s_u + T);   // FP64 loop: grid rounding e_j, [T]
+  double2* s_tab = reinterpret_cast<double2*>(s_e + T);   // FP64 loop: sin, cos table
   __shared__ int s_unit[3];                       // tile, first item, item count
   __shared__ double s_rec[4][64];                // each wave's current item record
   const DT* gwr;
@@ -1185,6 +1208,14 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
   const int wv = threadIdx.x >> 6;
   const int nwv = blockDim.x >> 6;
   const int nunits = unit_off[ntiles];
+  if constexpr (!MIXED) {
+    // (sin, cos)(2 pi k / kSinTab): the coarse factor of the bin loop's sincos
+    for (int k = threadIdx.x; k < kSinTab; k += blockDim.x) {
+      double sv, cv;
+      sincospi(2.0 * (double)k / (double)kSinTab, &sv, &cv);
+      s_tab[k] = make_double2(sv, cv);
+    }
+  }                                     // (the unit fetch below synchronises the block)
   for (;;) {
     // next unit (dynamic): up to kUnitItems items of one tile
     if (threadIdx.x == 0) {
@@ -1293,7 +1324,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
               const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
               const double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
               double sps, cps;
-              sincos_turns(ph, sps, cps);
+              sincos_tab(ph, s_tab, sps, cps);
               const double tpr = estrin_d<DT>(cT[0], s, s2, s4, s8);
               const double tpi = estrin_d<DT>(cT[1], s, s2, s4, s8);
               const double txr = estrin_d<DT>(cT[2], s, s2, s4, s8);
@@ -1331,7 +1362,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
               const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
               const double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
               double sps, cps;
-              sincos_turns(ph, sps, cps);
+              sincos_tab(ph, s_tab, sps, cps);
               const double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
               const double s3 = s2 * s;
               const double pw[10] = {1.0, s, s2, s3, s4, s4 * s, s4 * s2, s4 * s3, s8, s8 * s};
@@ -2147,8 +2178,9 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
                          ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.xerr, ws.direct,
                          ws.ndirect, um, ws.partials);
     }
-    // w, u (and e_j on the FP64 path) of one tile
-    const size_t lds = (size_t)chunk * (mixed ? 3 * sizeof(float) : 4 * sizeof(double));
+    // w, u (and e_j and the sincos table on the FP64 path) of one tile
+    const size_t lds = mixed ? (size_t)chunk * 3 * sizeof(float)
+                             : (size_t)chunk * 4 * sizeof(double) + kSinTab * sizeof(double2);
     if (ev_main) (void)hipEventRecord(ev_main[0], s);
     if (mixed)
       hipLaunchKernelGGL(k_eval_interp<true>, dim3(blocks), dim3(256), lds, s, g, ws.bounds, stride,
