@@ -1192,11 +1192,15 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                                                      double* __restrict__ partials) {
   typedef typename std::conditional<MIXED, float, double>::type DT;
   extern __shared__ unsigned char smem[];
-  DT* s_wr = reinterpret_cast<DT*>(smem);      // the tile's w and u, [3][T]
-  DT* s_wi = s_wr + T;
-  DT* s_u = s_wi + T;
-  double* s_e = reinterpret_cast<double*>(s_u + T);   // FP64 loop: grid rounding e_j, [T]
-  double2* s_tab = reinterpret_cast<double2*>(s_e + T);   // FP64 loop: sin, cos table
+  // The tile's w and u (and on the FP64 path e_j and the sincos table) at a
+  // fixed stride of the largest tile, so that every per-bin read shares one
+  // address register (constant offsets) whatever the tile size.
+  constexpr int TS = MIXED ? kMaxTileMixed : kMaxTileFp64;
+  double2* s_tab = reinterpret_cast<double2*>(smem);      // FP64 loop: sin, cos table
+  DT* s_wr = reinterpret_cast<DT*>(smem + (MIXED ? 0 : kSinTab * sizeof(double2)));
+  DT* s_wi = s_wr + TS;
+  DT* s_u = s_wi + TS;
+  double* s_e = reinterpret_cast<double*>(s_u + TS);     // FP64 loop: grid rounding e_j
   __shared__ int s_unit[3];                       // tile, first item, item count
   __shared__ double s_rec[4][64];                // each wave's current item record
   const DT* gwr;
@@ -2152,7 +2156,7 @@ void launch_worklist(int64_t m, const WorkSpace& ws, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(nblk(m, 256)), dim3(256), 0, s, ws.cnt, ws.off, m, ws.items);
 }
 
-int interp_max_tile(bool mixed) { return mixed ? 4096 : 2048; }
+int interp_max_tile(bool mixed) { return mixed ? kMaxTileMixed : kMaxTileFp64; }
 
 void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
                  int64_t n_particles, int32_t stride, int32_t chunk, const WorkSpace& ws,
@@ -2178,9 +2182,9 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
                          ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.xerr, ws.direct,
                          ws.ndirect, um, ws.partials);
     }
-    // w, u (and e_j and the sincos table on the FP64 path) of one tile
-    const size_t lds = mixed ? (size_t)chunk * 3 * sizeof(float)
-                             : (size_t)chunk * 4 * sizeof(double) + kSinTab * sizeof(double2);
+    // w, u (and e_j and the sincos table on the FP64 path) at the largest tile's stride
+    const size_t lds = mixed ? (size_t)kMaxTileMixed * 3 * sizeof(float)
+                             : (size_t)kMaxTileFp64 * 4 * sizeof(double) + kSinTab * sizeof(double2);
     if (ev_main) (void)hipEventRecord(ev_main[0], s);
     if (mixed)
       hipLaunchKernelGGL(k_eval_interp<true>, dim3(blocks), dim3(256), lds, s, g, ws.bounds, stride,
