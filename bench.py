@@ -44,14 +44,14 @@ def _peak_tflops(kind):
 # bytes read per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes
 # written per launch (WRITE_SIZE).
 MAIN_KERNEL = {"fp64": "k_eval_interp<false>", "mixed": "k_eval_interp<true>"}
-FLOP_PER_BIN = {"fp64": 124.69, "mixed": 65.99}      # FP64 + FP32
+FLOP_PER_BIN = {"fp64": 91.54, "mixed": 65.98}      # FP64 + FP32
 FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 39.18}      # of which FP32
-VALU_PER_BIN = {"fp64": 91.97, "mixed": 52.21}
+VALU_PER_BIN = {"fp64": 74.71, "mixed": 51.12}
 VALU32_PER_BIN = {"fp64": 0.01, "mixed": 25.12}      # of which FP32 arithmetic
-TRAFFIC = {"fp64": (0.5130, 6.651e7), "mixed": (0.2776, 3.779e7)}
+TRAFFIC = {"fp64": (0.5131, 6.642e7), "mixed": (0.2777, 3.776e7)}
 # sha256 of the kernel sources those counters were taken on; the figures are
 # reported as null once the sources differ.
-COUNTERS_SRC_SHA = "9a4d66bebc2cb5efcb9f6e96a75666e2588837b7dfd215a775351f2dbb165752"
+COUNTERS_SRC_SHA = "df8a39e07f388d161a594c663455fe44cd0077267e5d0a02f7c5351eebf74498"
 KERNEL_SOURCES = ("fstat_kernels.hip", "fstat_internal.h", "fstat_kernels.h")
 
 
