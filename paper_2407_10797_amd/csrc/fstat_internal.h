@@ -347,6 +347,45 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
   return d;
 }
 
+// sin(2 pi r), cos(2 pi r) for |r| < 2^22 turns: r = n / kSinTab + x with x
+// exact and |x| <= 1 / (2 kSinTab); the coarse factor from the LDS table, the
+// fine one from short Taylor series (sin to theta^5, cos to theta^6:
+// remainders below 1e-19 for |theta| <= pi / kSinTab), combined by the
+// angle-addition formulas.  In the bin loop |r| stays below ~1e4 turns (the
+// item's start phase is below one turn, the linear term below half a turn
+// per bin, the residual a few hundred turns at most).
+constexpr int kSinTab = 512;
+__device__ __forceinline__ void sincos_tab(double r, const double2* tab, double& s, double& c) {
+  const double n = rint(r * (double)kSinTab);
+  const double x = fma(-1.0 / (double)kSinTab, n, r);
+  const double2 e = tab[(int)n & (kSinTab - 1)];
+  const double th = x * 6.283185307179586477;
+  const double z = th * th;
+  const double ps = fma3(1.0 / 120.0, z, -1.0 / 6.0);
+  const double pc = fma(fma3(-1.0 / 720.0, z, 1.0 / 24.0), z, -0.5);
+  const double sl = fma(th * z, ps, th);
+  const double cl = fma(z, pc, 1.0);
+  s = fma(e.x, cl, e.y * sl);
+  c = fma(e.y, cl, -(e.x * sl));
+}
+
+// (sin, cos)(2 pi k / kSinTab) into a block's LDS table; every thread of the
+// block calls it (it ends with a block barrier).
+__device__ __forceinline__ void fill_sincos_table(double2* tab) {
+  for (int k = threadIdx.x; k < kSinTab; k += blockDim.x) {
+    double sv, cv;
+    sincospi(2.0 * (double)k / (double)kSinTab, &sv, &cv);
+    tab[k] = make_double2(sv, cv);
+  }
+  __syncthreads();
+}
+
+// sin(pi x), cos(pi x): from the table when one is given, else the library.
+__device__ __forceinline__ void sincospi_t(double x, const double2* tab, double* s, double* c) {
+  if (tab) sincos_tab(0.5 * x, tab, *s, *c);
+  else sincospi(x, s, c);
+}
+
 // hardware reciprocal / reciprocal square root seeds refined by two Newton
 // steps (accurate to about one ulp)
 __device__ __forceinline__ double rcp_nr(double x) {
@@ -403,7 +442,7 @@ __device__ __forceinline__ void channel_weights(int code, double w[3]) {
 __device__ __forceinline__ void michelson_fp64(const PartConst& P, double f, double s0, double c0,
                                                const double d[3][3], int a, double& tpr,
                                                double& tpi, double& txr, double& txi,
-                                               bool table = false) {
+                                               bool table = false, const double2* tab = nullptr) {
   const double kx = P.k[0], ky = P.k[1], kz = P.k[2];
   const double x0 = kPi * kLs * f;
   const double zr = c0 * c0 - s0 * s0, zi = -2.0 * s0 * c0;   // z = e^{-2 i x0}
@@ -419,7 +458,7 @@ __device__ __forceinline__ void michelson_fp64(const PartConst& P, double f, dou
     double un = P.u[0] * ax + P.u[1] * ay + P.u[2] * az;
     double vn = P.v[0] * ax + P.v[1] * ay + P.v[2] * az;
     double sq, cq;
-    sincospi(kLs * f * kn, &sq, &cq);
+    sincospi_t(kLs * f * kn, tab, &sq, &cq);
     double np_ = s0 * cq + c0 * sq, nm = s0 * cq - c0 * sq;   // sin(x0 (1 +- kn))
     double dp = x0 * (1.0 + kn), dm = x0 * (1.0 - kn);
     double sp, sm;
@@ -434,7 +473,7 @@ __device__ __forceinline__ void michelson_fp64(const PartConst& P, double f, dou
     double Sr = sp + zr * sm, Si = zi * sm;
     if (table) {   // link phase from the arm vector: rotate by exp(-i pi f kn (|d| - L))
       double se, ce;
-      sincospi(f * kn * (r2 * inv - kLs), &se, &ce);
+      sincospi_t(f * kn * (r2 * inv - kLs), tab, &se, &ce);
       const double tr = sq * ce + cq * se, tc = cq * ce - sq * se;
       sq = tr;
       cq = tc;
@@ -451,7 +490,7 @@ __device__ __forceinline__ void michelson_fp64(const PartConst& P, double f, dou
   if (a != 0) {
     const double kd = kx * (d[a][0] - d[0][0]) + ky * (d[a][1] - d[0][1]) + kz * (d[a][2] - d[0][2]);
     double sv, cv;
-    sincospi(2.0 * f * kd, &sv, &cv);          // e^{-i 2 pi f kd} = cv - i sv
+    sincospi_t(2.0 * f * kd, tab, &sv, &cv);   // e^{-i 2 pi f kd} = cv - i sv
     const double r0 = pr * cv + pi * sv, i0 = pi * cv - pr * sv;
     const double r1 = xr * cv + xi * sv, i1 = xi * cv - xr * sv;
     pr = r0; pi = i0; xr = r1; xi = i1;
@@ -463,7 +502,7 @@ __device__ __forceinline__ void michelson_fp64(const PartConst& P, double f, dou
 __device__ __forceinline__ void response_ch_fp64(const PartConst& P, double f, double s0, double c0,
                                                  const double d[3][3], int code, double& tpr,
                                                  double& tpi, double& txr, double& txi,
-                                                 bool table = false) {
+                                                 bool table = false, const double2* tab = nullptr) {
   double w[3];
   channel_weights(code, w);
   tpr = tpi = txr = txi = 0.0;
@@ -473,7 +512,7 @@ __device__ __forceinline__ void response_ch_fp64(const PartConst& P, double f, d
   for (int a = 0; a < 3; ++a) {
     if (w[a] == 0.0) continue;
     double pr, pi, xr, xi;
-    michelson_fp64(P, f, s0, c0, d, a, pr, pi, xr, xi, table);
+    michelson_fp64(P, f, s0, c0, d, a, pr, pi, xr, xi, table, tab);
     tpr = fma(w[a], pr, tpr); tpi = fma(w[a], pi, tpi);
     txr = fma(w[a], xr, txr); txi = fma(w[a], xi, txi);
   }
@@ -550,7 +589,8 @@ __device__ __forceinline__ void template_fp64(const PartConst& P, double f, doub
                                               double& cph, double& sph, double& tpr,
                                               double& tpi, double& txr, double& txi,
                                               const double* ek = nullptr, int code = 0,
-                                              const OrbitTable* orb = nullptr) {
+                                              const OrbitTable* orb = nullptr,
+                                              const double2* tab = nullptr) {
   double fr, tf;
   phase_and_tf(P, f, fr, tf, ek);
   double d[3][3];
@@ -559,13 +599,13 @@ __device__ __forceinline__ void template_fp64(const PartConst& P, double f, doub
     kp1 = k_dot_p1_table(P, *orb, tf, 0.0, d);
   } else {
     double sa, ca;
-    sincospi(2.0 * tf * (1.0 / kYear), &sa, &ca);
+    sincospi_t(2.0 * tf * (1.0 / kYear), tab, &sa, &ca);
     kp1 = k_dot_p1(P, ca, sa, d);
   }
   double ph = fr + f * kp1;               // Phi / (2 pi) in cycles
   ph -= rint(ph);
-  sincospi(2.0 * ph, &sph, &cph);
-  response_ch_fp64(P, f, s0, c0, d, code, tpr, tpi, txr, txi, orb && orb->coef);
+  sincospi_t(2.0 * ph, tab, &sph, &cph);
+  response_ch_fp64(P, f, s0, c0, d, code, tpr, tpi, txr, txi, orb && orb->coef, tab);
 }
 
 // The template at an arbitrary frequency fd (double-double; an interpolation
@@ -573,7 +613,8 @@ __device__ __forceinline__ void template_fp64(const PartConst& P, double f, doub
 // (double-double, not reduced) and the transfer without the Doppler factor.
 __device__ __forceinline__ dd template_node(const PartConst& P, dd fd, const double* ek,
                                             double& tpr, double& tpi, double& txr, double& txi,
-                                            int code = 0, const OrbitTable* orb = nullptr) {
+                                            int code = 0, const OrbitTable* orb = nullptr,
+                                            const double2* tab = nullptr) {
   dd tf;
   dd ph = phase_full(P, fd, tf, ek);
   const double f = fd.hi;
@@ -586,13 +627,13 @@ __device__ __forceinline__ dd template_node(const PartConst& P, dd fd, const dou
     {
       FSTAT_NO_CONTRACT
       const dd turns = dd_mul_d(tf, 1.0 / kYear);     // orbit angle in turns, reduced exactly
-      sincospi(2.0 * ((turns.hi - floor(turns.hi)) + turns.lo), &sa, &ca);
+      sincospi_t(2.0 * ((turns.hi - floor(turns.hi)) + turns.lo), tab, &sa, &ca);
     }
     kp1 = k_dot_p1(P, ca, sa, d);
   }
   double s0, c0;
-  sincospi(kLs * f, &s0, &c0);
-  response_ch_fp64(P, f, s0, c0, d, code, tpr, tpi, txr, txi, orb && orb->coef);
+  sincospi_t(kLs * f, tab, &s0, &c0);
+  response_ch_fp64(P, f, s0, c0, d, code, tpr, tpi, txr, txi, orb && orb->coef, tab);
   return dd_add(ph, dd_mul_d(fd, kp1));
 }
 

@@ -400,6 +400,8 @@ __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  __shared__ double2 s_tab[kSinTab];              // coarse angles of the template's sin/cos
+  fill_sincos_table(s_tab);
   // all items, or only those listed in sel (the interpolating kernel's rejects)
   const int W = sel ? nsel[0] : total[0];
   for (int iw = wave; iw < W; iw += nwaves) {
@@ -425,7 +427,8 @@ __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
     for (int j = b0 + lane; j < b1; j += 64) {
       double f = bin_freq(g, j);
       double cps, sps, tpr, tpi, txr, txi;
-      template_fp64(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq, code, &g.orb);
+      template_fp64(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq, code, &g.orb,
+                    s_tab);
       double a = wr[co + j], b = wi[co + j], uu = u[co + j];
       double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
       double t[8];
@@ -809,28 +812,6 @@ __device__ __forceinline__ double estrin_d(const double* c, double s, double s2,
 // FP64 loop evaluates the transfer interpolants at (5, 7 or 9).
 constexpr int kRec = 5 * kCheb + 5;
 static_assert(kRec == kInterpRec && kRec <= 64, "record layout");
-// sin(2 pi r), cos(2 pi r) for |r| < 2^22 turns: r = n / kSinTab + x with x
-// exact and |x| <= 1 / (2 kSinTab); the coarse factor from the LDS table, the
-// fine one from short Taylor series (sin to theta^5, cos to theta^6:
-// remainders below 1e-19 for |theta| <= pi / kSinTab), combined by the
-// angle-addition formulas.  In the bin loop |r| stays below ~1e4 turns (the
-// item's start phase is below one turn, the linear term below half a turn
-// per bin, the residual a few hundred turns at most).
-constexpr int kSinTab = 512;
-__device__ __forceinline__ void sincos_tab(double r, const double2* tab, double& s, double& c) {
-  const double n = rint(r * (double)kSinTab);
-  const double x = fma(-1.0 / (double)kSinTab, n, r);
-  const double2 e = tab[(int)n & (kSinTab - 1)];
-  const double th = x * 6.283185307179586477;
-  const double z = th * th;
-  const double ps = fma3(1.0 / 120.0, z, -1.0 / 6.0);
-  const double pc = fma(fma3(-1.0 / 720.0, z, 1.0 / 24.0), z, -0.5);
-  const double sl = fma(th * z, ps, th);
-  const double cl = fma(z, pc, 1.0);
-  s = fma(e.x, cl, e.y * sl);
-  c = fma(e.y, cl, -(e.x * sl));
-}
-
 template <bool MIXED> struct RecLayout {
   static constexpr int nT = MIXED ? kDegT + 1 : kCheb;
   static constexpr int tail = kCheb + 4 * nT;   // A, B', B, M-by-quadrature flag
@@ -958,6 +939,8 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  __shared__ double2 s_tab[kSinTab];              // coarse angles of the template's sin/cos
+  fill_sincos_table(s_tab);
   const int W = total[0];
   const int G = (W + kItemsWave - 1) / kItemsWave;
   const int q = min(lane / kLanesItem, kItemsWave - 1);
@@ -981,7 +964,7 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     const dd f = dd_add(two_prod((double)(g.k_lo + b0), g.df), two_prod(mk, g.df));
     double v[5], v0lo;
     const dd ph = template_node(P, f, ekq, v[1], v[2], v[3], v[4], g.chan.code[ch],
-                                TAB ? &g.orb : nullptr);
+                                TAB ? &g.orb : nullptr, s_tab);
     const double p0h = __shfl(ph.hi, base + kCheb, 64);
     const double p0l = __shfl(ph.lo, base + kCheb, 64);
     const double peh = __shfl(ph.hi, base + kCheb + 1, 64);
@@ -1090,6 +1073,7 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     double errt[2] = {0.0, 0.0};   // transfer error of the degree-5 and -7 truncations
     if (k >= kCheb) {
       const double* e = (k == kCheb) ? emin : eplu;
+      const double itmax = 1.0 / tmax;      // the estimates below need no correct rounding
       const dd eR = (k == kCheb) ? eRm : eRp;
       const double eRx = (k == kCheb) ? eRmx : eRpx;
       const dd dR = dd_add(eR, dd{-v[0], -v0lo});
@@ -1100,12 +1084,12 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
       for (int fn = 1; fn < 5; ++fn) {
         const double d = fabs(e[fn] - v[fn]);
         bad = bad || !(d <= tolT * tmax);
-        err = fmax(err, d / tmax);
+        err = fmax(err, d * itmax);
         if constexpr (!MIXED) {
 #pragma unroll
           for (int v2 = 0; v2 < 2; ++v2) {
             const double et = (k == kCheb) ? etm[v2][fn - 1] : etp[v2][fn - 1];
-            errt[v2] = fmax(errt[v2], fabs(et - v[fn]) / tmax);
+            errt[v2] = fmax(errt[v2], fabs(et - v[fn]) * itmax);
           }
         }
       }
@@ -1212,14 +1196,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
   const int wv = threadIdx.x >> 6;
   const int nwv = blockDim.x >> 6;
   const int nunits = unit_off[ntiles];
-  if constexpr (!MIXED) {
-    // (sin, cos)(2 pi k / kSinTab): the coarse factor of the bin loop's sincos
-    for (int k = threadIdx.x; k < kSinTab; k += blockDim.x) {
-      double sv, cv;
-      sincospi(2.0 * (double)k / (double)kSinTab, &sv, &cv);
-      s_tab[k] = make_double2(sv, cv);
-    }
-  }                                     // (the unit fetch below synchronises the block)
+  if constexpr (!MIXED) fill_sincos_table(s_tab);
   for (;;) {
     // next unit (dynamic): up to kUnitItems items of one tile
     if (threadIdx.x == 0) {
