@@ -166,8 +166,10 @@ __host__ __device__ __forceinline__ void phase_and_tf(const PartConst& P, double
   double c_ft = (ft.hi - floor(ft.hi)) + ft.lo;
   dd x = dd_mul_d(dd{P.mc_hi, P.mc_lo}, f);
   double lx = log(x.hi);
-  // y = x^{-1/3}: y0 ~ 1 ulp, then one Newton step on x y^3 = 1
-  double y0 = exp(lx * (-1.0 / 3.0));
+  // y = x^{-1/3}: y0 within a few ulp (the cube of w0 = x^{-1/9}, which the
+  // eccentric term needs anyway), then one Newton step on x y^3 = 1
+  const double w0 = ek ? 0.0 : exp(lx * (-1.0 / 9.0));
+  double y0 = ek ? exp(lx * (-1.0 / 3.0)) : w0 * w0 * w0;
   dd b = dd_mul(dd_mul_d(two_prod(y0, y0), y0), x);
   double r = (1.0 - b.hi) - b.lo;
   dd y = quick_two_sum(y0, y0 * r * (1.0 / 3.0));
@@ -182,8 +184,7 @@ __host__ __device__ __forceinline__ void phase_and_tf(const PartConst& P, double
   if (ek) {
     te = dd{knot_interp(ek, f), 0.0};
   } else {
-    // w = y^{1/3}: estimate, then one Newton step on w^3 = y
-    double w0 = exp(lx * (-1.0 / 9.0));
+    // w = y^{1/3}: estimate w0, then one Newton step on w^3 = y
     dd w3 = dd_mul_d(two_prod(w0, w0), w0);
     double rw = ((y.hi - w3.hi) + (y.lo - w3.lo)) * xy2;
     dd w = quick_two_sum(w0, w0 * rw * (1.0 / 3.0));
@@ -213,7 +214,8 @@ __host__ __device__ __forceinline__ dd phase_full(const PartConst& P, dd f, dd& 
   dd ft = dd_mul_d(f, P.tc);
   dd x = dd_mul(dd{P.mc_hi, P.mc_lo}, f);
   double lx = log(x.hi);
-  double y0 = exp(lx * (-1.0 / 3.0));
+  const double w0 = ek ? 0.0 : exp(lx * (-1.0 / 9.0));   // as in phase_and_tf
+  double y0 = ek ? exp(lx * (-1.0 / 3.0)) : w0 * w0 * w0;
   dd b = dd_mul(dd_mul_d(two_prod(y0, y0), y0), x);
   double r = (1.0 - b.hi) - b.lo;
   dd y = quick_two_sum(y0, y0 * r * (1.0 / 3.0));
@@ -228,7 +230,6 @@ __host__ __device__ __forceinline__ dd phase_full(const PartConst& P, dd f, dd& 
   if (ek) {
     te = dd{knot_interp(ek, f.hi), 0.0};
   } else {
-    double w0 = exp(lx * (-1.0 / 9.0));
     dd w3 = dd_mul_d(two_prod(w0, w0), w0);
     double rw = ((y.hi - w3.hi) + (y.lo - w3.lo)) * xy2;
     dd w = quick_two_sum(w0, w0 * rw * (1.0 / 3.0));
