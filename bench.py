@@ -48,10 +48,10 @@ FLOP_PER_BIN = {"fp64": 91.54, "mixed": 65.98}      # FP64 + FP32
 FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 39.18}      # of which FP32
 VALU_PER_BIN = {"fp64": 74.71, "mixed": 51.12}
 VALU32_PER_BIN = {"fp64": 0.01, "mixed": 25.12}      # of which FP32 arithmetic
-TRAFFIC = {"fp64": (0.5131, 6.642e7), "mixed": (0.2777, 3.776e7)}
+TRAFFIC = {"fp64": (0.5120, 6.641e7), "mixed": (0.2778, 3.776e7)}
 # sha256 of the kernel sources those counters were taken on; the figures are
 # reported as null once the sources differ.
-COUNTERS_SRC_SHA = "df8a39e07f388d161a594c663455fe44cd0077267e5d0a02f7c5351eebf74498"
+COUNTERS_SRC_SHA = "d71c88e802c678399ed6c8937e0684735efe5c6b7eb2a7d0841086888f0b6039"
 KERNEL_SOURCES = ("fstat_kernels.hip", "fstat_internal.h", "fstat_kernels.h")
 
 
