@@ -432,9 +432,15 @@ class Plan:
         if nodes is None:
             fstat_plan_set_orbit(self.handle, 0.0, 1.0, 0, None, 0, _stream())
             return
-        nd = np.ascontiguousarray(nodes, dtype=np.float64)
-        if nd.ndim != 4 or nd.shape[1:] != (3, 3, 10):
+        if tuple(nodes.shape[1:]) != (3, 3, 10) or len(nodes.shape) != 4:
             raise ValueError("nodes must be [n_seg, 3, 3, 10]")
+        if hasattr(nodes, "is_cuda") and nodes.is_cuda:       # a device tensor
+            import torch
+            nd = nodes.to(torch.float64).contiguous()
+            fstat_plan_set_orbit(self.handle, t0, dt, nd.shape[0], nd.data_ptr(),
+                                 FSTAT_DEVICE_PTRS, _stream())
+            return
+        nd = np.ascontiguousarray(nodes, dtype=np.float64)
         fstat_plan_set_orbit(self.handle, t0, dt, nd.shape[0], nd.ctypes.data, 0, _stream())
 
     def search(self, desc: fstat_search_desc) -> dict:

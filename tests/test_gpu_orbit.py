@@ -145,6 +145,22 @@ def test_orbit_with_aet_channels(torch_cuda):
     _check(P.cpu().numpy(), Po, cond, 1e-9, 1e-14)
 
 
+def test_orbit_table_from_device_memory(case, torch_cuda):
+    """The same table handed over in device memory gives the same values bit
+    for bit."""
+    s = case
+    x = torch_cuda.from_numpy(s["pts"])
+    nodes = _table(bump=1e-3)
+    try:
+        s["plan"].set_orbit(T0, DT, nodes)
+        Fh = s["plan"].eval(x, 4).cpu().numpy()
+        s["plan"].set_orbit(T0, DT, torch_cuda.from_numpy(nodes).cuda())
+        Fd = s["plan"].eval(x, 4).cpu().numpy()
+    finally:
+        s["plan"].set_orbit()
+    np.testing.assert_array_equal(Fd, Fh)
+
+
 def test_orbit_table_errors(case):
     s = case
     fstat = s["fstat"]
