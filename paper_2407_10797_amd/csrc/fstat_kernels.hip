@@ -21,7 +21,7 @@
 //   k_mark          partitions whose interpolation error could matter -> exact
 //   k_solve         one thread per (particle, partition): ordered sum of the
 //                   item partials and the 2x2 Hermitian closed form of F_l
-//   k_mean          one thread per particle: F_hat = mean_l F_l, or -inf / NaN
+//   k_mean          one wavefront per particle: F_hat = mean_l F_l, or -inf / NaN
 #include "fstat_internal.h"
 #include <type_traits>
 
@@ -383,6 +383,8 @@ __device__ __forceinline__ double wave_sum4(const double* a, int lane, int& idx)
   return d;
 }
 
+constexpr int kSmallItem = 8;   // exact kernel: items this short share a wavefront
+
 __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
                                                    const PartConst* __restrict__ pc,
                                                    const int32_t* __restrict__ bounds, int32_t stride,
@@ -402,52 +404,98 @@ __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
   __shared__ double2 s_tab[kSinTab];              // coarse angles of the template's sin/cos
   fill_sincos_table(s_tab);
-  // all items, or only those listed in sel (the interpolating kernel's rejects)
-  const int W = sel ? nsel[0] : total[0];
-  for (int iw = wave; iw < W; iw += nwaves) {
-    const int w = sel ? sel[iw] : iw;
-    int2 it = items[w];
-    int q = __builtin_amdgcn_readfirstlane(it.x);
-    int c = __builtin_amdgcn_readfirstlane(it.y);
-    int p = q / stride, l = q - p * stride;
+  // The eight partition terms of bin j for the item (q, c) of a particle
+  auto terms = [&](int q, int c, int j, double t[8]) {
+    const int p = q / stride;
     const PartConst& P = pc[p];
+    int ct, ch;
+    item_split(c, g.chan.n, ct, ch);
+    const int64_t co = (int64_t)ch * g.nbins;   // the channel's data
+    const double* ekq = (ek && P.sur) ? ek + 8 * (int64_t)q : nullptr;
+    double f = bin_freq(g, j);
+    double cps, sps, tpr, tpi, txr, txi;
+    template_fp64(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq, g.chan.code[ch],
+                  &g.orb, s_tab);
+    double a = wr[co + j], b = wi[co + j], uu = u[co + j];
+    double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
+    t[0] = Wr * tpr + Wi * tpi;     // Z+ = sum W conj(T'+)
+    t[1] = Wi * tpr - Wr * tpi;
+    t[2] = Wr * txr + Wi * txi;     // Zx
+    t[3] = Wi * txr - Wr * txi;
+    t[4] = uu * (tpr * tpr + tpi * tpi);
+    t[5] = uu * (txr * txr + txi * txi);
+    t[6] = uu * (tpr * txr + tpi * txi);   // R = sum u T'+ conj(T'x)
+    t[7] = uu * (tpi * txr - tpr * txi);
+  };
+  auto bins_of = [&](int w, int& q, int& c, int& b0, int& b1) {
+    const int2 it = items[w];
+    q = it.x;
+    c = it.y;
+    const int p = q / stride, l = q - p * stride;
     const int32_t* bp = bounds + (int64_t)p * (stride + 1);
     int ct, ch;
     item_split(c, g.chan.n, ct, ch);
-    const int code = g.chan.code[ch];
-    const int64_t co = (int64_t)ch * g.nbins;   // the channel's data
-    int b0, b1;
     item_bins(bp[l], bp[l + 1], ct, chunk, b0, b1);
-    const double* ekq = (ek && P.sur) ? ek + 8 * (int64_t)q : nullptr;
-    // Kahan-compensated per-lane sums (true sum ~ acc - cmp): the partition
-    // matrix can have cond ~ 1e5..1e8, which amplifies summation error.
-    double acc[8], cmp[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] = cmp[i] = 0.0;
-    for (int j = b0 + lane; j < b1; j += 64) {
-      double f = bin_freq(g, j);
-      double cps, sps, tpr, tpi, txr, txi;
-      template_fp64(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq, code, &g.orb,
-                    s_tab);
-      double a = wr[co + j], b = wi[co + j], uu = u[co + j];
-      double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
-      double t[8];
-      t[0] = Wr * tpr + Wi * tpi;     // Z+ = sum W conj(T'+)
-      t[1] = Wi * tpr - Wr * tpi;
-      t[2] = Wr * txr + Wi * txi;     // Zx
-      t[3] = Wi * txr - Wr * txi;
-      t[4] = uu * (tpr * tpr + tpi * tpi);
-      t[5] = uu * (txr * txr + txi * txi);
-      t[6] = uu * (tpr * txr + tpi * txi);   // R = sum u T'+ conj(T'x)
-      t[7] = uu * (tpi * txr - tpr * txi);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) kahan_add(acc[i], cmp[i], t[i]);
+  };
+  // all items, or only those listed in sel (the interpolating kernel's rejects),
+  // in groups of eight: an item of at most kSmallItem bins takes eight lanes of
+  // the wavefront (one bin each, then a fixed three-step butterfly), a larger
+  // one the whole wavefront.  Which path an item takes depends on the item
+  // alone, so its sums do not depend on the order of the list.
+  const int W = sel ? nsel[0] : total[0];
+  const int G = (W + 7) >> 3;
+  for (int gi = wave; gi < G; gi += nwaves) {
+    const int slot = gi * 8 + (lane >> 3);
+    const bool have = slot < W;
+    int w = 0, q = 0, c = 0, b0 = 0, b1 = 0;
+    if (have) {
+      w = sel ? sel[slot] : slot;
+      bins_of(w, q, c, b0, b1);
     }
+    const bool small = have && b1 - b0 <= kSmallItem;
+    {
+      double t[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] -= cmp[i];
-    int idx;
-    const double tot = wave_sum8(acc, lane, idx);
-    if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
+      for (int i = 0; i < 8; ++i) t[i] = 0.0;
+      const int j = b0 + (lane & 7);
+      if (small && j < b1) terms(q, c, j, t);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        t[i] += __shfl_xor(t[i], 4, 64);
+        t[i] += __shfl_xor(t[i], 2, 64);
+        t[i] += __shfl_xor(t[i], 1, 64);
+      }
+      if (small && (lane & 7) == 0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = t[i];
+      }
+    }
+    uint64_t big = __ballot(have && !small && (lane & 7) == 0);
+    while (big) {
+      const int src = __ffsll((long long)big) - 1;
+      big &= big - 1;
+      const int wb = __builtin_amdgcn_readfirstlane(__shfl(w, src, 64));
+      int qb, cb, bb0, bb1;
+      bins_of(wb, qb, cb, bb0, bb1);
+      qb = __builtin_amdgcn_readfirstlane(qb);
+      cb = __builtin_amdgcn_readfirstlane(cb);
+      // Kahan-compensated per-lane sums (true sum ~ acc - cmp): the partition
+      // matrix can have cond ~ 1e5..1e8, which amplifies summation error.
+      double acc[8], cmp[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[i] = cmp[i] = 0.0;
+      for (int j = bb0 + lane; j < bb1; j += 64) {
+        double tt[8];
+        terms(qb, cb, j, tt);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) kahan_add(acc[i], cmp[i], tt[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[i] -= cmp[i];
+      int idx;
+      const double tot = wave_sum8(acc, lane, idx);
+      if ((lane & 7) == 0) partials[(int64_t)wb * 8 + idx] = tot;
+    }
   }
 }
 
@@ -1968,16 +2016,19 @@ __global__ void k_solve(const PartConst* __restrict__ pc, int64_t n, int32_t str
     for (int k = 0; k < 4; ++k) amps[(p * part_stride + l) * 4 + k] = am[k];
 }
 
+// One wavefront per particle: lanes take every 64th partition, then a fixed
+// butterfly (the result does not depend on the launch).
 __global__ void k_mean(const PartConst* __restrict__ pc, int64_t n, int32_t stride,
                        const double* __restrict__ Fl, double* __restrict__ F_hat,
                        double* __restrict__ F_part, int64_t part_stride,
                        double* __restrict__ amps, unsigned long long* __restrict__ bin_counter) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (p >= n) return;
   const PartConst& P = pc[p];
   if (P.status == kStatusInvalid) {
-    F_hat[p] = __builtin_nan("");
-    for (int l = 0; l < P.np && l < part_stride; ++l) {
+    if (lane == 0) F_hat[p] = __builtin_nan("");
+    for (int l = lane; l < P.np && l < part_stride; l += 64) {
       if (F_part) F_part[p * part_stride + l] = __builtin_nan("");
       if (amps)
         for (int k = 0; k < 4; ++k) amps[(p * part_stride + l) * 4 + k] = __builtin_nan("");
@@ -1985,13 +2036,17 @@ __global__ void k_mean(const PartConst* __restrict__ pc, int64_t n, int32_t stri
     return;
   }
   if (P.status == kStatusEmpty) {
-    F_hat[p] = -__builtin_inf();
+    if (lane == 0) F_hat[p] = -__builtin_inf();
     return;
   }
   double s = 0.0;
-  for (int l = 0; l < P.np; ++l) s += Fl[p * stride + l];
-  F_hat[p] = s / (double)P.np;
-  if (bin_counter) atomicAdd(bin_counter, (unsigned long long)(P.j_hi - P.j_lo + 1));
+  for (int l = lane; l < P.np; l += 64) s += Fl[p * stride + l];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) {
+    F_hat[p] = s / (double)P.np;
+    if (bin_counter) atomicAdd(bin_counter, (unsigned long long)(P.j_hi - P.j_lo + 1));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2206,7 +2261,7 @@ void launch_solve_mean(int64_t n, int32_t stride, const WorkSpace& ws, double* F
   int64_t m = n * stride;
   hipLaunchKernelGGL(k_solve, dim3(nblk(m, 256)), dim3(256), 0, s, ws.pc, n, stride, ws.cnt,
                      ws.off, ws.partials, ws.Fl, F_part, part_stride, amps, umax);
-  hipLaunchKernelGGL(k_mean, dim3(nblk(n, 256)), dim3(256), 0, s, ws.pc, n, stride, ws.Fl, F_hat,
+  hipLaunchKernelGGL(k_mean, dim3(nblk(n * 64, 256)), dim3(256), 0, s, ws.pc, n, stride, ws.Fl, F_hat,
                      F_part, part_stride, amps, bin_counter);
 }
 
