@@ -108,3 +108,37 @@ def test_paper_scale_sampled_parity(paper, torch_cuda):
     assert np.all(rm <= 1e-4 + 1e-6 * c)
     # the injection stands out: 2 F_hat Np ~ rho^2 (+ noise) at the true parameters
     assert F[0] * 64 * 2 > 0.5 * s["snr"] ** 2
+
+
+def test_paper_scale_numerical_orbit_sampled_parity(paper, torch_cuda):
+    """The same batch with a tabulated Keplerian orbit (76 segments of 2^20 s,
+    as the benchmark's orbit lines): sampled particles recomputed by the
+    oracle on the same table."""
+    s = paper
+    g = s["g"]
+    dt = 2.0 ** 20
+    nseg = int(np.ceil((g.T_obs + 0.5 * dt) / dt))
+    nodes = S.kepler_orbit_nodes(-0.5 * dt, dt, nseg)
+    print(f"[paper] Kepler orbit table, {nseg} segments", flush=True)
+    s["plan"].set_orbit(-0.5 * dt, dt, nodes)
+    try:
+        F, P = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), 64, want_parts=True)
+        Fm, Pm = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), 64, mixed=True, want_parts=True)
+    finally:
+        s["plan"].set_orbit()
+    F, P, Fm, Pm = (t.cpu().numpy() for t in (F, P, Fm, Pm))
+    idx = np.array([0, 3, 777, 2222, 4000])
+    try:
+        O.set_orbit(-0.5 * dt, dt, nodes)
+        Fo, Po, cond = O.fstat(s["data"], s["psd"], g.k_lo, g.df, g.T_obs, s["pts"][idx], [64],
+                               want_cond=True)
+    finally:
+        O.set_orbit(None)
+    c = np.where(np.isfinite(cond), cond, 0.0)
+    r64 = _rel(P[idx], Po)
+    rm = _rel(Pm[idx], Po)
+    print(f"  fp64 max rel {r64.max():.2e}, mixed max rel {rm.max():.2e}, max cond {c.max():.2e}",
+          flush=True)
+    assert np.all(r64 <= 1e-9 + 1e-14 * c)
+    assert np.all(_rel(F[idx], Fo) <= 1e-9 + 1e-14 * c.max(axis=1))
+    assert np.all(rm <= 1e-4 + 1e-6 * c)
