@@ -179,3 +179,28 @@ def test_paper_scale_aet_sampled_parity(paper, torch_cuda):
     assert np.all(r64 <= 1e-9 + 1e-14 * c)
     assert np.all(_rel(F[idx], Fo) <= 1e-9 + 1e-14 * c.max(axis=1))
     assert np.all(rm <= 1e-4 + 1e-6 * c)
+
+
+def test_paper_scale_coherent_amplitudes_and_extrinsics(paper, torch_cuda):
+    """Fully coherent statistic (Np = 1, the last search stage) at paper scale:
+    amplitudes of sampled particles against the oracle's, and the extrinsic
+    parameters of the injection's amplitudes round-trip through the forward
+    map."""
+    from oracle import extrinsic as X
+    from paper_2407_10797_amd import fstat
+    s = paper
+    g = s["g"]
+    F, P, A = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), 1, want_parts=True, want_amps=True)
+    A = A.cpu().numpy()
+    idx = np.array([0, 9, 2048, 4093])
+    Fo, Po, cond, Ao = O.fstat(s["data"], s["psd"], g.k_lo, g.df, g.T_obs, s["pts"][idx], [1],
+                               want_cond=True, want_amps=True)
+    c = np.where(np.isfinite(cond), cond, 0.0)
+    err = np.linalg.norm(A[idx] - Ao, axis=-1)
+    tol = (1e-9 + 1e-12 * c) * np.linalg.norm(Ao, axis=-1)
+    print(f"[paper] coherent amplitudes: max error / tolerance {np.max(err / (tol + 1e-300)):.3f}",
+          flush=True)
+    assert np.all(err <= tol + 1e-300)
+    ext = fstat.extrinsic(A[:1, 0], s["pts"][:1]).cpu().numpy()[0]
+    np.testing.assert_allclose(X.forward(*X.physical(X.inverse(A[0, 0]), s["pts"][0][1])),
+                               X.forward(*ext), rtol=1e-9, atol=1e-12 * np.abs(A[0, 0]).max())
