@@ -1378,14 +1378,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
             double mr[DT + 1], mm[DT + 1];
 #pragma unroll
             for (int k = 0; k <= DT; ++k) mr[k] = mm[k] = 0.0;
-            for (int mi = lane; mi < nb; mi += 64) {
-              const double a = a_n, b = b_n, ej = e_n;
-              {
-                const int nx = e0 + min(mi + 64, last);
-                a_n = s_wr[nx];
-                b_n = s_wi[nx];
-                e_n = s_e[nx];
-              }
+            auto one_bin = [&](int mi, double a, double b, double ej) {
               const double m = (double)mi;
               const double s = fma(alpha, m, -1.0);
               const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
@@ -1393,15 +1386,32 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
               double sps, cps;
               sincos_tab(ph, s_tab, sps, cps);
               const double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
-              const double s3 = s2 * s;
-              const double pw[10] = {1.0, s, s2, s3, s4, s4 * s, s4 * s2, s4 * s3, s8, s8 * s};
+              // even moments from W, odd ones from W s, both against even powers
+              const double Vr = Wr * s, Vi = Wi * s;
+              const double pe[5] = {1.0, s2, s4, s4 * s2, s8};
               mr[0] += Wr;
               mm[0] += Wi;
+              mr[1] += Vr;
+              mm[1] += Vi;
 #pragma unroll
-              for (int k = 1; k <= DT; ++k) {
-                mr[k] = fma(Wr, pw[k], mr[k]);
-                mm[k] = fma(Wi, pw[k], mm[k]);
+              for (int k = 2; k <= DT; ++k) {
+                mr[k] = fma((k & 1) ? Vr : Wr, pe[k >> 1], mr[k]);
+                mm[k] = fma((k & 1) ? Vi : Wi, pe[k >> 1], mm[k]);
               }
+            };
+            // two bins per pass (half the loop control per bin), then at most
+            // one left over per lane
+            int mi = lane;
+            for (; mi + 64 < nb; mi += 128) {
+              const int i1 = e0 + mi, i2 = i1 + 64;
+              const double a1 = s_wr[i1], b1 = s_wi[i1], e1 = s_e[i1];
+              const double a2 = s_wr[i2], b2 = s_wi[i2], e2 = s_e[i2];
+              one_bin(mi, a1, b1, e1);
+              one_bin(mi + 64, a2, b2, e2);
+            }
+            if (mi < nb) {
+              const int i1 = e0 + mi;
+              one_bin(mi, s_wr[i1], s_wi[i1], s_e[i1]);
             }
             double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
