@@ -275,7 +275,7 @@ def main():
                          "the three-stage search")
     ap.add_argument("--search-iters", default="400,400,800",
                     help="PSO iterations of the three search stages (--only search)")
-    ap.add_argument("--search-checkpoint", default="gpurun_out/search.ckpt")
+    ap.add_argument("--search-checkpoint", default="fstat_search.ckpt")
     ap.add_argument("--search-last-stage", type=int, default=3)
     ap.add_argument("--search-resume", action="store_true",
                     help="continue from --search-checkpoint instead of starting afresh")
