@@ -147,11 +147,16 @@ int fstat_eval(fstat_plan_t plan, const double *params, int64_t n, const int32_t
  *          Chebyshev points t = t0 + dt (seg + (1 + s_k)/2),
  *          s_k = cos(pi (k + 1/2) / 10), of each segment of length dt
  * Positions between the points are the degree-9 interpolant of the segment
- * that holds t.  The table must cover [0, T_obs].  The plan converts it to
- * Chebyshev coefficients and keeps its own copy; later fstat_eval,
- * pso_stage and fstat_search calls use it.  n_seg = 0 returns to the analytic
- * orbit.  Flags: FSTAT_DEVICE_PTRS (nodes on the device).  Waits for
- * completion.  EINVAL: coverage, dt <= 0, non-finite values.               */
+ * that holds t (outside the table, the end segment's).  The table must cover
+ * [0, T_obs].  Delays and sinc arguments keep the nominal arm length; the
+ * link phases take the tabulated arm vectors.  The plan converts the table to
+ * Chebyshev coefficients and keeps its own device copy (the caller's buffer
+ * may be reused on return); later fstat_eval, pso_stage and fstat_search
+ * calls on this plan use it (fstat_waveform, which takes no plan, does not).
+ * n_seg = 0 returns to the analytic orbit.  Flags: FSTAT_DEVICE_PTRS (nodes
+ * on the device).  Waits for completion.  Must not overlap an evaluation on
+ * the same plan.  EINVAL: null plan or nodes, n_seg < 0, dt <= 0, coverage,
+ * non-finite values; ENOMEM / HIP errors leave the previous table in place.  */
 int fstat_plan_set_orbit(fstat_plan_t plan, double t0, double dt, int32_t n_seg,
                          const double *nodes, uint32_t flags, void *hip_stream);
 
