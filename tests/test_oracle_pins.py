@@ -91,6 +91,56 @@ def test_eccentric_correction_scaling():
     np.testing.assert_allclose(d1[0] / d1[1], (f[0] / f[1]) ** (-34.0 / 9.0), rtol=1e-9)
 
 
+def test_support_edges_newtonian_closed_form():
+    """Sec. II.B: the support is the range of instantaneous frequencies during
+    [0, T_obs], clipped to the band.  In the Newtonian limit the instantaneous
+    frequency of the quadrupole chirp is f(t) = (5 Mc / (256 (t_c - t)))^{3/8} /
+    (pi Mc) (the chirp whose rate is pinned above); the oracle's edges equal it
+    at t = 0 and t = T_obs, and the signal it injects is nonzero on exactly the
+    bins in between."""
+    O.set_pn_order(0)
+    g = S.grid_small()
+    p = P0.copy(); p[5] = 0.0
+    mpmath.mp.dps = 40
+    mc = mpmath.mpf(p[1]) * mpmath.mpf(MSUN_S)
+    def f_at(t):
+        return float((5 * mc / (256 * (mpmath.mpf(p[0]) - t))) ** (mpmath.mpf(3) / 8) / (mpmath.pi * mc))
+    lo, hi = f_at(0), f_at(mpmath.mpf(g.T_obs))
+    assert g.f_first < lo < hi < g.f_last           # both edges cut by the window
+    so = O.support(p, g.T_obs, g.f_first, g.f_last)
+    assert abs(so[0] - lo) <= 1e-14 * lo and abs(so[1] - hi) <= 1e-14 * hi
+    f = g.freqs()
+    inside = (f >= lo) & (f <= hi)
+    margin = np.min(np.abs(np.concatenate([f - lo, f - hi]))) / g.df
+    assert margin > 1e-6                            # no bin sits on an edge
+    sig = O.signal(p, np.array([1.0, 0.3, -0.2, 0.5]), g.df, g.k_lo, g.nbins, g.T_obs)
+    assert np.array_equal(sig != 0, inside)
+    # a window that starts later cuts the low edge where the chirp then is
+    so2 = O.support(p, g.T_obs, g.f_first, g.f_last)
+    p2 = p.copy(); p2[0] -= 2.0e5
+    lo2 = float((5 * mc / (256 * (mpmath.mpf(p2[0])))) ** (mpmath.mpf(3) / 8) / (mpmath.pi * mc))
+    assert abs(O.support(p2, g.T_obs, g.f_first, g.f_last)[0] - lo2) <= 1e-14 * lo2 and lo2 > so2[0]
+
+
+def test_amplitude_is_spa_of_quadrupole_chirp():
+    """App. A amplitude f^{-7/6}: the stationary-phase amplitude of a chirp
+    whose time-domain amplitude grows as f(t)^{2/3} (quadrupole emission) is
+    proportional to f^{2/3} / sqrt(df/dt) at t = t_f.  At Newtonian order the
+    oracle's templates obey |A^1| / |T+| = const * f^{2/3} sqrt(dt_f/df), with
+    dt_f/df from its own t_f (pinned above to the quadrupole chirp rate): a
+    wrong power of f fails by orders of magnitude over the band."""
+    O.set_pn_order(0)
+    p = P0.copy(); p[5] = 0.0
+    f = np.array([0.0105, 0.015, 0.022, 0.031, 0.047, 0.066, 0.094])
+    t = O.tf(p, f)
+    A = O.basis(p, f)
+    T = O.response(p, f, t)
+    h = f * 1e-5
+    dtdf = (O.tf(p, f + h) - O.tf(p, f - h)) / (2 * h)
+    r = np.abs(A[:, 0]) / np.abs(T[0]) / (f ** (2.0 / 3.0) * np.sqrt(dtdf))
+    assert np.max(r) / np.min(r) - 1.0 < 1e-7, r
+
+
 # ---- detector (Sec. IV) -----------------------------------------------------
 
 def test_orbit_geometry():
