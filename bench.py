@@ -49,18 +49,26 @@ FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 39.18}      # of which FP32
 VALU_PER_BIN = {"fp64": 71.40, "mixed": 51.12}
 VALU32_PER_BIN = {"fp64": 0.01, "mixed": 25.12}      # of which FP32 arithmetic
 TRAFFIC = {"fp64": (0.5123, 6.646e7), "mixed": (0.2776, 3.777e7)}
-# sha256 of the kernel sources those counters were taken on; the figures are
-# reported as null once the sources differ.
-COUNTERS_SRC_SHA = "5a4431441991142415339eb1bfb429702b7d1d1f26c5b99efe7d8d1cb7846e54"
-KERNEL_SOURCES = ("fstat_kernels.hip", "fstat_internal.h", "fstat_kernels.h")
+# sha256 of the main kernel's source (the k_eval_interp template and the two
+# headers it builds on) when those counters were taken; the figures are
+# reported as null once it differs.
+COUNTERS_SRC_SHA = "4505afdcaffc8813ee6238fc44cfb0947e54e6ac17c907dd2dc170e2fa157ac5"
+KERNEL_HEADERS = ("fstat_internal.h", "fstat_kernels.h")
+MAIN_KERNEL_START = "template <bool MIXED>\n__global__ __launch_bounds__(256) void k_eval_interp("
 
 
 def _kernel_sha():
     import hashlib
+    csrc = os.path.join(ROOT, "paper_2407_10797_amd", "csrc")
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2407_10797_amd", "csrc", f), "rb") as fh:
+    for f in KERNEL_HEADERS:
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "fstat_kernels.hip")) as fh:
+        src = fh.read()
+    a = src.index(MAIN_KERNEL_START)
+    b = src.index("\n}\n", a) + 3
+    h.update(src[a:b].encode())
     return h.hexdigest()
 
 

@@ -52,8 +52,9 @@ extern "C" {
 
 /* precision selectors (fstat_opts.precision is a mask of these bits) */
 #define FSTAT_FP64 1   /* everything in FP64                                   */
-#define FSTAT_MIXED 2  /* FP64 phase + SPA time + solve; FP32 response, products
-                          and Kahan-compensated partition sums                */
+#define FSTAT_MIXED 2  /* FP64 phase, SPA time, response and solve; the response
+                          rounded (or interpolated) in FP32, FP32 products and
+                          partition sums of the N-terms                       */
 
 /* flags */
 #define FSTAT_DEVICE_PTRS 1u  /* all array arguments are device pointers    */

@@ -405,9 +405,9 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
     return rc;
   }
   if (!(prec & FSTAT_FP64)) {
-    // the FP64 arrays are only needed to build the FP32 copies
+    // the FP64 data are only needed to build the FP32 copies (the exact mixed
+    // loop keeps sin, cos(pi f L) in FP64 for its FP64 response)
     dev_free(P->b64.wr); dev_free(P->b64.wi); dev_free(P->b64.u);
-    dev_free(P->b64.s0); dev_free(P->b64.c0);
   }
   *out = P;
   return FSTAT_OK;

@@ -16,8 +16,8 @@
 //                   data in LDS, and evaluate the interpolated template at every
 //                   bin of each item: the eight partition sums {Z+, Zx, P, Q, R}
 //                   per item (deterministic, no float atomics)
-//   k_eval_fp64 /   the exact template at every bin, for handed-over items, for
-//   k_eval_mixed    refinement and under FSTAT_EVAL_EXACT
+//   k_eval_exact    the exact template at every bin, for handed-over items, for
+//                   refinement and under FSTAT_EVAL_EXACT (FP64 and mixed)
 //   k_mark          partitions whose interpolation error could matter -> exact
 //   k_solve         one thread per (particle, partition): ordered sum of the
 //                   item partials and the 2x2 Hermitian closed form of F_l
@@ -340,6 +340,12 @@ __device__ __forceinline__ void kahan_add(double& s, double& c, double x) {
   c = (t - s) - y;
   s = t;
 }
+__device__ __forceinline__ void kahan_addf(float& s, float& c, float x) {
+  float y = x - c;
+  float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
 
 // Sums of eight per-lane values over the wavefront in 10 exchanges instead of
 // 8 x 6: each step hands half of the remaining values to the partner lane
@@ -385,26 +391,43 @@ __device__ __forceinline__ double wave_sum4(const double* a, int lane, int& idx)
 
 constexpr int kSmallItem = 8;   // exact kernel: items this short share a wavefront
 
-__global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
-                                                   const PartConst* __restrict__ pc,
-                                                   const int32_t* __restrict__ bounds, int32_t stride,
-                                                   const int2* __restrict__ items,
-                                                   const int32_t* __restrict__ total, int32_t chunk,
-                                                   const double* __restrict__ wr,
-                                                   const double* __restrict__ wi,
-                                                   const double* __restrict__ u,
-                                                   const double* __restrict__ s0a,
-                                                   const double* __restrict__ c0a,
-                                                   const double* __restrict__ ek,
-                                                   double* __restrict__ partials,
-                                                   const int32_t* __restrict__ sel,
-                                                   const int32_t* __restrict__ nsel) {
+// Exact per-bin template loop.  FP64 (MIXED = false): everything in FP64,
+// Kahan-compensated per-lane sums.  Mixed (MIXED = true): the phase, the orbit
+// and the TDI response are evaluated in FP64 exactly as on the FP64 path and
+// rounded once to FP32; the products with the FP32 data and the N-term sums
+// (Z+, Zx) are FP32 with Kahan compensation, the M-terms (P, Q, R) are FP64
+// sums of the rounded response.  The response is not computed in FP32: its
+// sinc factors are formed from sin(x0 (1 +- k.n)) by angle addition and the
+// two arms' contributions are subtracted, and in FP32 both cancel (relative
+// errors of 1e-6..1e-5 for sources near an arm direction), which tilts the
+// (T+, Tx) direction; the statistic amplifies such a tilt by ~sqrt(cond M) in
+// the weak eigen-direction of the short, ill-conditioned partitions this
+// kernel serves.  Rounding a correct response to FP32 tilts it by ~6e-8 only.
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_eval_exact(Grid g,
+                                                    const PartConst* __restrict__ pc,
+                                                    const int32_t* __restrict__ bounds, int32_t stride,
+                                                    const int2* __restrict__ items,
+                                                    const int32_t* __restrict__ total, int32_t chunk,
+                                                    const double* __restrict__ wr,
+                                                    const double* __restrict__ wi,
+                                                    const double* __restrict__ u,
+                                                    const float* __restrict__ wr32,
+                                                    const float* __restrict__ wi32,
+                                                    const float* __restrict__ u32,
+                                                    const double* __restrict__ s0a,
+                                                    const double* __restrict__ c0a,
+                                                    const double* __restrict__ ek,
+                                                    double* __restrict__ partials,
+                                                    const int32_t* __restrict__ sel,
+                                                    const int32_t* __restrict__ nsel) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
   __shared__ double2 s_tab[kSinTab];              // coarse angles of the template's sin/cos
   fill_sincos_table(s_tab);
-  // The eight partition terms of bin j for the item (q, c) of a particle
+  // The eight partition terms of bin j for the item (q, c) of a particle;
+  // on the mixed path t[0..3] are FP32 products (widened).
   auto terms = [&](int q, int c, int j, double t[8]) {
     const int p = q / stride;
     const PartConst& P = pc[p];
@@ -416,16 +439,33 @@ __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
     double cps, sps, tpr, tpi, txr, txi;
     template_fp64(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq, g.chan.code[ch],
                   &g.orb, s_tab);
-    double a = wr[co + j], b = wi[co + j], uu = u[co + j];
-    double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
-    t[0] = Wr * tpr + Wi * tpi;     // Z+ = sum W conj(T'+)
-    t[1] = Wi * tpr - Wr * tpi;
-    t[2] = Wr * txr + Wi * txi;     // Zx
-    t[3] = Wi * txr - Wr * txi;
-    t[4] = uu * (tpr * tpr + tpi * tpi);
-    t[5] = uu * (txr * txr + txi * txi);
-    t[6] = uu * (tpr * txr + tpi * txi);   // R = sum u T'+ conj(T'x)
-    t[7] = uu * (tpi * txr - tpr * txi);
+    if constexpr (MIXED) {
+      const float cf = (float)cps, sf = (float)sps;
+      const float pr = (float)tpr, pi = (float)tpi, xr = (float)txr, xi = (float)txi;
+      const float a = wr32[co + j], b = wi32[co + j];
+      const float Wr = a * cf - b * sf, Wi = a * sf + b * cf;   // w e^{i Phi}
+      t[0] = (double)(Wr * pr + Wi * pi);
+      t[1] = (double)(Wi * pr - Wr * pi);
+      t[2] = (double)(Wr * xr + Wi * xi);
+      t[3] = (double)(Wi * xr - Wr * xi);
+      tpr = pr; tpi = pi; txr = xr; txi = xi;     // M-terms from the same rounded response
+      const double uu = (double)u32[co + j];
+      t[4] = uu * (tpr * tpr + tpi * tpi);
+      t[5] = uu * (txr * txr + txi * txi);
+      t[6] = uu * (tpr * txr + tpi * txi);
+      t[7] = uu * (tpi * txr - tpr * txi);
+    } else {
+      double a = wr[co + j], b = wi[co + j], uu = u[co + j];
+      double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
+      t[0] = Wr * tpr + Wi * tpi;     // Z+ = sum W conj(T'+)
+      t[1] = Wi * tpr - Wr * tpi;
+      t[2] = Wr * txr + Wi * txi;     // Zx
+      t[3] = Wi * txr - Wr * txi;
+      t[4] = uu * (tpr * tpr + tpi * tpi);
+      t[5] = uu * (txr * txr + txi * txi);
+      t[6] = uu * (tpr * txr + tpi * txi);   // R = sum u T'+ conj(T'x)
+      t[7] = uu * (tpi * txr - tpr * txi);
+    }
   };
   auto bins_of = [&](int w, int& q, int& c, int& b0, int& b1) {
     const int2 it = items[w];
@@ -482,263 +522,37 @@ __global__ __launch_bounds__(256) void k_eval_fp64(Grid g,
       // Kahan-compensated per-lane sums (true sum ~ acc - cmp): the partition
       // matrix can have cond ~ 1e5..1e8, which amplifies summation error.
       double acc[8], cmp[8];
+      float accf[4], cmpf[4];
 #pragma unroll
       for (int i = 0; i < 8; ++i) acc[i] = cmp[i] = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) accf[i] = cmpf[i] = 0.0f;
       for (int j = bb0 + lane; j < bb1; j += 64) {
         double tt[8];
         terms(qb, cb, j, tt);
+        if constexpr (MIXED) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) kahan_add(acc[i], cmp[i], tt[i]);
+          for (int i = 0; i < 4; ++i) kahan_addf(accf[i], cmpf[i], (float)tt[i]);
+#pragma unroll
+          for (int i = 4; i < 8; ++i) kahan_add(acc[i], cmp[i], tt[i]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) kahan_add(acc[i], cmp[i], tt[i]);
+        }
       }
+      if constexpr (MIXED) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) acc[i] -= cmp[i];
+        for (int i = 0; i < 4; ++i) acc[i] = (double)accf[i] - (double)cmpf[i];
+#pragma unroll
+        for (int i = 4; i < 8; ++i) acc[i] -= cmp[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] -= cmp[i];
+      }
       int idx;
       const double tot = wave_sum8(acc, lane, idx);
       if ((lane & 7) == 0) partials[(int64_t)wb * 8 + idx] = tot;
     }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// the hot loop, mixed precision
-// ---------------------------------------------------------------------------
-// FP64: phase (cycles, double-double), SPA time, orbit angle and the large
-// Doppler term 2 k.(guiding centre) (1000 s, needs ~1e-12 relative).
-// FP32: constellation offsets, arm directions, antenna patterns, link sincs,
-// the reduced Doppler and template phases (hardware sin/cos on revolutions
-// reduced to [-1/2, 1/2]), products and Kahan-compensated partition sums.
-__device__ __forceinline__ void sincos_rev(double rev, float& s, float& c) {
-  double r = rev - rint(rev);            // [-1/2, 1/2] revolutions
-  float rf = (float)r;
-  s = __builtin_amdgcn_sinf(rf);         // sin(2 pi rf)
-  c = __builtin_amdgcn_cosf(rf);
-}
-__device__ __forceinline__ void sincos_revf(float r, float& s, float& c) {
-  r = r - rintf(r);
-  s = __builtin_amdgcn_sinf(r);
-  c = __builtin_amdgcn_cosf(r);
-}
-__device__ __forceinline__ float sincf_from(float num, float den) {
-  return (fabsf(den) < 1e-3f) ? 1.0f - den * den * (1.0f / 6.0f) : num / den;
-}
-__device__ __forceinline__ void kahan_addf(float& s, float& c, float x) {
-  float y = x - c;
-  float t = s + y;
-  c = (t - s) - y;
-  s = t;
-}
-
-// FP32 Michelson combination at spacecraft a relative to the phase reference
-// p_1 (see michelson_fp64).
-__device__ __forceinline__ void michelson_f32(const float k[3], const float u[3], const float v[3],
-                                              const float d[3][3], float fl, float s0, float c0,
-                                              int a, float& tpr, float& tpi, float& txr,
-                                              float& txi, bool table = false) {
-  const float x0 = (float)(kPi * kLs) * fl;
-  const float zr = c0 * c0 - s0 * s0, zi = -2.0f * s0 * c0;
-  float out[2][4];
-#pragma unroll
-  for (int arm = 0; arm < 2; ++arm) {
-    const int w = (a + 1 + arm) % 3;
-    float ax = d[w][0] - d[a][0], ay = d[w][1] - d[a][1], az = d[w][2] - d[a][2];
-    const float r2 = ax * ax + ay * ay + az * az;
-    float inv = __builtin_amdgcn_rsqf(r2);
-    ax *= inv; ay *= inv; az *= inv;
-    float kn = k[0] * ax + k[1] * ay + k[2] * az;
-    float un = u[0] * ax + u[1] * ay + u[2] * az;
-    float vn = v[0] * ax + v[1] * ay + v[2] * az;
-    float sq, cq;
-    sincos_revf(0.5f * (float)kLs * fl * kn, sq, cq);      // x0 kn
-    float np_ = s0 * cq + c0 * sq, nm = s0 * cq - c0 * sq;
-    float dp = x0 * (1.0f + kn), dm = x0 * (1.0f - kn);
-    float sp, sm;
-    if (fabsf(dp) > 1e-3f && fabsf(dm) > 1e-3f) {
-      float r = __builtin_amdgcn_rcpf(dp * dm);
-      sp = np_ * dm * r;
-      sm = nm * dp * r;
-    } else {
-      sp = sincf_from(np_, dp);
-      sm = sincf_from(nm, dm);
-    }
-    float Sr = sp + zr * sm, Si = zi * sm;
-    if (table) {   // link phase from the arm vector (see michelson_fp64)
-      float se, ce;
-      sincos_revf(0.5f * fl * kn * (r2 * inv - (float)kLs), se, ce);
-      const float tr = sq * ce + cq * se, tc = cq * ce - sq * se;
-      sq = tr;
-      cq = tc;
-    }
-    out[arm][0] = cq * Sr + sq * Si;
-    out[arm][1] = cq * Si - sq * Sr;
-    out[arm][2] = un * un - vn * vn;
-    out[arm][3] = 2.0f * un * vn;
-  }
-  float pr = out[1][2] * out[1][0] - out[0][2] * out[0][0];
-  float pi = out[1][2] * out[1][1] - out[0][2] * out[0][1];
-  float xr = out[1][3] * out[1][0] - out[0][3] * out[0][0];
-  float xi = out[1][3] * out[1][1] - out[0][3] * out[0][1];
-  if (a != 0) {
-    const float kd = k[0] * (d[a][0] - d[0][0]) + k[1] * (d[a][1] - d[0][1]) + k[2] * (d[a][2] - d[0][2]);
-    float sv, cv;
-    sincos_revf(fl * kd, sv, cv);               // e^{-i 2 pi f kd} = cv - i sv
-    const float r0 = pr * cv + pi * sv, i0 = pi * cv - pr * sv;
-    const float r1 = xr * cv + xi * sv, i1 = xi * cv - xr * sv;
-    pr = r0; pi = i0; xr = r1; xi = i1;
-  }
-  tpr = pr; tpi = pi; txr = xr; txi = xi;
-}
-
-__device__ __forceinline__ void template_mixed(const PartConst& P, double f, float s0, float c0,
-                                               float& cph, float& sph, float& tpr, float& tpi,
-                                               float& txr, float& txi, const double* ek,
-                                               int code = 0, const OrbitTable* orb = nullptr) {
-  double fr, tf;
-  phase_and_tf(P, f, fr, tf, ek);
-  double kP;                                             // FP64 part of k . p_1 [s]
-  float d[3][3];
-  if (orb && orb->coef) {
-    double dd3[3][3];
-    kP = k_dot_p1_table(P, *orb, tf, 0.0, dd3);             // d = p_i - p_1, so k . d_0 = 0
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) d[i][c] = (float)dd3[i][c];
-  } else {
-    double sad, cad;
-    sincospi(2.0 * tf * (1.0 / kYear), &sad, &cad);
-    kP = kRs * (P.k[0] * cad + P.k[1] * sad);           // k . guiding centre [s], FP64
-    orbit_offsets<float>((float)cad, (float)sad, d);
-  }
-  const float kx = (float)P.k[0], ky = (float)P.k[1], kz = (float)P.k[2];
-  const float ux = (float)P.u[0], uy = (float)P.u[1], uz = (float)P.u[2];
-  const float vx = (float)P.v[0], vy = (float)P.v[1], vz = (float)P.v[2];
-  float kd0 = kx * d[0][0] + ky * d[0][1] + kz * d[0][2];
-  sincos_rev(fr + f * (kP + (double)kd0), sph, cph);      // e^{i Phi}
-  const float fl = (float)f;
-  const bool table = orb && orb->coef;
-  if (code != 0) {
-    const float kk[3] = {kx, ky, kz}, uu[3] = {ux, uy, uz}, vv[3] = {vx, vy, vz};
-    double wd[3];
-    channel_weights(code, wd);
-    tpr = tpi = txr = txi = 0.0f;
-#pragma unroll 1
-    for (int a = 0; a < 3; ++a) {
-      if (wd[a] == 0.0) continue;
-      const float wa = (float)wd[a];
-      float pr, pi, xr, xi;
-      michelson_f32(kk, uu, vv, d, fl, s0, c0, a, pr, pi, xr, xi, table);
-      tpr += wa * pr; tpi += wa * pi; txr += wa * xr; txi += wa * xi;
-    }
-    return;
-  }
-  const float x0 = (float)(kPi * kLs) * fl;
-  const float zr = c0 * c0 - s0 * s0, zi = -2.0f * s0 * c0;
-  float out[2][4];
-#pragma unroll
-  for (int arm = 0; arm < 2; ++arm) {
-    float ax = d[arm + 1][0] - d[0][0], ay = d[arm + 1][1] - d[0][1], az = d[arm + 1][2] - d[0][2];
-    const float r2 = ax * ax + ay * ay + az * az;
-    float inv = __builtin_amdgcn_rsqf(r2);
-    ax *= inv; ay *= inv; az *= inv;
-    float kn = kx * ax + ky * ay + kz * az;
-    float un = ux * ax + uy * ay + uz * az;
-    float vn = vx * ax + vy * ay + vz * az;
-    float sq, cq;
-    sincos_revf(0.5f * (float)kLs * fl * kn, sq, cq);      // x0 kn
-    float np_ = s0 * cq + c0 * sq, nm = s0 * cq - c0 * sq;
-    float dp = x0 * (1.0f + kn), dm = x0 * (1.0f - kn);
-    float sp, sm;
-    if (fabsf(dp) > 1e-3f && fabsf(dm) > 1e-3f) {
-      float r = __builtin_amdgcn_rcpf(dp * dm);
-      sp = np_ * dm * r;
-      sm = nm * dp * r;
-    } else {
-      sp = sincf_from(np_, dp);
-      sm = sincf_from(nm, dm);
-    }
-    float Sr = sp + zr * sm, Si = zi * sm;
-    if (table) {   // link phase from the arm vector (see michelson_fp64)
-      float se, ce;
-      sincos_revf(0.5f * fl * kn * (r2 * inv - (float)kLs), se, ce);
-      const float tr = sq * ce + cq * se, tc = cq * ce - sq * se;
-      sq = tr;
-      cq = tc;
-    }
-    out[arm][0] = cq * Sr + sq * Si;
-    out[arm][1] = cq * Si - sq * Sr;
-    out[arm][2] = un * un - vn * vn;
-    out[arm][3] = 2.0f * un * vn;
-  }
-  tpr = out[1][2] * out[1][0] - out[0][2] * out[0][0];
-  tpi = out[1][2] * out[1][1] - out[0][2] * out[0][1];
-  txr = out[1][3] * out[1][0] - out[0][3] * out[0][0];
-  txi = out[1][3] * out[1][1] - out[0][3] * out[0][1];
-}
-
-__global__ __launch_bounds__(256) void k_eval_mixed(Grid g,
-                                                    const PartConst* __restrict__ pc,
-                                                    const int32_t* __restrict__ bounds, int32_t stride,
-                                                    const int2* __restrict__ items,
-                                                    const int32_t* __restrict__ total, int32_t chunk,
-                                                    const float* __restrict__ wr,
-                                                    const float* __restrict__ wi,
-                                                    const float* __restrict__ u,
-                                                    const float* __restrict__ s0a,
-                                                    const float* __restrict__ c0a,
-                                                    const double* __restrict__ ek,
-                                                    double* __restrict__ partials,
-                                                   const int32_t* __restrict__ sel,
-                                                   const int32_t* __restrict__ nsel) {
-  const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * blockDim.x) >> 6;
-  // all items, or only those listed in sel (the interpolating kernel's rejects)
-  const int W = sel ? nsel[0] : total[0];
-  for (int iw = wave; iw < W; iw += nwaves) {
-    const int w = sel ? sel[iw] : iw;
-    int2 it = items[w];
-    int q = __builtin_amdgcn_readfirstlane(it.x);
-    int c = __builtin_amdgcn_readfirstlane(it.y);
-    int p = q / stride, l = q - p * stride;
-    const PartConst& P = pc[p];
-    const int32_t* bp = bounds + (int64_t)p * (stride + 1);
-    int ct, ch;
-    item_split(c, g.chan.n, ct, ch);
-    const int code = g.chan.code[ch];
-    const int64_t co = (int64_t)ch * g.nbins;   // the channel's data
-    int b0, b1;
-    item_bins(bp[l], bp[l + 1], ct, chunk, b0, b1);
-    const double* ekq = (ek && P.sur) ? ek + 8 * (int64_t)q : nullptr;
-    // N-terms (Z+, Zx) in FP32 with Kahan; M-terms (P, Q, R) in FP64 from the
-    // FP32 response: the partition matrix can be ill-conditioned, and FP32
-    // sums would leave its weak eigen-direction unresolved.
-    float acc[4], cmp[4];
-    double m4[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { acc[i] = cmp[i] = 0.0f; m4[i] = 0.0; }
-    for (int j = b0 + lane; j < b1; j += 64) {
-      double f = bin_freq(g, j);
-      float cps, sps, tpr, tpi, txr, txi;
-      template_mixed(P, f, s0a[j], c0a[j], cps, sps, tpr, tpi, txr, txi, ekq, code, &g.orb);
-      float a = wr[co + j], b = wi[co + j];
-      float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
-      kahan_addf(acc[0], cmp[0], Wr * tpr + Wi * tpi);
-      kahan_addf(acc[1], cmp[1], Wi * tpr - Wr * tpi);
-      kahan_addf(acc[2], cmp[2], Wr * txr + Wi * txi);
-      kahan_addf(acc[3], cmp[3], Wi * txr - Wr * txi);
-      double uu = (double)u[co + j];
-      double pr = tpr, pi = tpi, xr = txr, xi = txi;
-      m4[0] += uu * (pr * pr + pi * pi);
-      m4[1] += uu * (xr * xr + xi * xi);
-      m4[2] += uu * (pr * xr + pi * xi);
-      m4[3] += uu * (pi * xr - pr * xi);
-    }
-    double red[8];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { red[i] = (double)acc[i] - (double)cmp[i]; red[4 + i] = m4[i]; }
-    int idx;
-    const double tot = wave_sum8(red, lane, idx);
-    if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
   }
 }
 
@@ -2243,14 +2057,9 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
     nsel = ws.ndirect;
   }
   auto exact_pass = [&](const int32_t* list, const int32_t* count) {
-    if (mixed)
-      hipLaunchKernelGGL(k_eval_mixed, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
-                         ws.items, ws.total, chunk, b32.wr, b32.wi, b32.u, b32.s0, b32.c0, ek,
-                         ws.partials, list, count);
-    else
-      hipLaunchKernelGGL(k_eval_fp64, dim3(blocks), dim3(256), 0, s, g, ws.pc, ws.bounds, stride,
-                         ws.items, ws.total, chunk, b.wr, b.wi, b.u, b.s0, b.c0, ek, ws.partials,
-                         list, count);
+    hipLaunchKernelGGL(mixed ? k_eval_exact<true> : k_eval_exact<false>, dim3(blocks), dim3(256),
+                       0, s, g, ws.pc, ws.bounds, stride, ws.items, ws.total, chunk, b.wr, b.wi,
+                       b.u, b32.wr, b32.wi, b32.u, b.s0, b.c0, ek, ws.partials, list, count);
   };
   if (!interp && ev_main) (void)hipEventRecord(ev_main[0], s);
   exact_pass(sel, nsel);
@@ -2314,9 +2123,9 @@ void launch_waveform(const Grid& g, const PartConst* pc, const double* amps,
 
 namespace fstat {
 hipError_t occupancy_fp64(int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_eval_fp64, 256, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_eval_exact<false>, 256, 0);
 }
 hipError_t occupancy_mixed(int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_eval_mixed, 256, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_eval_exact<true>, 256, 0);
 }
 }  // namespace fstat

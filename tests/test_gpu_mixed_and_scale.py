@@ -1,11 +1,14 @@
 """Mixed-precision error report and paper-scale sampled parity.
 
-Mixed path tolerance (FP32 response/products with Kahan partition sums, FP64
-phase and solve): 1e-4 relative where the partition matrix is well
-conditioned.  FP32 rounding of the response (eps32 = 6e-8) perturbs the
-weak eigen-direction of M; the statistic's sensitivity to that grows with
-cond(M), so per-partition values are held to 1e-4 + 1e-6 * cond(M_l)
-(relative, |F| floored at 1) and the error report is binned by cond.
+Mixed path: FP64 phase, SPA time, response (nodes of the interpolants, or
+every bin in the exact loop) and solve; the response rounded or interpolated
+in FP32, FP32 products and N-term sums.  Bar: 1e-4 relative per partition
+(|F| floored at 1) where cond(M_l) <= 1e4.  Above, FP32 rounding of the
+response tilts the (T+, Tx) direction by ~eps32 and the statistic amplifies
+that tilt by ~sqrt(cond M) along the weak eigen-direction, so partitions are
+held to 1e-4 + MIXED_SQRT_COND sqrt(cond M_l); the constant is twice the
+largest ratio measured on the 20,972-bin workload (16,384 particles at
+Np = 64 and 256).
 """
 import numpy as np
 import pytest
@@ -14,6 +17,8 @@ from oracle import oracle as O
 from paper_2407_10797_amd import synth as S
 
 pytestmark = pytest.mark.gpu
+EPS32 = 2.0 ** -24
+MIXED_SQRT_COND = 20 * EPS32
 
 
 @pytest.fixture(scope="module")
@@ -59,14 +64,26 @@ def test_mixed_precision_error_report(small_many, torch_cuda, npart):
         m = (c >= lo) & (c < hi)
         if m.any():
             print(f"  cond [{lo:.0e},{hi:.0e}): n={m.sum():6d}  mixed max {em[m].max():.2e} "
-                  f"median {np.median(em[m]):.2e} | fp64 max {e64[m].max():.2e}", flush=True)
-    tol = 1e-4 + 1e-6 * np.minimum(c, 1e30)
-    assert np.all(em[c < 1e12] <= tol[c < 1e12]), float(np.max(em[c < 1e12] / tol[c < 1e12]))
-    # argmax over the 16,384 particles (the PSO's use of the statistic)
+                  f"median {np.median(em[m]):.2e} max/(eps32 sqrt cond) "
+                  f"{np.max(em[m] / (EPS32 * np.sqrt(c[m]))):.2f} | fp64 max {e64[m].max():.2e} "
+                  f"max/(eps cond) {np.max(e64[m] / (2.0 ** -52 * c[m])):.3f}", flush=True)
+    well = c <= 1e4
+    assert np.all(em[well] <= 1e-4), float(em[well].max())
+    fin = c <= 1e12
+    tol = 1e-4 + MIXED_SQRT_COND * np.sqrt(c[fin])
+    assert np.all(em[fin] <= tol), float(np.max(em[fin] / tol))
+    # singular (pseudo-inverse) partitions: no amplification
+    assert np.all(em[~fin] <= 1e-4)
+    # argmax over the 16,384 particles (the PSO's use of the statistic): the
+    # mixed path's best particle is one whose oracle value lies within twice
+    # the mean's tolerance of the oracle's maximum
     am, ao = int(np.argmax(Fm)), int(np.argmax(Fo))
-    print(f"  argmax mixed {am} oracle {ao}; F_hat rel err at argmax {_rel(Fm[ao], Fo[ao]):.2e}",
-          flush=True)
-    assert _rel(Fm[ao], Fo[ao]) < 1e-3
+    cmax = np.max(np.where(c.reshape(-1, npart) <= 1e12, c.reshape(-1, npart), 0.0), axis=1)
+    tolF = (1e-4 + MIXED_SQRT_COND * np.sqrt(cmax)) * np.maximum(np.abs(Fo), 1.0)
+    print(f"  argmax mixed {am} oracle {ao}; F_hat rel err at argmax {_rel(Fm[ao], Fo[ao]):.2e}; "
+          f"oracle F_hat there {Fo[am]:.6f} vs max {Fo[ao]:.6f}", flush=True)
+    assert np.all(np.abs(Fm - Fo) <= tolF)
+    assert Fo[am] >= Fo[ao] - tolF[am] - tolF[ao]
     if npart == 1:
         assert am == ao
         assert np.max(_rel(Fm, Fo)) < 1e-4
@@ -86,28 +103,53 @@ def paper(torch_cuda):
     plan.close()
 
 
-def test_paper_scale_sampled_parity(paper, torch_cuda):
-    """7,101,001 bins, 4096 particles, Np = 64 in the benchmark's launch
-    configuration; eight sampled particles (including the injection)
-    recomputed by the oracle one by one."""
+PAPER_SAMPLE = np.array([0, 1, 517, 1024, 1500, 2047, 2900, 3333, 3500, 4000, 4095])
+
+
+@pytest.mark.parametrize("npart", [1, 16, 64, 256])
+def test_paper_scale_sampled_parity(paper, torch_cuda, npart):
+    """7,101,001 bins, 4096 particles in the benchmark's launch configuration,
+    at the partition counts of the search stages (Sec. III.B: N_seg 16 and 1)
+    and of the benchmark (64, 256); sampled particles (including the
+    injection) recomputed by the oracle one by one."""
     s = paper
-    print("[paper] 4096 particles, Np=64", flush=True)
-    F, P = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), 64, want_parts=True)
-    Fm, Pm = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), 64, mixed=True, want_parts=True)
+    print(f"[paper] 4096 particles, Np={npart}", flush=True)
+    F, P = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, want_parts=True)
+    items, rej, ref = s["plan"].interp_stats()
+    Fm, Pm = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, mixed=True, want_parts=True)
     F, P, Fm, Pm = (t.cpu().numpy() for t in (F, P, Fm, Pm))
-    idx = np.array([0, 1, 517, 1024, 2047, 2900, 3500, 4095])
+    idx = PAPER_SAMPLE
     Fo, Po, cond = O.fstat(s["data"], s["psd"], s["g"].k_lo, s["g"].df, s["g"].T_obs, s["pts"][idx],
-                           [64], want_cond=True)
+                           [npart], want_cond=True)
     c = np.where(np.isfinite(cond), cond, 0.0)
-    r64 = _rel(P[idx], Po)
-    rm = _rel(Pm[idx], Po)
-    print(f"  fp64 max rel {r64.max():.2e}, mixed max rel {rm.max():.2e}, max cond {c.max():.2e}",
-          flush=True)
+    r64 = _rel(P[idx, :npart], Po)
+    rm = _rel(Pm[idx, :npart], Po)
+    print(f"  {items} items, {rej} handed to the exact loop, {ref} refined; fp64 max rel "
+          f"{r64.max():.2e}, mixed max rel {rm.max():.2e}, max cond {c.max():.2e}", flush=True)
+    assert rej < items // 10            # the interpolating loop carries the batch
     assert np.all(r64 <= 1e-9 + 1e-14 * c)
     assert np.all(_rel(F[idx], Fo) <= 1e-9 + 1e-14 * c.max(axis=1))
-    assert np.all(rm <= 1e-4 + 1e-6 * c)
-    # the injection stands out: 2 F_hat Np ~ rho^2 (+ noise) at the true parameters
-    assert F[0] * 64 * 2 > 0.5 * s["snr"] ** 2
+    assert np.all(rm[c <= 1e4] <= 1e-4)
+    assert np.all(rm <= 1e-4 + MIXED_SQRT_COND * np.sqrt(c))
+    if npart == 64:
+        # the injection stands out: 2 F_hat Np ~ rho^2 (+ noise) at the true parameters
+        assert F[0] * 64 * 2 > 0.5 * s["snr"] ** 2
+
+
+@pytest.mark.parametrize("npart", [1, 16, 64, 256])
+def test_paper_scale_interpolating_matches_exact_everywhere(paper, torch_cuda, npart):
+    """Every partition of all 4096 particles: the interpolating loop (the
+    benchmark's path) against the exact template at every bin, 1e-10 relative
+    (|F| floored at 1)."""
+    s = paper
+    print(f"[paper] interpolating vs exact, 4096 particles, Np={npart}", flush=True)
+    F, P = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, want_parts=True)
+    Fe, Pe = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, want_parts=True, exact=True)
+    P, Pe = P.cpu().numpy()[:, :npart], Pe.cpu().numpy()[:, :npart]
+    r = _rel(P, Pe)
+    print(f"  max rel {r.max():.2e}, median {np.median(r):.2e}", flush=True)
+    assert np.all(r <= 1e-10)
+    np.testing.assert_allclose(F.cpu().numpy(), Fe.cpu().numpy(), rtol=1e-10, atol=1e-10)
 
 
 def test_paper_scale_numerical_orbit_sampled_parity(paper, torch_cuda):

@@ -48,6 +48,14 @@ def _rel(a, b, floor=1.0):
 
 def _check_parts(Fg, Fo, cond, np_parts):
     bad = []
+    worst = 0.0
+    for i in range(Fo.shape[0]):
+        npi = int(np_parts[i]) if np.ndim(np_parts) else int(np_parts)
+        c = cond[i, :npi]
+        fin = np.isfinite(c) & (c > 0)
+        if fin.any():
+            worst = max(worst, float(np.max(_rel(Fg[i, :npi], Fo[i, :npi])[fin] / (2.0 ** -52 * c[fin]))))
+    print(f"  max |GPU - oracle| / (eps cond) {worst:.3f}", flush=True)
     for i in range(Fo.shape[0]):
         npi = int(np_parts[i]) if np.ndim(np_parts) else int(np_parts)
         tol = REL + 1e-14 * np.where(np.isfinite(cond[i, :npi]), cond[i, :npi], 0.0)
@@ -161,10 +169,13 @@ def test_edge_cases(small, torch_cuda):
     F, P = F.cpu().numpy(), P.cpu().numpy()
     assert np.isfinite(F[0]) and F[1] == -np.inf and np.isnan(F[2]) and np.isnan(F[3])
     assert np.all(P[1] == 0)
-    Fo, Po = O.fstat(s["data"], s["psd"], s["g"].k_lo, s["g"].df, s["g"].T_obs, p, [1024])
+    Fo, Po, cond = O.fstat(s["data"], s["psd"], s["g"].k_lo, s["g"].df, s["g"].T_obs, p, [1024],
+                           want_cond=True)
     assert (Po[0] == 0).sum() > 500          # most of the 1024 partitions are empty
     np.testing.assert_array_equal(P[0] == 0, Po[0] == 0)
-    assert abs(F[0] - Fo[0]) <= 1e-6 * abs(Fo[0])
+    _check_parts(P[:1], Po, cond, 1024)
+    tolF = REL + 1e-14 * np.nanmax(np.where(np.isfinite(cond), cond, 0.0))
+    assert abs(F[0] - Fo[0]) <= tolF * max(abs(Fo[0]), 1.0)
 
 
 def test_host_pointer_errors(small, torch_cuda):
