@@ -6,6 +6,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2407_10797_amd import synth as S
+from tests.bars import FP64_KCOND, FP64_REL
 
 pytestmark = pytest.mark.gpu
 
@@ -56,7 +57,7 @@ def test_autotune_choice_is_cached_and_correct(small, torch_cuda, mixed):
     Fp = Fp.cpu().numpy()[:, :16]
     c16 = np.where(np.isfinite(cond[:, :16]), cond[:, :16], 1e30)
     rel = np.abs(Fp - Po[:, :16]) / np.maximum(np.abs(Po[:, :16]), 1.0)
-    tol = (1e-4 + 1e-6 * c16) if mixed else (1e-9 + 1e-14 * c16)
+    tol = (1e-4 + 1e-6 * c16) if mixed else (FP64_REL + FP64_KCOND * c16)
     ok = np.isfinite(Po[:, :16])
     assert np.all(rel[ok] <= tol[ok]), float((rel[ok] / tol[ok]).max())
 

@@ -6,15 +6,16 @@ in FP32, FP32 products and N-term sums.  Bar: 1e-4 relative per partition
 (|F| floored at 1) where cond(M_l) <= 1e4.  Above, FP32 rounding of the
 response tilts the (T+, Tx) direction by ~eps32 and the statistic amplifies
 that tilt by ~sqrt(cond M) along the weak eigen-direction, so partitions are
-held to 1e-4 + MIXED_SQRT_COND sqrt(cond M_l); the constant is twice the
-largest ratio measured on the 20,972-bin workload (16,384 particles at
-Np = 64 and 256).
+held to 1e-4 + MIXED_SQRT_COND sqrt(cond M_l); the largest ratio
+err / (2^-24 sqrt cond) measured on the 20,972-bin workload (16,384
+particles at Np = 64 and 256) is 3.2, and the constant is 20 x 2^-24.
 """
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2407_10797_amd import synth as S
+from tests.bars import FP64_KCOND, FP64_REL
 
 pytestmark = pytest.mark.gpu
 EPS32 = 2.0 ** -24
@@ -127,8 +128,8 @@ def test_paper_scale_sampled_parity(paper, torch_cuda, npart):
     print(f"  {items} items, {rej} handed to the exact loop, {ref} refined; fp64 max rel "
           f"{r64.max():.2e}, mixed max rel {rm.max():.2e}, max cond {c.max():.2e}", flush=True)
     assert rej < items // 10            # the interpolating loop carries the batch
-    assert np.all(r64 <= 1e-9 + 1e-14 * c)
-    assert np.all(_rel(F[idx], Fo) <= 1e-9 + 1e-14 * c.max(axis=1))
+    assert np.all(r64 <= FP64_REL + FP64_KCOND * c)
+    assert np.all(_rel(F[idx], Fo) <= FP64_REL + FP64_KCOND * c.max(axis=1))
     assert np.all(rm[c <= 1e4] <= 1e-4)
     assert np.all(rm <= 1e-4 + MIXED_SQRT_COND * np.sqrt(c))
     if npart == 64:
@@ -181,8 +182,8 @@ def test_paper_scale_numerical_orbit_sampled_parity(paper, torch_cuda):
     rm = _rel(Pm[idx], Po)
     print(f"  fp64 max rel {r64.max():.2e}, mixed max rel {rm.max():.2e}, max cond {c.max():.2e}",
           flush=True)
-    assert np.all(r64 <= 1e-9 + 1e-14 * c)
-    assert np.all(_rel(F[idx], Fo) <= 1e-9 + 1e-14 * c.max(axis=1))
+    assert np.all(r64 <= FP64_REL + FP64_KCOND * c)
+    assert np.all(_rel(F[idx], Fo) <= FP64_REL + FP64_KCOND * c.max(axis=1))
     assert np.all(rm <= 1e-4 + 1e-6 * c)
 
 
@@ -218,8 +219,8 @@ def test_paper_scale_aet_sampled_parity(paper, torch_cuda):
     rm = _rel(Pm[idx], Po)
     print(f"  fp64 max rel {r64.max():.2e}, mixed max rel {rm.max():.2e}, max cond {c.max():.2e}",
           flush=True)
-    assert np.all(r64 <= 1e-9 + 1e-14 * c)
-    assert np.all(_rel(F[idx], Fo) <= 1e-9 + 1e-14 * c.max(axis=1))
+    assert np.all(r64 <= FP64_REL + FP64_KCOND * c)
+    assert np.all(_rel(F[idx], Fo) <= FP64_REL + FP64_KCOND * c.max(axis=1))
     assert np.all(rm <= 1e-4 + 1e-6 * c)
 
 

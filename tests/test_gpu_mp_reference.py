@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import mp_reference as R
+from tests.bars import FP64_KCOND, FP64_REL
 from tests.tiny_workload import NPARTS, tiny
 
 pytestmark = pytest.mark.gpu
@@ -58,6 +59,6 @@ def test_gpu_against_50_digits(setup, torch_cuda, npart, path):
         well = fin & (Tc <= 1e4)
         assert np.all(err[well] <= 1e-4)
         return
-    assert np.all(err[fin] <= 1e-9 + 1e-14 * Tc[fin])
+    assert np.all(err[fin] <= FP64_REL + FP64_KCOND * Tc[fin])
     assert np.all(err[~fin] <= 1e-9)
     np.testing.assert_allclose(F, Th, rtol=1e-9)

@@ -1,12 +1,13 @@
 """Numerical orbit (Sec. IV: Chebyshev interpolation of tabulated spacecraft
 positions) on the GPU against the oracle with the same table.  Bars as in
-test_gpu_parity: FP64 1e-9 (+1e-14 cond) relative per partition, mixed 1e-4
+test_gpu_parity: FP64 1e-9 (+4 eps cond) relative per partition, mixed 1e-4
 (+1e-6 cond)."""
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2407_10797_amd import synth as S
+from tests.bars import FP64_KCOND, FP64_REL
 
 pytestmark = pytest.mark.gpu
 T0, DT, NSEG = -86400.0, 131072.0, 10
@@ -72,7 +73,7 @@ def test_breathing_orbit_matches_oracle(case, torch_cuda, npart, mode):
     finally:
         O.set_orbit(None)
         s["plan"].set_orbit()
-    rel, kc = (1e-4, 1e-6) if mode == "mixed" else (1e-9, 1e-14)
+    rel, kc = (1e-4, 1e-6) if mode == "mixed" else (FP64_REL, FP64_KCOND)
     worst = _check(P.cpu().numpy(), Po, cond, rel, kc)
     print(f"[orbit] breathing table {mode} Np={npart}: worst error / tolerance {worst:.3f}",
           flush=True)
@@ -97,7 +98,7 @@ def test_kepler_orbit_matches_oracle(case, torch_cuda, mode):
     finally:
         O.set_orbit(None)
         s["plan"].set_orbit()
-    rel, kc = (1e-4, 1e-6) if mode == "mixed" else (1e-9, 1e-14)
+    rel, kc = (1e-4, 1e-6) if mode == "mixed" else (FP64_REL, FP64_KCOND)
     worst = _check(P.cpu().numpy(), Po, cond, rel, kc)
     print(f"[orbit] Kepler table {mode} Np=4: worst error / tolerance {worst:.3f}", flush=True)
 
@@ -142,7 +143,7 @@ def test_orbit_with_aet_channels(torch_cuda):
         F, P = plan.eval(torch_cuda.from_numpy(pts), 4, want_parts=True)
     finally:
         plan.close()
-    _check(P.cpu().numpy(), Po, cond, 1e-9, 1e-14)
+    _check(P.cpu().numpy(), Po, cond, FP64_REL, FP64_KCOND)
 
 
 def test_orbit_table_from_device_memory(case, torch_cuda):

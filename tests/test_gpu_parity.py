@@ -5,8 +5,9 @@ Tolerance (FP64 path): the statistic is required to agree with the oracle to
 correct FP64 evaluations of 1/2 N^T M^{-1} N differ by about eps * cond(M)
 relative (backward-stable solve; the noise component along the weak
 eigen-direction is amplified by cond), so each per-partition value is
-checked against  1e-9 + 1e-14 * cond(M_l)  relative (with |F| floored at 1,
-the scale of the noise-only statistic, E[F_l] = 2).
+checked against  1e-9 + 4 eps cond(M_l)  relative (with |F| floored at 1,
+the scale of the noise-only statistic, E[F_l] = 2); the constant and its
+measurement against the 50-digit reference are in tests/bars.py.
 """
 import math
 
@@ -15,6 +16,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2407_10797_amd import synth as S
+from tests.bars import FP64_KCOND, FP64_REL
 
 pytestmark = pytest.mark.gpu
 
@@ -54,11 +56,12 @@ def _check_parts(Fg, Fo, cond, np_parts):
         c = cond[i, :npi]
         fin = np.isfinite(c) & (c > 0)
         if fin.any():
-            worst = max(worst, float(np.max(_rel(Fg[i, :npi], Fo[i, :npi])[fin] / (2.0 ** -52 * c[fin]))))
-    print(f"  max |GPU - oracle| / (eps cond) {worst:.3f}", flush=True)
+            excess = np.maximum(_rel(Fg[i, :npi], Fo[i, :npi])[fin] - REL, 0.0)
+            worst = max(worst, float(np.max(excess / (2.0 ** -52 * c[fin]))))
+    print(f"  max (|GPU - oracle| - 1e-9) / (eps cond) {worst:.3f}", flush=True)
     for i in range(Fo.shape[0]):
         npi = int(np_parts[i]) if np.ndim(np_parts) else int(np_parts)
-        tol = REL + 1e-14 * np.where(np.isfinite(cond[i, :npi]), cond[i, :npi], 0.0)
+        tol = REL + FP64_KCOND * np.where(np.isfinite(cond[i, :npi]), cond[i, :npi], 0.0)
         r = _rel(Fg[i, :npi], Fo[i, :npi])
         if np.any(r > tol):
             bad.append((i, float(r.max()), float(tol[np.argmax(r - tol)])))
@@ -77,7 +80,7 @@ def test_small_workload_matches_oracle(small, torch_cuda, npart):
     F, P = F.cpu().numpy(), P.cpu().numpy()
     _check_parts(P, Po, cond, npart)
     # F_hat: mean of the parts; relative error bounded by the worst part
-    tolF = REL + 1e-14 * np.nanmax(np.where(np.isfinite(cond), cond, 0.0), axis=1)
+    tolF = REL + FP64_KCOND * np.nanmax(np.where(np.isfinite(cond), cond, 0.0), axis=1)
     assert np.all(_rel(F, Fo) <= tolF), np.max(_rel(F, Fo))
     if npart == 1:
         assert np.max(_rel(F, Fo)) < REL
@@ -87,7 +90,7 @@ def test_small_workload_matches_oracle(small, torch_cuda, npart):
 def test_interpolating_and_exact_bin_loops_agree(small, torch_cuda, npart):
     """Default (per-item interpolation of the smooth factors, with exact
     fallback) vs FSTAT_EVAL_EXACT (exact template at every bin): 1e-10 relative
-    per partition, plus 1e-14 cond(M_l); both against the oracle elsewhere."""
+    per partition, plus 4 eps cond(M_l); both against the oracle elsewhere."""
     s = small
     _, _, cond = O.fstat(s["data"], s["psd"], s["g"].k_lo, s["g"].df, s["g"].T_obs, s["pts"],
                          [npart], want_cond=True)
@@ -98,10 +101,14 @@ def test_interpolating_and_exact_bin_loops_agree(small, torch_cuda, npart):
     print(f"[interp] Np={npart}: {items} items, {rej} handed to the exact loop, {ref} refined",
           flush=True)
     assert items == items_e and rej_e == items_e and ref_e == 0
+    if npart == 1:
+        # items of >= 32 bins exist only at Np = 1 here: most go through the
+        # interpolating loop, so this compares the two loops, not one with itself
+        assert rej < items // 2, (rej, items)
     P, Pe = P.cpu().numpy(), Pe.cpu().numpy()
     c = np.where(np.isfinite(cond[:, :npart]), cond[:, :npart], 0.0)
     r = _rel(P[:, :npart], Pe[:, :npart])
-    assert np.all(r <= 1e-10 + 1e-14 * c), float(r.max())
+    assert np.all(r <= 1e-10 + FP64_KCOND * c), float(r.max())
 
 
 def test_uneven_np_in_one_launch(small, torch_cuda):
@@ -131,7 +138,7 @@ def test_many_partitions_ragged_mix(small, torch_cuda):
                            part_stride=1000, want_cond=True)
     F, P = F.cpu().numpy(), P.cpu().numpy()
     _check_parts(P, Po, cond, nps)
-    tolF = REL + 1e-14 * np.nanmax(np.where(np.isfinite(cond), cond, 0.0), axis=1)
+    tolF = REL + FP64_KCOND * np.nanmax(np.where(np.isfinite(cond), cond, 0.0), axis=1)
     assert np.all(_rel(F, Fo) <= tolF), np.max(_rel(F, Fo))
 
 
@@ -174,7 +181,7 @@ def test_edge_cases(small, torch_cuda):
     assert (Po[0] == 0).sum() > 500          # most of the 1024 partitions are empty
     np.testing.assert_array_equal(P[0] == 0, Po[0] == 0)
     _check_parts(P[:1], Po, cond, 1024)
-    tolF = REL + 1e-14 * np.nanmax(np.where(np.isfinite(cond), cond, 0.0))
+    tolF = REL + FP64_KCOND * np.nanmax(np.where(np.isfinite(cond), cond, 0.0))
     assert abs(F[0] - Fo[0]) <= tolF * max(abs(Fo[0]), 1.0)
 
 
