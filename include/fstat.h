@@ -38,6 +38,7 @@
 #ifndef FSTAT_H
 #define FSTAT_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -140,6 +141,37 @@ int fstat_plan_create(fstat_plan_t *plan, const fstat_data_desc *data, const fst
 int fstat_eval(fstat_plan_t plan, const double *params, int64_t n, const int32_t *np,
                int32_t np_uniform, double *F_hat, double *F_part, double *amps,
                int64_t part_stride, uint32_t flags, void *hip_stream);
+
+/* Scratch of fstat_eval_noalloc on each device: 128 MiB (fixed). */
+#define FSTAT_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* Allocation-free variant of fstat_eval, for callers that cannot allocate
+ * device memory during an evaluation: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same statistic, kernels,
+ * arguments and results as fstat_eval with FSTAT_DEVICE_PTRS (bit for bit),
+ * but the work lists, per-item records and partial sums live in a fixed
+ * scratch array of FSTAT_NOALLOC_SCRATCH_BYTES per device, part of the
+ * library's device code (it stays allocated until the process ends); the call
+ * itself allocates nothing and does not synchronize.
+ *   params, np, F_hat, F_part, amps: device pointers, as fstat_eval's
+ *   flags    FSTAT_EVAL_MIXED and/or FSTAT_EVAL_EXACT (FSTAT_DEVICE_PTRS is
+ *            implied)
+ * The scratch holds n x (ceil(nbins / chunk) x channels + part_stride) work
+ * items at about 530 bytes each (chunk: the plan's work-item size); with the
+ * default 2048-bin items that is e.g. 320 particles at Np = 256 on 20,972
+ * bins, or 16,384 particles at Np = 1; larger calls fail with EINVAL and a
+ * message giving the bytes needed.
+ * Every call on a device shares that device's scratch, which keeps the last
+ * call's contents (each call initialises what it reads): calls that overlap
+ * on one device race, whatever their plans and streams, so serialise them
+ * (one stream, or events).  The plan must have been created on the current
+ * device (fstat_plan_create takes the scratch's device address there).  The
+ * plan's profiling (FSTAT_PROFILE) and fstat_interp_stats do not see these
+ * calls.  EINVAL as fstat_eval, and for a plan of another device or a call
+ * beyond the scratch; EUNSUPPORTED with FSTAT_EVAL_SURROGATE.              */
+int fstat_eval_noalloc(fstat_plan_t plan, const double *params, int64_t n, const int32_t *np,
+                       int32_t np_uniform, double *F_hat, double *F_part, double *amps,
+                       int64_t part_stride, uint32_t flags, void *hip_stream);
 
 /* Numerical spacecraft orbit for the plan's templates (Sec. IV: a numerical
  * orbit interpolated with Chebyshev polynomials instead of the analytic one).

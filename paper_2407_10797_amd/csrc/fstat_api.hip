@@ -8,6 +8,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/fstat.h"
@@ -16,6 +17,18 @@
 using namespace fstat;
 
 static_assert(sizeof(fstat_data_desc) == 64, "fstat_data_desc layout");
+
+// ---- scratch memory of the allocation-free entry point ----------------------
+// One fixed array per device, part of the library's device code: each GPU the
+// library runs on holds its own copy, at its own address, until the process
+// ends.  In host code the name `scratch` is a host-side stand-in, never a
+// device address: fstat_plan_create takes the device address once per device
+// (with that device current) and fstat_eval_noalloc passes only that address
+// to the kernels.
+static constexpr size_t kScratchBytes = FSTAT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static char* g_scratch_dev[64] = {};   // per device: device address of `scratch`
 
 namespace fstat {
 
@@ -97,6 +110,61 @@ int ensure_workspace(fstat_plan_s* P, int64_t n, int32_t stride, int chunk) {
   return FSTAT_OK;
 }
 
+// Workspace for (n, stride, chunk) carved out of one buffer in 256-byte
+// aligned pieces, in the order and sizes ensure_workspace allocates them.
+// With base == nullptr only the byte count is computed.
+static size_t carve_workspace(const fstat_plan_s* P, int64_t n, int32_t stride, int chunk,
+                              char* base, WorkSpace* ws) {
+  const size_t m = (size_t)n * (size_t)stride;
+  const size_t nch = (size_t)P->grid.chan.n;
+  const size_t ntiles = (size_t)((P->grid.nbins + chunk - 1) / chunk) * nch;
+  const size_t cap_items = (size_t)n * ((size_t)((P->grid.nbins + chunk - 1) / chunk) + stride) * nch;
+  size_t at = 0;
+  WorkSpace w{};
+  auto take = [&](auto** p, size_t count) {
+    at = (at + 255) & ~(size_t)255;
+    *p = base ? reinterpret_cast<std::remove_reference_t<decltype(*p)>>(base + at) : nullptr;
+    at += (count ? count : 1) * sizeof(**p);
+  };
+  take(&w.pc, (size_t)n);
+  take(&w.bounds, (size_t)n * (stride + 1));
+  take(&w.cnt, m);
+  take(&w.off, m);
+  take(&w.Fl, m);
+  take(&w.total, 1);
+  take(&w.bsum, (m + 4095) / 4096);
+  take(&w.items, cap_items);
+  take(&w.partials, cap_items * 8);
+  take(&w.direct, cap_items);
+  take(&w.ndirect, 1);
+  take(&w.tcnt, ntiles);
+  take(&w.tcur, ntiles);
+  take(&w.toff, ntiles + 1);
+  take(&w.uoff, ntiles + 1);
+  take(&w.tile_items, cap_items);
+  take(&w.tile_ctr, 1);
+  take(&w.xflag, cap_items);
+  take(&w.rec, cap_items * kInterpRec);
+  take(&w.xerr, cap_items);
+  take(&w.refine, cap_items);
+  take(&w.nrefine, 1);
+  if (ws) *ws = w;
+  return at;
+}
+
+// Device address of this device's scratch array, taken once per device.
+static int scratch_init(int dev) {
+  if (dev < 0 || dev >= 64) return set_error(FSTAT_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev]) return FSTAT_OK;
+  void* p = nullptr;
+  int rc = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address");
+  if (rc) return rc;
+  if (!p) return set_error(FSTAT_EDEVICE, "scratch address is null");
+  g_scratch_dev[dev] = static_cast<char*>(p);
+  return FSTAT_OK;
+}
+
 int eval_blocks(fstat_plan_s* P, bool mixed) {
   int& cached = mixed ? P->blocks_mixed : P->blocks_fp64;
   if (cached <= 0) {
@@ -109,21 +177,25 @@ int eval_blocks(fstat_plan_s* P, bool mixed) {
 }
 
 
-// Enqueue one evaluation with device pointers.
-int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t* np,
-                int32_t np_uniform, int32_t stride, double* F_hat, double* F_part,
-                int64_t part_stride, bool mixed, hipStream_t s, const uint8_t* skip,
-                bool allow_profile, bool surrogate, bool exact, double* amps) {
+static int check_chunk(const fstat_plan_s* P, bool mixed, bool exact) {
   const int chunk = chunk_for(P, mixed);
   if (!exact && chunk > interp_max_tile(mixed))
     return set_error(FSTAT_EINVAL, "work-item size %d exceeds the LDS tile limit %d (use a smaller "
                      "chunk or FSTAT_EVAL_EXACT)", chunk, interp_max_tile(mixed));
-  int rc = ensure_workspace(P, n, stride, chunk);
-  if (rc) return rc;
-  if (surrogate && (rc = sur_ensure(P, n, stride))) return rc;
-  launch_setup(P->grid, params, n, np, np_uniform, stride, chunk, skip, P->ws, s);
+  return FSTAT_OK;
+}
+
+// Enqueue the kernels of one evaluation on workspace `ws` (device pointers).
+static int eval_enqueue(fstat_plan_s* P, const WorkSpace& ws, const double* params, int64_t n,
+                        const int32_t* np, int32_t np_uniform, int32_t stride, double* F_hat,
+                        double* F_part, int64_t part_stride, bool mixed, hipStream_t s,
+                        const uint8_t* skip, bool allow_profile, bool surrogate, bool exact,
+                        double* amps) {
+  const int chunk = chunk_for(P, mixed);
+  int rc;
+  launch_setup(P->grid, params, n, np, np_uniform, stride, chunk, skip, ws, s);
   if (surrogate && (rc = sur_prepare(P, n, stride, s))) return rc;
-  launch_worklist(n * (int64_t)stride, P->ws, s);
+  launch_worklist(n * (int64_t)stride, ws, s);
   // profiling: the whole bin-loop stage (e[0], e[3]) and its main kernel (e[1], e[2])
   std::array<hipEvent_t, 4> ev = {nullptr, nullptr, nullptr, nullptr};
   const bool prof = P->profile && allow_profile;
@@ -139,16 +211,30 @@ int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t*
   um.ntiles = P->n_utiles;
   um.ssum = cheb_sums_table();
   if (!um.ssum) um.coef = nullptr;
-  launch_eval(mixed, !exact, P->refine_budget, P->grid, n, stride, chunk, P->ws, P->b64, P->b32,
+  launch_eval(mixed, !exact, P->refine_budget, P->grid, n, stride, chunk, ws, P->b64, P->b32,
               surrogate ? P->sur_ek : nullptr, eval_blocks(P, mixed), s,
               prof ? &ev[1] : nullptr, um);
   if (prof) {
     (void)hipEventRecord(ev[3], s);
     P->events.push_back(ev);
   }
-  launch_solve_mean(n, stride, P->ws, F_hat, F_part, amps, part_stride, P->umax,
+  launch_solve_mean(n, stride, ws, F_hat, F_part, amps, part_stride, P->umax,
                     prof ? P->bin_counter : nullptr, s);
   return hip_check(hipGetLastError(), "kernel launch");
+}
+
+// Enqueue one evaluation with device pointers on the plan's own (grow-only)
+// workspace.
+int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t* np,
+                int32_t np_uniform, int32_t stride, double* F_hat, double* F_part,
+                int64_t part_stride, bool mixed, hipStream_t s, const uint8_t* skip,
+                bool allow_profile, bool surrogate, bool exact, double* amps) {
+  int rc = check_chunk(P, mixed, exact);
+  if (rc) return rc;
+  if ((rc = ensure_workspace(P, n, stride, chunk_for(P, mixed)))) return rc;
+  if (surrogate && (rc = sur_ensure(P, n, stride))) return rc;
+  return eval_enqueue(P, P->ws, params, n, np, np_uniform, stride, F_hat, F_part, part_stride,
+                      mixed, s, skip, allow_profile, surrogate, exact, amps);
 }
 
 // ---- autotuner --------------------------------------------------------------
@@ -333,6 +419,7 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
                                                 P->device), "device attribute");
   if (!rc && interp_tables_init() != 0)
     rc = set_error(FSTAT_EDEVICE, "could not upload the interpolation tables");
+  if (!rc) rc = scratch_init(P->device);
   double *dd = nullptr, *dp = nullptr;
   if (!rc) rc = dev_alloc(&P->b64.wr, nbc, "alloc wr");
   if (!rc) rc = dev_alloc(&P->b64.wi, nbc, "alloc wi");
@@ -553,6 +640,57 @@ int fstat_eval(fstat_plan_t P, const double* params, int64_t n, const int32_t* n
   if (amps && (rc = hip_check(hipMemcpyAsync(amps, P->io.amps, sizeof(double) * n * ps * 4,
                                              hipMemcpyDeviceToHost, s), "copy amps"))) return rc;
   return hip_check(hipStreamSynchronize(s), "eval");
+}
+
+int fstat_eval_noalloc(fstat_plan_t P, const double* params, int64_t n, const int32_t* np,
+                       int32_t np_uniform, double* F_hat, double* F_part, double* amps,
+                       int64_t part_stride, uint32_t flags, void* hip_stream) {
+  g_err.clear();
+  if (!P) return set_error(FSTAT_EINVAL, "null plan");
+  if (n < 0) return set_error(FSTAT_EINVAL, "n < 0");
+  if (n == 0) return FSTAT_OK;
+  if (!params || !F_hat) return set_error(FSTAT_EINVAL, "null params or F_hat");
+  if (flags & FSTAT_EVAL_SURROGATE)
+    return set_error(FSTAT_EUNSUPPORTED, "fstat_eval_noalloc does not run the surrogate");
+  const bool mixed = (flags & FSTAT_EVAL_MIXED) != 0;
+  const bool exact = (flags & FSTAT_EVAL_EXACT) != 0;
+  if (mixed && !(P->prec & FSTAT_MIXED)) return set_error(FSTAT_EINVAL, "plan has no mixed data");
+  if (!mixed && !(P->prec & FSTAT_FP64)) return set_error(FSTAT_EINVAL, "plan has no FP64 data");
+  int32_t stride;
+  if (np) {
+    if (part_stride < 1 || part_stride > 65536)
+      return set_error(FSTAT_EINVAL, "part_stride must give the largest np (1..65536)");
+    stride = (int32_t)part_stride;
+  } else {
+    if (np_uniform < 1 || np_uniform > 65536) return set_error(FSTAT_EINVAL, "np_uniform out of range");
+    if ((F_part || amps) && part_stride < np_uniform)
+      return set_error(FSTAT_EINVAL, "part_stride < np");
+    stride = np_uniform;
+  }
+  int rc = check_chunk(P, mixed, exact);
+  if (rc) return rc;
+  int dev = -1;
+  if ((rc = hip_check(hipGetDevice(&dev), "hipGetDevice"))) return rc;
+  if (dev != P->device)
+    return set_error(FSTAT_EINVAL, "the plan lives on device %d, device %d is current", P->device, dev);
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = (dev >= 0 && dev < 64) ? g_scratch_dev[dev] : nullptr;
+  }
+  if (!base) return set_error(FSTAT_EDEVICE, "scratch of device %d was not set up", dev);
+  if ((size_t)n * (size_t)stride > (size_t)4096 * 4096)
+    return set_error(FSTAT_EINVAL, "n * stride above 16.7M partitions");
+  const int chunk = chunk_for(P, mixed);
+  const size_t need = carve_workspace(P, n, stride, chunk, nullptr, nullptr);
+  if (need > kScratchBytes)
+    return set_error(FSTAT_EINVAL, "fstat_eval_noalloc: %lld particles x (%d partitions + bin tiles) "
+                     "need %zu bytes of scratch, above its fixed %zu bytes (use fstat_eval, or "
+                     "fewer particles per call)", (long long)n, stride, need, kScratchBytes);
+  WorkSpace ws{};
+  carve_workspace(P, n, stride, chunk, base, &ws);
+  return eval_enqueue(P, ws, params, n, np, np_uniform, stride, F_hat, F_part, part_stride, mixed,
+                      (hipStream_t)hip_stream, nullptr, false, false, exact, amps);
 }
 
 int fstat_waveform(double T_obs, double df, int64_t k_lo, int64_t nbins, const double* params6,

@@ -28,7 +28,8 @@ FSTAT_EVAL_SURROGATE = 8
 FSTAT_AUTOTUNE_FORCE = 16
 FSTAT_EVAL_EXACT = 32
 
-EXPORTS = ("fstat_plan_create", "fstat_plan_set_orbit", "fstat_eval", "fstat_extrinsic",
+EXPORTS = ("fstat_plan_create", "fstat_plan_set_orbit", "fstat_eval", "fstat_eval_noalloc",
+           "fstat_extrinsic",
            "fstat_waveform", "pso_stage",
            "fstat_search", "fstat_search_boxes",
            "fstat_profile_read", "fstat_interp_stats", "fstat_autotune", "fstat_mlp_grad", "fstat_mlp_forward",
@@ -120,6 +121,8 @@ def lib() -> ctypes.CDLL:
         L.fstat_plan_create.restype = ctypes.c_int
         L.fstat_eval.argtypes = [vp, vp, i64, vp, i32, vp, vp, vp, i64, u32, vp]
         L.fstat_eval.restype = ctypes.c_int
+        L.fstat_eval_noalloc.argtypes = [vp, vp, i64, vp, i32, vp, vp, vp, i64, u32, vp]
+        L.fstat_eval_noalloc.restype = ctypes.c_int
         L.fstat_extrinsic.argtypes = [vp, vp, i64, vp, u32, vp]
         L.fstat_plan_set_orbit.argtypes = [vp, ctypes.c_double, ctypes.c_double, i32, vp, u32, vp]
         L.fstat_plan_set_orbit.restype = ctypes.c_int
@@ -181,6 +184,12 @@ def fstat_eval(plan, params, n, np_ptr, np_uniform, F_hat, F_part, amps, part_st
                stream=None):
     _check(lib().fstat_eval(plan, params, int(n), np_ptr, int(np_uniform), F_hat, F_part, amps,
                             int(part_stride), int(flags), stream))
+
+
+def fstat_eval_noalloc(plan, params, n, np_ptr, np_uniform, F_hat, F_part, amps, part_stride,
+                       flags, stream=None):
+    _check(lib().fstat_eval_noalloc(plan, params, int(n), np_ptr, int(np_uniform), F_hat, F_part,
+                                    amps, int(part_stride), int(flags), stream))
 
 
 def fstat_plan_set_orbit(plan, t0, dt, n_seg, nodes, flags, stream=None):
@@ -366,9 +375,10 @@ class Plan:
 
     def eval(self, params, np_parts=1, part_stride: int | None = None, mixed: bool = False,
              want_parts: bool = False, surrogate: bool = False, exact: bool = False,
-             want_amps: bool = False):
+             want_amps: bool = False, noalloc: bool = False):
         """F_hat [n] (and F_part [n, stride], amps [n, stride, 4]) for params
-        [n, 6] on the device."""
+        [n, 6] on the device; noalloc: through fstat_eval_noalloc (the
+        library's fixed scratch instead of the plan's workspace)."""
         torch = _torch()
         prm = torch.as_tensor(params).to("cuda", torch.float64).contiguous()
         n = prm.shape[0]
@@ -385,9 +395,10 @@ class Plan:
         Am = torch.zeros((n, stride, 4), device="cuda", dtype=torch.float64) if want_amps else None
         flags = (FSTAT_DEVICE_PTRS | (FSTAT_EVAL_MIXED if mixed else 0)
                  | (FSTAT_EVAL_SURROGATE if surrogate else 0) | (FSTAT_EVAL_EXACT if exact else 0))
-        fstat_eval(self.handle, prm.data_ptr(), n, npp, npu, F.data_ptr(),
-                   Fp.data_ptr() if Fp is not None else None,
-                   Am.data_ptr() if Am is not None else None, stride, flags, _stream())
+        (fstat_eval_noalloc if noalloc else fstat_eval)(
+            self.handle, prm.data_ptr(), n, npp, npu, F.data_ptr(),
+            Fp.data_ptr() if Fp is not None else None,
+            Am.data_ptr() if Am is not None else None, stride, flags, _stream())
         out = (F,)
         if want_parts:
             out += (Fp,)

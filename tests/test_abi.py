@@ -15,6 +15,7 @@ def _declared():
 
 def test_header_declares_the_boundary():
     assert _declared() == sorted(["fstat_plan_create", "fstat_plan_set_orbit", "fstat_eval",
+                                  "fstat_eval_noalloc",
                                   "fstat_extrinsic", "fstat_waveform",
                                   "fstat_search", "fstat_search_boxes",
                                   "pso_stage", "fstat_profile_read", "fstat_interp_stats",
