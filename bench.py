@@ -23,25 +23,71 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X vector ALU: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-instructions/s;
-# with FMA = 2 FLOP that is 78.6 TFLOP/s for FP64.  FP32 arithmetic issues at
-# twice that rate (157.3 TFLOP/s; measured here: the mixed loop's instruction
-# rate has exceeded the single-rate issue budget), so a kernel that mixes
-# the two is held to the time floor f64 / 78.6 + f32 / 157.3.
+# Published MI355X peaks: vector ALU 256 CUs x 64 lanes x 2.4 GHz = 3.93e13
+# lane-instructions/s, i.e. 78.6 TFLOP/s FP64 with FMA = 2; FP32 157.3 TFLOP/s
+# (twice the FP64 rate: reached with packed FP32 instructions, which this
+# build does not emit); HBM 8 TB/s.  A kernel that mixes FP64 and FP32 is held
+# to the time floor f64 / peak64 + f32 / peak32.  The calibration leg measures
+# the FP64 and unpacked FP32 FMA rates and the copy bandwidth on the box.
 PEAK_VALU_TFLOPS = 78.6
 PEAK_F32_TFLOPS = 157.3
+PEAK_HBM_GBPS = 8000.0
 PEAK_LANE_INSTR = 256 * 64 * 2.4e9
 
+# Algorithmic FLOPs per bin-template of the interpolating loop (FMA = 2),
+# derived from its arithmetic (see the repository documentation): per bin the
+# item coordinate s and s^2, s^4, s^8 (5), the phase polynomial in Estrin form
+# (18) plus the linear and grid terms (5), sin/cos by table and Taylor series
+# (22), w e^{i Phi} (6), and the moments sum W s^k: W s (2), s^6 (1), k = 0, 1
+# by additions (4) and 4 per further degree, 4 (D - 1), D the item's transfer
+# degree; items without quadrature M-terms evaluate the four transfer
+# polynomials (Estrin, 2 x 5, 7, 9 FMAs each for D = 5, 7, 9) and form N- and
+# M-terms per bin (36) instead of the moments.
+ALG_FP64 = {"deg5": 79.0, "deg7": 87.0, "deg9": 95.0, "per_bin_m": 132.0}
+# Mixed loop: FP64 phase (Horner, 24 FP64), FP32 sin/cos (2 instructions,
+# not counted), w e^{i Phi} (6), powers (5) and moments k <= 6 (26) in FP32;
+# items without quadrature M-terms: four degree-6 FP32 transfer polynomials
+# (48) and FP32 N-terms (16 + 6), M-terms in FP64 (20).
+ALG_MIXED = {"n_only": (24.0, 37.0), "per_bin_m": (44.0, 70.0)}     # (FP64, FP32)
 
-def _peak_tflops(kind):
-    """Effective peak of a kernel's FP64/FP32 operation mix [TFLOP/s]."""
-    f32 = FLOP32_PER_BIN[kind]
-    f64 = FLOP_PER_BIN[kind] - f32
-    return FLOP_PER_BIN[kind] / (f64 / PEAK_VALU_TFLOPS + f32 / PEAK_F32_TFLOPS)
-# Per bin-template figures of the main bin-loop kernel of each path (the
-# interpolating loop k_eval_interp; profiles/k_eval_interp_paper_4096x64_counters.md):
-# floating-point operations (FP64 + FP32, FMA = 2, x64 lanes), VALU instructions, HBM
-# bytes read per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes
+
+def alg_flops(kind, mix):
+    """Algorithmic FLOPs of the main kernel over one launch, from the launch's
+    bins by kind of per-bin work (fstat_interp_stats bin_mix), as (FP64, FP32)."""
+    if kind == "fp64":
+        f64 = (mix[0] * ALG_FP64["deg5"] + mix[1] * ALG_FP64["deg7"] + mix[2] * ALG_FP64["deg9"]
+               + mix[3] * ALG_FP64["per_bin_m"])
+        return f64, 0.0
+    a, b = ALG_MIXED["n_only"], ALG_MIXED["per_bin_m"]
+    nq = mix[0] + mix[1] + mix[2]
+    return nq * a[0] + mix[3] * b[0], nq * a[1] + mix[3] * b[1]
+
+
+def floor_peak(f64, f32, p64, p32):
+    """Effective peak [TFLOP/s] of an FP64/FP32 operation mix on units of those rates."""
+    return (f64 + f32) / (f64 / p64 + f32 / p32)
+
+
+def calibrate(reps=10):
+    """Measured peaks on this GPU: FP64 and unpacked FP32 FMA chains, and a
+    1 GiB device-to-device copy."""
+    from paper_2407_10797_amd import fstat
+    f64, ms64 = fstat.calibrate(fstat.FSTAT_CALIB_FMA64, 2000, reps)
+    f32, ms32 = fstat.calibrate(fstat.FSTAT_CALIB_FMA32, 2000, reps)
+    bw, msc = fstat.calibrate(fstat.FSTAT_CALIB_COPY, 1 << 30, reps)
+    return {"fp64_fma_tflops": f64, "fp32_fma_unpacked_tflops": f32, "copy_GBps": bw,
+            "ms": {"fp64": ms64, "fp32": ms32, "copy": msc},
+            "config": "FMA chains: 8 independent chains x 128 FMAs x 2000 rounds per lane, "
+                      "16 blocks of 256 per CU; copy: 1 GiB, 16 B per lane access, read + written",
+            "published": {"fp64_tflops": PEAK_VALU_TFLOPS, "fp32_tflops": PEAK_F32_TFLOPS,
+                          "hbm_GBps": PEAK_HBM_GBPS}}
+
+
+# Per bin-template figures of the main bin-loop kernel of each path counted
+# by rocprofv3 (the interpolating loop k_eval_interp;
+# profiles/k_eval_interp_paper_4096x64_counters.md): floating-point operations
+# executed (FP64 + FP32, FMA = 2, x64 lanes), VALU instructions, HBM bytes read
+# per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes
 # written per launch (WRITE_SIZE).
 MAIN_KERNEL = {"fp64": "k_eval_interp<false>", "mixed": "k_eval_interp<true>"}
 FLOP_PER_BIN = {"fp64": 91.25, "mixed": 65.98}      # FP64 + FP32
@@ -52,7 +98,7 @@ TRAFFIC = {"fp64": (0.5123, 6.646e7), "mixed": (0.2776, 3.777e7)}
 # sha256 of the main kernel's source (the k_eval_interp template and the two
 # headers it builds on) when those counters were taken; the figures are
 # reported as null once it differs.
-COUNTERS_SRC_SHA = "4505afdcaffc8813ee6238fc44cfb0947e54e6ac17c907dd2dc170e2fa157ac5"
+COUNTERS_SRC_SHA = "11d72361b2cd048971854aa4711a6744357ca439b74a8ec0ddd17d1abca2e550"
 KERNEL_HEADERS = ("fstat_internal.h", "fstat_kernels.h")
 MAIN_KERNEL_START = "template <bool MIXED>\n__global__ __launch_bounds__(256) void k_eval_interp("
 
@@ -290,6 +336,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-steps", type=int, default=3000)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default work-item shape")
+    ap.add_argument("--no-calibrate", action="store_true",
+                    help="skip measuring the FMA and copy peaks")
     ap.add_argument("--pso-iters", type=int, default=2000, help="0 skips the PSO measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (for scaling "
@@ -323,6 +371,11 @@ def main():
              f"{out['pso']['eager']['iterations_per_s']:.1f} eager")
         print(json.dumps(out), flush=True)
         return
+    calib = None
+    if not args.no_calibrate:
+        calib = calibrate()
+        _log(f"calibration: FP64 FMA {calib['fp64_fma_tflops']:.1f} TFLOP/s, unpacked FP32 FMA "
+             f"{calib['fp32_fma_unpacked_tflops']:.1f} TFLOP/s, copy {calib['copy_GBps']:.0f} GB/s")
     _log("building workload")
     g, data, psd, pts, inj = make_workload(args.particles)
     plan = fstat.Plan(data, psd, g.T_obs, g.df, g.k_lo, profile=True)
@@ -345,8 +398,9 @@ def main():
                 extra.update(tuned_chunk=c, tuned_grid_mult=m)
                 _log(f"{name}: autotuned work item {c} bins, grid x{m}")
             r = time_path(plan, prm, args.np, args.steps, args.warmup, mixed, sur)
-            items, rejected, refined = plan.interp_stats()
-            extra.update(work_items=items, exact_items=rejected, refined_items=refined)
+            items, rejected, refined, mix = plan.interp_stats(bin_mix=True)
+            extra.update(work_items=items, exact_items=rejected, refined_items=refined,
+                         bin_mix=dict(zip(["n_deg5", "n_deg7", "n_deg9", "n_and_m", "exact"], mix)))
             if sur:
                 extra["used"], extra["fallback"] = plan.surrogate_stats()
         except fstat.FstatError as e:
@@ -356,22 +410,33 @@ def main():
         kind = "mixed" if mixed else "fp64"
         secs = r["main_ms"] * 1e-3          # the main kernel alone (HIP events)
         bins = r["bins_per_launch"]
-        # the per-bin figures belong to the kernel sources they were counted on
-        achieved = FLOP_PER_BIN[kind] * bins / secs / 1e12 if same_src else None
+        # algorithmic FLOPs of the main kernel per launch, from its bin mix
+        a64, a32 = alg_flops(kind, mix)
+        alg = a64 + a32
+        peak = floor_peak(a64, a32, PEAK_VALU_TFLOPS, PEAK_F32_TFLOPS)
+        achieved = alg / secs / 1e12
+        step_secs = r["seconds"] / args.steps
+        roof = dict(bound="alu", achieved=achieved, peak=round(peak, 1), unit="TFLOP/s",
+                    frac=achieved / peak, flop_per_launch=alg, flop_fp32_per_launch=a32,
+                    frac_step=alg / step_secs / 1e12 / peak)
+        if calib:
+            pm = floor_peak(a64, a32, calib["fp64_fma_tflops"], calib["fp32_fma_unpacked_tflops"])
+            roof.update(peak_measured=round(pm, 1), frac_measured=achieved / pm)
+        # the counted figures belong to the kernel sources they were counted on
         rd, wr = TRAFFIC[kind]
         traffic = rd * bins + wr if same_src else None
+        roof["traffic"] = traffic
         variants[name] = dict(templates_per_s=tps, ms_per_step=1e3 * r["seconds"] / args.steps,
                               stage_ms=r["kernel_ms"], main_kernel=MAIN_KERNEL[kind],
                               main_kernel_ms=r["main_ms"], bins_per_launch=bins,
                               bin_templates_per_s=bins / (r["kernel_ms"] * 1e-3),
-                              # issue cycles: FP32 arithmetic at twice the rate
-                              valu_issue_frac=(VALU_PER_BIN[kind] - 0.5 * VALU32_PER_BIN[kind])
-                              * bins / secs / PEAK_LANE_INSTR if same_src else None,
+                              executed_flop_per_bin=FLOP_PER_BIN[kind] if same_src else None,
+                              # issue slots: unpacked FP32 issues at the FP64 rate (measured
+                              # by the calibration leg), so every VALU instruction counts once
+                              valu_issue_frac=VALU_PER_BIN[kind] * bins / secs / PEAK_LANE_INSTR
+                              if same_src else None,
                               hbm_GBps=traffic / secs / 1e9 if traffic else None,
-                              roofline=dict(bound="alu", achieved=achieved,
-                                            peak=round(_peak_tflops(kind), 1), unit="TFLOP/s",
-                                            frac=achieved / _peak_tflops(kind) if achieved else None,
-                                            traffic=traffic), **extra)
+                              roofline=roof, **extra)
         _log(f"{name}: {tps:.1f} templates/s, bin-loop stage {r['kernel_ms']:.2f} ms, main kernel "
              f"{r['main_ms']:.2f} ms, {r['bins_per_launch']:.3e} bin-templates/launch")
     if not args.no_orbit and args.only in (None, "orbit"):
@@ -415,6 +480,8 @@ def main():
         "roofline": head.get("roofline"),
         "variants": variants,
     }
+    if calib:
+        out["calibration"] = calib
     if args.pso_iters > 0:
         _log("batched PSO stage")
         out["pso"] = pso_bench(args.pso_iters)

@@ -106,8 +106,12 @@ typedef struct {
   int32_t reserved;
   double refine_budget; /* FP64 interpolating loop: partitions where the
                            interpolation error could move F by more than this
-                           (relative; bound 2 cond(M) e) are evaluated again
-                           exactly.  0 = 1e-9; < 0 = never                   */
+                           (relative to max(|F|, 1); a first-order estimate
+                           from the maximising amplitudes beta = M^{-1} N,
+                           the noise-weighted norm of each item's template
+                           error and the error of its quadrature M-terms)
+                           get their largest-error items evaluated again
+                           exactly.  0 = 5e-10; < 0 = never                 */
 } fstat_opts;
 
 /* Create a plan: validates the grid (EINVAL on nbins < 1, df <= 0, k_lo < 1,
@@ -359,10 +363,14 @@ int fstat_profile_read(fstat_plan_t plan, int reset, double *kernel_ms, double *
  * than 32 bins, or interpolants that missed an end point; all items after an
  * FSTAT_EVAL_EXACT evaluation), `refined` = interpolated items evaluated again
  * exactly because their partition's matrix is ill-conditioned enough for the
- * interpolation error to matter (FP64 path only).  Waits for hip_stream.
+ * interpolation error to matter (FP64 path only).  bin_mix [5] (or NULL):
+ * bins of the items by the interpolating loop's per-bin work, [0..2] N-terms
+ * only (M-terms by quadrature) at transfer degree 5, 7, 9 (every mixed-path
+ * item counts as 9), [3] N- and M-terms per bin, [4] handed to the exact loop
+ * (EINVAL after an FSTAT_EVAL_EXACT evaluation).  Waits for hip_stream.
  * EINVAL before the first evaluation.                                      */
 int fstat_interp_stats(fstat_plan_t plan, int64_t *items, int64_t *rejected, int64_t *refined,
-                       void *hip_stream);
+                       int64_t *bin_mix, void *hip_stream);
 
 /* ---- learned surrogate for the eccentric phase (App. A) ------------------- */
 /* One forward and backward pass of the surrogate network on the device, for
@@ -409,6 +417,23 @@ int fstat_surrogate_train(fstat_plan_t plan, fstat_surrogate_desc *desc, void *h
 /* Particles of the last FSTAT_EVAL_SURROGATE evaluation that used the
  * surrogate and that fell back to the analytic template.                  */
 int fstat_surrogate_stats(fstat_plan_t plan, int64_t *used, int64_t *fallback);
+
+/* Measured peaks for the roofline (not part of the statistic): kind
+ *   FSTAT_CALIB_FMA64  chains of FP64 fused multiply-adds, `size` rounds of
+ *                      128 per lane, 16 blocks of 256 per compute unit;
+ *                      rate in TFLOP/s (FMA = 2)
+ *   FSTAT_CALIB_FMA32  the same in FP32 (scalar, unpacked instructions)
+ *   FSTAT_CALIB_COPY   device-to-device copy of `size` bytes; rate in GB/s
+ *                      counting bytes read plus bytes written
+ * Each is launched once to warm up, then `reps` times between two events;
+ * ms is the average launch.  Allocates (and frees) its own buffers and waits
+ * for completion.  EINVAL: unknown kind, size or reps < 1, size above 2^24
+ * rounds or 64 GiB.                                                       */
+#define FSTAT_CALIB_FMA64 0
+#define FSTAT_CALIB_FMA32 1
+#define FSTAT_CALIB_COPY 2
+int fstat_calibrate(int32_t kind, int64_t size, int32_t reps, double *rate, double *ms,
+                    void *hip_stream);
 
 /* Release the plan and its device memory (NULL is ignored). */
 void fstat_plan_destroy(fstat_plan_t plan);

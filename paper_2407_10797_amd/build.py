@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfstat.so")
-SOURCES = ["fstat_kernels.hip", "fstat_api.hip", "pso.hip", "mlp.hip", "surrogate.hip", "search.hip"]
+SOURCES = ["fstat_kernels.hip", "fstat_api.hip", "pso.hip", "mlp.hip", "surrogate.hip", "search.hip", "calib.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -211,6 +211,7 @@ static int eval_enqueue(fstat_plan_s* P, const WorkSpace& ws, const double* para
   um.ntiles = P->n_utiles;
   um.ssum = cheb_sums_table();
   if (!um.ssum) um.coef = nullptr;
+  um.upre = P->upre;
   launch_eval(mixed, !exact, P->refine_budget, P->grid, n, stride, chunk, ws, P->b64, P->b32,
               surrogate ? P->sur_ek : nullptr, eval_blocks(P, mixed), s,
               prof ? &ev[1] : nullptr, um);
@@ -233,6 +234,10 @@ int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t*
   if (rc) return rc;
   if ((rc = ensure_workspace(P, n, stride, chunk_for(P, mixed)))) return rc;
   if (surrogate && (rc = sur_ensure(P, n, stride))) return rc;
+  P->last.stride = stride;
+  P->last.chunk = chunk_for(P, mixed);
+  P->last.mixed = mixed;
+  P->last.exact = exact;
   return eval_enqueue(P, P->ws, params, n, np, np_uniform, stride, F_hat, F_part, part_stride,
                       mixed, s, skip, allow_profile, surrogate, exact, amps);
 }
@@ -381,7 +386,7 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
   if (prec == 0) prec = FSTAT_FP64 | FSTAT_MIXED;
   if (prec & ~(FSTAT_FP64 | FSTAT_MIXED)) return set_error(FSTAT_EINVAL, "bad precision mask");
   int chunk = (opts && opts->chunk > 0) ? opts->chunk : 2048;
-  const double budget = (opts && opts->refine_budget != 0.0) ? opts->refine_budget : 1e-9;
+  const double budget = (opts && opts->refine_budget != 0.0) ? opts->refine_budget : 5e-10;
   if (!std::isfinite(budget)) return set_error(FSTAT_EINVAL, "refine_budget must be finite");
   if (chunk < 64 || chunk > (1 << 24)) return set_error(FSTAT_EINVAL, "chunk out of range");
   const bool dev = (flags & FSTAT_DEVICE_PTRS) != 0;
@@ -460,6 +465,9 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
     if (!rc) rc = dev_alloc(&P->ubad, (size_t)nut_all + 1, "alloc u model flags");
   }
   if (!rc) rc = dev_alloc(&P->ures, (size_t)nut_all, "alloc u model residuals");
+  double* ubsum = nullptr;
+  if (!rc) rc = dev_alloc(&P->upre, (size_t)(nb + 1) * chan.n, "alloc u prefix sums");
+  if (!rc) rc = dev_alloc(&ubsum, (size_t)uprefix_block_sums(nb), "alloc u prefix scratch");
   double* dres = P->ures;
   if (!rc) {
     launch_prep(P->grid, ddata, dpsd, P->b64, s);
@@ -468,6 +476,8 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
     for (int c = 0; c < chan.n; ++c)
       launch_ufit(P->b64.u + (int64_t)c * nb, nb, P->n_utiles,
                   P->ucoef + (int64_t)c * P->n_utiles * kUCoef, dres + (int64_t)c * P->n_utiles, s);
+    for (int c = 0; c < chan.n; ++c)
+      launch_uprefix(P->b64.u + (int64_t)c * nb, nb, ubsum, P->upre + (int64_t)c * (nb + 1), s);
     rc = hip_check(hipGetLastError(), "prep launch");
   }
   if (!rc) rc = hip_check(hipMemcpyAsync(ures.data(), dres, sizeof(double) * nut_all,
@@ -487,6 +497,7 @@ int fstat_plan_create(fstat_plan_t* out, const fstat_data_desc* d, const fstat_o
   }
   dev_free(dd);
   dev_free(dp);
+  dev_free(ubsum);
   if (rc) {
     fstat_plan_destroy(P);
     return rc;
@@ -514,7 +525,7 @@ void fstat_plan_destroy(fstat_plan_t P) {
   dev_free(P->ws.tile_ctr); dev_free(P->ws.xflag); dev_free(P->ws.rec); dev_free(P->ws.xerr); dev_free(P->ws.refine); dev_free(P->ws.nrefine);
   dev_free(P->io.params); dev_free(P->io.np); dev_free(P->io.F_hat); dev_free(P->io.F_part);
   dev_free(P->io.amps); dev_free(P->umax); dev_free(P->ucoef); dev_free(P->ubad);
-  dev_free(P->ures); dev_free(P->orb_coef);
+  dev_free(P->ures); dev_free(P->upre); dev_free(P->orb_coef);
   pso_release(P);
   sur_release(P);
   for (auto& e : P->events)
@@ -524,11 +535,31 @@ void fstat_plan_destroy(fstat_plan_t P) {
 }
 
 int fstat_interp_stats(fstat_plan_t P, int64_t* items, int64_t* rejected, int64_t* refined,
-                       void* hip_stream) {
+                       int64_t* bin_mix, void* hip_stream) {
   g_err.clear();
-  if (!P || !P->ws.total || !P->ws.ndirect || !P->ws.nrefine)
+  if (!P || !P->ws.total || !P->ws.ndirect || !P->ws.nrefine || P->last.stride < 1)
     return set_error(FSTAT_EINVAL, "no evaluation yet");
   hipStream_t s = (hipStream_t)hip_stream;
+  int rc0 = FSTAT_OK;
+  if (bin_mix) {
+    unsigned long long* d = nullptr;
+    unsigned long long h[5] = {0, 0, 0, 0, 0};
+    rc0 = hip_check(hipMalloc(&d, sizeof(h)), "alloc bin mix");
+    if (!rc0) rc0 = hip_check(hipMemcpyAsync(d, h, sizeof(h), hipMemcpyHostToDevice, s), "clear bin mix");
+    if (!rc0 && P->last.exact) {
+      // every item went through the exact loop: count them all as exact bins
+      rc0 = set_error(FSTAT_EINVAL, "the last evaluation used the exact loop only");
+    }
+    if (!rc0) {
+      launch_bin_mix(P->last.mixed, P->last.stride, P->last.chunk, P->grid.chan.n, P->ws, d, s);
+      rc0 = hip_check(hipGetLastError(), "bin mix launch");
+    }
+    if (!rc0) rc0 = hip_check(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s), "read bin mix");
+    if (!rc0) rc0 = hip_check(hipStreamSynchronize(s), "bin mix");
+    if (d) (void)hipFree(d);
+    if (rc0) return rc0;
+    for (int i = 0; i < 5; ++i) bin_mix[i] = (int64_t)h[i];
+  }
   int32_t v[3] = {0, 0, 0};
   int rc = hip_check(hipMemcpyAsync(&v[0], P->ws.total, sizeof(int32_t), hipMemcpyDeviceToHost, s),
                      "read total");

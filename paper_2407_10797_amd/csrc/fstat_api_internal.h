@@ -22,7 +22,7 @@ struct fstat_plan_s {
   int prec = 0;
   int chunk = 2048;                 // bins per work item (both precisions unless tuned)
   int chunk_mixed = 0;              // tuned value for the mixed path (0: use chunk)
-  double refine_budget = 1e-9;     // see fstat_opts.refine_budget
+  double refine_budget = 5e-10;    // see fstat_opts.refine_budget
   int grid_mult_fp64 = 1, grid_mult_mixed = 1;   // persistent-grid multiplier
   int blocks_fp64 = 0, blocks_mixed = 0;
   fstat::Grid grid{};
@@ -33,6 +33,7 @@ struct fstat_plan_s {
   double* ucoef = nullptr;          // smooth model of u per u-tile (M-term quadrature)
   int32_t* ubad = nullptr;          // prefix count of u-tiles the model does not fit
   double* ures = nullptr;           // relative residual of the model per u-tile
+  double* upre = nullptr;           // [channels][nbins + 1] prefix sums of u
   double* orb_coef = nullptr;       // numerical orbit (fstat_plan_set_orbit)
   int32_t n_utiles = 0;
   int32_t n_ufit = 0;               // u-tiles fitted to within tolerance
@@ -50,6 +51,10 @@ struct fstat_plan_s {
     double* F_part = nullptr;
     double* amps = nullptr;
   } io;
+  struct {                          // shape of the last fstat_eval (fstat_interp_stats)
+    int32_t stride = 0, chunk = 0;
+    bool mixed = false, exact = false;
+  } last;
   PsoState* pso = nullptr;
   // profiling (FSTAT_PROFILE)
   bool profile = false;

@@ -56,7 +56,8 @@ struct WorkSpace {
   int32_t* tile_ctr;  // [1] next unit to take (dynamic schedule)
   uint8_t* xflag;     // [capacity] 1: item evaluated by the exact kernel
   double* rec;        // [capacity][53] per-item interpolation records
-  float* xerr;        // [capacity] end-point error of each interpolated item
+  float2* xerr;       // [capacity] interpolation error of each interpolated item:
+                      // x template (norm-weighted), y M-term quadrature (absolute)
   int32_t* refine;    // [capacity] interpolated items of ill-conditioned partitions
   int32_t* nrefine;   // [1]
 };
@@ -91,10 +92,14 @@ struct UModel {
   const double* resid = nullptr;       // [ntiles] largest relative residual of each fit
   int32_t ntiles = 0;
   const double* ssum = nullptr;        // [5][kSsumMax + 1]: sum_m T_2i(s_m), s_m = 2m/(nb-1) - 1
+  const double* upre = nullptr;        // [channels][nbins + 1] prefix sums of u
 };
 const double* cheb_sums_table();       // the current device's quadrature table (after init)
 void launch_ufit(const double* u, int64_t nbins, int32_t ntiles, double* coef, double* resid,
                  hipStream_t s);
+// prefix sums out[0..n] of u[0..n) (bsum: uprefix_block_sums(n) doubles of scratch)
+int uprefix_block_sums(int64_t n);
+void launch_uprefix(const double* u, int64_t n, double* bsum, double* out, hipStream_t s);
 void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
                  int64_t n_particles, int32_t stride, int32_t chunk,
                  const WorkSpace& ws, BinData<double> b, BinData<float> b32, const double* ek,
@@ -106,6 +111,9 @@ void launch_sur_knots(const Grid& g, int32_t stride, int64_t n, int64_t rows, co
 void launch_sur_check(const Grid& g, int32_t stride, int64_t n, const WorkSpace& ws,
                       const float* ynn, double* ek, double* mm, double thr,
                       unsigned long long* counters, hipStream_t s);
+// bins of the last evaluation by kind of interpolating-loop work (out[5] accumulated)
+void launch_bin_mix(bool mixed, int32_t stride, int32_t chunk, int32_t nch, const WorkSpace& ws,
+                    unsigned long long* out, hipStream_t s);
 void launch_solve_mean(int64_t n, int32_t stride, const WorkSpace& ws, double* F_hat,
                        double* F_part, double* amps, int64_t part_stride, const double* umax,
                        unsigned long long* bin_counter, hipStream_t s);

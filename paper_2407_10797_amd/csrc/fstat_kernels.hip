@@ -253,19 +253,20 @@ __global__ __launch_bounds__(256) void k_setup(Grid g, const double* __restrict_
 // scan plus its offset.
 constexpr int kScanBlock = 4096;   // counts per block (1024 threads x 4)
 
-__device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t* sh, int32_t& total) {
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T x, T* sh, T& total) {
   // inclusive scan across the 1024 threads of the block (Hillis-Steele in LDS)
   const int t = threadIdx.x;
   sh[t] = x;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
-    int32_t y = t >= o ? sh[t - o] : 0;
+    T y = t >= o ? sh[t - o] : T(0);
     __syncthreads();
     sh[t] += y;
     __syncthreads();
   }
   total = sh[1023];
-  int32_t r = sh[t] - x;
+  T r = sh[t] - x;
   __syncthreads();
   return r;
 }
@@ -329,6 +330,54 @@ __global__ void k_fill(const int32_t* __restrict__ cnt, const int32_t* __restric
   if (q >= m) return;
   int c = cnt[q], o = off[q];
   for (int i = 0; i < c; ++i) items[o + i] = make_int2((int)q, i);
+}
+
+// Prefix sums of the per-bin weight u (one channel): out[0] = 0,
+// out[j + 1] = u_0 + ... + u_j.  The refinement estimate takes an item's
+// sum of u from two entries.  Same three passes as the count scan.
+__global__ __launch_bounds__(1024) void k_uscan_sums(const double* __restrict__ u, int64_t n,
+                                                     double* __restrict__ bsum) {
+  __shared__ double red[1024];
+  const int64_t i0 = (int64_t)blockIdx.x * kScanBlock + 4 * threadIdx.x;
+  double v = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v += (i0 + e < n) ? u[i0 + e] : 0.0;
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void k_uscan_top(double* __restrict__ bsum, int32_t nb) {
+  __shared__ double sh[1024];
+  const int i0 = 4 * threadIdx.x;
+  double v[4], x = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) { v[e] = (i0 + e < nb) ? bsum[i0 + e] : 0.0; x += v[e]; }
+  double tot;
+  double run = block_excl_scan(x, sh, tot);
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (i0 + e < nb) { bsum[i0 + e] = run; run += v[e]; }
+}
+
+__global__ __launch_bounds__(1024) void k_uscan_apply(const double* __restrict__ u, int64_t n,
+                                                      const double* __restrict__ bsum,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[1024];
+  const int64_t i0 = (int64_t)blockIdx.x * kScanBlock + 4 * threadIdx.x;
+  double v[4], x = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) { v[e] = (i0 + e < n) ? u[i0 + e] : 0.0; x += v[e]; }
+  double tot;
+  double run = block_excl_scan(x, sh, tot) + bsum[blockIdx.x];
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (i0 + e < n) { run += v[e]; out[i0 + e + 1] = run; }
 }
 
 // ---------------------------------------------------------------------------
@@ -477,11 +526,13 @@ __global__ __launch_bounds__(256) void k_eval_exact(Grid g,
     item_split(c, g.chan.n, ct, ch);
     item_bins(bp[l], bp[l + 1], ct, chunk, b0, b1);
   };
-  // all items, or only those listed in sel (the interpolating kernel's rejects),
-  // in groups of eight: an item of at most kSmallItem bins takes eight lanes of
-  // the wavefront (one bin each, then a fixed three-step butterfly), a larger
-  // one the whole wavefront.  Which path an item takes depends on the item
-  // alone, so its sums do not depend on the order of the list.
+  // All items, or only those listed in sel (the interpolating kernel's
+  // rejects and refinements).  Items of at most kSmallItem bins go in groups
+  // of eight list entries per wavefront, eight lanes each (one bin per lane,
+  // then a fixed three-step butterfly); larger ones one per wavefront in a
+  // second sweep over the list, so that a list of long items (the refinement
+  // pass) spreads over the whole grid.  Which path an item takes depends on
+  // the item alone, so its sums do not depend on the order of the list.
   const int W = sel ? nsel[0] : total[0];
   const int G = (W + 7) >> 3;
   for (int gi = wave; gi < G; gi += nwaves) {
@@ -493,32 +544,34 @@ __global__ __launch_bounds__(256) void k_eval_exact(Grid g,
       bins_of(w, q, c, b0, b1);
     }
     const bool small = have && b1 - b0 <= kSmallItem;
-    {
-      double t[8];
+    if (!__any(small)) continue;
+    double t[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) t[i] = 0.0;
-      const int j = b0 + (lane & 7);
-      if (small && j < b1) terms(q, c, j, t);
+    for (int i = 0; i < 8; ++i) t[i] = 0.0;
+    const int j = b0 + (lane & 7);
+    if (small && j < b1) terms(q, c, j, t);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        t[i] += __shfl_xor(t[i], 4, 64);
-        t[i] += __shfl_xor(t[i], 2, 64);
-        t[i] += __shfl_xor(t[i], 1, 64);
-      }
-      if (small && (lane & 7) == 0) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = t[i];
-      }
+    for (int i = 0; i < 8; ++i) {
+      t[i] += __shfl_xor(t[i], 4, 64);
+      t[i] += __shfl_xor(t[i], 2, 64);
+      t[i] += __shfl_xor(t[i], 1, 64);
     }
-    uint64_t big = __ballot(have && !small && (lane & 7) == 0);
-    while (big) {
-      const int src = __ffsll((long long)big) - 1;
-      big &= big - 1;
-      const int wb = __builtin_amdgcn_readfirstlane(__shfl(w, src, 64));
-      int qb, cb, bb0, bb1;
-      bins_of(wb, qb, cb, bb0, bb1);
-      qb = __builtin_amdgcn_readfirstlane(qb);
-      cb = __builtin_amdgcn_readfirstlane(cb);
+    if (small && (lane & 7) == 0) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = t[i];
+    }
+  }
+  for (int slot = wave; slot < W; slot += nwaves) {
+    // the slot is the same on every lane: keep the item's indices scalar
+    const int wb = __builtin_amdgcn_readfirstlane(sel ? sel[slot] : slot);
+    int qb, cb, bb0, bb1;
+    bins_of(wb, qb, cb, bb0, bb1);
+    qb = __builtin_amdgcn_readfirstlane(qb);
+    cb = __builtin_amdgcn_readfirstlane(cb);
+    bb0 = __builtin_amdgcn_readfirstlane(bb0);
+    bb1 = __builtin_amdgcn_readfirstlane(bb1);
+    if (bb1 - bb0 <= kSmallItem) continue;
+    {
       // Kahan-compensated per-lane sums (true sum ~ acc - cmp): the partition
       // matrix can have cond ~ 1e5..1e8, which amplifies summation error.
       double acc[8], cmp[8];
@@ -587,22 +640,22 @@ constexpr int kUnitItems = 32;      // items per scheduling unit of the bin loop
 constexpr double kTruncFloor = 6e-14;  // FP64 transfer truncation allowance
 
 __constant__ double c_cheb_s[kCheb];          // nodes cos(pi (k + 1/2) / 10)
-__constant__ double c_cheb_G[kCheb][kCheb];   // node value k -> coefficient of s^n
-__constant__ double c_cheb_E[2][kCheb];       // node value k -> interpolant at s = -1, +1
+// Row tables of the node kernel, indexed [node kn][lane k of the item]: on a
+// node lane (k < kCheb) the map node value kn -> monomial coefficient of s^k
+// of the interpolant, on the end lanes k = kCheb, kCheb + 1 the map node
+// value kn -> interpolant at s = -1, +1.
+__constant__ double c_row9[kCheb][kLanesItem];      // degree-9 interpolant
 // The mixed path's transfer interpolants: the Chebyshev series truncated
 // after degree kDegT (its error, a few 1e-10 at 2048 bins, is far below FP32
-// rounding), as monomials, and their values at s = -1, +1.  (Degree 4 would
-// save 8 FP32 operations per bin but fails the end check on enough 4096-bin
-// items that the exact fallback costs more.)
+// rounding); node rows above kDegT are zero.  (Degree 4 would save 8 FP32
+// operations per bin but fails the end check on enough 4096-bin items that
+// the exact fallback costs more.)
 constexpr int kDegT = 6;
-__constant__ double c_cheb_G6[kCheb][kDegT + 1];
-__constant__ double c_cheb_E6[2][kCheb];
+__constant__ double c_row6[kCheb][kLanesItem];
 // The FP64 loop's transfer interpolants may be truncated after degree 5 or 7
 // per item when that keeps them within the item's own error (most paper-scale
-// items need 5-7 of the 10 Chebyshev terms at the 2e-13 bar): maps node value
-// -> monomial coefficient and -> value at s = -1, +1 of the truncated series.
-__constant__ double c_cheb_Gt[2][kCheb][kCheb];   // [0]: degree 5, [1]: degree 7
-__constant__ double c_cheb_Et[2][2][kCheb];
+// items need 5-7 of the 10 Chebyshev terms at the 2e-13 bar).
+__constant__ double c_rowt[2][kCheb][kLanesItem];   // [0]: degree 5, [1]: degree 7
 // Quadrature of an item's interpolant: sum over its bins of the degree-9
 // interpolant through the nodes = sum_k W_k g(s_k), W_k = sum_j c_jk S_j(nb)
 // with c_jk the node-to-Chebyshev-coefficient map and S_j(nb) = sum_m T_j(s_m)
@@ -793,7 +846,7 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
                                                       const double* __restrict__ ek,
                                                       double* __restrict__ rec,
                                                       uint8_t* __restrict__ xflag,
-                                                      float* __restrict__ xerr,
+                                                      float2* __restrict__ xerr,
                                                       int32_t* __restrict__ direct,
                                                       int32_t* __restrict__ ndirect,
                                                       UModel um,
@@ -819,6 +872,15 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     int b0, b1;
     item_bins(bp[l], bp[l + 1], ct, T, b0, b1);
     const int nb = b1 - b0;
+    if (!__any(nb >= kMinInterp)) {
+      // no item of this group is long enough to interpolate: all of them go
+      // to the exact loop without evaluating their nodes
+      if (k == kCheb && lane - base < kLanesItem && grp * kItemsWave + q < W) {
+        xflag[w] = 1;
+        direct[atomicAdd(ndirect, 1)] = w;
+      }
+      continue;
+    }
     const double* ekq = (ek && P.sur) ? ek + 8 * (int64_t)it.x : nullptr;
     const double sk = k < kCheb ? c_cheb_s[k] : (k == kCheb ? -1.0 : 1.0);
     const double mk = (sk + 1.0) * 0.5 * (double)(nb > 1 ? nb - 1 : 0);
@@ -867,101 +929,76 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
       }
     }
     typedef RecLayout<MIXED> L;
-    double coef[5], emin[5], eplu[5], tmax = 0.0;
-    double gsum[4], gmin[4], gplu[4], gmax = 0.0;
-    // FP64: the transfer series truncated after degree 5 and 7 ([0], [1])
-    double ctr[2][4], etm[2][4], etp[2][4];
+    // Lane k forms sum_kn row[kn][k] v_kn: on node lanes (k < kCheb) the
+    // interpolant's monomial coefficient k, on the end lanes its value at the
+    // lane's own end point, which the lane has evaluated exactly.
+    // R in double-double: R reaches a few cycles, the node-to-monomial map has
+    // entries of a few hundred, and a plain double sum would leave ~1e-13
+    // cycles of cancellation error in the coefficients.
+    dd aR{0.0, 0.0};
+    double aRx = 0.0, tmax = 0.0, gmax = 0.0;
+    double aT[4], aTt[2][4], aG[4];
 #pragma unroll
-    for (int v2 = 0; v2 < 2; ++v2)
-#pragma unroll
-      for (int fn = 0; fn < 4; ++fn) { ctr[v2][fn] = 0.0; etm[v2][fn] = 0.0; etp[v2][fn] = 0.0; }
-#pragma unroll
-    for (int fn = 0; fn < 5; ++fn) { coef[fn] = 0.0; emin[fn] = 0.0; eplu[fn] = 0.0; }
-#pragma unroll
-    for (int fn = 0; fn < 4; ++fn) { gsum[fn] = 0.0; gmin[fn] = 0.0; gplu[fn] = 0.0; }
-    // R's coefficient and end values in double-double: R reaches a few cycles,
-    // the node-to-monomial map has entries of a few hundred, and a plain double
-    // sum would leave ~1e-13 cycles of cancellation error in the coefficients
-    dd cRd{0.0, 0.0}, eRm{0.0, 0.0}, eRp{0.0, 0.0};
-    double cRx = 0.0, eRmx = 0.0, eRpx = 0.0;
+    for (int fn = 0; fn < 4; ++fn) {
+      aT[fn] = 0.0; aG[fn] = 0.0; aTt[0][fn] = 0.0; aTt[1][fn] = 0.0;
+    }
     // not unrolled: unrolling hoists every node's table loads and needs more
     // registers than the kernel can hold at a useful occupancy
 #pragma unroll 1
     for (int kn = 0; kn < kCheb; ++kn) {
-      const double gk = c_cheb_G[kn][k < kCheb ? k : 0];
-      const double gt = MIXED ? c_cheb_G6[kn][k < L::nT ? k : 0] : gk;
-      const double em = c_cheb_E[0][kn], ep = c_cheb_E[1][kn];
-      const double emt = MIXED ? c_cheb_E6[0][kn] : em, ept = MIXED ? c_cheb_E6[1][kn] : ep;
+      const double r9 = c_row9[kn][k];
+      const double rT = MIXED ? c_row6[kn][k] : r9;
       {
         const double vn = __shfl(v[0], base + kn, 64), vl = __shfl(v0lo, base + kn, 64);
-        cRd = dd_add(cRd, two_prod(vn, gk));
-        eRm = dd_add(eRm, two_prod(vn, em));
-        eRp = dd_add(eRp, two_prod(vn, ep));
-        cRx = fma(vl, gk, cRx);
-        eRmx = fma(vl, em, eRmx);
-        eRpx = fma(vl, ep, eRpx);
+        aR = dd_add(aR, two_prod(vn, r9));
+        aRx = fma(vl, r9, aRx);
       }
 #pragma unroll
       for (int fn = 1; fn < 5; ++fn) {
         const double vn = __shfl(v[fn], base + kn, 64);
-        coef[fn] = fma(vn, gt, coef[fn]);
-        emin[fn] = fma(vn, emt, emin[fn]);
-        eplu[fn] = fma(vn, ept, eplu[fn]);
+        aT[fn - 1] = fma(vn, rT, aT[fn - 1]);
         tmax = fmax(tmax, fabs(vn));
         if constexpr (!MIXED) {
 #pragma unroll
-          for (int v2 = 0; v2 < 2; ++v2) {
-            ctr[v2][fn - 1] = fma(vn, c_cheb_Gt[v2][kn][k < kCheb ? k : 0], ctr[v2][fn - 1]);
-            etm[v2][fn - 1] = fma(vn, c_cheb_Et[v2][0][kn], etm[v2][fn - 1]);
-            etp[v2][fn - 1] = fma(vn, c_cheb_Et[v2][1][kn], etp[v2][fn - 1]);
-          }
+          for (int v2 = 0; v2 < 2; ++v2) aTt[v2][fn - 1] = fma(vn, c_rowt[v2][kn][k], aTt[v2][fn - 1]);
         }
       }
+      // M-term integrands: lane 0 sums the quadrature, the end lanes interpolate
       const double wk = __shfl(wq, base + kn, 64);
+      const double rg = k == 0 ? wk : (k >= kCheb ? r9 : 0.0);
 #pragma unroll
       for (int fn = 0; fn < 4; ++fn) {
         const double gn = __shfl(gq[fn], base + kn, 64);
-        gsum[fn] = fma(gn, wk, gsum[fn]);
-        gmin[fn] = fma(gn, em, gmin[fn]);
-        gplu[fn] = fma(gn, ep, gplu[fn]);
+        aG[fn] = fma(gn, rg, aG[fn]);
         if (fn < 2) gmax = fmax(gmax, fabs(gn));
       }
     }
     const double tolP = MIXED ? kInterpTolPhaseMixed : kInterpTolPhase;
     const double tolT = MIXED ? kInterpTolTMixed : kInterpTolT;
-    coef[0] = cRd.hi + (cRd.lo + cRx);
+    const double cR = aR.hi + (aR.lo + aRx);
     bool bad = false;
     double err = 0.0;           // relative template error at this end point
     double errt[2] = {0.0, 0.0};   // transfer error of the degree-5 and -7 truncations
+    double gerr = 0.0;          // M-term integrands' error (relative to max u |T|^2)
     if (k >= kCheb) {
-      const double* e = (k == kCheb) ? emin : eplu;
       const double itmax = 1.0 / tmax;      // the estimates below need no correct rounding
-      const dd eR = (k == kCheb) ? eRm : eRp;
-      const double eRx = (k == kCheb) ? eRmx : eRpx;
-      const dd dR = dd_add(eR, dd{-v[0], -v0lo});
-      const double dph = fabs(dR.hi + (dR.lo + eRx));
+      const dd dR = dd_add(aR, dd{-v[0], -v0lo});
+      const double dph = fabs(dR.hi + (dR.lo + aRx));
       bad = !(dph <= tolP);
       err = 2.0 * kPi * dph;
 #pragma unroll
       for (int fn = 1; fn < 5; ++fn) {
-        const double d = fabs(e[fn] - v[fn]);
+        const double d = fabs(aT[fn - 1] - v[fn]);
         bad = bad || !(d <= tolT * tmax);
         err = fmax(err, d * itmax);
         if constexpr (!MIXED) {
 #pragma unroll
-          for (int v2 = 0; v2 < 2; ++v2) {
-            const double et = (k == kCheb) ? etm[v2][fn - 1] : etp[v2][fn - 1];
-            errt[v2] = fmax(errt[v2], fabs(et - v[fn]) * itmax);
-          }
+          for (int v2 = 0; v2 < 2; ++v2)
+            errt[v2] = fmax(errt[v2], fabs(aTt[v2][fn - 1] - v[fn]) * itmax);
         }
       }
-    }
-    // end-point check of the M-term interpolants (relative to max u |T|^2)
-    double gerr = 0.0;
-    if (k >= kCheb) {
-      const double* e = (k == kCheb) ? gmin : gplu;
 #pragma unroll
-      for (int fn = 0; fn < 4; ++fn) gerr = fmax(gerr, fabs(e[fn] - gq[fn]));
+      for (int fn = 0; fn < 4; ++fn) gerr = fmax(gerr, fabs(aG[fn] - gq[fn]));
       gerr = gmax > 0.0 ? gerr / gmax : (gerr > 0.0 ? 1.0 : 0.0);
     }
     const double tolG = MIXED ? kInterpTolTMixed : 4.0 * kInterpTolT;
@@ -971,6 +1008,9 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     for (int kk = 0; kk < kLanesItem; ++kk) gerr = fmax(gerr, __shfl(ures, base + kk, 64));
     const uint64_t badmask = __ballot(bad);
     err = fmax(__shfl(err, base + kCheb, 64), __shfl(err, base + kCheb + 1, 64));
+    double gsum[4];
+#pragma unroll
+    for (int fn = 0; fn < 4; ++fn) gsum[fn] = __shfl(aG[fn], base, 64);
     // FP64: lowest transfer degree whose truncation error stays within the
     // item's own interpolation error, or kTruncFloor of the largest component
     // (a larger allowance sends more items of ill-conditioned partitions to
@@ -987,17 +1027,16 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     if (!mine) continue;
     const bool rej = nb < kMinInterp || ((badmask >> base) & ((1ull << kLanesItem) - 1ull)) != 0ull;
     const bool mq = ufit && ((gbadmask >> base) & ((1ull << kLanesItem) - 1ull)) == 0ull;
-    if (mq) err = fmax(err, gerr);
     if (mq && k < 4)
       partials[(int64_t)w * 8 + 4 + k] = k == 0 ? gsum[0] : (k == 1 ? gsum[1] : (k == 2 ? gsum[2] : gsum[3]));
     double* r = rec + (int64_t)w * kRec;
     if (k < kCheb) {
-      r[k] = coef[0];
+      r[k] = cR;
       if (k < L::nT) {
 #pragma unroll
         for (int fn = 1; fn < 5; ++fn)
           r[kCheb + (fn - 1) * L::nT + k] =
-              degT == 5 ? ctr[0][fn - 1] : (degT == 7 ? ctr[1][fn - 1] : coef[fn]);
+              degT == 5 ? aTt[0][fn - 1] : (degT == 7 ? aTt[1][fn - 1] : aT[fn - 1]);
       }
     } else if (k == kCheb) {
       FSTAT_NO_CONTRACT
@@ -1007,7 +1046,12 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
       r[L::tail + 2] = B;
       r[L::tail + 3] = mq ? 1.0 : 0.0;
       xflag[w] = rej ? 1 : 0;
-      xerr[w] = (float)err;
+      // the template error times the norm sqrt(sum u) max|T| of the item's
+      // templates, and the M-term quadrature's error bound: its relative error
+      // at the end points times max u |T|^2 times the bin count (see k_mark)
+      const int64_t uo = (int64_t)ch * (g.nbins + 1);
+      const double U = um.upre ? fmax(um.upre[uo + b1] - um.upre[uo + b0], 0.0) : (double)nb;
+      xerr[w] = make_float2((float)(err * tmax * sqrt(U)), mq ? (float)(gerr * gmax * nb) : 0.0f);
       if (rej) direct[atomicAdd(ndirect, 1)] = w;
     }
   }
@@ -1348,15 +1392,32 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
   }
 }
 
-// Partitions whose interpolation error could move F by more than `budget`
-// (relative): 2 cond(M) e_max > budget, with e_max the largest end-point
-// error of their interpolated items; those items are listed for exact
-// evaluation (the sums are formed as in k_solve; the eigenvalues of the 2x2
-// Hermitian form give the condition).
+// Refinement of the FP64 interpolating loop's partitions.  With beta =
+// H^{-1} z the maximiser and r the data minus its projection on the template
+// span, a template error dA and an error dH_q of the quadrature M-terms move
+// F = 1/2 z^H H^{-1} z (Sec. II.A, Eq. coherent_F_stat) to first order by
+//     dF = Re <r, dA beta> + Re <A beta, dA beta> - 1/2 beta^H dH_q beta
+// (the last two vanish where the M-terms are summed from the same
+// interpolated templates).  |A beta|^2 = 2F; for Gaussian noise <r, v> is a
+// normal variable of variance at most |v|^2; an item whose transfer and phase
+// interpolants are off by at most e relative to its largest transfer
+// component m contributes at most 2 e^2 m^2 sum(u) to |dA_k|^2 (k = +, x),
+// and each entry of its quadrature M-terms is off by at most g (the
+// quadrature's end-point error times max u|T|^2 times its bin count).  So
+//   |dF| <~ sqrt 2 (kappa + sqrt(2F)) b sqrt(sum (e m)^2 sum u) + b^2 sum g / 2
+// with b = |beta_+| + |beta_x| and kappa = kRefineKappa covering six standard
+// deviations of the noise and an unmatched signal of SNR 10 in the
+// partition.  Where this exceeds budget * max(|F|, 1), the items whose share
+// of either term is above half the budget's share are evaluated again
+// exactly, which brings the remainder under the budget.  Partitions within a
+// factor kFragile of the pseudo-inverse cut are refined whole (a small error
+// could flip the rank decision).
+constexpr double kRefineKappa = 16.0;
+constexpr double kFragile = 1e3;
 __global__ void k_mark(const PartConst* __restrict__ pc, int64_t n, int32_t stride,
                        const int32_t* __restrict__ cnt, const int32_t* __restrict__ off,
                        const double* __restrict__ partials, const uint8_t* __restrict__ xflag,
-                       const float* __restrict__ xerr, double budget,
+                       const float2* __restrict__ xerr, double budget,
                        int32_t* __restrict__ refine, int32_t* __restrict__ nrefine) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n * stride) return;
@@ -1366,11 +1427,13 @@ __global__ void k_mark(const PartConst* __restrict__ pc, int64_t n, int32_t stri
   if (l >= P.np || P.status != kStatusOk) return;
   const int o = off[q], c = cnt[q];
   int ninterp = 0;
-  double emax = 1e-16;
+  double s2 = 0.0, mt = 0.0;
   for (int i = 0; i < c; ++i)
     if (xflag[o + i] == 0) {
       ++ninterp;
-      emax = fmax(emax, (double)xerr[o + i]);
+      const float2 x = xerr[o + i];
+      s2 = fma((double)x.x, (double)x.x, s2);
+      mt += (double)x.y;
     }
   if (ninterp == 0) return;
   double a[8], e[8];
@@ -1387,19 +1450,75 @@ __global__ void k_mark(const PartConst* __restrict__ pc, int64_t n, int32_t stri
   const double hs = 0.5 * (Pm + Qm), hd = 0.5 * (Pm - Qm);
   const double lp = hs + sqrt(hd * hd + rr * rr + ri * ri);
   const double lm = (Pm * Qm - (rr * rr + ri * ri)) / lp;
-  // F moves by up to 2 cond(M) e for a relative template error e, e the
-  // largest error among the partition's interpolated items: re-evaluating the
-  // items above budget / (2 cond) brings the bound under the budget
-  if (!(lp > 0.0) || !(2.0 * emax * lp <= budget * lm)) {
-    const bool all = !(lp > 0.0) || !(lm > 0.0);
-    const double thr = all ? 0.0 : budget * lm / (2.0 * lp);
-    int nsel = 0;
-    for (int i = 0; i < c; ++i)
-      if (xflag[o + i] == 0 && (all || (double)xerr[o + i] > thr)) ++nsel;
-    int at = atomicAdd(nrefine, nsel);
-    for (int i = 0; i < c; ++i)
-      if (xflag[o + i] == 0 && (all || (double)xerr[o + i] > thr)) refine[at++] = o + i;
+  const bool all = !(lp > 0.0) || !(lm > kFragile * kRankCut * lp);
+  double thr_t = 0.0, thr_m = 0.0;
+  if (!all) {
+    double beta[4];
+    solve_beta(a, beta);
+    const double F = solve_partition(a);
+    const double b = hypot(beta[0], beta[1]) + hypot(beta[2], beta[3]);
+    const double kt = 1.4142135623730951 * (kRefineKappa + sqrt(2.0 * fmax(F, 0.0))) * b;
+    const double km = 0.5 * b * b;
+    const double tol = budget * fmax(fabs(F), 1.0);
+    if (kt * sqrt(s2) + km * mt <= tol) return;
+    // refining every item above these leaves at most tol / 2 in each term
+    thr_t = 0.5 * tol / (kt * sqrt((double)ninterp));
+    thr_m = 0.5 * tol / (km * (double)ninterp);
   }
+  auto sel = [&](int i) {
+    if (xflag[o + i] != 0) return false;
+    const float2 x = xerr[o + i];
+    return all || (double)x.x > thr_t || (double)x.y > thr_m;
+  };
+  int nsel = 0;
+  for (int i = 0; i < c; ++i)
+    if (sel(i)) ++nsel;
+  int at = atomicAdd(nrefine, nsel);
+  for (int i = 0; i < c; ++i)
+    if (sel(i)) refine[at++] = o + i;
+}
+
+// Bins of the last evaluation's items by the kind of per-bin work the
+// interpolating loop did on them: out[0..2] interpolated with quadrature
+// M-terms at transfer degree 5, 7, 9 (the mixed path's items all count as 9),
+// out[3] interpolated with per-bin M-terms, out[4] evaluated exactly (rejects;
+// refined items count where the interpolating loop ran them).
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_bin_mix(const int2* __restrict__ items,
+                                                 const int32_t* __restrict__ total,
+                                                 const int32_t* __restrict__ bounds,
+                                                 int32_t stride, int32_t T, int32_t nch,
+                                                 const double* __restrict__ rec,
+                                                 const uint8_t* __restrict__ xflag,
+                                                 unsigned long long* __restrict__ out) {
+  typedef RecLayout<MIXED> L;
+  __shared__ unsigned long long acc[5];
+  if (threadIdx.x < 5) acc[threadIdx.x] = 0ull;
+  __syncthreads();
+  const int W = total[0];
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
+    const int2 it = items[w];
+    const int p = it.x / stride, l = it.x - p * stride;
+    const int32_t* bp = bounds + (int64_t)p * (stride + 1);
+    int ct, ch, b0, b1;
+    item_split(it.y, nch, ct, ch);
+    item_bins(bp[l], bp[l + 1], ct, T, b0, b1);
+    int kind = 4;
+    if (!xflag[w]) {
+      const double* r = rec + (int64_t)w * kRec;
+      const int deg = (int)r[L::tail + 4];
+      kind = r[L::tail + 3] == 0.0 ? 3 : (deg == 5 ? 0 : (deg == 7 ? 1 : 2));
+    }
+    atomicAdd(&acc[kind], (unsigned long long)(b1 - b0));
+  }
+  __syncthreads();
+  if (threadIdx.x < 5 && acc[threadIdx.x]) atomicAdd(&out[threadIdx.x], acc[threadIdx.x]);
+}
+
+void launch_bin_mix(bool mixed, int32_t stride, int32_t chunk, int32_t nch, const WorkSpace& ws,
+                    unsigned long long* out, hipStream_t s) {
+  hipLaunchKernelGGL(mixed ? k_bin_mix<true> : k_bin_mix<false>, dim3(1024), dim3(256), 0, s,
+                     ws.items, ws.total, ws.bounds, stride, chunk, nch, ws.rec, ws.xflag, out);
 }
 
 // ---- grouping of the work items by bin tile ---------------------------------
@@ -1570,10 +1689,19 @@ int interp_tables_init() {
     E6[1][kk] = (double)lp6;
   }
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_s), S, sizeof(S)) != hipSuccess) return -1;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_G), G, sizeof(G)) != hipSuccess) return -1;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_E), E, sizeof(E)) != hipSuccess) return -1;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_G6), G6, sizeof(G6)) != hipSuccess) return -1;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_E6), E6, sizeof(E6)) != hipSuccess) return -1;
+  double R9[kCheb][kLanesItem], R6[kCheb][kLanesItem];
+  for (int kk = 0; kk < K; ++kk) {
+    for (int n = 0; n < K; ++n) {
+      R9[kk][n] = G[kk][n];
+      R6[kk][n] = n <= kDegT ? G6[kk][n] : 0.0;
+    }
+    for (int e = 0; e < 2; ++e) {
+      R9[kk][kCheb + e] = E[e][kk];
+      R6[kk][kCheb + e] = E6[e][kk];
+    }
+  }
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_row9), R9, sizeof(R9)) != hipSuccess) return -1;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_row6), R6, sizeof(R6)) != hipSuccess) return -1;
   // truncations after degree 5 and 7 (FP64 loop)
   double Gt[2][kCheb][kCheb], Et[2][2][kCheb];
   for (int v = 0; v < 2; ++v) {
@@ -1592,8 +1720,13 @@ int interp_tables_init() {
       Et[v][1][kk] = (double)lp;
     }
   }
-  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_Gt), Gt, sizeof(Gt)) != hipSuccess) return -1;
-  if (hipMemcpyToSymbol(HIP_SYMBOL(c_cheb_Et), Et, sizeof(Et)) != hipSuccess) return -1;
+  double Rt[2][kCheb][kLanesItem];
+  for (int v = 0; v < 2; ++v)
+    for (int kk = 0; kk < K; ++kk) {
+      for (int n = 0; n < K; ++n) Rt[v][kk][n] = Gt[v][kk][n];
+      for (int e = 0; e < 2; ++e) Rt[v][kk][kCheb + e] = Et[v][e][kk];
+    }
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_rowt), Rt, sizeof(Rt)) != hipSuccess) return -1;
   // quadrature weights' Chebyshev part (even degrees only)
   double D[5][kCheb];
   for (int i = 0; i < 5; ++i)
@@ -2101,6 +2234,15 @@ void launch_sur_check(const Grid& g, int32_t stride, int64_t n, const WorkSpace&
                      ws.bounds, stride, n, ynn, ek, mm);
   hipLaunchKernelGGL(k_sur_decide, dim3(nblk(n, 128)), dim3(128), 0, s, ws.pc, n, stride, mm, thr,
                      counters);
+}
+
+int uprefix_block_sums(int64_t n) { return (int)((n + kScanBlock - 1) / kScanBlock); }
+
+void launch_uprefix(const double* u, int64_t n, double* bsum, double* out, hipStream_t s) {
+  const int32_t nb = uprefix_block_sums(n);
+  hipLaunchKernelGGL(k_uscan_sums, dim3(nb), dim3(1024), 0, s, u, n, bsum);
+  hipLaunchKernelGGL(k_uscan_top, dim3(1), dim3(1024), 0, s, bsum, nb);
+  hipLaunchKernelGGL(k_uscan_apply, dim3(nb), dim3(1024), 0, s, u, n, bsum, out);
 }
 
 void launch_ufit(const double* u, int64_t nbins, int32_t ntiles, double* coef, double* resid,

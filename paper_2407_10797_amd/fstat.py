@@ -34,7 +34,7 @@ EXPORTS = ("fstat_plan_create", "fstat_plan_set_orbit", "fstat_eval", "fstat_eva
            "fstat_search", "fstat_search_boxes",
            "fstat_profile_read", "fstat_interp_stats", "fstat_autotune", "fstat_mlp_grad", "fstat_mlp_forward",
            "fstat_surrogate_train", "fstat_surrogate_stats", "fstat_plan_destroy",
-           "fstat_last_error")
+           "fstat_calibrate", "fstat_last_error")
 
 
 class fstat_data_desc(ctypes.Structure):
@@ -143,7 +143,7 @@ def lib() -> ctypes.CDLL:
         L.fstat_mlp_grad.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double), vp, vp]
         L.fstat_mlp_grad.restype = ctypes.c_int
         L.fstat_interp_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
-                                         ctypes.POINTER(i64), vp]
+                                         ctypes.POINTER(i64), vp, vp]
         L.fstat_interp_stats.restype = ctypes.c_int
         L.fstat_mlp_forward.argtypes = [vp, vp, i64, vp]
         L.fstat_mlp_forward.restype = ctypes.c_int
@@ -154,6 +154,9 @@ def lib() -> ctypes.CDLL:
         L.fstat_autotune.argtypes = [vp, vp, i64, i32, u32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                      ctypes.POINTER(ctypes.c_double), vp]
         L.fstat_autotune.restype = ctypes.c_int
+        L.fstat_calibrate.argtypes = [i32, i64, i32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double), vp]
+        L.fstat_calibrate.restype = ctypes.c_int
         L.fstat_plan_destroy.argtypes = [vp]
         L.fstat_plan_destroy.restype = None
         L.fstat_last_error.argtypes = []
@@ -190,6 +193,18 @@ def fstat_eval_noalloc(plan, params, n, np_ptr, np_uniform, F_hat, F_part, amps,
                        flags, stream=None):
     _check(lib().fstat_eval_noalloc(plan, params, int(n), np_ptr, int(np_uniform), F_hat, F_part,
                                     amps, int(part_stride), int(flags), stream))
+
+
+FSTAT_CALIB_FMA64, FSTAT_CALIB_FMA32, FSTAT_CALIB_COPY = 0, 1, 2
+
+
+def calibrate(kind: int, size: int, reps: int = 10):
+    """Measured peak of one resource: (rate, ms per launch); rate in TFLOP/s
+    for the FMA kinds, GB/s (read + written) for the copy."""
+    rate, ms = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().fstat_calibrate(int(kind), int(size), int(reps), ctypes.byref(rate),
+                                 ctypes.byref(ms), _stream()))
+    return rate.value, ms.value
 
 
 def fstat_plan_set_orbit(plan, t0, dt, n_seg, nodes, flags, stream=None):
@@ -290,10 +305,13 @@ def fstat_mlp_grad(params, x, t):
     return loss.value, grad, y
 
 
-def fstat_interp_stats(plan, stream=None):
+def fstat_interp_stats(plan, stream=None, bin_mix=False):
     items, rej, ref = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    mix = (ctypes.c_int64 * 5)() if bin_mix else None
     _check(lib().fstat_interp_stats(plan, ctypes.byref(items), ctypes.byref(rej), ctypes.byref(ref),
-                                    stream))
+                                    mix, stream))
+    if bin_mix:
+        return items.value, rej.value, ref.value, list(mix)
     return items.value, rej.value, ref.value
 
 
@@ -494,10 +512,12 @@ class Plan:
                  | (FSTAT_AUTOTUNE_FORCE if force else 0) | (FSTAT_EVAL_EXACT if exact else 0))
         return fstat_autotune(self.handle, prm.data_ptr(), prm.shape[0], int(np_parts), flags, _stream())
 
-    def interp_stats(self):
+    def interp_stats(self, bin_mix: bool = False):
         """(work items, items handed to the exact loop, items refined exactly) of
-        the last evaluation."""
-        return fstat_interp_stats(self.handle, _stream())
+        the last evaluation, and with bin_mix the bins by kind of per-bin work
+        ([0..2] N-terms only at transfer degree 5, 7, 9; [3] N- and M-terms;
+        [4] exact)."""
+        return fstat_interp_stats(self.handle, _stream(), bin_mix)
 
     def surrogate_stats(self):
         """(particles that used the surrogate, particles that fell back) in the last

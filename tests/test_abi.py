@@ -22,7 +22,8 @@ def test_header_declares_the_boundary():
                                   "fstat_autotune",
                                   "fstat_mlp_grad", "fstat_mlp_forward",
                                   "fstat_surrogate_train", "fstat_surrogate_stats",
-                                  "fstat_plan_destroy", "fstat_last_error"])
+                                  "fstat_calibrate", "fstat_plan_destroy",
+                                  "fstat_last_error"])
 
 
 def test_library_loads_and_exports_every_declared_symbol():

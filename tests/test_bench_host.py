@@ -22,12 +22,29 @@ def test_more_than_one_gpu_is_refused():
 def test_mixed_peak_is_the_time_floor_of_the_operation_mix():
     import bench
     # all FP64 -> the FP64 peak; all FP32 -> the FP32 peak; a mix lies between
-    assert bench._peak_tflops("fp64") == pytest.approx(bench.PEAK_VALU_TFLOPS, rel=1e-3)
-    f = bench.FLOP_PER_BIN["mixed"]
-    f32 = bench.FLOP32_PER_BIN["mixed"]
-    expect = f / ((f - f32) / bench.PEAK_VALU_TFLOPS + f32 / bench.PEAK_F32_TFLOPS)
-    assert bench._peak_tflops("mixed") == pytest.approx(expect)
-    assert bench.PEAK_VALU_TFLOPS < bench._peak_tflops("mixed") < bench.PEAK_F32_TFLOPS
+    p64, p32 = bench.PEAK_VALU_TFLOPS, bench.PEAK_F32_TFLOPS
+    assert bench.floor_peak(1.0, 0.0, p64, p32) == pytest.approx(p64)
+    assert bench.floor_peak(0.0, 1.0, p64, p32) == pytest.approx(p32)
+    f64, f32 = bench.ALG_MIXED["n_only"]
+    expect = (f64 + f32) / (f64 / p64 + f32 / p32)
+    assert bench.floor_peak(f64, f32, p64, p32) == pytest.approx(expect)
+    assert p64 < bench.floor_peak(f64, f32, p64, p32) < p32
+
+
+def test_algorithmic_flops_follow_the_bin_mix():
+    """Per-bin algorithmic counts of the interpolating loop: 63 + 4 (D - 1)
+    FLOPs for the moment loop at transfer degree D, and the launch total is
+    the bin-weighted sum of its kinds (exact-loop bins are not the main
+    kernel's work)."""
+    import bench
+    for d in (5, 7, 9):
+        assert bench.ALG_FP64[f"deg{d}"] == 63 + 4 * (d - 1)
+    mix = [10, 20, 30, 4, 1000]
+    f64, f32 = bench.alg_flops("fp64", mix)
+    assert f32 == 0.0
+    assert f64 == 10 * 79 + 20 * 87 + 30 * 95 + 4 * 132
+    m64, m32 = bench.alg_flops("mixed", mix)
+    assert (m64, m32) == (60 * 24 + 4 * 44, 60 * 37 + 4 * 70)
 
 
 def test_counter_figures_match_the_kernel_sources():

@@ -20,6 +20,7 @@ from tests.bars import FP64_KCOND, FP64_REL
 pytestmark = pytest.mark.gpu
 EPS32 = 2.0 ** -24
 MIXED_SQRT_COND = 20 * EPS32
+REFINE_BUDGET = 5e-10   # the plan's default refinement budget (fstat_opts.refine_budget)
 
 
 @pytest.fixture(scope="module")
@@ -140,17 +141,32 @@ def test_paper_scale_sampled_parity(paper, torch_cuda, npart):
 @pytest.mark.parametrize("npart", [1, 16, 64, 256])
 def test_paper_scale_interpolating_matches_exact_everywhere(paper, torch_cuda, npart):
     """Every partition of all 4096 particles: the interpolating loop (the
-    benchmark's path) against the exact template at every bin, 1e-10 relative
-    (|F| floored at 1)."""
+    benchmark's path) against the exact template at every bin, within the
+    plan's refinement budget (5e-10 relative, |F| floored at 1) plus the
+    rounding allowance 4 eps cond(M_l) of two FP64 evaluations."""
     s = paper
     print(f"[paper] interpolating vs exact, 4096 particles, Np={npart}", flush=True)
     F, P = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, want_parts=True)
+    items, rej, ref = s["plan"].interp_stats()
     Fe, Pe = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, want_parts=True, exact=True)
     P, Pe = P.cpu().numpy()[:, :npart], Pe.cpu().numpy()[:, :npart]
     r = _rel(P, Pe)
-    print(f"  max rel {r.max():.2e}, median {np.median(r):.2e}", flush=True)
-    assert np.all(r <= 1e-10)
-    np.testing.assert_allclose(F.cpu().numpy(), Fe.cpu().numpy(), rtol=1e-10, atol=1e-10)
+    print(f"  {items} items, {rej} exact, {ref} refined; max rel {r.max():.2e}, p99.99 "
+          f"{np.quantile(r, 0.9999):.2e}, median {np.median(r):.2e}", flush=True)
+    # partitions above the budget alone: their conditioning from the oracle
+    # (a handful of particles) must account for the excess
+    out = np.unique(np.nonzero(r > REFINE_BUDGET)[0])
+    if out.size:
+        assert out.size <= 16, out.size
+        _, Po, cond = O.fstat(s["data"], s["psd"], s["g"].k_lo, s["g"].df, s["g"].T_obs,
+                              s["pts"][out], [npart], want_cond=True)
+        c = np.where(np.isfinite(cond), cond, 0.0)
+        excess = np.max((r[out] - REFINE_BUDGET) / (FP64_KCOND * c + 1e-300))
+        print(f"  {out.size} particles above the budget; largest excess / (4 eps cond) "
+              f"{excess:.3f}, their cond up to {c.max():.2e}", flush=True)
+        assert np.all(r[out] <= REFINE_BUDGET + FP64_KCOND * c)
+    Fh, Fhe = F.cpu().numpy(), Fe.cpu().numpy()
+    assert np.all(_rel(Fh, Fhe) <= 2.0 * np.max(r, axis=1) + 1e-15)   # F_l >= 0
 
 
 def test_paper_scale_numerical_orbit_sampled_parity(paper, torch_cuda):

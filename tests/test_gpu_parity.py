@@ -89,8 +89,9 @@ def test_small_workload_matches_oracle(small, torch_cuda, npart):
 @pytest.mark.parametrize("npart", [1, 16, 256])
 def test_interpolating_and_exact_bin_loops_agree(small, torch_cuda, npart):
     """Default (per-item interpolation of the smooth factors, with exact
-    fallback) vs FSTAT_EVAL_EXACT (exact template at every bin): 1e-10 relative
-    per partition, plus 4 eps cond(M_l); both against the oracle elsewhere."""
+    fallback) vs FSTAT_EVAL_EXACT (exact template at every bin): within the
+    plan's refinement budget (5e-10 relative) per partition, plus 4 eps
+    cond(M_l); both against the oracle elsewhere."""
     s = small
     _, _, cond = O.fstat(s["data"], s["psd"], s["g"].k_lo, s["g"].df, s["g"].T_obs, s["pts"],
                          [npart], want_cond=True)
@@ -108,7 +109,7 @@ def test_interpolating_and_exact_bin_loops_agree(small, torch_cuda, npart):
     P, Pe = P.cpu().numpy(), Pe.cpu().numpy()
     c = np.where(np.isfinite(cond[:, :npart]), cond[:, :npart], 0.0)
     r = _rel(P[:, :npart], Pe[:, :npart])
-    assert np.all(r <= 1e-10 + FP64_KCOND * c), float(r.max())
+    assert np.all(r <= 5e-10 + FP64_KCOND * c), float(r.max())
 
 
 def test_uneven_np_in_one_launch(small, torch_cuda):
