@@ -298,16 +298,38 @@ def orbit_bench(plan, g, pts, npart, steps, warmup, mixed):
                        "bins as the analytic-orbit line")
 
 
-def cpu_baseline(g, data, psd, pts, npart, sample):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, data, psd, pts, npart, sample, sample_1core):
+    """The oracle (built here with -O3 -march=native, plain IEEE double) on a
+    sample of the batch: all the threads OpenMP is given, then one thread."""
     from oracle import oracle as O
-    sub = pts[:sample]
+    O.use_native()
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    O.set_threads(threads)
     t0 = time.perf_counter()
-    O.fstat(data, psd, g.k_lo, g.df, g.T_obs, sub, [npart])
+    O.fstat(data, psd, g.k_lo, g.df, g.T_obs, pts[:sample], [npart])
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": sample / dt, "unit": "templates/s", "cores": cores, "kind": "oracle",
+    O.set_threads(1)
+    t0 = time.perf_counter()
+    O.fstat(data, psd, g.k_lo, g.df, g.T_obs, pts[sample:sample + sample_1core], [npart])
+    dt1 = time.perf_counter() - t0
+    O.set_threads(threads)
+    return {"value": sample / dt, "unit": "templates/s", "cores": threads, "kind": "oracle",
             "sample": f"{sample} of the {len(pts)} particles, Np={npart}, full 7,101,001-bin data, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s on {threads} threads; one thread: {sample_1core} further "
+                      f"particles in {dt1:.1f} s",
+            "value_1core": sample_1core / dt1, "cpu_model": _cpu_model(),
+            "build": "gcc -O3 -march=native -fopenmp -ffp-contract=off -fno-fast-math"}
 
 
 def main():
@@ -318,6 +340,7 @@ def main():
     ap.add_argument("--np", type=int, default=64)
     ap.add_argument("--particles", type=int, default=4096)
     ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--cpu-sample-1core", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-aet", action="store_true", help="skip the three-channel measurement")
@@ -489,7 +512,8 @@ def main():
              f"{out['pso']['eager']['iterations_per_s']:.1f} eager")
     if not args.no_cpu:
         _log("timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(g, data, psd, pts, args.np, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(g, data, psd, pts, args.np, args.cpu_sample,
+                                           args.cpu_sample_1core)
     print(json.dumps(out), flush=True)
 
 

@@ -33,7 +33,29 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+_LIB_NATIVE = os.path.join(_HERE, "libfstat_oracle_native.so")
+
+
+def build_native() -> str:
+    """The same oracle tuned for the host it runs on (-O3 -march=native; still
+    plain IEEE double, no contraction, no fast math), for timing the CPU
+    baseline only: built where it runs, since the host may differ from the one
+    that built the default copy."""
+    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
+           "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", _LIB_NATIVE + ".tmp", "-lquadmath",
+           "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_LIB_NATIVE + ".tmp", _LIB_NATIVE)
+    return _LIB_NATIVE
+
+
 _lib = None
+
+
+def use_native() -> None:
+    """Route the wrappers below through the host-tuned copy (build_native)."""
+    global _lib
+    _lib = _load(build_native())
 
 
 def lib():
@@ -41,7 +63,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
+        _lib = _load(_LIB)
+    return _lib
+
+
+def _load(path):
+    if True:
+        L = ctypes.CDLL(path)
         L.or_set_pn_order.argtypes = [ctypes.c_int]
         L.or_phase.argtypes = [_dp, ctypes.c_double, _dp, ctypes.c_int64, _dp, _dp]
         L.or_tf.argtypes = [_dp, _dp, ctypes.c_int64, _dp]
@@ -59,8 +87,12 @@ def lib():
         L.or_fstat.argtypes = [_dp, _dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
                                ctypes.c_double, _dp, ctypes.c_int64, _i32p, ctypes.c_int32,
                                _dp, _dp, ctypes.c_int64, _dp, _dp, _i32p, ctypes.c_int32]
-        _lib = L
-    return _lib
+    return L
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's particle loop (libgomp, process-wide)."""
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
 
 
 def _d(a):
