@@ -167,7 +167,7 @@ def pso_boxes(inj, R, seed=4001):
     return boxes
 
 
-def pso_bench(iters):
+def pso_bench(iters, surrogate=True):
     """Batched PSO stage on the 20,972-bin workload: 8 runs x 40 particles,
     per-run Np 256/64/16/1 in every launch, (w, c1, c2) = (0.7, 1.5, 1.5)."""
     import torch
@@ -181,6 +181,10 @@ def pso_bench(iters):
     boxes = pso_boxes(inj, 8)
     nps = np.array([256, 64, 16, 1] * 2, dtype=np.int32)
     out = {}
+    # work-item shape for this batch: 40 points from each run's box at Np = 64
+    pts = np.vstack([S.uniform_box(boxes[r], 40, 4100 + r) for r in range(len(boxes))])
+    c, m, _ = plan.autotune(torch.from_numpy(pts).cuda(), 64)
+    out["tuned_chunk"], out["tuned_grid_mult"] = int(c), int(m)
     for mode, graph in (("graph", True), ("eager", False)):
         plan.pso(boxes, nps, n_part=40, iters=20, use_graph=graph, seed=4001)   # warm-up
         torch.cuda.synchronize()
@@ -192,8 +196,46 @@ def pso_bench(iters):
     out["best_F"] = [float(x) for x in res["best_F"]]
     out["config"] = "8 runs x 40 particles, per-run Np 256/64/16/1, 20,972-bin data, " \
                     f"{iters} iterations, w=0.7 c1=c2=1.5 vmax=0.5 ring radius 1"
+    if surrogate:
+        out["surrogate"] = pso_surrogate_report(plan, boxes, nps, iters, res, inj)
     plan.close()
     return out
+
+
+def _recovery(x, inj):
+    """Errors of estimates x [R, 6] against the injection: relative Mc, t_c in
+    seconds, sky angle in radians, absolute e0."""
+    th, ph = x[:, 3], x[:, 4]
+    cosd = (np.sin(th) * np.sin(inj[3]) * np.cos(ph - inj[4]) + np.cos(th) * np.cos(inj[3]))
+    return dict(Mc_rel=np.abs(x[:, 1] / inj[1] - 1.0).tolist(),
+                tc_s=np.abs(x[:, 0] - inj[0]).tolist(),
+                sky_rad=np.arccos(np.clip(cosd, -1.0, 1.0)).tolist(),
+                e0_abs=np.abs(x[:, 5] - inj[5]).tolist())
+
+
+def pso_surrogate_report(plan, boxes, nps, iters, res_plain, inj):
+    """The batched PSO stage with the learned eccentric-phase surrogate in its
+    Np >= 16 runs (the Np = 1 runs keep the analytic template), same seed as
+    the plain run: throughput, fallback counts and the recovered parameters of
+    both, against the injection."""
+    import torch
+    t0 = time.perf_counter()
+    rep = plan.train_surrogate(steps=3000)
+    train_s = time.perf_counter() - t0
+    plan.pso(boxes, nps, n_part=40, iters=20, use_graph=True, seed=4001, surrogate=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = plan.pso(boxes, nps, n_part=40, iters=iters, use_graph=True, seed=4001, surrogate=True)
+    dt = time.perf_counter() - t0
+    used, fb = plan.surrogate_stats()
+    plain = _recovery(res_plain["best_x"], inj)
+    sur = _recovery(res["best_x"], inj)
+    return dict(iterations_per_s=iters / dt, train_s=train_s, val_rmse=rep["val_rmse"],
+                last_iteration_used=used, last_iteration_fallback=fb,
+                best_F=[float(x) for x in res["best_F"]], np_runs=[int(v) for v in nps],
+                recovered_plain=plain, recovered_surrogate=sur,
+                best_x_rel_diff=(np.abs(res["best_x"] - res_plain["best_x"])
+                                 / np.maximum(np.abs(res_plain["best_x"]), 1e-300)).tolist())
 
 
 def search_bench(iters, ckpt, last_stage=3, resume=False):

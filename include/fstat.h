@@ -415,8 +415,19 @@ typedef struct {
 int fstat_surrogate_train(fstat_plan_t plan, fstat_surrogate_desc *desc, void *hip_stream);
 
 /* Particles of the last FSTAT_EVAL_SURROGATE evaluation that used the
- * surrogate and that fell back to the analytic template.                  */
-int fstat_surrogate_stats(fstat_plan_t plan, int64_t *used, int64_t *fallback);
+ * surrogate and that fell back to the analytic template; flags [n] (host, or
+ * NULL): 1 where particle i of that evaluation used the surrogate, else 0
+ * (n at most that evaluation's particle count).  EINVAL before any surrogate
+ * evaluation or for n beyond the last evaluation.                         */
+int fstat_surrogate_stats(fstat_plan_t plan, int64_t *used, int64_t *fallback, int32_t *flags,
+                          int64_t n);
+
+/* The surrogate network's weights (host arrays of 198,657 floats in the flat
+ * layout of fstat_mlp_grad): `out` (or NULL) receives the plan's trained
+ * weights; `in` (or NULL) replaces them and marks the surrogate trained, for
+ * reuse of one training across plans.  Waits for completion.  EINVAL: null
+ * plan, `out` without a trained surrogate, non-finite weights in `in`.    */
+int fstat_surrogate_params(fstat_plan_t plan, const float *in, float *out, void *hip_stream);
 
 /* Measured peaks for the roofline (not part of the statistic): kind
  *   FSTAT_CALIB_FMA64  chains of FP64 fused multiply-adds, `size` rounds of

@@ -234,6 +234,7 @@ int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t*
   if (rc) return rc;
   if ((rc = ensure_workspace(P, n, stride, chunk_for(P, mixed)))) return rc;
   if (surrogate && (rc = sur_ensure(P, n, stride))) return rc;
+  P->last.n = n;
   P->last.stride = stride;
   P->last.chunk = chunk_for(P, mixed);
   P->last.mixed = mixed;

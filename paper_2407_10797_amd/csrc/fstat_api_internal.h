@@ -52,6 +52,7 @@ struct fstat_plan_s {
     double* amps = nullptr;
   } io;
   struct {                          // shape of the last fstat_eval (fstat_interp_stats)
+    int64_t n = 0;
     int32_t stride = 0, chunk = 0;
     bool mixed = false, exact = false;
   } last;

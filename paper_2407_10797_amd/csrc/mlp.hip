@@ -19,8 +19,17 @@
 
 namespace fstat {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// gfx950's 16x16x32 BF16 MFMA: lane l supplies A[l % 16][k] and B[k][l % 16]
+// for its eight k of group l / 16 (the same k for A and B, so the order of k
+// within a group does not matter), and receives D[4 (l / 16) + r][l % 16].
+__device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                 __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
 
 __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
   uint32_t u = __float_as_uint(f);
@@ -38,13 +47,14 @@ __device__ __forceinline__ float dsilu(float z) {
 // ---------------------------------------------------------------------------
 // C[m][n] = sum_k A(m,k) B(k,n), A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn]
 // (BF16), FP32 accumulate.  Block = 4 wavefronts = 64x64 outputs, each wave a
-// 32x32 quadrant of 2x2 MFMA 16x16x16 tiles; K advances 16 at a time through
-// LDS.  M, N multiples of 64, K a multiple of 16 (checked by the host).
+// 32x32 quadrant of 2x2 MFMA 16x16x32 tiles; K advances 32 at a time through
+// LDS.  M, N multiples of 64, K a multiple of 32 (checked by the host).
 // Split K: block z covers k in [z * kper, (z + 1) * kper) and writes C + z * cz.
 // Epilogue FWD: z = acc + bias[n] -> Z[m][n] (FP32), H[m][n] = bf16(SiLU(z)).
 // Epilogue STORE: C[m][n] = acc.
 // ---------------------------------------------------------------------------
 enum { kEpiFwd = 0, kEpiStore = 1 };
+constexpr int kGemmK = 32;
 
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t* __restrict__ A, int64_t sam,
@@ -54,8 +64,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t* __restrict__ 
                                                    const float* __restrict__ bias,
                                                    uint16_t* __restrict__ H, int64_t ldh,
                                                    int kper, int64_t cz) {
-  __shared__ uint16_t As[64][16 + 4];
-  __shared__ uint16_t Bs[16][64 + 4];
+  __shared__ __align__(16) uint16_t As[64][kGemmK + 8];   // rows of 80 B (16-byte multiple)
+  __shared__ uint16_t Bs[kGemmK][64 + 4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int wr = w >> 1, wc = w & 1;
@@ -66,30 +76,28 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t* __restrict__ 
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kbeg; k0 < kend; k0 += 16) {
+  for (int k0 = kbeg; k0 < kend; k0 += kGemmK) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {       // 64x16 A tile and 16x64 B tile, 4 elements per thread
-      int idx = t * 4 + e;
-      int ar = idx >> 4, ak = idx & 15;
+    for (int e = 0; e < 8; ++e) {       // 64x32 A tile and 32x64 B tile, 8 elements per thread
+      int idx = t * 8 + e;
+      int ar = idx >> 5, ak = idx & 31;
       As[ar][ak] = A[(int64_t)(m0 + ar) * sam + (int64_t)(k0 + ak) * sak];
       int bk = idx >> 6, bn = idx & 63;
       Bs[bk][bn] = B[(int64_t)(k0 + bk) * sbk + (int64_t)(n0 + bn) * sbn];
     }
     __syncthreads();
-    const int kb = 4 * (lane >> 4), rr = lane & 15;
+    const int kb = 8 * (lane >> 4), rr = lane & 15;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      v4s a;
       const int row = 32 * wr + 16 * i + rr;
-      a[0] = (short)As[row][kb + 0]; a[1] = (short)As[row][kb + 1];
-      a[2] = (short)As[row][kb + 2]; a[3] = (short)As[row][kb + 3];
+      const v8s a = *reinterpret_cast<const v8s*>(&As[row][kb]);
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        v4s b;
+        v8s b;
         const int col = 32 * wc + 16 * j + rr;
-        b[0] = (short)Bs[kb + 0][col]; b[1] = (short)Bs[kb + 1][col];
-        b[2] = (short)Bs[kb + 2][col]; b[3] = (short)Bs[kb + 3][col];
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) b[q] = (short)Bs[kb + q][col];
+        acc[i][j] = mfma32(a, b, acc[i][j]);
       }
     }
     __syncthreads();
@@ -252,41 +260,42 @@ __global__ void k_sum_dy(const float* __restrict__ dy, int B, float* __restrict_
 
 // Inference-only forward of the whole network on R rows, keeping no
 // activations (knot evaluation).  One wavefront per 16 rows, four per block;
-// the weights pass through LDS in 8 KB k-slabs shared by the four waves.
-// Layer 1 runs on the VALU straight into the MFMA A-operand layout (lane l:
-// row l % 16, k = 16 kb + 4 (l / 16) + j); layers 2-4 are 16x16x16 BF16 MFMA
-// tiles over all 256 outputs with the weights' BF16 copies read from the LDS
-// slabs in the B-operand layout (col l % 16, same k); between layers the
-// 16x256 tile goes through the wave's own LDS rows to turn the D layout (row 4 (l / 16)
-// + r, col l % 16) back into the A layout.  The output unit is a lane
-// reduction.  Same operand rounding as the training forward: BF16 hidden
-// activations, FP32 last pre-activation, FP32 output layer.
+// the weights pass through LDS in 16 KB k-slabs of 32 shared by the four
+// waves.  Layer 1 runs on the VALU straight into the MFMA A-operand layout
+// (lane l: row l % 16, k = 32 kb + 8 (l / 16) + j); layers 2-4 are 16x16x32
+// BF16 MFMA tiles over all 256 outputs with the weights' BF16 copies read from
+// the LDS slabs in the B-operand layout (col l % 16, same k); between layers
+// the 16x256 tile goes through the wave's own LDS rows to turn the D layout
+// (row 4 (l / 16) + r, col l % 16) back into the A layout.  The output unit
+// is a lane reduction.  Same operand rounding as the training forward: BF16
+// hidden activations, FP32 last pre-activation, FP32 output layer.
 __global__ __launch_bounds__(256, 2) void k_mlp_infer(const float* __restrict__ x, int64_t R,
                                                    const float* __restrict__ P,
                                                    const uint16_t* __restrict__ wbf,
                                                    float* __restrict__ y) {
-  __shared__ uint16_t T[4][16][kHid + 8];
-  __shared__ __align__(16) uint16_t Ws[2][kHid][16 + 4];   // two k-slabs of W (rows n, 16 k)
+  __shared__ __align__(16) uint16_t T[4][16][kHid + 8];
+  __shared__ __align__(16) uint16_t Ws[2][kHid][kGemmK + 8];   // two k-slabs of W (rows n, 32 k)
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c16 = lane & 15, g4 = lane >> 4;
   const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 16;
   const int64_t row = r0 + c16 < R ? r0 + c16 : R - 1;
   const float x0 = x[row * 3 + 0], x1 = x[row * 3 + 1], x2 = x[row * 3 + 2];
-  v4s a[16];
+  constexpr int NK = kHid / kGemmK;
+  v8s a[NK];
   {
     const float* W1 = P + mlp_off_w(0);
     const float* b1 = P + mlp_off_b(0);
 #pragma unroll
-    for (int kb = 0; kb < 16; ++kb)
+    for (int kb = 0; kb < NK; ++kb)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = 16 * kb + 4 * g4 + j;
+      for (int j = 0; j < 8; ++j) {
+        const int k = kGemmK * kb + 8 * g4 + j;
         float z = b1[k] + W1[3 * k] * x0 + W1[3 * k + 1] * x1 + W1[3 * k + 2] * x2;
         a[kb][j] = (short)f2bf(silu(z));
       }
   }
   v4f acc[16];
-  // W_l[n][k] in k-slabs of 16 (8 KB), staged in LDS once for the block's four
+  // W_l[n][k] in k-slabs of 32 (16 KB), staged in LDS once for the block's four
   // waves and double-buffered: slab kb + 1 is fetched while slab kb is used
   const int tid = threadIdx.x;                      // row n of W that this thread stages
   for (int L = 0; L < 3; ++L) {
@@ -295,27 +304,28 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(const float* __restrict__ 
 #pragma unroll
     for (int nt = 0; nt < 16; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
     {
-      const uint2* src = reinterpret_cast<const uint2*>(W + (size_t)tid * kHid);
+      const uint4* src = reinterpret_cast<const uint4*>(W + (size_t)tid * kHid);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2*>(&Ws[0][tid][4 * q]) = src[q];
+      for (int q = 0; q < 4; ++q) *reinterpret_cast<uint4*>(&Ws[0][tid][8 * q]) = src[q];
     }
     __syncthreads();
 #pragma unroll
-    for (int kb = 0; kb < 16; ++kb) {
-      uint2 nxt[4];
-      if (kb + 1 < 16) {
-        const uint2* src = reinterpret_cast<const uint2*>(W + (size_t)tid * kHid + 16 * (kb + 1));
+    for (int kb = 0; kb < NK; ++kb) {
+      uint4 nxt[4];
+      if (kb + 1 < NK) {
+        const uint4* src =
+            reinterpret_cast<const uint4*>(W + (size_t)tid * kHid + kGemmK * (kb + 1));
 #pragma unroll
         for (int q = 0; q < 4; ++q) nxt[q] = src[q];
       }
 #pragma unroll
       for (int nt = 0; nt < 16; ++nt) {
-        const v4s b = *reinterpret_cast<const v4s*>(&Ws[kb & 1][16 * nt + c16][4 * g4]);
-        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[kb], b, acc[nt], 0, 0, 0);
+        const v8s b = *reinterpret_cast<const v8s*>(&Ws[kb & 1][16 * nt + c16][8 * g4]);
+        acc[nt] = mfma32(a[kb], b, acc[nt]);
       }
-      if (kb + 1 < 16) {
+      if (kb + 1 < NK) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2*>(&Ws[(kb + 1) & 1][tid][4 * q]) = nxt[q];
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<uint4*>(&Ws[(kb + 1) & 1][tid][8 * q]) = nxt[q];
       }
       __syncthreads();
     }
@@ -328,9 +338,8 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(const float* __restrict__ 
       }
       __syncthreads();
 #pragma unroll
-      for (int kb = 0; kb < 16; ++kb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) a[kb][j] = (short)T[w][c16][16 * kb + 4 * g4 + j];
+      for (int kb = 0; kb < NK; ++kb)
+        a[kb] = *reinterpret_cast<const v8s*>(&T[w][c16][kGemmK * kb + 8 * g4]);
       __syncthreads();
     }
   }
@@ -480,7 +489,7 @@ void Mlp::backward(const float* x, int B, hipStream_t s) {
   float* G = grad;
   const int sl = B / 64 < kRedSlices ? B / 64 : kRedSlices;
   int ks = kSplitK;
-  while (ks > 1 && (B % (16 * ks))) ks >>= 1;
+  while (ks > 1 && (B % (kGemmK * ks))) ks >>= 1;
   // dW5[k] = sum_m dy[m] SiLU(z4[m][k]); db5 = sum_m dy[m]
   hipLaunchKernelGGL((k_colred<1, 1, true>), dim3(kHid / 64, sl), dim3(256), 0, s, z[3], B, dy, 1, red);
   hipLaunchKernelGGL(k_colfin<1>, dim3(1), dim3(kHid), 0, s, red, sl,

@@ -205,12 +205,49 @@ extern "C" int fstat_surrogate_train(fstat_plan_t P, fstat_surrogate_desc* d, vo
   return FSTAT_OK;
 }
 
-extern "C" int fstat_surrogate_stats(fstat_plan_t P, int64_t* used, int64_t* fallback) {
+extern "C" int fstat_surrogate_stats(fstat_plan_t P, int64_t* used, int64_t* fallback,
+                                     int32_t* flags, int64_t n) {
   if (!P || !P->sur_counters) return set_error(FSTAT_EINVAL, "no surrogate evaluation yet");
+  if (flags && (n < 0 || n > P->last.n))
+    return set_error(FSTAT_EINVAL, "flags for %lld particles, the last evaluation had %lld",
+                     (long long)n, (long long)P->last.n);
   unsigned long long c[2] = {0, 0};
   int rc = hip_check(hipMemcpy(c, P->sur_counters, sizeof(c), hipMemcpyDeviceToHost), "read counters");
+  // the per-particle decision is the `sur` field of each particle's constants
+  if (!rc && flags && n > 0)
+    rc = hip_check(hipMemcpy2D(flags, sizeof(int32_t), &P->ws.pc[0].sur, sizeof(PartConst),
+                               sizeof(int32_t), (size_t)n, hipMemcpyDeviceToHost), "read flags");
   if (rc) return rc;
   if (used) *used = (int64_t)c[0];
   if (fallback) *fallback = (int64_t)c[1];
+  return FSTAT_OK;
+}
+
+extern "C" int fstat_surrogate_params(fstat_plan_t P, const float* in, float* out, void* hip_stream) {
+  if (!P) return set_error(FSTAT_EINVAL, "null plan");
+  hipStream_t s = (hipStream_t)hip_stream;
+  int rc = FSTAT_OK;
+  if (out) {
+    if (!P->sur || !P->sur_trained) return set_error(FSTAT_EINVAL, "no trained surrogate to read");
+    rc = hip_check(hipMemcpyAsync(out, P->sur->params, sizeof(float) * kNParams,
+                                  hipMemcpyDeviceToHost, s), "read surrogate weights");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "read surrogate weights");
+    if (rc) return rc;
+  }
+  if (in) {
+    for (int64_t i = 0; i < kNParams; ++i)
+      if (!std::isfinite(in[i])) return set_error(FSTAT_EINVAL, "weight %lld is not finite", (long long)i);
+    if (!P->sur) P->sur = new Mlp();
+    rc = P->sur->alloc(64);
+    if (!rc) rc = hip_check(hipMemcpyAsync(P->sur->params, in, sizeof(float) * kNParams,
+                                           hipMemcpyHostToDevice, s), "copy surrogate weights");
+    if (!rc) {
+      P->sur->refresh_bf16(s);
+      rc = hip_check(hipGetLastError(), "surrogate weights");
+    }
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "copy surrogate weights");
+    if (rc) return rc;
+    P->sur_trained = true;
+  }
   return FSTAT_OK;
 }

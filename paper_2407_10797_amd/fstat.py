@@ -33,7 +33,8 @@ EXPORTS = ("fstat_plan_create", "fstat_plan_set_orbit", "fstat_eval", "fstat_eva
            "fstat_waveform", "pso_stage",
            "fstat_search", "fstat_search_boxes",
            "fstat_profile_read", "fstat_interp_stats", "fstat_autotune", "fstat_mlp_grad", "fstat_mlp_forward",
-           "fstat_surrogate_train", "fstat_surrogate_stats", "fstat_plan_destroy",
+           "fstat_surrogate_train", "fstat_surrogate_stats", "fstat_surrogate_params",
+           "fstat_plan_destroy",
            "fstat_calibrate", "fstat_last_error")
 
 
@@ -149,8 +150,10 @@ def lib() -> ctypes.CDLL:
         L.fstat_mlp_forward.restype = ctypes.c_int
         L.fstat_surrogate_train.argtypes = [vp, ctypes.POINTER(fstat_surrogate_desc), vp]
         L.fstat_surrogate_train.restype = ctypes.c_int
-        L.fstat_surrogate_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.fstat_surrogate_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, i64]
         L.fstat_surrogate_stats.restype = ctypes.c_int
+        L.fstat_surrogate_params.argtypes = [vp, vp, vp, vp]
+        L.fstat_surrogate_params.restype = ctypes.c_int
         L.fstat_autotune.argtypes = [vp, vp, i64, i32, u32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                      ctypes.POINTER(ctypes.c_double), vp]
         L.fstat_autotune.restype = ctypes.c_int
@@ -329,10 +332,31 @@ def fstat_surrogate_train(plan, desc: fstat_surrogate_desc, stream=None):
     _check(lib().fstat_surrogate_train(plan, ctypes.byref(desc), stream))
 
 
-def fstat_surrogate_stats(plan):
+def fstat_surrogate_stats(plan, n_flags: int = 0):
     used, fb = ctypes.c_int64(), ctypes.c_int64()
-    _check(lib().fstat_surrogate_stats(plan, ctypes.byref(used), ctypes.byref(fb)))
+    flags = np.zeros(max(n_flags, 0), dtype=np.int32)
+    _check(lib().fstat_surrogate_stats(plan, ctypes.byref(used), ctypes.byref(fb),
+                                       flags.ctypes.data if n_flags > 0 else None, int(n_flags)))
+    if n_flags > 0:
+        return used.value, fb.value, flags
     return used.value, fb.value
+
+
+N_SURROGATE_PARAMS = 198657
+
+
+def fstat_surrogate_params(plan, params=None, stream=None):
+    """Set the surrogate's weights from `params` (float32 [198,657]) or, with
+    None, return the plan's trained weights."""
+    if params is not None:
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != N_SURROGATE_PARAMS:
+            raise ValueError("surrogate weights must have 198,657 values")
+        _check(lib().fstat_surrogate_params(plan, p.ctypes.data, None, stream))
+        return None
+    out = np.zeros(N_SURROGATE_PARAMS, dtype=np.float32)
+    _check(lib().fstat_surrogate_params(plan, None, out.ctypes.data, stream))
+    return out
 
 
 def fstat_autotune(plan, params, n, np_uniform, flags, stream=None):
@@ -519,10 +543,16 @@ class Plan:
         [4] exact)."""
         return fstat_interp_stats(self.handle, _stream(), bin_mix)
 
-    def surrogate_stats(self):
+    def surrogate_stats(self, n_flags: int = 0):
         """(particles that used the surrogate, particles that fell back) in the last
-        surrogate evaluation."""
-        return fstat_surrogate_stats(self.handle)
+        surrogate evaluation, and with n_flags > 0 the per-particle flags of its
+        first n_flags particles (1: surrogate used)."""
+        return fstat_surrogate_stats(self.handle, n_flags)
+
+    def surrogate_params(self, params=None):
+        """The trained surrogate weights (float32 [198,657]), or with `params`
+        load them into this plan (marks the surrogate trained)."""
+        return fstat_surrogate_params(self.handle, params, _stream())
 
     def profile_read(self, reset: bool = True):
         """(bin-loop stage ms, its main kernel ms, evaluations, bin-template

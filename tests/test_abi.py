@@ -22,6 +22,7 @@ def test_header_declares_the_boundary():
                                   "fstat_autotune",
                                   "fstat_mlp_grad", "fstat_mlp_forward",
                                   "fstat_surrogate_train", "fstat_surrogate_stats",
+                                  "fstat_surrogate_params",
                                   "fstat_calibrate", "fstat_plan_destroy",
                                   "fstat_last_error"])
 
