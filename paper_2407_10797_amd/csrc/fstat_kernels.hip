@@ -855,7 +855,24 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
   __shared__ double2 s_tab[kSinTab];              // coarse angles of the template's sin/cos
-  fill_sincos_table(s_tab);
+  // the row tables in LDS (the coefficient loop reads one entry of each per
+  // node and lane; from the constant tables each read is a vector memory load)
+  __shared__ double s_r9[kCheb][kLanesItem], s_rT[kCheb][kLanesItem];
+  __shared__ double s_rt[MIXED ? 1 : 2][kCheb][kLanesItem];
+  // each lane's node values, read back by the lanes of its item (one write,
+  // broadcast reads: LDS operations of one wave complete in order)
+  __shared__ __align__(16) double s_nd[4][64][12];
+  double* my_nd = s_nd[threadIdx.x >> 6][lane];
+  for (int i = threadIdx.x; i < kCheb * kLanesItem; i += blockDim.x) {
+    const int kn = i / kLanesItem, kk = i - kn * kLanesItem;
+    s_r9[kn][kk] = c_row9[kn][kk];
+    s_rT[kn][kk] = MIXED ? c_row6[kn][kk] : c_row9[kn][kk];
+    if constexpr (!MIXED) {
+      s_rt[0][kn][kk] = c_rowt[0][kn][kk];
+      s_rt[1][kn][kk] = c_rowt[1][kn][kk];
+    }
+  }
+  fill_sincos_table(s_tab);                       // ends with a block barrier
   const int W = total[0];
   const int G = (W + kItemsWave - 1) / kItemsWave;
   const int q = min(lane / kLanesItem, kItemsWave - 1);
@@ -942,37 +959,45 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     for (int fn = 0; fn < 4; ++fn) {
       aT[fn] = 0.0; aG[fn] = 0.0; aTt[0][fn] = 0.0; aTt[1][fn] = 0.0;
     }
+    my_nd[0] = v[0]; my_nd[1] = v0lo;
+    my_nd[2] = v[1]; my_nd[3] = v[2]; my_nd[4] = v[3]; my_nd[5] = v[4];
+    my_nd[6] = gq[0]; my_nd[7] = gq[1]; my_nd[8] = gq[2]; my_nd[9] = gq[3];
+    my_nd[10] = wq;
+    __builtin_amdgcn_wave_barrier();
+    const double* item_nd = s_nd[threadIdx.x >> 6][base];
     // not unrolled: unrolling hoists every node's table loads and needs more
     // registers than the kernel can hold at a useful occupancy
 #pragma unroll 1
     for (int kn = 0; kn < kCheb; ++kn) {
-      const double r9 = c_row9[kn][k];
-      const double rT = MIXED ? c_row6[kn][k] : r9;
+      const double r9 = s_r9[kn][k];
+      const double rT = MIXED ? s_rT[kn][k] : r9;
+      const double2* nd = reinterpret_cast<const double2*>(item_nd + 12 * kn);
+      const double2 n01 = nd[0], n23 = nd[1], n45 = nd[2], n67 = nd[3], n89 = nd[4], nab = nd[5];
       {
-        const double vn = __shfl(v[0], base + kn, 64), vl = __shfl(v0lo, base + kn, 64);
-        aR = dd_add(aR, two_prod(vn, r9));
-        aRx = fma(vl, r9, aRx);
+        aR = dd_add(aR, two_prod(n01.x, r9));
+        aRx = fma(n01.y, r9, aRx);
       }
+      const double vt[4] = {n23.x, n23.y, n45.x, n45.y};
 #pragma unroll
-      for (int fn = 1; fn < 5; ++fn) {
-        const double vn = __shfl(v[fn], base + kn, 64);
-        aT[fn - 1] = fma(vn, rT, aT[fn - 1]);
-        tmax = fmax(tmax, fabs(vn));
+      for (int fn = 0; fn < 4; ++fn) {
+        aT[fn] = fma(vt[fn], rT, aT[fn]);
+        tmax = fmax(tmax, fabs(vt[fn]));
         if constexpr (!MIXED) {
 #pragma unroll
-          for (int v2 = 0; v2 < 2; ++v2) aTt[v2][fn - 1] = fma(vn, c_rowt[v2][kn][k], aTt[v2][fn - 1]);
+          for (int v2 = 0; v2 < 2; ++v2) aTt[v2][fn] = fma(vt[fn], s_rt[v2][kn][k], aTt[v2][fn]);
         }
       }
       // M-term integrands: lane 0 sums the quadrature, the end lanes interpolate
-      const double wk = __shfl(wq, base + kn, 64);
+      const double wk = nab.x;
       const double rg = k == 0 ? wk : (k >= kCheb ? r9 : 0.0);
+      const double gt[4] = {n67.x, n67.y, n89.x, n89.y};
 #pragma unroll
       for (int fn = 0; fn < 4; ++fn) {
-        const double gn = __shfl(gq[fn], base + kn, 64);
-        aG[fn] = fma(gn, rg, aG[fn]);
-        if (fn < 2) gmax = fmax(gmax, fabs(gn));
+        aG[fn] = fma(gt[fn], rg, aG[fn]);
+        if (fn < 2) gmax = fmax(gmax, fabs(gt[fn]));
       }
     }
+    __builtin_amdgcn_wave_barrier();   // the slots are rewritten by the next group
     const double tolP = MIXED ? kInterpTolPhaseMixed : kInterpTolPhase;
     const double tolT = MIXED ? kInterpTolTMixed : kInterpTolT;
     const double cR = aR.hi + (aR.lo + aRx);
