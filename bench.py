@@ -181,10 +181,15 @@ def pso_bench(iters, surrogate=True):
     boxes = pso_boxes(inj, 8)
     nps = np.array([256, 64, 16, 1] * 2, dtype=np.int32)
     out = {}
-    # work-item shape for this batch: 40 points from each run's box at Np = 64
+    # work-item shape and bin loop (interpolating or exact) for this batch: 40
+    # points from each run's box at the run's Np
     pts = np.vstack([S.uniform_box(boxes[r], 40, 4100 + r) for r in range(len(boxes))])
-    c, m, _ = plan.autotune(torch.from_numpy(pts).cuda(), 64)
+    prm = torch.from_numpy(pts).cuda()
+    c, m, _ = plan.autotune(prm, np.repeat(nps, 40), mode=True)
+    plan.eval(prm, np.repeat(nps, 40))
+    items, rej, _ = plan.interp_stats()
     out["tuned_chunk"], out["tuned_grid_mult"] = int(c), int(m)
+    out["tuned_loop"] = "exact" if rej == items else "interpolating"
     for mode, graph in (("graph", True), ("eager", False)):
         plan.pso(boxes, nps, n_part=40, iters=20, use_graph=graph, seed=4001)   # warm-up
         torch.cuda.synchronize()
@@ -431,7 +436,7 @@ def main():
         print(json.dumps(out), flush=True)
         return
     if args.only == "pso":
-        out = {"pso": pso_bench(args.pso_iters)}
+        out = {"pso": pso_bench(args.pso_iters, surrogate=not args.no_surrogate)}
         _log(f"pso: {out['pso']['graph']['iterations_per_s']:.1f} iterations/s with hipGraph, "
              f"{out['pso']['eager']['iterations_per_s']:.1f} eager")
         print(json.dumps(out), flush=True)
@@ -549,7 +554,7 @@ def main():
         out["calibration"] = calib
     if args.pso_iters > 0:
         _log("batched PSO stage")
-        out["pso"] = pso_bench(args.pso_iters)
+        out["pso"] = pso_bench(args.pso_iters, surrogate=not args.no_surrogate)
         _log(f"pso: {out['pso']['graph']['iterations_per_s']:.1f} iterations/s with hipGraph, "
              f"{out['pso']['eager']['iterations_per_s']:.1f} eager")
     if not args.no_cpu:

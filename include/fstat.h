@@ -64,6 +64,9 @@ extern "C" {
 #define FSTAT_EVAL_SURROGATE 8u /* fstat_eval / pso_stage: learned eccentric
                                    phase for particles with Np >= 16        */
 #define FSTAT_AUTOTUNE_FORCE 16u /* fstat_autotune: ignore the cache         */
+#define FSTAT_AUTOTUNE_MODE 64u  /* fstat_autotune: also time the exact loop and
+                                    keep it for the plan's later evaluations
+                                    of that precision when it is faster     */
 #define FSTAT_EVAL_EXACT 32u  /* fstat_eval / pso_stage / fstat_autotune: the
                                  exact template at every bin instead of the
                                  per-work-item interpolation of its smooth
@@ -226,16 +229,23 @@ int fstat_waveform(double T_obs, double df, int64_t k_lo, int64_t nbins, const d
                    const double *amps4, double *out, uint32_t flags, void *hip_stream);
 
 /* Autotuner for the bin loop: times fstat_eval of `params` (device pointers,
- * n particles, uniform np) for work items of 256..8192 bins and persistent
- * grids of 1, 2, 4 times the resident occupancy, keeps the fastest for the
- * precision selected by flags (FSTAT_EVAL_MIXED) in the plan, and returns it.
+ * n particles; np [n] partition counts (device) with part_stride their
+ * maximum, or np NULL and np_uniform for all) for work items of 256..8192
+ * bins and persistent grids of 1, 2, 4 times the resident occupancy, keeps
+ * the fastest for the precision selected by flags (FSTAT_EVAL_MIXED) in the
+ * plan, and returns it.  With FSTAT_AUTOTUNE_MODE it times the exact per-bin
+ * loop as well and, when that is faster (small batches, where the
+ * interpolating loop's node evaluations are a latency chain), makes the
+ * plan's later evaluations of that precision use it (the statistic is the
+ * same within the parity bars; FSTAT_EVAL_EXACT tunes the exact loop only).
  * Results are cached in the text file named by $FSTAT_TUNE_CACHE (if set),
- * keyed by GPU architecture, band size, Np class and precision;
- * FSTAT_AUTOTUNE_FORCE re-measures.  Requires FSTAT_DEVICE_PTRS; waits for
- * completion.  best_ms is -1 when the value came from the cache.          */
+ * keyed by GPU architecture, band size, Np class (and whether Np varies),
+ * precision and mode; FSTAT_AUTOTUNE_FORCE re-measures.  Requires
+ * FSTAT_DEVICE_PTRS; waits for completion.  best_ms is -1 when the value came
+ * from the cache.                                                          */
 int fstat_autotune(fstat_plan_t plan, const double *params, int64_t n, int32_t np_uniform,
-                   uint32_t flags, int32_t *best_chunk, int32_t *best_mult, double *best_ms,
-                   void *hip_stream);
+                   const int32_t *np, int32_t part_stride, uint32_t flags, int32_t *best_chunk,
+                   int32_t *best_mult, double *best_ms, void *hip_stream);
 
 /* ---- particle swarm stage (Sec. III.A; batched runs of Sec. III.B) -------- */
 typedef struct {

@@ -230,6 +230,8 @@ int eval_device(fstat_plan_s* P, const double* params, int64_t n, const int32_t*
                 int32_t np_uniform, int32_t stride, double* F_hat, double* F_part,
                 int64_t part_stride, bool mixed, hipStream_t s, const uint8_t* skip,
                 bool allow_profile, bool surrogate, bool exact, double* amps) {
+  // the autotuner may have found the exact loop faster for this plan's batches
+  exact = exact || (mixed ? P->prefer_exact_mixed : P->prefer_exact_fp64);
   int rc = check_chunk(P, mixed, exact);
   if (rc) return rc;
   if ((rc = ensure_workspace(P, n, stride, chunk_for(P, mixed)))) return rc;
@@ -263,14 +265,15 @@ static std::string tune_key(const fstat_plan_s* P, int32_t np, bool mixed) {
 
 // Choices made in this process, keyed like the cache file.
 static std::mutex g_tune_mu;
-static std::map<std::string, std::pair<int, int>> g_tune_mem;
+static std::map<std::string, std::array<int, 3>> g_tune_mem;
 
-static bool tune_cache_get(const std::string& key, int* chunk, int* mult) {
+// (chunk, grid multiplier, 1 when the exact loop won) of a key
+static bool tune_cache_get(const std::string& key, int* chunk, int* mult, int* ex) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_mem.find(key);
     if (it != g_tune_mem.end()) {
-      *chunk = it->second.first; *mult = it->second.second;
+      *chunk = it->second[0]; *mult = it->second[1]; *ex = it->second[2];
       return true;
     }
   }
@@ -282,25 +285,26 @@ static bool tune_cache_get(const std::string& key, int* chunk, int* mult) {
   bool found = false;
   while (fgets(line, sizeof(line), fp)) {
     char k[400];
-    int c, m;
-    if (sscanf(line, "%399[^|]|%d %d", k, &c, &m) == 3 && key == k) {
-      *chunk = c; *mult = m; found = true;   // last entry wins
+    int c, m, e = 0;
+    const int got = sscanf(line, "%399[^|]|%d %d %d", k, &c, &m, &e);
+    if (got >= 3 && key == k) {
+      *chunk = c; *mult = m; *ex = got == 4 ? e : 0; found = true;   // last entry wins
     }
   }
   fclose(fp);
   return found;
 }
 
-static void tune_cache_put(const std::string& key, int chunk, int mult) {
+static void tune_cache_put(const std::string& key, int chunk, int mult, int ex) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_mem[key] = {chunk, mult};
+    g_tune_mem[key] = {chunk, mult, ex};
   }
   const char* path = getenv("FSTAT_TUNE_CACHE");
   if (!path || !*path) return;
   FILE* fp = fopen(path, "a");
   if (!fp) return;
-  fprintf(fp, "%s|%d %d\n", key.c_str(), chunk, mult);
+  fprintf(fp, "%s|%d %d %d\n", key.c_str(), chunk, mult, ex);
   fclose(fp);
 }
 
@@ -309,21 +313,26 @@ static void tune_cache_put(const std::string& key, int chunk, int mult) {
 extern "C" {
 
 int fstat_autotune(fstat_plan_t P, const double* params, int64_t n, int32_t np_uniform,
-                   uint32_t flags, int32_t* best_chunk, int32_t* best_mult, double* best_ms,
-                   void* hip_stream) {
+                   const int32_t* np, int32_t part_stride, uint32_t flags, int32_t* best_chunk,
+                   int32_t* best_mult, double* best_ms, void* hip_stream) {
   g_err.clear();
-  if (!P || !params || n < 1 || np_uniform < 1 || np_uniform > 65536)
-    return set_error(FSTAT_EINVAL, "fstat_autotune: bad arguments");
+  if (!P || !params || n < 1) return set_error(FSTAT_EINVAL, "fstat_autotune: bad arguments");
+  if (np ? (part_stride < 1 || part_stride > 65536) : (np_uniform < 1 || np_uniform > 65536))
+    return set_error(FSTAT_EINVAL, "fstat_autotune: np_uniform or part_stride out of range");
   if (!(flags & FSTAT_DEVICE_PTRS)) return set_error(FSTAT_EINVAL, "fstat_autotune needs device pointers");
   const bool mixed = (flags & FSTAT_EVAL_MIXED) != 0;
   const bool exact = (flags & FSTAT_EVAL_EXACT) != 0;
+  const bool mode = (flags & FSTAT_AUTOTUNE_MODE) != 0 && !exact;
   if (mixed ? !(P->prec & FSTAT_MIXED) : !(P->prec & FSTAT_FP64))
     return set_error(FSTAT_EINVAL, "precision not built into the plan");
   hipStream_t s = (hipStream_t)hip_stream;
-  const std::string key = tune_key(P, np_uniform, mixed) + (exact ? " exact" : "");
-  int c = 0, m = 0;
+  const int32_t stride = np ? part_stride : np_uniform;
+  const std::string key = tune_key(P, stride, mixed) + (np ? " npmix" : "") +
+                          (exact ? " exact" : (mode ? " mode" : ""));
+  bool& prefer = mixed ? P->prefer_exact_mixed : P->prefer_exact_fp64;
+  int c = 0, m = 0, e = 0;
   double ms_best = -1.0;
-  if (!(flags & FSTAT_AUTOTUNE_FORCE) && tune_cache_get(key, &c, &m) && c >= 64 && m >= 1) {
+  if (!(flags & FSTAT_AUTOTUNE_FORCE) && tune_cache_get(key, &c, &m, &e) && c >= 64 && m >= 1) {
     // cached
   } else {
     static const int chunks[] = {256, 512, 1024, 2048, 4096, 8192};
@@ -335,34 +344,43 @@ int fstat_autotune(fstat_plan_t P, const double* params, int64_t n, int32_t np_u
     if (!rc) rc = hip_check(hipEventCreate(&e1), "event");
     const int save_c = P->chunk, save_cm = P->chunk_mixed;
     const int save_m = mixed ? P->grid_mult_mixed : P->grid_mult_fp64;
-    for (int ci = 0; ci < 6 && !rc; ++ci)
-      for (int mi = 0; mi < 3 && !rc; ++mi) {
-        if (!exact && chunks[ci] > interp_max_tile(mixed)) continue;
-        if (mixed) { P->chunk_mixed = chunks[ci]; P->grid_mult_mixed = mults[mi]; }
-        else { P->chunk = chunks[ci]; P->grid_mult_fp64 = mults[mi]; }
-        double t_min = 1e300;
-        for (int rep = 0; rep < 3 && !rc; ++rep) {
-          rc = hip_check(hipEventRecord(e0, s), "record");
-          if (!rc) rc = eval_device(P, params, n, nullptr, np_uniform, np_uniform, F, nullptr, 0,
-                                    mixed, s, nullptr, false, false, exact);
-          if (!rc) rc = hip_check(hipEventRecord(e1, s), "record");
-          if (!rc) rc = hip_check(hipEventSynchronize(e1), "sync");
-          float ms = 0.f;
-          if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
-          if (rep > 0 && ms < t_min) t_min = ms;   // first repetition is a warm-up
+    const bool save_p = prefer;
+    prefer = false;     // each candidate below runs the loop it names
+    // interpolating loop (unless exact is requested), then the exact loop
+    // (when requested, or when the mode is tuned as well)
+    for (int ex = exact ? 1 : 0; ex <= ((exact || mode) ? 1 : 0) && !rc; ++ex)
+      for (int ci = 0; ci < 6 && !rc; ++ci)
+        for (int mi = 0; mi < 3 && !rc; ++mi) {
+          if (!ex && chunks[ci] > interp_max_tile(mixed)) continue;
+          if (mixed) { P->chunk_mixed = chunks[ci]; P->grid_mult_mixed = mults[mi]; }
+          else { P->chunk = chunks[ci]; P->grid_mult_fp64 = mults[mi]; }
+          double t_min = 1e300;
+          for (int rep = 0; rep < 3 && !rc; ++rep) {
+            rc = hip_check(hipEventRecord(e0, s), "record");
+            if (!rc) rc = eval_device(P, params, n, np, np_uniform, stride, F, nullptr, 0,
+                                      mixed, s, nullptr, false, false, ex != 0);
+            if (!rc) rc = hip_check(hipEventRecord(e1, s), "record");
+            if (!rc) rc = hip_check(hipEventSynchronize(e1), "sync");
+            float ms = 0.f;
+            if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+            if (rep > 0 && ms < t_min) t_min = ms;   // first repetition is a warm-up
+          }
+          if (!rc && (ms_best < 0 || t_min < ms_best)) {
+            ms_best = t_min; c = chunks[ci]; m = mults[mi]; e = ex;
+          }
         }
-        if (!rc && (ms_best < 0 || t_min < ms_best)) { ms_best = t_min; c = chunks[ci]; m = mults[mi]; }
-      }
     P->chunk = save_c; P->chunk_mixed = save_cm;
     if (mixed) P->grid_mult_mixed = save_m; else P->grid_mult_fp64 = save_m;
+    prefer = save_p;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (F) (void)hipFree(F);
     if (rc) return rc;
-    tune_cache_put(key, c, m);
+    tune_cache_put(key, c, m, e);
   }
   if (mixed) { P->chunk_mixed = c; P->grid_mult_mixed = m; }
   else { P->chunk = c; P->grid_mult_fp64 = m; }
+  if (!exact) prefer = mode && e != 0;
   if (best_chunk) *best_chunk = c;
   if (best_mult) *best_mult = m;
   if (best_ms) *best_ms = ms_best;
@@ -685,7 +703,8 @@ int fstat_eval_noalloc(fstat_plan_t P, const double* params, int64_t n, const in
   if (flags & FSTAT_EVAL_SURROGATE)
     return set_error(FSTAT_EUNSUPPORTED, "fstat_eval_noalloc does not run the surrogate");
   const bool mixed = (flags & FSTAT_EVAL_MIXED) != 0;
-  const bool exact = (flags & FSTAT_EVAL_EXACT) != 0;
+  const bool exact = (flags & FSTAT_EVAL_EXACT) != 0 ||
+                     (mixed ? P->prefer_exact_mixed : P->prefer_exact_fp64);
   if (mixed && !(P->prec & FSTAT_MIXED)) return set_error(FSTAT_EINVAL, "plan has no mixed data");
   if (!mixed && !(P->prec & FSTAT_FP64)) return set_error(FSTAT_EINVAL, "plan has no FP64 data");
   int32_t stride;

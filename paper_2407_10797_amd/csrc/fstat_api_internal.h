@@ -24,6 +24,7 @@ struct fstat_plan_s {
   int chunk_mixed = 0;              // tuned value for the mixed path (0: use chunk)
   double refine_budget = 5e-10;    // see fstat_opts.refine_budget
   int grid_mult_fp64 = 1, grid_mult_mixed = 1;   // persistent-grid multiplier
+  bool prefer_exact_fp64 = false, prefer_exact_mixed = false;   // autotuned bin-loop choice
   int blocks_fp64 = 0, blocks_mixed = 0;
   fstat::Grid grid{};
   fstat::BinData<double> b64{};

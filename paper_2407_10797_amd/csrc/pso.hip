@@ -165,12 +165,14 @@ struct DevBufs {
 
 // $FSTAT_PROGRESS = N > 0: every N iterations wait for the stream and print
 // one line to stderr (long stages report while they run).
-int report_progress(int done, int total, hipStream_t s) {
+// a progress line each time `done` (advanced by `step`) passes a multiple of
+// $FSTAT_PROGRESS iterations
+int report_progress(int done, int total, hipStream_t s, int step = 1) {
   static const long every = [] {
     const char* e = getenv("FSTAT_PROGRESS");
     return e ? strtol(e, nullptr, 10) : 0L;
   }();
-  if (every <= 0 || done % every != 0 || done == total) return FSTAT_OK;
+  if (every <= 0 || done / every == (done - step) / every || done == total) return FSTAT_OK;
   int rc = hip_check(hipStreamSynchronize(s), "pso progress");
   if (!rc) {
     fprintf(stderr, "[pso] %d / %d iterations\n", done, total);
@@ -180,6 +182,8 @@ int report_progress(int done, int total, hipStream_t s) {
 }
 
 }  // namespace
+
+constexpr int kGraphIters = 16;   // PSO iterations per captured graph
 
 extern "C" int pso_stage(fstat_plan_t P, const pso_stage_desc* d, pso_result* res,
                          void* hip_stream) {
@@ -250,25 +254,37 @@ extern "C" int pso_stage(fstat_plan_t P, const pso_stage_desc* d, pso_result* re
     return hip_check(hipGetLastError(), "pso launch");
   };
   if (d->use_graph && I > 0) {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    if ((rc = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture")))
-      return rc;
-    int rci = iteration();
-    hipError_t ec = hipStreamEndCapture(s, &graph);
-    if (rci) {
+    // kGraphIters iterations per graph (the iteration counter lives on the
+    // device, so consecutive iterations are identical launches): one graph
+    // launch per kGraphIters iterations, and a second graph for the remainder
+    auto capture = [&](int iters, hipGraphExec_t* exec) -> int {
+      hipGraph_t graph = nullptr;
+      int r2 = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+      if (r2) return r2;
+      int rci = 0;
+      for (int k = 0; k < iters && !rci; ++k) rci = iteration();
+      hipError_t ec = hipStreamEndCapture(s, &graph);
+      if (!rci) rci = hip_check(ec, "end capture");
+      if (!rci) rci = hip_check(hipGraphInstantiate(exec, graph, nullptr, nullptr, 0), "instantiate");
       if (graph) (void)hipGraphDestroy(graph);
       return rci;
-    }
-    if ((rc = hip_check(ec, "end capture"))) return rc;
-    rc = hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
-    for (int k = 0; k < I && !rc; ++k) {
+    };
+    const int G = I < kGraphIters ? I : kGraphIters;
+    const int full = I / G, rest = I - full * G;
+    hipGraphExec_t exec = nullptr, exec_rest = nullptr;
+    rc = capture(G, &exec);
+    if (!rc && rest) rc = capture(rest, &exec_rest);
+    for (int k = 0; k < full && !rc; ++k) {
       rc = hip_check(hipGraphLaunch(exec, s), "graph launch");
-      if (!rc) rc = report_progress(k + 1, I, s);
+      if (!rc) rc = report_progress((k + 1) * G, I, s, G);
+    }
+    if (!rc && rest) {
+      rc = hip_check(hipGraphLaunch(exec_rest, s), "graph launch");
+      if (!rc) rc = report_progress(I, I, s, rest);
     }
     if (!rc) rc = hip_check(hipStreamSynchronize(s), "pso graph");
     if (exec) (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
+    if (exec_rest) (void)hipGraphExecDestroy(exec_rest);
     if (rc) return rc;
   } else {
     for (int k = 0; k < I; ++k)

@@ -27,6 +27,7 @@ FSTAT_PROFILE = 4
 FSTAT_EVAL_SURROGATE = 8
 FSTAT_AUTOTUNE_FORCE = 16
 FSTAT_EVAL_EXACT = 32
+FSTAT_AUTOTUNE_MODE = 64
 
 EXPORTS = ("fstat_plan_create", "fstat_plan_set_orbit", "fstat_eval", "fstat_eval_noalloc",
            "fstat_extrinsic",
@@ -154,8 +155,8 @@ def lib() -> ctypes.CDLL:
         L.fstat_surrogate_stats.restype = ctypes.c_int
         L.fstat_surrogate_params.argtypes = [vp, vp, vp, vp]
         L.fstat_surrogate_params.restype = ctypes.c_int
-        L.fstat_autotune.argtypes = [vp, vp, i64, i32, u32, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                     ctypes.POINTER(ctypes.c_double), vp]
+        L.fstat_autotune.argtypes = [vp, vp, i64, i32, vp, i32, u32, ctypes.POINTER(i32),
+                                     ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), vp]
         L.fstat_autotune.restype = ctypes.c_int
         L.fstat_calibrate.argtypes = [i32, i64, i32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double), vp]
@@ -359,10 +360,11 @@ def fstat_surrogate_params(plan, params=None, stream=None):
     return out
 
 
-def fstat_autotune(plan, params, n, np_uniform, flags, stream=None):
+def fstat_autotune(plan, params, n, np_uniform, flags, stream=None, np_ptr=None, part_stride=0):
     c, m, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
-    _check(lib().fstat_autotune(plan, params, int(n), int(np_uniform), int(flags), ctypes.byref(c),
-                                ctypes.byref(m), ctypes.byref(ms), stream))
+    _check(lib().fstat_autotune(plan, params, int(n), int(np_uniform), np_ptr, int(part_stride),
+                                int(flags), ctypes.byref(c), ctypes.byref(m), ctypes.byref(ms),
+                                stream))
     return c.value, m.value, ms.value
 
 
@@ -526,15 +528,23 @@ class Plan:
             out["loss_trace"] = trace
         return out
 
-    def autotune(self, params, np_parts: int, mixed: bool = False, force: bool = False,
-                 exact: bool = False):
-        """Pick the work-item size and grid multiplier for this precision; returns
-        (chunk, grid multiplier, best ms or -1 if cached)."""
+    def autotune(self, params, np_parts, mixed: bool = False, force: bool = False,
+                 exact: bool = False, mode: bool = False):
+        """Pick the work-item size and grid multiplier for this precision (and
+        with `mode` whether the exact loop beats the interpolating one) for a
+        batch like params [n, 6] with np_parts (int, or [n] per particle);
+        returns (chunk, grid multiplier, best ms or -1 if cached)."""
         torch = _torch()
         prm = torch.as_tensor(params).to("cuda", torch.float64).contiguous()
         flags = (FSTAT_DEVICE_PTRS | (FSTAT_EVAL_MIXED if mixed else 0)
-                 | (FSTAT_AUTOTUNE_FORCE if force else 0) | (FSTAT_EVAL_EXACT if exact else 0))
-        return fstat_autotune(self.handle, prm.data_ptr(), prm.shape[0], int(np_parts), flags, _stream())
+                 | (FSTAT_AUTOTUNE_FORCE if force else 0) | (FSTAT_EVAL_EXACT if exact else 0)
+                 | (FSTAT_AUTOTUNE_MODE if mode else 0))
+        if isinstance(np_parts, int):
+            return fstat_autotune(self.handle, prm.data_ptr(), prm.shape[0], int(np_parts), flags,
+                                  _stream())
+        npt = torch.as_tensor(np_parts).to("cuda", torch.int32).contiguous()
+        return fstat_autotune(self.handle, prm.data_ptr(), prm.shape[0], 0, flags, _stream(),
+                              npt.data_ptr(), int(npt.max().item()))
 
     def interp_stats(self, bin_mix: bool = False):
         """(work items, items handed to the exact loop, items refined exactly) of

@@ -50,7 +50,7 @@ def test_autotune_choice_is_cached_and_correct(small, torch_cuda, mixed):
     assert (c2, m2, ms2) == (c, m, -1.0)
     key = "mixed" if mixed else "fp64"
     lines = [ln for ln in s["cache"].read_text().splitlines() if ln.split("|")[0].endswith(key)]
-    assert lines and lines[-1].split("|")[1].split() == [str(c), str(m)]
+    assert lines and lines[-1].split("|")[1].split() == [str(c), str(m), "0"]
     Fo, Po, cond = O.fstat(s["data"], s["psd"], s["g"].k_lo, s["g"].df, s["g"].T_obs, s["pts"],
                            [16], want_cond=True)
     F, Fp = s["plan"].eval(prm, 16, mixed=mixed, want_parts=True)
@@ -60,6 +60,36 @@ def test_autotune_choice_is_cached_and_correct(small, torch_cuda, mixed):
     tol = (1e-4 + 1e-6 * c16) if mixed else (FP64_REL + FP64_KCOND * c16)
     ok = np.isfinite(Po[:, :16])
     assert np.all(rel[ok] <= tol[ok]), float((rel[ok] / tol[ok]).max())
+
+
+def test_autotuned_mode_on_a_pso_batch(small, torch_cuda):
+    """FSTAT_AUTOTUNE_MODE on a batched-PSO-like batch (per-particle Np 256,
+    64, 16, 1): the exact and interpolating loops are both timed, the choice is
+    cached with its mode, and the plan's later evaluations (whichever loop they
+    take) match the oracle to the FP64 bar, partition by partition."""
+    from paper_2407_10797_amd import fstat
+    s = small
+    nps = np.array([256, 64, 16, 1] * (len(s["pts"]) // 4), dtype=np.int32)
+    pts = s["pts"][:len(nps)]
+    prm = torch_cuda.from_numpy(pts).cuda()
+    c, m, ms = s["plan"].autotune(prm, nps, force=True, mode=True)
+    lines = [ln for ln in s["cache"].read_text().splitlines() if " npmix " in ln and "mode" in ln]
+    ex = int(lines[-1].split("|")[1].split()[2])
+    print(f"[autotune] PSO-like batch: chunk {c} x{m}, {'exact' if ex else 'interpolating'} loop, "
+          f"{ms:.3f} ms", flush=True)
+    assert c in CHUNKS and m in MULTS and ms > 0 and ex in (0, 1)
+    F, P = s["plan"].eval(prm, nps, 256, want_parts=True)
+    items, rej, _ = s["plan"].interp_stats()
+    assert (rej == items) == bool(ex)
+    Fo, Po, cond = O.fstat(s["data"], s["psd"], s["g"].k_lo, s["g"].df, s["g"].T_obs, pts, nps,
+                           part_stride=256, want_cond=True)
+    P = P.cpu().numpy()
+    for i, k in enumerate(nps):
+        c_ = np.where(np.isfinite(cond[i, :k]), cond[i, :k], 0.0)
+        rel = np.abs(P[i, :k] - Po[i, :k]) / np.maximum(np.abs(Po[i, :k]), 1.0)
+        assert np.all(rel <= FP64_REL + FP64_KCOND * c_), (i, float(rel.max()))
+    # back to the interpolating loop for the other tests on this plan
+    s["plan"].autotune(prm, 16, force=True)
 
 
 def test_autotune_rejects_host_pointers(small):

@@ -78,6 +78,22 @@ def test_pso_graph_replay_equals_eager_and_linear_inertia(setup):
     np.testing.assert_allclose(a["final_x"], ref["final_x"], rtol=0, atol=1e-9)
 
 
+def test_graph_of_several_iterations_with_remainder(setup):
+    """37 iterations: two replays of a 16-iteration graph and one 5-iteration
+    graph, bit for bit the eager trajectory and the step-by-step reference."""
+    s = setup
+    boxes = _boxes(s["inj"], 2)
+    nps = np.array([4, 1], dtype=np.int32)
+    kw = dict(KW, iters=37)
+    a = s["plan"].pso(boxes, nps, w=(0.9, 0.4), want_final=True, use_graph=True, **kw)
+    b = s["plan"].pso(boxes, nps, w=(0.9, 0.4), want_final=True, use_graph=False, **kw)
+    for k in ("trace", "final_x", "best_x", "best_F"):
+        np.testing.assert_array_equal(a[k], b[k])
+    ref = PO.run(_oracle_fit(s), boxes, nps, w_start=0.9, w_end=0.4, **kw)
+    np.testing.assert_allclose(a["trace"], ref["trace"], rtol=1e-8)
+    np.testing.assert_allclose(a["final_x"], ref["final_x"], rtol=0, atol=1e-9)
+
+
 def test_runs_are_independent(setup):
     """A run's trajectory does not depend on the other runs in the launch."""
     s = setup
