@@ -136,15 +136,15 @@ def make_workload(n_particles: int, seed_pts: int = 2003):
     return g, data, psd, pts, inj
 
 
-def time_path(plan, prm, npart, steps, warmup, mixed, surrogate=False):
+def time_path(plan, prm, npart, steps, warmup, mixed, surrogate=False, exact=False):
     import torch
     for _ in range(warmup):
-        plan.eval(prm, npart, mixed=mixed, surrogate=surrogate)
+        plan.eval(prm, npart, mixed=mixed, surrogate=surrogate, exact=exact)
     torch.cuda.synchronize()
     plan.profile_read(reset=True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        F = plan.eval(prm, npart, mixed=mixed, surrogate=surrogate)
+        F = plan.eval(prm, npart, mixed=mixed, surrogate=surrogate, exact=exact)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kms, mms, launches, bins = plan.profile_read(reset=True)
@@ -393,7 +393,7 @@ def main():
     ap.add_argument("--no-aet", action="store_true", help="skip the three-channel measurement")
     ap.add_argument("--no-orbit", action="store_true", help="skip the numerical-orbit measurement")
     ap.add_argument("--only", choices=["fp64", "mixed", "mixed+surrogate", "pso", "search", "aet",
-                                       "orbit"],
+                                       "orbit", "exact"],
                     default=None,
                     help="one paper-scale variant, or only the batched PSO measurement, or only "
                          "the three-stage search")
@@ -509,6 +509,18 @@ def main():
                               roofline=roof, **extra)
         _log(f"{name}: {tps:.1f} templates/s, bin-loop stage {r['kernel_ms']:.2f} ms, main kernel "
              f"{r['main_ms']:.2f} ms, {r['bins_per_launch']:.3e} bin-templates/launch")
+    if args.only == "exact":
+        # the exact template at every bin (FSTAT_EVAL_EXACT): the reference the
+        # interpolating loop is measured against; not part of the default run
+        for name, mixed in (("exact-fp64", False), ("exact-mixed", True)):
+            r = time_path(plan, prm, args.np, args.steps, args.warmup, mixed, exact=True)
+            variants[name] = dict(templates_per_s=args.particles * args.steps / r["seconds"],
+                                  ms_per_step=1e3 * r["seconds"] / args.steps,
+                                  stage_ms=r["kernel_ms"], main_kernel_ms=r["main_ms"],
+                                  main_kernel="k_eval_exact<true>" if mixed else "k_eval_exact<false>",
+                                  bins_per_launch=r["bins_per_launch"])
+            _log(f"{name}: {variants[name]['templates_per_s']:.1f} templates/s, bin-loop stage "
+                 f"{r['kernel_ms']:.2f} ms")
     if not args.no_orbit and args.only in (None, "orbit"):
         for name, mixed in (("orbit-fp64", False), ("orbit-mixed", True)):
             if mixed and args.no_mixed:
@@ -531,6 +543,8 @@ def main():
         except fstat.FstatError as e:
             _log(f"aet-fp64: {e}")
     head = variants.get("fp64") or next(iter(variants.values()))
+    if "roofline" not in head:
+        head = dict(head, roofline=None)
     out = {
         "metric": "F-stat templates/s at 7.1M bins, Np=64; %roofline; plain vs mixed+surrogate",
         "value": head["templates_per_s"],
