@@ -40,27 +40,22 @@ PEAK_LANE_INSTR = 256 * 64 * 2.4e9
 # (18) plus the linear and grid terms (5), sin/cos by table and Taylor series
 # (22), w e^{i Phi} (6), and the moments sum W s^k: W s (2), s^6 (1), k = 0, 1
 # by additions (4) and 4 per further degree, 4 (D - 1), D the item's transfer
-# degree; items without quadrature M-terms evaluate the four transfer
-# polynomials (Estrin, 2 x 5, 7, 9 FMAs each for D = 5, 7, 9) and form N- and
-# M-terms per bin (36) instead of the moments.
-ALG_FP64 = {"deg5": 79.0, "deg7": 87.0, "deg9": 95.0, "per_bin_m": 132.0}
+# degree (every interpolated item takes its M-terms by quadrature; the few
+# whose u the plan's model does not fit go to the exact loop).
+ALG_FP64 = {"deg5": 79.0, "deg7": 87.0, "deg9": 95.0}
 # Mixed loop: FP64 phase (Horner, 24 FP64), FP32 sin/cos (2 instructions,
-# not counted), w e^{i Phi} (6), powers (5) and moments k <= 6 (26) in FP32;
-# items without quadrature M-terms: four degree-6 FP32 transfer polynomials
-# (48) and FP32 N-terms (16 + 6), M-terms in FP64 (20).
-ALG_MIXED = {"n_only": (24.0, 37.0), "per_bin_m": (44.0, 70.0)}     # (FP64, FP32)
+# not counted), w e^{i Phi} (6), powers (5) and moments k <= 6 (26) in FP32.
+ALG_MIXED = {"n_only": (24.0, 37.0)}     # (FP64, FP32)
 
 
 def alg_flops(kind, mix):
     """Algorithmic FLOPs of the main kernel over one launch, from the launch's
-    bins by kind of per-bin work (fstat_interp_stats bin_mix), as (FP64, FP32)."""
+    bins by transfer degree (fstat_interp_stats bin_mix), as (FP64, FP32)."""
     if kind == "fp64":
-        f64 = (mix[0] * ALG_FP64["deg5"] + mix[1] * ALG_FP64["deg7"] + mix[2] * ALG_FP64["deg9"]
-               + mix[3] * ALG_FP64["per_bin_m"])
-        return f64, 0.0
-    a, b = ALG_MIXED["n_only"], ALG_MIXED["per_bin_m"]
+        return mix[0] * ALG_FP64["deg5"] + mix[1] * ALG_FP64["deg7"] + mix[2] * ALG_FP64["deg9"], 0.0
+    a = ALG_MIXED["n_only"]
     nq = mix[0] + mix[1] + mix[2]
-    return nq * a[0] + mix[3] * b[0], nq * a[1] + mix[3] * b[1]
+    return nq * a[0], nq * a[1]
 
 
 def floor_peak(f64, f32, p64, p32):
@@ -90,15 +85,15 @@ def calibrate(reps=10):
 # per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes
 # written per launch (WRITE_SIZE).
 MAIN_KERNEL = {"fp64": "k_eval_interp<false>", "mixed": "k_eval_interp<true>"}
-FLOP_PER_BIN = {"fp64": 91.25, "mixed": 65.98}      # FP64 + FP32
+FLOP_PER_BIN = {"fp64": 91.26, "mixed": 65.99}      # FP64 + FP32
 FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 39.18}      # of which FP32
-VALU_PER_BIN = {"fp64": 71.40, "mixed": 51.12}
+VALU_PER_BIN = {"fp64": 74.74, "mixed": 50.98}
 VALU32_PER_BIN = {"fp64": 0.01, "mixed": 25.12}      # of which FP32 arithmetic
-TRAFFIC = {"fp64": (0.5123, 6.646e7), "mixed": (0.2776, 3.777e7)}
+TRAFFIC = {"fp64": (0.4608, 6.670e7), "mixed": (0.2516, 3.789e7)}
 # sha256 of the main kernel's source (the k_eval_interp template and the two
 # headers it builds on) when those counters were taken; the figures are
 # reported as null once it differs.
-COUNTERS_SRC_SHA = "11d72361b2cd048971854aa4711a6744357ca439b74a8ec0ddd17d1abca2e550"
+COUNTERS_SRC_SHA = "c0f7e2b85ea8ddf19ba5c62d25c54f3be495a602490826847d336f8259c2960c"
 KERNEL_HEADERS = ("fstat_internal.h", "fstat_kernels.h")
 MAIN_KERNEL_START = "template <bool MIXED>\n__global__ __launch_bounds__(256) void k_eval_interp("
 
@@ -470,7 +465,7 @@ def main():
             r = time_path(plan, prm, args.np, args.steps, args.warmup, mixed, sur)
             items, rejected, refined, mix = plan.interp_stats(bin_mix=True)
             extra.update(work_items=items, exact_items=rejected, refined_items=refined,
-                         bin_mix=dict(zip(["n_deg5", "n_deg7", "n_deg9", "n_and_m", "exact"], mix)))
+                         bin_mix=dict(deg5=mix[0], deg7=mix[1], deg9=mix[2], exact=mix[4]))
             if sur:
                 extra["used"], extra["fallback"] = plan.surrogate_stats()
         except fstat.FstatError as e:

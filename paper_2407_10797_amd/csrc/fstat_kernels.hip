@@ -1050,8 +1050,11 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     }
     const bool mine = lane - base < kLanesItem && grp * kItemsWave + q < W;   // not a repeat lane
     if (!mine) continue;
-    const bool rej = nb < kMinInterp || ((badmask >> base) & ((1ull << kLanesItem) - 1ull)) != 0ull;
     const bool mq = ufit && ((gbadmask >> base) & ((1ull << kLanesItem) - 1ull)) == 0ull;
+    // items without quadrature M-terms (u not fitted on one of their u-tiles,
+    // or M-term interpolants that miss an end point) go to the exact loop too
+    const bool rej = nb < kMinInterp || !mq ||
+                     ((badmask >> base) & ((1ull << kLanesItem) - 1ull)) != 0ull;
     if (mq && k < 4)
       partials[(int64_t)w * 8 + 4 + k] = k == 0 ? gsum[0] : (k == 1 ? gsum[1] : (k == 2 ? gsum[2] : gsum[3]));
     double* r = rec + (int64_t)w * kRec;
@@ -1098,31 +1101,32 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                                                      int32_t* __restrict__ tile_ctr,
                                                      const double* __restrict__ wr64,
                                                      const double* __restrict__ wi64,
-                                                     const double* __restrict__ u64,
                                                      const float* __restrict__ wr32,
                                                      const float* __restrict__ wi32,
-                                                     const float* __restrict__ u32,
                                                      const double* __restrict__ rec,
                                                      const uint8_t* __restrict__ xflag,
                                                      double* __restrict__ partials) {
   typedef typename std::conditional<MIXED, float, double>::type DT;
   extern __shared__ unsigned char smem[];
-  // The tile's w and u (and on the FP64 path e_j and the sincos table) at a
-  // fixed stride of the largest tile, so that every per-bin read shares one
-  // address register (constant offsets) whatever the tile size.
+  // The tile's w (and on the FP64 path e_j and the sincos table) at a fixed
+  // stride of the largest tile, so that every per-bin read shares one address
+  // register (constant offsets) whatever the tile size.  Every item here has
+  // its M-terms from the node kernel's quadrature (the others go to the exact
+  // loop), so u is not staged; e_j is kept in FP32 (|e_j| <= half an ulp of
+  // f_j; its product with t_f <~ 1e8 s enters the phase at <~ 1e-10 cycles,
+  // and FP32 rounding of it at ~1e-17 cycles).  FP64: 20 B per bin, three
+  // blocks per CU.
   constexpr int TS = MIXED ? kMaxTileMixed : kMaxTileFp64;
   double2* s_tab = reinterpret_cast<double2*>(smem);      // FP64 loop: sin, cos table
   DT* s_wr = reinterpret_cast<DT*>(smem + (MIXED ? 0 : kSinTab * sizeof(double2)));
   DT* s_wi = s_wr + TS;
-  DT* s_u = s_wi + TS;
-  double* s_e = reinterpret_cast<double*>(s_u + TS);     // FP64 loop: grid rounding e_j
+  float* s_e = reinterpret_cast<float*>(s_wi + TS);      // FP64 loop: grid rounding e_j
   __shared__ int s_unit[3];                       // tile, first item, item count
   __shared__ double s_rec[4][64];                // each wave's current item record
   const DT* gwr;
   const DT* gwi;
-  const DT* gu;
-  if constexpr (MIXED) { gwr = wr32; gwi = wi32; gu = u32; }
-  else { gwr = wr64; gwi = wi64; gu = u64; }
+  if constexpr (MIXED) { gwr = wr32; gwi = wi32; }
+  else { gwr = wr64; gwi = wi64; }
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int nwv = blockDim.x >> 6;
@@ -1157,12 +1161,11 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
     for (int i = threadIdx.x; i < nt; i += blockDim.x) {
       s_wr[i] = gwr[co + j0 + i];
       s_wi[i] = gwi[co + j0 + i];
-      s_u[i] = gu[co + j0 + i];
       if constexpr (!MIXED) {
         // f_j = (k_lo + j) df rounds to a double; e_j is the rounding error of
         // that product (one FMA), formed once per bin of the tile
         const double jd = (double)(g.k_lo + j0 + i);
-        s_e[i] = fma(jd, g.df, -(jd * g.df));
+        s_e[i] = (float)fma(jd, g.df, -(jd * g.df));
       }
     }
     __syncthreads();
@@ -1191,7 +1194,6 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
       const double A = R[L::tail];
       const double Bp = R[L::tail + 1];
       const double Bf = R[L::tail + 2];
-      const bool mq = R[L::tail + 3] != 0.0;   // M-terms already summed by quadrature
       const int degT = (int)R[L::tail + 4];      // transfer degree (FP64 loop)
       const double alpha = 2.0 / (double)(nb - 1);
       const int e0 = b0 - j0;            // LDS offset of the item's first bin
@@ -1202,58 +1204,11 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         // with the tile): up to ~1e-9 cycles at t_f ~ 1e8 s.
         const double kB = -Bf / g.df;
         const int last = nb - 1;
-        // WM: also sum the M-terms per bin (items without quadrature M-terms);
         // DT: degree of the transfer interpolants (5, 7 or 9)
-        auto loop = [&](auto wm, auto dt) {
-          constexpr bool WM = decltype(wm)::value;
+        auto loop = [&](auto dt) {
           constexpr int DT = decltype(dt)::value;
-          // the next bin's w, u, e_j are read one iteration ahead (LDS latency)
-          double a_n = s_wr[e0 + min(lane, last)], b_n = s_wi[e0 + min(lane, last)];
-          double u_n = WM ? s_u[e0 + min(lane, last)] : 0.0;
-          double e_n = s_e[e0 + min(lane, last)];
           int idx;
-          if constexpr (WM) {
-            double cT[4][DT + 1];
-#pragma unroll
-            for (int fn = 0; fn < 4; ++fn)
-#pragma unroll
-              for (int n = 0; n <= DT; ++n) cT[fn][n] = R[kCheb + fn * L::nT + n];
-            __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
-            double acc[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) acc[i] = 0.0;
-            for (int mi = lane; mi < nb; mi += 64) {
-              const double a = a_n, b = b_n, uu = u_n, ej = e_n;
-              {
-                const int nx = e0 + min(mi + 64, last);
-                a_n = s_wr[nx];
-                b_n = s_wi[nx];
-                e_n = s_e[nx];
-                u_n = s_u[nx];
-              }
-              const double m = (double)mi;
-              const double s = fma(alpha, m, -1.0);
-              const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
-              const double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
-              double sps, cps;
-              sincos_tab(ph, s_tab, sps, cps);
-              const double tpr = estrin_d<DT>(cT[0], s, s2, s4, s8);
-              const double tpi = estrin_d<DT>(cT[1], s, s2, s4, s8);
-              const double txr = estrin_d<DT>(cT[2], s, s2, s4, s8);
-              const double txi = estrin_d<DT>(cT[3], s, s2, s4, s8);
-              const double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
-              acc[0] += Wr * tpr + Wi * tpi;
-              acc[1] += Wi * tpr - Wr * tpi;
-              acc[2] += Wr * txr + Wi * txi;
-              acc[3] += Wi * txr - Wr * txi;
-              acc[4] += uu * (tpr * tpr + tpi * tpi);
-              acc[5] += uu * (txr * txr + txi * txi);
-              acc[6] += uu * (tpr * txr + tpi * txi);
-              acc[7] += uu * (tpi * txr - tpr * txi);
-            }
-            const double tot = wave_sum8(acc, lane, idx);
-            if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
-          } else {
+          {
             // N-terms only.  They are linear in the transfer interpolants
             // T(s) = sum_k c_k s^k, so the loop sums the moments
             // sum_j w_j e^{i Phi_j} s_j^k (k <= DT) and the coefficients are
@@ -1314,61 +1269,15 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         using D5 = std::integral_constant<int, 5>;
         using D7 = std::integral_constant<int, 7>;
         using D9 = std::integral_constant<int, 9>;
-        if (mq) {
-          if (degT == 5) loop(std::false_type{}, D5{});
-          else if (degT == 7) loop(std::false_type{}, D7{});
-          else loop(std::false_type{}, D9{});
-        } else {
-          if (degT == 5) loop(std::true_type{}, D5{});
-          else if (degT == 7) loop(std::true_type{}, D7{});
-          else loop(std::true_type{}, D9{});
-        }
+        if (degT == 5) loop(D5{});
+        else if (degT == 7) loop(D7{});
+        else loop(D9{});
       } else {
         // per lane at most T / 64 terms: plain FP32 sums of the N-terms (their
-        // rounding, ~1e-7 relative, is far inside the mixed path's bar); M-terms
-        // (items without quadrature M-terms) in FP64 from the FP32 response
-        auto loop = [&](auto wm) {
-          constexpr bool WM = decltype(wm)::value;
+        // rounding, ~1e-7 relative, is far inside the mixed path's bar)
+        {
           int idx;
-          if constexpr (WM) {
-            float cT[4][kDegT + 1];
-#pragma unroll
-            for (int fn = 0; fn < 4; ++fn)
-#pragma unroll
-              for (int n = 0; n <= kDegT; ++n) cT[fn][n] = (float)R[kCheb + fn * L::nT + n];
-            __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
-            float acc[4];
-            double m4[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) { acc[i] = 0.0f; m4[i] = 0.0; }
-            for (int mi = lane; mi < nb; mi += 64) {
-              const double m = (double)mi;
-              const double s = fma(alpha, m, -1.0);
-              const double ph = fma(Bp, m, horner(cR, s)) + A;
-              const float rf = (float)(ph - rint(ph));
-              const float sps = __builtin_amdgcn_sinf(rf), cps = __builtin_amdgcn_cosf(rf);
-              const float sf = (float)s;
-              const float tpr = horner_n<kDegT>(cT[0], sf), tpi = horner_n<kDegT>(cT[1], sf);
-              const float txr = horner_n<kDegT>(cT[2], sf), txi = horner_n<kDegT>(cT[3], sf);
-              const float a = s_wr[e0 + mi], b = s_wi[e0 + mi];
-              const float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
-              acc[0] += Wr * tpr + Wi * tpi;
-              acc[1] += Wi * tpr - Wr * tpi;
-              acc[2] += Wr * txr + Wi * txi;
-              acc[3] += Wi * txr - Wr * txi;
-              const double uu = (double)s_u[e0 + mi];
-              const double pr = tpr, pi = tpi, xr = txr, xi = txi;
-              m4[0] += uu * (pr * pr + pi * pi);
-              m4[1] += uu * (xr * xr + xi * xi);
-              m4[2] += uu * (pr * xr + pi * xi);
-              m4[3] += uu * (pi * xr - pr * xi);
-            }
-            double red[8];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) { red[i] = (double)acc[i]; red[4 + i] = m4[i]; }
-            const double tot = wave_sum8(red, lane, idx);
-            if ((lane & 7) == 0) partials[(int64_t)w * 8 + idx] = tot;
-          } else {
+          {
             // N-terms only: FP32 moments sum_j w_j e^{i Phi_j} s_j^k (k <= 6), the
             // transfer coefficients applied per lane after the loop in FP64
             float mr[kDegT + 1], mm[kDegT + 1];
@@ -1408,9 +1317,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
             const double tot = wave_sum4(red, lane, idx);
             if ((lane & 15) == 0) partials[(int64_t)w * 8 + idx] = tot;
           }
-        };
-        if (mq) loop(std::false_type{});
-        else loop(std::true_type{});
+        }
       }
     }
     __syncthreads();   // every wave is done with this unit's LDS and s_unit
@@ -1532,7 +1439,7 @@ __global__ __launch_bounds__(256) void k_bin_mix(const int2* __restrict__ items,
     if (!xflag[w]) {
       const double* r = rec + (int64_t)w * kRec;
       const int deg = (int)r[L::tail + 4];
-      kind = r[L::tail + 3] == 0.0 ? 3 : (deg == 5 ? 0 : (deg == 7 ? 1 : 2));
+      kind = deg == 5 ? 0 : (deg == 7 ? 1 : 2);
     }
     atomicAdd(&acc[kind], (unsigned long long)(b1 - b0));
   }
@@ -2196,20 +2103,20 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
                          ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.xerr, ws.direct,
                          ws.ndirect, um, ws.partials);
     }
-    // w, u (and e_j and the sincos table on the FP64 path) at the largest tile's stride
-    const size_t lds = mixed ? (size_t)kMaxTileMixed * 3 * sizeof(float)
-                             : (size_t)kMaxTileFp64 * 4 * sizeof(double) + kSinTab * sizeof(double2);
+    // w (and e_j and the sincos table on the FP64 path) at the largest tile's stride
+    const size_t lds = mixed ? (size_t)kMaxTileMixed * 2 * sizeof(float)
+                             : (size_t)kMaxTileFp64 * (2 * sizeof(double) + sizeof(float)) +
+                                   kSinTab * sizeof(double2);
     if (ev_main) (void)hipEventRecord(ev_main[0], s);
     if (mixed)
       hipLaunchKernelGGL(k_eval_interp<true>, dim3(blocks), dim3(256), lds, s, g, ws.bounds, stride,
                          ws.items, chunk, ws.tile_items, ws.toff, ws.uoff, ntiles, ws.tile_ctr,
-                         b.wr, b.wi,
-                         b.u, b32.wr, b32.wi, b32.u, ws.rec, ws.xflag, ws.partials);
+                         b.wr, b.wi, b32.wr, b32.wi, ws.rec, ws.xflag, ws.partials);
     else
       hipLaunchKernelGGL(k_eval_interp<false>, dim3(blocks), dim3(256), lds, s, g, ws.bounds,
                          stride, ws.items, chunk, ws.tile_items, ws.toff, ws.uoff, ntiles,
                          ws.tile_ctr,
-                         b.wr, b.wi, b.u, b32.wr, b32.wi, b32.u, ws.rec, ws.xflag, ws.partials);
+                         b.wr, b.wi, b32.wr, b32.wi, ws.rec, ws.xflag, ws.partials);
     if (ev_main) (void)hipEventRecord(ev_main[1], s);
     sel = ws.direct;
     nsel = ws.ndirect;

@@ -39,12 +39,12 @@ def test_algorithmic_flops_follow_the_bin_mix():
     import bench
     for d in (5, 7, 9):
         assert bench.ALG_FP64[f"deg{d}"] == 63 + 4 * (d - 1)
-    mix = [10, 20, 30, 4, 1000]
+    mix = [10, 20, 30, 0, 1000]
     f64, f32 = bench.alg_flops("fp64", mix)
     assert f32 == 0.0
-    assert f64 == 10 * 79 + 20 * 87 + 30 * 95 + 4 * 132
+    assert f64 == 10 * 79 + 20 * 87 + 30 * 95
     m64, m32 = bench.alg_flops("mixed", mix)
-    assert (m64, m32) == (60 * 24 + 4 * 44, 60 * 37 + 4 * 70)
+    assert (m64, m32) == (60 * 24, 60 * 37)
 
 
 def test_counter_figures_match_the_kernel_sources():
