@@ -638,6 +638,21 @@ constexpr double kInterpTolPhase = 1e-12;
 constexpr double kInterpTolT = 2e-13;
 constexpr int kUnitItems = 32;      // items per scheduling unit of the bin loop
 constexpr double kTruncFloor = 6e-14;  // FP64 transfer truncation allowance
+// Difference recurrence of the FP64 bin loop: shortest lane run that takes
+// it (below, the set-up of about 140 operations per lane costs more than the
+// ~15 it saves per bin), the largest |phi| of its series, and the largest
+// phase error allowed from the neglected fifth difference [rad].
+constexpr int kRecMinRun = 9;
+constexpr double kRecPhiMax = 4e-3;
+constexpr double kRecTrunc = 1e-13;
+constexpr double kTwoPi = 6.283185307179586477;
+// j! S(k, j) for j = 2..5 (row j - 2), k = 0..9: the j-th forward difference
+// of t^k at t = 0
+constexpr double kDiff[4][10] = {
+    {0, 0, 2, 6, 14, 30, 62, 126, 254, 510},
+    {0, 0, 0, 6, 36, 150, 540, 1806, 5796, 18150},
+    {0, 0, 0, 0, 24, 240, 1560, 8400, 40824, 186480},
+    {0, 0, 0, 0, 0, 120, 1800, 16800, 126000, 834120}};
 
 __constant__ double c_cheb_s[kCheb];          // nodes cos(pi (k + 1/2) / 10)
 // Row tables of the node kernel, indexed [node kn][lane k of the item]: on a
@@ -1203,7 +1218,61 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         // -(B / df) e_j, with e_j the rounding error of the product (staged
         // with the tile): up to ~1e-9 cycles at t_f ~ 1e8 s.
         const double kB = -Bf / g.df;
-        const int last = nb - 1;
+        // Difference recurrence for items whose lanes get runs of at least
+        // kRecMinRun bins.  Lane l takes the contiguous bins m0 = l Lr ..
+        // m0 + Lr - 1 (Lr odd, so that the lanes' LDS addresses fall in
+        // distinct banks).  With a_k = alpha^k R^(k)(s0) / k! the phase is
+        // Phi(m0 + t) = Phi(m0) + Bp t + sum_k a_k t^k; its forward differences
+        // D_j (D_j(t + 1) = D_j(t) + D_{j+1}(t)) start at D_1 = Bp + sum_k a_k
+        // and D_j = sum_k j! S(k, j) a_k (S: Stirling numbers of the second
+        // kind).  Per bin the template factor advances as E0 <- E0 E1(t), with
+        // E1(t) = E1(0) e^{i phi(t)} and phi(t) = 2 pi sum_{i<t} D_2(i) (D_2, D_3
+        // advanced by their differences, D_4 held): no phase polynomial and no
+        // sine per bin.  Over <= 33 bins the rounding of the products stays
+        // near 1e-14, below the direct evaluation's own ~1e-13 cycles; an item
+        // takes the direct loop when phi can leave the range of its series or
+        // the neglected D_5 could move the phase by more than kRecTrunc.
+        const int Lr = ((nb + 63) >> 6) | 1;
+        const int m0 = lane * Lr;
+        const int cnt = min(max(nb - m0, 0), Lr);
+        double E0r = 0.0, E0i = 0.0, E1r = 0.0, E1i = 0.0, th2 = 0.0, th3 = 0.0, th4 = 0.0;
+        bool rec = Lr >= kRecMinRun;
+        if (rec) {
+          const double s0 = fma(alpha, (double)m0, -1.0);
+          // Taylor coefficients of R at s0 (repeated synthetic division)
+          double p[kCheb];
+#pragma unroll
+          for (int n = 0; n < kCheb; ++n) p[n] = cR[n];
+#pragma unroll
+          for (int k = 0; k < kCheb - 1; ++k)
+#pragma unroll
+            for (int j = kCheb - 2; j >= k; --j) p[j] = fma(p[j + 1], s0, p[j]);
+          double ap[kCheb];
+          ap[0] = 1.0;
+#pragma unroll
+          for (int k = 1; k < kCheb; ++k) ap[k] = ap[k - 1] * alpha;
+          double d1 = 0.0, d2 = 0.0, d3 = 0.0, d4 = 0.0, d5 = 0.0;
+#pragma unroll
+          for (int k = kCheb - 1; k >= 1; --k) {    // smallest terms first
+            const double ak = p[k] * ap[k];
+            d1 += ak;
+            if (k >= 2) d2 = fma(kDiff[0][k], ak, d2);
+            if (k >= 3) d3 = fma(kDiff[1][k], ak, d3);
+            if (k >= 4) d4 = fma(kDiff[2][k], ak, d4);
+            if (k >= 5) d5 = fma(kDiff[3][k], ak, d5);
+          }
+          d1 += Bp;
+          sincos_tab(fma(Bp, (double)m0, p[0]) + A, s_tab, E0i, E0r);
+          sincos_tab(d1, s_tab, E1i, E1r);
+          th2 = kTwoPi * d2;
+          th3 = kTwoPi * d3;
+          th4 = kTwoPi * d4;
+          const double x = (double)Lr;
+          const double phimax = x * (fabs(th2) + x * (fabs(th3) + x * fabs(th4)));
+          const double c5 = x * (x - 1.0) * (x - 2.0) * (x - 3.0) * (x - 4.0) * (1.0 / 120.0);
+          const bool ok = cnt == 0 || (phimax <= kRecPhiMax && c5 * kTwoPi * fabs(d5) <= kRecTrunc);
+          rec = __all(ok);
+        }
         // DT: degree of the transfer interpolants (5, 7 or 9)
         auto loop = [&](auto dt) {
           constexpr int DT = decltype(dt)::value;
@@ -1216,15 +1285,9 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
             double mr[DT + 1], mm[DT + 1];
 #pragma unroll
             for (int k = 0; k <= DT; ++k) mr[k] = mm[k] = 0.0;
-            auto one_bin = [&](int mi, double a, double b, double ej) {
-              const double m = (double)mi;
-              const double s = fma(alpha, m, -1.0);
-              const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
-              const double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
-              double sps, cps;
-              sincos_tab(ph, s_tab, sps, cps);
-              const double Wr = a * cps - b * sps, Wi = a * sps + b * cps;   // w e^{i Phi}
-              // even moments from W, odd ones from W s, both against even powers
+            // even moments from W = w e^{i Phi}, odd ones from W s, both
+            // against even powers of s
+            auto moments = [&](double Wr, double Wi, double s, double s2, double s4, double s8) {
               const double Vr = Wr * s, Vi = Wi * s;
               const double pe[5] = {1.0, s2, s4, s4 * s2, s8};
               mr[0] += Wr;
@@ -1237,19 +1300,64 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                 mm[k] = fma((k & 1) ? Vi : Wi, pe[k >> 1], mm[k]);
               }
             };
-            // two bins per pass (half the loop control per bin), then at most
-            // one left over per lane
-            int mi = lane;
-            for (; mi + 64 < nb; mi += 128) {
-              const int i1 = e0 + mi, i2 = i1 + 64;
-              const double a1 = s_wr[i1], b1 = s_wi[i1], e1 = s_e[i1];
-              const double a2 = s_wr[i2], b2 = s_wi[i2], e2 = s_e[i2];
-              one_bin(mi, a1, b1, e1);
-              one_bin(mi + 64, a2, b2, e2);
-            }
-            if (mi < nb) {
-              const int i1 = e0 + mi;
-              one_bin(mi, s_wr[i1], s_wi[i1], s_e[i1]);
+            if (rec) {
+              const double kBe = kTwoPi * kB;
+              double s = fma(alpha, (double)m0, -1.0), phi = 0.0, t2 = th2, t3 = th3;
+              double er = E0r, ei = E0i;
+              auto rec_bin = [&](double a, double b, float ef) {
+                // the grid rounding as the factor 1 + i eps (|eps| <~ 1e-8)
+                const double eps = kBe * (double)ef;
+                const double xr = fma(-eps, ei, er), xi = fma(eps, er, ei);
+                const double s2 = s * s, s4 = s2 * s2;
+                moments(a * xr - b * xi, a * xi + b * xr, s, s2, s4, DT == 9 ? s4 * s4 : 0.0);
+                // E1(t) = E1(0) e^{i phi}: |phi| <= kRecPhiMax, series to phi^6
+                // (cos) and phi^5 (sin), remainders below 1e-17
+                const double z = phi * phi;
+                const double cph = fma(fma3(1.0 / 24.0, z, -0.5), z, 1.0);
+                const double sph = phi * fma(fma3(1.0 / 120.0, z, -1.0 / 6.0), z, 1.0);
+                const double e1r = E1r * cph - E1i * sph, e1i = E1r * sph + E1i * cph;
+                const double nr = er * e1r - ei * e1i;
+                ei = er * e1i + ei * e1r;
+                er = nr;
+                phi += t2;
+                t2 += t3;
+                t3 += th4;
+                s += alpha;
+              };
+              const int ib = e0 + m0;
+              int t = 0;
+              for (; t + 1 < cnt; t += 2) {
+                const double a1 = s_wr[ib + t], a2 = s_wr[ib + t + 1];
+                const double b1 = s_wi[ib + t], b2 = s_wi[ib + t + 1];
+                const float f1 = s_e[ib + t], f2 = s_e[ib + t + 1];
+                rec_bin(a1, b1, f1);
+                rec_bin(a2, b2, f2);
+              }
+              if (t < cnt) rec_bin(s_wr[ib + t], s_wi[ib + t], s_e[ib + t]);
+            } else {
+              auto one_bin = [&](int mi, double a, double b, double ej) {
+                const double m = (double)mi;
+                const double s = fma(alpha, m, -1.0);
+                const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
+                const double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
+                double sps, cps;
+                sincos_tab(ph, s_tab, sps, cps);
+                moments(a * cps - b * sps, a * sps + b * cps, s, s2, s4, s8);
+              };
+              // lanes interleaved; two bins per pass (half the loop control per
+              // bin), then at most one left over per lane
+              int mi = lane;
+              for (; mi + 64 < nb; mi += 128) {
+                const int i1 = e0 + mi, i2 = i1 + 64;
+                const double a1 = s_wr[i1], b1 = s_wi[i1], e1 = s_e[i1];
+                const double a2 = s_wr[i2], b2 = s_wi[i2], e2 = s_e[i2];
+                one_bin(mi, a1, b1, e1);
+                one_bin(mi + 64, a2, b2, e2);
+              }
+              if (mi < nb) {
+                const int i1 = e0 + mi;
+                one_bin(mi, s_wr[i1], s_wi[i1], s_e[i1]);
+              }
             }
             double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
