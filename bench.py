@@ -35,26 +35,32 @@ PEAK_HBM_GBPS = 8000.0
 PEAK_LANE_INSTR = 256 * 64 * 2.4e9
 
 # Algorithmic FLOPs per bin-template of the interpolating loop (FMA = 2),
-# derived from its arithmetic (see the repository documentation): per bin the
-# item coordinate s and s^2, s^4, s^8 (5), the phase polynomial in Estrin form
-# (18) plus the linear and grid terms (5), sin/cos by table and Taylor series
-# (22), w e^{i Phi} (6), and the moments sum W s^k: W s (2), s^6 (1), k = 0, 1
-# by additions (4) and 4 per further degree, 4 (D - 1), D the item's transfer
-# degree (every interpolated item takes its M-terms by quadrature; the few
-# whose u the plan's model does not fit go to the exact loop).
-ALG_FP64 = {"deg5": 79.0, "deg7": 87.0, "deg9": 95.0}
+# derived from its arithmetic (see the repository documentation).  Direct
+# loop, per bin: the item coordinate s and s^2, s^4, s^8 (5), the phase
+# polynomial in Estrin form (18) plus the linear and grid terms (5), sin/cos by
+# table and Taylor series (22), w e^{i Phi} (6), and the moments sum W s^k: W s
+# (2), s^6 (1), k = 0, 1 by additions (4) and 4 per further degree, 4 (D - 1),
+# D the item's transfer degree: 63 + 4 (D - 1).  FP64 difference recurrence,
+# per bin: the grid term eps and the factor 1 + i eps (5), w e^{i Phi} (6),
+# s, s^2, s^4 (3), the series of e^{i phi} (10), E1 = E1(0) e^{i phi} (6),
+# E0 <- E0 E1 (6), the difference updates (3) and the same moments (7 + 4 (D -
+# 1), s^8 at D = 9): 46 + 4 (D - 1), plus 1 at D = 9.  Every interpolated item
+# takes its M-terms by quadrature (the few whose u the plan's model does not
+# fit go to the exact loop).
+ALG_FP64 = {"deg5": 79.0, "deg7": 87.0, "deg9": 95.0, "rec5": 62.0, "rec7": 70.0, "rec9": 79.0}
 # Mixed loop: FP64 phase (Horner, 24 FP64), FP32 sin/cos (2 instructions,
 # not counted), w e^{i Phi} (6), powers (5) and moments k <= 6 (26) in FP32.
 ALG_MIXED = {"n_only": (24.0, 37.0)}     # (FP64, FP32)
+BIN_MIX_KEYS = ("deg5", "deg7", "deg9", "rec5", "rec7", "rec9", "exact")
 
 
 def alg_flops(kind, mix):
     """Algorithmic FLOPs of the main kernel over one launch, from the launch's
-    bins by transfer degree (fstat_interp_stats bin_mix), as (FP64, FP32)."""
+    bins by kind of per-bin work (fstat_interp_stats bin_mix), as (FP64, FP32)."""
     if kind == "fp64":
-        return mix[0] * ALG_FP64["deg5"] + mix[1] * ALG_FP64["deg7"] + mix[2] * ALG_FP64["deg9"], 0.0
+        return sum(mix[i] * ALG_FP64[BIN_MIX_KEYS[i]] for i in range(6)), 0.0
     a = ALG_MIXED["n_only"]
-    nq = mix[0] + mix[1] + mix[2]
+    nq = sum(mix[:6])
     return nq * a[0], nq * a[1]
 
 
@@ -85,31 +91,25 @@ def calibrate(reps=10):
 # per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes
 # written per launch (WRITE_SIZE).
 MAIN_KERNEL = {"fp64": "k_eval_interp<false>", "mixed": "k_eval_interp<true>"}
-FLOP_PER_BIN = {"fp64": 91.26, "mixed": 65.99}      # FP64 + FP32
+FLOP_PER_BIN = {"fp64": 85.08, "mixed": 65.62}      # FP64 + FP32
 FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 39.18}      # of which FP32
-VALU_PER_BIN = {"fp64": 74.74, "mixed": 50.98}
+VALU_PER_BIN = {"fp64": 63.77, "mixed": 48.95}
 VALU32_PER_BIN = {"fp64": 0.01, "mixed": 25.12}      # of which FP32 arithmetic
-TRAFFIC = {"fp64": (0.4608, 6.670e7), "mixed": (0.2516, 3.789e7)}
-# sha256 of the main kernel's source (the k_eval_interp template and the two
+TRAFFIC = {"fp64": (0.4250, 1.272e8), "mixed": (0.2307, 3.778e7)}
+# sha256 of the bin-loop kernels' source (fstat_kernels.hip and the two
 # headers it builds on) when those counters were taken; the figures are
 # reported as null once it differs.
-COUNTERS_SRC_SHA = "c0f7e2b85ea8ddf19ba5c62d25c54f3be495a602490826847d336f8259c2960c"
+COUNTERS_SRC_SHA = "fc5de5549d855a1de86d0630db91fe101f8d5f1226d944851da177f5f56f55b6"
 KERNEL_HEADERS = ("fstat_internal.h", "fstat_kernels.h")
-MAIN_KERNEL_START = "template <bool MIXED>\n__global__ __launch_bounds__(256) void k_eval_interp("
 
 
 def _kernel_sha():
     import hashlib
     csrc = os.path.join(ROOT, "paper_2407_10797_amd", "csrc")
     h = hashlib.sha256()
-    for f in KERNEL_HEADERS:
+    for f in KERNEL_HEADERS + ("fstat_kernels.hip",):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
-    with open(os.path.join(csrc, "fstat_kernels.hip")) as fh:
-        src = fh.read()
-    a = src.index(MAIN_KERNEL_START)
-    b = src.index("\n}\n", a) + 3
-    h.update(src[a:b].encode())
     return h.hexdigest()
 
 
@@ -465,7 +465,7 @@ def main():
             r = time_path(plan, prm, args.np, args.steps, args.warmup, mixed, sur)
             items, rejected, refined, mix = plan.interp_stats(bin_mix=True)
             extra.update(work_items=items, exact_items=rejected, refined_items=refined,
-                         bin_mix=dict(deg5=mix[0], deg7=mix[1], deg9=mix[2], exact=mix[4]))
+                         bin_mix=dict(zip(BIN_MIX_KEYS, mix)))
             if sur:
                 extra["used"], extra["fallback"] = plan.surrogate_stats()
         except fstat.FstatError as e:

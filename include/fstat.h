@@ -373,13 +373,12 @@ int fstat_profile_read(fstat_plan_t plan, int reset, double *kernel_ms, double *
  * than 32 bins, or interpolants that missed an end point; all items after an
  * FSTAT_EVAL_EXACT evaluation), `refined` = interpolated items evaluated again
  * exactly because their partition's matrix is ill-conditioned enough for the
- * interpolation error to matter (FP64 path only).  bin_mix [5] (or NULL):
- * bins of the items by the interpolating loop's per-bin work, [0..2] at
- * transfer degree 5, 7, 9 (every mixed-path item counts as 9), [3] always 0
- * (every interpolated item takes its M-terms by quadrature; an item whose u
- * the plan's model does not fit goes to the exact loop), [4] handed to the
- * exact loop (EINVAL after an FSTAT_EVAL_EXACT evaluation).  Waits for
- * hip_stream.
+ * interpolation error to matter (FP64 path only).  bin_mix [7] (or NULL):
+ * bins of the items by the interpolating loop's per-bin work, [0..2] phase
+ * polynomial and sine at every bin, at transfer degree 5, 7, 9 (every
+ * mixed-path item counts as 9), [3..5] the FP64 loop's difference recurrence
+ * for the template factor, at degree 5, 7, 9, [6] handed to the exact loop
+ * (EINVAL after an FSTAT_EVAL_EXACT evaluation).  Waits for hip_stream.
  * EINVAL before the first evaluation.                                      */
 int fstat_interp_stats(fstat_plan_t plan, int64_t *items, int64_t *rejected, int64_t *refined,
                        int64_t *bin_mix, void *hip_stream);

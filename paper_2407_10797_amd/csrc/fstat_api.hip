@@ -562,7 +562,7 @@ int fstat_interp_stats(fstat_plan_t P, int64_t* items, int64_t* rejected, int64_
   int rc0 = FSTAT_OK;
   if (bin_mix) {
     unsigned long long* d = nullptr;
-    unsigned long long h[5] = {0, 0, 0, 0, 0};
+    unsigned long long h[kBinMix] = {};
     rc0 = hip_check(hipMalloc(&d, sizeof(h)), "alloc bin mix");
     if (!rc0) rc0 = hip_check(hipMemcpyAsync(d, h, sizeof(h), hipMemcpyHostToDevice, s), "clear bin mix");
     if (!rc0 && P->last.exact) {
@@ -577,7 +577,7 @@ int fstat_interp_stats(fstat_plan_t P, int64_t* items, int64_t* rejected, int64_
     if (!rc0) rc0 = hip_check(hipStreamSynchronize(s), "bin mix");
     if (d) (void)hipFree(d);
     if (rc0) return rc0;
-    for (int i = 0; i < 5; ++i) bin_mix[i] = (int64_t)h[i];
+    for (int i = 0; i < kBinMix; ++i) bin_mix[i] = (int64_t)h[i];
   }
   int32_t v[3] = {0, 0, 0};
   int rc = hip_check(hipMemcpyAsync(&v[0], P->ws.total, sizeof(int32_t), hipMemcpyDeviceToHost, s),

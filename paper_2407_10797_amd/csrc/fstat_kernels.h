@@ -75,7 +75,7 @@ int interp_tables_init();
 constexpr int kMaxTileFp64 = 2048;   // largest tile (bins) of the LDS-staged loops
 constexpr int kMaxTileMixed = 4096;
 int interp_max_tile(bool mixed);   // largest tile (bins) the LDS-staged loop accepts
-constexpr int kInterpRec = 55;     // doubles per interpolation record
+constexpr int kInterpRec = 59;     // doubles per interpolation record
 
 // Smooth model of the template-independent weight u = 4 df f^{-7/3} |C|^2 / S
 // (scaled): a degree-9 Chebyshev least-squares fit per u-tile of kUTile bins,
@@ -111,7 +111,8 @@ void launch_sur_knots(const Grid& g, int32_t stride, int64_t n, int64_t rows, co
 void launch_sur_check(const Grid& g, int32_t stride, int64_t n, const WorkSpace& ws,
                       const float* ynn, double* ek, double* mm, double thr,
                       unsigned long long* counters, hipStream_t s);
-// bins of the last evaluation by kind of interpolating-loop work (out[5] accumulated)
+// bins of the last evaluation by kind of interpolating-loop work (out[kBinMix] accumulated)
+constexpr int kBinMix = 7;
 void launch_bin_mix(bool mixed, int32_t stride, int32_t chunk, int32_t nch, const WorkSpace& ws,
                     unsigned long long* out, hipStream_t s);
 void launch_solve_mean(int64_t n, int32_t stride, const WorkSpace& ws, double* F_hat,

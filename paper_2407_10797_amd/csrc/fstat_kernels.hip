@@ -737,14 +737,17 @@ __device__ __forceinline__ double estrin_d(const double* c, double s, double s2,
 
 // Per-item interpolation record: monomial coefficients of R (kCheb), then of
 // Re T''_+, Im T''_+, Re T''_x, Im T''_x (nT each: kCheb, or kDegT + 1 on the
-// mixed path), then A = frac(Phi_0), B' = B - rint(B), B, 1 when the item's
-// M-terms were summed by quadrature (0: sum them per bin), and the degree the
-// FP64 loop evaluates the transfer interpolants at (5, 7 or 9).
-constexpr int kRec = 5 * kCheb + 5;
+// mixed path), then A = frac(Phi_0), B' = B - rint(B), B, the item's state
+// (0: the exact loop takes it; 1: interpolated; the FP64 bin loop sets 2 when
+// it took the difference recurrence), the degree the FP64 loop evaluates the
+// transfer interpolants at (5, 7 or 9), the item's first bin within its tile
+// and its bin count, the step alpha = 2 / (bins - 1) of s per bin and -B / df
+// (so that the bin loop needs nothing else per item, and no division).
+constexpr int kRec = 5 * kCheb + 9;
 static_assert(kRec == kInterpRec && kRec <= 64, "record layout");
 template <bool MIXED> struct RecLayout {
   static constexpr int nT = MIXED ? kDegT + 1 : kCheb;
-  static constexpr int tail = kCheb + 4 * nT;   // A, B', B, M-by-quadrature flag
+  static constexpr int tail = kCheb + 4 * nT;   // A, B', B, state, degree, first bin, bins, alpha, -B/df
 };
 
 // Chebyshev series sum_k c_k T_k(x) (Clenshaw).
@@ -909,6 +912,7 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
       // to the exact loop without evaluating their nodes
       if (k == kCheb && lane - base < kLanesItem && grp * kItemsWave + q < W) {
         xflag[w] = 1;
+        rec[(int64_t)w * kRec + RecLayout<MIXED>::tail + 3] = 0.0;
         direct[atomicAdd(ndirect, 1)] = w;
       }
       continue;
@@ -1087,7 +1091,11 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
       r[L::tail] = (p0h - floor(p0h)) + p0l;     // fractional cycle at the first bin
       r[L::tail + 1] = B - rint(B);              // whole cycles per bin drop out (m is an integer)
       r[L::tail + 2] = B;
-      r[L::tail + 3] = mq ? 1.0 : 0.0;
+      r[L::tail + 3] = rej ? 0.0 : 1.0;
+      r[L::tail + 5] = (double)(b0 % T);          // first bin within its tile
+      r[L::tail + 6] = (double)nb;
+      r[L::tail + 7] = nb > 1 ? 2.0 / (double)(nb - 1) : 0.0;
+      r[L::tail + 8] = -B / g.df;
       xflag[w] = rej ? 1 : 0;
       // the template error times the norm sqrt(sum u) max|T| of the item's
       // templates, and the M-term quadrature's error bound: its relative error
@@ -1100,14 +1108,11 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
   }
 }
 
-// The bins of the interpolated items, tile by tile: the tile's w and u are
-// staged once in LDS; each wave takes one item at a time, broadcasts its
-// record into registers and runs the per-bin loop from LDS.
+// The bins of the interpolated items, tile by tile: the tile's w is staged
+// once in LDS; each wave takes one item at a time, broadcasts its record into
+// registers and runs the per-bin loop from LDS.
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
-                                                     const int32_t* __restrict__ bounds,
-                                                     int32_t stride,
-                                                     const int2* __restrict__ items,
                                                      int32_t T,
                                                      const int32_t* __restrict__ tile_items,
                                                      const int32_t* __restrict__ tile_off,
@@ -1118,8 +1123,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                                                      const double* __restrict__ wi64,
                                                      const float* __restrict__ wr32,
                                                      const float* __restrict__ wi32,
-                                                     const double* __restrict__ rec,
-                                                     const uint8_t* __restrict__ xflag,
+                                                     double* __restrict__ rec,
                                                      double* __restrict__ partials) {
   typedef typename std::conditional<MIXED, float, double>::type DT;
   extern __shared__ unsigned char smem[];
@@ -1186,38 +1190,41 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
     __syncthreads();
     const int i0 = s_unit[1];
     const int cnt = s_unit[2];
+    typedef RecLayout<MIXED> L;
+    double* R = s_rec[wv];
+    // Each item's record holds all the loop needs of it; a wave loads the next
+    // item's record while it runs the current one, so that only the first
+    // load of a unit is waited for.
+    int wn = wv < cnt ? tile_items[i0 + wv] : 0;
+    double rv = (wv < cnt && lane < kRec) ? rec[(int64_t)wn * kRec + lane] : 0.0;
     for (int idx = wv; idx < cnt; idx += nwv) {
-      const int w = tile_items[i0 + idx];
-      if (xflag[w]) continue;                      // evaluated by the exact kernel
-      const int2 it = items[w];
-      const int p = it.x / stride, l = it.x - p * stride;
-      const int32_t* bp = bounds + (int64_t)p * (stride + 1);
-      int ct, ich;
-      item_split(it.y, g.chan.n, ct, ich);
-      int b0, b1;
-      item_bins(bp[l], bp[l + 1], ct, T, b0, b1);
-      const int nb = b1 - b0;
-      typedef RecLayout<MIXED> L;
+      const int w = wn;
       // the record through the wave's LDS slot: one write, then broadcast reads
       // (LDS operations of one wave complete in order)
-      double* R = s_rec[wv];
-      if (lane < kRec) R[lane] = rec[(int64_t)w * kRec + lane];
+      if (lane < kRec) R[lane] = rv;
       __builtin_amdgcn_wave_barrier();
+      const int idn = idx + nwv;
+      wn = idn < cnt ? tile_items[i0 + idn] : 0;
+      rv = (idn < cnt && lane < kRec) ? rec[(int64_t)wn * kRec + lane] : 0.0;
+      if (R[L::tail + 3] == 0.0) {                 // evaluated by the exact kernel
+        __builtin_amdgcn_wave_barrier();
+        continue;
+      }
+      const int e0 = (int)R[L::tail + 5];         // LDS offset of the item's first bin
+      const int nb = (int)R[L::tail + 6];
       double cR[kCheb];
 #pragma unroll
       for (int n = 0; n < kCheb; ++n) cR[n] = R[n];
       const double A = R[L::tail];
       const double Bp = R[L::tail + 1];
-      const double Bf = R[L::tail + 2];
       const int degT = (int)R[L::tail + 4];      // transfer degree (FP64 loop)
-      const double alpha = 2.0 / (double)(nb - 1);
-      const int e0 = b0 - j0;            // LDS offset of the item's first bin
+      const double alpha = R[L::tail + 7];        // 2 / (nb - 1)
       if constexpr (!MIXED) {
         // The grid is f_j = (k_lo + j) df rounded to a double; the interpolants
         // are exact in f, so the phase moves by (dPhi/df)(f_j - exact) =
         // -(B / df) e_j, with e_j the rounding error of the product (staged
         // with the tile): up to ~1e-9 cycles at t_f ~ 1e8 s.
-        const double kB = -Bf / g.df;
+        const double kB = R[L::tail + 8];           // -B / df
         // Difference recurrence for items whose lanes get runs of at least
         // kRecMinRun bins.  Lane l takes the contiguous bins m0 = l Lr ..
         // m0 + Lr - 1 (Lr odd, so that the lanes' LDS addresses fall in
@@ -1236,8 +1243,8 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         const int m0 = lane * Lr;
         const int cnt = min(max(nb - m0, 0), Lr);
         double E0r = 0.0, E0i = 0.0, E1r = 0.0, E1i = 0.0, th2 = 0.0, th3 = 0.0, th4 = 0.0;
-        bool rec = Lr >= kRecMinRun;
-        if (rec) {
+        bool use_rec = Lr >= kRecMinRun;
+        if (use_rec) {
           const double s0 = fma(alpha, (double)m0, -1.0);
           // Taylor coefficients of R at s0 (repeated synthetic division)
           double p[kCheb];
@@ -1271,8 +1278,9 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
           const double phimax = x * (fabs(th2) + x * (fabs(th3) + x * fabs(th4)));
           const double c5 = x * (x - 1.0) * (x - 2.0) * (x - 3.0) * (x - 4.0) * (1.0 / 120.0);
           const bool ok = cnt == 0 || (phimax <= kRecPhiMax && c5 * kTwoPi * fabs(d5) <= kRecTrunc);
-          rec = __all(ok);
+          use_rec = __all(ok);
         }
+        if (lane == 0 && use_rec) rec[(int64_t)w * kRec + L::tail + 3] = 2.0;   // for fstat_interp_stats
         // DT: degree of the transfer interpolants (5, 7 or 9)
         auto loop = [&](auto dt) {
           constexpr int DT = decltype(dt)::value;
@@ -1283,33 +1291,37 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
             // sum_j w_j e^{i Phi_j} s_j^k (k <= DT) and the coefficients are
             // applied once per lane afterwards: no transfer polynomial per bin.
             double mr[DT + 1], mm[DT + 1];
-#pragma unroll
-            for (int k = 0; k <= DT; ++k) mr[k] = mm[k] = 0.0;
             // even moments from W = w e^{i Phi}, odd ones from W s, both
-            // against even powers of s
-            auto moments = [&](double Wr, double Wi, double s, double s2, double s4, double s8) {
+            // against even powers of s; the first bin of a run sets them
+            auto moments = [&](auto first, double Wr, double Wi, double s, double s2, double s4,
+                               double s8) {
+              constexpr bool F = decltype(first)::value;
               const double Vr = Wr * s, Vi = Wi * s;
               const double pe[5] = {1.0, s2, s4, s4 * s2, s8};
-              mr[0] += Wr;
-              mm[0] += Wi;
-              mr[1] += Vr;
-              mm[1] += Vi;
+              mr[0] = F ? Wr : mr[0] + Wr;
+              mm[0] = F ? Wi : mm[0] + Wi;
+              mr[1] = F ? Vr : mr[1] + Vr;
+              mm[1] = F ? Vi : mm[1] + Vi;
 #pragma unroll
               for (int k = 2; k <= DT; ++k) {
-                mr[k] = fma((k & 1) ? Vr : Wr, pe[k >> 1], mr[k]);
-                mm[k] = fma((k & 1) ? Vi : Wi, pe[k >> 1], mm[k]);
+                const double xr = (k & 1) ? Vr : Wr, xi = (k & 1) ? Vi : Wi;
+                mr[k] = F ? xr * pe[k >> 1] : fma(xr, pe[k >> 1], mr[k]);
+                mm[k] = F ? xi * pe[k >> 1] : fma(xi, pe[k >> 1], mm[k]);
               }
             };
-            if (rec) {
+            using First = std::true_type;
+            using Next = std::false_type;
+            if (use_rec) {
               const double kBe = kTwoPi * kB;
               double s = fma(alpha, (double)m0, -1.0), phi = 0.0, t2 = th2, t3 = th3;
               double er = E0r, ei = E0i;
-              auto rec_bin = [&](double a, double b, float ef) {
+              auto rec_bin = [&](auto first, double a, double b, float ef) {
                 // the grid rounding as the factor 1 + i eps (|eps| <~ 1e-8)
                 const double eps = kBe * (double)ef;
                 const double xr = fma(-eps, ei, er), xi = fma(eps, er, ei);
                 const double s2 = s * s, s4 = s2 * s2;
-                moments(a * xr - b * xi, a * xi + b * xr, s, s2, s4, DT == 9 ? s4 * s4 : 0.0);
+                moments(first, a * xr - b * xi, a * xi + b * xr, s, s2, s4,
+                        DT == 9 ? s4 * s4 : 0.0);
                 // E1(t) = E1(0) e^{i phi}: |phi| <= kRecPhiMax, series to phi^6
                 // (cos) and phi^5 (sin), remainders below 1e-17
                 const double z = phi * phi;
@@ -1324,16 +1336,20 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                 t3 += th4;
                 s += alpha;
               };
+              // the first bin sets the moments (lanes without bins take w = 0);
+              // the rest of an odd run goes two bins per pass
               const int ib = e0 + m0;
-              int t = 0;
+              const bool any = cnt > 0;
+              rec_bin(First{}, any ? s_wr[ib] : 0.0, any ? s_wi[ib] : 0.0, any ? s_e[ib] : 0.0f);
+              int t = 1;
               for (; t + 1 < cnt; t += 2) {
                 const double a1 = s_wr[ib + t], a2 = s_wr[ib + t + 1];
                 const double b1 = s_wi[ib + t], b2 = s_wi[ib + t + 1];
                 const float f1 = s_e[ib + t], f2 = s_e[ib + t + 1];
-                rec_bin(a1, b1, f1);
-                rec_bin(a2, b2, f2);
+                rec_bin(Next{}, a1, b1, f1);
+                rec_bin(Next{}, a2, b2, f2);
               }
-              if (t < cnt) rec_bin(s_wr[ib + t], s_wi[ib + t], s_e[ib + t]);
+              if (t < cnt) rec_bin(Next{}, s_wr[ib + t], s_wi[ib + t], s_e[ib + t]);
             } else {
               auto one_bin = [&](int mi, double a, double b, double ej) {
                 const double m = (double)mi;
@@ -1342,8 +1358,10 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                 const double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
                 double sps, cps;
                 sincos_tab(ph, s_tab, sps, cps);
-                moments(a * cps - b * sps, a * sps + b * cps, s, s2, s4, s8);
+                moments(Next{}, a * cps - b * sps, a * sps + b * cps, s, s2, s4, s8);
               };
+#pragma unroll
+              for (int k = 0; k <= DT; ++k) mr[k] = mm[k] = 0.0;
               // lanes interleaved; two bins per pass (half the loop control per
               // bin), then at most one left over per lane
               int mi = lane;
@@ -1359,15 +1377,16 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                 one_bin(mi, s_wr[i1], s_wi[i1], s_e[i1]);
               }
             }
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            // sum Wr T+r + Wi T+i, sum Wi T+r - Wr T+i, and the same for x
+            double acc[4];
 #pragma unroll
             for (int k = 0; k <= DT; ++k) {
               const double t0 = R[kCheb + k], t1 = R[kCheb + L::nT + k];
               const double t2 = R[kCheb + 2 * L::nT + k], t3 = R[kCheb + 3 * L::nT + k];
-              acc[0] += t0 * mr[k] + t1 * mm[k];      // sum Wr T+r + Wi T+i
-              acc[1] += t0 * mm[k] - t1 * mr[k];      // sum Wi T+r - Wr T+i
-              acc[2] += t2 * mr[k] + t3 * mm[k];
-              acc[3] += t2 * mm[k] - t3 * mr[k];
+              acc[0] = (k ? acc[0] : 0.0) + (t0 * mr[k] + t1 * mm[k]);
+              acc[1] = (k ? acc[1] : 0.0) + (t0 * mm[k] - t1 * mr[k]);
+              acc[2] = (k ? acc[2] : 0.0) + (t2 * mr[k] + t3 * mm[k]);
+              acc[3] = (k ? acc[3] : 0.0) + (t2 * mm[k] - t3 * mr[k]);
             }
             __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
             const double tot = wave_sum4(acc, lane, idx);
@@ -1410,16 +1429,16 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                 mm[k] = fmaf(Wi, pw[k], mm[k]);
               }
             }
-            double red[4] = {0.0, 0.0, 0.0, 0.0};
+            double red[4];
 #pragma unroll
             for (int k = 0; k <= kDegT; ++k) {
               const double t0 = R[kCheb + k], t1 = R[kCheb + L::nT + k];
               const double t2 = R[kCheb + 2 * L::nT + k], t3 = R[kCheb + 3 * L::nT + k];
               const double r = mr[k], q = mm[k];
-              red[0] += t0 * r + t1 * q;
-              red[1] += t0 * q - t1 * r;
-              red[2] += t2 * r + t3 * q;
-              red[3] += t2 * q - t3 * r;
+              red[0] = fma(t0, r, k ? fma(t1, q, red[0]) : t1 * q);
+              red[1] = fma(t0, q, k ? fma(-t1, r, red[1]) : -t1 * r);
+              red[2] = fma(t2, r, k ? fma(t3, q, red[2]) : t3 * q);
+              red[3] = fma(t2, q, k ? fma(-t3, r, red[3]) : -t3 * r);
             }
             __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
             const double tot = wave_sum4(red, lane, idx);
@@ -1519,10 +1538,10 @@ __global__ void k_mark(const PartConst* __restrict__ pc, int64_t n, int32_t stri
 }
 
 // Bins of the last evaluation's items by the kind of per-bin work the
-// interpolating loop did on them: out[0..2] interpolated with quadrature
-// M-terms at transfer degree 5, 7, 9 (the mixed path's items all count as 9),
-// out[3] interpolated with per-bin M-terms, out[4] evaluated exactly (rejects;
-// refined items count where the interpolating loop ran them).
+// interpolating loop did on them: out[0..2] direct phase and sine per bin at
+// transfer degree 5, 7, 9 (the mixed path's items all count as 9), out[3..5]
+// the difference recurrence at degree 5, 7, 9, out[6] evaluated exactly
+// (rejects; refined items count where the interpolating loop ran them).
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_bin_mix(const int2* __restrict__ items,
                                                  const int32_t* __restrict__ total,
@@ -1532,8 +1551,8 @@ __global__ __launch_bounds__(256) void k_bin_mix(const int2* __restrict__ items,
                                                  const uint8_t* __restrict__ xflag,
                                                  unsigned long long* __restrict__ out) {
   typedef RecLayout<MIXED> L;
-  __shared__ unsigned long long acc[5];
-  if (threadIdx.x < 5) acc[threadIdx.x] = 0ull;
+  __shared__ unsigned long long acc[kBinMix];
+  if (threadIdx.x < kBinMix) acc[threadIdx.x] = 0ull;
   __syncthreads();
   const int W = total[0];
   for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < W; w += gridDim.x * blockDim.x) {
@@ -1543,16 +1562,16 @@ __global__ __launch_bounds__(256) void k_bin_mix(const int2* __restrict__ items,
     int ct, ch, b0, b1;
     item_split(it.y, nch, ct, ch);
     item_bins(bp[l], bp[l + 1], ct, T, b0, b1);
-    int kind = 4;
+    int kind = kBinMix - 1;
     if (!xflag[w]) {
       const double* r = rec + (int64_t)w * kRec;
       const int deg = (int)r[L::tail + 4];
-      kind = deg == 5 ? 0 : (deg == 7 ? 1 : 2);
+      kind = (deg == 5 ? 0 : (deg == 7 ? 1 : 2)) + (r[L::tail + 3] == 2.0 ? 3 : 0);
     }
     atomicAdd(&acc[kind], (unsigned long long)(b1 - b0));
   }
   __syncthreads();
-  if (threadIdx.x < 5 && acc[threadIdx.x]) atomicAdd(&out[threadIdx.x], acc[threadIdx.x]);
+  if (threadIdx.x < kBinMix && acc[threadIdx.x]) atomicAdd(&out[threadIdx.x], acc[threadIdx.x]);
 }
 
 void launch_bin_mix(bool mixed, int32_t stride, int32_t chunk, int32_t nch, const WorkSpace& ws,
@@ -2217,14 +2236,13 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
                                    kSinTab * sizeof(double2);
     if (ev_main) (void)hipEventRecord(ev_main[0], s);
     if (mixed)
-      hipLaunchKernelGGL(k_eval_interp<true>, dim3(blocks), dim3(256), lds, s, g, ws.bounds, stride,
-                         ws.items, chunk, ws.tile_items, ws.toff, ws.uoff, ntiles, ws.tile_ctr,
-                         b.wr, b.wi, b32.wr, b32.wi, ws.rec, ws.xflag, ws.partials);
+      hipLaunchKernelGGL(k_eval_interp<true>, dim3(blocks), dim3(256), lds, s, g, chunk,
+                         ws.tile_items, ws.toff, ws.uoff, ntiles, ws.tile_ctr, b.wr, b.wi,
+                         b32.wr, b32.wi, ws.rec, ws.partials);
     else
-      hipLaunchKernelGGL(k_eval_interp<false>, dim3(blocks), dim3(256), lds, s, g, ws.bounds,
-                         stride, ws.items, chunk, ws.tile_items, ws.toff, ws.uoff, ntiles,
-                         ws.tile_ctr,
-                         b.wr, b.wi, b32.wr, b32.wi, ws.rec, ws.xflag, ws.partials);
+      hipLaunchKernelGGL(k_eval_interp<false>, dim3(blocks), dim3(256), lds, s, g, chunk,
+                         ws.tile_items, ws.toff, ws.uoff, ntiles, ws.tile_ctr, b.wr, b.wi,
+                         b32.wr, b32.wi, ws.rec, ws.partials);
     if (ev_main) (void)hipEventRecord(ev_main[1], s);
     sel = ws.direct;
     nsel = ws.ndirect;

@@ -311,7 +311,7 @@ def fstat_mlp_grad(params, x, t):
 
 def fstat_interp_stats(plan, stream=None, bin_mix=False):
     items, rej, ref = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    mix = (ctypes.c_int64 * 5)() if bin_mix else None
+    mix = (ctypes.c_int64 * 7)() if bin_mix else None
     _check(lib().fstat_interp_stats(plan, ctypes.byref(items), ctypes.byref(rej), ctypes.byref(ref),
                                     mix, stream))
     if bin_mix:
@@ -549,8 +549,8 @@ class Plan:
     def interp_stats(self, bin_mix: bool = False):
         """(work items, items handed to the exact loop, items refined exactly) of
         the last evaluation, and with bin_mix the bins by kind of per-bin work
-        ([0..2] N-terms only at transfer degree 5, 7, 9; [3] N- and M-terms;
-        [4] exact)."""
+        ([0..2] phase and sine per bin at transfer degree 5, 7, 9; [3..5] the
+        difference recurrence at degree 5, 7, 9; [6] exact)."""
         return fstat_interp_stats(self.handle, _stream(), bin_mix)
 
     def surrogate_stats(self, n_flags: int = 0):

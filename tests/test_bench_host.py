@@ -33,17 +33,19 @@ def test_mixed_peak_is_the_time_floor_of_the_operation_mix():
 
 def test_algorithmic_flops_follow_the_bin_mix():
     """Per-bin algorithmic counts of the interpolating loop: 63 + 4 (D - 1)
-    FLOPs for the moment loop at transfer degree D, and the launch total is
-    the bin-weighted sum of its kinds (exact-loop bins are not the main
-    kernel's work)."""
+    FLOPs with the phase and sine at every bin, 46 + 4 (D - 1) (plus s^8 at
+    D = 9) with the difference recurrence, at transfer degree D; the launch
+    total is the bin-weighted sum of its kinds (exact-loop bins are not the
+    main kernel's work)."""
     import bench
     for d in (5, 7, 9):
         assert bench.ALG_FP64[f"deg{d}"] == 63 + 4 * (d - 1)
-    mix = [10, 20, 30, 0, 1000]
+        assert bench.ALG_FP64[f"rec{d}"] == 46 + 4 * (d - 1) + (d == 9)
+    mix = [10, 20, 30, 1, 2, 3, 1000]
     f64, f32 = bench.alg_flops("fp64", mix)
     assert f32 == 0.0
-    assert f64 == 10 * 79 + 20 * 87 + 30 * 95
-    m64, m32 = bench.alg_flops("mixed", mix)
+    assert f64 == 10 * 79 + 20 * 87 + 30 * 95 + 1 * 62 + 2 * 70 + 3 * 79
+    m64, m32 = bench.alg_flops("mixed", [0, 0, 60, 0, 0, 0, 1000])
     assert (m64, m32) == (60 * 24, 60 * 37)
 
 
