@@ -91,15 +91,15 @@ def calibrate(reps=10):
 # per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes
 # written per launch (WRITE_SIZE).
 MAIN_KERNEL = {"fp64": "k_eval_interp<false>", "mixed": "k_eval_interp<true>"}
-FLOP_PER_BIN = {"fp64": 85.08, "mixed": 65.62}      # FP64 + FP32
+FLOP_PER_BIN = {"fp64": 83.88, "mixed": 65.42}      # FP64 + FP32
 FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 39.18}      # of which FP32
-VALU_PER_BIN = {"fp64": 63.77, "mixed": 48.95}
+VALU_PER_BIN = {"fp64": 62.12, "mixed": 48.67}
 VALU32_PER_BIN = {"fp64": 0.01, "mixed": 25.12}      # of which FP32 arithmetic
-TRAFFIC = {"fp64": (0.4250, 1.272e8), "mixed": (0.2307, 3.778e7)}
+TRAFFIC = {"fp64": (0.3677, 1.052e+08), "mixed": (0.2153, 3.456e+07)}
 # sha256 of the bin-loop kernels' source (fstat_kernels.hip and the two
 # headers it builds on) when those counters were taken; the figures are
 # reported as null once it differs.
-COUNTERS_SRC_SHA = "fc5de5549d855a1de86d0630db91fe101f8d5f1226d944851da177f5f56f55b6"
+COUNTERS_SRC_SHA = "51a80e19a06aa51feaa4627ba878beebedbc96ccde5531e06de936460c7a1ee7"
 KERNEL_HEADERS = ("fstat_internal.h", "fstat_kernels.h")
 
 

@@ -230,8 +230,10 @@ int fstat_waveform(double T_obs, double df, int64_t k_lo, int64_t nbins, const d
 
 /* Autotuner for the bin loop: times fstat_eval of `params` (device pointers,
  * n particles; np [n] partition counts (device) with part_stride their
- * maximum, or np NULL and np_uniform for all) for work items of 256..8192
- * bins and persistent grids of 1, 2, 4 times the resident occupancy, keeps
+ * maximum, or np NULL and np_uniform for all) for work items of 256, 512,
+ * 1024, 2048, 2560, 4096, 4608 and 8192 bins (those above the interpolating
+ * loop's LDS tile, 2560 bins FP64 and 4608 mixed, for the exact loop only) and
+ * persistent grids of 1, 2, 4 times the resident occupancy, keeps
  * the fastest for the precision selected by flags (FSTAT_EVAL_MIXED) in the
  * plan, and returns it.  With FSTAT_AUTOTUNE_MODE it times the exact per-bin
  * loop as well and, when that is faster (small batches, where the

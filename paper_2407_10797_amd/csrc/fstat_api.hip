@@ -335,7 +335,7 @@ int fstat_autotune(fstat_plan_t P, const double* params, int64_t n, int32_t np_u
   if (!(flags & FSTAT_AUTOTUNE_FORCE) && tune_cache_get(key, &c, &m, &e) && c >= 64 && m >= 1) {
     // cached
   } else {
-    static const int chunks[] = {256, 512, 1024, 2048, 4096, 8192};
+    static const int chunks[] = {256, 512, 1024, 2048, 2560, 4096, 4608, 8192};
     static const int mults[] = {1, 2, 4};
     double* F = nullptr;
     int rc = hip_check(hipMalloc(&F, sizeof(double) * n), "alloc tune out");
@@ -349,7 +349,7 @@ int fstat_autotune(fstat_plan_t P, const double* params, int64_t n, int32_t np_u
     // interpolating loop (unless exact is requested), then the exact loop
     // (when requested, or when the mode is tuned as well)
     for (int ex = exact ? 1 : 0; ex <= ((exact || mode) ? 1 : 0) && !rc; ++ex)
-      for (int ci = 0; ci < 6 && !rc; ++ci)
+      for (int ci = 0; ci < (int)(sizeof(chunks) / sizeof(chunks[0])) && !rc; ++ci)
         for (int mi = 0; mi < 3 && !rc; ++mi) {
           if (!ex && chunks[ci] > interp_max_tile(mixed)) continue;
           if (mixed) { P->chunk_mixed = chunks[ci]; P->grid_mult_mixed = mults[mi]; }

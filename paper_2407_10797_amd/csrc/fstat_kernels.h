@@ -72,8 +72,8 @@ void launch_setup(const Grid& g, const double* params, int64_t n,
                   const uint8_t* skip, const WorkSpace& ws, hipStream_t s);
 void launch_worklist(int64_t m, const WorkSpace& ws, hipStream_t s);
 int interp_tables_init();
-constexpr int kMaxTileFp64 = 2048;   // largest tile (bins) of the LDS-staged loops
-constexpr int kMaxTileMixed = 4096;
+constexpr int kMaxTileFp64 = 2560;   // largest tile (bins) of the LDS-staged loops
+constexpr int kMaxTileMixed = 4608;   // FP32 w: 36 KB + 2 KB per block, four blocks per CU
 int interp_max_tile(bool mixed);   // largest tile (bins) the LDS-staged loop accepts
 constexpr int kInterpRec = 59;     // doubles per interpolation record
 

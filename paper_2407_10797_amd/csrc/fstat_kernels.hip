@@ -655,6 +655,10 @@ constexpr double kDiff[4][10] = {
     {0, 0, 0, 0, 0, 120, 1800, 16800, 126000, 834120}};
 
 __constant__ double c_cheb_s[kCheb];          // nodes cos(pi (k + 1/2) / 10)
+// (sin, cos)(2 pi k / kSinTab) for the FP64 bin loop, which needs it only in
+// the per-lane set-up of the difference recurrence and in the direct form
+// (its LDS holds the tile instead)
+__constant__ double2 c_sincos[kSinTab];
 // Row tables of the node kernel, indexed [node kn][lane k of the item]: on a
 // node lane (k < kCheb) the map node value kn -> monomial coefficient of s^k
 // of the interpolant, on the end lanes k = kCheb, kCheb + 1 the map node
@@ -1127,17 +1131,17 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                                                      double* __restrict__ partials) {
   typedef typename std::conditional<MIXED, float, double>::type DT;
   extern __shared__ unsigned char smem[];
-  // The tile's w (and on the FP64 path e_j and the sincos table) at a fixed
-  // stride of the largest tile, so that every per-bin read shares one address
-  // register (constant offsets) whatever the tile size.  Every item here has
-  // its M-terms from the node kernel's quadrature (the others go to the exact
-  // loop), so u is not staged; e_j is kept in FP32 (|e_j| <= half an ulp of
-  // f_j; its product with t_f <~ 1e8 s enters the phase at <~ 1e-10 cycles,
-  // and FP32 rounding of it at ~1e-17 cycles).  FP64: 20 B per bin, three
-  // blocks per CU.
+  // The tile's w (and on the FP64 path e_j) at a fixed stride of the largest
+  // tile, so that every per-bin read shares one address register (constant
+  // offsets) whatever the tile size.  Every item here has its M-terms from the
+  // node kernel's quadrature (the others go to the exact loop), so u is not
+  // staged; e_j is kept in FP32 (|e_j| <= half an ulp of f_j; its product with
+  // t_f <~ 1e8 s enters the phase at <~ 1e-10 cycles, and FP32 rounding of it
+  // at ~1e-17 cycles).  FP64: 20 B per bin, three blocks of 2560-bin tiles per
+  // CU.
   constexpr int TS = MIXED ? kMaxTileMixed : kMaxTileFp64;
-  double2* s_tab = reinterpret_cast<double2*>(smem);      // FP64 loop: sin, cos table
-  DT* s_wr = reinterpret_cast<DT*>(smem + (MIXED ? 0 : kSinTab * sizeof(double2)));
+  const double2* s_tab = c_sincos;                       // FP64 loop: sin, cos table
+  DT* s_wr = reinterpret_cast<DT*>(smem);
   DT* s_wi = s_wr + TS;
   float* s_e = reinterpret_cast<float*>(s_wi + TS);      // FP64 loop: grid rounding e_j
   __shared__ int s_unit[3];                       // tile, first item, item count
@@ -1150,7 +1154,6 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
   const int wv = threadIdx.x >> 6;
   const int nwv = blockDim.x >> 6;
   const int nunits = unit_off[ntiles];
-  if constexpr (!MIXED) fill_sincos_table(s_tab);
   for (;;) {
     // next unit (dynamic): up to kUnitItems items of one tile
     if (threadIdx.x == 0) {
@@ -1760,6 +1763,14 @@ int interp_tables_init() {
     }
   }
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_row9), R9, sizeof(R9)) != hipSuccess) return -1;
+  {
+    double2 tab[kSinTab];
+    for (int i = 0; i < kSinTab; ++i) {
+      const long double a = 2.0L * pi * (long double)i / (long double)kSinTab;
+      tab[i] = make_double2((double)sinl(a), (double)cosl(a));
+    }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_sincos), tab, sizeof(tab)) != hipSuccess) return -1;
+  }
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_row6), R6, sizeof(R6)) != hipSuccess) return -1;
   // truncations after degree 5 and 7 (FP64 loop)
   double Gt[2][kCheb][kCheb], Et[2][2][kCheb];
@@ -2230,10 +2241,9 @@ void launch_eval(bool mixed, bool interp, double refine_budget, const Grid& g,
                          ws.items, ws.total, chunk, ek, ws.rec, ws.xflag, ws.xerr, ws.direct,
                          ws.ndirect, um, ws.partials);
     }
-    // w (and e_j and the sincos table on the FP64 path) at the largest tile's stride
+    // w (and e_j on the FP64 path) at the largest tile's stride
     const size_t lds = mixed ? (size_t)kMaxTileMixed * 2 * sizeof(float)
-                             : (size_t)kMaxTileFp64 * (2 * sizeof(double) + sizeof(float)) +
-                                   kSinTab * sizeof(double2);
+                             : (size_t)kMaxTileFp64 * (2 * sizeof(double) + sizeof(float));
     if (ev_main) (void)hipEventRecord(ev_main[0], s);
     if (mixed)
       hipLaunchKernelGGL(k_eval_interp<true>, dim3(blocks), dim3(256), lds, s, g, chunk,

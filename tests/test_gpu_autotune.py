@@ -10,7 +10,7 @@ from tests.bars import FP64_KCOND, FP64_REL
 
 pytestmark = pytest.mark.gpu
 
-CHUNKS = {256, 512, 1024, 2048, 4096, 8192}
+CHUNKS = {256, 512, 1024, 2048, 2560, 4096, 4608, 8192}
 MULTS = {1, 2, 4}
 
 

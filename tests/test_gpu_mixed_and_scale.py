@@ -147,12 +147,18 @@ def test_paper_scale_interpolating_matches_exact_everywhere(paper, torch_cuda, n
     s = paper
     print(f"[paper] interpolating vs exact, 4096 particles, Np={npart}", flush=True)
     F, P = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, want_parts=True)
-    items, rej, ref = s["plan"].interp_stats()
+    items, rej, ref, mix = s["plan"].interp_stats(bin_mix=True)
     Fe, Pe = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, want_parts=True, exact=True)
     P, Pe = P.cpu().numpy()[:, :npart], Pe.cpu().numpy()[:, :npart]
     r = _rel(P, Pe)
+    rec, direct = sum(mix[3:6]), sum(mix[:3])
     print(f"  {items} items, {rej} exact, {ref} refined; max rel {r.max():.2e}, p99.99 "
-          f"{np.quantile(r, 0.9999):.2e}, median {np.median(r):.2e}", flush=True)
+          f"{np.quantile(r, 0.9999):.2e}, median {np.median(r):.2e}; bins by difference "
+          f"recurrence {rec}, direct {direct}, exact {mix[6]}", flush=True)
+    if npart <= 64:
+        # the smooth phases of this workload take the difference recurrence:
+        # this compares it, not only the direct form, with the exact loop
+        assert rec > 0.9 * (rec + direct), (rec, direct)
     # partitions above the budget alone: their conditioning from the oracle
     # (a handful of particles) must account for the excess
     out = np.unique(np.nonzero(r > REFINE_BUDGET)[0])

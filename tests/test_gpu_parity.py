@@ -96,16 +96,19 @@ def test_interpolating_and_exact_bin_loops_agree(small, torch_cuda, npart):
     _, _, cond = O.fstat(s["data"], s["psd"], s["g"].k_lo, s["g"].df, s["g"].T_obs, s["pts"],
                          [npart], want_cond=True)
     F, P = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, want_parts=True)
-    items, rej, ref = s["plan"].interp_stats()
+    items, rej, ref, mix = s["plan"].interp_stats(bin_mix=True)
     Fe, Pe = s["plan"].eval(torch_cuda.from_numpy(s["pts"]), npart, want_parts=True, exact=True)
     items_e, rej_e, ref_e = s["plan"].interp_stats()
-    print(f"[interp] Np={npart}: {items} items, {rej} handed to the exact loop, {ref} refined",
-          flush=True)
+    print(f"[interp] Np={npart}: {items} items, {rej} handed to the exact loop, {ref} refined; "
+          f"bins direct {sum(mix[:3])}, recurrence {sum(mix[3:6])}, exact {mix[6]}", flush=True)
     assert items == items_e and rej_e == items_e and ref_e == 0
     if npart == 1:
         # items of >= 32 bins exist only at Np = 1 here: most go through the
         # interpolating loop, so this compares the two loops, not one with itself
         assert rej < items // 2, (rej, items)
+        # the short, fast-chirping items of this workload take the direct form
+        # of the bin loop (the paper-scale tests cover the difference recurrence)
+        assert sum(mix[:3]) > 0
     P, Pe = P.cpu().numpy(), Pe.cpu().numpy()
     c = np.where(np.isfinite(cond[:, :npart]), cond[:, :npart], 0.0)
     r = _rel(P[:, :npart], Pe[:, :npart])
