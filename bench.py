@@ -49,8 +49,9 @@ PEAK_LANE_INSTR = 256 * 64 * 2.4e9
 # fit go to the exact loop).
 ALG_FP64 = {"deg5": 79.0, "deg7": 87.0, "deg9": 95.0, "rec5": 62.0, "rec7": 70.0, "rec9": 79.0}
 # Mixed loop: FP64 phase (Horner, 24 FP64), FP32 sin/cos (2 instructions,
-# not counted), w e^{i Phi} (6), powers (5) and moments k <= 6 (26) in FP32.
-ALG_MIXED = {"n_only": (24.0, 37.0)}     # (FP64, FP32)
+# not counted), w e^{i Phi} (6), powers (5) and moments k <= 6 (26) in FP32 at
+# transfer degree 6; at degree 4 powers (3) and moments k <= 4 (18).
+ALG_MIXED = {"deg6": (24.0, 37.0), "deg4": (24.0, 27.0)}     # (FP64, FP32)
 BIN_MIX_KEYS = ("deg5", "deg7", "deg9", "rec5", "rec7", "rec9", "exact")
 
 
@@ -59,9 +60,8 @@ def alg_flops(kind, mix):
     bins by kind of per-bin work (fstat_interp_stats bin_mix), as (FP64, FP32)."""
     if kind == "fp64":
         return sum(mix[i] * ALG_FP64[BIN_MIX_KEYS[i]] for i in range(6)), 0.0
-    a = ALG_MIXED["n_only"]
-    nq = sum(mix[:6])
-    return nq * a[0], nq * a[1]
+    a4, a6 = ALG_MIXED["deg4"], ALG_MIXED["deg6"]     # mixed path: [0] degree 4, [2] degree 6
+    return mix[0] * a4[0] + mix[2] * a6[0], mix[0] * a4[1] + mix[2] * a6[1]
 
 
 def floor_peak(f64, f32, p64, p32):
@@ -91,15 +91,15 @@ def calibrate(reps=10):
 # per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes
 # written per launch (WRITE_SIZE).
 MAIN_KERNEL = {"fp64": "k_eval_interp<false>", "mixed": "k_eval_interp<true>"}
-FLOP_PER_BIN = {"fp64": 83.88, "mixed": 65.42}      # FP64 + FP32
-FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 39.18}      # of which FP32
-VALU_PER_BIN = {"fp64": 62.12, "mixed": 48.67}
-VALU32_PER_BIN = {"fp64": 0.01, "mixed": 25.12}      # of which FP32 arithmetic
-TRAFFIC = {"fp64": (0.3677, 1.052e+08), "mixed": (0.2153, 3.456e+07)}
+FLOP_PER_BIN = {"fp64": 83.88, "mixed": 56.92}      # FP64 + FP32
+FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 31.18}      # of which FP32
+VALU_PER_BIN = {"fp64": 62.12, "mixed": 43.47}
+VALU32_PER_BIN = {"fp64": 0.01, "mixed": 20.32}      # of which FP32 arithmetic
+TRAFFIC = {"fp64": (0.3682, 1.052e+08), "mixed": (0.2148, 3.456e+07)}
 # sha256 of the bin-loop kernels' source (fstat_kernels.hip and the two
 # headers it builds on) when those counters were taken; the figures are
 # reported as null once it differs.
-COUNTERS_SRC_SHA = "51a80e19a06aa51feaa4627ba878beebedbc96ccde5531e06de936460c7a1ee7"
+COUNTERS_SRC_SHA = "2419b5d76693b0ffab94cbb947a52fad4619455f4a0fe3ca9dce18e507dd930d"
 KERNEL_HEADERS = ("fstat_internal.h", "fstat_kernels.h")
 
 

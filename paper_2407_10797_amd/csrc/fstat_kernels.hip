@@ -666,11 +666,14 @@ __constant__ double2 c_sincos[kSinTab];
 __constant__ double c_row9[kCheb][kLanesItem];      // degree-9 interpolant
 // The mixed path's transfer interpolants: the Chebyshev series truncated
 // after degree kDegT (its error, a few 1e-10 at 2048 bins, is far below FP32
-// rounding); node rows above kDegT are zero.  (Degree 4 would save 8 FP32
-// operations per bin but fails the end check on enough 4096-bin items that
-// the exact fallback costs more.)
+// rounding); node rows above kDegT are zero.  Items whose series truncated
+// after degree kDegTLow stays within kInterpTolTMixed at both ends take that
+// one (2 powers and 4 FP32 FMAs per bin fewer); degree 4 for every item would
+// send enough items to the exact loop to cost more than it saves.
 constexpr int kDegT = 6;
+constexpr int kDegTLow = 4;
 __constant__ double c_row6[kCheb][kLanesItem];
+__constant__ double c_row4[kCheb][kLanesItem];
 // The FP64 loop's transfer interpolants may be truncated after degree 5 or 7
 // per item when that keeps them within the item's own error (most paper-scale
 // items need 5-7 of the 10 Chebyshev terms at the 2e-13 bar).
@@ -892,6 +895,8 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     if constexpr (!MIXED) {
       s_rt[0][kn][kk] = c_rowt[0][kn][kk];
       s_rt[1][kn][kk] = c_rowt[1][kn][kk];
+    } else {
+      s_rt[0][kn][kk] = c_row4[kn][kk];
     }
   }
   fill_sincos_table(s_tab);                       // ends with a block barrier
@@ -1005,10 +1010,9 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
       for (int fn = 0; fn < 4; ++fn) {
         aT[fn] = fma(vt[fn], rT, aT[fn]);
         tmax = fmax(tmax, fabs(vt[fn]));
-        if constexpr (!MIXED) {
 #pragma unroll
-          for (int v2 = 0; v2 < 2; ++v2) aTt[v2][fn] = fma(vt[fn], s_rt[v2][kn][k], aTt[v2][fn]);
-        }
+        for (int v2 = 0; v2 < (MIXED ? 1 : 2); ++v2)
+          aTt[v2][fn] = fma(vt[fn], s_rt[v2][kn][k], aTt[v2][fn]);
       }
       // M-term integrands: lane 0 sums the quadrature, the end lanes interpolate
       const double wk = nab.x;
@@ -1026,7 +1030,7 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     const double cR = aR.hi + (aR.lo + aRx);
     bool bad = false;
     double err = 0.0;           // relative template error at this end point
-    double errt[2] = {0.0, 0.0};   // transfer error of the degree-5 and -7 truncations
+    double errt[2] = {0.0, 0.0};   // transfer error of the degree-5 and -7 (mixed: 4) truncations
     double gerr = 0.0;          // M-term integrands' error (relative to max u |T|^2)
     if (k >= kCheb) {
       const double itmax = 1.0 / tmax;      // the estimates below need no correct rounding
@@ -1039,11 +1043,9 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
         const double d = fabs(aT[fn - 1] - v[fn]);
         bad = bad || !(d <= tolT * tmax);
         err = fmax(err, d * itmax);
-        if constexpr (!MIXED) {
 #pragma unroll
-          for (int v2 = 0; v2 < 2; ++v2)
-            errt[v2] = fmax(errt[v2], fabs(aTt[v2][fn - 1] - v[fn]) * itmax);
-        }
+        for (int v2 = 0; v2 < (MIXED ? 1 : 2); ++v2)
+          errt[v2] = fmax(errt[v2], fabs(aTt[v2][fn - 1] - v[fn]) * itmax);
       }
 #pragma unroll
       for (int fn = 0; fn < 4; ++fn) gerr = fmax(gerr, fabs(aG[fn] - gq[fn]));
@@ -1063,13 +1065,16 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     // item's own interpolation error, or kTruncFloor of the largest component
     // (a larger allowance sends more items of ill-conditioned partitions to
     // the exact re-evaluation than the lower degree saves)
-    int degT = kCheb - 1;
+    int degT = MIXED ? kDegT : kCheb - 1;
     if constexpr (!MIXED) {
       const double allow = fmin(fmax(err, kTruncFloor), tolT);
       const double e7 = fmax(__shfl(errt[1], base + kCheb, 64), __shfl(errt[1], base + kCheb + 1, 64));
       const double e5 = fmax(__shfl(errt[0], base + kCheb, 64), __shfl(errt[0], base + kCheb + 1, 64));
       if (e5 <= allow) { degT = 5; err = fmax(err, e5); }
       else if (e7 <= allow) { degT = 7; err = fmax(err, e7); }
+    } else {
+      const double e4 = fmax(__shfl(errt[0], base + kCheb, 64), __shfl(errt[0], base + kCheb + 1, 64));
+      if (e4 <= tolT) { degT = kDegTLow; err = fmax(err, e4); }
     }
     const bool mine = lane - base < kLanesItem && grp * kItemsWave + q < W;   // not a repeat lane
     if (!mine) continue;
@@ -1087,7 +1092,8 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
 #pragma unroll
         for (int fn = 1; fn < 5; ++fn)
           r[kCheb + (fn - 1) * L::nT + k] =
-              degT == 5 ? aTt[0][fn - 1] : (degT == 7 ? aTt[1][fn - 1] : aT[fn - 1]);
+              MIXED ? (degT == kDegTLow ? aTt[0][fn - 1] : aT[fn - 1])
+                    : (degT == 5 ? aTt[0][fn - 1] : (degT == 7 ? aTt[1][fn - 1] : aT[fn - 1]));
       }
     } else if (k == kCheb) {
       FSTAT_NO_CONTRACT
@@ -1404,50 +1410,53 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         else loop(D9{});
       } else {
         // per lane at most T / 64 terms: plain FP32 sums of the N-terms (their
-        // rounding, ~1e-7 relative, is far inside the mixed path's bar)
-        {
+        // rounding, ~1e-7 relative, is far inside the mixed path's bar); the
+        // transfer degree is kDegT, or kDegTLow where the node kernel found it
+        // enough
+        auto loop = [&](auto dt) {
+          constexpr int D = decltype(dt)::value;
           int idx;
-          {
-            // N-terms only: FP32 moments sum_j w_j e^{i Phi_j} s_j^k (k <= 6), the
-            // transfer coefficients applied per lane after the loop in FP64
-            float mr[kDegT + 1], mm[kDegT + 1];
+          // N-terms only: FP32 moments sum_j w_j e^{i Phi_j} s_j^k (k <= D), the
+          // transfer coefficients applied per lane after the loop in FP64
+          float mr[D + 1], mm[D + 1];
 #pragma unroll
-            for (int k = 0; k <= kDegT; ++k) mr[k] = mm[k] = 0.0f;
-            for (int mi = lane; mi < nb; mi += 64) {
-              const double m = (double)mi;
-              const double s = fma(alpha, m, -1.0);
-              const double ph = fma(Bp, m, horner(cR, s)) + A;
-              const float rf = (float)(ph - rint(ph));
-              const float sps = __builtin_amdgcn_sinf(rf), cps = __builtin_amdgcn_cosf(rf);
-              const float sf = (float)s;
-              const float a = s_wr[e0 + mi], b = s_wi[e0 + mi];
-              const float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
-              const float s2 = sf * sf, s3 = s2 * sf, s4 = s2 * s2;
-              const float pw[7] = {1.0f, sf, s2, s3, s4, s4 * sf, s4 * s2};
-              mr[0] += Wr;
-              mm[0] += Wi;
+          for (int k = 0; k <= D; ++k) mr[k] = mm[k] = 0.0f;
+          for (int mi = lane; mi < nb; mi += 64) {
+            const double m = (double)mi;
+            const double s = fma(alpha, m, -1.0);
+            const double ph = fma(Bp, m, horner(cR, s)) + A;
+            const float rf = (float)(ph - rint(ph));
+            const float sps = __builtin_amdgcn_sinf(rf), cps = __builtin_amdgcn_cosf(rf);
+            const float sf = (float)s;
+            const float a = s_wr[e0 + mi], b = s_wi[e0 + mi];
+            const float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
+            const float s2 = sf * sf, s3 = s2 * sf, s4 = s2 * s2;
+            const float pw[7] = {1.0f, sf, s2, s3, s4, D > 4 ? s4 * sf : 0.0f, D > 4 ? s4 * s2 : 0.0f};
+            mr[0] += Wr;
+            mm[0] += Wi;
 #pragma unroll
-              for (int k = 1; k <= kDegT; ++k) {
-                mr[k] = fmaf(Wr, pw[k], mr[k]);
-                mm[k] = fmaf(Wi, pw[k], mm[k]);
-              }
+            for (int k = 1; k <= D; ++k) {
+              mr[k] = fmaf(Wr, pw[k], mr[k]);
+              mm[k] = fmaf(Wi, pw[k], mm[k]);
             }
-            double red[4];
-#pragma unroll
-            for (int k = 0; k <= kDegT; ++k) {
-              const double t0 = R[kCheb + k], t1 = R[kCheb + L::nT + k];
-              const double t2 = R[kCheb + 2 * L::nT + k], t3 = R[kCheb + 3 * L::nT + k];
-              const double r = mr[k], q = mm[k];
-              red[0] = fma(t0, r, k ? fma(t1, q, red[0]) : t1 * q);
-              red[1] = fma(t0, q, k ? fma(-t1, r, red[1]) : -t1 * r);
-              red[2] = fma(t2, r, k ? fma(t3, q, red[2]) : t3 * q);
-              red[3] = fma(t2, q, k ? fma(-t3, r, red[3]) : -t3 * r);
-            }
-            __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
-            const double tot = wave_sum4(red, lane, idx);
-            if ((lane & 15) == 0) partials[(int64_t)w * 8 + idx] = tot;
           }
-        }
+          double red[4];
+#pragma unroll
+          for (int k = 0; k <= D; ++k) {
+            const double t0 = R[kCheb + k], t1 = R[kCheb + L::nT + k];
+            const double t2 = R[kCheb + 2 * L::nT + k], t3 = R[kCheb + 3 * L::nT + k];
+            const double r = mr[k], q = mm[k];
+            red[0] = fma(t0, r, k ? fma(t1, q, red[0]) : t1 * q);
+            red[1] = fma(t0, q, k ? fma(-t1, r, red[1]) : -t1 * r);
+            red[2] = fma(t2, r, k ? fma(t3, q, red[2]) : t3 * q);
+            red[3] = fma(t2, q, k ? fma(-t3, r, red[3]) : -t3 * r);
+          }
+          __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
+          const double tot = wave_sum4(red, lane, idx);
+          if ((lane & 15) == 0) partials[(int64_t)w * 8 + idx] = tot;
+        };
+        if (degT == kDegTLow) loop(std::integral_constant<int, kDegTLow>{});
+        else loop(std::integral_constant<int, kDegT>{});
       }
     }
     __syncthreads();   // every wave is done with this unit's LDS and s_unit
@@ -1542,7 +1551,7 @@ __global__ void k_mark(const PartConst* __restrict__ pc, int64_t n, int32_t stri
 
 // Bins of the last evaluation's items by the kind of per-bin work the
 // interpolating loop did on them: out[0..2] direct phase and sine per bin at
-// transfer degree 5, 7, 9 (the mixed path's items all count as 9), out[3..5]
+// transfer degree 5, 7, 9 (mixed path: [0] degree 4, [2] degree 6), out[3..5]
 // the difference recurrence at degree 5, 7, 9, out[6] evaluated exactly
 // (rejects; refined items count where the interpolating loop ran them).
 template <bool MIXED>
@@ -1569,7 +1578,8 @@ __global__ __launch_bounds__(256) void k_bin_mix(const int2* __restrict__ items,
     if (!xflag[w]) {
       const double* r = rec + (int64_t)w * kRec;
       const int deg = (int)r[L::tail + 4];
-      kind = (deg == 5 ? 0 : (deg == 7 ? 1 : 2)) + (r[L::tail + 3] == 2.0 ? 3 : 0);
+      kind = MIXED ? (deg == kDegTLow ? 0 : 2)
+                   : (deg == 5 ? 0 : (deg == 7 ? 1 : 2)) + (r[L::tail + 3] == 2.0 ? 3 : 0);
     }
     atomicAdd(&acc[kind], (unsigned long long)(b1 - b0));
   }
@@ -1797,6 +1807,24 @@ int interp_tables_init() {
       for (int e = 0; e < 2; ++e) Rt[v][kk][kCheb + e] = Et[v][e][kk];
     }
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_rowt), Rt, sizeof(Rt)) != hipSuccess) return -1;
+  {
+    // truncation after degree kDegTLow (mixed loop)
+    double R4[kCheb][kLanesItem];
+    for (int kk = 0; kk < K; ++kk) {
+      long double lm = 0.0L, lp = 0.0L;
+      for (int n = 0; n < K; ++n) {
+        long double gsum = 0.0L;
+        for (int j = 0; j <= kDegTLow; ++j)
+          gsum += (2.0L / K) * cosl(pi * j * (kk + 0.5L) / K) * (j == 0 ? 0.5L : 1.0L) * M[j][n];
+        R4[kk][n] = (double)gsum;
+        lp += gsum;
+        lm += (n & 1) ? -gsum : gsum;
+      }
+      R4[kk][kCheb] = (double)lm;
+      R4[kk][kCheb + 1] = (double)lp;
+    }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_row4), R4, sizeof(R4)) != hipSuccess) return -1;
+  }
   // quadrature weights' Chebyshev part (even degrees only)
   double D[5][kCheb];
   for (int i = 0; i < 5; ++i)

@@ -549,8 +549,9 @@ class Plan:
     def interp_stats(self, bin_mix: bool = False):
         """(work items, items handed to the exact loop, items refined exactly) of
         the last evaluation, and with bin_mix the bins by kind of per-bin work
-        ([0..2] phase and sine per bin at transfer degree 5, 7, 9; [3..5] the
-        difference recurrence at degree 5, 7, 9; [6] exact)."""
+        ([0..2] phase and sine per bin at transfer degree 5, 7, 9 -- mixed path:
+        [0] degree 4, [2] degree 6; [3..5] the difference recurrence at degree
+        5, 7, 9; [6] exact)."""
         return fstat_interp_stats(self.handle, _stream(), bin_mix)
 
     def surrogate_stats(self, n_flags: int = 0):

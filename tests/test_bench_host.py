@@ -25,7 +25,7 @@ def test_mixed_peak_is_the_time_floor_of_the_operation_mix():
     p64, p32 = bench.PEAK_VALU_TFLOPS, bench.PEAK_F32_TFLOPS
     assert bench.floor_peak(1.0, 0.0, p64, p32) == pytest.approx(p64)
     assert bench.floor_peak(0.0, 1.0, p64, p32) == pytest.approx(p32)
-    f64, f32 = bench.ALG_MIXED["n_only"]
+    f64, f32 = bench.ALG_MIXED["deg6"]
     expect = (f64 + f32) / (f64 / p64 + f32 / p32)
     assert bench.floor_peak(f64, f32, p64, p32) == pytest.approx(expect)
     assert p64 < bench.floor_peak(f64, f32, p64, p32) < p32
@@ -45,8 +45,8 @@ def test_algorithmic_flops_follow_the_bin_mix():
     f64, f32 = bench.alg_flops("fp64", mix)
     assert f32 == 0.0
     assert f64 == 10 * 79 + 20 * 87 + 30 * 95 + 1 * 62 + 2 * 70 + 3 * 79
-    m64, m32 = bench.alg_flops("mixed", [0, 0, 60, 0, 0, 0, 1000])
-    assert (m64, m32) == (60 * 24, 60 * 37)
+    m64, m32 = bench.alg_flops("mixed", [40, 0, 60, 0, 0, 0, 1000])
+    assert (m64, m32) == (100 * 24, 40 * 27 + 60 * 37)
 
 
 def test_counter_figures_match_the_kernel_sources():
