@@ -238,13 +238,14 @@ def pso_surrogate_report(plan, boxes, nps, iters, res_plain, inj):
                                  / np.maximum(np.abs(res_plain["best_x"]), 1e-300)).tolist())
 
 
-def search_bench(iters, ckpt, last_stage=3, resume=False):
+def search_bench(iters, ckpt, last_stage=3, resume=False, seed=2004):
     """The three-stage search (Sec. III.B) on the paper-scale workload with the
     paper's run counts (24 t_c intervals x 24 runs, 24 x 8, 2 x 48; 128
     particles; N_seg 16, 16, 1) and `iters` iterations per stage; stages 1-2
     on the mixed path, stage 3 in FP64.  Runs stage by stage through the
     checkpoint file `ckpt` (kept with resume=True), so that a search longer
-    than one process can be continued by the next, up to `last_stage`."""
+    than one process can be continued by the next, up to `last_stage`; `seed`
+    seeds the PSO streams (the data stay the benchmark's)."""
     import torch
     from paper_2407_10797_amd import fstat, synth as S
     g, data, psd, pts, inj = make_workload(4096)
@@ -254,7 +255,7 @@ def search_bench(iters, ckpt, last_stage=3, resume=False):
     plan.autotune(prm, 1)
     if not resume and os.path.exists(ckpt):
         os.remove(ckpt)
-    desc = dict(seed=2004, flags=(fstat.FSTAT_EVAL_MIXED, fstat.FSTAT_EVAL_MIXED, 0),
+    desc = dict(seed=seed, flags=(fstat.FSTAT_EVAL_MIXED, fstat.FSTAT_EVAL_MIXED, 0),
                 checkpoint=ckpt, iters=tuple(iters))
     res, stage_s, evals = None, [None] * 3, [None] * 3
     for stage in range(1, last_stage + 1):
@@ -272,7 +273,7 @@ def search_bench(iters, ckpt, last_stage=3, resume=False):
     out = dict(config=f"paper-scale workload, box {S.PAPER_BOX.tolist()}, runs (24x24, 24x8, 2x48) x 128 "
                       f"particles, iterations {tuple(iters)}, N_seg (16, 16, 1), stages 1-2 mixed, "
                       "stage 3 FP64",
-               stages_done=int(res["stages_done"]), stage_s=stage_s, evals=evals,
+               seed=seed, stages_done=int(res["stages_done"]), stage_s=stage_s, evals=evals,
                evals_per_s=[e / s if e and s else None for e, s in zip(evals, stage_s)],
                best_F=float(res["best_F"]), F_injection_coherent=float(F_true),
                stage1_F=[float(x) for x in res["stage1_F"]],
@@ -396,6 +397,7 @@ def main():
                     help="PSO iterations of the three search stages (--only search)")
     ap.add_argument("--search-checkpoint", default="fstat_search.ckpt")
     ap.add_argument("--search-last-stage", type=int, default=3)
+    ap.add_argument("--search-seed", type=int, default=2004, help="seed of the search's PSO streams")
     ap.add_argument("--search-resume", action="store_true",
                     help="continue from --search-checkpoint instead of starting afresh")
     ap.add_argument("--no-surrogate", action="store_true")
@@ -427,7 +429,7 @@ def main():
     if args.only == "search":
         out = {"search": search_bench([int(x) for x in args.search_iters.split(",")],
                                       args.search_checkpoint, args.search_last_stage,
-                                      args.search_resume)}
+                                      args.search_resume, args.search_seed)}
         print(json.dumps(out), flush=True)
         return
     if args.only == "pso":
