@@ -164,7 +164,7 @@ int fstat_eval(fstat_plan_t plan, const double *params, int64_t n, const int32_t
  *   flags    FSTAT_EVAL_MIXED and/or FSTAT_EVAL_EXACT (FSTAT_DEVICE_PTRS is
  *            implied)
  * The scratch holds n x (ceil(nbins / chunk) x channels + part_stride) work
- * items at about 530 bytes each (chunk: the plan's work-item size); with the
+ * items at about 565 bytes each (chunk: the plan's work-item size); with the
  * default 2048-bin items that is e.g. 320 particles at Np = 256 on 20,972
  * bins, or 16,384 particles at Np = 1; larger calls fail with EINVAL and a
  * message giving the bytes needed.
