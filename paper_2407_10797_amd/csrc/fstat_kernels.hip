@@ -1386,16 +1386,17 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                 one_bin(mi, s_wr[i1], s_wi[i1], s_e[i1]);
               }
             }
-            // sum Wr T+r + Wi T+i, sum Wi T+r - Wr T+i, and the same for x
+            // sum Wr T+r + Wi T+i, sum Wi T+r - Wr T+i, and the same for x: FMA
+            // chains, one transfer component pair at a time (fewer live registers)
             double acc[4];
 #pragma unroll
-            for (int k = 0; k <= DT; ++k) {
-              const double t0 = R[kCheb + k], t1 = R[kCheb + L::nT + k];
-              const double t2 = R[kCheb + 2 * L::nT + k], t3 = R[kCheb + 3 * L::nT + k];
-              acc[0] = (k ? acc[0] : 0.0) + (t0 * mr[k] + t1 * mm[k]);
-              acc[1] = (k ? acc[1] : 0.0) + (t0 * mm[k] - t1 * mr[k]);
-              acc[2] = (k ? acc[2] : 0.0) + (t2 * mr[k] + t3 * mm[k]);
-              acc[3] = (k ? acc[3] : 0.0) + (t2 * mm[k] - t3 * mr[k]);
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+              for (int k = 0; k <= DT; ++k) {
+                const double tr = R[kCheb + 2 * h * L::nT + k], ti = R[kCheb + (2 * h + 1) * L::nT + k];
+                acc[2 * h] = fma(tr, mr[k], k ? fma(ti, mm[k], acc[2 * h]) : ti * mm[k]);
+                acc[2 * h + 1] = fma(tr, mm[k], k ? fma(-ti, mr[k], acc[2 * h + 1]) : -ti * mr[k]);
+              }
             }
             __builtin_amdgcn_wave_barrier();   // the slot is rewritten for the next item
             const double tot = wave_sum4(acc, lane, idx);
