@@ -14,8 +14,10 @@
 //   k_tile_*        items grouped by tile; scheduling units of <= 32 items
 //   k_eval_interp   persistent blocks take units dynamically, stage the tile's
 //                   data in LDS, and evaluate the interpolated template at every
-//                   bin of each item: the eight partition sums {Z+, Zx, P, Q, R}
-//                   per item (deterministic, no float atomics)
+//                   bin of each item (FP64: advanced by a difference recurrence
+//                   along each lane's run of bins): the N-term sums per item
+//                   (deterministic, no float atomics); the M-terms come from the
+//                   node kernel's quadrature
 //   k_eval_exact    the exact template at every bin, for handed-over items, for
 //                   refinement and under FSTAT_EVAL_EXACT (FP64 and mixed)
 //   k_mark          partitions whose interpolation error could matter -> exact
@@ -626,9 +628,9 @@ __global__ __launch_bounds__(256) void k_eval_exact(Grid g,
 // than 1e-12 cycles (phase; the exact phase itself carries ~1e-13) or 2e-13 of
 // the largest transfer component, or that has fewer than kMinInterp bins,
 // goes to the exact per-bin kernels (sel list).
-// An error e in the template moves F by up to 2 cond(M) e, so partitions
-// where that could exceed the plan's refinement budget (default 1e-9,
-// relative) are evaluated again exactly (k_mark).
+// Items whose interpolation error could move their partition's F by more
+// than the plan's refinement budget (default 5e-10, relative; the first-order
+// estimate of k_mark) are evaluated again exactly.
 // Node evaluation packs 5 items x 12 points onto one wavefront's lanes.
 constexpr int kCheb = 10;
 constexpr int kLanesItem = kCheb + 2;
@@ -639,7 +641,7 @@ constexpr double kInterpTolT = 2e-13;
 constexpr int kUnitItems = 32;      // items per scheduling unit of the bin loop
 constexpr double kTruncFloor = 6e-14;  // FP64 transfer truncation allowance
 // Difference recurrence of the FP64 bin loop: shortest lane run that takes
-// it (below, the set-up of about 140 operations per lane costs more than the
+// it (below, the set-up of about 160 operations per lane costs more than the
 // ~15 it saves per bin), the largest |phi| of its series, and the largest
 // phase error allowed from the neglected fifth difference [rad].
 constexpr int kRecMinRun = 9;
@@ -665,7 +667,7 @@ __constant__ double2 c_sincos[kSinTab];
 // value kn -> interpolant at s = -1, +1.
 __constant__ double c_row9[kCheb][kLanesItem];      // degree-9 interpolant
 // The mixed path's transfer interpolants: the Chebyshev series truncated
-// after degree kDegT (its error, a few 1e-10 at 2048 bins, is far below FP32
+// after degree kDegT (its error, ~1e-10 on paper-scale items, is far below FP32
 // rounding); node rows above kDegT are zero.  Items whose series truncated
 // after degree kDegTLow stays within kInterpTolTMixed at both ends take that
 // one (2 powers and 4 FP32 FMAs per bin fewer); degree 4 for every item would
