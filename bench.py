@@ -96,11 +96,11 @@ FLOP_PER_BIN = {"fp64": 83.76, "mixed": 56.92}      # FP64 + FP32
 FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 31.18}      # of which FP32
 VALU_PER_BIN = {"fp64": 61.23, "mixed": 43.47}
 VALU32_PER_BIN = {"fp64": 0.01, "mixed": 20.32}      # of which FP32 arithmetic
-TRAFFIC = {"fp64": (0.3679, 1.052e+08), "mixed": (0.2149, 3.456e+07)}
+TRAFFIC = {"fp64": (0.3685, 1.052e+08), "mixed": (0.2148, 3.457e+07)}
 # sha256 of the bin-loop kernels' code (fstat_kernels.hip and the two headers
 # it builds on, comments removed) when those counters were taken; the figures
 # are reported as null once it differs.
-COUNTERS_SRC_SHA = "a90406e7c61f47d861f7b721271a44b59a14104606c55207e87cafc1fd289d60"
+COUNTERS_SRC_SHA = "fc3abbabbb06234b631ff1d46e078220f1925de9071df41893f47773be14179b"
 KERNEL_HEADERS = ("fstat_internal.h", "fstat_kernels.h")
 
 

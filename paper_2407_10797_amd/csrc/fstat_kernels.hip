@@ -441,6 +441,7 @@ __device__ __forceinline__ double wave_sum4(const double* a, int lane, int& idx)
 }
 
 constexpr int kSmallItem = 8;   // exact kernel: items this short share a wavefront
+constexpr int kBigItem = 256;   // exact kernel: items longer than this take a whole block
 
 // Exact per-bin template loop.  FP64 (MIXED = false): everything in FP64,
 // Kahan-compensated per-lane sums.  Mixed (MIXED = true): the phase, the orbit
@@ -476,6 +477,7 @@ __global__ __launch_bounds__(256) void k_eval_exact(Grid g,
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
   __shared__ double2 s_tab[kSinTab];              // coarse angles of the template's sin/cos
+  __shared__ double s_red[4][8];                  // per-wave sums of a block-wide item
   fill_sincos_table(s_tab);
   // The eight partition terms of bin j for the item (q, c) of a particle;
   // on the mixed path t[0..3] are FP32 products (widened).
@@ -563,6 +565,46 @@ __global__ __launch_bounds__(256) void k_eval_exact(Grid g,
       for (int i = 0; i < 8; ++i) partials[(int64_t)w * 8 + i] = t[i];
     }
   }
+  // Kahan-compensated sums of this thread's bins j0, j0 + step, ... < j1 of
+  // one item (true sum ~ acc - cmp, returned compensated): the partition
+  // matrix can have cond ~ 1e5..1e8, which amplifies summation error.
+  auto thread_sums = [&](int qb, int cb, int j0, int j1, int step, double* acc) {
+    double cmp[8];
+    float accf[4], cmpf[4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = cmp[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) accf[i] = cmpf[i] = 0.0f;
+    for (int j = j0; j < j1; j += step) {
+      double tt[8];
+      terms(qb, cb, j, tt);
+      if constexpr (MIXED) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) kahan_addf(accf[i], cmpf[i], (float)tt[i]);
+#pragma unroll
+        for (int i = 4; i < 8; ++i) kahan_add(acc[i], cmp[i], tt[i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) kahan_add(acc[i], cmp[i], tt[i]);
+      }
+    }
+    if constexpr (MIXED) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] = (double)accf[i] - (double)cmpf[i];
+#pragma unroll
+      for (int i = 4; i < 8; ++i) acc[i] -= cmp[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[i] -= cmp[i];
+    }
+  };
+  // A short list (rejects, refinement) leaves most wavefronts idle while a few
+  // take its long items: there items above kBigItem bins take a whole block.
+  // A long list (every item, FSTAT_EVAL_EXACT) fills the grid one item per
+  // wavefront.
+  const bool by_block = W < 4 * nwaves;
+  // items of kSmallItem + 1 bins and more (up to kBigItem for a short list):
+  // one per wavefront
   for (int slot = wave; slot < W; slot += nwaves) {
     // the slot is the same on every lane: keep the item's indices scalar
     const int wb = __builtin_amdgcn_readfirstlane(sel ? sel[slot] : slot);
@@ -572,42 +614,36 @@ __global__ __launch_bounds__(256) void k_eval_exact(Grid g,
     cb = __builtin_amdgcn_readfirstlane(cb);
     bb0 = __builtin_amdgcn_readfirstlane(bb0);
     bb1 = __builtin_amdgcn_readfirstlane(bb1);
-    if (bb1 - bb0 <= kSmallItem) continue;
-    {
-      // Kahan-compensated per-lane sums (true sum ~ acc - cmp): the partition
-      // matrix can have cond ~ 1e5..1e8, which amplifies summation error.
-      double acc[8], cmp[8];
-      float accf[4], cmpf[4];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) acc[i] = cmp[i] = 0.0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) accf[i] = cmpf[i] = 0.0f;
-      for (int j = bb0 + lane; j < bb1; j += 64) {
-        double tt[8];
-        terms(qb, cb, j, tt);
-        if constexpr (MIXED) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) kahan_addf(accf[i], cmpf[i], (float)tt[i]);
-#pragma unroll
-          for (int i = 4; i < 8; ++i) kahan_add(acc[i], cmp[i], tt[i]);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 8; ++i) kahan_add(acc[i], cmp[i], tt[i]);
-        }
-      }
-      if constexpr (MIXED) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = (double)accf[i] - (double)cmpf[i];
-#pragma unroll
-        for (int i = 4; i < 8; ++i) acc[i] -= cmp[i];
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] -= cmp[i];
-      }
-      int idx;
-      const double tot = wave_sum8(acc, lane, idx);
-      if ((lane & 7) == 0) partials[(int64_t)wb * 8 + idx] = tot;
-    }
+    if (bb1 - bb0 <= kSmallItem || (by_block && bb1 - bb0 > kBigItem)) continue;
+    double acc[8];
+    thread_sums(qb, cb, bb0 + lane, bb1, 64, acc);
+    int idx;
+    const double tot = wave_sum8(acc, lane, idx);
+    if ((lane & 7) == 0) partials[(int64_t)wb * 8 + idx] = tot;
+  }
+  // longer items: one per block (a few long rejects or refined items would
+  // otherwise each hold one wavefront for the whole pass); the four waves'
+  // sums are added in a fixed order
+  for (int slot = blockIdx.x; by_block && slot < W; slot += gridDim.x) {
+    const int wb = __builtin_amdgcn_readfirstlane(sel ? sel[slot] : slot);
+    int qb, cb, bb0, bb1;
+    bins_of(wb, qb, cb, bb0, bb1);
+    qb = __builtin_amdgcn_readfirstlane(qb);
+    cb = __builtin_amdgcn_readfirstlane(cb);
+    bb0 = __builtin_amdgcn_readfirstlane(bb0);
+    bb1 = __builtin_amdgcn_readfirstlane(bb1);
+    if (bb1 - bb0 <= kBigItem) continue;         // the same for every thread of the block
+    double acc[8];
+    thread_sums(qb, cb, bb0 + (int)threadIdx.x, bb1, (int)blockDim.x, acc);
+    int idx;
+    const double tot = wave_sum8(acc, lane, idx);
+    if ((lane & 7) == 0) s_red[threadIdx.x >> 6][idx] = tot;
+    __syncthreads();
+    if (threadIdx.x < 8)
+      partials[(int64_t)wb * 8 + threadIdx.x] =
+          ((s_red[0][threadIdx.x] + s_red[1][threadIdx.x]) + s_red[2][threadIdx.x]) +
+          s_red[3][threadIdx.x];
+    __syncthreads();                              // s_red is rewritten by the next item
   }
 }
 
