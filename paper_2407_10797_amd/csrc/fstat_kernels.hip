@@ -535,8 +535,10 @@ __global__ __launch_bounds__(256) void k_eval_exact(Grid g,
   // of eight list entries per wavefront, eight lanes each (one bin per lane,
   // then a fixed three-step butterfly); larger ones one per wavefront in a
   // second sweep over the list, so that a list of long items (the refinement
-  // pass) spreads over the whole grid.  Which path an item takes depends on
-  // the item alone, so its sums do not depend on the order of the list.
+  // pass) spreads over the whole grid, and on a short list those above
+  // kBigItem bins one per block in a third.  Which path an item takes depends
+  // on the item and the list's length alone, so its sums do not depend on the
+  // order of the list.
   const int W = sel ? nsel[0] : total[0];
   const int G = (W + 7) >> 3;
   for (int gi = wave; gi < G; gi += nwaves) {
