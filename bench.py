@@ -54,6 +54,14 @@ ALG_FP64 = {"deg5": 79.0, "deg7": 87.0, "deg9": 95.0, "rec5": 62.0, "rec7": 70.0
 # transfer degree 6; at degree 4 powers (3) and moments k <= 4 (18).
 ALG_MIXED = {"deg6": (24.0, 37.0), "deg4": (24.0, 27.0)}     # (FP64, FP32)
 BIN_MIX_KEYS = ("deg5", "deg7", "deg9", "rec5", "rec7", "rec9", "exact")
+# The mixed path fills [0] (transfer degree 4), [2] (degree 6) and [6] (exact).
+BIN_MIX_KEYS_MIXED = ("deg4", None, "deg6", None, None, None, "exact")
+
+
+def bin_mix_dict(mixed, mix):
+    """fstat_interp_stats bin_mix as a dict keyed by the kind of per-bin work."""
+    keys = BIN_MIX_KEYS_MIXED if mixed else BIN_MIX_KEYS
+    return {k: v for k, v in zip(keys, mix) if k is not None}
 
 
 def alg_flops(kind, mix):
@@ -474,7 +482,7 @@ def main():
             r = time_path(plan, prm, args.np, args.steps, args.warmup, mixed, sur)
             items, rejected, refined, mix = plan.interp_stats(bin_mix=True)
             extra.update(work_items=items, exact_items=rejected, refined_items=refined,
-                         bin_mix=dict(zip(BIN_MIX_KEYS, mix)))
+                         bin_mix=bin_mix_dict(mixed, mix))
             if sur:
                 extra["used"], extra["fallback"] = plan.surrogate_stats()
         except fstat.FstatError as e:

@@ -47,6 +47,9 @@ def test_algorithmic_flops_follow_the_bin_mix():
     assert f64 == 10 * 79 + 20 * 87 + 30 * 95 + 1 * 62 + 2 * 70 + 3 * 79
     m64, m32 = bench.alg_flops("mixed", [40, 0, 60, 0, 0, 0, 1000])
     assert (m64, m32) == (100 * 24, 40 * 27 + 60 * 37)
+    assert bench.bin_mix_dict(True, [40, 0, 60, 0, 0, 0, 1000]) == {
+        "deg4": 40, "deg6": 60, "exact": 1000}
+    assert list(bench.bin_mix_dict(False, mix).values()) == mix
 
 
 def test_counter_figures_match_the_kernel_sources():
