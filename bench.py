@@ -35,42 +35,59 @@ PEAK_F32_TFLOPS = 157.3
 PEAK_HBM_GBPS = 8000.0
 PEAK_LANE_INSTR = 256 * 64 * 2.4e9
 
-# Algorithmic FLOPs per bin-template of the interpolating loop (FMA = 2),
-# derived from its arithmetic (see the repository documentation).  Direct
-# loop, per bin: the item coordinate s and s^2, s^4, s^8 (5), the phase
-# polynomial in Estrin form (18) plus the linear and grid terms (5), sin/cos by
-# table and Taylor series (22), w e^{i Phi} (6), and the moments sum W s^k: W s
-# (2), s^6 (1), k = 0, 1 by additions (4) and 4 per further degree, 4 (D - 1),
-# D the item's transfer degree: 63 + 4 (D - 1).  FP64 difference recurrence,
-# per bin: the grid term eps and the factor 1 + i eps (5), w e^{i Phi} (6),
-# s, s^2, s^4 (3), the series of e^{i phi} (10), E1 = E1(0) e^{i phi} (6),
-# E0 <- E0 E1 (6), the difference updates (3) and the same moments (7 + 4 (D -
-# 1), s^8 at D = 9): 46 + 4 (D - 1), plus 1 at D = 9.  Every interpolated item
-# takes its M-terms by quadrature (the few whose u the plan's model does not
-# fit go to the exact loop).
-ALG_FP64 = {"deg5": 79.0, "deg7": 87.0, "deg9": 95.0, "rec5": 62.0, "rec7": 70.0, "rec9": 79.0}
-# Mixed loop: FP64 phase (Horner, 24 FP64), FP32 sin/cos (2 instructions,
-# not counted), w e^{i Phi} (6), powers (5) and moments k <= 6 (26) in FP32 at
-# transfer degree 6; at degree 4 powers (3) and moments k <= 4 (18).
+# Algorithmic FLOPs of the interpolating loop (FMA = 2), derived from its
+# arithmetic (see the repository documentation), per bin-template and per lane
+# run (the lanes of an item that hold bins, each of which does its per-lane
+# work once).  Direct loop, per bin: the item coordinate s and s^2, s^4, s^8
+# (5), the phase polynomial in Estrin form (18) plus the linear and grid terms
+# (5), sin/cos by table and Taylor series (22), w e^{i Phi} (6), and the
+# moments sum W s^k: W s (2), s^6 (1), k = 0, 1 by additions (4) and 4 per
+# further degree, 4 (D - 1), D the item's transfer degree: 63 + 4 (D - 1).
+# FP64 difference recurrence, per bin: the grid term eps and the factor
+# 1 + i eps (5), w e^{i Phi} x into the zeroth binomial moment (8), the series
+# of e^{i phi} (10), E1 = E1(0) e^{i phi} (6), E0 <- E0 E1 (6), the difference
+# updates (3) and the binomial moments' running sums (2 D): 38 + 2 D.  Per
+# run, every loop applies the transfer coefficients to the moments, 4 sums of
+# D + 1 terms (12 + 16 D); the recurrence also has its set-up (the start s,
+# the Taylor shift of the phase polynomial (90), powers of the step (9), the
+# forward differences (71), the two start factors (48: phase, two table
+# sin/cos), the scaled differences (3): 223) and the moments' change from
+# binomial to power form (Stirling numbers 2 D (D - 1), scaling 3 D, shift to
+# the origin 2 D (D + 1), the run's end 2: 4 D^2 + 3 D + 2).  Every
+# interpolated item takes its M-terms by quadrature (the few whose u the
+# plan's model does not fit go to the exact loop).
+ALG_FP64 = {"deg5": 79.0, "deg7": 87.0, "deg9": 95.0, "rec5": 48.0, "rec7": 52.0, "rec9": 56.0}
+RUN_FP64 = {"deg5": 92.0, "deg7": 124.0, "deg9": 156.0, "rec5": 432.0, "rec7": 566.0, "rec9": 732.0}
+# Mixed loop, per bin: FP64 phase (Horner, 24 FP64), FP32 sin/cos (2
+# instructions, not counted), w e^{i Phi} (6), powers (5) and moments k <= 6
+# (26) in FP32 at transfer degree 6; at degree 4 powers (3) and moments k <= 4
+# (18).  Per run: the coefficients in FP64, 12 + 16 D.
 ALG_MIXED = {"deg6": (24.0, 37.0), "deg4": (24.0, 27.0)}     # (FP64, FP32)
+RUN_MIXED = {"deg6": 108.0, "deg4": 76.0}                    # FP64
 BIN_MIX_KEYS = ("deg5", "deg7", "deg9", "rec5", "rec7", "rec9", "exact")
 # The mixed path fills [0] (transfer degree 4), [2] (degree 6) and [6] (exact).
 BIN_MIX_KEYS_MIXED = ("deg4", None, "deg6", None, None, None, "exact")
 
 
 def bin_mix_dict(mixed, mix):
-    """fstat_interp_stats bin_mix as a dict keyed by the kind of per-bin work."""
+    """fstat_interp_stats bin_mix as two dicts keyed by the kind of work: the
+    bins ([0..6]) and the lane runs ([7..12]; "exact": the items, [13])."""
     keys = BIN_MIX_KEYS_MIXED if mixed else BIN_MIX_KEYS
-    return {k: v for k, v in zip(keys, mix) if k is not None}
+    return ({k: v for k, v in zip(keys, mix[:7]) if k is not None},
+            {k: v for k, v in zip(keys, mix[7:14]) if k is not None})
 
 
-def alg_flops(kind, mix):
+def alg_flops(kind, mix, runs=True):
     """Algorithmic FLOPs of the main kernel over one launch, from the launch's
-    bins by kind of per-bin work (fstat_interp_stats bin_mix), as (FP64, FP32)."""
+    bins and lane runs by kind of work (fstat_interp_stats bin_mix), as (FP64,
+    FP32); runs=False: the per-bin work alone."""
+    r = 1.0 if runs else 0.0
     if kind == "fp64":
-        return sum(mix[i] * ALG_FP64[BIN_MIX_KEYS[i]] for i in range(6)), 0.0
+        k = BIN_MIX_KEYS
+        return sum(mix[i] * ALG_FP64[k[i]] + r * mix[7 + i] * RUN_FP64[k[i]] for i in range(6)), 0.0
     a4, a6 = ALG_MIXED["deg4"], ALG_MIXED["deg6"]     # mixed path: [0] degree 4, [2] degree 6
-    return mix[0] * a4[0] + mix[2] * a6[0], mix[0] * a4[1] + mix[2] * a6[1]
+    f64 = mix[0] * a4[0] + mix[2] * a6[0] + r * (mix[7] * RUN_MIXED["deg4"] + mix[9] * RUN_MIXED["deg6"])
+    return f64, mix[0] * a4[1] + mix[2] * a6[1]
 
 
 def floor_peak(f64, f32, p64, p32):
@@ -481,8 +498,9 @@ def main():
                 _log(f"{name}: autotuned work item {c} bins, grid x{m}")
             r = time_path(plan, prm, args.np, args.steps, args.warmup, mixed, sur)
             items, rejected, refined, mix = plan.interp_stats(bin_mix=True)
+            bmix, rmix = bin_mix_dict(mixed, mix)
             extra.update(work_items=items, exact_items=rejected, refined_items=refined,
-                         bin_mix=bin_mix_dict(mixed, mix))
+                         bin_mix=bmix, run_mix=rmix)
             if sur:
                 extra["used"], extra["fallback"] = plan.surrogate_stats()
         except fstat.FstatError as e:
@@ -492,15 +510,19 @@ def main():
         kind = "mixed" if mixed else "fp64"
         secs = r["main_ms"] * 1e-3          # the main kernel alone (HIP events)
         bins = r["bins_per_launch"]
-        # algorithmic FLOPs of the main kernel per launch, from its bin mix
+        # algorithmic FLOPs of the main kernel per launch, from its bin and run mix
         a64, a32 = alg_flops(kind, mix)
         alg = a64 + a32
         peak = floor_peak(a64, a32, PEAK_VALU_TFLOPS, PEAK_F32_TFLOPS)
         achieved = alg / secs / 1e12
         step_secs = r["seconds"] / args.steps
+        b64, b32 = alg_flops(kind, mix, runs=False)
         roof = dict(bound="alu", achieved=achieved, peak=round(peak, 1), unit="TFLOP/s",
                     frac=achieved / peak, flop_per_launch=alg, flop_fp32_per_launch=a32,
-                    frac_step=alg / step_secs / 1e12 / peak)
+                    frac_step=alg / step_secs / 1e12 / peak,
+                    flop_bins_per_launch=b64 + b32,
+                    frac_bins=(b64 + b32) / secs / 1e12 / floor_peak(b64, b32, PEAK_VALU_TFLOPS,
+                                                                     PEAK_F32_TFLOPS))
         if calib:
             pm = floor_peak(a64, a32, calib["fp64_fma_tflops"], calib["fp32_fma_unpacked_tflops"])
             roof.update(peak_measured=round(pm, 1), frac_measured=achieved / pm)

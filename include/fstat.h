@@ -375,12 +375,14 @@ int fstat_profile_read(fstat_plan_t plan, int reset, double *kernel_ms, double *
  * than 32 bins, or interpolants that missed an end point; all items after an
  * FSTAT_EVAL_EXACT evaluation), `refined` = interpolated items evaluated again
  * exactly because their partition's matrix is ill-conditioned enough for the
- * interpolation error to matter (FP64 path only).  bin_mix [7] (or NULL):
+ * interpolation error to matter (FP64 path only).  bin_mix [14] (or NULL):
  * bins of the items by the interpolating loop's per-bin work, [0..2] phase
  * polynomial and sine at every bin, at transfer degree 5, 7, 9 (on the mixed
  * path [0] degree 4 and [2] degree 6), [3..5] the FP64 loop's difference recurrence
- * for the template factor, at degree 5, 7, 9, [6] handed to the exact loop
- * (EINVAL after an FSTAT_EVAL_EXACT evaluation).  Waits for hip_stream.
+ * for the template factor, at degree 5, 7, 9, [6] handed to the exact loop;
+ * [7 + k] (k < 6) the lanes with bins (runs) of the items of kind k, each of
+ * which does the kind's per-lane work once, [13] the items handed to the exact
+ * loop (EINVAL after an FSTAT_EVAL_EXACT evaluation).  Waits for hip_stream.
  * EINVAL before the first evaluation.                                      */
 int fstat_interp_stats(fstat_plan_t plan, int64_t *items, int64_t *rejected, int64_t *refined,
                        int64_t *bin_mix, void *hip_stream);

@@ -111,8 +111,9 @@ void launch_sur_knots(const Grid& g, int32_t stride, int64_t n, int64_t rows, co
 void launch_sur_check(const Grid& g, int32_t stride, int64_t n, const WorkSpace& ws,
                       const float* ynn, double* ek, double* mm, double thr,
                       unsigned long long* counters, hipStream_t s);
-// bins of the last evaluation by kind of interpolating-loop work (out[kBinMix] accumulated)
-constexpr int kBinMix = 7;
+// bins of the last evaluation by kind of interpolating-loop work, then the
+// lane runs of those items by kind (out[kBinMix] accumulated)
+constexpr int kBinMix = 14;
 void launch_bin_mix(bool mixed, int32_t stride, int32_t chunk, int32_t nch, const WorkSpace& ws,
                     unsigned long long* out, hipStream_t s);
 void launch_solve_mean(int64_t n, int32_t stride, const WorkSpace& ws, double* F_hat,

@@ -686,13 +686,20 @@ constexpr int kRecMinRun = 9;
 constexpr double kRecPhiMax = 4e-3;
 constexpr double kRecTrunc = 1e-13;
 constexpr double kTwoPi = 6.283185307179586477;
-// j! S(k, j) for j = 2..5 (row j - 2), k = 0..9: the j-th forward difference
-// of t^k at t = 0
-constexpr double kDiff[4][10] = {
-    {0, 0, 2, 6, 14, 30, 62, 126, 254, 510},
-    {0, 0, 0, 6, 36, 150, 540, 1806, 5796, 18150},
-    {0, 0, 0, 0, 24, 240, 1560, 8400, 40824, 186480},
-    {0, 0, 0, 0, 0, 120, 1800, 16800, 126000, 834120}};
+// kStirF[k][j] = j! S(k, j) (S: Stirling numbers of the second kind), the
+// j-th forward difference of t^k at t = 0; equivalently
+// t^k = sum_j kStirF[k][j] C(t, j)
+constexpr double kStirF[kCheb][kCheb] = {
+    {1, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 1, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 1, 2, 0, 0, 0, 0, 0, 0, 0},
+    {0, 1, 6, 6, 0, 0, 0, 0, 0, 0},
+    {0, 1, 14, 36, 24, 0, 0, 0, 0, 0},
+    {0, 1, 30, 150, 240, 120, 0, 0, 0, 0},
+    {0, 1, 62, 540, 1560, 1800, 720, 0, 0, 0},
+    {0, 1, 126, 1806, 8400, 16800, 15120, 5040, 0, 0},
+    {0, 1, 254, 5796, 40824, 126000, 191520, 141120, 40320, 0},
+    {0, 1, 510, 18150, 186480, 834120, 1905120, 2328480, 1451520, 362880}};
 
 __constant__ double c_cheb_s[kCheb];          // nodes cos(pi (k + 1/2) / 10)
 // (sin, cos)(2 pi k / kSinTab) for the FP64 bin loop, which needs it only in
@@ -1312,10 +1319,10 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
           for (int k = kCheb - 1; k >= 1; --k) {    // smallest terms first
             const double ak = p[k] * ap[k];
             d1 += ak;
-            if (k >= 2) d2 = fma(kDiff[0][k], ak, d2);
-            if (k >= 3) d3 = fma(kDiff[1][k], ak, d3);
-            if (k >= 4) d4 = fma(kDiff[2][k], ak, d4);
-            if (k >= 5) d5 = fma(kDiff[3][k], ak, d5);
+            if (k >= 2) d2 = fma(kStirF[k][2], ak, d2);
+            if (k >= 3) d3 = fma(kStirF[k][3], ak, d3);
+            if (k >= 4) d4 = fma(kStirF[k][4], ak, d4);
+            if (k >= 5) d5 = fma(kStirF[k][5], ak, d5);
           }
           d1 += Bp;
           sincos_tab(fma(Bp, (double)m0, p[0]) + A, s_tab, E0i, E0r);
@@ -1340,37 +1347,36 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
             // sum_j w_j e^{i Phi_j} s_j^k (k <= DT) and the coefficients are
             // applied once per lane afterwards: no transfer polynomial per bin.
             double mr[DT + 1], mm[DT + 1];
-            // even moments from W = w e^{i Phi}, odd ones from W s, both
-            // against even powers of s; the first bin of a run sets them
-            auto moments = [&](auto first, double Wr, double Wi, double s, double s2, double s4,
-                               double s8) {
-              constexpr bool F = decltype(first)::value;
-              const double Vr = Wr * s, Vi = Wi * s;
-              const double pe[5] = {1.0, s2, s4, s4 * s2, s8};
-              mr[0] = F ? Wr : mr[0] + Wr;
-              mm[0] = F ? Wi : mm[0] + Wi;
-              mr[1] = F ? Vr : mr[1] + Vr;
-              mm[1] = F ? Vi : mm[1] + Vi;
-#pragma unroll
-              for (int k = 2; k <= DT; ++k) {
-                const double xr = (k & 1) ? Vr : Wr, xi = (k & 1) ? Vi : Wi;
-                mr[k] = F ? xr * pe[k >> 1] : fma(xr, pe[k >> 1], mr[k]);
-                mm[k] = F ? xi * pe[k >> 1] : fma(xi, pe[k >> 1], mm[k]);
-              }
-            };
             using First = std::true_type;
             using Next = std::false_type;
             if (use_rec) {
+              // The run's bins are equally spaced in s, so the loop sums
+              // binomial moments instead: per bin A_m += A_{m-1} (m = DT..1),
+              // then A_0 += X_t, which leaves A_m = sum_t X_t C(cnt - 1 - t, m)
+              // (X_t = w e^{i Phi} at the run's bin t); no power of s per bin.
+              // They become power moments once per lane below.
               const double kBe = kTwoPi * kB;
-              double s = fma(alpha, (double)m0, -1.0), phi = 0.0, t2 = th2, t3 = th3;
+              double phi = 0.0, t2 = th2, t3 = th3;
               double er = E0r, ei = E0i;
               auto rec_bin = [&](auto first, double a, double b, float ef) {
+                constexpr bool F = decltype(first)::value;
                 // the grid rounding as the factor 1 + i eps (|eps| <~ 1e-8)
                 const double eps = kBe * (double)ef;
                 const double xr = fma(-eps, ei, er), xi = fma(eps, er, ei);
-                const double s2 = s * s, s4 = s2 * s2;
-                moments(first, a * xr - b * xi, a * xi + b * xr, s, s2, s4,
-                        DT == 9 ? s4 * s4 : 0.0);
+                if constexpr (F) {
+                  mr[0] = fma(-b, xi, a * xr);
+                  mm[0] = fma(b, xr, a * xi);
+#pragma unroll
+                  for (int m = 1; m <= DT; ++m) mr[m] = mm[m] = 0.0;
+                } else {
+#pragma unroll
+                  for (int m = DT; m >= 1; --m) {
+                    mr[m] += mr[m - 1];
+                    mm[m] += mm[m - 1];
+                  }
+                  mr[0] = fma(a, xr, fma(-b, xi, mr[0]));
+                  mm[0] = fma(a, xi, fma(b, xr, mm[0]));
+                }
                 // E1(t) = E1(0) e^{i phi}: |phi| <= kRecPhiMax, series to phi^6
                 // (cos) and phi^5 (sin), remainders below 1e-17
                 const double z = phi * phi;
@@ -1383,7 +1389,6 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                 phi += t2;
                 t2 += t3;
                 t3 += th4;
-                s += alpha;
               };
               // the first bin sets the moments (lanes without bins take w = 0);
               // the rest of an odd run goes two bins per pass
@@ -1399,7 +1404,56 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                 rec_bin(Next{}, a2, b2, f2);
               }
               if (t < cnt) rec_bin(Next{}, s_wr[ib + t], s_wi[ib + t], s_e[ib + t]);
+              // To power moments M_k = sum_t X_t s_t^k.  With u = cnt - 1 - t,
+              // s_t = s_e - alpha u (s_e: the run's last bin): sum_t X_t u^j =
+              // sum_m m! S(j, m) A_m, scaled by (-alpha)^j, then shifted to the
+              // origin by M_k = sum_j C(k, j) s_e^(k - j) (...)_j.  Over a run
+              // of <~ 0.03 in s every step keeps its terms near the result's
+              // own size.
+#pragma unroll
+              for (int j = DT; j >= 2; --j) {
+                double pr = kStirF[j][j] * mr[j], pi = kStirF[j][j] * mm[j];
+#pragma unroll
+                for (int m = j - 1; m >= 2; --m) {
+                  pr = fma(kStirF[j][m], mr[m], pr);
+                  pi = fma(kStirF[j][m], mm[m], pi);
+                }
+                mr[j] = pr + mr[1];
+                mm[j] = pi + mm[1];
+              }
+              const double na = -alpha;
+              double pw = na;
+#pragma unroll
+              for (int j = 1; j <= DT; ++j) {
+                mr[j] *= pw;
+                mm[j] *= pw;
+                pw *= na;
+              }
+              const double se = fma(alpha, (double)(m0 + cnt - 1), -1.0);
+#pragma unroll
+              for (int k = 0; k < DT; ++k)
+#pragma unroll
+                for (int j = DT; j > k; --j) {
+                  mr[j] = fma(se, mr[j - 1], mr[j]);
+                  mm[j] = fma(se, mm[j - 1], mm[j]);
+                }
             } else {
+              // direct form: even moments from W = w e^{i Phi}, odd ones from
+              // W s, both against even powers of s
+              auto moments = [&](double Wr, double Wi, double s, double s2, double s4, double s8) {
+                const double Vr = Wr * s, Vi = Wi * s;
+                const double pe[5] = {1.0, s2, s4, s4 * s2, s8};
+                mr[0] += Wr;
+                mm[0] += Wi;
+                mr[1] += Vr;
+                mm[1] += Vi;
+#pragma unroll
+                for (int k = 2; k <= DT; ++k) {
+                  const double xr = (k & 1) ? Vr : Wr, xi = (k & 1) ? Vi : Wi;
+                  mr[k] = fma(xr, pe[k >> 1], mr[k]);
+                  mm[k] = fma(xi, pe[k >> 1], mm[k]);
+                }
+              };
               auto one_bin = [&](int mi, double a, double b, double ej) {
                 const double m = (double)mi;
                 const double s = fma(alpha, m, -1.0);
@@ -1407,7 +1461,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
                 const double ph = fma(Bp, m, estrin9(cR, s, s2, s4, s8)) + fma(kB, ej, A);
                 double sps, cps;
                 sincos_tab(ph, s_tab, sps, cps);
-                moments(Next{}, a * cps - b * sps, a * sps + b * cps, s, s2, s4, s8);
+                moments(a * cps - b * sps, a * sps + b * cps, s, s2, s4, s8);
               };
 #pragma unroll
               for (int k = 0; k <= DT; ++k) mr[k] = mm[k] = 0.0;
@@ -1450,37 +1504,121 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         else if (degT == 7) loop(D7{});
         else loop(D9{});
       } else {
-        // per lane at most T / 64 terms: plain FP32 sums of the N-terms (their
-        // rounding, ~1e-7 relative, is far inside the mixed path's bar); the
-        // transfer degree is kDegT, or kDegTLow where the node kernel found it
-        // enough
+        // Lane l takes the contiguous bins m0 = l Lr .. m0 + Lr - 1 (Lr odd:
+        // distinct LDS banks).  The phase R(s) + Bp m + A [turns] advances by
+        // its forward differences in FP64: R has degree 9, so the ninth
+        // difference is constant and every phase of the run is exact up to
+        // rounding (~1e-13 turns over a run), no polynomial per bin.  The
+        // N-terms are summed in FP32 as binomial moments (A_m += A_{m-1}, then
+        // A_0 += w e^{i Phi}: A_m = sum_t w_t e^{i Phi_t} C(cnt - 1 - t, m)),
+        // changed once per lane to power moments sum w e^{i Phi} s^k (k <= D)
+        // over the run's <~ 0.03 in s, where each step keeps its terms near the
+        // result's size; their FP32 rounding, ~1e-7 relative, is far inside the
+        // mixed path's bar.  The transfer degree is kDegT, or kDegTLow where the
+        // node kernel found it enough; the coefficients are applied in FP64.
+        const int Lr = ((nb + 63) >> 6) | 1;
+        const int m0 = lane * Lr;
+        const int cnt = min(max(nb - m0, 0), Lr);
+        double dd[kCheb];                 // dd[j]: j-th forward difference (j >= 1)
+        double ph;
+        {
+          // Taylor coefficients of R at the run's start (repeated synthetic
+          // division), a_k = alpha^k R^(k)(s0) / k!, D_j = sum_k j! S(k, j) a_k
+          const double s0 = fma(alpha, (double)m0, -1.0);
+          double p[kCheb];
+#pragma unroll
+          for (int n = 0; n < kCheb; ++n) p[n] = cR[n];
+#pragma unroll
+          for (int k = 0; k < kCheb - 1; ++k)
+#pragma unroll
+            for (int j = kCheb - 2; j >= k; --j) p[j] = fma(p[j + 1], s0, p[j]);
+          double ap[kCheb];
+          ap[1] = alpha;
+#pragma unroll
+          for (int k = 2; k < kCheb; ++k) ap[k] = ap[k - 1] * alpha;
+#pragma unroll
+          for (int j = 1; j < kCheb; ++j) dd[j] = 0.0;
+#pragma unroll
+          for (int k = kCheb - 1; k >= 1; --k) {    // smallest terms first
+            const double ak = p[k] * ap[k];
+#pragma unroll
+            for (int j = 1; j <= k; ++j) dd[j] = fma(kStirF[k][j], ak, dd[j]);
+          }
+          dd[1] += Bp;
+          ph = fma(Bp, (double)m0, p[0]) + A;
+          ph -= rint(ph);
+        }
         auto loop = [&](auto dt) {
           constexpr int D = decltype(dt)::value;
           int idx;
-          // N-terms only: FP32 moments sum_j w_j e^{i Phi_j} s_j^k (k <= D), the
-          // transfer coefficients applied per lane after the loop in FP64
           float mr[D + 1], mm[D + 1];
-#pragma unroll
-          for (int k = 0; k <= D; ++k) mr[k] = mm[k] = 0.0f;
-          for (int mi = lane; mi < nb; mi += 64) {
-            const double m = (double)mi;
-            const double s = fma(alpha, m, -1.0);
-            const double ph = fma(Bp, m, horner(cR, s)) + A;
+          auto bin = [&](auto first, float a, float b) {
+            constexpr bool F = decltype(first)::value;
             const float rf = (float)(ph - rint(ph));
             const float sps = __builtin_amdgcn_sinf(rf), cps = __builtin_amdgcn_cosf(rf);
-            const float sf = (float)s;
-            const float a = s_wr[e0 + mi], b = s_wi[e0 + mi];
-            const float Wr = a * cps - b * sps, Wi = a * sps + b * cps;
-            const float s2 = sf * sf, s3 = s2 * sf, s4 = s2 * s2;
-            const float pw[7] = {1.0f, sf, s2, s3, s4, D > 4 ? s4 * sf : 0.0f, D > 4 ? s4 * s2 : 0.0f};
-            mr[0] += Wr;
-            mm[0] += Wi;
+            if constexpr (F) {
+              mr[0] = fmaf(-b, sps, a * cps);
+              mm[0] = fmaf(b, cps, a * sps);
 #pragma unroll
-            for (int k = 1; k <= D; ++k) {
-              mr[k] = fmaf(Wr, pw[k], mr[k]);
-              mm[k] = fmaf(Wi, pw[k], mm[k]);
+              for (int m = 1; m <= D; ++m) mr[m] = mm[m] = 0.0f;
+            } else {
+#pragma unroll
+              for (int m = D; m >= 1; --m) {
+                mr[m] += mr[m - 1];
+                mm[m] += mm[m - 1];
+              }
+              mr[0] = fmaf(a, cps, fmaf(-b, sps, mr[0]));
+              mm[0] = fmaf(a, sps, fmaf(b, cps, mm[0]));
             }
+            ph += dd[1];
+#pragma unroll
+            for (int j = 1; j < kCheb - 1; ++j) dd[j] += dd[j + 1];
+          };
+          using First = std::true_type;
+          using Next = std::false_type;
+          // the first bin sets the moments (lanes without bins take w = 0);
+          // the rest of an odd run goes two bins per pass
+          const int ib = e0 + m0;
+          const bool any = cnt > 0;
+          bin(First{}, any ? s_wr[ib] : 0.0f, any ? s_wi[ib] : 0.0f);
+          int t = 1;
+          for (; t + 1 < cnt; t += 2) {
+            const float a1 = s_wr[ib + t], a2 = s_wr[ib + t + 1];
+            const float b1 = s_wi[ib + t], b2 = s_wi[ib + t + 1];
+            bin(Next{}, a1, b1);
+            bin(Next{}, a2, b2);
           }
+          if (t < cnt) bin(Next{}, s_wr[ib + t], s_wi[ib + t]);
+          // to power moments: with u = cnt - 1 - t and s_t = s_e - alpha u,
+          // sum_t X_t u^j = sum_m m! S(j, m) A_m, scaled by (-alpha)^j, then
+          // shifted to the origin by M_k = sum_j C(k, j) s_e^(k - j) (...)_j
+#pragma unroll
+          for (int j = D; j >= 2; --j) {
+            float pr = (float)kStirF[j][j] * mr[j], pi = (float)kStirF[j][j] * mm[j];
+#pragma unroll
+            for (int m = j - 1; m >= 2; --m) {
+              pr = fmaf((float)kStirF[j][m], mr[m], pr);
+              pi = fmaf((float)kStirF[j][m], mm[m], pi);
+            }
+            mr[j] = pr + mr[1];
+            mm[j] = pi + mm[1];
+          }
+          const float na = (float)(-alpha);
+          float pw = na;
+#pragma unroll
+          for (int j = 1; j <= D; ++j) {
+            mr[j] *= pw;
+            mm[j] *= pw;
+            pw *= na;
+          }
+          const float se = (float)fma(alpha, (double)(m0 + cnt - 1), -1.0);
+#pragma unroll
+          for (int k = 0; k < D; ++k)
+#pragma unroll
+            for (int j = D; j > k; --j) {
+              mr[j] = fmaf(se, mr[j - 1], mr[j]);
+              mm[j] = fmaf(se, mm[j - 1], mm[j]);
+            }
           double red[4];
 #pragma unroll
           for (int k = 0; k <= D; ++k) {
@@ -1595,6 +1733,9 @@ __global__ void k_mark(const PartConst* __restrict__ pc, int64_t n, int32_t stri
 // transfer degree 5, 7, 9 (mixed path: [0] degree 4, [2] degree 6), out[3..5]
 // the difference recurrence at degree 5, 7, 9, out[6] evaluated exactly
 // (rejects; refined items count where the interpolating loop ran them).
+// out[7 + k] (k < 6): the lanes with bins (runs) of the items of kind k, each
+// of which does its kind's per-lane work once (recurrence set-up, moments to
+// power form, coefficients); out[13]: items evaluated exactly.
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_bin_mix(const int2* __restrict__ items,
                                                  const int32_t* __restrict__ total,
@@ -1615,14 +1756,20 @@ __global__ __launch_bounds__(256) void k_bin_mix(const int2* __restrict__ items,
     int ct, ch, b0, b1;
     item_split(it.y, nch, ct, ch);
     item_bins(bp[l], bp[l + 1], ct, T, b0, b1);
-    int kind = kBinMix - 1;
+    const int nb = b1 - b0;
+    int kind = 6, runs = 1;
     if (!xflag[w]) {
       const double* r = rec + (int64_t)w * kRec;
       const int deg = (int)r[L::tail + 4];
-      kind = MIXED ? (deg == kDegTLow ? 0 : 2)
-                   : (deg == 5 ? 0 : (deg == 7 ? 1 : 2)) + (r[L::tail + 3] == 2.0 ? 3 : 0);
+      const bool dr = !MIXED && r[L::tail + 3] == 2.0;
+      kind = MIXED ? (deg == kDegTLow ? 0 : 2) : (deg == 5 ? 0 : (deg == 7 ? 1 : 2)) + (dr ? 3 : 0);
+      // the recurrence's and the mixed loop's lanes take runs of Lr
+      // contiguous bins, the FP64 direct form's lanes every 64th bin
+      const int Lr = ((nb + 63) >> 6) | 1;
+      runs = (MIXED || dr) ? (nb + Lr - 1) / Lr : min(nb, 64);
     }
-    atomicAdd(&acc[kind], (unsigned long long)(b1 - b0));
+    atomicAdd(&acc[kind], (unsigned long long)nb);
+    atomicAdd(&acc[7 + kind], (unsigned long long)runs);
   }
   __syncthreads();
   if (threadIdx.x < kBinMix && acc[threadIdx.x]) atomicAdd(&out[threadIdx.x], acc[threadIdx.x]);

@@ -311,7 +311,7 @@ def fstat_mlp_grad(params, x, t):
 
 def fstat_interp_stats(plan, stream=None, bin_mix=False):
     items, rej, ref = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    mix = (ctypes.c_int64 * 7)() if bin_mix else None
+    mix = (ctypes.c_int64 * 14)() if bin_mix else None
     _check(lib().fstat_interp_stats(plan, ctypes.byref(items), ctypes.byref(rej), ctypes.byref(ref),
                                     mix, stream))
     if bin_mix:
@@ -551,7 +551,8 @@ class Plan:
         the last evaluation, and with bin_mix the bins by kind of per-bin work
         ([0..2] phase and sine per bin at transfer degree 5, 7, 9 -- mixed path:
         [0] degree 4, [2] degree 6; [3..5] the difference recurrence at degree
-        5, 7, 9; [6] exact)."""
+        5, 7, 9; [6] exact), then [7 + k] the lanes with bins (runs) of the
+        items of kind k < 6 and [13] the items evaluated exactly."""
         return fstat_interp_stats(self.handle, _stream(), bin_mix)
 
     def surrogate_stats(self, n_flags: int = 0):

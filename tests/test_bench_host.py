@@ -33,23 +33,34 @@ def test_mixed_peak_is_the_time_floor_of_the_operation_mix():
 
 def test_algorithmic_flops_follow_the_bin_mix():
     """Per-bin algorithmic counts of the interpolating loop: 63 + 4 (D - 1)
-    FLOPs with the phase and sine at every bin, 46 + 4 (D - 1) (plus s^8 at
-    D = 9) with the difference recurrence, at transfer degree D; the launch
-    total is the bin-weighted sum of its kinds (exact-loop bins are not the
-    main kernel's work)."""
+    FLOPs with the phase and sine at every bin, 38 + 2 D with the difference
+    recurrence and binomial moments, at transfer degree D; per lane run the
+    coefficients (12 + 16 D), and with the recurrence its set-up (223) and the
+    moments' change to power form (4 D^2 + 3 D + 2).  The launch total is the
+    bin- and run-weighted sum of its kinds (exact-loop bins are not the main
+    kernel's work)."""
     import bench
     for d in (5, 7, 9):
         assert bench.ALG_FP64[f"deg{d}"] == 63 + 4 * (d - 1)
-        assert bench.ALG_FP64[f"rec{d}"] == 46 + 4 * (d - 1) + (d == 9)
-    mix = [10, 20, 30, 1, 2, 3, 1000]
+        assert bench.ALG_FP64[f"rec{d}"] == 38 + 2 * d
+        assert bench.RUN_FP64[f"deg{d}"] == 12 + 16 * d
+        assert bench.RUN_FP64[f"rec{d}"] == 223 + (4 * d * d + 3 * d + 2) + 12 + 16 * d
+    for d in (4, 6):
+        assert bench.RUN_MIXED[f"deg{d}"] == 12 + 16 * d
+    mix = [10, 20, 30, 1, 2, 3, 1000, 4, 5, 6, 7, 8, 9, 11]
     f64, f32 = bench.alg_flops("fp64", mix)
     assert f32 == 0.0
-    assert f64 == 10 * 79 + 20 * 87 + 30 * 95 + 1 * 62 + 2 * 70 + 3 * 79
-    m64, m32 = bench.alg_flops("mixed", [40, 0, 60, 0, 0, 0, 1000])
-    assert (m64, m32) == (100 * 24, 40 * 27 + 60 * 37)
-    assert bench.bin_mix_dict(True, [40, 0, 60, 0, 0, 0, 1000]) == {
-        "deg4": 40, "deg6": 60, "exact": 1000}
-    assert list(bench.bin_mix_dict(False, mix).values()) == mix
+    bins = 10 * 79 + 20 * 87 + 30 * 95 + 1 * 48 + 2 * 52 + 3 * 56
+    assert bench.alg_flops("fp64", mix, runs=False) == (bins, 0.0)
+    assert f64 == bins + 4 * 92 + 5 * 124 + 6 * 156 + 7 * 432 + 8 * 566 + 9 * 732
+    mmix = [40, 0, 60, 0, 0, 0, 1000, 3, 0, 5, 0, 0, 0, 7]
+    m64, m32 = bench.alg_flops("mixed", mmix)
+    assert (m64, m32) == (100 * 24 + 3 * 76 + 5 * 108, 40 * 27 + 60 * 37)
+    assert bench.alg_flops("mixed", mmix, runs=False) == (100 * 24, 40 * 27 + 60 * 37)
+    assert bench.bin_mix_dict(True, mmix) == ({"deg4": 40, "deg6": 60, "exact": 1000},
+                                              {"deg4": 3, "deg6": 5, "exact": 7})
+    b, r = bench.bin_mix_dict(False, mix)
+    assert list(b.values()) == mix[:7] and list(r.values()) == mix[7:]
 
 
 def test_counter_figures_match_the_kernel_sources():

@@ -152,6 +152,7 @@ def test_paper_scale_interpolating_matches_exact_everywhere(paper, torch_cuda, n
     P, Pe = P.cpu().numpy()[:, :npart], Pe.cpu().numpy()[:, :npart]
     r = _rel(P, Pe)
     rec, direct = sum(mix[3:6]), sum(mix[:3])
+    assert mix[13] == rej and sum(mix[7:13]) <= 64 * (items - rej)
     print(f"  {items} items, {rej} exact, {ref} refined; max rel {r.max():.2e}, p99.99 "
           f"{np.quantile(r, 0.9999):.2e}, median {np.median(r):.2e}; bins by difference "
           f"recurrence {rec}, direct {direct}, exact {mix[6]}", flush=True)

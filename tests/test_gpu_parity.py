@@ -102,6 +102,8 @@ def test_interpolating_and_exact_bin_loops_agree(small, torch_cuda, npart):
     print(f"[interp] Np={npart}: {items} items, {rej} handed to the exact loop, {ref} refined; "
           f"bins direct {sum(mix[:3])}, recurrence {sum(mix[3:6])}, exact {mix[6]}", flush=True)
     assert items == items_e and rej_e == items_e and ref_e == 0
+    # runs: at most one per lane of each interpolated item; [13] the exact items
+    assert mix[13] == rej and sum(mix[7:13]) <= 64 * (items - rej)
     if npart == 1:
         # items of >= 32 bins exist only at Np = 1 here: most go through the
         # interpolating loop, so this compares the two loops, not one with itself
