@@ -58,15 +58,22 @@ PEAK_LANE_INSTR = 256 * 64 * 2.4e9
 # plan's model does not fit go to the exact loop).
 ALG_FP64 = {"deg5": 79.0, "deg7": 87.0, "deg9": 95.0, "rec5": 48.0, "rec7": 52.0, "rec9": 56.0}
 RUN_FP64 = {"deg5": 92.0, "deg7": 124.0, "deg9": 156.0, "rec5": 432.0, "rec7": 566.0, "rec9": 732.0}
-# Mixed loop, per bin: FP64 phase (Horner, 24 FP64), FP32 sin/cos (2
-# instructions, not counted), w e^{i Phi} (6), powers (5) and moments k <= 6
-# (26) in FP32 at transfer degree 6; at degree 4 powers (3) and moments k <= 4
-# (18).  Per run: the coefficients in FP64, 12 + 16 D.
-ALG_MIXED = {"deg6": (24.0, 37.0), "deg4": (24.0, 27.0)}     # (FP64, FP32)
-RUN_MIXED = {"deg6": 108.0, "deg4": 76.0}                    # FP64
+# Mixed loop, per bin: the phase's forward differences in FP64 (9 additions,
+# or 4 where the wave holds the fourth difference) and its reduction to one
+# turn (1), FP32 sin/cos (2 instructions, not counted), w e^{i Phi} into the
+# zeroth binomial moment (8 FP32) and the running sums (2 D FP32).  Per run:
+# the start s (2), the Taylor shift of the phase polynomial (90), powers of
+# the step (8), the forward differences (99), the linear term (1), the start
+# phase (4) and the run's end (2): 206 FP64; the moments' change to power form
+# (4 D^2 + 3 D FP32); the coefficients (12 + 16 D FP64).
+ALG_MIXED = {"deg4": (10.0, 16.0), "deg6": (10.0, 20.0),           # (FP64, FP32)
+             "deg4_d4": (5.0, 16.0), "deg6_d4": (5.0, 20.0)}
+RUN_MIXED = {"deg4": (282.0, 76.0), "deg6": (314.0, 162.0),
+             "deg4_d4": (282.0, 76.0), "deg6_d4": (314.0, 162.0)}
 BIN_MIX_KEYS = ("deg5", "deg7", "deg9", "rec5", "rec7", "rec9", "exact")
-# The mixed path fills [0] (transfer degree 4), [2] (degree 6) and [6] (exact).
-BIN_MIX_KEYS_MIXED = ("deg4", None, "deg6", None, None, None, "exact")
+# The mixed path fills [0], [2] (transfer degree 4, 6; nine phase differences),
+# [3], [5] (the same with four) and [6] (exact).
+BIN_MIX_KEYS_MIXED = ("deg4", None, "deg6", "deg4_d4", None, "deg6_d4", "exact")
 
 
 def bin_mix_dict(mixed, mix):
@@ -85,9 +92,12 @@ def alg_flops(kind, mix, runs=True):
     if kind == "fp64":
         k = BIN_MIX_KEYS
         return sum(mix[i] * ALG_FP64[k[i]] + r * mix[7 + i] * RUN_FP64[k[i]] for i in range(6)), 0.0
-    a4, a6 = ALG_MIXED["deg4"], ALG_MIXED["deg6"]     # mixed path: [0] degree 4, [2] degree 6
-    f64 = mix[0] * a4[0] + mix[2] * a6[0] + r * (mix[7] * RUN_MIXED["deg4"] + mix[9] * RUN_MIXED["deg6"])
-    return f64, mix[0] * a4[1] + mix[2] * a6[1]
+    f64 = f32 = 0.0
+    for i, k in enumerate(BIN_MIX_KEYS_MIXED[:6]):
+        if k is not None:
+            f64 += mix[i] * ALG_MIXED[k][0] + r * mix[7 + i] * RUN_MIXED[k][0]
+            f32 += mix[i] * ALG_MIXED[k][1] + r * mix[7 + i] * RUN_MIXED[k][1]
+    return f64, f32
 
 
 def floor_peak(f64, f32, p64, p32):

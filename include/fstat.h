@@ -377,9 +377,11 @@ int fstat_profile_read(fstat_plan_t plan, int reset, double *kernel_ms, double *
  * exactly because their partition's matrix is ill-conditioned enough for the
  * interpolation error to matter (FP64 path only).  bin_mix [14] (or NULL):
  * bins of the items by the interpolating loop's per-bin work, [0..2] phase
- * polynomial and sine at every bin, at transfer degree 5, 7, 9 (on the mixed
- * path [0] degree 4 and [2] degree 6), [3..5] the FP64 loop's difference recurrence
- * for the template factor, at degree 5, 7, 9, [6] handed to the exact loop;
+ * polynomial and sine at every bin, at transfer degree 5, 7, 9, [3..5] the
+ * FP64 loop's difference recurrence for the template factor, at degree 5, 7,
+ * 9 (on the mixed path [0] degree 4 and [2] degree 6 with the phase carried
+ * by all nine forward differences, [3] degree 4 and [5] degree 6 with four),
+ * [6] handed to the exact loop;
  * [7 + k] (k < 6) the lanes with bins (runs) of the items of kind k, each of
  * which does the kind's per-lane work once, [13] the items handed to the exact
  * loop (EINVAL after an FSTAT_EVAL_EXACT evaluation).  Waits for hip_stream.

@@ -715,12 +715,17 @@ __constant__ double c_row9[kCheb][kLanesItem];      // degree-9 interpolant
 // after degree kDegT (its error, ~1e-10 on paper-scale items, is far below FP32
 // rounding); node rows above kDegT are zero.  Items whose series truncated
 // after degree kDegTLow stays within kInterpTolTMixed at both ends take that
-// one (2 powers and 4 FP32 FMAs per bin fewer); degree 4 for every item would
+// one (4 FP32 additions per bin fewer); degree 4 for every item would
 // send enough items to the exact loop to cost more than it saves.
 constexpr int kDegT = 6;
 constexpr int kDegTLow = 4;
 __constant__ double c_row6[kCheb][kLanesItem];
 __constant__ double c_row4[kCheb][kLanesItem];
+// Mixed loop: forward differences of the phase carried per bin where the
+// rest may be dropped, and the largest phase error [turns] that dropping them
+// may cause (the FP32 sine's own error is ~1e-7 turns).
+constexpr int kMixDiff = 4;
+constexpr double kMixTrunc = 1e-9;
 // The FP64 loop's transfer interpolants may be truncated after degree 5 or 7
 // per item when that keeps them within the item's own error (most paper-scale
 // items need 5-7 of the 10 Chebyshev terms at the 2e-13 bar).
@@ -1508,7 +1513,9 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         // distinct LDS banks).  The phase R(s) + Bp m + A [turns] advances by
         // its forward differences in FP64: R has degree 9, so the ninth
         // difference is constant and every phase of the run is exact up to
-        // rounding (~1e-13 turns over a run), no polynomial per bin.  The
+        // rounding (~1e-13 turns over a run), no polynomial per bin; where the
+        // fifth to ninth differences move no phase of any lane's run by more
+        // than kMixTrunc, the wave holds the fourth constant instead.  The
         // N-terms are summed in FP32 as binomial moments (A_m += A_{m-1}, then
         // A_0 += w e^{i Phi}: A_m = sum_t w_t e^{i Phi_t} C(cnt - 1 - t, m)),
         // changed once per lane to power moments sum w e^{i Phi} s^k (k <= D)
@@ -1548,8 +1555,20 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
           ph = fma(Bp, (double)m0, p[0]) + A;
           ph -= rint(ph);
         }
-        auto loop = [&](auto dt) {
+        // the neglected differences' largest effect on the run: C(t, j) <=
+        // C(Lr, j) for every t < Lr
+        double cj = 1.0, drop = 0.0;
+#pragma unroll
+        for (int j = 1; j < kCheb; ++j) {
+          cj *= (double)(Lr - j + 1) * (1.0 / (double)j);
+          if (j > kMixDiff) drop = fma(cj, fabs(dd[j]), drop);
+        }
+        const bool trunc = __all(cnt == 0 || drop <= kMixTrunc);
+        if (lane == 0 && trunc) rec[(int64_t)w * kRec + L::tail + 3] = 2.0;   // for fstat_interp_stats
+        // D: transfer degree; ND: forward differences carried (the last held)
+        auto loop = [&](auto dt, auto ndt) {
           constexpr int D = decltype(dt)::value;
+          constexpr int ND = decltype(ndt)::value;
           int idx;
           float mr[D + 1], mm[D + 1];
           auto bin = [&](auto first, float a, float b) {
@@ -1572,7 +1591,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
             }
             ph += dd[1];
 #pragma unroll
-            for (int j = 1; j < kCheb - 1; ++j) dd[j] += dd[j + 1];
+            for (int j = 1; j < ND; ++j) dd[j] += dd[j + 1];
           };
           using First = std::true_type;
           using Next = std::false_type;
@@ -1634,8 +1653,17 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
           const double tot = wave_sum4(red, lane, idx);
           if ((lane & 15) == 0) partials[(int64_t)w * 8 + idx] = tot;
         };
-        if (degT == kDegTLow) loop(std::integral_constant<int, kDegTLow>{});
-        else loop(std::integral_constant<int, kDegT>{});
+        using DLow = std::integral_constant<int, kDegTLow>;
+        using DHigh = std::integral_constant<int, kDegT>;
+        using NShort = std::integral_constant<int, kMixDiff>;
+        using NFull = std::integral_constant<int, kCheb - 1>;
+        if (degT == kDegTLow) {
+          if (trunc) loop(DLow{}, NShort{});
+          else loop(DLow{}, NFull{});
+        } else {
+          if (trunc) loop(DHigh{}, NShort{});
+          else loop(DHigh{}, NFull{});
+        }
       }
     }
     __syncthreads();   // every wave is done with this unit's LDS and s_unit
@@ -1730,8 +1758,9 @@ __global__ void k_mark(const PartConst* __restrict__ pc, int64_t n, int32_t stri
 
 // Bins of the last evaluation's items by the kind of per-bin work the
 // interpolating loop did on them: out[0..2] direct phase and sine per bin at
-// transfer degree 5, 7, 9 (mixed path: [0] degree 4, [2] degree 6), out[3..5]
-// the difference recurrence at degree 5, 7, 9, out[6] evaluated exactly
+// transfer degree 5, 7, 9, out[3..5] the difference recurrence at degree 5, 7,
+// 9 (mixed path: [0] degree 4 and [2] degree 6 with all nine phase
+// differences, [3] and [5] the same with four), out[6] evaluated exactly
 // (rejects; refined items count where the interpolating loop ran them).
 // out[7 + k] (k < 6): the lanes with bins (runs) of the items of kind k, each
 // of which does its kind's per-lane work once (recurrence set-up, moments to
@@ -1761,8 +1790,8 @@ __global__ __launch_bounds__(256) void k_bin_mix(const int2* __restrict__ items,
     if (!xflag[w]) {
       const double* r = rec + (int64_t)w * kRec;
       const int deg = (int)r[L::tail + 4];
-      const bool dr = !MIXED && r[L::tail + 3] == 2.0;
-      kind = MIXED ? (deg == kDegTLow ? 0 : 2) : (deg == 5 ? 0 : (deg == 7 ? 1 : 2)) + (dr ? 3 : 0);
+      const bool dr = r[L::tail + 3] == 2.0;
+      kind = (MIXED ? (deg == kDegTLow ? 0 : 2) : (deg == 5 ? 0 : (deg == 7 ? 1 : 2))) + (dr ? 3 : 0);
       // the recurrence's and the mixed loop's lanes take runs of Lr
       // contiguous bins, the FP64 direct form's lanes every 64th bin
       const int Lr = ((nb + 63) >> 6) | 1;

@@ -549,10 +549,11 @@ class Plan:
     def interp_stats(self, bin_mix: bool = False):
         """(work items, items handed to the exact loop, items refined exactly) of
         the last evaluation, and with bin_mix the bins by kind of per-bin work
-        ([0..2] phase and sine per bin at transfer degree 5, 7, 9 -- mixed path:
-        [0] degree 4, [2] degree 6; [3..5] the difference recurrence at degree
-        5, 7, 9; [6] exact), then [7 + k] the lanes with bins (runs) of the
-        items of kind k < 6 and [13] the items evaluated exactly."""
+        ([0..2] phase and sine per bin at transfer degree 5, 7, 9; [3..5] the
+        difference recurrence at degree 5, 7, 9 -- mixed path: [0] degree 4,
+        [2] degree 6 with nine phase differences, [3], [5] the same with four;
+        [6] exact), then [7 + k] the lanes with bins (runs) of the items of
+        kind k < 6 and [13] the items evaluated exactly."""
         return fstat_interp_stats(self.handle, _stream(), bin_mix)
 
     def surrogate_stats(self, n_flags: int = 0):

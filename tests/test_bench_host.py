@@ -36,7 +36,10 @@ def test_algorithmic_flops_follow_the_bin_mix():
     FLOPs with the phase and sine at every bin, 38 + 2 D with the difference
     recurrence and binomial moments, at transfer degree D; per lane run the
     coefficients (12 + 16 D), and with the recurrence its set-up (223) and the
-    moments' change to power form (4 D^2 + 3 D + 2).  The launch total is the
+    moments' change to power form (4 D^2 + 3 D + 2); the mixed loop's phase
+    differences (10 or 5 FP64) and moments (8 + 2 D FP32) per bin, its set-up
+    (206 FP64), coefficients and change to power form (4 D^2 + 3 D FP32) per
+    run.  The launch total is the
     bin- and run-weighted sum of its kinds (exact-loop bins are not the main
     kernel's work)."""
     import bench
@@ -46,19 +49,23 @@ def test_algorithmic_flops_follow_the_bin_mix():
         assert bench.RUN_FP64[f"deg{d}"] == 12 + 16 * d
         assert bench.RUN_FP64[f"rec{d}"] == 223 + (4 * d * d + 3 * d + 2) + 12 + 16 * d
     for d in (4, 6):
-        assert bench.RUN_MIXED[f"deg{d}"] == 12 + 16 * d
+        for k in (f"deg{d}", f"deg{d}_d4"):
+            assert bench.RUN_MIXED[k] == (206 + 12 + 16 * d, 4 * d * d + 3 * d)
+            assert bench.ALG_MIXED[k] == (10.0 if k == f"deg{d}" else 5.0, 8 + 2 * d)
     mix = [10, 20, 30, 1, 2, 3, 1000, 4, 5, 6, 7, 8, 9, 11]
     f64, f32 = bench.alg_flops("fp64", mix)
     assert f32 == 0.0
     bins = 10 * 79 + 20 * 87 + 30 * 95 + 1 * 48 + 2 * 52 + 3 * 56
     assert bench.alg_flops("fp64", mix, runs=False) == (bins, 0.0)
     assert f64 == bins + 4 * 92 + 5 * 124 + 6 * 156 + 7 * 432 + 8 * 566 + 9 * 732
-    mmix = [40, 0, 60, 0, 0, 0, 1000, 3, 0, 5, 0, 0, 0, 7]
+    mmix = [40, 0, 60, 20, 0, 30, 1000, 3, 0, 5, 2, 0, 4, 7]
     m64, m32 = bench.alg_flops("mixed", mmix)
-    assert (m64, m32) == (100 * 24 + 3 * 76 + 5 * 108, 40 * 27 + 60 * 37)
-    assert bench.alg_flops("mixed", mmix, runs=False) == (100 * 24, 40 * 27 + 60 * 37)
-    assert bench.bin_mix_dict(True, mmix) == ({"deg4": 40, "deg6": 60, "exact": 1000},
-                                              {"deg4": 3, "deg6": 5, "exact": 7})
+    b64, b32 = 100 * 10 + 50 * 5, 60 * 16 + 90 * 20
+    assert bench.alg_flops("mixed", mmix, runs=False) == (b64, b32)
+    assert (m64, m32) == (b64 + 5 * 282 + 9 * 314, b32 + 5 * 76 + 9 * 162)
+    assert bench.bin_mix_dict(True, mmix) == (
+        {"deg4": 40, "deg6": 60, "deg4_d4": 20, "deg6_d4": 30, "exact": 1000},
+        {"deg4": 3, "deg6": 5, "deg4_d4": 2, "deg6_d4": 4, "exact": 7})
     b, r = bench.bin_mix_dict(False, mix)
     assert list(b.values()) == mix[:7] and list(r.values()) == mix[7:]
 
