@@ -127,15 +127,15 @@ def calibrate(reps=10):
 # per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes
 # written per launch (WRITE_SIZE).
 MAIN_KERNEL = {"fp64": "k_eval_interp<false>", "mixed": "k_eval_interp<true>"}
-FLOP_PER_BIN = {"fp64": 83.76, "mixed": 56.92}      # FP64 + FP32
-FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 31.18}      # of which FP32
-VALU_PER_BIN = {"fp64": 61.23, "mixed": 43.47}
-VALU32_PER_BIN = {"fp64": 0.01, "mixed": 20.32}      # of which FP32 arithmetic
-TRAFFIC = {"fp64": (0.3685, 1.052e+08), "mixed": (0.2148, 3.457e+07)}
+FLOP_PER_BIN = {"fp64": 69.28, "mixed": 31.57}      # FP64 + FP32
+FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 20.69}      # of which FP32
+VALU_PER_BIN = {"fp64": 56.82, "mixed": 31.39}
+VALU32_PER_BIN = {"fp64": 0.01, "mixed": 16.01}      # of which FP32 arithmetic
+TRAFFIC = {"fp64": (0.3682, 1.052e+08), "mixed": (0.2153, 6.767e+07)}
 # sha256 of the bin-loop kernels' code (fstat_kernels.hip and the two headers
 # it builds on, comments removed) when those counters were taken; the figures
 # are reported as null once it differs.
-COUNTERS_SRC_SHA = "fc3abbabbb06234b631ff1d46e078220f1925de9071df41893f47773be14179b"
+COUNTERS_SRC_SHA = "1c724cb8219a516a6a34f96f9360ba507c786e20c38964318ea509730ee29bfc"
 KERNEL_HEADERS = ("fstat_internal.h", "fstat_kernels.h")
 
 
