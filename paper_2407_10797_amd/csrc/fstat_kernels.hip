@@ -938,7 +938,8 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
   __shared__ double s_rt[MIXED ? 1 : 2][kCheb][kLanesItem];
   // each lane's node values, read back by the lanes of its item (one write,
   // broadcast reads: LDS operations of one wave complete in order)
-  __shared__ __align__(16) double s_nd[4][64][12];
+  constexpr int kNd = 14;
+  __shared__ __align__(16) double s_nd[4][64][kNd];
   double* my_nd = s_nd[threadIdx.x >> 6][lane];
   for (int i = threadIdx.x; i < kCheb * kLanesItem; i += blockDim.x) {
     const int kn = i / kLanesItem, kk = i - kn * kLanesItem;
@@ -1029,11 +1030,12 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     // Lane k forms sum_kn row[kn][k] v_kn: on node lanes (k < kCheb) the
     // interpolant's monomial coefficient k, on the end lanes its value at the
     // lane's own end point, which the lane has evaluated exactly.
-    // R in double-double: R reaches a few cycles, the node-to-monomial map has
-    // entries of a few hundred, and a plain double sum would leave ~1e-13
-    // cycles of cancellation error in the coefficients.
-    dd aR{0.0, 0.0};
-    double aRx = 0.0, tmax = 0.0, gmax = 0.0;
+    // FP64 path: R compensated (a twice-the-working-precision dot product:
+    // error-free products and sums, their errors summed apart): R reaches a
+    // few cycles, the node-to-monomial map has entries of a few hundred, and a
+    // plain double sum would leave ~1e-13 cycles of cancellation error in the
+    // coefficients.  Mixed path: a plain sum (its tolerance is 1e-9 cycles).
+    double aRs = 0.0, aRx = 0.0, tmax = 0.0, gmax = 0.0;
     double aT[4], aTt[2][4], aG[4];
 #pragma unroll
     for (int fn = 0; fn < 4; ++fn) {
@@ -1043,51 +1045,58 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     my_nd[2] = v[1]; my_nd[3] = v[2]; my_nd[4] = v[3]; my_nd[5] = v[4];
     my_nd[6] = gq[0]; my_nd[7] = gq[1]; my_nd[8] = gq[2]; my_nd[9] = gq[3];
     my_nd[10] = wq;
+    // the node's largest transfer component and |M-term integrand|
+    my_nd[12] = fmax(fmax(fabs(v[1]), fabs(v[2])), fmax(fabs(v[3]), fabs(v[4])));
+    my_nd[13] = fmax(fabs(gq[0]), fabs(gq[1]));
     __builtin_amdgcn_wave_barrier();
     const double* item_nd = s_nd[threadIdx.x >> 6][base];
     // not unrolled: unrolling hoists every node's table loads and needs more
     // registers than the kernel can hold at a useful occupancy
+    // M-term integrands: lane 0 sums the quadrature, the end lanes interpolate
+    const double sel0 = k == 0 ? 1.0 : 0.0, selE = k >= kCheb ? 1.0 : 0.0;
 #pragma unroll 1
     for (int kn = 0; kn < kCheb; ++kn) {
       const double r9 = s_r9[kn][k];
       const double rT = MIXED ? s_rT[kn][k] : r9;
-      const double2* nd = reinterpret_cast<const double2*>(item_nd + 12 * kn);
-      const double2 n01 = nd[0], n23 = nd[1], n45 = nd[2], n67 = nd[3], n89 = nd[4], nab = nd[5];
-      {
-        aR = dd_add(aR, two_prod(n01.x, r9));
-        aRx = fma(n01.y, r9, aRx);
+      const double2* nd = reinterpret_cast<const double2*>(item_nd + kNd * kn);
+      const double2 n01 = nd[0], n23 = nd[1], n45 = nd[2], n67 = nd[3], n89 = nd[4], nab = nd[5],
+                    ncd = nd[6];
+      if constexpr (MIXED) {
+        aRx = fma(n01.x, r9, aRx);
+      } else {
+        FSTAT_NO_CONTRACT
+        const dd pr = two_prod(n01.x, r9);
+        const dd sm = two_sum(aRs, pr.hi);
+        aRs = sm.hi;
+        aRx = fma(n01.y, r9, aRx + (sm.lo + pr.lo));
       }
       const double vt[4] = {n23.x, n23.y, n45.x, n45.y};
 #pragma unroll
       for (int fn = 0; fn < 4; ++fn) {
         aT[fn] = fma(vt[fn], rT, aT[fn]);
-        tmax = fmax(tmax, fabs(vt[fn]));
 #pragma unroll
         for (int v2 = 0; v2 < (MIXED ? 1 : 2); ++v2)
           aTt[v2][fn] = fma(vt[fn], s_rt[v2][kn][k], aTt[v2][fn]);
       }
-      // M-term integrands: lane 0 sums the quadrature, the end lanes interpolate
-      const double wk = nab.x;
-      const double rg = k == 0 ? wk : (k >= kCheb ? r9 : 0.0);
+      tmax = fmax(tmax, ncd.x);
+      gmax = fmax(gmax, ncd.y);
+      const double rg = fma(sel0, nab.x, selE * r9);
       const double gt[4] = {n67.x, n67.y, n89.x, n89.y};
 #pragma unroll
-      for (int fn = 0; fn < 4; ++fn) {
-        aG[fn] = fma(gt[fn], rg, aG[fn]);
-        if (fn < 2) gmax = fmax(gmax, fabs(gt[fn]));
-      }
+      for (int fn = 0; fn < 4; ++fn) aG[fn] = fma(gt[fn], rg, aG[fn]);
     }
     __builtin_amdgcn_wave_barrier();   // the slots are rewritten by the next group
     const double tolP = MIXED ? kInterpTolPhaseMixed : kInterpTolPhase;
     const double tolT = MIXED ? kInterpTolTMixed : kInterpTolT;
-    const double cR = aR.hi + (aR.lo + aRx);
+    const double cR = aRs + aRx;
     bool bad = false;
     double err = 0.0;           // relative template error at this end point
     double errt[2] = {0.0, 0.0};   // transfer error of the degree-5 and -7 (mixed: 4) truncations
     double gerr = 0.0;          // M-term integrands' error (relative to max u |T|^2)
     if (k >= kCheb) {
       const double itmax = 1.0 / tmax;      // the estimates below need no correct rounding
-      const dd dR = dd_add(aR, dd{-v[0], -v0lo});
-      const double dph = fabs(dR.hi + (dR.lo + aRx));
+      // (aRs - v0 is exact wherever the interpolant is close enough to pass)
+      const double dph = fabs(((aRs - v[0]) + aRx) - v0lo);
       bad = !(dph <= tolP);
       err = 2.0 * kPi * dph;
 #pragma unroll
