@@ -131,11 +131,11 @@ FLOP_PER_BIN = {"fp64": 69.28, "mixed": 31.57}      # FP64 + FP32
 FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 20.69}      # of which FP32
 VALU_PER_BIN = {"fp64": 56.82, "mixed": 31.39}
 VALU32_PER_BIN = {"fp64": 0.01, "mixed": 16.01}      # of which FP32 arithmetic
-TRAFFIC = {"fp64": (0.3682, 1.052e+08), "mixed": (0.2153, 6.767e+07)}
+TRAFFIC = {"fp64": (0.3674, 1.052e+08), "mixed": (0.2147, 6.766e+07)}
 # sha256 of the bin-loop kernels' code (fstat_kernels.hip and the two headers
 # it builds on, comments removed) when those counters were taken; the figures
 # are reported as null once it differs.
-COUNTERS_SRC_SHA = "1c724cb8219a516a6a34f96f9360ba507c786e20c38964318ea509730ee29bfc"
+COUNTERS_SRC_SHA = "381c9ac3ab51f9d7c9fed24296cc4a87582640570cf4e7f36cf6a5b58bdb29c4"
 KERNEL_HEADERS = ("fstat_internal.h", "fstat_kernels.h")
 
 
