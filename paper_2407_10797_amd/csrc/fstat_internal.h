@@ -253,6 +253,32 @@ __host__ __device__ __forceinline__ dd phase_full(const PartConst& P, dd f, dd& 
   return ph;
 }
 
+// The same phase and t_f in plain FP64 (whole cycles kept): at ~1e7 cycles
+// the phase rounds to ~2e-9 cycles, enough where the sine is taken in FP32
+// (~6e-8 turns).  y = x^{-1/3} from w0^3 with one Newton step, as above.
+__host__ __device__ __forceinline__ double phase_full_fp64(const PartConst& P, double f,
+                                                           double& tf,
+                                                           const double* ek = nullptr) {
+  const double x = P.mc_hi * f;
+  const double lx = log(x);
+  const double w0 = ek ? 0.0 : exp(lx * (-1.0 / 9.0));
+  const double y0 = ek ? exp(lx * (-1.0 / 3.0)) : w0 * w0 * w0;
+  const double r = fma(-(y0 * y0) * y0, x, 1.0);
+  const double y = fma(y0 * r, 1.0 / 3.0, y0);
+  const double y2 = y * y, y3 = y2 * y, y5 = y3 * y2;
+  const double xy2 = x * y2;
+  const double tN = P.cN_hi * y5, t1 = P.c1_hi * y3, t15 = P.c15_hi * y2;
+  const double te = ek ? knot_interp(ek, f) : P.ce_hi * (y5 * y5 * y) * w0;
+  const double lnv = P.ln_vfac + lx * (1.0 / 3.0);
+  const double t2 = P.c2 * y;
+  const double t6 = P.c6 * xy2;
+  const double small = P.c5 * lnv + t6 * (P.a6k + P.b6 * lnv);
+  const double D = (-5.0 / 3.0) * tN - t1 - (2.0 / 3.0) * t15 - (1.0 / 3.0) * t2 + P.c5v5 +
+                   t6 * (P.a6k + P.b6 + P.b6 * lnv) * (1.0 / 3.0) - (34.0 / 9.0) * te;
+  tf = P.tc + D * (P.mc_hi * y3);
+  return f * P.tc + (tN + ((t1 + t15) + (te + (t2 + small))));
+}
+
 // Per-particle phase coefficients (see PartConst), double-double where the
 // term they multiply reaches 10^2..10^7 cycles.
 __host__ __device__ inline void fill_constants(PartConst& P, const double* th) {
@@ -636,6 +662,29 @@ __device__ __forceinline__ dd template_node(const PartConst& P, dd fd, const dou
   sincospi_t(kLs * f, tab, &s0, &c0);
   response_ch_fp64(P, f, s0, c0, d, code, tpr, tpi, txr, txi, orb && orb->coef, tab);
   return dd_add(ph, dd_mul_d(fd, kp1));
+}
+
+// The same node template in plain FP64 (the mixed path's interpolation nodes).
+__device__ __forceinline__ double template_node_fp64(const PartConst& P, double f, const double* ek,
+                                                     double& tpr, double& tpi, double& txr,
+                                                     double& txi, int code = 0,
+                                                     const OrbitTable* orb = nullptr,
+                                                     const double2* tab = nullptr) {
+  double tf;
+  const double ph = phase_full_fp64(P, f, tf, ek);
+  double d[3][3];
+  double kp1;
+  if (orb && orb->coef) {
+    kp1 = k_dot_p1_table(P, *orb, tf, 0.0, d);
+  } else {
+    double sa, ca;
+    sincospi_t(2.0 * tf * (1.0 / kYear), tab, &sa, &ca);
+    kp1 = k_dot_p1(P, ca, sa, d);
+  }
+  double s0, c0;
+  sincospi_t(kLs * f, tab, &s0, &c0);
+  response_ch_fp64(P, f, s0, c0, d, code, tpr, tpi, txr, txi, orb && orb->coef, tab);
+  return fma(f, kp1, ph);
 }
 
 // ---- per-partition solve (2x2 Hermitian closed form) --------------------------

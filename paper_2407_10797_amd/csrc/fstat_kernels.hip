@@ -904,8 +904,11 @@ __global__ __launch_bounds__(kUTile) void k_ufit(const double* __restrict__ u, i
     resid[tile] = !full ? __builtin_inf() : (aa > 0.0 ? rr / aa : 0.0);
   }
 }
-// tolerances of the end-point check on the mixed path (FP32 products)
-constexpr double kInterpTolPhaseMixed = 1e-9;
+// tolerances of the end-point check on the mixed path (FP32 products; its
+// node phases are plain FP64, ~2e-9 cycles of rounding at 1e7 cycles, which
+// the interpolant carries to its end points a few times over; the FP32 sine
+// resolves ~6e-8 turns)
+constexpr double kInterpTolPhaseMixed = 1e-7;
 constexpr double kInterpTolTMixed = 3e-8;
 
 // Node values, coefficients and end-point check of every work item (all
@@ -985,8 +988,13 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     // exact frequency (k_lo + b0 + mk) df of the node, as double-double
     const dd f = dd_add(two_prod((double)(g.k_lo + b0), g.df), two_prod(mk, g.df));
     double v[5], v0lo;
-    const dd ph = template_node(P, f, ekq, v[1], v[2], v[3], v[4], g.chan.code[ch],
-                                TAB ? &g.orb : nullptr, s_tab);
+    dd ph;
+    if constexpr (MIXED)
+      ph = dd{template_node_fp64(P, f.hi, ekq, v[1], v[2], v[3], v[4], g.chan.code[ch],
+                                 TAB ? &g.orb : nullptr, s_tab), 0.0};
+    else
+      ph = template_node(P, f, ekq, v[1], v[2], v[3], v[4], g.chan.code[ch],
+                         TAB ? &g.orb : nullptr, s_tab);
     const double p0h = __shfl(ph.hi, base + kCheb, 64);
     const double p0l = __shfl(ph.lo, base + kCheb, 64);
     const double peh = __shfl(ph.hi, base + kCheb + 1, 64);
