@@ -1058,11 +1058,12 @@ __global__ __launch_bounds__(256, 2) void k_interp_nodes(Grid g,
     my_nd[13] = fmax(fabs(gq[0]), fabs(gq[1]));
     __builtin_amdgcn_wave_barrier();
     const double* item_nd = s_nd[threadIdx.x >> 6][base];
-    // not unrolled: unrolling hoists every node's table loads and needs more
-    // registers than the kernel can hold at a useful occupancy
+    // two nodes per pass (their LDS reads overlap); unrolled fully, the loop
+    // hoists every node's table loads and needs more registers than the kernel
+    // can hold at a useful occupancy
     // M-term integrands: lane 0 sums the quadrature, the end lanes interpolate
     const double sel0 = k == 0 ? 1.0 : 0.0, selE = k >= kCheb ? 1.0 : 0.0;
-#pragma unroll 1
+#pragma unroll 2
     for (int kn = 0; kn < kCheb; ++kn) {
       const double r9 = s_r9[kn][k];
       const double rT = MIXED ? s_rT[kn][k] : r9;
