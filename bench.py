@@ -131,11 +131,11 @@ FLOP_PER_BIN = {"fp64": 69.28, "mixed": 31.57}      # FP64 + FP32
 FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 20.69}      # of which FP32
 VALU_PER_BIN = {"fp64": 56.82, "mixed": 31.39}
 VALU32_PER_BIN = {"fp64": 0.01, "mixed": 16.01}      # of which FP32 arithmetic
-TRAFFIC = {"fp64": (0.3674, 1.052e+08), "mixed": (0.2147, 6.766e+07)}
+TRAFFIC = {"fp64": (0.3680, 1.052e+08), "mixed": (0.2147, 6.765e+07)}
 # sha256 of the bin-loop kernels' code (fstat_kernels.hip and the two headers
 # it builds on, comments removed) when those counters were taken; the figures
 # are reported as null once it differs.
-COUNTERS_SRC_SHA = "381c9ac3ab51f9d7c9fed24296cc4a87582640570cf4e7f36cf6a5b58bdb29c4"
+COUNTERS_SRC_SHA = "b12d4830620c5d69c13a950e1b85543b2fcf530006ea0dca2429e2dc746ea7ed"
 KERNEL_HEADERS = ("fstat_internal.h", "fstat_kernels.h")
 
 
