@@ -1531,9 +1531,10 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         // distinct LDS banks).  The phase R(s) + Bp m + A [turns] advances by
         // its forward differences in FP64: R has degree 9, so the ninth
         // difference is constant and every phase of the run is exact up to
-        // rounding (~1e-13 turns over a run), no polynomial per bin; where the
-        // fifth to ninth differences move no phase of any lane's run by more
-        // than kMixTrunc, the wave holds the fourth constant instead.  The
+        // rounding (~1e-13 turns over a run), no polynomial per bin; where a
+        // bound on what the fifth to ninth differences add stays below
+        // kMixTrunc on every lane's run, the wave holds the fourth constant
+        // and forms only the first four.  The
         // N-terms are summed in FP32 as binomial moments (A_m += A_{m-1}, then
         // A_0 += w e^{i Phi}: A_m = sum_t w_t e^{i Phi_t} C(cnt - 1 - t, m)),
         // changed once per lane to power moments sum w e^{i Phi} s^k (k <= D)
@@ -1546,6 +1547,7 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
         const int cnt = min(max(nb - m0, 0), Lr);
         double dd[kCheb];                 // dd[j]: j-th forward difference (j >= 1)
         double ph;
+        bool trunc;
         {
           // Taylor coefficients of R at the run's start (repeated synthetic
           // division), a_k = alpha^k R^(k)(s0) / k!, D_j = sum_k j! S(k, j) a_k
@@ -1557,6 +1559,18 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
           for (int k = 0; k < kCheb - 1; ++k)
 #pragma unroll
             for (int j = kCheb - 2; j >= k; --j) p[j] = fma(p[j + 1], s0, p[j]);
+          // What the fifth to ninth differences add to the phase t bins in:
+          // sum_{k>=5} a_k sum_{j>=5} C(t, j) j! S(k, j), whose inner sums are
+          // at most sum_j C(t, j) j! S(k, j) = t^k; so with t < Lr it is below
+          // sum_{k>=5} |R^(k)(s0) / k!| (alpha Lr)^k.
+          const double x = alpha * (double)Lr;
+          double xk = (x * x) * (x * x), bound = 0.0;
+#pragma unroll
+          for (int k = kMixDiff + 1; k < kCheb; ++k) {
+            xk *= x;
+            bound = fma(fabs(p[k]), xk, bound);
+          }
+          trunc = __all(cnt == 0 || bound <= kMixTrunc);
           double ap[kCheb];
           ap[1] = alpha;
 #pragma unroll
@@ -1567,21 +1581,20 @@ __global__ __launch_bounds__(256) void k_eval_interp(Grid g,
           for (int k = kCheb - 1; k >= 1; --k) {    // smallest terms first
             const double ak = p[k] * ap[k];
 #pragma unroll
-            for (int j = 1; j <= k; ++j) dd[j] = fma(kStirF[k][j], ak, dd[j]);
+            for (int j = 1; j <= k && j <= kMixDiff; ++j) dd[j] = fma(kStirF[k][j], ak, dd[j]);
+          }
+          if (!trunc) {                               // the wave carries all nine
+#pragma unroll
+            for (int k = kCheb - 1; k > kMixDiff; --k) {
+              const double ak = p[k] * ap[k];
+#pragma unroll
+              for (int j = kMixDiff + 1; j <= k; ++j) dd[j] = fma(kStirF[k][j], ak, dd[j]);
+            }
           }
           dd[1] += Bp;
           ph = fma(Bp, (double)m0, p[0]) + A;
           ph -= rint(ph);
         }
-        // the neglected differences' largest effect on the run: C(t, j) <=
-        // C(Lr, j) for every t < Lr
-        double cj = 1.0, drop = 0.0;
-#pragma unroll
-        for (int j = 1; j < kCheb; ++j) {
-          cj *= (double)(Lr - j + 1) * (1.0 / (double)j);
-          if (j > kMixDiff) drop = fma(cj, fabs(dd[j]), drop);
-        }
-        const bool trunc = __all(cnt == 0 || drop <= kMixTrunc);
         if (lane == 0 && trunc) rec[(int64_t)w * kRec + L::tail + 3] = 2.0;   // for fstat_interp_stats
         // D: transfer degree; ND: forward differences carried (the last held)
         auto loop = [&](auto dt, auto ndt) {
