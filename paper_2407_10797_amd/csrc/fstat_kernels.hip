@@ -676,7 +676,7 @@ constexpr int kItemsWave = 5;
 constexpr int kMinInterp = 32;
 constexpr double kInterpTolPhase = 1e-12;
 constexpr double kInterpTolT = 2e-13;
-constexpr int kUnitItems = 32;      // items per scheduling unit of the bin loop
+constexpr int kUnitItems = 64;      // items per scheduling unit of the bin loop
 constexpr double kTruncFloor = 6e-14;  // FP64 transfer truncation allowance
 // Difference recurrence of the FP64 bin loop: shortest lane run that takes
 // it (below, the set-up of about 160 operations per lane costs more than the
