@@ -128,15 +128,15 @@ def calibrate(reps=10):
 # per bin-template (FETCH_SIZE x 2, calibrated on a plain copy) and bytes
 # written per launch (WRITE_SIZE).
 MAIN_KERNEL = {"fp64": "k_eval_interp<false>", "mixed": "k_eval_interp<true>"}
-FLOP_PER_BIN = {"fp64": 69.28, "mixed": 30.90}      # FP64 + FP32
-FLOP32_PER_BIN = {"fp64": 0.01, "mixed": 20.69}      # of which FP32
-VALU_PER_BIN = {"fp64": 56.83, "mixed": 30.77}
-VALU32_PER_BIN = {"fp64": 0.01, "mixed": 16.01}      # of which FP32 arithmetic
-TRAFFIC = {"fp64": (0.3678, 1.052e+08), "mixed": (0.2147, 6.766e+07)}
+FLOP_PER_BIN = {"fp64": 69.19, "mixed": 30.90}      # FP64 + FP32
+FLOP32_PER_BIN = {"fp64": 0.00, "mixed": 20.69}      # of which FP32
+VALU_PER_BIN = {"fp64": 56.42, "mixed": 30.55}
+VALU32_PER_BIN = {"fp64": 0.00, "mixed": 16.01}      # of which FP32 arithmetic
+TRAFFIC = {"fp64": (0.3551, 1.046e+08), "mixed": (0.2081, 6.732e+07)}
 # sha256 of the bin-loop kernels' code (fstat_kernels.hip and the two headers
 # it builds on, comments removed) when those counters were taken; the figures
 # are reported as null once it differs.
-COUNTERS_SRC_SHA = "f466b78c271f0f09123467dd80bbcbe00b382f78b33b342372e00688abe916ea"
+COUNTERS_SRC_SHA = "e8889c6449f65bacb229c420ddea1065f83206feb718405fdafe89e2bf523b38"
 KERNEL_HEADERS = ("fstat_internal.h", "fstat_kernels.h")
 
 
